@@ -1,0 +1,223 @@
+"""Pins of the oracle's step-by-step statements (signatures, filter, PCSR,
+join levels) against properties the paper and the mathematics fix.  CPU only."""
+import decimal
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import spec
+import workloads as w
+
+
+def test_knuth_constants_are_golden_ratio_fractions():
+    decimal.getcontext().prec = 60
+    phi_inv = (decimal.Decimal(5).sqrt() - 1) / 2
+    assert int(phi_inv * (1 << 64)) == spec.KNUTH64
+    # 32-bit constant: the largest prime below 2^32 / phi (Knuth's choice)
+    x = int(phi_inv * (1 << 32))
+
+    def prime(n):
+        return n > 1 and all(n % d for d in range(2, int(n ** 0.5) + 1))
+    assert prime(spec.KNUTH32) and spec.KNUTH32 <= x
+    assert not any(prime(c) for c in range(spec.KNUTH32 + 1, x + 1))
+
+
+def _field(sig, v, g):
+    word = 1 + g // 16
+    return (int(sig[word, v]) >> (2 * (g % 16))) & 3
+
+
+def test_signature_codes_hand_built():
+    # v0 has neighbours: v1 (label 1) via edge label 0, twice the same key via
+    # v2 and v3 (label 2, edge label 1), and v4 (label 2) via edge label 0.
+    g = w.make_graph(5, [9, 1, 2, 2, 2], [(0, 1), (0, 2), (0, 3), (0, 4)], [0, 1, 1, 0])
+    sig = spec.signature_table(g)
+    assert sig[0].tolist() == [9, 1, 2, 2, 2]
+    ga = int(spec.signature_group(0, 1))
+    gb = int(spec.signature_group(1, 2))
+    gc = int(spec.signature_group(0, 2))
+    expect = {}
+    for grp, code in ((ga, 1), (gb, 3), (gc, 1)):
+        expect[grp] = expect.get(grp, 0) + (1 if code == 1 else 2)
+    for grp in range(spec.SIG_GROUPS):
+        want = expect.get(grp, 0)
+        want = 0 if want == 0 else (1 if want == 1 else 3)
+        assert _field(sig, 0, grp) == want
+    # a leaf (v1) has exactly one pair: one 01 field, nothing else
+    bits = sum(bin(int(sig[wd, 1])).count("1") for wd in range(1, 16))
+    assert bits == 1
+
+
+def test_signature_groups_spread():
+    g = spec.signature_group(np.repeat(np.arange(20), 100), np.tile(np.arange(100), 20))
+    assert g.min() >= 0 and g.max() < spec.SIG_GROUPS
+    assert len(np.unique(g)) > 200   # 2000 keys reach most of 240 groups
+
+
+@pytest.mark.parametrize("seed", range(15))
+def test_filter_is_sound(seed):
+    # every embedding the oracle finds maps u into C(u) (Sec. III-A claim)
+    r = np.random.default_rng(seed)
+    g = w.random_small_graph(40, 0.15, 3, 3, seed)
+    sig = spec.signature_table(g)
+    for t in range(3):
+        q = w.random_connected_query(int(r.integers(2, 6)), 2, 3, 3, seed * 10 + t)
+        cands = spec.filter_candidates(sig, spec.query_signatures(q))
+        res = oracle.match(g, q)
+        for u in range(q.k):
+            assert set(res.tuples[:, u].tolist()) <= set(cands[u].tolist())
+
+
+def test_filter_special_cases():
+    # single query vertex: C(u) is exactly the vertices of the same label
+    g = w.config_graph("er1k")
+    sig = spec.signature_table(g)
+    q = w.make_query([2], [], [])
+    c = spec.filter_candidates(sig, spec.query_signatures(q))[0]
+    np.testing.assert_array_equal(c, np.nonzero(g.vlabel == 2)[0])
+    # complete graph, uniform labels: every vertex is a candidate of every u
+    g = w.complete_graph(8)
+    sig = spec.signature_table(g)
+    for q in (w.clique_query(5), w.path_query(4), w.star_query(6)):
+        for c in spec.filter_candidates(sig, spec.query_signatures(q)):
+            assert len(c) == 8
+    # a query vertex whose neighbour label is absent from G has no candidates
+    q = w.make_query([0, 5], [(0, 1)], [0])
+    cs = spec.filter_candidates(sig, spec.query_signatures(q))
+    assert len(cs[0]) == 0 and len(cs[1]) == 0
+
+
+def _check_pcsr(g, degenerate=False):
+    nb = spec.neighbour_lists(g)
+    lay = spec.pcsr(g, degenerate)
+    for l, lists in nb.items():
+        gl, ci = lay[l]
+        assert gl.shape[0] == len(lists)              # |V(D)| groups
+        assert ci.shape[0] == sum(len(x) for x in lists.values())
+        # ci is laid out group by group; offsets never decrease
+        offs = gl[:, 1::2].astype(np.int64)
+        assert (np.diff(offs, axis=1) >= 0).all()
+        assert (offs[1:, 0] == offs[:-1, -1]).all()   # END = first offset of next group
+        keys = gl[:, 0:30:2]
+        used = keys[keys != spec.NONE]
+        assert sorted(used.tolist()) == sorted(lists)  # every vertex stored once
+        for v, want in lists.items():
+            got, reads = spec.pcsr_locate(gl, ci, v, degenerate)
+            np.testing.assert_array_equal(got, want)
+        # a vertex without l-edges is reported absent
+        absent = [v for v in range(g.n) if v not in lists][:20]
+        for v in absent:
+            got, _ = spec.pcsr_locate(gl, ci, v, degenerate)
+            assert len(got) == 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_pcsr_locate_random(seed):
+    _check_pcsr(w.random_small_graph(50, 0.2, 2, 3, seed))
+
+
+def test_pcsr_er1k_and_degenerate_chains():
+    g = w.config_graph("er1k")
+    _check_pcsr(g)
+    _check_pcsr(g, degenerate=True)
+    # the degenerate hash really builds chains longer than one group
+    gl, ci = spec.pcsr(g, True)[0]
+    assert (gl[:, 30] != spec.NONE).sum() > 0
+    # star centre: one key with a long list
+    _check_pcsr(w.star_graph(300))
+
+
+def test_pcsr_chain_bound_claim1():
+    # Claim 1: overflow always finds empty groups; with |V(D)| keys in |V(D)|
+    # groups the chain count never exceeds the number of empty groups
+    g = w.config_graph("er1k")
+    for l, (gl, ci) in spec.pcsr(g).items():
+        nkeys = (gl[:, 0:30:2] != spec.NONE).sum(axis=1)
+        assert (nkeys <= 15).all()
+
+
+def test_pcsr_paper_example(golden_dir):
+    gold = json.load(open(os.path.join(golden_dir, "paper_example.json")))
+    g, q = w.paper_example()
+    lay = spec.pcsr(g)
+    gla, cia = lay[0]
+    got, _ = spec.pcsr_locate(gla, cia, 0)
+    assert len(got) == gold["N_v0_a_len"]["value"]
+    glb, cib = lay[1]
+    assert glb.shape[0] == len(gold["partition_b"]["vertices"])
+    assert cib.shape[0] == 2 * gold["partition_b"]["edges"]
+    stored = sorted(glb[:, 0:30:2][glb[:, 0:30:2] != spec.NONE].tolist())
+    assert stored == gold["partition_b"]["vertices"]
+
+
+def test_join_levels_paper_example(golden_dir):
+    gold = json.load(open(os.path.join(golden_dir, "paper_example.json")))
+    g, q = w.paper_example()
+    cs = gold["candidate_sets_label_only"]
+    cands = [np.arange(a, b + 1, dtype=np.uint32) for a, b in (cs["C_u0"], cs["C_u1"], cs["C_u2"], cs["C_u3"])]
+    order = [0, 1, 2, 3]
+    # first edge u1u2 (label a) for u2, as the paper's figure assumes
+    M, lev = spec.join_levels(g, q, cands, order, [None, 0, 1, 1])
+    assert lev[1]["GBA"] == gold["gba_e0_label_a"]["value"]
+    assert lev[1]["F"][99] == gold["F_99"]["value"]
+    assert lev[1]["F"][100] - lev[1]["F"][99] == 3
+    # first edge u0u2 (label b), the rarer label Algorithm 4 prefers
+    M2, lev2 = spec.join_levels(g, q, cands, order, [None, 0, 0, 1])
+    assert lev2[1]["GBA"] == gold["gba_e0_label_b"]["value"]
+    assert spec.to_query_order(M, order).tolist() == [gold["single_match"]["tuple"]]
+    assert spec.to_query_order(M2, order).tolist() == [gold["single_match"]["tuple"]]
+    # buf_99 step by step (row m_99 = (v0, v100))
+    nb = spec.neighbour_lists(g)
+    row = (0, 100)
+    after_sub = [int(x) for x in nb[0][100] if int(x) not in row]
+    assert after_sub == gold["buf99_after_subtraction"]["value"]
+    after_int = [x for x in after_sub if x in set(nb[1][0].tolist())]
+    assert after_int == gold["buf99_after_intersection"]["value"]
+    # the plan's own choice picks label b (frequency 2/202 < 200/202)
+    order_p, e0 = spec.plan(q, [len(c) for c in cands], spec.label_frequency(g))
+    assert order_p[0] == 0 and e0[order_p.index(2)] == 0
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_join_levels_equal_oracle(seed):
+    r = np.random.default_rng(seed)
+    g = w.random_small_graph(30, 0.25, 2, 2, seed)
+    sig = spec.signature_table(g)
+    q = w.random_connected_query(int(r.integers(2, 6)), int(r.integers(0, 3)), 2, 2, seed + 77)
+    cands = spec.filter_candidates(sig, spec.query_signatures(q))
+    order, e0 = spec.plan(q, [len(c) for c in cands], spec.label_frequency(g))
+    M, lev = spec.join_levels(g, q, cands, order, e0)
+    got = spec.to_query_order(M, order)
+    got = got[np.lexsort(got.T[::-1])] if len(got) else got.reshape(0, q.k)
+    want = oracle.match(g, q).tuples
+    np.testing.assert_array_equal(got, want)
+    # each level's rows = embeddings of the query induced on the placed prefix
+    for j, L in enumerate(lev, start=1):
+        sub = order[:j]
+        keep = [i for i in range(q.m) if int(q.src[i]) in sub and int(q.dst[i]) in sub]
+        remap = {u: i for i, u in enumerate(sub)}
+        qs = w.make_query(q.vlabel[sub], [(remap[int(q.src[i])], remap[int(q.dst[i])]) for i in keep], q.elabel[keep])
+        rows = oracle.match(g, qs).tuples
+        inC = np.ones(len(rows), bool)
+        for i, u in enumerate(sub):
+            inC &= np.isin(rows[:, i], cands[u])
+        assert L["R"] == int(inC.sum())
+        assert L["S"] <= L["GBA"]
+
+
+def test_plan_prefix_connected_and_e0_linking():
+    g = w.config_graph("er1k")
+    sig = spec.signature_table(g)
+    mk = w.QueryMaker(g)
+    for i in range(8):
+        q = w.config_query(g, "er1k", i, maker=mk)
+        cands = spec.filter_candidates(sig, spec.query_signatures(q))
+        order, e0 = spec.plan(q, [len(c) for c in cands], spec.label_frequency(g))
+        assert sorted(order) == list(range(q.k))
+        edges = {frozenset((int(a), int(b))) for a, b in zip(q.src, q.dst)}
+        for j in range(1, q.k):
+            assert e0[j] in order[:j]
+            assert frozenset((e0[j], order[j])) in edges

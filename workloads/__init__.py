@@ -1,0 +1,348 @@
+"""Seeded synthetic inputs: labelled data graphs and random-walk query graphs.
+
+This module is the only code shared by the CPU oracle side (tests, the bench's
+CPU baseline) and the GPU library side: it *generates* inputs and holds none
+of the matching method's arithmetic.  Every generator is deterministic in its
+seed.  Graph models and PRNG are documented in ``gen.c``.
+
+Workload recipes (the paper's datasets, Sec. VIII-A / Table III, are not
+available; these synthetic graphs stand in for them, with power-law labels as
+in Sec. VIII-A and random-walk queries as in the same section):
+
+  ER-1K     Erdos-Renyi, 1,000 vertices, 5,000 edges, 4 vertex labels and
+            2 edge labels uniform; 8 walk queries with 4 vertices.
+  BA-1M     Barabasi-Albert (Batagelj-Brandes), 1,000,000 vertices, seed K_11
+            and 10 attachments per vertex (9,999,945 edges); 32 vertex labels
+            Zipf(1.1), 8 edge labels uniform; 100 walk queries, 6..12 vertices.
+  RMAT-23   R-MAT scale 23, 100M edges, (a,b,c) = (0.57,0.19,0.19); 100 vertex
+            labels and 20 edge labels Zipf(1.1); 50 queries of 12 vertices
+            (25 walk + 25 dense).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gen.c")
+_LIB = os.path.join(_HERE, "libgen.so")
+_lib = None
+
+U32P = ctypes.POINTER(ctypes.c_uint32)
+
+
+def build(force: bool = False) -> str:
+    """Compile gen.c into libgen.so (gcc, host code only)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        lib.gen_er.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, U32P, U32P]
+        lib.gen_er.restype = ctypes.c_int
+        lib.gen_ba_edge_count.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        lib.gen_ba_edge_count.restype = ctypes.c_uint64
+        lib.gen_ba.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, U32P, U32P]
+        lib.gen_ba.restype = ctypes.c_int
+        lib.gen_rmat.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_uint64, U32P, U32P]
+        lib.gen_rmat.restype = ctypes.c_int
+        lib.gen_labels_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, U32P]
+        lib.gen_labels_uniform.restype = None
+        lib.gen_labels_zipf.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64, U32P]
+        lib.gen_labels_zipf.restype = None
+        lib.gen_qctx_create.argtypes = [ctypes.c_uint32, U32P, ctypes.c_uint64, U32P, U32P, U32P]
+        lib.gen_qctx_create.restype = ctypes.c_void_p
+        lib.gen_qctx_free.argtypes = [ctypes.c_void_p]
+        lib.gen_qctx_free.restype = None
+        lib.gen_query.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_uint64,
+                                  U32P, U32P, U32P, U32P, U32P]
+        lib.gen_query.restype = ctypes.c_int64
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.uint32 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(U32P)
+
+
+@dataclass
+class Graph:
+    """Undirected labelled graph: one label per vertex and per edge."""
+    n: int
+    vlabel: np.ndarray  # uint32[n]
+    src: np.ndarray     # uint32[m]
+    dst: np.ndarray     # uint32[m]
+    elabel: np.ndarray  # uint32[m]
+    name: str = ""
+
+    @property
+    def m(self) -> int:
+        return int(self.src.shape[0])
+
+
+@dataclass
+class Query:
+    """Connected query graph with vertices 0..k-1."""
+    k: int
+    vlabel: np.ndarray
+    src: np.ndarray
+    dst: np.ndarray
+    elabel: np.ndarray
+    mode: str = ""
+    seed: int = 0
+    source: np.ndarray = field(default_factory=lambda: np.zeros(0, np.uint32))
+
+    @property
+    def m(self) -> int:
+        return int(self.src.shape[0])
+
+
+def _u32(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.uint32))
+
+
+def make_graph(n, vlabel, edges, elabel, name="") -> Graph:
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    return Graph(int(n), _u32(vlabel), _u32(e[:, 0]), _u32(e[:, 1]), _u32(elabel), name)
+
+
+def make_query(vlabel, edges, elabel, mode="manual") -> Query:
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    return Query(len(vlabel), _u32(vlabel), _u32(e[:, 0]), _u32(e[:, 1]), _u32(elabel), mode)
+
+
+# ------------------------------------------------------------------ labels
+def labels_uniform(n: int, nl: int, seed: int) -> np.ndarray:
+    out = np.empty(n, np.uint32)
+    _load().gen_labels_uniform(n, nl, seed, _p(out))
+    return out
+
+
+def labels_zipf(n: int, nl: int, s: float, seed: int) -> np.ndarray:
+    out = np.empty(n, np.uint32)
+    _load().gen_labels_zipf(n, nl, s, seed, _p(out))
+    return out
+
+
+# ------------------------------------------------------------------ models
+def er_edges(n: int, m: int, seed: int):
+    src = np.empty(m, np.uint32)
+    dst = np.empty(m, np.uint32)
+    rc = _load().gen_er(n, m, seed, _p(src), _p(dst))
+    if rc:
+        raise ValueError("gen_er failed: %d" % rc)
+    return src, dst
+
+
+def ba_edges(n: int, d: int, seed: int):
+    lib = _load()
+    m = int(lib.gen_ba_edge_count(n, d))
+    src = np.empty(m, np.uint32)
+    dst = np.empty(m, np.uint32)
+    rc = lib.gen_ba(n, d, seed, _p(src), _p(dst))
+    if rc:
+        raise ValueError("gen_ba failed: %d" % rc)
+    return src, dst
+
+
+def rmat_edges(scale: int, m: int, a: float, b: float, c: float, seed: int):
+    src = np.empty(m, np.uint32)
+    dst = np.empty(m, np.uint32)
+    rc = _load().gen_rmat(scale, m, a, b, c, seed, _p(src), _p(dst))
+    if rc:
+        raise ValueError("gen_rmat failed: %d" % rc)
+    return src, dst
+
+
+# ----------------------------------------------------------------- queries
+MODES = {"walk": 0, "tree": 1, "dense": 2, "walk_cycle": 3}
+
+
+class QueryMaker:
+    """Random-walk query extraction over one data graph (Sec. VIII-A recipe)."""
+
+    def __init__(self, g: Graph):
+        self.g = g
+        self._lib = _load()
+        self._h = self._lib.gen_qctx_create(g.n, _p(g.vlabel), g.m, _p(g.src), _p(g.dst), _p(g.elabel))
+
+    def close(self):
+        if self._h:
+            self._lib.gen_qctx_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def make(self, k: int, mode: str, seed: int) -> Query:
+        cap = max(1, k * (k - 1) // 2)
+        ql = np.empty(k, np.uint32)
+        qs = np.empty(cap, np.uint32)
+        qd = np.empty(cap, np.uint32)
+        qe = np.empty(cap, np.uint32)
+        srcv = np.empty(k, np.uint32)
+        ne = self._lib.gen_query(self._h, k, MODES[mode], seed, _p(ql), _p(qs), _p(qd), _p(qe), _p(srcv))
+        if ne < 0:
+            raise RuntimeError("no random walk reached %d vertices" % k)
+        return Query(k, ql, qs[:ne].copy(), qd[:ne].copy(), qe[:ne].copy(), mode, seed, srcv)
+
+
+def _stream(seed: int, i: int) -> np.random.Generator:
+    return np.random.default_rng([seed, i])
+
+
+def query_seed(base: int, index: int, attempt: int = 0) -> int:
+    """Seed of query `index` (redrawn as `attempt` grows)."""
+    return (base << 32) ^ (index << 12) ^ attempt
+
+
+def query_spec(base: int, index: int, kmin: int, kmax: int, modes) -> tuple:
+    """(k, mode) of query `index`: k uniform in [kmin, kmax], mode uniform over `modes`."""
+    r = _stream(base, index)
+    k = int(r.integers(kmin, kmax + 1))
+    mode = modes[int(r.integers(0, len(modes)))]
+    return k, mode
+
+
+# ----------------------------------------------------------------- configs
+CONFIGS = {
+    "er1k": dict(model="er", n=1000, m=5000, nvl=4, nel=2, vdist="uniform", edist="uniform",
+                 gseed=17, lseed=2017, qseed=1017, nq=8, kmin=4, kmax=4, modes=("walk",)),
+    "ba1m": dict(model="ba", n=1_000_000, d=10, nvl=32, nel=8, vdist="zipf", edist="uniform",
+                 gseed=18, lseed=2018, qseed=1018, nq=100, kmin=6, kmax=12, modes=("walk",)),
+    "rmat23": dict(model="rmat", scale=23, m=100_000_000, nvl=100, nel=20, vdist="zipf", edist="zipf",
+                   gseed=19, lseed=2019, qseed=1019, nq=50, kmin=12, kmax=12, modes=("walk", "dense")),
+}
+
+
+def config_graph(name: str) -> Graph:
+    c = CONFIGS[name]
+    if c["model"] == "er":
+        src, dst = er_edges(c["n"], c["m"], c["gseed"])
+        n = c["n"]
+    elif c["model"] == "ba":
+        src, dst = ba_edges(c["n"], c["d"], c["gseed"])
+        n = c["n"]
+    elif c["model"] == "rmat":
+        src, dst = rmat_edges(c["scale"], c["m"], 0.57, 0.19, 0.19, c["gseed"])
+        n = 1 << c["scale"]
+    else:
+        raise KeyError(c["model"])
+    m = src.shape[0]
+    lseed = c["lseed"]
+    if c["vdist"] == "zipf":
+        vl = labels_zipf(n, c["nvl"], 1.1, lseed)
+    else:
+        vl = labels_uniform(n, c["nvl"], lseed)
+    if c["edist"] == "zipf":
+        el = labels_zipf(m, c["nel"], 1.1, lseed + 1)
+    else:
+        el = labels_uniform(m, c["nel"], lseed + 1)
+    return Graph(n, vl, src, dst, el, name)
+
+
+def config_query(g: Graph, name: str, index: int, attempt: int = 0, maker: QueryMaker | None = None) -> Query:
+    c = CONFIGS[name]
+    k, mode = query_spec(c["qseed"], index, c["kmin"], c["kmax"], c["modes"])
+    mk = maker or QueryMaker(g)
+    return mk.make(k, mode, query_seed(c["qseed"], index, attempt))
+
+
+# ------------------------------------------------------- small named graphs
+def complete_graph(n: int, vl: int = 0, el: int = 0) -> Graph:
+    e = [(a, b) for a in range(n) for b in range(a + 1, n)]
+    return make_graph(n, [vl] * n, e, [el] * len(e), "K%d" % n)
+
+
+def cycle_graph(n: int) -> Graph:
+    e = [(i, (i + 1) % n) for i in range(n)]
+    return make_graph(n, [0] * n, e, [0] * n, "C%d" % n)
+
+
+def path_query(k: int) -> Query:
+    return make_query([0] * k, [(i, i + 1) for i in range(k - 1)], [0] * (k - 1), "path")
+
+
+def cycle_query(k: int) -> Query:
+    return make_query([0] * k, [(i, (i + 1) % k) for i in range(k)], [0] * k, "cycle")
+
+
+def clique_query(k: int) -> Query:
+    e = [(a, b) for a in range(k) for b in range(a + 1, k)]
+    return make_query([0] * k, e, [0] * len(e), "clique")
+
+
+def star_graph(n: int, center_label: int = 0, leaf_label: int = 0) -> Graph:
+    """Star with centre 0 and leaves 1..n-1."""
+    e = [(0, i) for i in range(1, n)]
+    return make_graph(n, [center_label] + [leaf_label] * (n - 1), e, [0] * (n - 1), "S%d" % n)
+
+
+def star_query(k: int, center_label: int = 0, leaf_label: int = 0) -> Query:
+    e = [(0, i) for i in range(1, k)]
+    return make_query([center_label] + [leaf_label] * (k - 1), e, [0] * (k - 1), "star")
+
+
+def complete_bipartite(a: int, b: int, la: int = 0, lb: int = 1) -> Graph:
+    e = [(i, a + j) for i in range(a) for j in range(b)]
+    return make_graph(a + b, [la] * a + [lb] * b, e, [0] * len(e), "K%d,%d" % (a, b))
+
+
+def random_small_graph(n: int, p: float, nvl: int, nel: int, seed: int) -> Graph:
+    r = np.random.default_rng(seed)
+    e = [(a, b) for a in range(n) for b in range(a + 1, n) if r.random() < p]
+    return make_graph(n, r.integers(0, nvl, n), e, r.integers(0, nel, len(e)), "rand%d" % n)
+
+
+def random_connected_query(k: int, extra: int, nvl: int, nel: int, seed: int) -> Query:
+    """A random spanning tree on k vertices plus up to `extra` more edges."""
+    r = np.random.default_rng(seed)
+    edges = set()
+    for v in range(1, k):
+        u = int(r.integers(0, v))
+        edges.add((u, v))
+    for _ in range(extra):
+        a, b = sorted(int(x) for x in r.integers(0, k, 2))
+        if a != b:
+            edges.add((a, b))
+    edges = sorted(edges)
+    return make_query(r.integers(0, nvl, k), edges, r.integers(0, nel, len(edges)), "random")
+
+
+def paper_example():
+    """A data graph and query consistent with every number the paper prints
+    for its running example (Sec. III-B, Sec. IV, Sec. V, Example Fig. 1).
+
+    Vertex labels: v0 is A(0); v1..v100 are B(1); v101..v201 are C(2).
+    Edges with label a(0): (v0,vj) j=1..100; (v100,v200); (v100,v201);
+    (vj, v100+j) for j=2..99.  Edges with label b(1): (v0,v201), (v1,v101).
+    Query: u0:A, u1:B, u2:C, u3:C; edges u0u1:a, u0u2:b, u1u2:a, u1u3:a.
+    """
+    A, B, C = 0, 1, 2
+    a, b = 0, 1
+    vl = [A] + [B] * 100 + [C] * 101
+    edges, el = [], []
+    for j in range(1, 101):
+        edges.append((0, j)); el.append(a)
+    edges.append((100, 200)); el.append(a)
+    edges.append((100, 201)); el.append(a)
+    for j in range(2, 100):
+        edges.append((j, 100 + j)); el.append(a)
+    edges.append((0, 201)); el.append(b)
+    edges.append((1, 101)); el.append(b)
+    g = make_graph(202, vl, edges, el, "paper_example")
+    q = make_query([A, B, C, C], [(0, 1), (0, 2), (1, 2), (1, 3)], [a, b, a, a], "paper_example")
+    return g, q

@@ -1,0 +1,236 @@
+/*
+ * gsi.h — C ABI of the MI355X subgraph-isomorphism library.
+ *
+ * The library enumerates every label-preserving injective embedding of a
+ * small connected query graph Q in a large vertex- and edge-labelled data
+ * graph G (GSI, arXiv 1906.03420, Sec. II-A, Definitions 1-3; Q connected as
+ * assumed in the same section).  An embedding is a map f: V(Q) -> V(G) that is
+ * injective, keeps vertex labels, and maps every query edge (u1,u2) with label
+ * l onto a data edge (f(u1),f(u2)) with label l.  Non-edges of Q are not
+ * constrained.  The result is the table of all embeddings, one row per map,
+ * column j holding f(j) (query-vertex order), or only its row count.
+ *
+ * Conventions
+ *  - Every function returns gsi_status; nothing throws across the ABI.  On a
+ *    failure gsi_last_error() returns a message for the calling thread.
+ *  - Vertex ids are uint32 in [0, n_vertices); 0xFFFFFFFF is reserved.
+ *    Labels are uint32; edge labels must be < GSI_MAX_EDGE_LABELS.
+ *  - Graphs are simple and undirected: no self-loops and at most one edge
+ *    (hence one label) per vertex pair (Definition 1).  Each undirected edge
+ *    is given once.
+ *  - "host" pointers are read during the call only and copied; "device"
+ *    pointers are device memory on the context's GPU, read on the context's
+ *    stream during the call.
+ *  - All device memory the library uses is carved out of one caller-owned
+ *    arena given at context creation.  The library never frees the arena and
+ *    never calls hipMalloc for data; the caller keeps the arena alive until
+ *    gsi_ctx_destroy returns.
+ *  - Handles (context, graph, result) belong to the caller and are released
+ *    with the matching *_free / *_destroy call.  A context runs one call at a
+ *    time; calls on the same context from several threads must be serialised
+ *    by the caller (GSI_E_BUSY is returned when they overlap).
+ */
+#ifndef GSI_H
+#define GSI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GSI_OK = 0,
+    GSI_E_INVALID = 1,   /* bad argument, graph or query */
+    GSI_E_NOMEM = 2,     /* arena exhausted */
+    GSI_E_DEVICE = 3,    /* a HIP runtime call failed */
+    GSI_E_CAPACITY = 4,  /* caller buffer too small */
+    GSI_E_BUSY = 5,      /* context already in a call */
+    GSI_E_INTERNAL = 6   /* an invariant of the library failed */
+} gsi_status;
+
+#define GSI_MAX_K 32                 /* maximum query vertices */
+#define GSI_MAX_EDGE_LABELS 65536    /* edge labels are < this */
+#define GSI_SIG_WORDS 16             /* N = 512-bit signatures (Sec. VIII-B) */
+#define GSI_PCSR_GPN 16              /* pairs per PCSR group (Sec. IV) */
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char *gsi_last_error(void);
+/* Library version string. */
+const char *gsi_version(void);
+
+typedef struct gsi_ctx gsi_ctx;
+typedef struct gsi_graph gsi_graph;
+typedef struct gsi_result gsi_result;
+
+/* Context flags */
+#define GSI_CTX_PROFILE 0x1u  /* time every kernel launch with HIP events */
+
+typedef struct {
+    int32_t device;       /* HIP device ordinal of the arena */
+    void *hip_stream;     /* hipStream_t for all work; NULL = the null stream */
+    void *arena_ptr;      /* device memory, 256-byte aligned, caller-owned */
+    uint64_t arena_bytes; /* size of the arena */
+    uint32_t flags;       /* GSI_CTX_* */
+} gsi_options;
+
+/* Creates a context over a caller-owned device arena.  Errors:
+ * GSI_E_INVALID on a NULL/misaligned arena or size < 1 MiB; GSI_E_DEVICE when
+ * the device cannot be selected. */
+gsi_status gsi_ctx_create(const gsi_options *opts, gsi_ctx **out);
+/* Releases the context (and any graph or result still alive on it). */
+gsi_status gsi_ctx_destroy(gsi_ctx *ctx);
+/* Arena accounting: bytes held by live graphs and results, and the peak of
+ * persistent + per-call scratch bytes since creation. */
+gsi_status gsi_ctx_memory(const gsi_ctx *ctx, uint64_t *live_bytes, uint64_t *peak_bytes);
+
+/* Per-kernel timing gathered while GSI_CTX_PROFILE is set: for each kernel
+ * name, the number of launches, the summed duration measured with HIP events
+ * recorded on the context stream around each launch, and the summed
+ * algorithmic bytes (the bytes the step must move at least, as documented per
+ * kernel).  Returns at most `cap` entries in `out`, the number in *n. */
+typedef struct {
+    char name[32];
+    uint64_t launches;
+    double total_ms;
+    double alg_bytes;
+} gsi_kernel_stat;
+gsi_status gsi_ctx_kernel_stats(gsi_ctx *ctx, gsi_kernel_stat *out, uint32_t cap, uint32_t *n);
+gsi_status gsi_ctx_kernel_stats_reset(gsi_ctx *ctx);
+
+/* Upper bound of arena bytes a graph of this size needs while it is built
+ * (persistent structures + build scratch), so the caller can size the arena. */
+gsi_status gsi_graph_bytes_needed(uint32_t n_vertices, uint64_t n_edges, uint64_t *out_bytes);
+
+/* Graph flags */
+#define GSI_GRAPH_TEST_FEW_HOME_GROUPS 0x1u  /* test only: hash PCSR keys into
+    ceil(|V(D)|/16) home groups so overflow chains form (same lookups) */
+
+/*
+ * Loads a data graph and builds, on the device, everything a query needs
+ * (Sec. III-A offline signature table; Sec. IV PCSR for every edge label,
+ * Algorithm 1):
+ *   - the edge-label partitions P(G,l), each stored as PCSR(G,l) = {gl, ci}:
+ *     |V(D)| groups of GPN=16 (vertex, offset) pairs, 128 bytes each, the
+ *     last pair (GID, END); ci holds each vertex's l-neighbours ascending;
+ *   - the column-first signature table S(v), 16 x |V| 32-bit words: word 0
+ *     the vertex label, words 1..15 240 two-bit saturating groups;
+ *   - |E_l| per label (for freq(l) = |E_l|/|E|, Algorithm 2).
+ * vertex_labels[n_vertices]; src/dst/edge_labels[n_edges] (host memory).
+ * Errors: GSI_E_INVALID for n_vertices == 0 or >= 0xFFFFFFFF, an endpoint out
+ * of range, a self-loop, a repeated vertex pair, an edge label >=
+ * GSI_MAX_EDGE_LABELS or more than 2^31-1 edges; GSI_E_NOMEM if the arena is
+ * too small.  *out is valid only on GSI_OK.
+ */
+gsi_status gsi_graph_load(gsi_ctx *ctx, uint32_t n_vertices, const uint32_t *vertex_labels, uint64_t n_edges,
+                          const uint32_t *src, const uint32_t *dst, const uint32_t *edge_labels, uint32_t flags,
+                          gsi_graph **out);
+/* Same, with the four input arrays already in device memory (not modified). */
+gsi_status gsi_graph_load_device(gsi_ctx *ctx, uint32_t n_vertices, const uint32_t *vertex_labels,
+                                 uint64_t n_edges, const uint32_t *src, const uint32_t *dst,
+                                 const uint32_t *edge_labels, uint32_t flags, gsi_graph **out);
+gsi_status gsi_graph_free(gsi_graph *g);
+
+typedef struct {
+    uint32_t n_vertices;
+    uint64_t n_edges;
+    uint32_t n_edge_labels;  /* max edge label + 1 */
+    uint64_t total_groups;   /* sum over labels of |V(D)| */
+    uint32_t max_chain;      /* longest PCSR group chain (1 = no overflow) */
+    uint64_t device_bytes;   /* persistent bytes of PCSR + signatures */
+    double build_ms;         /* device time of the build */
+} gsi_graph_info;
+gsi_status gsi_graph_get_info(const gsi_graph *g, gsi_graph_info *out);
+/* |E_l| (undirected edges with label l); 0 for an absent label. */
+gsi_status gsi_graph_label_edges(const gsi_graph *g, uint32_t label, uint64_t *out);
+
+/* Copies the signature table (16 x n_vertices uint32, column-first: word w of
+ * vertex v at [w * n_vertices + v]) to host memory of `capacity_words`. */
+gsi_status gsi_graph_copy_signatures(const gsi_graph *g, uint32_t *host_dst, uint64_t capacity_words);
+/* Copies PCSR(G,label): gl as groups x 32 uint32 (pairs interleaved vertex,
+ * offset; offsets relative to this label's ci) and ci.  With host buffers of
+ * zero capacity only the sizes are returned. GSI_E_CAPACITY if too small. */
+gsi_status gsi_graph_copy_pcsr(const gsi_graph *g, uint32_t label, uint32_t *host_gl, uint64_t gl_capacity_words,
+                               uint32_t *host_ci, uint64_t ci_capacity, uint64_t *out_groups, uint64_t *out_ci_len);
+
+/* Query flags */
+#define GSI_COUNT_ONLY 0x1u        /* keep count and digest, write no rows */
+#define GSI_FILTER_LABEL_ONLY 0x2u /* test only: C(u) = vertices with u's label
+                                      (skips the signature test) */
+
+/* Optional controls of one query run (NULL = defaults). */
+typedef struct {
+    uint32_t flags;            /* GSI_COUNT_ONLY | GSI_FILTER_LABEL_ONLY */
+    const uint32_t *order;     /* NULL, or k query vertices: the matching order */
+    const uint32_t *first_edge;/* NULL, or k entries: first_edge[j] (j >= 1) is
+                                  the placed query vertex whose edge to order[j]
+                                  is e0 (Algorithm 4); needs `order` */
+    uint64_t max_rows;         /* 0, or a cap on rows of any intermediate table;
+                                  exceeding it returns GSI_E_CAPACITY */
+} gsi_query_options;
+
+/*
+ * Runs one query (Sec. III: filtering then joining):
+ *   1. query signatures S(u) (host) and the signature filter over the whole
+ *      table, all query vertices in one pass: C(u) as a |V|-bit bitset;
+ *   2. the matching order of Algorithm 2 (host, from |C(u)| and freq(l));
+ *   3. M = C(u_first); then for each further query vertex u one join level
+ *      (Algorithm 3 with Algorithm 4): locate N(v',l) through PCSR for every
+ *      linking edge, prefix-sum the first-edge list lengths into F (|GBA|),
+ *      keep x in N(v'_i,l0) iff x is not in row m_i, x is in C(u) and x is in
+ *      every other linking list; prefix-sum survivors; link m_i with each
+ *      survivor into M' (Prealloc-Combine, one join pass);
+ *   4. the last level writes rows in query-vertex order (or only counts) and
+ *      the order-independent digest.
+ * q_vertex_labels[k]; q_src/q_dst/q_edge_labels[q_edges] (host).
+ * Errors: GSI_E_INVALID for k == 0 or k > GSI_MAX_K, an endpoint >= k, a
+ * self-loop, a repeated pair, a disconnected Q or a bad option; GSI_E_NOMEM
+ * when the arena cannot hold a level.  An edge label absent from G is not an
+ * error: the result has 0 rows.
+ */
+gsi_status gsi_query_run(gsi_graph *g, uint32_t k, const uint32_t *q_vertex_labels, uint32_t q_edges,
+                         const uint32_t *q_src, const uint32_t *q_dst, const uint32_t *q_edge_labels,
+                         const gsi_query_options *opts, gsi_result **out);
+
+/* Runs only the signature filter (step 1 above) and copies C(u) bitsets
+ * (k x ceil(n/64) uint64, bit v%64 of word v/64 set iff v in C(u)) and
+ * counts (k uint32) to host memory. */
+gsi_status gsi_query_filter(gsi_graph *g, uint32_t k, const uint32_t *q_vertex_labels, uint32_t q_edges,
+                            const uint32_t *q_src, const uint32_t *q_dst, const uint32_t *q_edge_labels,
+                            uint64_t *host_bitsets, uint64_t capacity_words, uint32_t *host_counts);
+
+/* Number of embeddings (rows). */
+gsi_status gsi_result_count(const gsi_result *r, uint64_t *rows);
+/* Copies the rows (row-major, rows x k uint32, column j = f(j)) to host memory
+ * of capacity_rows rows; GSI_E_CAPACITY if too small; GSI_E_INVALID for a
+ * GSI_COUNT_ONLY result.  Row order is deterministic but unspecified. */
+gsi_status gsi_result_rows(const gsi_result *r, uint32_t *host_dst, uint64_t capacity_rows);
+/* Borrowed device pointer to the same rows; valid until gsi_result_free. */
+gsi_status gsi_result_device_rows(const gsi_result *r, const uint32_t **dev_rows);
+/* Order-independent digest: for each row t, h(t) = SplitMix64 finalizer of
+ * FNV-1a-64 over the 4k little-endian bytes of t; out = {sum of h mod 2^64,
+ * xor of h}. */
+gsi_status gsi_result_digest(const gsi_result *r, uint64_t out_sum_xor[2]);
+
+typedef struct {
+    uint32_t k;
+    uint32_t levels;                 /* join levels run (k-1 unless stopped early) */
+    uint32_t order[GSI_MAX_K];       /* matching order (query vertex ids) */
+    uint32_t first_edge[GSI_MAX_K];  /* first_edge[j]: placed end of e0 at level j */
+    uint32_t n_link[GSI_MAX_K];      /* |ES| at level j */
+    uint32_t cand[GSI_MAX_K];        /* |C(u)| per query vertex id */
+    uint64_t rows[GSI_MAX_K];        /* rows[j] = rows of M entering level j (rows[0] = |C(order[0])|) */
+    uint64_t gba[GSI_MAX_K];         /* |GBA| at level j */
+    uint64_t other_elems[GSI_MAX_K]; /* sum of non-first linking list lengths at level j */
+    uint64_t survivors[GSI_MAX_K];   /* rows of M' produced by level j */
+    double filter_ms;                /* host wall time of the filter step */
+    double join_ms;                  /* host wall time of the joins */
+    double total_ms;                 /* host wall time of the whole call */
+} gsi_stats;
+gsi_status gsi_result_stats(const gsi_result *r, gsi_stats *out);
+gsi_status gsi_result_free(gsi_result *r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSI_H */

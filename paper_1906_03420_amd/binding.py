@@ -1,0 +1,402 @@
+"""ctypes binding of libgsi.so: the same entry points as include/gsi.h.
+
+Argument marshalling only — every step of the matching path runs in the HIP
+library.  There is no CPU fallback: if libgsi.so is missing or the GPU call
+fails, the call raises.
+
+PyTorch provides device memory (the arena tensor) and the stream; see
+``Context``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgsi.so")
+
+GSI_OK, GSI_E_INVALID, GSI_E_NOMEM, GSI_E_DEVICE, GSI_E_CAPACITY, GSI_E_BUSY, GSI_E_INTERNAL = range(7)
+GSI_MAX_K = 32
+GSI_SIG_WORDS = 16
+GSI_CTX_PROFILE = 0x1
+GSI_GRAPH_TEST_FEW_HOME_GROUPS = 0x1
+GSI_COUNT_ONLY = 0x1
+GSI_FILTER_LABEL_ONLY = 0x2
+
+STATUS_NAMES = {0: "GSI_OK", 1: "GSI_E_INVALID", 2: "GSI_E_NOMEM", 3: "GSI_E_DEVICE", 4: "GSI_E_CAPACITY",
+                5: "GSI_E_BUSY", 6: "GSI_E_INTERNAL"}
+
+U32P = ctypes.POINTER(ctypes.c_uint32)
+U64P = ctypes.POINTER(ctypes.c_uint64)
+VP = ctypes.c_void_p
+
+
+class GsiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class gsi_options(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("hip_stream", VP), ("arena_ptr", VP), ("arena_bytes", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32)]
+
+
+class gsi_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double)]
+
+
+class gsi_graph_info(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_uint32), ("n_edges", ctypes.c_uint64), ("n_edge_labels", ctypes.c_uint32),
+                ("total_groups", ctypes.c_uint64), ("max_chain", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64),
+                ("build_ms", ctypes.c_double)]
+
+
+class gsi_query_options(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("order", U32P), ("first_edge", U32P), ("max_rows", ctypes.c_uint64)]
+
+
+class gsi_stats(ctypes.Structure):
+    K = GSI_MAX_K
+    _fields_ = [("k", ctypes.c_uint32), ("levels", ctypes.c_uint32), ("order", ctypes.c_uint32 * K),
+                ("first_edge", ctypes.c_uint32 * K), ("n_link", ctypes.c_uint32 * K), ("cand", ctypes.c_uint32 * K),
+                ("rows", ctypes.c_uint64 * K), ("gba", ctypes.c_uint64 * K), ("other_elems", ctypes.c_uint64 * K),
+                ("survivors", ctypes.c_uint64 * K), ("filter_ms", ctypes.c_double), ("join_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+
+# name -> (restype, argtypes) for every exported function of gsi.h
+SIGNATURES = {
+    "gsi_last_error": (ctypes.c_char_p, []),
+    "gsi_version": (ctypes.c_char_p, []),
+    "gsi_ctx_create": (ctypes.c_int, [ctypes.POINTER(gsi_options), ctypes.POINTER(VP)]),
+    "gsi_ctx_destroy": (ctypes.c_int, [VP]),
+    "gsi_ctx_memory": (ctypes.c_int, [VP, U64P, U64P]),
+    "gsi_ctx_kernel_stats": (ctypes.c_int, [VP, ctypes.POINTER(gsi_kernel_stat), ctypes.c_uint32, U32P]),
+    "gsi_ctx_kernel_stats_reset": (ctypes.c_int, [VP]),
+    "gsi_graph_bytes_needed": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint64, U64P]),
+    "gsi_graph_load": (ctypes.c_int, [VP, ctypes.c_uint32, U32P, ctypes.c_uint64, U32P, U32P, U32P, ctypes.c_uint32,
+                                      ctypes.POINTER(VP)]),
+    "gsi_graph_load_device": (ctypes.c_int, [VP, ctypes.c_uint32, VP, ctypes.c_uint64, VP, VP, VP, ctypes.c_uint32,
+                                             ctypes.POINTER(VP)]),
+    "gsi_graph_free": (ctypes.c_int, [VP]),
+    "gsi_graph_get_info": (ctypes.c_int, [VP, ctypes.POINTER(gsi_graph_info)]),
+    "gsi_graph_label_edges": (ctypes.c_int, [VP, ctypes.c_uint32, U64P]),
+    "gsi_graph_copy_signatures": (ctypes.c_int, [VP, U32P, ctypes.c_uint64]),
+    "gsi_graph_copy_pcsr": (ctypes.c_int, [VP, ctypes.c_uint32, U32P, ctypes.c_uint64, U32P, ctypes.c_uint64, U64P,
+                                           U64P]),
+    "gsi_query_run": (ctypes.c_int, [VP, ctypes.c_uint32, U32P, ctypes.c_uint32, U32P, U32P, U32P,
+                                     ctypes.POINTER(gsi_query_options), ctypes.POINTER(VP)]),
+    "gsi_query_filter": (ctypes.c_int, [VP, ctypes.c_uint32, U32P, ctypes.c_uint32, U32P, U32P, U32P, U64P,
+                                        ctypes.c_uint64, U32P]),
+    "gsi_result_count": (ctypes.c_int, [VP, U64P]),
+    "gsi_result_rows": (ctypes.c_int, [VP, U32P, ctypes.c_uint64]),
+    "gsi_result_device_rows": (ctypes.c_int, [VP, ctypes.POINTER(VP)]),
+    "gsi_result_digest": (ctypes.c_int, [VP, U64P]),
+    "gsi_result_stats": (ctypes.c_int, [VP, ctypes.POINTER(gsi_stats)]),
+    "gsi_result_free": (ctypes.c_int, [VP]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libgsi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError("libgsi.so is not built (run __graft_entry__.build()); there is no CPU fallback")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(st: int):
+    if st != GSI_OK:
+        raise GsiError(st, gsi_last_error())
+
+
+def _u32(a):
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    return a, a.ctypes.data_as(U32P)
+
+
+# --------------------------------------------------------------- raw calls
+def gsi_last_error() -> str:
+    return load_library().gsi_last_error().decode()
+
+
+def gsi_version() -> str:
+    return load_library().gsi_version().decode()
+
+
+def gsi_ctx_create(device: int, hip_stream: int, arena_ptr: int, arena_bytes: int, flags: int = 0) -> int:
+    o = gsi_options(device, hip_stream or None, arena_ptr, arena_bytes, flags)
+    h = VP()
+    _check(load_library().gsi_ctx_create(ctypes.byref(o), ctypes.byref(h)))
+    return h.value
+
+
+def gsi_ctx_destroy(ctx: int):
+    _check(load_library().gsi_ctx_destroy(ctx))
+
+
+def gsi_ctx_memory(ctx: int):
+    a, b = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load_library().gsi_ctx_memory(ctx, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def gsi_ctx_kernel_stats(ctx: int) -> list:
+    buf = (gsi_kernel_stat * 64)()
+    n = ctypes.c_uint32()
+    _check(load_library().gsi_ctx_kernel_stats(ctx, buf, 64, ctypes.byref(n)))
+    return [dict(name=buf[i].name.decode(), launches=buf[i].launches, total_ms=buf[i].total_ms,
+                 alg_bytes=buf[i].alg_bytes) for i in range(n.value)]
+
+
+def gsi_ctx_kernel_stats_reset(ctx: int):
+    _check(load_library().gsi_ctx_kernel_stats_reset(ctx))
+
+
+def gsi_graph_bytes_needed(n_vertices: int, n_edges: int) -> int:
+    out = ctypes.c_uint64()
+    _check(load_library().gsi_graph_bytes_needed(n_vertices, n_edges, ctypes.byref(out)))
+    return out.value
+
+
+def gsi_graph_load(ctx: int, n_vertices: int, vertex_labels, src, dst, edge_labels, flags: int = 0) -> int:
+    vl, vlp = _u32(vertex_labels)
+    s, sp = _u32(src)
+    d, dp = _u32(dst)
+    l, lp = _u32(edge_labels)
+    h = VP()
+    _check(load_library().gsi_graph_load(ctx, n_vertices, vlp, s.shape[0], sp, dp, lp, flags, ctypes.byref(h)))
+    return h.value
+
+
+def gsi_graph_load_device(ctx: int, n_vertices: int, vertex_labels_ptr: int, n_edges: int, src_ptr: int,
+                          dst_ptr: int, edge_labels_ptr: int, flags: int = 0) -> int:
+    h = VP()
+    _check(load_library().gsi_graph_load_device(ctx, n_vertices, vertex_labels_ptr, n_edges, src_ptr, dst_ptr,
+                                                edge_labels_ptr, flags, ctypes.byref(h)))
+    return h.value
+
+
+def gsi_graph_free(g: int):
+    _check(load_library().gsi_graph_free(g))
+
+
+def gsi_graph_get_info(g: int) -> dict:
+    i = gsi_graph_info()
+    _check(load_library().gsi_graph_get_info(g, ctypes.byref(i)))
+    return {f: getattr(i, f) for f, _ in gsi_graph_info._fields_}
+
+
+def gsi_graph_label_edges(g: int, label: int) -> int:
+    out = ctypes.c_uint64()
+    _check(load_library().gsi_graph_label_edges(g, label, ctypes.byref(out)))
+    return out.value
+
+
+def gsi_graph_copy_signatures(g: int, n_vertices: int) -> np.ndarray:
+    out = np.zeros((GSI_SIG_WORDS, n_vertices), np.uint32)
+    _check(load_library().gsi_graph_copy_signatures(g, out.ctypes.data_as(U32P), out.size))
+    return out
+
+
+def gsi_graph_copy_pcsr(g: int, label: int):
+    lib = load_library()
+    ng, nc = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib.gsi_graph_copy_pcsr(g, label, None, 0, None, 0, ctypes.byref(ng), ctypes.byref(nc)))
+    gl = np.zeros((ng.value, 32), np.uint32)
+    ci = np.zeros(nc.value, np.uint32)
+    if ng.value or nc.value:
+        _check(lib.gsi_graph_copy_pcsr(g, label, gl.ctypes.data_as(U32P), gl.size, ci.ctypes.data_as(U32P), ci.size,
+                                       ctypes.byref(ng), ctypes.byref(nc)))
+    return gl, ci
+
+
+def gsi_query_run(g: int, k: int, q_vertex_labels, q_src, q_dst, q_edge_labels, flags: int = 0, order=None,
+                  first_edge=None, max_rows: int = 0) -> int:
+    vl, vlp = _u32(q_vertex_labels)
+    s, sp = _u32(q_src)
+    d, dp = _u32(q_dst)
+    l, lp = _u32(q_edge_labels)
+    keep = []
+    o = gsi_query_options(flags, None, None, max_rows)
+    if order is not None:
+        a, p = _u32(order)
+        keep.append(a)
+        o.order = p
+    if first_edge is not None:
+        fe = np.array([0xFFFFFFFF if x is None else x for x in first_edge], np.uint32)
+        a, p = _u32(fe)
+        keep.append(a)
+        o.first_edge = p
+    h = VP()
+    _check(load_library().gsi_query_run(g, k, vlp, s.shape[0], sp, dp, lp, ctypes.byref(o), ctypes.byref(h)))
+    return h.value
+
+
+def gsi_query_filter(g: int, n_vertices: int, k: int, q_vertex_labels, q_src, q_dst, q_edge_labels):
+    vl, vlp = _u32(q_vertex_labels)
+    s, sp = _u32(q_src)
+    d, dp = _u32(q_dst)
+    l, lp = _u32(q_edge_labels)
+    words = (n_vertices + 63) // 64
+    bits = np.zeros((k, words), np.uint64)
+    cnt = np.zeros(k, np.uint32)
+    _check(load_library().gsi_query_filter(g, k, vlp, s.shape[0], sp, dp, lp, bits.ctypes.data_as(U64P), bits.size,
+                                           cnt.ctypes.data_as(U32P)))
+    return bits, cnt
+
+
+def gsi_result_count(r: int) -> int:
+    out = ctypes.c_uint64()
+    _check(load_library().gsi_result_count(r, ctypes.byref(out)))
+    return out.value
+
+
+def gsi_result_rows(r: int, k: int) -> np.ndarray:
+    n = gsi_result_count(r)
+    out = np.zeros((n, k), np.uint32)
+    _check(load_library().gsi_result_rows(r, out.ctypes.data_as(U32P), n))
+    return out
+
+
+def gsi_result_device_rows(r: int) -> int:
+    p = VP()
+    _check(load_library().gsi_result_device_rows(r, ctypes.byref(p)))
+    return p.value or 0
+
+
+def gsi_result_digest(r: int) -> tuple:
+    out = (ctypes.c_uint64 * 2)()
+    _check(load_library().gsi_result_digest(r, out))
+    return int(out[0]), int(out[1])
+
+
+def gsi_result_stats(r: int) -> dict:
+    s = gsi_stats()
+    _check(load_library().gsi_result_stats(r, ctypes.byref(s)))
+    k = s.k
+    lv = s.levels
+    return dict(k=k, levels=lv, order=list(s.order[:k]), first_edge=list(s.first_edge[:k]),
+                n_link=list(s.n_link[:k]), cand=list(s.cand[:k]), rows=list(s.rows[:k]), gba=list(s.gba[:k]),
+                other_elems=list(s.other_elems[:k]), survivors=list(s.survivors[:k]), filter_ms=s.filter_ms,
+                join_ms=s.join_ms, total_ms=s.total_ms)
+
+
+def gsi_result_free(r: int):
+    _check(load_library().gsi_result_free(r))
+
+
+# ------------------------------------------------------------ conveniences
+class Result:
+    def __init__(self, h: int, k: int):
+        self.h, self.k = h, k
+
+    @property
+    def count(self) -> int:
+        return gsi_result_count(self.h)
+
+    @property
+    def digest(self) -> tuple:
+        return gsi_result_digest(self.h)
+
+    def rows(self) -> np.ndarray:
+        return gsi_result_rows(self.h, self.k)
+
+    def sorted_rows(self) -> np.ndarray:
+        r = self.rows()
+        return r[np.lexsort(r.T[::-1])] if len(r) else r
+
+    def stats(self) -> dict:
+        return gsi_result_stats(self.h)
+
+    def free(self):
+        if self.h:
+            gsi_result_free(self.h)
+            self.h = 0
+
+
+class Graph:
+    def __init__(self, ctx: "Context", h: int, n: int):
+        self.ctx, self.h, self.n = ctx, h, n
+
+    def info(self) -> dict:
+        return gsi_graph_get_info(self.h)
+
+    def signatures(self) -> np.ndarray:
+        return gsi_graph_copy_signatures(self.h, self.n)
+
+    def pcsr(self, label: int):
+        return gsi_graph_copy_pcsr(self.h, label)
+
+    def query(self, q, flags: int = 0, order=None, first_edge=None, max_rows: int = 0) -> Result:
+        h = gsi_query_run(self.h, q.k, q.vlabel, q.src, q.dst, q.elabel, flags, order, first_edge, max_rows)
+        return Result(h, q.k)
+
+    def filter(self, q):
+        return gsi_query_filter(self.h, self.n, q.k, q.vlabel, q.src, q.dst, q.elabel)
+
+    def free(self):
+        if self.h:
+            gsi_graph_free(self.h)
+            self.h = 0
+
+
+class Context:
+    """A library context over a torch-allocated device arena on `device`,
+    using torch's current stream of that device."""
+
+    def __init__(self, arena_bytes: int, device: int = 0, flags: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the library has no CPU path")
+        load_library()
+        self.torch = torch
+        self.device = device
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda:%d" % device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.h = gsi_ctx_create(device, self.stream.cuda_stream, self.arena.data_ptr(), int(arena_bytes), flags)
+
+    def load(self, g, flags: int = 0) -> Graph:
+        h = gsi_graph_load(self.h, g.n, g.vlabel, g.src, g.dst, g.elabel, flags)
+        return Graph(self, h, g.n)
+
+    def load_device(self, n: int, vlabel_t, src_t, dst_t, elabel_t, flags: int = 0) -> Graph:
+        """Graph from uint32 arrays already on the device (torch int32 tensors
+        holding the uint32 bit patterns)."""
+        h = gsi_graph_load_device(self.h, n, vlabel_t.data_ptr(), int(src_t.numel()), src_t.data_ptr(),
+                                  dst_t.data_ptr(), elabel_t.data_ptr(), flags)
+        return Graph(self, h, n)
+
+    def memory(self):
+        return gsi_ctx_memory(self.h)
+
+    def kernel_stats(self) -> list:
+        return gsi_ctx_kernel_stats(self.h)
+
+    def kernel_stats_reset(self):
+        gsi_ctx_kernel_stats_reset(self.h)
+
+    def close(self):
+        if self.h:
+            gsi_ctx_destroy(self.h)
+            self.h = 0
+            self.arena = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

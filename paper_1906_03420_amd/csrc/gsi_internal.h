@@ -1,0 +1,264 @@
+// Internal declarations of the gfx950 subgraph-isomorphism library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <map>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "gsi.h"
+
+namespace gsi {
+
+constexpr uint32_t NONE32 = 0xFFFFFFFFu;
+constexpr uint32_t KEYS_PER_GROUP = GSI_PCSR_GPN - 1;  // 15 keys + (GID, END)
+constexpr uint32_t GROUP_WORDS = 2 * GSI_PCSR_GPN;      // 32 uint32 = 128 bytes
+constexpr uint32_t SIG_GROUPS = 240;                     // (512 - 32) / 2
+
+// ------------------------------------------------------------------ errors
+void set_error(const char *fmt, ...);
+void clear_error();
+
+struct Fail {
+    gsi_status st;
+};
+
+#define GSI_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            ::gsi::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                             __LINE__);                                                    \
+            throw ::gsi::Fail{GSI_E_DEVICE};                                               \
+        }                                                                                  \
+    } while (0)
+
+[[noreturn]] void fail(gsi_status st, const char *fmt, ...);
+
+// ------------------------------------------------------------------- arena
+// First-fit allocator over the caller's device buffer.  Long-lived blocks
+// (graph structures, result tables) are placed from the high end, per-call
+// scratch from the low end, so scratch holes coalesce back between calls.
+class Arena {
+  public:
+    void init(void *base, uint64_t size);
+    void *alloc(uint64_t bytes, bool high);  // nullptr when it does not fit
+    void release(void *p);
+    uint64_t used() const { return used_; }
+    uint64_t peak() const { return peak_; }
+    uint64_t largest_free() const;
+
+  private:
+    uintptr_t base_ = 0;
+    uint64_t size_ = 0;
+    std::map<uint64_t, uint64_t> free_;  // offset -> size
+    std::map<uint64_t, uint64_t> live_;  // offset -> size
+    uint64_t used_ = 0, peak_ = 0;
+};
+
+struct KernelRec {
+    int kid;
+    hipEvent_t a, b;
+    double bytes;
+};
+
+}  // namespace gsi
+
+struct gsi_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint32_t flags = 0;
+    gsi::Arena arena;
+    uint64_t *pinned = nullptr;  // host-pinned scalars for per-level readbacks
+    std::atomic<int> busy{0};
+    std::set<gsi_graph *> graphs;
+    std::set<gsi_result *> results;
+    // profiling
+    std::vector<std::string> knames;
+    std::vector<gsi::KernelRec> recs;
+    std::vector<hipEvent_t> free_events;
+    std::vector<gsi_kernel_stat> acc;
+};
+
+struct gsi_graph {
+    gsi_ctx *ctx = nullptr;
+    uint32_t n = 0;
+    uint64_t m = 0;
+    uint32_t nlab = 0;      // max edge label + 1
+    uint32_t flags = 0;
+    uint32_t *sig = nullptr;  // [16 * n] column-first
+    uint32_t *gl = nullptr;   // [total_groups * 32]
+    uint32_t *ci = nullptr;   // [2m]
+    std::vector<uint64_t> group_base;  // per label: first global group
+    std::vector<uint32_t> G;           // per label: |V(D)| groups
+    std::vector<uint32_t> H;           // per label: home groups the hash spreads over
+    std::vector<uint64_t> ci_base;     // per label: first ci entry
+    std::vector<uint64_t> edges;       // per label: |E_l| (undirected)
+    uint64_t total_groups = 0;
+    uint32_t max_chain = 0;
+    uint64_t bytes = 0;
+    double build_ms = 0;
+};
+
+struct gsi_result {
+    gsi_ctx *ctx = nullptr;
+    uint32_t k = 0;
+    uint64_t count = 0;
+    uint64_t digest[2] = {0, 0};
+    uint32_t *rows = nullptr;  // device, row-major count x k (arena, high end)
+    bool count_only = false;
+    gsi_stats stats{};
+};
+
+namespace gsi {
+
+// Profiled launch: records HIP events around `fn` on the context stream when
+// GSI_CTX_PROFILE is set, and checks the launch.
+int kernel_id(gsi_ctx *c, const char *name);
+hipEvent_t take_event(gsi_ctx *c);
+
+template <typename F>
+inline void launch(gsi_ctx *c, const char *name, double alg_bytes, F &&fn) {
+    if (c->flags & GSI_CTX_PROFILE) {
+        int kid = kernel_id(c, name);
+        hipEvent_t a = take_event(c), b = take_event(c);
+        GSI_HIP(hipEventRecord(a, c->stream));
+        fn();
+        GSI_HIP(hipGetLastError());
+        GSI_HIP(hipEventRecord(b, c->stream));
+        c->recs.push_back(KernelRec{kid, a, b, alg_bytes});
+    } else {
+        fn();
+        GSI_HIP(hipGetLastError());
+    }
+}
+
+// Scoped scratch allocations, released in reverse order on scope exit.
+struct Scratch {
+    gsi_ctx *c;
+    std::vector<void *> held;
+    explicit Scratch(gsi_ctx *cc) : c(cc) {}
+    ~Scratch() {
+        for (auto it = held.rbegin(); it != held.rend(); ++it) c->arena.release(*it);
+    }
+    template <typename T>
+    T *get(uint64_t count, const char *what) {
+        uint64_t bytes = count * sizeof(T);
+        if (bytes == 0) bytes = 256;
+        void *p = c->arena.alloc(bytes, false);
+        if (!p)
+            fail(GSI_E_NOMEM, "arena exhausted allocating %llu bytes for %s (largest free block %llu)",
+                 (unsigned long long)bytes, what, (unsigned long long)c->arena.largest_free());
+        held.push_back(p);
+        return static_cast<T *>(p);
+    }
+    void drop(void *p) {
+        for (auto it = held.begin(); it != held.end(); ++it)
+            if (*it == p) {
+                held.erase(it);
+                c->arena.release(p);
+                return;
+            }
+    }
+};
+
+template <typename T>
+T *persist(gsi_ctx *c, uint64_t count, const char *what) {
+    uint64_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = 256;
+    void *p = c->arena.alloc(bytes, true);
+    if (!p)
+        fail(GSI_E_NOMEM, "arena exhausted allocating %llu bytes for %s (largest free block %llu)",
+             (unsigned long long)bytes, what, (unsigned long long)c->arena.largest_free());
+    return static_cast<T *>(p);
+}
+
+// Reads back `n` uint64 values from device memory (synchronises the stream).
+void read_scalars(gsi_ctx *c, const uint64_t *dev, uint64_t *host, int n);
+void sync(gsi_ctx *c);
+
+// ------------------------------------------------------------- primitives
+void fill_u32(gsi_ctx *c, uint32_t *p, uint32_t value, uint64_t n);
+void fill_u64(gsi_ctx *c, uint64_t *p, uint64_t value, uint64_t n);
+// out[i] = sum_{j<i} in[j] for i in [0, n]; out has n+1 entries.
+void exclusive_scan(gsi_ctx *c, const uint32_t *in, uint64_t n, uint64_t *out, Scratch &s);
+// Stable LSD radix sort of `n` tuples held in `na` parallel uint32 arrays
+// (a[0..na-1]); pass p orders by bits [shift, shift+8) of array key_arr[p].
+// tmp holds na arrays of n entries.  Returns true if the result ended in tmp
+// (the caller swaps pointers).
+struct SortPass {
+    int key_arr;
+    int shift;
+};
+bool radix_sort(gsi_ctx *c, uint32_t n, int na, uint32_t *const *a, uint32_t *const *tmp,
+                const std::vector<SortPass> &passes, Scratch &s);
+
+// --------------------------------------------------------------- pieces
+void build_graph(gsi_graph *g, const uint32_t *d_vlabel, const uint32_t *d_src, const uint32_t *d_dst,
+                 const uint32_t *d_elabel);
+
+struct HostQuery {
+    uint32_t k = 0;
+    std::vector<uint32_t> vl, src, dst, el;
+    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> adj;  // (neighbour, label)
+};
+HostQuery validate_query(uint32_t k, const uint32_t *vl, uint32_t qm, const uint32_t *s, const uint32_t *d,
+                         const uint32_t *l);
+void run_filter(gsi_graph *g, const HostQuery &q, uint64_t *d_bits, uint32_t *d_counts);
+gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options *opt);
+
+}  // namespace gsi
+
+// ------------------------------------------------------- device helpers
+namespace gsi {
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// number of set bits of m strictly below this lane
+__device__ __forceinline__ uint32_t rank_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_sum(T v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T t = __shfl_up(v, o, 64);
+        if (lane >= (uint32_t)o) v += t;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_xor(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v ^= __shfl_xor(v, o, 64);
+    return v;
+}
+
+// PCSR home group (Sec. IV hash f): Knuth multiplicative hash of the vertex
+// id, reduced to [0, H) by a multiply-shift.
+__device__ __host__ __forceinline__ uint32_t pcsr_home(uint32_t v, uint32_t H) {
+    uint32_t x = v * 0x9E3779B1u;
+    return (uint32_t)(((uint64_t)x * (uint64_t)H) >> 32);
+}
+
+// Signature group of the key (edge label, neighbour label), Sec. III-A.
+__device__ __host__ __forceinline__ uint32_t sig_group(uint32_t elabel, uint32_t nlabel) {
+    uint64_t key = ((uint64_t)elabel << 32) | nlabel;
+    uint64_t hi = (key * 0x9E3779B97F4A7C15ull) >> 32;
+    return (uint32_t)((hi * (uint64_t)SIG_GROUPS) >> 32);
+}
+
+}  // namespace gsi

@@ -1,0 +1,739 @@
+// One query: signature filter (Sec. III-A), matching order (Algorithm 2) and
+// the vertex-at-a-time Prealloc-Combine join (Sec. V, Algorithms 3-4).
+//
+// Intermediate tables are column-major (column c of M at M + c*R): the link
+// step then writes every column of M' with fully coalesced stores and the
+// join reads one column of a row without touching the others.  The last
+// level writes rows in query-vertex order.
+//
+// Join level j, for the next query vertex u with linking edges ES:
+//   k_locate  one thread per row i: locate N(v,l) in PCSR for every e in ES
+//             (home group, probe the 15 keys of its 128-byte group, follow GID);
+//             bound_i = |N(v'_i, l0)| for the first edge e0 (Algorithm 4)
+//   scan      F = exclusive prefix sum of bound; |GBA| = F[R]
+//   k_join    the element index space [0, |GBA|) is cut into tiles of 256
+//             (one element per lane): the element at p belongs to the row i
+//             with F[i] <= p < F[i+1] and is x = N(v'_i, l0)[p - F[i]]; it is
+//             kept iff x is not in m_i (set subtraction), x is in C(u) (one
+//             bitset probe) and x is in every other linking list (binary
+//             search in the sorted list).  The tile's keep flags are written
+//             as one 64-bit ballot word per wave: GBA holds one bit per
+//             pre-allocated slot instead of a vertex id, so the join writes
+//             |GBA|/8 bytes, coalesced.
+//   scan      tile survivor counts -> tile offsets; |M'| = total
+//   k_link    every kept slot re-reads its x and writes (m_i, x) at its
+//             position in M' (order: parent row, then ascending x).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+
+#include "gsi_internal.h"
+
+namespace gsi {
+
+constexpr uint32_t QT = 256;  // threads per workgroup (4 waves)
+
+static uint32_t nblocks(uint64_t n, uint64_t per = QT) {
+    uint64_t b = (n + per - 1) / per;
+    if (b == 0) b = 1;
+    if (b > 0x7FFFFFFFull) fail(GSI_E_CAPACITY, "grid of %llu workgroups exceeds the launch limit",
+                                (unsigned long long)b);
+    return (uint32_t)b;
+}
+
+// ------------------------------------------------------------ validation
+HostQuery validate_query(uint32_t k, const uint32_t *vl, uint32_t qm, const uint32_t *s, const uint32_t *d,
+                         const uint32_t *l) {
+    if (k < 1 || k > GSI_MAX_K) fail(GSI_E_INVALID, "query must have 1..%d vertices", GSI_MAX_K);
+    if (!vl) fail(GSI_E_INVALID, "null query labels");
+    if (qm && (!s || !d || !l)) fail(GSI_E_INVALID, "null query edge array");
+    if (qm > (uint32_t)k * (k - 1) / 2) fail(GSI_E_INVALID, "too many query edges for a simple graph");
+    HostQuery q;
+    q.k = k;
+    q.vl.assign(vl, vl + k);
+    q.adj.assign(k, {});
+    std::vector<uint8_t> seen((size_t)k * k, 0);
+    for (uint32_t e = 0; e < qm; e++) {
+        uint32_t a = s[e], b = d[e];
+        if (a >= k || b >= k) fail(GSI_E_INVALID, "query edge %u has an endpoint >= k", e);
+        if (a == b) fail(GSI_E_INVALID, "query edge %u is a self-loop", e);
+        if (seen[(size_t)a * k + b]) fail(GSI_E_INVALID, "query edge %u repeats a vertex pair", e);
+        seen[(size_t)a * k + b] = seen[(size_t)b * k + a] = 1;
+        q.src.push_back(a);
+        q.dst.push_back(b);
+        q.el.push_back(l[e]);
+        q.adj[a].push_back({b, l[e]});
+        q.adj[b].push_back({a, l[e]});
+    }
+    std::vector<uint8_t> vis(k, 0);
+    std::vector<uint32_t> st{0};
+    vis[0] = 1;
+    uint32_t reached = 1;
+    while (!st.empty()) {
+        uint32_t x = st.back();
+        st.pop_back();
+        for (auto &p : q.adj[x])
+            if (!vis[p.first]) {
+                vis[p.first] = 1;
+                reached++;
+                st.push_back(p.first);
+            }
+    }
+    if (reached != k) fail(GSI_E_INVALID, "query graph is not connected");
+    return q;
+}
+
+// ------------------------------------------------------------------ filter
+struct FilterArgs {
+    uint32_t k;
+    uint32_t label_only;
+    uint32_t q[GSI_MAX_K][GSI_SIG_WORDS];
+};
+
+// Query signatures with the same encoding as the data table (Sec. III-A).
+static void query_signatures(const HostQuery &q, FilterArgs &fa) {
+    memset(&fa, 0, sizeof(fa));
+    fa.k = q.k;
+    for (uint32_t u = 0; u < q.k; u++) {
+        fa.q[u][0] = q.vl[u];
+        uint32_t cnt[SIG_GROUPS] = {0};
+        for (auto &p : q.adj[u]) cnt[sig_group(p.second, q.vl[p.first])]++;
+        for (uint32_t g = 0; g < SIG_GROUPS; g++)
+            if (cnt[g]) fa.q[u][1 + g / 16] |= (cnt[g] == 1 ? 1u : 3u) << (2 * (g % 16));
+    }
+}
+
+// One pass over the column-first table for all query vertices: a wave reads
+// word w of 64 consecutive signatures in one coalesced load, and its ballot
+// of "v in C(u)" is the bitset word of those 64 vertices.  Waves none of
+// whose vertices carries a query label skip words 1..15.
+__global__ __launch_bounds__(QT) void k_filter(const uint32_t *sig, uint32_t n, uint64_t nwords, FilterArgs fa,
+                                              uint64_t *bits, uint32_t *counts) {
+    __shared__ uint32_t s_cnt[GSI_MAX_K];
+    if (threadIdx.x < GSI_MAX_K) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t v = (uint64_t)blockIdx.x * QT + threadIdx.x;
+    const bool valid = v < n;
+    const uint32_t lane = lane_id();
+    const uint64_t wave_first = (uint64_t)blockIdx.x * QT + (threadIdx.x & ~63u);
+    uint32_t w[GSI_SIG_WORDS];
+    w[0] = valid ? sig[v] : NONE32;
+    bool lab = false;
+    for (uint32_t u = 0; u < fa.k; u++) lab |= (w[0] == fa.q[u][0]);
+    const bool need_rest = !fa.label_only && __ballot(valid && lab) != 0;
+#pragma unroll
+    for (int i = 1; i < GSI_SIG_WORDS; i++) w[i] = (need_rest && valid) ? sig[(uint64_t)i * n + v] : 0u;
+    for (uint32_t u = 0; u < fa.k; u++) {
+        bool ok = valid && w[0] == fa.q[u][0];
+        if (need_rest) {
+#pragma unroll
+            for (int i = 1; i < GSI_SIG_WORDS; i++) ok = ok && ((w[i] & fa.q[u][i]) == fa.q[u][i]);
+        }
+        uint64_t mask = __ballot(ok);
+        if (lane == 0 && wave_first < n) {
+            bits[(uint64_t)u * nwords + (wave_first >> 6)] = mask;
+            if (mask) atomicAdd(&s_cnt[u], (uint32_t)__popcll(mask));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < fa.k && s_cnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], s_cnt[threadIdx.x]);
+}
+
+static void filter_impl(gsi_graph *g, const HostQuery &q, bool label_only, uint64_t *bits, uint32_t *counts) {
+    gsi_ctx *c = g->ctx;
+    FilterArgs fa;
+    query_signatures(q, fa);
+    fa.label_only = label_only ? 1u : 0u;
+    uint64_t nwords = ((uint64_t)g->n + 63) / 64;
+    fill_u32(c, counts, 0, q.k);
+    double bytes = 64.0 * g->n + (double)q.k * nwords * 8;
+    launch(c, "filter", bytes, [&] {
+        hipLaunchKernelGGL(k_filter, nblocks(g->n), QT, 0, c->stream, g->sig, g->n, nwords, fa, bits, counts);
+    });
+}
+
+void run_filter(gsi_graph *g, const HostQuery &q, uint64_t *bits, uint32_t *counts) {
+    filter_impl(g, q, false, bits, counts);
+}
+
+// ----------------------------------------------------- M0 from a bitset
+__global__ void k_word_popc(const uint64_t *bits, uint64_t nwords, uint32_t *cnt) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nwords) cnt[i] = (uint32_t)__popcll(bits[i]);
+}
+__global__ void k_word_emit(const uint64_t *bits, uint64_t nwords, const uint64_t *off, uint32_t *out) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nwords) return;
+    uint64_t b = bits[i];
+    uint64_t o = off[i];
+    while (b) {
+        uint32_t t = (uint32_t)__ffsll((unsigned long long)b) - 1;
+        out[o++] = (uint32_t)(i * 64 + t);
+        b &= b - 1;
+    }
+}
+
+// ------------------------------------------------------------ join level
+struct EdgeRef {
+    const uint32_t *gl;  // this label's groups
+    const uint32_t *ci;  // this label's neighbour lists
+    uint32_t G, H;       // groups, home groups
+    uint32_t col;        // column of M holding the placed endpoint
+    uint32_t pad;
+};
+
+struct LevelArgs {
+    const uint32_t *M;
+    uint64_t R;
+    uint32_t j, ne, e0, k;
+    EdgeRef e[GSI_MAX_K];
+    const uint64_t *Cu;
+    uint32_t *loc;  // start at [e*R + i], length at [(ne+e)*R + i]
+    uint32_t *bound;
+    unsigned long long *other_sum;
+    const uint64_t *F;
+    uint64_t gba;
+    uint64_t *bitmap;
+    uint32_t *tile_cnt;
+    const uint64_t *tile_off;
+    uint32_t *Mn;
+    uint64_t S;
+    uint32_t *out;
+    unsigned long long *digest;
+    uint32_t qcol[GSI_MAX_K];  // query vertex -> column (last level)
+    uint32_t final_level, count_only;
+};
+
+// N(v,l) through PCSR (Sec. IV lookup): read the home group (8 x 16-byte
+// loads = its 128 bytes), probe the 15 key slots in ascending key order,
+// follow the GID chain.  Keys of a chain ascend, so meeting a larger key (or
+// the empty marker) ends the search.  Returns (offset, length) in ci.
+__device__ __forceinline__ uint2 pcsr_find(const uint32_t *gl, uint32_t G, uint32_t H, uint32_t v) {
+    if (G == 0) return make_uint2(0, 0);
+    uint32_t grp = pcsr_home(v, H);
+    for (uint32_t hop = 0; hop < G; hop++) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(gl + (uint64_t)grp * GROUP_WORDS);
+        uint32_t w[GROUP_WORDS];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            uint4 t = p[i];
+            w[4 * i] = t.x;
+            w[4 * i + 1] = t.y;
+            w[4 * i + 2] = t.z;
+            w[4 * i + 3] = t.w;
+        }
+#pragma unroll
+        for (uint32_t s = 0; s < KEYS_PER_GROUP; s++) {
+            uint32_t key = w[2 * s];
+            if (key == v) return make_uint2(w[2 * s + 1], w[2 * s + 3] - w[2 * s + 1]);
+            if (key > v) return make_uint2(0, 0);
+        }
+        grp = w[2 * KEYS_PER_GROUP];
+        if (grp == NONE32) break;
+    }
+    return make_uint2(0, 0);
+}
+
+__global__ __launch_bounds__(QT) void k_locate(LevelArgs a) {
+    const uint64_t i = (uint64_t)blockIdx.x * QT + threadIdx.x;
+    const bool valid = i < a.R;
+    uint64_t other = 0;
+    if (valid) {
+        for (uint32_t e = 0; e < a.ne; e++) {
+            const EdgeRef &er = a.e[e];
+            uint32_t v = a.M[(uint64_t)er.col * a.R + i];
+            uint2 r = pcsr_find(er.gl, er.G, er.H, v);
+            a.loc[(uint64_t)e * a.R + i] = r.x;
+            a.loc[(uint64_t)(a.ne + e) * a.R + i] = r.y;
+            if (e == a.e0) a.bound[i] = r.y;
+            else other += r.y;
+        }
+    }
+    other = wave_sum(other);
+    if (lane_id() == 0 && other) atomicAdd(a.other_sum, (unsigned long long)other);
+}
+
+// largest i in [lo, hi] with F[i] <= p (F non-decreasing, F[lo] <= p)
+__device__ __forceinline__ uint64_t row_of(const uint64_t *F, uint64_t lo, uint64_t hi, uint64_t p) {
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo + 1) / 2;
+        if (F[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool in_sorted(const uint32_t *list, uint32_t len, uint32_t x) {
+    uint32_t lo = 0, hi = len;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (list[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < len && list[lo] == x;
+}
+
+__device__ __forceinline__ void tile_rows(const LevelArgs &a, uint64_t p0, uint64_t *lo, uint64_t *hi) {
+    uint64_t last = p0 + QT - 1;
+    if (last >= a.gba) last = a.gba - 1;
+    *lo = row_of(a.F, 0, a.R - 1, p0);
+    *hi = row_of(a.F, *lo, a.R - 1, last);
+}
+
+__global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
+    __shared__ uint64_t s_lo, s_hi;
+    __shared__ uint32_t s_cnt[QT / 64];
+    const uint64_t p0 = (uint64_t)blockIdx.x * QT;
+    if (threadIdx.x == 0) tile_rows(a, p0, &s_lo, &s_hi);
+    __syncthreads();
+    const uint64_t p = p0 + threadIdx.x;
+    bool keep = false;
+    if (p < a.gba) {
+        const uint64_t i = row_of(a.F, s_lo, s_hi, p);
+        const uint32_t t = (uint32_t)(p - a.F[i]);
+        const uint32_t x = a.e[a.e0].ci[a.loc[(uint64_t)a.e0 * a.R + i] + t];
+        keep = (a.Cu[x >> 6] >> (x & 63)) & 1ull;
+        for (uint32_t c = 0; keep && c < a.j; c++) keep = a.M[(uint64_t)c * a.R + i] != x;
+        for (uint32_t e = 0; keep && e < a.ne; e++) {
+            if (e == a.e0) continue;
+            uint32_t st = a.loc[(uint64_t)e * a.R + i];
+            uint32_t len = a.loc[(uint64_t)(a.ne + e) * a.R + i];
+            keep = in_sorted(a.e[e].ci + st, len, x);
+        }
+    }
+    const uint64_t mask = __ballot(keep);
+    const uint32_t w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        a.bitmap[(uint64_t)blockIdx.x * (QT / 64) + w] = mask;
+        s_cnt[w] = (uint32_t)__popcll(mask);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int q = 0; q < QT / 64; q++) t += s_cnt[q];
+        a.tile_cnt[blockIdx.x] = t;
+    }
+}
+
+// FNV-1a-64 over the four little-endian bytes of one 32-bit word
+__device__ __forceinline__ uint64_t fnv_word(uint64_t h, uint32_t v) {
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+        h ^= (v >> (8 * b)) & 0xFFu;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+// SplitMix64 output mixing (Steele, Lea, Flood 2014)
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
+    __shared__ uint64_t s_lo, s_hi;
+    const uint64_t tile = blockIdx.x;
+    if (a.tile_off[tile + 1] == a.tile_off[tile]) return;  // whole tile empty (uniform)
+    const uint64_t p0 = tile * QT;
+    if (threadIdx.x == 0) tile_rows(a, p0, &s_lo, &s_hi);
+    __syncthreads();
+    const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+    const uint64_t *words = a.bitmap + tile * (QT / 64);
+    const uint64_t word = words[w];
+    const bool keep = (word >> lane) & 1ull;
+    uint64_t before = 0;
+    for (uint32_t q = 0; q < w; q++) before += (uint64_t)__popcll(words[q]);
+    const uint64_t pos = a.tile_off[tile] + before + rank_below(word);
+    uint64_t h = 0;
+    if (keep && pos < a.S) {
+        const uint64_t p = p0 + threadIdx.x;
+        const uint64_t i = row_of(a.F, s_lo, s_hi, p);
+        const uint32_t x = a.e[a.e0].ci[a.loc[(uint64_t)a.e0 * a.R + i] + (uint32_t)(p - a.F[i])];
+        if (!a.final_level) {
+            for (uint32_t c = 0; c < a.j; c++) a.Mn[(uint64_t)c * a.S + pos] = a.M[(uint64_t)c * a.R + i];
+            a.Mn[(uint64_t)a.j * a.S + pos] = x;
+        } else {
+            uint64_t f = 14695981039346656037ull;
+            for (uint32_t u = 0; u < a.k; u++) {
+                uint32_t c = a.qcol[u];
+                uint32_t val = c < a.j ? a.M[(uint64_t)c * a.R + i] : x;
+                if (!a.count_only) a.out[pos * a.k + u] = val;
+                f = fnv_word(f, val);
+            }
+            h = mix64(f);
+        }
+    }
+    if (a.final_level) {
+        uint64_t sum = wave_sum(h);
+        uint64_t xr = wave_xor(h);
+        if (lane == 0 && word) {
+            atomicAdd(&a.digest[0], (unsigned long long)sum);
+            atomicXor(&a.digest[1], (unsigned long long)xr);
+        }
+    }
+}
+
+// rows of a one-column table (k = 1): copy out and digest
+__global__ __launch_bounds__(QT) void k_emit_single(const uint32_t *M, uint64_t R, uint32_t *out, uint32_t count_only,
+                                                   unsigned long long *digest) {
+    const uint64_t i = (uint64_t)blockIdx.x * QT + threadIdx.x;
+    uint64_t h = 0;
+    if (i < R) {
+        uint32_t v = M[i];
+        if (!count_only) out[i] = v;
+        h = mix64(fnv_word(14695981039346656037ull, v));
+    }
+    uint64_t sum = wave_sum(h), xr = wave_xor(h);
+    if (lane_id() == 0) {
+        atomicAdd(&digest[0], (unsigned long long)sum);
+        atomicXor(&digest[1], (unsigned long long)xr);
+    }
+}
+
+// ---------------------------------------------------------------- planner
+// Algorithm 2: the first vertex minimises |C(u)|/deg(u); afterwards the
+// unplaced vertex adjacent to the placed ones with the least score, where
+// every placement multiplies the scores of its neighbours by freq(l) =
+// |E_l|/|E|.  Ties go to the smaller query vertex id.  First edge e0
+// (Algorithm 4): the linking edge of least freq(l), ties to the placed end
+// that was placed first.
+static void make_plan(const gsi_graph *g, const HostQuery &q, const std::vector<uint32_t> &cand,
+                      std::vector<uint32_t> &order, std::vector<uint32_t> &e0src) {
+    const uint32_t k = q.k;
+    order.clear();
+    e0src.assign(k, NONE32);
+    auto freq = [&](uint32_t l) -> double {
+        if (l >= g->nlab || g->m == 0) return 0.0;
+        return (double)g->edges[l] / (double)g->m;
+    };
+    if (k == 1) {
+        order.push_back(0);
+        return;
+    }
+    std::vector<double> score(k);
+    for (uint32_t u = 0; u < k; u++) score[u] = (double)cand[u] / (double)q.adj[u].size();
+    std::vector<uint8_t> placed(k, 0);
+    std::vector<uint32_t> pos(k, NONE32);
+    auto place = [&](uint32_t u) {
+        pos[u] = (uint32_t)order.size();
+        order.push_back(u);
+        placed[u] = 1;
+        for (auto &p : q.adj[u]) score[p.first] *= freq(p.second);
+    };
+    uint32_t first = 0;
+    for (uint32_t u = 1; u < k; u++)
+        if (score[u] < score[first]) first = u;
+    place(first);
+    while (order.size() < k) {
+        uint32_t best = NONE32;
+        for (uint32_t u = 0; u < k; u++) {
+            if (placed[u]) continue;
+            bool linked = false;
+            for (auto &p : q.adj[u]) linked |= placed[p.first] != 0;
+            if (!linked) continue;
+            if (best == NONE32 || score[u] < score[best]) best = u;
+        }
+        uint32_t e0 = NONE32;
+        double fbest = 0;
+        for (auto &p : q.adj[best]) {
+            if (!placed[p.first]) continue;
+            double f = freq(p.second);
+            if (e0 == NONE32 || f < fbest || (f == fbest && pos[p.first] < pos[e0])) {
+                e0 = p.first;
+                fbest = f;
+            }
+        }
+        e0src[order.size()] = e0;
+        place(best);
+    }
+}
+
+// ---------------------------------------------------------------- driver
+namespace {
+struct Block {
+    gsi_ctx *c;
+    void *p = nullptr;
+    explicit Block(gsi_ctx *cc) : c(cc) {}
+    ~Block() { reset(); }
+    void reset() {
+        if (p) c->arena.release(p);
+        p = nullptr;
+    }
+    template <typename T>
+    T *get(uint64_t count, const char *what) {
+        reset();
+        uint64_t bytes = count * sizeof(T);
+        p = c->arena.alloc(bytes ? bytes : 256, false);
+        if (!p)
+            fail(GSI_E_NOMEM, "arena exhausted allocating %llu bytes for %s (largest free block %llu)",
+                 (unsigned long long)bytes, what, (unsigned long long)c->arena.largest_free());
+        return static_cast<T *>(p);
+    }
+};
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+}  // namespace
+
+gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options *opt) {
+    gsi_ctx *c = g->ctx;
+    auto t0 = std::chrono::steady_clock::now();
+    const uint32_t k = q.k;
+    const uint32_t flags = opt ? opt->flags : 0u;
+    if (flags & ~(GSI_COUNT_ONLY | GSI_FILTER_LABEL_ONLY)) fail(GSI_E_INVALID, "unknown query flag");
+    const bool count_only = (flags & GSI_COUNT_ONLY) != 0;
+    const uint64_t max_rows = opt ? opt->max_rows : 0;
+
+    std::vector<uint32_t> order, e0src;
+    if (opt && opt->order) {
+        order.assign(opt->order, opt->order + k);
+        std::vector<uint8_t> seen(k, 0);
+        for (uint32_t j = 0; j < k; j++) {
+            if (order[j] >= k || seen[order[j]]) fail(GSI_E_INVALID, "order is not a permutation of 0..k-1");
+            seen[order[j]] = 1;
+            if (j == 0) continue;
+            bool linked = false;
+            for (auto &p : q.adj[order[j]])
+                for (uint32_t i = 0; i < j; i++) linked |= p.first == order[i];
+            if (!linked) fail(GSI_E_INVALID, "order[%u] has no edge to an earlier vertex", j);
+        }
+        if (opt->first_edge) {
+            e0src.assign(opt->first_edge, opt->first_edge + k);
+            for (uint32_t j = 1; j < k; j++) {
+                bool ok = false;
+                for (auto &p : q.adj[order[j]])
+                    for (uint32_t i = 0; i < j; i++) ok |= (p.first == order[i] && p.first == e0src[j]);
+                if (!ok) fail(GSI_E_INVALID, "first_edge[%u] is not a placed neighbour of order[%u]", j, j);
+            }
+        }
+    } else if (opt && opt->first_edge) {
+        fail(GSI_E_INVALID, "first_edge needs order");
+    }
+
+    // a result that never reaches the caller gives its rows back to the arena
+    struct ResultGuard {
+        gsi_result *r;
+        ~ResultGuard() {
+            if (r) {
+                r->ctx->arena.release(r->rows);
+                delete r;
+            }
+        }
+        gsi_result *operator->() { return r; }
+        gsi_result *release() {
+            gsi_result *t = r;
+            r = nullptr;
+            return t;
+        }
+    } res{new gsi_result()};
+    res->ctx = c;
+    res->k = k;
+    res->count_only = count_only;
+    gsi_stats &st = res->stats;
+    st.k = k;
+    for (uint32_t j = 0; j < GSI_MAX_K; j++) st.order[j] = st.first_edge[j] = NONE32;
+
+    auto finish = [&]() -> gsi_result * {
+        st.total_ms = ms_since(t0);
+        return res.release();
+    };
+
+    // a query edge whose label G lacks has no match
+    for (uint32_t e = 0; e < q.el.size(); e++) {
+        uint32_t l = q.el[e];
+        if (l >= g->nlab || g->edges[l] == 0) return finish();
+    }
+
+    Scratch s(c);
+    const uint64_t nwords = ((uint64_t)g->n + 63) / 64;
+    uint64_t *bits = s.get<uint64_t>(nwords * k, "candidate bitsets");
+    uint32_t *dcnt = s.get<uint32_t>(k, "candidate counts");
+    uint64_t *dscal = s.get<uint64_t>(4, "level scalars");
+    auto tf = std::chrono::steady_clock::now();
+    filter_impl(g, q, (flags & GSI_FILTER_LABEL_ONLY) != 0, bits, dcnt);
+    std::vector<uint32_t> cand(k);
+    {
+        uint64_t tmp[GSI_MAX_K / 2 + 1];
+        read_scalars(c, reinterpret_cast<const uint64_t *>(dcnt), tmp, (int)((k + 1) / 2));
+        memcpy(cand.data(), tmp, 4ull * k);
+    }
+    st.filter_ms = ms_since(tf);
+    for (uint32_t u = 0; u < k; u++) st.cand[u] = cand[u];
+    for (uint32_t u = 0; u < k; u++)
+        if (cand[u] == 0) return finish();
+
+    if (order.empty()) make_plan(g, q, cand, order, e0src);
+    if (e0src.empty()) {
+        // order given without first edges: least freq(l), earliest placed end
+        e0src.assign(k, NONE32);
+        for (uint32_t j = 1; j < k; j++) {
+            double fb = 0;
+            for (uint32_t i = 0; i < j; i++)
+                for (auto &p : q.adj[order[j]])
+                    if (p.first == order[i]) {
+                        double f = (double)g->edges[p.second] / (double)g->m;
+                        if (e0src[j] == NONE32 || f < fb) {
+                            e0src[j] = order[i];
+                            fb = f;
+                        }
+                    }
+        }
+    }
+    for (uint32_t j = 0; j < k; j++) {
+        st.order[j] = order[j];
+        st.first_edge[j] = e0src[j];
+    }
+    std::vector<uint32_t> col(k, NONE32);
+    for (uint32_t j = 0; j < k; j++) col[order[j]] = j;
+
+    auto tj = std::chrono::steady_clock::now();
+    unsigned long long *digest = reinterpret_cast<unsigned long long *>(dscal);  // dscal[0..1]
+    unsigned long long *other_sum = reinterpret_cast<unsigned long long *>(dscal + 2);
+
+    // M0 = C(order[0]), ascending
+    uint64_t R = cand[order[0]];
+    if (max_rows && R > max_rows) fail(GSI_E_CAPACITY, "rows exceed max_rows");
+    Block Mb(c);
+    uint32_t *M = Mb.get<uint32_t>(R, "first table");
+    {
+        Scratch s0(c);
+        uint32_t *wc = s0.get<uint32_t>(nwords, "word counts");
+        uint64_t *wo = s0.get<uint64_t>(nwords + 1, "word offsets");
+        const uint64_t *b0 = bits + (uint64_t)order[0] * nwords;
+        launch(c, "first_table", 8.0 * nwords, [&] {
+            hipLaunchKernelGGL(k_word_popc, nblocks(nwords), QT, 0, c->stream, b0, nwords, wc);
+        });
+        exclusive_scan(c, wc, nwords, wo, s0);
+        launch(c, "first_table", 16.0 * nwords + 4.0 * R, [&] {
+            hipLaunchKernelGGL(k_word_emit, nblocks(nwords), QT, 0, c->stream, b0, nwords, (const uint64_t *)wo, M);
+        });
+    }
+    st.rows[0] = R;
+    fill_u64(c, dscal, 0, 4);
+
+    if (k == 1) {
+        uint32_t *out = count_only ? nullptr : persist<uint32_t>(c, R, "result rows");
+        res->rows = out;
+        launch(c, "emit", 8.0 * R, [&] {
+            hipLaunchKernelGGL(k_emit_single, nblocks(R), QT, 0, c->stream, M, R, out, count_only ? 1u : 0u, digest);
+        });
+        uint64_t dg[2];
+        read_scalars(c, dscal, dg, 2);
+        res->rows = out;
+        res->count = R;
+        res->digest[0] = dg[0];
+        res->digest[1] = dg[1];
+        st.join_ms = ms_since(tj);
+        return finish();
+    }
+
+    for (uint32_t j = 1; j < k; j++) {
+        const uint32_t u = order[j];
+        const bool final_level = (j == k - 1);
+        st.rows[j] = R;
+        LevelArgs a;
+        memset(&a, 0, sizeof(a));
+        a.M = M;
+        a.R = R;
+        a.j = j;
+        a.k = k;
+        a.Cu = bits + (uint64_t)u * nwords;
+        uint32_t ne = 0;
+        for (uint32_t i = 0; i < j; i++)
+            for (auto &p : q.adj[u])
+                if (p.first == order[i]) {
+                    uint32_t l = p.second;
+                    EdgeRef &er = a.e[ne];
+                    er.gl = g->gl + g->group_base[l] * GROUP_WORDS;
+                    er.ci = g->ci + g->ci_base[l];
+                    er.G = g->G[l];
+                    er.H = g->H[l];
+                    er.col = i;
+                    if (order[i] == e0src[j]) a.e0 = ne;
+                    ne++;
+                }
+        a.ne = ne;
+        st.n_link[j] = ne;
+        for (uint32_t v = 0; v < k; v++) a.qcol[v] = col[v];
+        a.final_level = final_level ? 1u : 0u;
+        a.count_only = count_only ? 1u : 0u;
+
+        Scratch ls(c);
+        a.loc = ls.get<uint32_t>(2ull * ne * R, "located lists");
+        a.bound = ls.get<uint32_t>(R, "row bounds");
+        uint64_t *F = ls.get<uint64_t>(R + 1, "offsets F");
+        a.F = F;
+        a.other_sum = other_sum;
+        fill_u64(c, dscal + 2, 0, 1);
+        launch(c, "locate", (double)R * (4.0 * ne + 128.0 * ne + 8.0 * ne + 4.0), [&] {
+            hipLaunchKernelGGL(k_locate, nblocks(R), QT, 0, c->stream, a);
+        });
+        exclusive_scan(c, a.bound, R, F, ls);
+        uint64_t sc[2];
+        GSI_HIP(hipMemcpyAsync(dscal + 3, F + R, 8, hipMemcpyDeviceToDevice, c->stream));
+        read_scalars(c, dscal + 2, sc, 2);
+        const uint64_t gba = sc[1];
+        st.gba[j] = gba;
+        st.other_elems[j] = sc[0];
+        st.levels = j;
+        if (gba == 0) {
+            st.survivors[j] = 0;
+            return finish();
+        }
+        a.gba = gba;
+        const uint64_t ntiles = (gba + QT - 1) / QT;
+        a.bitmap = ls.get<uint64_t>(ntiles * (QT / 64), "GBA bitmap");
+        a.tile_cnt = ls.get<uint32_t>(ntiles, "tile counts");
+        uint64_t *toff = ls.get<uint64_t>(ntiles + 1, "tile offsets");
+        a.tile_off = toff;
+        double jb = 4.0 * gba + (double)R * (8.0 + 8.0 * ne + 4.0 * j) + 4.0 * (double)sc[0] + gba / 8.0 + 4.0 * ntiles;
+        launch(c, "join", jb, [&] { hipLaunchKernelGGL(k_join, nblocks(gba), QT, 0, c->stream, a); });
+        exclusive_scan(c, a.tile_cnt, ntiles, toff, ls);
+        uint64_t S;
+        read_scalars(c, toff + ntiles, &S, 1);
+        st.survivors[j] = S;
+        if (S == 0) return finish();
+        if (max_rows && S > max_rows) fail(GSI_E_CAPACITY, "rows exceed max_rows at level %u", j);
+        a.S = S;
+        Block Mn(c);
+        double lb = (double)S * (4.0 + 4.0 * j) + gba / 8.0 + 8.0 * ntiles;
+        if (final_level) {
+            if (!count_only) {
+                a.out = persist<uint32_t>(c, S * k, "result rows");
+                res->rows = a.out;
+                lb += 4.0 * k * S;
+            }
+            a.digest = digest;
+        } else {
+            a.Mn = Mn.get<uint32_t>((uint64_t)(j + 1) * S, "next table");
+            lb += 4.0 * (j + 1) * S;
+        }
+        launch(c, final_level ? "link_final" : "link", lb, [&] {
+            hipLaunchKernelGGL(k_link, (uint32_t)ntiles, QT, 0, c->stream, a);
+        });
+        if (final_level) {
+            uint64_t dg[2];
+            read_scalars(c, dscal, dg, 2);
+            res->rows = a.out;
+            res->count = S;
+            res->digest[0] = dg[0];
+            res->digest[1] = dg[1];
+            st.join_ms = ms_since(tj);
+            return finish();
+        }
+        // M' replaces M; level scratch goes with `ls`
+        Mb.reset();
+        Mb.p = Mn.p;
+        Mn.p = nullptr;
+        M = a.Mn;
+        R = S;
+    }
+    return finish();
+}
+
+}  // namespace gsi

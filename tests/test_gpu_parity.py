@@ -1,0 +1,223 @@
+"""GPU parity: every step of the HIP path against the CPU oracle, through the
+C ABI.  Integer work, so every comparison is bit-exact."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import spec
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1906_03420_amd as gsi
+    c = gsi.Context(8 << 30)
+    yield c
+    c.close()
+
+
+def _sorted(a):
+    return a[np.lexsort(a.T[::-1])] if len(a) else a
+
+
+def check_query(dg, g, q, og=None, threads=4, **kw):
+    print("query k=%d m=%d" % (q.k, q.m), flush=True)
+    r = dg.query(q, **kw)
+    want = (og or oracle.OracleGraph(g)).match(q, threads=threads)
+    assert want.status == 0
+    assert r.count == want.count
+    if not kw.get("flags", 0) & 1:
+        np.testing.assert_array_equal(r.sorted_rows(), want.tuples)
+    assert r.digest == want.digest
+    st = r.stats()
+    r.free()
+    return st
+
+
+# ------------------------------------------------------------ structures
+@pytest.mark.parametrize("name,flags", [("er1k", 0), ("er1k", 1), ("rand", 0), ("rand", 1), ("star", 0),
+                                        ("example", 0)])
+def test_pcsr_and_signatures_bit_exact(ctx, name, flags):
+    if name == "er1k":
+        g = w.config_graph("er1k")
+    elif name == "rand":
+        g = w.random_small_graph(300, 0.05, 3, 5, 11)
+    elif name == "star":
+        g = w.star_graph(700)
+    else:
+        g, _ = w.paper_example()
+    print("graph", name, flags, flush=True)
+    dg = ctx.load(g, flags)
+    want = spec.pcsr(g, degenerate=bool(flags))
+    info = dg.info()
+    assert info["n_edge_labels"] == int(g.elabel.max()) + 1
+    assert info["total_groups"] == sum(gl.shape[0] for gl, _ in want.values())
+    for l in range(info["n_edge_labels"]):
+        gl, ci = dg.pcsr(l)
+        if l not in want:
+            assert gl.shape[0] == 0 and ci.shape[0] == 0
+            continue
+        np.testing.assert_array_equal(gl, want[l][0])
+        np.testing.assert_array_equal(ci, want[l][1])
+    if flags:
+        assert info["max_chain"] > 1
+    np.testing.assert_array_equal(dg.signatures(), spec.signature_table(g))
+    dg.free()
+
+
+def test_filter_bit_exact(ctx):
+    g = w.config_graph("er1k")
+    dg = ctx.load(g)
+    sig = spec.signature_table(g)
+    mk = w.QueryMaker(g)
+    for i in range(8):
+        q = w.config_query(g, "er1k", i, maker=mk)
+        bits, cnt = dg.filter(q)
+        cands = spec.filter_candidates(sig, spec.query_signatures(q))
+        np.testing.assert_array_equal(bits, spec.filter_bitsets(cands, g.n))
+        assert cnt.tolist() == [len(c) for c in cands]
+    dg.free()
+
+
+# ------------------------------------------------------------- end to end
+def test_er1k_all_queries(ctx):
+    g = w.config_graph("er1k")
+    dg = ctx.load(g)
+    og = oracle.OracleGraph(g)
+    mk = w.QueryMaker(g)
+    for i in range(8):
+        q = w.config_query(g, "er1k", i, maker=mk)
+        check_query(dg, g, q, og)
+    dg.free()
+
+
+@pytest.mark.parametrize("seed", range(25))
+def test_random_graphs(ctx, seed):
+    r = np.random.default_rng(seed)
+    n = int(r.integers(5, 400))
+    g = w.random_small_graph(n, float(r.uniform(0.02, 0.4)) if n < 100 else 0.03, int(r.integers(1, 4)),
+                             int(r.integers(1, 4)), seed)
+    if g.m == 0:
+        return
+    dg = ctx.load(g)
+    og = oracle.OracleGraph(g)
+    for t in range(3):
+        k = int(r.integers(1, 7))
+        q = w.random_connected_query(k, int(r.integers(0, 4)), int(g.vlabel.max()) + 1, int(g.elabel.max()) + 1,
+                                     seed * 100 + t)
+        check_query(dg, g, q, og)
+    dg.free()
+
+
+def test_closed_forms(ctx):
+    perm = lambda n, k: math.factorial(n) // math.factorial(n - k)
+    g = w.complete_graph(9)
+    dg = ctx.load(g)
+    for k in range(1, 8):
+        for q in (w.clique_query(k), w.path_query(k), w.star_query(k)):
+            r = dg.query(q)
+            assert r.count == perm(9, k)
+            r.free()
+    dg.free()
+    g = w.cycle_graph(40)
+    dg = ctx.load(g)
+    for k in (2, 5, 17, 32):
+        r = dg.query(w.path_query(k))
+        assert r.count == 80
+        r.free()
+    r = dg.query(w.cycle_query(7))
+    assert r.count == 0
+    r.free()
+    dg.free()
+    g = w.complete_bipartite(4, 6, 0, 1)
+    dg = ctx.load(g)
+    r = dg.query(w.star_query(5, 0, 1))
+    assert r.count == 4 * math.factorial(6) // math.factorial(2)
+    r.free()
+    dg.free()
+
+
+def test_edge_cases(ctx):
+    import paper_1906_03420_amd as gsi
+    g = w.config_graph("er1k")
+    dg = ctx.load(g)
+    og = oracle.OracleGraph(g)
+    # k = 1: all vertices of the label
+    q = w.make_query([2], [], [])
+    st = check_query(dg, g, q, og)
+    assert st["cand"][0] == int((g.vlabel == 2).sum())
+    # absent edge label / absent vertex label -> 0 rows
+    for q in (w.make_query([0, 1], [(0, 1)], [5]), w.make_query([0, 9], [(0, 1)], [0])):
+        r = dg.query(q)
+        assert r.count == 0 and r.rows().shape == (0, 2)
+        r.free()
+    # invalid queries
+    for bad in (w.make_query([0, 0, 0], [(0, 1)], [0]),          # disconnected
+                w.make_query([0, 0], [(0, 0)], [0]),              # self-loop
+                w.make_query([0, 0], [(0, 1), (1, 0)], [0, 0])):  # repeated pair
+        with pytest.raises(gsi.GsiError) as e:
+            dg.query(bad)
+        assert e.value.status == gsi.GSI_E_INVALID
+    # count-only keeps count and digest
+    mk = w.QueryMaker(g)
+    q = w.config_query(g, "er1k", 0, maker=mk)
+    a = dg.query(q)
+    b = dg.query(q, flags=gsi.GSI_COUNT_ONLY)
+    assert (a.count, a.digest) == (b.count, b.digest)
+    with pytest.raises(gsi.GsiError):
+        b.rows()
+    a.free(); b.free()
+    dg.free()
+    # invalid graphs
+    for bad in (w.make_graph(3, [0, 0, 0], [(0, 0)], [0]), w.make_graph(3, [0, 0, 0], [(0, 1), (1, 0)], [0, 1]),
+                w.make_graph(3, [0, 0, 0], [(0, 5)], [0])):
+        with pytest.raises(gsi.GsiError) as e:
+            ctx.load(bad)
+        assert e.value.status == gsi.GSI_E_INVALID
+    live, _ = ctx.memory()
+    assert live == 0
+
+
+def test_levels_match_spec(ctx):
+    g = w.config_graph("er1k")
+    dg = ctx.load(g)
+    sig = spec.signature_table(g)
+    mk = w.QueryMaker(g)
+    nb = spec.neighbour_lists(g)
+    for i in range(8):
+        q = w.config_query(g, "er1k", i, maker=mk)
+        cands = spec.filter_candidates(sig, spec.query_signatures(q))
+        r = dg.query(q)
+        st = r.stats()
+        order, e0 = spec.plan(q, [len(c) for c in cands], spec.label_frequency(g))
+        assert st["order"] == order
+        assert st["first_edge"][1:] == e0[1:]
+        M, lev = spec.join_levels(g, q, cands, order, e0, nb)
+        for j, L in enumerate(lev, start=1):
+            assert (st["rows"][j], st["gba"][j], st["survivors"][j]) == (L["R"], L["GBA"], L["S"])
+        r.free()
+    dg.free()
+
+
+def test_paper_example_join_numbers(ctx, golden_dir):
+    import paper_1906_03420_amd as gsi
+    gold = json.load(open(os.path.join(golden_dir, "paper_example.json")))
+    g, q = w.paper_example()
+    dg = ctx.load(g)
+    for e0_u2, key in ((1, "gba_e0_label_a"), (0, "gba_e0_label_b")):
+        r = dg.query(q, flags=gsi.GSI_FILTER_LABEL_ONLY, order=[0, 1, 2, 3], first_edge=[None, 0, e0_u2, 1])
+        st = r.stats()
+        assert st["cand"] == [1, 100, 101, 101]
+        assert st["gba"][2] == gold[key]["value"]
+        assert r.rows().tolist() == [gold["single_match"]["tuple"]]
+        r.free()
+    r = dg.query(q)
+    assert r.rows().tolist() == [gold["single_match"]["tuple"]]
+    r.free()
+    dg.free()

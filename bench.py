@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark of the subgraph-isomorphism hot path on one MI355X.
+
+One step = one pass of the whole path over the workload: build the device
+structures (PCSR for every edge label, signature table) from the edge list
+already resident in HBM, then run every query of the query set one at a time
+(filter, plan, join levels, result rows in HBM with their digest).
+
+Workload (default "ba1m"): Barabasi-Albert graph with 1,000,000 vertices and
+9,999,945 undirected edges, 32 vertex labels Zipf(1.1), 8 edge labels
+uniform; 100 random-walk queries with 6..12 vertices.  Synthetic, seeded.
+
+Prints ONE JSON line.  Fields beyond the common contract:
+  roofline      the kernel with the largest share of device time in the timed
+                steps: algorithmic bytes / its summed HIP-event duration,
+                against the 8 TB/s HBM peak
+  cpu_baseline  the CPU oracle (count + digest of every embedding) on the
+                same graph and queries, all host threads
+  queries_per_s, latency_ms {p50, p99}: per query, submit -> result ready
+  parity        GPU counts and digests against the stored oracle values
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "embeddings/s and queries/s (batched vs single) on one MI355X; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+# kernels of the path's own steps: signature filter, PCSR locate, join
+# (set subtraction + intersections), link (Prealloc-Combine table write)
+HOT_KERNELS = ("k_filter", "k_locate", "k_join", "k_link")
+
+WORKLOAD_TEXT = {
+    "ba1m": "BA graph 1,000,000 vertices / 9,999,945 edges, 32 vertex labels Zipf(1.1), 8 edge labels uniform; "
+            "100 random-walk queries of 6-12 vertices; single-query path",
+    "er1k": "ER graph 1,000 vertices / 5,000 edges, 4 vertex labels, 2 edge labels; 8 random-walk queries of 4 "
+            "vertices; single-query path",
+}
+
+
+def host_threads() -> int:
+    env = os.environ.get("OMP_NUM_THREADS")
+    n = os.cpu_count() or 1
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, min(n, 16))
+
+
+def load_golden(name):
+    path = os.path.join(ROOT, "tests", "golden", "%s.json" % name)
+    if not os.path.exists(path):
+        return None
+    return json.load(open(path))
+
+
+def make_workload(name):
+    import workloads as w
+    g = w.config_graph(name)
+    mk = w.QueryMaker(g)
+    gold = load_golden(name)
+    qs = []
+    nq = w.CONFIGS[name]["nq"]
+    for i in range(nq):
+        attempt = gold["queries"][i]["attempt"] if gold else 0
+        qs.append(w.config_query(g, name, i, attempt=attempt, maker=mk))
+    mk.close()
+    return g, qs, gold
+
+
+def cpu_baseline(g, qs, threads):
+    import oracle
+    t0 = time.perf_counter()
+    og = oracle.OracleGraph(g)
+    total = 0
+    for q in qs:
+        r = og.match(q, threads=threads, tuples=False)
+        total += r.count
+    dt = time.perf_counter() - t0
+    og.close()
+    return dict(value=total / dt, unit="embeddings/s", cores=threads, kind="oracle",
+                sample="whole workload: adjacency build + all %d queries (count + digest of every embedding), "
+                       "%.2f s wall" % (len(qs), dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ba1m", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--arena-gb", type=float, default=48.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device copy of this size (a reference kernel for HBM counters)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (asked for %d)" % max(args.gpus, world),
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1906_03420_amd as gsi
+
+    g, qs, gold = make_workload(args.workload)
+    dev = torch.device("cuda:0")
+    as_t = lambda a: torch.from_numpy(a.view(np.int32)).to(dev)
+    vl_t, s_t, d_t, l_t = as_t(g.vlabel), as_t(g.src), as_t(g.dst), as_t(g.elabel)
+    torch.cuda.synchronize()
+
+    arena = int(args.arena_gb * (1 << 30))
+    ctx = None
+    if args.copy_probe_mib:
+        a = torch.empty(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def step():
+        t0 = time.perf_counter()
+        dg = ctx.load_device(g.n, vl_t, s_t, d_t, l_t)
+        tb = time.perf_counter()
+        lat, out = [], []
+        for q in qs:
+            tq = time.perf_counter()
+            r = dg.query(q)
+            lat.append(time.perf_counter() - tq)
+            out.append((r.count, r.digest))
+            r.free()
+        dg.free()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, tb - t0, lat, out
+
+    def matches(out):
+        return all(c == q["count"] and [str(d[0]), str(d[1])] == q["digest"] for (c, d), q in zip(out, gold["queries"]))
+
+    # timed region: plain context, no per-launch events
+    ctx = gsi.Context(arena)
+    parity_ok = None
+    for _ in range(args.warmup):
+        _, _, _, out = step()
+        if gold:
+            parity_ok = matches(out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat_all, build_all, emb = [], [], 0
+    for _ in range(args.steps):
+        dt, bt, lat, out = step()
+        lat_all += lat
+        build_all.append(bt)
+        emb += sum(c for c, _ in out)
+        if gold:
+            parity_ok = matches(out) if parity_ok is None else (parity_ok and matches(out))
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ctx.close()
+
+    # roofline: the same steps again with HIP events recorded around every
+    # launch on the library's stream
+    ctx = gsi.Context(arena, flags=gsi.GSI_CTX_PROFILE)
+    tp = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    prof_ms = (time.perf_counter() - tp) / args.steps * 1e3
+    ks = ctx.kernel_stats()
+    ctx.close()
+    ks = [k for k in ks if k["launches"]]
+    dev_ms = sum(k["total_ms"] for k in ks)
+    dom = max((k for k in ks if k["name"] in HOT_KERNELS), key=lambda k: k["total_ms"])
+    achieved = dom["alg_bytes"] / (dom["total_ms"] * 1e-3) / 1e9
+    lat_ms = np.array(lat_all) * 1e3
+    nq_total = len(qs) * args.steps
+
+    res = dict(
+        metric=METRIC,
+        value=emb / total,
+        unit="embeddings/s",
+        n_gpus=1,
+        steps=args.steps,
+        warmup=args.warmup,
+        ms_per_step=total / args.steps * 1e3,
+        higher_is_better=True,
+        scaling="weak",
+        vs_baseline=None,
+        dtype="u32",
+        data="synthetic",
+        config=dict(workload=WORKLOAD_TEXT[args.workload], name=args.workload, queries=len(qs),
+                    path="single-query", embeddings_per_step=emb // args.steps),
+        queries_per_s=nq_total / total,
+        latency_ms=dict(p50=float(np.percentile(lat_ms, 50)), p99=float(np.percentile(lat_ms, 99)),
+                        max=float(lat_ms.max())),
+        build_ms=float(np.mean(build_all) * 1e3),
+        parity=("bit-exact counts+digests vs oracle, %d/%d queries" % (len(qs), len(qs))) if parity_ok
+        else ("MISMATCH" if parity_ok is False else "no stored oracle values"),
+        roofline=dict(kernel=dom["name"], bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=achieved / HBM_PEAK_GBS, traffic=None, launches=dom["launches"],
+                      avg_launch_us=dom["total_ms"] / dom["launches"] * 1e3,
+                      share_of_device_time=dom["total_ms"] / dev_ms if dev_ms else None,
+                      measured="HIP events around every launch in %d profiled steps (%.1f ms/step with events)"
+                               % (args.steps, prof_ms)),
+        kernels={k["name"]: dict(launches=k["launches"], ms=round(k["total_ms"], 3),
+                                 gbs=round(k["alg_bytes"] / (k["total_ms"] * 1e-3) / 1e9, 1) if k["total_ms"] else None)
+                 for k in ks},
+    )
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(g, qs, host_threads())
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

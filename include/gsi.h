@@ -221,7 +221,8 @@ typedef struct {
     uint32_t cand[GSI_MAX_K];        /* |C(u)| per query vertex id */
     uint64_t rows[GSI_MAX_K];        /* rows[j] = rows of M entering level j (rows[0] = |C(order[0])|) */
     uint64_t gba[GSI_MAX_K];         /* |GBA| at level j */
-    uint64_t other_elems[GSI_MAX_K]; /* sum of non-first linking list lengths at level j */
+    uint64_t other_elems[GSI_MAX_K]; /* sum of non-first linking list lengths at level j
+                                        (gathered in GSI_CTX_PROFILE contexts only, else 0) */
     uint64_t survivors[GSI_MAX_K];   /* rows of M' produced by level j */
     double filter_ms;                /* host wall time of the filter step */
     double join_ms;                  /* host wall time of the joins */

@@ -43,9 +43,10 @@ static int bits_for(uint64_t maxval) {
 
 enum : uint32_t { ERR_RANGE = 1, ERR_SELF = 2, ERR_LABEL = 4, ERR_DUP = 8, ERR_CLAIM1 = 16 };
 
-__global__ void k_validate_expand(const uint32_t *src, const uint32_t *dst, const uint32_t *el, uint64_t m,
-                                  uint32_t n, uint32_t *os, uint32_t *od, uint32_t *ol, uint32_t *err,
-                                  uint32_t *maxlab) {
+__global__ __launch_bounds__(BT) void k_validate_expand(const uint32_t *src, const uint32_t *dst,
+                                                        const uint32_t *el, uint64_t m, uint32_t n, uint32_t *os,
+                                                        uint32_t *od, uint32_t *ol, uint32_t *err,
+                                                        uint32_t *maxlab_part) {
     uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool valid = e < m;
     uint32_t a = 0, b = 0, l = 0;
@@ -63,14 +64,23 @@ __global__ void k_validate_expand(const uint32_t *src, const uint32_t *dst, cons
             l = 0;
         }
     }
-    // every lane of the wave takes part in the reduction
+    // every lane of the wave takes part in the reduction; one partial maximum
+    // per workgroup (no same-address atomics)
+    __shared__ uint32_t s_max[BT / 64];
     uint32_t wl = l;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         uint32_t t = __shfl_xor(wl, o, 64);
         wl = t > wl ? t : wl;
     }
-    if (lane_id() == 0) atomicMax(maxlab, wl);
+    if (lane_id() == 0) s_max[threadIdx.x >> 6] = wl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t mx = 0;
+#pragma unroll
+        for (int q = 0; q < BT / 64; q++) mx = s_max[q] > mx ? s_max[q] : mx;
+        maxlab_part[blockIdx.x] = mx;
+    }
     if (!valid) return;
     os[2 * e] = a;
     od[2 * e] = b;
@@ -78,6 +88,23 @@ __global__ void k_validate_expand(const uint32_t *src, const uint32_t *dst, cons
     os[2 * e + 1] = b;
     od[2 * e + 1] = a;
     ol[2 * e + 1] = l;
+}
+
+__global__ __launch_bounds__(1024) void k_max_u32(const uint32_t *part, uint64_t n, uint32_t *out) {
+    __shared__ uint32_t s_m[16];
+    uint32_t mx = 0;
+    for (uint64_t i = threadIdx.x; i < n; i += 1024) mx = part[i] > mx ? part[i] : mx;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t t = __shfl_xor(mx, o, 64);
+        mx = t > mx ? t : mx;
+    }
+    if (lane_id() == 0) s_m[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 16; q++) mx = s_m[q] > mx ? s_m[q] : mx;
+        *out = mx;
+    }
 }
 
 // after sorting by (src, dst): equal neighbours are repeated vertex pairs
@@ -326,11 +353,13 @@ void build_graph(gsi_graph *g, const uint32_t *vl, const uint32_t *src, const ui
         A[i] = s.get<uint32_t>(nd, "sort buffer");
         B[i] = s.get<uint32_t>(nd, "sort buffer");
     }
-    if (m)
-        launch(c, "validate_expand", 12.0 * m + 24.0 * m, [&] {
-            hipLaunchKernelGGL(k_validate_expand, blocks(m), BT, 0, c->stream, src, dst, el, m, n, A[0], A[1], A[2],
-                               err, maxlab);
-        });
+    if (m) {
+        uint32_t nb = blocks(m);
+        uint32_t *mpart = s.get<uint32_t>(nb, "label maxima");
+        launch(c, "k_validate_expand", 12.0 * m + 24.0 * m, k_validate_expand, nb, BT, src, dst, el, m, n, A[0], A[1],
+               A[2], err, mpart);
+        launch(c, "k_max_u32", 4.0 * nb, k_max_u32, 1, 1024, (const uint32_t *)mpart, (uint64_t)nb, maxlab);
+    }
     uint64_t hs[3];
     read_scalars(c, scal, hs, 3);
     uint32_t e0 = (uint32_t)hs[0];
@@ -350,9 +379,7 @@ void build_graph(gsi_graph *g, const uint32_t *vl, const uint32_t *src, const ui
         bool t = radix_sort(c, (uint32_t)nd, 3, A, B, passes, s);
         cur = t ? B : A;
         uint32_t **other = t ? A : B;
-        launch(c, "check_dup", 8.0 * nd, [&] {
-            hipLaunchKernelGGL(k_check_dup, blocks(nd), BT, 0, c->stream, cur[0], cur[1], nd, err);
-        });
+        launch(c, "k_check_dup", 8.0 * nd, k_check_dup, blocks(nd), BT, cur[0], cur[1], nd, err);
         std::vector<SortPass> lp;
         for (int sh = 0; sh < lb; sh += 8) lp.push_back({2, sh});
         bool t2 = radix_sort(c, (uint32_t)nd, 3, cur, other, lp, s);
@@ -369,9 +396,7 @@ void build_graph(gsi_graph *g, const uint32_t *vl, const uint32_t *src, const ui
     uint32_t *head = s.get<uint32_t>(nd, "run heads");
     uint64_t *hscan = s.get<uint64_t>(nd + 1, "run scan");
     if (m)
-        launch(c, "segments", 12.0 * nd, [&] {
-            hipLaunchKernelGGL(k_segments, blocks(nd), BT, 0, c->stream, S, L, nd, seg, seg_hi, head);
-        });
+        launch(c, "k_segments", 12.0 * nd, k_segments, blocks(nd), BT, S, L, nd, seg, seg_hi, head);
     exclusive_scan(c, head, nd, hscan, s);
     uint64_t R;
     read_scalars(c, hscan + nd, &R, 1);
@@ -380,16 +405,11 @@ void build_graph(gsi_graph *g, const uint32_t *vl, const uint32_t *src, const ui
     uint32_t *run_vid = s.get<uint32_t>(R, "run vertex");
     uint32_t *run_lab = s.get<uint32_t>(R, "run label");
     if (m)
-        launch(c, "runs", 12.0 * nd, [&] {
-            hipLaunchKernelGGL(k_runs, blocks(nd), BT, 0, c->stream, S, L, head, hscan, nd, run_start, run_vid,
-                               run_lab);
-        });
+        launch(c, "k_runs", 12.0 * nd, k_runs, blocks(nd), BT, S, L, head, hscan, nd, run_start, run_vid, run_lab);
     uint64_t *lab_rb = s.get<uint64_t>(2 * (uint64_t)nlab + 2, "label runs");
     uint64_t *lab_re = lab_rb + nlab + 1;
     if (nlab)
-        launch(c, "label_runs", 32.0 * nlab, [&] {
-            hipLaunchKernelGGL(k_label_runs, blocks(nlab), BT, 0, c->stream, seg, seg_hi, hscan, nlab, lab_rb, lab_re);
-        });
+        launch(c, "k_label_runs", 32.0 * nlab, k_label_runs, blocks(nlab), BT, seg, seg_hi, hscan, nlab, lab_rb, lab_re);
     std::vector<uint64_t> h_rb(nlab), h_re(nlab), h_lo(nlab), h_hi(nlab);
     if (nlab) {
         GSI_HIP(hipMemcpyAsync(h_rb.data(), lab_rb, 8ull * nlab, hipMemcpyDeviceToHost, c->stream));
@@ -449,9 +469,7 @@ void build_graph(gsi_graph *g, const uint32_t *vl, const uint32_t *src, const ui
         uint32_t *rid2 = s.get<uint32_t>(R, "run id tmp");
         uint32_t *cnt = s.get<uint32_t>(R, "home counts");
         fill_u32(c, cnt, 0, R);
-        launch(c, "home", 16.0 * R, [&] {
-            hipLaunchKernelGGL(k_home, blocks(R), BT, 0, c->stream, run_vid, run_lab, R, lt, key, rid, cnt);
-        });
+        launch(c, "k_home", 16.0 * R, k_home, blocks(R), BT, run_vid, run_lab, R, lt, key, rid, cnt);
         std::vector<SortPass> kp;
         int kb = bits_for(R - 1);
         for (int sh = 0; sh < kb; sh += 8) kp.push_back({0, sh});
@@ -463,57 +481,35 @@ void build_graph(gsi_graph *g, const uint32_t *vl, const uint32_t *src, const ui
         exclusive_scan(c, cnt, R, gstart, s);
         uint32_t *need = s.get<uint32_t>(R, "overflow need");
         uint32_t *empt = s.get<uint32_t>(R, "empty flag");
-        launch(c, "overflow_flags", 12.0 * R, [&] {
-            hipLaunchKernelGGL(k_overflow_flags, blocks(R), BT, 0, c->stream, cnt, R, need, empt);
-        });
+        launch(c, "k_overflow_flags", 12.0 * R, k_overflow_flags, blocks(R), BT, cnt, R, need, empt);
         uint64_t *nscan = s.get<uint64_t>(R + 1, "need scan");
         uint64_t *escan = s.get<uint64_t>(R + 1, "empty scan");
         exclusive_scan(c, need, R, nscan, s);
         exclusive_scan(c, empt, R, escan, s);
         uint32_t *elist = s.get<uint32_t>(R, "empty list");
         fill_u32(c, elist, NONE32, R);
-        launch(c, "empty_list", 16.0 * R, [&] {
-            hipLaunchKernelGGL(k_empty_list, blocks(R), BT, 0, c->stream, empt, escan, R, d_rb, d_G, nlab, elist);
-        });
-        launch(c, "claim1", 32.0 * nlab, [&] {
-            hipLaunchKernelGGL(k_claim1, blocks(nlab), BT, 0, c->stream, nscan, escan, d_rb, d_G, nlab, err);
-        });
+        launch(c, "k_empty_list", 16.0 * R, k_empty_list, blocks(R), BT, empt, escan, R, d_rb, d_G, nlab, elist);
+        launch(c, "k_claim1", 32.0 * nlab, k_claim1, blocks(nlab), BT, nscan, escan, d_rb, d_G, nlab, err);
         uint32_t *next = s.get<uint32_t>(R, "chain next");
         uint32_t *owner = s.get<uint32_t>(R, "chain owner");
         uint32_t *cidx = s.get<uint32_t>(R, "chain index");
         fill_u32(c, next, NONE32, R);
         fill_u32(c, owner, NONE32, R);
         fill_u32(c, maxchain, 1, 1);
-        launch(c, "chains", 12.0 * R, [&] {
-            hipLaunchKernelGGL(k_chains, blocks(R), BT, 0, c->stream, need, nscan, elist, R, d_rb, d_G, nlab, next,
-                               owner, cidx, maxchain);
-        });
+        launch(c, "k_chains", 12.0 * R, k_chains, blocks(R), BT, need, nscan, elist, R, d_rb, d_G, nlab, next, owner, cidx, maxchain);
         uint64_t *kfirst = s.get<uint64_t>(R, "group first key");
         uint32_t *nkeys = s.get<uint32_t>(R, "group keys");
         uint32_t *gdeg = s.get<uint32_t>(R, "group degree");
-        launch(c, "group_keys", 32.0 * R, [&] {
-            hipLaunchKernelGGL(k_group_keys, blocks(R), BT, 0, c->stream, cnt, gstart, owner, cidx, sorted_rid,
-                               run_start, R, nd, d_rb, d_G, nlab, kfirst, nkeys, gdeg);
-        });
+        launch(c, "k_group_keys", 32.0 * R, k_group_keys, blocks(R), BT, cnt, gstart, owner, cidx, sorted_rid, run_start, R, nd, d_rb, d_G, nlab, kfirst, nkeys, gdeg);
         uint64_t *gci = s.get<uint64_t>(R + 1, "group ci start");
         exclusive_scan(c, gdeg, R, gci, s);
         uint32_t *run_off = s.get<uint32_t>(R, "run offset");
-        launch(c, "write_groups", 128.0 * R + 24.0 * R, [&] {
-            hipLaunchKernelGGL(k_write_groups, blocks(R), BT, 0, c->stream, kfirst, nkeys, gci, next, sorted_rid,
-                               run_start, run_vid, R, nd, d_rb, d_G, d_seg, nlab, g->gl, run_off);
-        });
-        launch(c, "scatter_ci", 24.0 * nd, [&] {
-            hipLaunchKernelGGL(k_scatter_ci, blocks(nd), BT, 0, c->stream, D, L, hscan, run_start, run_off, d_seg,
-                               nd, g->ci);
-        });
+        launch(c, "k_write_groups", 128.0 * R + 24.0 * R, k_write_groups, blocks(R), BT, kfirst, nkeys, gci, next, sorted_rid, run_start, run_vid, R, nd, d_rb, d_G, d_seg, nlab, g->gl, run_off);
+        launch(c, "k_scatter_ci", 24.0 * nd, k_scatter_ci, blocks(nd), BT, D, L, hscan, run_start, run_off, d_seg, nd, g->ci);
     }
-    launch(c, "sig_labels", 8.0 * n + 60.0 * n, [&] {
-        hipLaunchKernelGGL(k_sig_labels, blocks(n), BT, 0, c->stream, vl, n, g->sig);
-    });
+    launch(c, "k_sig_labels", 8.0 * n + 60.0 * n, k_sig_labels, blocks(n), BT, vl, n, g->sig);
     if (nd)
-        launch(c, "sig_pairs", 20.0 * nd, [&] {
-            hipLaunchKernelGGL(k_sig_pairs, blocks(nd), BT, 0, c->stream, S, D, L, vl, nd, n, g->sig);
-        });
+        launch(c, "k_sig_pairs", 20.0 * nd, k_sig_pairs, blocks(nd), BT, S, D, L, vl, nd, n, g->sig);
     read_scalars(c, scal, hs, 3);
     if ((uint32_t)hs[0] & ERR_CLAIM1) fail(GSI_E_INTERNAL, "PCSR: not enough empty groups (Claim 1)");
     g->max_chain = R ? (uint32_t)hs[2] : 0;

@@ -1,6 +1,7 @@
 // Internal declarations of the gfx950 subgraph-isomorphism library.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -116,23 +117,25 @@ struct gsi_result {
 
 namespace gsi {
 
-// Profiled launch: records HIP events around `fn` on the context stream when
-// GSI_CTX_PROFILE is set, and checks the launch.
+// Kernel launch on the context stream.  With GSI_CTX_PROFILE the launch goes
+// through hipExtLaunchKernelGGL with a start and a stop event that the
+// command processor records with the dispatch itself, so the measured span is
+// the kernel's own execution; the pair is kept with the kernel's algorithmic
+// bytes until gsi_ctx_kernel_stats drains it.
 int kernel_id(gsi_ctx *c, const char *name);
 hipEvent_t take_event(gsi_ctx *c);
 
-template <typename F>
-inline void launch(gsi_ctx *c, const char *name, double alg_bytes, F &&fn) {
+template <typename K, typename... Args>
+inline void launch(gsi_ctx *c, const char *name, double alg_bytes, K kernel, dim3 grid, dim3 block,
+                   Args... args) {
     if (c->flags & GSI_CTX_PROFILE) {
         int kid = kernel_id(c, name);
         hipEvent_t a = take_event(c), b = take_event(c);
-        GSI_HIP(hipEventRecord(a, c->stream));
-        fn();
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, c->stream, a, b, 0, args...);
         GSI_HIP(hipGetLastError());
-        GSI_HIP(hipEventRecord(b, c->stream));
         c->recs.push_back(KernelRec{kid, a, b, alg_bytes});
     } else {
-        fn();
+        hipLaunchKernelGGL(kernel, grid, block, 0, c->stream, args...);
         GSI_HIP(hipGetLastError());
     }
 }
@@ -184,8 +187,10 @@ void sync(gsi_ctx *c);
 // ------------------------------------------------------------- primitives
 void fill_u32(gsi_ctx *c, uint32_t *p, uint32_t value, uint64_t n);
 void fill_u64(gsi_ctx *c, uint64_t *p, uint64_t value, uint64_t n);
-// out[i] = sum_{j<i} in[j] for i in [0, n]; out has n+1 entries.
-void exclusive_scan(gsi_ctx *c, const uint32_t *in, uint64_t n, uint64_t *out, Scratch &s);
+// out[i] = sum_{j<i} in[j] for i in [0, n]; out has n+1 entries.  When
+// `total` is given the sum is also written there (device memory).
+void exclusive_scan(gsi_ctx *c, const uint32_t *in, uint64_t n, uint64_t *out, Scratch &s,
+                    uint64_t *total = nullptr);
 // Stable LSD radix sort of `n` tuples held in `na` parallel uint32 arrays
 // (a[0..na-1]); pass p orders by bits [shift, shift+8) of array key_arr[p].
 // tmp holds na arrays of n entries.  Returns true if the result ended in tmp

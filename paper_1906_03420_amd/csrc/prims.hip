@@ -21,11 +21,11 @@ static uint32_t grid_for(uint64_t n, uint32_t per_block, uint32_t cap = 65536) {
 
 void fill_u32(gsi_ctx *c, uint32_t *p, uint32_t v, uint64_t n) {
     if (!n) return;
-    launch(c, "fill", 4.0 * n, [&] { hipLaunchKernelGGL(k_fill<uint32_t>, grid_for(n, 1024), 256, 0, c->stream, p, v, n); });
+    launch(c, "k_fill", 4.0 * n, k_fill<uint32_t>, grid_for(n, 1024), 256, p, v, n);
 }
 void fill_u64(gsi_ctx *c, uint64_t *p, uint64_t v, uint64_t n) {
     if (!n) return;
-    launch(c, "fill", 8.0 * n, [&] { hipLaunchKernelGGL(k_fill<uint64_t>, grid_for(n, 1024), 256, 0, c->stream, p, v, n); });
+    launch(c, "k_fill", 8.0 * n, k_fill<uint64_t>, grid_for(n, 1024), 256, p, v, n);
 }
 
 // ------------------------------------------------------------------- scan
@@ -68,7 +68,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t *in
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_partials(uint64_t *part, uint64_t nb, uint64_t *total) {
+__global__ __launch_bounds__(1024) void k_scan_partials(uint64_t *part, uint64_t nb, uint64_t *total,
+                                                       uint64_t *total2) {
     uint64_t carry = 0;
     for (uint64_t c0 = 0; c0 < nb; c0 += 1024) {
         uint64_t idx = c0 + threadIdx.x;
@@ -78,7 +79,10 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint64_t *part, uint64_t
         if (idx < nb) part[idx] = carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0) *total = carry;
+    if (threadIdx.x == 0) {
+        *total = carry;
+        if (total2) *total2 = carry;
+    }
 }
 
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t *in, uint64_t n, const uint64_t *part,
@@ -102,23 +106,49 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t *in,
     }
 }
 
-void exclusive_scan(gsi_ctx *c, const uint32_t *in, uint64_t n, uint64_t *out, Scratch &s) {
+// whole scan in one workgroup (1024 threads x 8 consecutive items), for
+// inputs of at most SMALL_SCAN items: one launch instead of three
+constexpr int SMALL_SCAN = 1024 * SCAN_ITEMS;
+__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *total) {
+    uint64_t base = (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        uint64_t idx = base + i;
+        v[i] = idx < n ? in[idx] : 0;
+        s += v[i];
+    }
+    uint64_t tot;
+    uint64_t run = block_exclusive_sum<1024>(s, &tot);
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        uint64_t idx = base + i;
+        if (idx < n) out[idx] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0) {
+        out[n] = tot;
+        if (total) *total = tot;
+    }
+}
+
+void exclusive_scan(gsi_ctx *c, const uint32_t *in, uint64_t n, uint64_t *out, Scratch &s, uint64_t *total) {
     if (n == 0) {
         fill_u64(c, out, 0, 1);
+        if (total) fill_u64(c, total, 0, 1);
+        return;
+    }
+    if (n <= (uint64_t)SMALL_SCAN) {
+        launch(c, "k_scan_small", 12.0 * n, k_scan_small, 1, 1024, in, n, out, total);
         return;
     }
     uint64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb > 0x7FFFFFFFull) fail(GSI_E_INVALID, "scan too large");
     uint64_t *part = s.get<uint64_t>(nb, "scan partials");
-    launch(c, "scan", 4.0 * n, [&] {
-        hipLaunchKernelGGL(k_scan_reduce, (uint32_t)nb, SCAN_THREADS, 0, c->stream, in, n, part);
-    });
-    launch(c, "scan", 16.0 * nb, [&] {
-        hipLaunchKernelGGL(k_scan_partials, 1, 1024, 0, c->stream, part, nb, out + n);
-    });
-    launch(c, "scan", 12.0 * n, [&] {
-        hipLaunchKernelGGL(k_scan_apply, (uint32_t)nb, SCAN_THREADS, 0, c->stream, in, n, (const uint64_t *)part, out);
-    });
+    launch(c, "k_scan_reduce", 4.0 * n, k_scan_reduce, (uint32_t)nb, SCAN_THREADS, in, n, part);
+    launch(c, "k_scan_partials", 16.0 * nb, k_scan_partials, 1, 1024, part, nb, out + n, total);
+    launch(c, "k_scan_apply", 12.0 * n, k_scan_apply, (uint32_t)nb, SCAN_THREADS, in, n, (const uint64_t *)part, out);
     s.drop(part);
 }
 
@@ -226,22 +256,19 @@ bool radix_sort(gsi_ctx *c, uint32_t n, int na, uint32_t *const *a, uint32_t *co
     for (const SortPass &p : passes) {
         Arrays3 from = in_tmp ? B : A, to = in_tmp ? A : B;
         const uint32_t *key = from.p[p.key_arr];
-        launch(c, "radix_hist", 4.0 * n, [&] {
-            hipLaunchKernelGGL(k_radix_hist, ntiles, RS_THREADS, 0, c->stream, key, p.shift, n, ntiles, hist);
-        });
+        launch(c, "k_radix_hist", 4.0 * n, k_radix_hist, ntiles, RS_THREADS, key, p.shift, n, ntiles, hist);
         exclusive_scan(c, hist, nh, offs, s);
         double bytes = 8.0 * na * n;
-        launch(c, "radix_scatter", bytes, [&] {
-            if (na == 1)
-                hipLaunchKernelGGL(k_radix_scatter<1>, ntiles, RS_THREADS, 0, c->stream, from, to, p.key_arr, p.shift,
-                                   n, ntiles, (const uint64_t *)offs);
-            else if (na == 2)
-                hipLaunchKernelGGL(k_radix_scatter<2>, ntiles, RS_THREADS, 0, c->stream, from, to, p.key_arr, p.shift,
-                                   n, ntiles, (const uint64_t *)offs);
-            else
-                hipLaunchKernelGGL(k_radix_scatter<3>, ntiles, RS_THREADS, 0, c->stream, from, to, p.key_arr, p.shift,
-                                   n, ntiles, (const uint64_t *)offs);
-        });
+        const uint64_t *co = offs;
+        if (na == 1)
+            launch(c, "k_radix_scatter", bytes, k_radix_scatter<1>, ntiles, RS_THREADS, from, to, p.key_arr, p.shift, n,
+                   ntiles, co);
+        else if (na == 2)
+            launch(c, "k_radix_scatter", bytes, k_radix_scatter<2>, ntiles, RS_THREADS, from, to, p.key_arr, p.shift, n,
+                   ntiles, co);
+        else
+            launch(c, "k_radix_scatter", bytes, k_radix_scatter<3>, ntiles, RS_THREADS, from, to, p.key_arr, p.shift, n,
+                   ntiles, co);
         in_tmp = !in_tmp;
     }
     return in_tmp;

@@ -150,9 +150,7 @@ static void filter_impl(gsi_graph *g, const HostQuery &q, bool label_only, uint6
     uint64_t nwords = ((uint64_t)g->n + 63) / 64;
     fill_u32(c, counts, 0, q.k);
     double bytes = 64.0 * g->n + (double)q.k * nwords * 8;
-    launch(c, "filter", bytes, [&] {
-        hipLaunchKernelGGL(k_filter, nblocks(g->n), QT, 0, c->stream, g->sig, g->n, nwords, fa, bits, counts);
-    });
+    launch(c, "k_filter", bytes, k_filter, nblocks(g->n), QT, g->sig, g->n, nwords, fa, bits, counts);
 }
 
 void run_filter(gsi_graph *g, const HostQuery &q, uint64_t *bits, uint32_t *counts) {
@@ -193,8 +191,9 @@ struct LevelArgs {
     const uint64_t *Cu;
     uint32_t *loc;  // start at [e*R + i], length at [(ne+e)*R + i]
     uint32_t *bound;
-    unsigned long long *other_sum;
+    uint64_t *part;            // per-workgroup partial sums of k_locate
     const uint64_t *F;
+    const uint64_t *tile_row;  // row holding element 256*t (entry ntiles = R-1)
     uint64_t gba;
     uint64_t *bitmap;
     uint32_t *tile_cnt;
@@ -202,7 +201,7 @@ struct LevelArgs {
     uint32_t *Mn;
     uint64_t S;
     uint32_t *out;
-    unsigned long long *digest;
+    uint64_t *dig_part;  // per tile (sum, xor) of the tuple hashes (last level)
     uint32_t qcol[GSI_MAX_K];  // query vertex -> column (last level)
     uint32_t final_level, count_only;
 };
@@ -252,8 +251,27 @@ __global__ __launch_bounds__(QT) void k_locate(LevelArgs a) {
             else other += r.y;
         }
     }
+    if (!a.part) return;  // list-length totals are gathered for profiling only
+    __shared__ uint64_t s_o[QT / 64];
     other = wave_sum(other);
-    if (lane_id() == 0 && other) atomicAdd(a.other_sum, (unsigned long long)other);
+    if (lane_id() == 0) s_o[threadIdx.x >> 6] = other;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+#pragma unroll
+        for (int q = 0; q < QT / 64; q++) t += s_o[q];
+        a.part[2 * (uint64_t)blockIdx.x] = t;
+        a.part[2 * (uint64_t)blockIdx.x + 1] = 0;
+    }
+}
+
+// tile_row[t] = the row whose slice of GBA holds element 256*t
+__global__ __launch_bounds__(QT) void k_tile_rows(const uint64_t *F, uint64_t R, uint64_t ntiles, uint64_t *tile_row) {
+    const uint64_t i = (uint64_t)blockIdx.x * QT + threadIdx.x;
+    if (i >= R) return;
+    const uint64_t lo = F[i], hi = F[i + 1];
+    for (uint64_t t = (lo + QT - 1) / QT; t * QT < hi; t++) tile_row[t] = i;
+    if (i == R - 1) tile_row[ntiles] = R - 1;
 }
 
 // largest i in [lo, hi] with F[i] <= p (F non-decreasing, F[lo] <= p)
@@ -276,23 +294,14 @@ __device__ __forceinline__ bool in_sorted(const uint32_t *list, uint32_t len, ui
     return lo < len && list[lo] == x;
 }
 
-__device__ __forceinline__ void tile_rows(const LevelArgs &a, uint64_t p0, uint64_t *lo, uint64_t *hi) {
-    uint64_t last = p0 + QT - 1;
-    if (last >= a.gba) last = a.gba - 1;
-    *lo = row_of(a.F, 0, a.R - 1, p0);
-    *hi = row_of(a.F, *lo, a.R - 1, last);
-}
-
 __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
-    __shared__ uint64_t s_lo, s_hi;
     __shared__ uint32_t s_cnt[QT / 64];
     const uint64_t p0 = (uint64_t)blockIdx.x * QT;
-    if (threadIdx.x == 0) tile_rows(a, p0, &s_lo, &s_hi);
-    __syncthreads();
+    const uint64_t r_lo = a.tile_row[blockIdx.x], r_hi = a.tile_row[blockIdx.x + 1];
     const uint64_t p = p0 + threadIdx.x;
     bool keep = false;
     if (p < a.gba) {
-        const uint64_t i = row_of(a.F, s_lo, s_hi, p);
+        const uint64_t i = row_of(a.F, r_lo, r_hi, p);
         const uint32_t t = (uint32_t)(p - a.F[i]);
         const uint32_t x = a.e[a.e0].ci[a.loc[(uint64_t)a.e0 * a.R + i] + t];
         keep = (a.Cu[x >> 6] >> (x & 63)) & 1ull;
@@ -336,12 +345,17 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 }
 
 __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
-    __shared__ uint64_t s_lo, s_hi;
+    __shared__ uint64_t s_d[2][QT / 64];
     const uint64_t tile = blockIdx.x;
-    if (a.tile_off[tile + 1] == a.tile_off[tile]) return;  // whole tile empty (uniform)
+    if (a.tile_off[tile + 1] == a.tile_off[tile]) {  // whole tile empty (uniform)
+        if (a.final_level && threadIdx.x == 0) {
+            a.dig_part[2 * tile] = 0;
+            a.dig_part[2 * tile + 1] = 0;
+        }
+        return;
+    }
     const uint64_t p0 = tile * QT;
-    if (threadIdx.x == 0) tile_rows(a, p0, &s_lo, &s_hi);
-    __syncthreads();
+    const uint64_t r_lo = a.tile_row[tile], r_hi = a.tile_row[tile + 1];
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
     const uint64_t *words = a.bitmap + tile * (QT / 64);
     const uint64_t word = words[w];
@@ -352,7 +366,7 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
     uint64_t h = 0;
     if (keep && pos < a.S) {
         const uint64_t p = p0 + threadIdx.x;
-        const uint64_t i = row_of(a.F, s_lo, s_hi, p);
+        const uint64_t i = row_of(a.F, r_lo, r_hi, p);
         const uint32_t x = a.e[a.e0].ci[a.loc[(uint64_t)a.e0 * a.R + i] + (uint32_t)(p - a.F[i])];
         if (!a.final_level) {
             for (uint32_t c = 0; c < a.j; c++) a.Mn[(uint64_t)c * a.S + pos] = a.M[(uint64_t)c * a.R + i];
@@ -369,18 +383,56 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
         }
     }
     if (a.final_level) {
-        uint64_t sum = wave_sum(h);
-        uint64_t xr = wave_xor(h);
-        if (lane == 0 && word) {
-            atomicAdd(&a.digest[0], (unsigned long long)sum);
-            atomicXor(&a.digest[1], (unsigned long long)xr);
+        // per-tile partial digest; reduced by one small kernel afterwards
+        uint64_t sum = wave_sum(h), xr = wave_xor(h);
+        if (lane == 0) {
+            s_d[0][w] = sum;
+            s_d[1][w] = xr;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t ts = 0, tx = 0;
+#pragma unroll
+            for (int q = 0; q < QT / 64; q++) {
+                ts += s_d[0][q];
+                tx ^= s_d[1][q];
+            }
+            a.dig_part[2 * tile] = ts;
+            a.dig_part[2 * tile + 1] = tx;
         }
     }
 }
 
-// rows of a one-column table (k = 1): copy out and digest
+// (sum, xor) over n pairs part[2i], part[2i+1]: one workgroup
+__global__ __launch_bounds__(1024) void k_reduce_pairs(const uint64_t *part, uint64_t n, uint64_t *out) {
+    __shared__ uint64_t s_s[16], s_x[16];
+    uint64_t sm = 0, xr = 0;
+    for (uint64_t i = threadIdx.x; i < n; i += 1024) {
+        sm += part[2 * i];
+        xr ^= part[2 * i + 1];
+    }
+    sm = wave_sum(sm);
+    xr = wave_xor(xr);
+    if (lane_id() == 0) {
+        s_s[threadIdx.x >> 6] = sm;
+        s_x[threadIdx.x >> 6] = xr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t ts = 0, tx = 0;
+        for (int q = 0; q < 16; q++) {
+            ts += s_s[q];
+            tx ^= s_x[q];
+        }
+        out[0] = ts;
+        out[1] = tx;
+    }
+}
+
+// rows of a one-column table (k = 1): copy out, per-workgroup partial digest
 __global__ __launch_bounds__(QT) void k_emit_single(const uint32_t *M, uint64_t R, uint32_t *out, uint32_t count_only,
-                                                   unsigned long long *digest) {
+                                                   uint64_t *dig_part) {
+    __shared__ uint64_t s_d[2][QT / 64];
     const uint64_t i = (uint64_t)blockIdx.x * QT + threadIdx.x;
     uint64_t h = 0;
     if (i < R) {
@@ -390,9 +442,24 @@ __global__ __launch_bounds__(QT) void k_emit_single(const uint32_t *M, uint64_t 
     }
     uint64_t sum = wave_sum(h), xr = wave_xor(h);
     if (lane_id() == 0) {
-        atomicAdd(&digest[0], (unsigned long long)sum);
-        atomicXor(&digest[1], (unsigned long long)xr);
+        s_d[0][threadIdx.x >> 6] = sum;
+        s_d[1][threadIdx.x >> 6] = xr;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t ts = 0, tx = 0;
+#pragma unroll
+        for (int q = 0; q < QT / 64; q++) {
+            ts += s_d[0][q];
+            tx ^= s_d[1][q];
+        }
+        dig_part[2 * (uint64_t)blockIdx.x] = ts;
+        dig_part[2 * (uint64_t)blockIdx.x + 1] = tx;
+    }
+}
+
+static void reduce_pairs(gsi_ctx *c, const uint64_t *part, uint64_t n, uint64_t *out) {
+    launch(c, "k_reduce_pairs", 16.0 * n + 16.0, k_reduce_pairs, 1, 1024, part, n, out);
 }
 
 // ---------------------------------------------------------------- planner
@@ -592,8 +659,6 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     for (uint32_t j = 0; j < k; j++) col[order[j]] = j;
 
     auto tj = std::chrono::steady_clock::now();
-    unsigned long long *digest = reinterpret_cast<unsigned long long *>(dscal);  // dscal[0..1]
-    unsigned long long *other_sum = reinterpret_cast<unsigned long long *>(dscal + 2);
 
     // M0 = C(order[0]), ascending
     uint64_t R = cand[order[0]];
@@ -605,23 +670,19 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         uint32_t *wc = s0.get<uint32_t>(nwords, "word counts");
         uint64_t *wo = s0.get<uint64_t>(nwords + 1, "word offsets");
         const uint64_t *b0 = bits + (uint64_t)order[0] * nwords;
-        launch(c, "first_table", 8.0 * nwords, [&] {
-            hipLaunchKernelGGL(k_word_popc, nblocks(nwords), QT, 0, c->stream, b0, nwords, wc);
-        });
+        launch(c, "k_word_popc", 8.0 * nwords, k_word_popc, nblocks(nwords), QT, b0, nwords, wc);
         exclusive_scan(c, wc, nwords, wo, s0);
-        launch(c, "first_table", 16.0 * nwords + 4.0 * R, [&] {
-            hipLaunchKernelGGL(k_word_emit, nblocks(nwords), QT, 0, c->stream, b0, nwords, (const uint64_t *)wo, M);
-        });
+        launch(c, "k_word_emit", 16.0 * nwords + 4.0 * R, k_word_emit, nblocks(nwords), QT, b0, nwords, (const uint64_t *)wo, M);
     }
     st.rows[0] = R;
-    fill_u64(c, dscal, 0, 4);
 
     if (k == 1) {
         uint32_t *out = count_only ? nullptr : persist<uint32_t>(c, R, "result rows");
         res->rows = out;
-        launch(c, "emit", 8.0 * R, [&] {
-            hipLaunchKernelGGL(k_emit_single, nblocks(R), QT, 0, c->stream, M, R, out, count_only ? 1u : 0u, digest);
-        });
+        uint64_t nb = nblocks(R);
+        uint64_t *dpart = s.get<uint64_t>(2 * nb, "digest partials");
+        launch(c, "k_emit_single", 8.0 * R, k_emit_single, (uint32_t)nb, QT, M, R, out, count_only ? 1u : 0u, dpart);
+        reduce_pairs(c, dpart, nb, dscal);
         uint64_t dg[2];
         read_scalars(c, dscal, dg, 2);
         res->rows = out;
@@ -668,15 +729,15 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         a.bound = ls.get<uint32_t>(R, "row bounds");
         uint64_t *F = ls.get<uint64_t>(R + 1, "offsets F");
         a.F = F;
-        a.other_sum = other_sum;
-        fill_u64(c, dscal + 2, 0, 1);
-        launch(c, "locate", (double)R * (4.0 * ne + 128.0 * ne + 8.0 * ne + 4.0), [&] {
-            hipLaunchKernelGGL(k_locate, nblocks(R), QT, 0, c->stream, a);
-        });
-        exclusive_scan(c, a.bound, R, F, ls);
+        const uint64_t nbr = nblocks(R);
+        const bool prof = (c->flags & GSI_CTX_PROFILE) != 0;
+        a.part = prof ? ls.get<uint64_t>(2 * nbr, "locate partials") : nullptr;
+        launch(c, "k_locate", (double)R * (4.0 * ne + 128.0 * ne + 8.0 * ne + 4.0), k_locate, (uint32_t)nbr, QT, a);
+        if (prof) reduce_pairs(c, a.part, nbr, dscal + 2);
+        exclusive_scan(c, a.bound, R, F, ls, dscal + 3);
         uint64_t sc[2];
-        GSI_HIP(hipMemcpyAsync(dscal + 3, F + R, 8, hipMemcpyDeviceToDevice, c->stream));
         read_scalars(c, dscal + 2, sc, 2);
+        if (!prof) sc[0] = 0;
         const uint64_t gba = sc[1];
         st.gba[j] = gba;
         st.other_elems[j] = sc[0];
@@ -691,11 +752,14 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         a.tile_cnt = ls.get<uint32_t>(ntiles, "tile counts");
         uint64_t *toff = ls.get<uint64_t>(ntiles + 1, "tile offsets");
         a.tile_off = toff;
+        uint64_t *trow = ls.get<uint64_t>(ntiles + 1, "tile rows");
+        a.tile_row = trow;
+        launch(c, "k_tile_rows", 16.0 * R + 8.0 * ntiles, k_tile_rows, nblocks(R), QT, (const uint64_t *)F, R, ntiles, trow);
         double jb = 4.0 * gba + (double)R * (8.0 + 8.0 * ne + 4.0 * j) + 4.0 * (double)sc[0] + gba / 8.0 + 4.0 * ntiles;
-        launch(c, "join", jb, [&] { hipLaunchKernelGGL(k_join, nblocks(gba), QT, 0, c->stream, a); });
-        exclusive_scan(c, a.tile_cnt, ntiles, toff, ls);
+        launch(c, "k_join", jb, k_join, nblocks(gba), QT, a);
+        exclusive_scan(c, a.tile_cnt, ntiles, toff, ls, dscal + 1);
         uint64_t S;
-        read_scalars(c, toff + ntiles, &S, 1);
+        read_scalars(c, dscal + 1, &S, 1);
         st.survivors[j] = S;
         if (S == 0) return finish();
         if (max_rows && S > max_rows) fail(GSI_E_CAPACITY, "rows exceed max_rows at level %u", j);
@@ -708,15 +772,14 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
                 res->rows = a.out;
                 lb += 4.0 * k * S;
             }
-            a.digest = digest;
+            a.dig_part = ls.get<uint64_t>(2 * ntiles, "digest partials");
         } else {
             a.Mn = Mn.get<uint32_t>((uint64_t)(j + 1) * S, "next table");
             lb += 4.0 * (j + 1) * S;
         }
-        launch(c, final_level ? "link_final" : "link", lb, [&] {
-            hipLaunchKernelGGL(k_link, (uint32_t)ntiles, QT, 0, c->stream, a);
-        });
+        launch(c, "k_link", lb, k_link, (uint32_t)ntiles, QT, a);
         if (final_level) {
+            reduce_pairs(c, a.dig_part, ntiles, dscal);
             uint64_t dg[2];
             read_scalars(c, dscal, dg, 2);
             res->rows = a.out;

@@ -1,0 +1,54 @@
+"""Writes oracle counts and digests for the named workloads.
+
+Calls only the CPU oracle and the seeded input generators.  Usage:
+    python tests/golden/make_golden.py er1k ba1m
+Each query is accepted when the oracle finishes it within the deterministic
+limits below (at most 10^9 embeddings and 2*10^10 search nodes); a rejected
+query would be redrawn with the next attempt number and the rejection logged.
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+import workloads as w  # noqa: E402
+
+MAX_COUNT = 1_000_000_000
+MAX_NODES = 20_000_000_000
+
+
+def make(name: str, threads: int):
+    c = w.CONFIGS[name]
+    g = w.config_graph(name)
+    og = oracle.OracleGraph(g)
+    mk = w.QueryMaker(g)
+    out = dict(workload=name, n=g.n, m=g.m, limits=dict(max_count=MAX_COUNT, max_nodes=MAX_NODES),
+               queries=[], rejected=[])
+    for i in range(c["nq"]):
+        attempt = 0
+        while True:
+            q = w.config_query(g, name, i, attempt=attempt, maker=mk)
+            t = time.time()
+            r = og.match(q, threads=threads, tuples=False, max_count=MAX_COUNT, max_nodes=MAX_NODES)
+            dt = time.time() - t
+            if r.status == oracle.OR_OK:
+                break
+            out["rejected"].append(dict(index=i, attempt=attempt, status=r.status))
+            attempt += 1
+        out["queries"].append(dict(index=i, attempt=attempt, k=q.k, m=q.m, mode=q.mode, count=r.count,
+                                   digest=[str(r.digest[0]), str(r.digest[1])], nodes=r.nodes,
+                                   oracle_s=round(dt, 4)))
+        print(name, i, q.k, r.count, flush=True)
+    path = os.path.join(HERE, "%s.json" % name)
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    for nm in sys.argv[1:] or ["er1k", "ba1m"]:
+        make(nm, threads=os.cpu_count() or 1)

@@ -31,8 +31,9 @@ sys.path.insert(0, ROOT)
 METRIC = "embeddings/s and queries/s (batched vs single) on one MI355X; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 # kernels of the path's own steps: signature filter, PCSR locate, join
-# (set subtraction + intersections), link (Prealloc-Combine table write)
-HOT_KERNELS = ("k_filter", "k_locate", "k_join", "k_link")
+# (set subtraction + intersections), link (Prealloc-Combine table write), and
+# the fused workgroup that runs locate/join/link for small tables
+HOT_KERNELS = ("k_filter", "k_locate", "k_join", "k_link", "k_fused_levels")
 
 WORKLOAD_TEXT = {
     "ba1m": "BA graph 1,000,000 vertices / 9,999,945 edges, 32 vertex labels Zipf(1.1), 8 edge labels uniform; "
@@ -86,6 +87,71 @@ def cpu_baseline(g, qs, threads):
                        "%.2f s wall" % (len(qs), dt))
 
 
+def batched_section(args, vl_t, s_t, d_t, l_t, g, arena):
+    """The 1,024-query mixed workload on the same resident graph, run one
+    query at a time and as one batch; both timed over --steps passes after
+    --warmup passes (the autotuner runs in the first warm-up pass)."""
+    import numpy as np
+    import torch
+    import workloads as w
+    import paper_1906_03420_amd as gsi
+    name = "ba1m_batch"
+    gold = load_golden(name)
+    mk = w.QueryMaker(g)
+    qs = [w.config_query(g, name, x["index"], attempt=x["attempt"], maker=mk) for x in gold["queries"]]
+    mk.close()
+    ctx = gsi.Context(arena)
+    dg = ctx.load_device(g.n, vl_t, s_t, d_t, l_t)
+
+    def ok(counts):
+        return all(c == x["count"] and [str(d[0]), str(d[1])] == x["digest"] for (c, d), x in zip(counts, gold["queries"]))
+
+    def sequential():
+        out = []
+        for q in qs:
+            r = dg.query(q)
+            out.append((r.count, r.digest))
+            r.free()
+        torch.cuda.synchronize()
+        return out
+
+    def batched():
+        b = dg.batch(qs)
+        out = [(b.count(i), b.digest(i)) for i in range(len(qs))]
+        info = b.info()
+        b.free()
+        torch.cuda.synchronize()
+        return out, info
+
+    tune = None
+    parity = True
+    for i in range(max(1, args.warmup)):
+        if i == 0:
+            tune = dg.tune(qs, sample=256)
+        parity &= ok(sequential())
+        parity &= ok(batched()[0])
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        parity &= ok(sequential())
+    t_seq = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out, info = batched()
+        parity &= ok(out)
+    t_bat = (time.perf_counter() - t0) / args.steps
+    dg.free()
+    ctx.close()
+    emb = sum(x["count"] for x in gold["queries"])
+    return dict(workload="BA graph (same as above) with 1,024 random-walk queries of 4-16 vertices, shapes tree / "
+                         "walk with a cycle / dense; %d embeddings per pass" % emb,
+                sequential=dict(queries_per_s=len(qs) / t_seq, embeddings_per_s=emb / t_seq, ms_per_pass=t_seq * 1e3),
+                batched=dict(queries_per_s=len(qs) / t_bat, embeddings_per_s=emb / t_bat, ms_per_pass=t_bat * 1e3),
+                speedup=t_seq / t_bat, schedule=info["schedule"], autotune=tune,
+                tiers=dict(empty=info["empty"], tier1=info["tier1"], tier2=info["tier2"], per_level=info["per_level"]),
+                parity="bit-exact counts+digests vs oracle, both paths, %d/%d" % (len(qs), len(qs)) if parity
+                else "MISMATCH")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +160,7 @@ def main():
     ap.add_argument("--workload", default="ba1m", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--arena-gb", type=float, default=48.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device copy of this size (a reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -174,6 +241,11 @@ def main():
     dev_ms = sum(k["total_ms"] for k in ks)
     dom = max((k for k in ks if k["name"] in HOT_KERNELS), key=lambda k: k["total_ms"])
     achieved = dom["alg_bytes"] / (dom["total_ms"] * 1e-3) / 1e9
+    large = [k for k in ks if k["name"].endswith("@large") and k["name"].split("@")[0] in HOT_KERNELS]
+    large_lines = {k["name"]: dict(launches=k["launches"], ms=round(k["total_ms"], 3),
+                                   achieved_gbs=round(k["alg_bytes"] / (k["total_ms"] * 1e-3) / 1e9, 1),
+                                   frac=round(k["alg_bytes"] / (k["total_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+                   for k in large}
     lat_ms = np.array(lat_all) * 1e3
     nq_total = len(qs) * args.steps
 
@@ -203,11 +275,14 @@ def main():
                       avg_launch_us=dom["total_ms"] / dom["launches"] * 1e3,
                       share_of_device_time=dom["total_ms"] / dev_ms if dev_ms else None,
                       measured="HIP events around every launch in %d profiled steps (%.1f ms/step with events)"
-                               % (args.steps, prof_ms)),
+                               % (args.steps, prof_ms),
+                      large_launches=large_lines),
         kernels={k["name"]: dict(launches=k["launches"], ms=round(k["total_ms"], 3),
                                  gbs=round(k["alg_bytes"] / (k["total_ms"] * 1e-3) / 1e9, 1) if k["total_ms"] else None)
                  for k in ks},
     )
+    if not args.no_batched:
+        res["batched"] = batched_section(args, vl_t, s_t, d_t, l_t, g, arena)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(g, qs, host_threads())
     print(json.dumps(res), flush=True)

@@ -88,7 +88,9 @@ gsi_status gsi_ctx_memory(const gsi_ctx *ctx, uint64_t *live_bytes, uint64_t *pe
  * name, the number of launches, the summed duration measured with HIP events
  * recorded on the context stream around each launch, and the summed
  * algorithmic bytes (the bytes the step must move at least, as documented per
- * kernel).  Returns at most `cap` entries in `out`, the number in *n. */
+ * kernel).  Launches of at least 16 MiB of algorithmic bytes are summed a
+ * second time under "<name>@large".  Returns at most `cap` entries in `out`,
+ * the number in *n. */
 typedef struct {
     char name[32];
     uint64_t launches;
@@ -157,6 +159,8 @@ gsi_status gsi_graph_copy_pcsr(const gsi_graph *g, uint32_t label, uint32_t *hos
 #define GSI_COUNT_ONLY 0x1u        /* keep count and digest, write no rows */
 #define GSI_FILTER_LABEL_ONLY 0x2u /* test only: C(u) = vertices with u's label
                                       (skips the signature test) */
+#define GSI_NO_FUSED 0x4u          /* run every level with the per-level kernels
+                                      (no fused small-table workgroup) */
 
 /* Optional controls of one query run (NULL = defaults). */
 typedef struct {
@@ -167,6 +171,10 @@ typedef struct {
                                   is e0 (Algorithm 4); needs `order` */
     uint64_t max_rows;         /* 0, or a cap on rows of any intermediate table;
                                   exceeding it returns GSI_E_CAPACITY */
+    uint32_t fused_max_rows;   /* 0 = default (4096); test only: a lower row
+                                  capacity of the fused small-table workgroup */
+    uint32_t fused_max_slots;  /* 0 = default (16384); test only: a lower |GBA|
+                                  capacity of the fused workgroup */
 } gsi_query_options;
 
 /*
@@ -182,6 +190,9 @@ typedef struct {
  *      survivor into M' (Prealloc-Combine, one join pass);
  *   4. the last level writes rows in query-vertex order (or only counts) and
  *      the order-independent digest.
+ * While the tables stay small (at most 4096 rows and 16384 |GBA| slots per
+ * level) one fused workgroup runs the levels without host round trips; the
+ * remaining levels run as separate kernels.  Both give identical results.
  * q_vertex_labels[k]; q_src/q_dst/q_edge_labels[q_edges] (host).
  * Errors: GSI_E_INVALID for k == 0 or k > GSI_MAX_K, an endpoint >= k, a
  * self-loop, a repeated pair, a disconnected Q or a bad option; GSI_E_NOMEM
@@ -230,6 +241,74 @@ typedef struct {
 } gsi_stats;
 gsi_status gsi_result_stats(const gsi_result *r, gsi_stats *out);
 gsi_status gsi_result_free(gsi_result *r);
+
+/* ------------------------------------------------------------ batches */
+/* One query of a batch (host arrays, read during the call). */
+typedef struct {
+    uint32_t k;
+    const uint32_t *vertex_labels;  /* k */
+    uint32_t n_edges;
+    const uint32_t *src, *dst, *edge_labels;  /* n_edges each */
+} gsi_query_desc;
+
+/* How a batch is scheduled.  Queries whose tables stay small run in a
+ * persistent fused launch: every workgroup takes the next query from a
+ * shared counter and runs all of its join levels (Algorithm 3 with
+ * Algorithm 4) in LDS-staged form.  A first tier uses workgroups of
+ * `threads` threads (64, 256 or 1024; tables of up to 4x`threads` rows and
+ * 16x`threads` |GBA| slots per level); queries it cannot hold rerun in a
+ * second tier of 1024-thread workgroups, and the rest run one by one with
+ * the per-level kernels.  `grid_scale` (1..8) multiplies the number of
+ * resident workgroups per compute unit that is launched, in eighths. */
+typedef struct {
+    uint32_t threads;     /* first-tier workgroup size: 64, 256 or 1024 */
+    uint32_t grid_scale;  /* eighths of full occupancy launched, 1..8 */
+} gsi_batch_schedule;
+
+typedef struct {
+    uint32_t flags;               /* GSI_COUNT_ONLY */
+    gsi_batch_schedule schedule;  /* threads == 0: the graph's tuned schedule
+                                     (gsi_batch_tune), else 256 / 8 eighths */
+} gsi_batch_options;
+
+typedef struct gsi_batch gsi_batch;
+
+/* Runs `nq` queries over one resident graph (the batched path):
+ *   1. one signature-filter pass per 32 query vertices of the whole batch
+ *      (query vertices grouped by label), one readback of all |C(u)|;
+ *   2. each query's matching order (Algorithm 2) on the host;
+ *   3. all root tables C(u_first) compacted in one pass;
+ *   4. the fused tiers and the per-level fallback described above.
+ * Every query's result is the one gsi_query_run returns (same rows, count
+ * and digest; row order may differ).  Errors as gsi_query_run, for the first
+ * invalid query (its index is in the message). */
+gsi_status gsi_batch_run(gsi_graph *g, uint32_t nq, const gsi_query_desc *queries, const gsi_batch_options *opt,
+                         gsi_batch **out);
+gsi_status gsi_batch_count(const gsi_batch *b, uint32_t qi, uint64_t *rows);
+gsi_status gsi_batch_digest(const gsi_batch *b, uint32_t qi, uint64_t out_sum_xor[2]);
+/* Rows of query qi, row-major in query-vertex order; GSI_E_CAPACITY if
+ * capacity_rows is too small, GSI_E_INVALID for a GSI_COUNT_ONLY batch. */
+gsi_status gsi_batch_rows(const gsi_batch *b, uint32_t qi, uint32_t *host_dst, uint64_t capacity_rows);
+
+typedef struct {
+    uint32_t queries;
+    uint32_t empty;        /* answered by the filter alone (0 rows) */
+    uint32_t tier1;        /* finished in the first fused tier */
+    uint32_t tier2;        /* finished in the 1024-thread tier */
+    uint32_t per_level;    /* finished with the per-level kernels */
+    gsi_batch_schedule schedule;
+    double filter_ms, tier1_ms, tier2_ms, per_level_ms, total_ms;  /* host wall time */
+} gsi_batch_info;
+gsi_status gsi_batch_get_info(const gsi_batch *b, gsi_batch_info *out);
+gsi_status gsi_batch_free(gsi_batch *b);
+
+/* Autotuner: runs a sample of the batch (the first min(nq, sample) queries,
+ * counts only) under every candidate schedule — first-tier sizes 64, 256
+ * and 1024 threads at full and half occupancy — and keeps the fastest as the
+ * graph's tuned schedule (used when gsi_batch_options.schedule.threads is
+ * 0).  The winner and its time per query are returned. */
+gsi_status gsi_batch_tune(gsi_graph *g, uint32_t nq, const gsi_query_desc *queries, uint32_t sample,
+                          gsi_batch_schedule *out, double *out_ms_per_query);
 
 #ifdef __cplusplus
 }

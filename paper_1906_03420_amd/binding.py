@@ -24,6 +24,7 @@ GSI_CTX_PROFILE = 0x1
 GSI_GRAPH_TEST_FEW_HOME_GROUPS = 0x1
 GSI_COUNT_ONLY = 0x1
 GSI_FILTER_LABEL_ONLY = 0x2
+GSI_NO_FUSED = 0x4
 
 STATUS_NAMES = {0: "GSI_OK", 1: "GSI_E_INVALID", 2: "GSI_E_NOMEM", 3: "GSI_E_DEVICE", 4: "GSI_E_CAPACITY",
                 5: "GSI_E_BUSY", 6: "GSI_E_INTERNAL"}
@@ -56,7 +57,8 @@ class gsi_graph_info(ctypes.Structure):
 
 
 class gsi_query_options(ctypes.Structure):
-    _fields_ = [("flags", ctypes.c_uint32), ("order", U32P), ("first_edge", U32P), ("max_rows", ctypes.c_uint64)]
+    _fields_ = [("flags", ctypes.c_uint32), ("order", U32P), ("first_edge", U32P), ("max_rows", ctypes.c_uint64),
+                ("fused_max_rows", ctypes.c_uint32), ("fused_max_slots", ctypes.c_uint32)]
 
 
 class gsi_stats(ctypes.Structure):
@@ -66,6 +68,26 @@ class gsi_stats(ctypes.Structure):
                 ("rows", ctypes.c_uint64 * K), ("gba", ctypes.c_uint64 * K), ("other_elems", ctypes.c_uint64 * K),
                 ("survivors", ctypes.c_uint64 * K), ("filter_ms", ctypes.c_double), ("join_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double)]
+
+
+class gsi_query_desc(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("vertex_labels", U32P), ("n_edges", ctypes.c_uint32), ("src", U32P),
+                ("dst", U32P), ("edge_labels", U32P)]
+
+
+class gsi_batch_schedule(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_uint32), ("grid_scale", ctypes.c_uint32)]
+
+
+class gsi_batch_options(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("schedule", gsi_batch_schedule)]
+
+
+class gsi_batch_info(ctypes.Structure):
+    _fields_ = [("queries", ctypes.c_uint32), ("empty", ctypes.c_uint32), ("tier1", ctypes.c_uint32),
+                ("tier2", ctypes.c_uint32), ("per_level", ctypes.c_uint32), ("schedule", gsi_batch_schedule),
+                ("filter_ms", ctypes.c_double), ("tier1_ms", ctypes.c_double), ("tier2_ms", ctypes.c_double),
+                ("per_level_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
 
 
 # name -> (restype, argtypes) for every exported function of gsi.h
@@ -98,6 +120,15 @@ SIGNATURES = {
     "gsi_result_digest": (ctypes.c_int, [VP, U64P]),
     "gsi_result_stats": (ctypes.c_int, [VP, ctypes.POINTER(gsi_stats)]),
     "gsi_result_free": (ctypes.c_int, [VP]),
+    "gsi_batch_run": (ctypes.c_int, [VP, ctypes.c_uint32, ctypes.POINTER(gsi_query_desc),
+                                     ctypes.POINTER(gsi_batch_options), ctypes.POINTER(VP)]),
+    "gsi_batch_count": (ctypes.c_int, [VP, ctypes.c_uint32, U64P]),
+    "gsi_batch_digest": (ctypes.c_int, [VP, ctypes.c_uint32, U64P]),
+    "gsi_batch_rows": (ctypes.c_int, [VP, ctypes.c_uint32, U32P, ctypes.c_uint64]),
+    "gsi_batch_get_info": (ctypes.c_int, [VP, ctypes.POINTER(gsi_batch_info)]),
+    "gsi_batch_free": (ctypes.c_int, [VP]),
+    "gsi_batch_tune": (ctypes.c_int, [VP, ctypes.c_uint32, ctypes.POINTER(gsi_query_desc), ctypes.c_uint32,
+                                      ctypes.POINTER(gsi_batch_schedule), ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
@@ -225,13 +256,13 @@ def gsi_graph_copy_pcsr(g: int, label: int):
 
 
 def gsi_query_run(g: int, k: int, q_vertex_labels, q_src, q_dst, q_edge_labels, flags: int = 0, order=None,
-                  first_edge=None, max_rows: int = 0) -> int:
+                  first_edge=None, max_rows: int = 0, fused_max_rows: int = 0, fused_max_slots: int = 0) -> int:
     vl, vlp = _u32(q_vertex_labels)
     s, sp = _u32(q_src)
     d, dp = _u32(q_dst)
     l, lp = _u32(q_edge_labels)
     keep = []
-    o = gsi_query_options(flags, None, None, max_rows)
+    o = gsi_query_options(flags, None, None, max_rows, fused_max_rows, fused_max_slots)
     if order is not None:
         a, p = _u32(order)
         keep.append(a)
@@ -299,7 +330,92 @@ def gsi_result_free(r: int):
     _check(load_library().gsi_result_free(r))
 
 
+def _descs(queries):
+    """gsi_query_desc array for query objects (k, vlabel, src, dst, elabel);
+    returns (array, keep-alive list)."""
+    arr = (gsi_query_desc * max(1, len(queries)))()
+    keep = []
+    for i, q in enumerate(queries):
+        parts = [_u32(q.vlabel), _u32(q.src), _u32(q.dst), _u32(q.elabel)]
+        keep.append(parts)
+        arr[i] = gsi_query_desc(q.k, parts[0][1], parts[1][0].shape[0], parts[1][1], parts[2][1], parts[3][1])
+    return arr, keep
+
+
+def gsi_batch_run(g: int, queries, flags: int = 0, threads: int = 0, grid_scale: int = 0) -> int:
+    arr, keep = _descs(queries)
+    o = gsi_batch_options(flags, gsi_batch_schedule(threads, grid_scale))
+    h = VP()
+    _check(load_library().gsi_batch_run(g, len(queries), arr, ctypes.byref(o), ctypes.byref(h)))
+    return h.value
+
+
+def gsi_batch_count(b: int, qi: int) -> int:
+    out = ctypes.c_uint64()
+    _check(load_library().gsi_batch_count(b, qi, ctypes.byref(out)))
+    return out.value
+
+
+def gsi_batch_digest(b: int, qi: int) -> tuple:
+    out = (ctypes.c_uint64 * 2)()
+    _check(load_library().gsi_batch_digest(b, qi, out))
+    return int(out[0]), int(out[1])
+
+
+def gsi_batch_rows(b: int, qi: int, k: int) -> np.ndarray:
+    n = gsi_batch_count(b, qi)
+    out = np.zeros((n, k), np.uint32)
+    _check(load_library().gsi_batch_rows(b, qi, out.ctypes.data_as(U32P), n))
+    return out
+
+
+def gsi_batch_get_info(b: int) -> dict:
+    i = gsi_batch_info()
+    _check(load_library().gsi_batch_get_info(b, ctypes.byref(i)))
+    d = {f: getattr(i, f) for f, _ in gsi_batch_info._fields_ if f != "schedule"}
+    d["schedule"] = dict(threads=i.schedule.threads, grid_scale=i.schedule.grid_scale)
+    return d
+
+
+def gsi_batch_free(b: int):
+    _check(load_library().gsi_batch_free(b))
+
+
+def gsi_batch_tune(g: int, queries, sample: int = 128):
+    arr, keep = _descs(queries)
+    sc = gsi_batch_schedule()
+    ms = ctypes.c_double()
+    _check(load_library().gsi_batch_tune(g, len(queries), arr, sample, ctypes.byref(sc), ctypes.byref(ms)))
+    return dict(threads=sc.threads, grid_scale=sc.grid_scale, ms_per_query=ms.value)
+
+
 # ------------------------------------------------------------ conveniences
+class Batch:
+    def __init__(self, h: int, ks):
+        self.h, self.ks = h, list(ks)
+
+    def count(self, qi: int) -> int:
+        return gsi_batch_count(self.h, qi)
+
+    def digest(self, qi: int) -> tuple:
+        return gsi_batch_digest(self.h, qi)
+
+    def rows(self, qi: int) -> np.ndarray:
+        return gsi_batch_rows(self.h, qi, self.ks[qi])
+
+    def sorted_rows(self, qi: int) -> np.ndarray:
+        r = self.rows(qi)
+        return r[np.lexsort(r.T[::-1])] if len(r) else r
+
+    def info(self) -> dict:
+        return gsi_batch_get_info(self.h)
+
+    def free(self):
+        if self.h:
+            gsi_batch_free(self.h)
+            self.h = 0
+
+
 class Result:
     def __init__(self, h: int, k: int):
         self.h, self.k = h, k
@@ -341,12 +457,20 @@ class Graph:
     def pcsr(self, label: int):
         return gsi_graph_copy_pcsr(self.h, label)
 
-    def query(self, q, flags: int = 0, order=None, first_edge=None, max_rows: int = 0) -> Result:
-        h = gsi_query_run(self.h, q.k, q.vlabel, q.src, q.dst, q.elabel, flags, order, first_edge, max_rows)
+    def query(self, q, flags: int = 0, order=None, first_edge=None, max_rows: int = 0, fused_max_rows: int = 0,
+              fused_max_slots: int = 0) -> Result:
+        h = gsi_query_run(self.h, q.k, q.vlabel, q.src, q.dst, q.elabel, flags, order, first_edge, max_rows,
+                          fused_max_rows, fused_max_slots)
         return Result(h, q.k)
 
     def filter(self, q):
         return gsi_query_filter(self.h, self.n, q.k, q.vlabel, q.src, q.dst, q.elabel)
+
+    def batch(self, queries, flags: int = 0, threads: int = 0, grid_scale: int = 0) -> Batch:
+        return Batch(gsi_batch_run(self.h, queries, flags, threads, grid_scale), [q.k for q in queries])
+
+    def tune(self, queries, sample: int = 128) -> dict:
+        return gsi_batch_tune(self.h, queries, sample)
 
     def free(self):
         if self.h:

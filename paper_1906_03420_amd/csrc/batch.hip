@@ -1,0 +1,467 @@
+// The batched path: many queries over one resident graph.
+//
+//   filter   one pass of the signature filter per 32 query vertices of the
+//            whole batch (query vertices grouped by label), one readback
+//   plan     Algorithm 2 per query on the host
+//   roots    every fused query's C(u_first) compacted in one pass
+//   tier 1   persistent fused launch, workgroups of the scheduled size pull
+//            queries from a shared counter and run all levels per query
+//   tier 2   what tier 1 could not hold, in 1024-thread workgroups
+//   rest     one by one with the per-level kernels (run_query)
+//
+// The schedule (tier-1 workgroup size, launched occupancy) is chosen by the
+// autotuner, which times every candidate on a sample of the batch.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <memory>
+
+#include "fused.h"
+#include "gsi_internal.h"
+
+struct gsi_batch {
+    gsi_ctx *ctx = nullptr;
+    uint32_t nq = 0;
+    bool count_only = false;
+    struct Entry {
+        uint32_t k = 0;
+        uint64_t count = 0;
+        uint64_t digest[2] = {0, 0};
+        uint8_t where = 0;  // 0: no rows, 1: fused output buffer, 2: own result
+        uint64_t out_off = 0;
+        gsi_result *res = nullptr;
+    };
+    std::vector<Entry> e;
+    uint32_t *out = nullptr;
+    gsi_batch_info info{};
+    ~gsi_batch() {
+        for (auto &x : e)
+            if (x.res) {
+                ctx->arena.release(x.res->rows);
+                delete x.res;
+            }
+        if (out) ctx->arena.release(out);
+    }
+};
+
+namespace gsi {
+
+constexpr uint32_t BQT = 256;
+constexpr uint32_t TIER2_THREADS = 1024;
+
+__global__ __launch_bounds__(BQT) void k_roots_popc(const uint64_t *bits, const uint32_t *rows, uint64_t nwords,
+                                                   uint64_t total, uint32_t *cnt) {
+    const uint64_t idx = (uint64_t)blockIdx.x * BQT + threadIdx.x;
+    if (idx >= total) return;
+    const uint64_t q = idx / nwords, wi = idx - q * nwords;
+    cnt[idx] = (uint32_t)__popcll(bits[(uint64_t)rows[q] * nwords + wi]);
+}
+
+__global__ __launch_bounds__(BQT) void k_roots_emit(const uint64_t *bits, const uint32_t *rows, uint64_t nwords,
+                                                   uint64_t total, const uint64_t *off, uint32_t *out) {
+    const uint64_t idx = (uint64_t)blockIdx.x * BQT + threadIdx.x;
+    if (idx >= total) return;
+    const uint64_t q = idx / nwords, wi = idx - q * nwords;
+    uint64_t b = bits[(uint64_t)rows[q] * nwords + wi];
+    uint64_t o = off[idx];
+    while (b) {
+        const uint32_t t = (uint32_t)__ffsll((unsigned long long)b) - 1;
+        out[o++] = (uint32_t)(wi * 64 + t);
+        b &= b - 1;
+    }
+}
+
+static uint32_t bgrid(uint64_t n) {
+    uint64_t b = (n + BQT - 1) / BQT;
+    if (b == 0) b = 1;
+    if (b > 0x7FFFFFFFull) fail(GSI_E_CAPACITY, "grid too large");
+    return (uint32_t)b;
+}
+
+static double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+static int cu_count(gsi_ctx *c) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || n < 1) n = 1;
+    return n;
+}
+
+struct FusedQuery {
+    uint32_t qi;       // batch index
+    uint32_t R0;
+    uint64_t plan_off; // bytes
+    uint64_t m0_off;   // rows
+    uint64_t out_off;  // words
+};
+
+// Runs one fused tier over `list`; fills entries of finished queries and
+// returns the ones it could not hold.
+static std::vector<FusedQuery> run_tier(gsi_graph *g, gsi_batch *b, const FTier &t, uint32_t grid_scale,
+                                        const std::vector<FusedQuery> &list, const std::vector<uint32_t> &ks,
+                                        const uint8_t *d_plans, const uint32_t *d_M0, Scratch &s) {
+    gsi_ctx *c = g->ctx;
+    std::vector<FusedQuery> left;
+    if (list.empty()) return left;
+    const uint32_t n = (uint32_t)list.size();
+    uint32_t kmax = 2;
+    std::vector<FBatchItem> items(n);
+    for (uint32_t i = 0; i < n; i++) {
+        items[i].plan_off = list[i].plan_off;
+        items[i].m0_off = list[i].m0_off;
+        items[i].out_off = list[i].out_off;
+        items[i].R0 = list[i].R0;
+        kmax = std::max(kmax, ks[list[i].qi]);
+    }
+    const uint64_t per_cu = std::max<uint64_t>(1, (uint64_t)t.blocks_per_cu * grid_scale / 8);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(n, per_cu * cu_count(c));
+    const uint64_t slot_words = 2ull * t.cap_rows * kmax + 2ull * (kmax - 1) * t.cap_rows;
+    Scratch ts(c);
+    FBatchItem *d_items = ts.get<FBatchItem>(n, "batch items");
+    uint32_t *scratch = ts.get<uint32_t>(slot_words * grid, "batch slots");
+    FStatus *d_st = reinterpret_cast<FStatus *>(ts.get<uint64_t>((uint64_t)n * sizeof(FStatus) / 8, "batch status"));
+    uint32_t *counter = ts.get<uint32_t>(1, "batch counter");
+    GSI_HIP(hipMemcpyAsync(d_items, items.data(), sizeof(FBatchItem) * n, hipMemcpyHostToDevice, c->stream));
+    fill_u64(c, reinterpret_cast<uint64_t *>(d_st), 0, (uint64_t)n * sizeof(FStatus) / 8);
+    fill_u32(c, counter, 0, 1);
+    launch_fused_batch(c, t, grid, d_plans, d_items, n, d_M0, scratch, slot_words, kmax, b->count_only ? nullptr : b->out,
+                       d_st, counter, 0.0);
+    std::vector<FStatus> hs(n);
+    GSI_HIP(hipMemcpyAsync(hs.data(), d_st, sizeof(FStatus) * n, hipMemcpyDeviceToHost, c->stream));
+    sync(c);  // also keeps `items` alive until its copy has run
+    for (uint32_t i = 0; i < n; i++) {
+        gsi_batch::Entry &en = b->e[list[i].qi];
+        if (hs[i].done) {
+            en.count = hs[i].count;
+            en.digest[0] = hs[i].digest[0];
+            en.digest[1] = hs[i].digest[1];
+            en.where = (!b->count_only && hs[i].count) ? 1 : 0;
+            en.out_off = list[i].out_off;
+        } else {
+            left.push_back(list[i]);
+        }
+    }
+    return left;
+}
+
+gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32_t flags,
+                     gsi_batch_schedule sched) {
+    gsi_ctx *c = g->ctx;
+    auto t0 = std::chrono::steady_clock::now();
+    if (flags & ~GSI_COUNT_ONLY) fail(GSI_E_INVALID, "unknown batch flag");
+    if (sched.threads != 64 && sched.threads != 256 && sched.threads != 1024)
+        fail(GSI_E_INVALID, "schedule threads must be 64, 256 or 1024");
+    if (sched.grid_scale < 1 || sched.grid_scale > 8) fail(GSI_E_INVALID, "schedule grid_scale must be 1..8");
+    std::vector<HostQuery> hq(nq);
+    for (uint32_t i = 0; i < nq; i++) {
+        try {
+            hq[i] = validate_query(qd[i].k, qd[i].vertex_labels, qd[i].n_edges, qd[i].src, qd[i].dst,
+                                   qd[i].edge_labels);
+        } catch (const Fail &f) {
+            std::string m = std::string("query ") + std::to_string(i) + ": " + gsi_last_error();
+            fail(f.st, "%s", m.c_str());
+        }
+    }
+    std::unique_ptr<gsi_batch> b(new gsi_batch());
+    b->ctx = c;
+    b->nq = nq;
+    b->count_only = (flags & GSI_COUNT_ONLY) != 0;
+    b->e.resize(nq);
+    b->info.queries = nq;
+    b->info.schedule = sched;
+    for (uint32_t i = 0; i < nq; i++) b->e[i].k = hq[i].k;
+
+    // queries whose edge labels G lacks have no match
+    std::vector<uint32_t> active;
+    for (uint32_t i = 0; i < nq; i++) {
+        bool ok = true;
+        for (uint32_t l : hq[i].el) ok &= l < g->nlab && g->edges[l] > 0;
+        if (ok) active.push_back(i);
+        else b->info.empty++;
+    }
+    Scratch s(c);
+    const uint64_t nwords = ((uint64_t)g->n + 63) / 64;
+    std::vector<const HostQuery *> aq;
+    std::vector<uint32_t> qbase{0};
+    for (uint32_t i : active) {
+        aq.push_back(&hq[i]);
+        qbase.push_back(qbase.back() + hq[i].k);
+    }
+    const uint64_t nqv = qbase.back();
+    auto tf = std::chrono::steady_clock::now();
+    uint64_t *bits = s.get<uint64_t>(std::max<uint64_t>(1, nqv) * nwords, "batch candidate bitsets");
+    uint32_t *dcnt = s.get<uint32_t>(std::max<uint64_t>(1, nqv), "batch candidate counts");
+    std::vector<uint32_t> cnt(nqv);
+    if (nqv) {
+        run_filter_many(g, aq, qbase, bits, dcnt);
+        GSI_HIP(hipMemcpyAsync(cnt.data(), dcnt, 4 * nqv, hipMemcpyDeviceToHost, c->stream));
+        sync(c);
+    }
+    b->info.filter_ms = ms_since(tf);
+
+    // plans, tiers
+    const FTier t1 = fused_tier(sched.threads), t2 = fused_tier(TIER2_THREADS);
+    std::vector<uint32_t> ks(nq);
+    for (uint32_t i = 0; i < nq; i++) ks[i] = hq[i].k;
+    std::vector<FusedQuery> fused;        // tier candidates, in root order
+    std::vector<uint32_t> per_level;      // batch indices
+    std::vector<uint8_t> plan_blob;
+    std::vector<uint32_t> root_rows;      // bitset row of each fused query's root
+    uint64_t m0_total = 0, out_total = 0;
+    for (size_t a = 0; a < active.size(); a++) {
+        const uint32_t qi = active[a];
+        const HostQuery &q = hq[qi];
+        std::vector<uint32_t> cand(cnt.begin() + qbase[a], cnt.begin() + qbase[a] + q.k);
+        bool empty = false;
+        for (uint32_t x : cand) empty |= x == 0;
+        if (empty) {
+            b->info.empty++;
+            continue;
+        }
+        std::vector<uint32_t> order, e0src;
+        make_plan(g, q, cand, order, e0src);
+        const uint32_t R0 = cand[order[0]];
+        if (q.k < 2 || R0 > t2.cap_rows) {
+            per_level.push_back(qi);
+            continue;
+        }
+        uint32_t n_edges = 0;
+        for (uint32_t j = 1; j < q.k; j++)
+            for (uint32_t i = 0; i < j; i++)
+                for (auto &p : q.adj[order[j]]) n_edges += p.first == order[i];
+        const size_t pb = (fplan_bytes(n_edges) + 15) & ~size_t(15);
+        const uint64_t off = plan_blob.size();
+        plan_blob.resize(off + pb, 0);
+        FPlan *hp = reinterpret_cast<FPlan *>(plan_blob.data() + off);
+        hp->k = q.k;
+        hp->count_only = b->count_only ? 1u : 0u;
+        hp->cap_rows = 0xFFFFFFFFu;  // the tier's own capacities apply
+        hp->cap_slots = 0xFFFFFFFFu;
+        std::vector<uint32_t> col(q.k);
+        for (uint32_t j = 0; j < q.k; j++) col[order[j]] = j;
+        for (uint32_t v = 0; v < q.k; v++) hp->qcol[v] = col[v];
+        uint32_t ei = 0;
+        for (uint32_t j = 1; j < q.k; j++) {
+            hp->lv_first[j] = ei;
+            hp->Cu[j] = bits + (uint64_t)(qbase[a] + order[j]) * nwords;
+            uint32_t ne = 0;
+            for (uint32_t i = 0; i < j; i++)
+                for (auto &p : q.adj[order[j]])
+                    if (p.first == order[i]) {
+                        const uint32_t l = p.second;
+                        FEdge &fe = hp->edges[ei + ne];
+                        fe.gl = g->gl + g->group_base[l] * GROUP_WORDS;
+                        fe.ci = g->ci + g->ci_base[l];
+                        fe.G = g->G[l];
+                        fe.H = g->H[l];
+                        fe.col = i;
+                        if (order[i] == e0src[j]) hp->lv_e0[j] = ne;
+                        ne++;
+                    }
+            hp->lv_ne[j] = ne;
+            ei += ne;
+        }
+        FusedQuery f;
+        f.qi = qi;
+        f.R0 = R0;
+        f.plan_off = off;
+        f.m0_off = m0_total;
+        f.out_off = out_total;
+        m0_total += R0;
+        out_total += b->count_only ? 0 : (uint64_t)t2.cap_slots * q.k;
+        root_rows.push_back(qbase[a] + order[0]);
+        fused.push_back(f);
+    }
+
+    if (!fused.empty()) {
+        uint8_t *d_plans = s.get<uint8_t>(plan_blob.size(), "batch plans");
+        uint32_t *d_rows = s.get<uint32_t>(root_rows.size(), "batch root rows");
+        GSI_HIP(hipMemcpyAsync(d_plans, plan_blob.data(), plan_blob.size(), hipMemcpyHostToDevice, c->stream));
+        GSI_HIP(hipMemcpyAsync(d_rows, root_rows.data(), 4 * root_rows.size(), hipMemcpyHostToDevice, c->stream));
+        // all root tables in one pass
+        const uint64_t tw = (uint64_t)root_rows.size() * nwords;
+        uint32_t *d_M0 = s.get<uint32_t>(m0_total, "batch root tables");
+        {
+            Scratch rs(c);
+            uint32_t *wc = rs.get<uint32_t>(tw, "root word counts");
+            uint64_t *wo = rs.get<uint64_t>(tw + 1, "root word offsets");
+            launch(c, "k_roots_popc", 12.0 * tw, k_roots_popc, bgrid(tw), BQT, (const uint64_t *)bits,
+                   (const uint32_t *)d_rows, nwords, tw, wc);
+            exclusive_scan(c, wc, tw, wo, rs);
+            launch(c, "k_roots_emit", 16.0 * tw + 4.0 * m0_total, k_roots_emit, bgrid(tw), BQT, (const uint64_t *)bits,
+                   (const uint32_t *)d_rows, nwords, tw, (const uint64_t *)wo, d_M0);
+            sync(c);  // host vectors copied above stay alive until here
+        }
+        if (!b->count_only && out_total) b->out = persist<uint32_t>(c, out_total, "batch rows");
+        std::vector<FusedQuery> first, second;
+        for (auto &f : fused) (f.R0 <= t1.cap_rows ? first : second).push_back(f);
+        auto ta = std::chrono::steady_clock::now();
+        std::vector<FusedQuery> left = run_tier(g, b.get(), t1, sched.grid_scale, first, ks, d_plans, d_M0, s);
+        b->info.tier1 = (uint32_t)(first.size() - left.size());
+        b->info.tier1_ms = ms_since(ta);
+        if (t1.threads != t2.threads) {
+            second.insert(second.end(), left.begin(), left.end());
+            left.clear();
+        } else {
+            left.insert(left.end(), second.begin(), second.end());
+            second.clear();
+        }
+        auto tb = std::chrono::steady_clock::now();
+        std::vector<FusedQuery> left2 = run_tier(g, b.get(), t2, 8, second, ks, d_plans, d_M0, s);
+        b->info.tier2 = (uint32_t)(second.size() - left2.size());
+        b->info.tier2_ms = ms_since(tb);
+        for (auto &f : left) per_level.push_back(f.qi);
+        for (auto &f : left2) per_level.push_back(f.qi);
+    }
+
+    // the rest, one by one
+    auto tp = std::chrono::steady_clock::now();
+    std::sort(per_level.begin(), per_level.end());
+    for (uint32_t qi : per_level) {
+        gsi_query_options o{};
+        o.flags = (b->count_only ? GSI_COUNT_ONLY : 0u) | GSI_NO_FUSED;
+        gsi_result *r = run_query(g, hq[qi], &o);
+        gsi_batch::Entry &en = b->e[qi];
+        en.res = r;
+        en.count = r->count;
+        en.digest[0] = r->digest[0];
+        en.digest[1] = r->digest[1];
+        en.where = (r->rows && r->count) ? 2 : 0;
+        b->info.per_level++;
+    }
+    b->info.per_level_ms = ms_since(tp);
+    b->info.total_ms = ms_since(t0);
+    return b.release();
+}
+
+}  // namespace gsi
+
+using namespace gsi;
+
+#define B_TRY(...)                               \
+    try {                                         \
+        clear_error();                            \
+        __VA_ARGS__;                              \
+        return GSI_OK;                            \
+    } catch (const Fail &f_) {                    \
+        return f_.st;                             \
+    } catch (const std::bad_alloc &) {            \
+        set_error("host allocation failed");      \
+        return GSI_E_NOMEM;                       \
+    } catch (...) {                               \
+        set_error("unexpected internal exception"); \
+        return GSI_E_INTERNAL;                    \
+    }
+
+namespace {
+struct BusyB {
+    gsi_ctx *c;
+    explicit BusyB(gsi_ctx *cc) : c(cc) {
+        int z = 0;
+        if (!c->busy.compare_exchange_strong(z, 1)) fail(GSI_E_BUSY, "context is already running a call");
+    }
+    ~BusyB() { c->busy.store(0); }
+};
+const gsi_batch::Entry &entry(const gsi_batch *b, uint32_t qi) {
+    if (!b) fail(GSI_E_INVALID, "null batch");
+    if (qi >= b->nq) fail(GSI_E_INVALID, "query index %u out of range (batch of %u)", qi, b->nq);
+    return b->e[qi];
+}
+}  // namespace
+
+extern "C" {
+
+gsi_status gsi_batch_run(gsi_graph *g, uint32_t nq, const gsi_query_desc *qs, const gsi_batch_options *opt,
+                         gsi_batch **out) {
+    B_TRY({
+        if (!g || !out || (nq && !qs)) fail(GSI_E_INVALID, "null argument");
+        *out = nullptr;
+        gsi_batch_schedule sc = opt ? opt->schedule : gsi_batch_schedule{0, 0};
+        if (sc.threads == 0) sc = g->tuned;
+        if (sc.threads == 0) sc = gsi_batch_schedule{256, 8};
+        gsi_ctx *c = g->ctx;
+        BusyB busy(c);
+        GSI_HIP(hipSetDevice(c->device));
+        *out = run_batch(g, nq, qs, opt ? opt->flags : 0u, sc);
+    })
+}
+
+gsi_status gsi_batch_count(const gsi_batch *b, uint32_t qi, uint64_t *rows) {
+    B_TRY({
+        const auto &e = entry(b, qi);
+        if (!rows) fail(GSI_E_INVALID, "null argument");
+        *rows = e.count;
+    })
+}
+
+gsi_status gsi_batch_digest(const gsi_batch *b, uint32_t qi, uint64_t out[2]) {
+    B_TRY({
+        const auto &e = entry(b, qi);
+        if (!out) fail(GSI_E_INVALID, "null argument");
+        out[0] = e.digest[0];
+        out[1] = e.digest[1];
+    })
+}
+
+gsi_status gsi_batch_rows(const gsi_batch *b, uint32_t qi, uint32_t *dst, uint64_t cap) {
+    B_TRY({
+        const auto &e = entry(b, qi);
+        if (b->count_only) fail(GSI_E_INVALID, "batch was run with GSI_COUNT_ONLY");
+        if (cap < e.count) fail(GSI_E_CAPACITY, "need %llu rows", (unsigned long long)e.count);
+        if (e.count == 0) return GSI_OK;
+        if (!dst) fail(GSI_E_INVALID, "null buffer");
+        gsi_ctx *c = b->ctx;
+        GSI_HIP(hipSetDevice(c->device));
+        const uint32_t *src = e.where == 1 ? b->out + e.out_off : e.res->rows;
+        GSI_HIP(hipMemcpyAsync(dst, src, e.count * e.k * 4, hipMemcpyDeviceToHost, c->stream));
+        GSI_HIP(hipStreamSynchronize(c->stream));
+    })
+}
+
+gsi_status gsi_batch_get_info(const gsi_batch *b, gsi_batch_info *out) {
+    B_TRY({
+        if (!b || !out) fail(GSI_E_INVALID, "null argument");
+        *out = b->info;
+    })
+}
+
+gsi_status gsi_batch_free(gsi_batch *b) {
+    B_TRY({
+        if (!b) return GSI_OK;
+        gsi_ctx *c = b->ctx;
+        GSI_HIP(hipSetDevice(c->device));
+        GSI_HIP(hipStreamSynchronize(c->stream));
+        delete b;
+    })
+}
+
+gsi_status gsi_batch_tune(gsi_graph *g, uint32_t nq, const gsi_query_desc *qs, uint32_t sample,
+                          gsi_batch_schedule *out, double *out_ms) {
+    B_TRY({
+        if (!g || !out || (nq && !qs)) fail(GSI_E_INVALID, "null argument");
+        gsi_ctx *c = g->ctx;
+        BusyB busy(c);
+        GSI_HIP(hipSetDevice(c->device));
+        const uint32_t n = std::max<uint32_t>(1, std::min(nq, sample ? sample : 128u));
+        if (nq == 0) fail(GSI_E_INVALID, "no queries to tune on");
+        const gsi_batch_schedule cands[] = {{64, 8}, {64, 4}, {256, 8}, {256, 4}, {1024, 8}, {1024, 4}};
+        double best = 1e300;
+        gsi_batch_schedule win{256, 8};
+        for (const auto &sc : cands) {
+            auto t0 = std::chrono::steady_clock::now();
+            gsi_batch *b = run_batch(g, n, qs, GSI_COUNT_ONLY, sc);
+            double ms = ms_since(t0);
+            delete b;
+            if (ms < best) {
+                best = ms;
+                win = sc;
+            }
+        }
+        g->tuned = win;
+        *out = win;
+        if (out_ms) *out_ms = best / n;
+    })
+}
+
+}  // extern "C"

@@ -94,6 +94,21 @@ void Arena::release(void *p) {
     free_[off] = sz;
 }
 
+void Arena::shrink(void *p, uint64_t bytes) {
+    if (!p) return;
+    uint64_t off = (uintptr_t)p - base_;
+    auto it = live_.find(off);
+    if (it == live_.end()) return;
+    uint64_t keep = round_up(bytes ? bytes : 1);
+    if (keep >= it->second) return;
+    uint64_t tail = it->second - keep;
+    it->second = keep;
+    used_ -= tail;
+    live_[off + keep] = tail;  // hand the tail back through release()
+    used_ += tail;
+    release((void *)(base_ + off + keep));
+}
+
 uint64_t Arena::largest_free() const {
     uint64_t b = 0;
     for (auto &kv : free_) b = kv.second > b ? kv.second : b;
@@ -122,6 +137,11 @@ hipEvent_t take_event(gsi_ctx *c) {
     return e;
 }
 
+// launches with at least this many algorithmic bytes are also summed under
+// "<kernel>@large", so bandwidth-bound launches can be read apart from the
+// latency-bound small ones
+static constexpr double LARGE_LAUNCH_BYTES = 16.0 * (1 << 20);
+
 static void drain_records(gsi_ctx *c) {
     if (c->recs.empty()) return;
     GSI_HIP(hipStreamSynchronize(c->stream));
@@ -131,6 +151,13 @@ static void drain_records(gsi_ctx *c) {
         c->acc[r.kid].launches++;
         c->acc[r.kid].total_ms += ms;
         c->acc[r.kid].alg_bytes += r.bytes;
+        if (r.bytes >= LARGE_LAUNCH_BYTES) {
+            std::string big = c->knames[r.kid] + "@large";
+            int kb = kernel_id(c, big.c_str());
+            c->acc[kb].launches++;
+            c->acc[kb].total_ms += ms;
+            c->acc[kb].alg_bytes += r.bytes;
+        }
         c->free_events.push_back(r.a);
         c->free_events.push_back(r.b);
     }
@@ -158,10 +185,10 @@ struct Busy {
 
 using namespace gsi;
 
-#define GSI_TRY(body)                                     \
+#define GSI_TRY(...)                                     \
     try {                                                 \
         clear_error();                                    \
-        body;                                             \
+        __VA_ARGS__;                                      \
         return GSI_OK;                                    \
     } catch (const Fail &f_) {                            \
         return f_.st;                                     \
@@ -195,7 +222,7 @@ gsi_status gsi_ctx_create(const gsi_options *o, gsi_ctx **out) {
         c->stream = (hipStream_t)o->hip_stream;
         c->flags = o->flags;
         c->arena.init(o->arena_ptr, o->arena_bytes);
-        hipError_t e = hipHostMalloc((void **)&c->pinned, 4096, hipHostMallocDefault);
+        hipError_t e = hipHostMalloc((void **)&c->pinned, 65536, hipHostMallocDefault);
         if (e != hipSuccess) {
             delete c;
             fail(GSI_E_DEVICE, "hipHostMalloc failed: %s", hipGetErrorString(e));

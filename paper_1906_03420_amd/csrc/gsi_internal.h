@@ -49,6 +49,7 @@ class Arena {
     void init(void *base, uint64_t size);
     void *alloc(uint64_t bytes, bool high);  // nullptr when it does not fit
     void release(void *p);
+    void shrink(void *p, uint64_t bytes);  // keep the first `bytes`, free the rest
     uint64_t used() const { return used_; }
     uint64_t peak() const { return peak_; }
     uint64_t largest_free() const;
@@ -74,7 +75,7 @@ struct gsi_ctx {
     hipStream_t stream = nullptr;
     uint32_t flags = 0;
     gsi::Arena arena;
-    uint64_t *pinned = nullptr;  // host-pinned scalars for per-level readbacks
+    uint64_t *pinned = nullptr;  // host-pinned staging: scalars [0,4K), status [4K,8K), plans [8K,64K)
     std::atomic<int> busy{0};
     std::set<gsi_graph *> graphs;
     std::set<gsi_result *> results;
@@ -103,6 +104,7 @@ struct gsi_graph {
     uint32_t max_chain = 0;
     uint64_t bytes = 0;
     double build_ms = 0;
+    gsi_batch_schedule tuned{0, 0};  // schedule picked by gsi_batch_tune
 };
 
 struct gsi_result {
@@ -214,6 +216,11 @@ struct HostQuery {
 HostQuery validate_query(uint32_t k, const uint32_t *vl, uint32_t qm, const uint32_t *s, const uint32_t *d,
                          const uint32_t *l);
 void run_filter(gsi_graph *g, const HostQuery &q, uint64_t *d_bits, uint32_t *d_counts);
+// query vertex u of query i has bitset row / count slot qbase[i] + u
+void run_filter_many(gsi_graph *g, const std::vector<const HostQuery *> &qs, const std::vector<uint32_t> &qbase,
+                     uint64_t *d_bits, uint32_t *d_counts);
+void make_plan(const gsi_graph *g, const HostQuery &q, const std::vector<uint32_t> &cand,
+               std::vector<uint32_t> &order, std::vector<uint32_t> &e0src);
 gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options *opt);
 
 }  // namespace gsi

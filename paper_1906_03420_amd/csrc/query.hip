@@ -31,6 +31,8 @@
 #include <numeric>
 
 #include "gsi_internal.h"
+#include "fused.h"
+#include "join_device.h"
 
 namespace gsi {
 
@@ -90,6 +92,8 @@ HostQuery validate_query(uint32_t k, const uint32_t *vl, uint32_t qm, const uint
 struct FilterArgs {
     uint32_t k;
     uint32_t label_only;
+    uint32_t word_mask;            // bit i set when some query vertex has bits in word i
+    uint32_t dst[GSI_MAX_K];       // bitset row / count slot of query vertex u
     uint32_t q[GSI_MAX_K][GSI_SIG_WORDS];
 };
 
@@ -98,20 +102,26 @@ static void query_signatures(const HostQuery &q, FilterArgs &fa) {
     memset(&fa, 0, sizeof(fa));
     fa.k = q.k;
     for (uint32_t u = 0; u < q.k; u++) {
+        fa.dst[u] = u;
         fa.q[u][0] = q.vl[u];
         uint32_t cnt[SIG_GROUPS] = {0};
         for (auto &p : q.adj[u]) cnt[sig_group(p.second, q.vl[p.first])]++;
         for (uint32_t g = 0; g < SIG_GROUPS; g++)
             if (cnt[g]) fa.q[u][1 + g / 16] |= (cnt[g] == 1 ? 1u : 3u) << (2 * (g % 16));
+        for (int i = 1; i < GSI_SIG_WORDS; i++)
+            if (fa.q[u][i]) fa.word_mask |= 1u << i;
     }
 }
 
-// One pass over the column-first table for all query vertices: a wave reads
-// word w of 64 consecutive signatures in one coalesced load, and its ballot
-// of "v in C(u)" is the bitset word of those 64 vertices.  Waves none of
-// whose vertices carries a query label skip words 1..15.
+// One pass over the column-first table for all query vertices.  A lane owns
+// one data vertex and a bit mask of the query vertices whose label it
+// carries.  It then issues, back to back, the loads of every signature word
+// some query vertex uses (a wave reads word i of 64 consecutive vertices in
+// one 256-byte access; a lane whose label matched no query vertex fetches
+// nothing) and tests each candidate query vertex against the words.  The
+// wave's ballot of "v in C(u)" is the bitset word of its 64 vertices.
 __global__ __launch_bounds__(QT) void k_filter(const uint32_t *sig, uint32_t n, uint64_t nwords, FilterArgs fa,
-                                              uint64_t *bits, uint32_t *counts) {
+                                              uint64_t *bits, uint32_t *part) {
     __shared__ uint32_t s_cnt[GSI_MAX_K];
     if (threadIdx.x < GSI_MAX_K) s_cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -119,27 +129,97 @@ __global__ __launch_bounds__(QT) void k_filter(const uint32_t *sig, uint32_t n, 
     const bool valid = v < n;
     const uint32_t lane = lane_id();
     const uint64_t wave_first = (uint64_t)blockIdx.x * QT + (threadIdx.x & ~63u);
-    uint32_t w[GSI_SIG_WORDS];
-    w[0] = valid ? sig[v] : NONE32;
-    bool lab = false;
-    for (uint32_t u = 0; u < fa.k; u++) lab |= (w[0] == fa.q[u][0]);
-    const bool need_rest = !fa.label_only && __ballot(valid && lab) != 0;
+    const uint32_t w0 = valid ? sig[v] : NONE32;
+    uint32_t ok = 0;
+    for (uint32_t u = 0; u < fa.k; u++) ok |= (valid && w0 == fa.q[u][0]) ? (1u << u) : 0u;
+    const uint32_t need = fa.label_only ? 0u : fa.word_mask;
+    uint32_t wv[GSI_SIG_WORDS];
 #pragma unroll
-    for (int i = 1; i < GSI_SIG_WORDS; i++) w[i] = (need_rest && valid) ? sig[(uint64_t)i * n + v] : 0u;
-    for (uint32_t u = 0; u < fa.k; u++) {
-        bool ok = valid && w[0] == fa.q[u][0];
-        if (need_rest) {
+    for (int i = 1; i < GSI_SIG_WORDS; i++)
+        wv[i] = (((need >> i) & 1u) && ok) ? sig[(uint64_t)i * n + v] : 0xFFFFFFFFu;
+    if (ok && need) {
+        for (uint32_t u = 0; u < fa.k; u++) {
+            if (!((ok >> u) & 1u)) continue;
+            bool good = true;
 #pragma unroll
-            for (int i = 1; i < GSI_SIG_WORDS; i++) ok = ok && ((w[i] & fa.q[u][i]) == fa.q[u][i]);
+            for (int i = 1; i < GSI_SIG_WORDS; i++) {
+                const uint32_t qw = fa.q[u][i];
+                good = good && ((wv[i] & qw) == qw);
+            }
+            if (!good) ok &= ~(1u << u);
         }
-        uint64_t mask = __ballot(ok);
+    }
+    for (uint32_t u = 0; u < fa.k; u++) {
+        const uint64_t mask = __ballot((ok >> u) & 1u);
         if (lane == 0 && wave_first < n) {
-            bits[(uint64_t)u * nwords + (wave_first >> 6)] = mask;
+            bits[(uint64_t)fa.dst[u] * nwords + (wave_first >> 6)] = mask;
             if (mask) atomicAdd(&s_cnt[u], (uint32_t)__popcll(mask));
         }
     }
     __syncthreads();
-    if (threadIdx.x < fa.k && s_cnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], s_cnt[threadIdx.x]);
+    // one partial count per workgroup and query vertex (summed by
+    // k_filter_counts; no same-address atomics across workgroups)
+    if (threadIdx.x < GSI_MAX_K) part[(uint64_t)blockIdx.x * GSI_MAX_K + threadIdx.x] = s_cnt[threadIdx.x];
+}
+
+// counts[dst[u]] = sum over workgroups of the partial counts of u; one
+// workgroup per query vertex
+__global__ __launch_bounds__(QT) void k_filter_counts(const uint32_t *part, uint32_t nb, FilterArgs fa,
+                                                     uint32_t *counts) {
+    __shared__ uint32_t s_w[QT / 64];
+    const uint32_t u = blockIdx.x;
+    uint32_t sum = 0;
+    for (uint32_t b = threadIdx.x; b < nb; b += QT) sum += part[(uint64_t)b * GSI_MAX_K + u];
+    sum = wave_sum(sum);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int q = 0; q < QT / 64; q++) t += s_w[q];
+        counts[fa.dst[u]] = t;
+    }
+}
+
+static void launch_filter(gsi_ctx *c, gsi_graph *g, const FilterArgs &fa, uint64_t *bits, uint32_t *counts,
+                          uint32_t *part) {
+    const uint64_t nwords = ((uint64_t)g->n + 63) / 64;
+    const uint32_t nb = nblocks(g->n);
+    double bytes = 4.0 * g->n * (1 + __builtin_popcount(fa.word_mask)) + (double)fa.k * nwords * 8;
+    launch(c, "k_filter", bytes, k_filter, nb, QT, (const uint32_t *)g->sig, g->n, nwords, fa, bits, part);
+    launch(c, "k_filter_counts", 4.0 * nb * fa.k, k_filter_counts, fa.k, QT, (const uint32_t *)part, nb, fa, counts);
+}
+
+// Batched filter: the query vertices of many queries, 32 per pass.  Passes
+// take query vertices sorted by label, so a pass usually covers one or two
+// labels and lanes of other labels read nothing past word 0.
+void run_filter_many(gsi_graph *g, const std::vector<const HostQuery *> &qs, const std::vector<uint32_t> &qbase,
+                     uint64_t *bits, uint32_t *counts) {
+    gsi_ctx *c = g->ctx;
+    struct QV {
+        uint32_t label, q, u;
+    };
+    std::vector<QV> all;
+    for (size_t i = 0; i < qs.size(); i++)
+        for (uint32_t u = 0; u < qs[i]->k; u++) all.push_back({qs[i]->vl[u], (uint32_t)i, u});
+    std::stable_sort(all.begin(), all.end(), [](const QV &a, const QV &b) { return a.label < b.label; });
+    Scratch s(c);
+    uint32_t *part = s.get<uint32_t>((uint64_t)nblocks(g->n) * GSI_MAX_K, "filter partial counts");
+    std::vector<FilterArgs> one(qs.size());
+    for (size_t i = 0; i < qs.size(); i++) query_signatures(*qs[i], one[i]);
+    for (size_t base = 0; base < all.size(); base += GSI_MAX_K) {
+        FilterArgs fa;
+        memset(&fa, 0, sizeof(fa));
+        uint32_t k = (uint32_t)std::min<size_t>(GSI_MAX_K, all.size() - base);
+        fa.k = k;
+        for (uint32_t t = 0; t < k; t++) {
+            const QV &x = all[base + t];
+            fa.dst[t] = qbase[x.q] + x.u;
+            memcpy(fa.q[t], one[x.q].q[x.u], sizeof(fa.q[t]));
+            for (int i = 1; i < GSI_SIG_WORDS; i++)
+                if (fa.q[t][i]) fa.word_mask |= 1u << i;
+        }
+        launch_filter(c, g, fa, bits, counts, part);
+    }
 }
 
 static void filter_impl(gsi_graph *g, const HostQuery &q, bool label_only, uint64_t *bits, uint32_t *counts) {
@@ -147,10 +227,9 @@ static void filter_impl(gsi_graph *g, const HostQuery &q, bool label_only, uint6
     FilterArgs fa;
     query_signatures(q, fa);
     fa.label_only = label_only ? 1u : 0u;
-    uint64_t nwords = ((uint64_t)g->n + 63) / 64;
-    fill_u32(c, counts, 0, q.k);
-    double bytes = 64.0 * g->n + (double)q.k * nwords * 8;
-    launch(c, "k_filter", bytes, k_filter, nblocks(g->n), QT, g->sig, g->n, nwords, fa, bits, counts);
+    Scratch s(c);
+    uint32_t *part = s.get<uint32_t>((uint64_t)nblocks(g->n) * GSI_MAX_K, "filter partial counts");
+    launch_filter(c, g, fa, bits, counts, part);
 }
 
 void run_filter(gsi_graph *g, const HostQuery &q, uint64_t *bits, uint32_t *counts) {
@@ -206,36 +285,6 @@ struct LevelArgs {
     uint32_t final_level, count_only;
 };
 
-// N(v,l) through PCSR (Sec. IV lookup): read the home group (8 x 16-byte
-// loads = its 128 bytes), probe the 15 key slots in ascending key order,
-// follow the GID chain.  Keys of a chain ascend, so meeting a larger key (or
-// the empty marker) ends the search.  Returns (offset, length) in ci.
-__device__ __forceinline__ uint2 pcsr_find(const uint32_t *gl, uint32_t G, uint32_t H, uint32_t v) {
-    if (G == 0) return make_uint2(0, 0);
-    uint32_t grp = pcsr_home(v, H);
-    for (uint32_t hop = 0; hop < G; hop++) {
-        const uint4 *p = reinterpret_cast<const uint4 *>(gl + (uint64_t)grp * GROUP_WORDS);
-        uint32_t w[GROUP_WORDS];
-#pragma unroll
-        for (int i = 0; i < 8; i++) {
-            uint4 t = p[i];
-            w[4 * i] = t.x;
-            w[4 * i + 1] = t.y;
-            w[4 * i + 2] = t.z;
-            w[4 * i + 3] = t.w;
-        }
-#pragma unroll
-        for (uint32_t s = 0; s < KEYS_PER_GROUP; s++) {
-            uint32_t key = w[2 * s];
-            if (key == v) return make_uint2(w[2 * s + 1], w[2 * s + 3] - w[2 * s + 1]);
-            if (key > v) return make_uint2(0, 0);
-        }
-        grp = w[2 * KEYS_PER_GROUP];
-        if (grp == NONE32) break;
-    }
-    return make_uint2(0, 0);
-}
-
 __global__ __launch_bounds__(QT) void k_locate(LevelArgs a) {
     const uint64_t i = (uint64_t)blockIdx.x * QT + threadIdx.x;
     const bool valid = i < a.R;
@@ -284,26 +333,65 @@ __device__ __forceinline__ uint64_t row_of(const uint64_t *F, uint64_t lo, uint6
     return lo;
 }
 
-__device__ __forceinline__ bool in_sorted(const uint32_t *list, uint32_t len, uint32_t x) {
-    uint32_t lo = 0, hi = len;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (list[mid] < x) lo = mid + 1;
-        else hi = mid;
+// The rows a tile touches, staged once per workgroup: F[i] and the start of
+// N(v'_i, l0) in ci for rows r_lo..r_hi.  A thread then finds its row with a
+// binary search in LDS instead of a chain of dependent global loads.  Tiles
+// spanning more than QT rows (long runs of rows with no first-edge
+// neighbours) search F in global memory instead.
+struct TileRows {
+    uint64_t r_lo, r_hi;
+    bool staged;
+};
+
+__device__ __forceinline__ TileRows stage_rows(const LevelArgs &a, uint64_t tile, uint64_t *s_F, uint32_t *s_st) {
+    TileRows t;
+    t.r_lo = a.tile_row[tile];
+    t.r_hi = a.tile_row[tile + 1];
+    const uint64_t nr = t.r_hi - t.r_lo + 1;
+    t.staged = nr <= QT;
+    if (t.staged) {
+        if (threadIdx.x < nr) {
+            s_F[threadIdx.x] = a.F[t.r_lo + threadIdx.x];
+            s_st[threadIdx.x] = a.loc[(uint64_t)a.e0 * a.R + t.r_lo + threadIdx.x];
+        }
+        __syncthreads();
     }
-    return lo < len && list[lo] == x;
+    return t;
+}
+
+// row i holding slot p, with F[i] and the ci start of its first-edge list
+__device__ __forceinline__ void find_row(const LevelArgs &a, const TileRows &t, const uint64_t *s_F,
+                                         const uint32_t *s_st, uint64_t p, uint64_t *i, uint64_t *Fi, uint32_t *st) {
+    if (t.staged) {
+        uint32_t lo = 0, hi = (uint32_t)(t.r_hi - t.r_lo);
+        while (lo < hi) {
+            uint32_t mid = (lo + hi + 1) >> 1;
+            if (s_F[mid] <= p) lo = mid;
+            else hi = mid - 1;
+        }
+        *i = t.r_lo + lo;
+        *Fi = s_F[lo];
+        *st = s_st[lo];
+    } else {
+        *i = row_of(a.F, t.r_lo, t.r_hi, p);
+        *Fi = a.F[*i];
+        *st = a.loc[(uint64_t)a.e0 * a.R + *i];
+    }
 }
 
 __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
     __shared__ uint32_t s_cnt[QT / 64];
+    __shared__ uint64_t s_F[QT];
+    __shared__ uint32_t s_st[QT];
     const uint64_t p0 = (uint64_t)blockIdx.x * QT;
-    const uint64_t r_lo = a.tile_row[blockIdx.x], r_hi = a.tile_row[blockIdx.x + 1];
+    const TileRows tr = stage_rows(a, blockIdx.x, s_F, s_st);
     const uint64_t p = p0 + threadIdx.x;
     bool keep = false;
     if (p < a.gba) {
-        const uint64_t i = row_of(a.F, r_lo, r_hi, p);
-        const uint32_t t = (uint32_t)(p - a.F[i]);
-        const uint32_t x = a.e[a.e0].ci[a.loc[(uint64_t)a.e0 * a.R + i] + t];
+        uint64_t i, Fi;
+        uint32_t st0;
+        find_row(a, tr, s_F, s_st, p, &i, &Fi, &st0);
+        const uint32_t x = a.e[a.e0].ci[st0 + (uint32_t)(p - Fi)];
         keep = (a.Cu[x >> 6] >> (x & 63)) & 1ull;
         for (uint32_t c = 0; keep && c < a.j; c++) keep = a.M[(uint64_t)c * a.R + i] != x;
         for (uint32_t e = 0; keep && e < a.ne; e++) {
@@ -328,24 +416,10 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
     }
 }
 
-// FNV-1a-64 over the four little-endian bytes of one 32-bit word
-__device__ __forceinline__ uint64_t fnv_word(uint64_t h, uint32_t v) {
-#pragma unroll
-    for (int b = 0; b < 4; b++) {
-        h ^= (v >> (8 * b)) & 0xFFu;
-        h *= 1099511628211ull;
-    }
-    return h;
-}
-// SplitMix64 output mixing (Steele, Lea, Flood 2014)
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
 __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
     __shared__ uint64_t s_d[2][QT / 64];
+    __shared__ uint64_t s_F[QT];
+    __shared__ uint32_t s_st[QT];
     const uint64_t tile = blockIdx.x;
     if (a.tile_off[tile + 1] == a.tile_off[tile]) {  // whole tile empty (uniform)
         if (a.final_level && threadIdx.x == 0) {
@@ -355,7 +429,7 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
         return;
     }
     const uint64_t p0 = tile * QT;
-    const uint64_t r_lo = a.tile_row[tile], r_hi = a.tile_row[tile + 1];
+    const TileRows tr = stage_rows(a, tile, s_F, s_st);
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
     const uint64_t *words = a.bitmap + tile * (QT / 64);
     const uint64_t word = words[w];
@@ -366,8 +440,10 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
     uint64_t h = 0;
     if (keep && pos < a.S) {
         const uint64_t p = p0 + threadIdx.x;
-        const uint64_t i = row_of(a.F, r_lo, r_hi, p);
-        const uint32_t x = a.e[a.e0].ci[a.loc[(uint64_t)a.e0 * a.R + i] + (uint32_t)(p - a.F[i])];
+        uint64_t i, Fi;
+        uint32_t st0;
+        find_row(a, tr, s_F, s_st, p, &i, &Fi, &st0);
+        const uint32_t x = a.e[a.e0].ci[st0 + (uint32_t)(p - Fi)];
         if (!a.final_level) {
             for (uint32_t c = 0; c < a.j; c++) a.Mn[(uint64_t)c * a.S + pos] = a.M[(uint64_t)c * a.R + i];
             a.Mn[(uint64_t)a.j * a.S + pos] = x;
@@ -469,8 +545,8 @@ static void reduce_pairs(gsi_ctx *c, const uint64_t *part, uint64_t n, uint64_t 
 // |E_l|/|E|.  Ties go to the smaller query vertex id.  First edge e0
 // (Algorithm 4): the linking edge of least freq(l), ties to the placed end
 // that was placed first.
-static void make_plan(const gsi_graph *g, const HostQuery &q, const std::vector<uint32_t> &cand,
-                      std::vector<uint32_t> &order, std::vector<uint32_t> &e0src) {
+void make_plan(const gsi_graph *g, const HostQuery &q, const std::vector<uint32_t> &cand,
+               std::vector<uint32_t> &order, std::vector<uint32_t> &e0src) {
     const uint32_t k = q.k;
     order.clear();
     e0src.assign(k, NONE32);
@@ -552,7 +628,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     auto t0 = std::chrono::steady_clock::now();
     const uint32_t k = q.k;
     const uint32_t flags = opt ? opt->flags : 0u;
-    if (flags & ~(GSI_COUNT_ONLY | GSI_FILTER_LABEL_ONLY)) fail(GSI_E_INVALID, "unknown query flag");
+    if (flags & ~(GSI_COUNT_ONLY | GSI_FILTER_LABEL_ONLY | GSI_NO_FUSED)) fail(GSI_E_INVALID, "unknown query flag");
     const bool count_only = (flags & GSI_COUNT_ONLY) != 0;
     const uint64_t max_rows = opt ? opt->max_rows : 0;
 
@@ -693,7 +769,105 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         return finish();
     }
 
-    for (uint32_t j = 1; j < k; j++) {
+    // Fused small-table levels: one workgroup runs levels while they fit,
+    // then the per-level kernels continue from where it stopped.
+    uint32_t jstart = 1;
+    Scratch fs(c);
+    {
+        uint32_t cap_rows = FUSED_MAX_ROWS, cap_slots = FUSED_MAX_SLOTS;
+        if (opt && opt->fused_max_rows) cap_rows = std::min(cap_rows, opt->fused_max_rows);
+        if (opt && opt->fused_max_slots) cap_slots = std::min(cap_slots, opt->fused_max_slots);
+        if (!(flags & GSI_NO_FUSED) && R <= cap_rows && cap_slots >= 64) {
+            uint32_t n_edges = 0;
+            for (uint32_t j = 1; j < k; j++)
+                for (uint32_t i = 0; i < j; i++)
+                    for (auto &p : q.adj[order[j]]) n_edges += p.first == order[i];
+            const size_t pb = fplan_bytes(n_edges);
+            if (pb > 56 * 1024) fail(GSI_E_INTERNAL, "query plan too large for the staging buffer");
+            FPlan *hp = reinterpret_cast<FPlan *>(reinterpret_cast<char *>(c->pinned) + 8192);
+            memset(hp, 0, pb);
+            hp->k = k;
+            hp->count_only = count_only ? 1u : 0u;
+            hp->cap_rows = cap_rows;
+            hp->cap_slots = cap_slots;
+            for (uint32_t v = 0; v < k; v++) hp->qcol[v] = col[v];
+            uint32_t ei = 0;
+            for (uint32_t j = 1; j < k; j++) {
+                hp->lv_first[j] = ei;
+                hp->Cu[j] = bits + (uint64_t)order[j] * nwords;
+                uint32_t ne = 0;
+                for (uint32_t i = 0; i < j; i++)
+                    for (auto &p : q.adj[order[j]])
+                        if (p.first == order[i]) {
+                            const uint32_t l = p.second;
+                            FEdge &fe = hp->edges[ei + ne];
+                            fe.gl = g->gl + g->group_base[l] * GROUP_WORDS;
+                            fe.ci = g->ci + g->ci_base[l];
+                            fe.G = g->G[l];
+                            fe.H = g->H[l];
+                            fe.col = i;
+                            if (order[i] == e0src[j]) hp->lv_e0[j] = ne;
+                            ne++;
+                        }
+                hp->lv_ne[j] = ne;
+                st.n_link[j] = ne;
+                ei += ne;
+            }
+            FPlan *dplan = reinterpret_cast<FPlan *>(fs.get<uint8_t>(pb, "fused plan"));
+            GSI_HIP(hipMemcpyAsync(dplan, hp, pb, hipMemcpyHostToDevice, c->stream));
+            uint32_t *buf0 = fs.get<uint32_t>((uint64_t)cap_rows * k, "fused table 0");
+            uint32_t *buf1 = fs.get<uint32_t>((uint64_t)cap_rows * k, "fused table 1");
+            uint32_t *floc = fs.get<uint32_t>(2ull * (k - 1) * cap_rows, "fused lookups");
+            FStatus *dst = reinterpret_cast<FStatus *>(fs.get<uint64_t>(sizeof(FStatus) / 8, "fused status"));
+            fill_u64(c, reinterpret_cast<uint64_t *>(dst), 0, sizeof(FStatus) / 8);
+            uint32_t *out = count_only ? nullptr : persist<uint32_t>(c, (uint64_t)cap_slots * k, "result rows");
+            res->rows = out;
+            launch_fused(c, dplan, M, (uint32_t)R, buf0, buf1, floc, out, dst, 0.0);
+            FStatus *hs = reinterpret_cast<FStatus *>(reinterpret_cast<char *>(c->pinned) + 4096);
+            GSI_HIP(hipMemcpyAsync(hs, dst, sizeof(FStatus), hipMemcpyDeviceToHost, c->stream));
+            sync(c);
+            // algorithmic bytes of the fused launch, from the sizes it met
+            if ((c->flags & GSI_CTX_PROFILE) && !c->recs.empty()) {
+                double b = 0;
+                uint32_t last = hs->done ? (uint32_t)hs->levels : (uint32_t)hs->level;
+                for (uint32_t j = 1; j <= last && j < k; j++) {
+                    double Rj = (double)hs->lv_rows[j], Gj = (double)hs->lv_gba[j], Sj = (double)hs->lv_surv[j];
+                    double ne = hp->lv_ne[j];
+                    b += Rj * (4.0 * ne + 128.0 * ne + 8.0 * ne + 4.0 * j) + 4.0 * Gj +
+                         Sj * (4.0 + 4.0 * j + 4.0 * (j + 1));
+                }
+                c->recs.back().bytes = b;
+            }
+            const uint32_t last = hs->done ? (uint32_t)hs->levels : (uint32_t)hs->level;
+            for (uint32_t j = 1; j <= last && j < k; j++) {
+                st.rows[j] = hs->lv_rows[j];
+                st.gba[j] = hs->lv_gba[j];
+                st.survivors[j] = hs->lv_surv[j];
+            }
+            if (hs->done) {
+                st.levels = (uint32_t)hs->levels;
+                res->count = hs->count;
+                res->digest[0] = hs->digest[0];
+                res->digest[1] = hs->digest[1];
+                if (out && hs->count == 0) {
+                    c->arena.release(out);
+                    res->rows = nullptr;
+                } else if (out) {
+                    c->arena.shrink(out, hs->count * k * 4);
+                }
+                st.join_ms = ms_since(tj);
+                return finish();
+            }
+            if (out) c->arena.release(out);
+            res->rows = nullptr;
+            jstart = (uint32_t)hs->level;
+            R = hs->rows;
+            if (hs->mloc == 0) M = buf0;
+            else if (hs->mloc == 1) M = buf1;
+        }
+    }
+
+    for (uint32_t j = jstart; j < k; j++) {
         const uint32_t u = order[j];
         const bool final_level = (j == k - 1);
         st.rows[j] = R;

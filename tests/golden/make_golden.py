@@ -2,9 +2,10 @@
 
 Calls only the CPU oracle and the seeded input generators.  Usage:
     python tests/golden/make_golden.py er1k ba1m
-Each query is accepted when the oracle finishes it within the deterministic
-limits below (at most 10^9 embeddings and 2*10^10 search nodes); a rejected
-query would be redrawn with the next attempt number and the rejection logged.
+Each query is accepted when the generator produces it and the oracle
+finishes it within deterministic limits (at most 10^9 embeddings and a
+per-workload cap on search nodes); otherwise it is redrawn with the next
+attempt number and the rejection is logged in the output file.
 """
 import json
 import os
@@ -18,7 +19,8 @@ import oracle  # noqa: E402
 import workloads as w  # noqa: E402
 
 MAX_COUNT = 1_000_000_000
-MAX_NODES = 20_000_000_000
+MAX_NODES = {"er1k": 20_000_000_000, "ba1m": 20_000_000_000, "ba1m_batch": 4_000_000_000,
+             "rmat23": 4_000_000_000}
 
 
 def make(name: str, threads: int):
@@ -26,14 +28,20 @@ def make(name: str, threads: int):
     g = w.config_graph(name)
     og = oracle.OracleGraph(g)
     mk = w.QueryMaker(g)
-    out = dict(workload=name, n=g.n, m=g.m, limits=dict(max_count=MAX_COUNT, max_nodes=MAX_NODES),
+    max_nodes = MAX_NODES[name]
+    out = dict(workload=name, n=g.n, m=g.m, limits=dict(max_count=MAX_COUNT, max_nodes=max_nodes),
                queries=[], rejected=[])
     for i in range(c["nq"]):
         attempt = 0
         while True:
-            q = w.config_query(g, name, i, attempt=attempt, maker=mk)
+            try:
+                q = w.config_query(g, name, i, attempt=attempt, maker=mk)
+            except RuntimeError:
+                out["rejected"].append(dict(index=i, attempt=attempt, status="no walk"))
+                attempt += 1
+                continue
             t = time.time()
-            r = og.match(q, threads=threads, tuples=False, max_count=MAX_COUNT, max_nodes=MAX_NODES)
+            r = og.match(q, threads=threads, tuples=False, max_count=MAX_COUNT, max_nodes=max_nodes)
             dt = time.time() - t
             if r.status == oracle.OR_OK:
                 break

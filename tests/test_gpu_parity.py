@@ -221,3 +221,64 @@ def test_paper_example_join_numbers(ctx, golden_dir):
     assert r.rows().tolist() == [gold["single_match"]["tuple"]]
     r.free()
     dg.free()
+
+
+FUSED_MODES = [dict(), dict(flags=4), dict(fused_max_rows=64, fused_max_slots=128),
+               dict(fused_max_rows=300, fused_max_slots=64), dict(fused_max_rows=8, fused_max_slots=4096)]
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_fused_and_per_level_paths_agree(ctx, seed):
+    """The fused small-table workgroup, the per-level kernels, and every mix
+    forced by low fused capacities give the oracle's result and the same
+    per-level sizes."""
+    r = np.random.default_rng(1000 + seed)
+    n = int(r.integers(50, 400))
+    g = w.random_small_graph(n, float(r.uniform(0.01, 0.05)), int(r.integers(1, 3)), int(r.integers(1, 3)), seed + 5)
+    if g.m == 0:
+        return
+    dg = ctx.load(g)
+    og = oracle.OracleGraph(g)
+    for t in range(3):
+        k = int(r.integers(2, 8))
+        q = w.random_connected_query(k, int(r.integers(0, 3)), int(g.vlabel.max()) + 1, int(g.elabel.max()) + 1,
+                                     seed * 31 + t)
+        want = og.match(q, threads=4, max_count=3_000_000)
+        if want.status != 0:  # more than 3M embeddings: too large for a tuple-level check
+            continue
+        ref = None
+        for mode in FUSED_MODES:
+            print("seed", seed, "query", t, "k", k, "mode", mode, flush=True)
+            res = dg.query(q, **mode)
+            assert res.count == want.count
+            np.testing.assert_array_equal(res.sorted_rows(), want.tuples)
+            assert res.digest == want.digest
+            stt = res.stats()
+            sizes = (stt["rows"], stt["gba"], stt["survivors"])
+            if ref is None:
+                ref = sizes
+            else:
+                assert sizes == ref
+            res.free()
+    dg.free()
+
+
+def test_fused_path_er1k_and_count_only(ctx):
+    import paper_1906_03420_amd as gsi
+    g = w.config_graph("er1k")
+    dg = ctx.load(g)
+    og = oracle.OracleGraph(g)
+    mk = w.QueryMaker(g)
+    for i in range(8):
+        q = w.config_query(g, "er1k", i, maker=mk)
+        want = og.match(q, threads=4)
+        for mode in FUSED_MODES:
+            a = dg.query(q, **mode)
+            b = dg.query(q, flags=mode.get("flags", 0) | gsi.GSI_COUNT_ONLY,
+                         **{k2: v for k2, v in mode.items() if k2 != "flags"})
+            assert a.count == b.count == want.count
+            assert a.digest == b.digest == want.digest
+            np.testing.assert_array_equal(a.sorted_rows(), want.tuples)
+            a.free(); b.free()
+    live, _ = ctx.memory()
+    dg.free()

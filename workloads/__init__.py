@@ -14,6 +14,9 @@ in Sec. VIII-A and random-walk queries as in the same section):
   BA-1M     Barabasi-Albert (Batagelj-Brandes), 1,000,000 vertices, seed K_11
             and 10 attachments per vertex (9,999,945 edges); 32 vertex labels
             Zipf(1.1), 8 edge labels uniform; 100 walk queries, 6..12 vertices.
+  BA-1M-B   the BA-1M graph with 1,024 queries of 4..16 vertices, shapes tree,
+            walk with a cycle (|E(Q)| >= |V(Q)|) and dense (all data edges among
+            the walk's vertices), for the batched path.
   RMAT-23   R-MAT scale 23, 100M edges, (a,b,c) = (0.57,0.19,0.19); 100 vertex
             labels and 20 edge labels Zipf(1.1); 50 queries of 12 vertices
             (25 walk + 25 dense).
@@ -223,6 +226,9 @@ CONFIGS = {
                  gseed=17, lseed=2017, qseed=1017, nq=8, kmin=4, kmax=4, modes=("walk",)),
     "ba1m": dict(model="ba", n=1_000_000, d=10, nvl=32, nel=8, vdist="zipf", edist="uniform",
                  gseed=18, lseed=2018, qseed=1018, nq=100, kmin=6, kmax=12, modes=("walk",)),
+    "ba1m_batch": dict(model="ba", n=1_000_000, d=10, nvl=32, nel=8, vdist="zipf", edist="uniform",
+                       gseed=18, lseed=2018, qseed=1020, nq=1024, kmin=4, kmax=16,
+                       modes=("tree", "walk_cycle", "dense")),
     "rmat23": dict(model="rmat", scale=23, m=100_000_000, nvl=100, nel=20, vdist="zipf", edist="zipf",
                    gseed=19, lseed=2019, qseed=1019, nq=50, kmin=12, kmax=12, modes=("walk", "dense")),
 }

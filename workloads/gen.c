@@ -263,7 +263,9 @@ static int64_t edge_label(const qctx *q, uint32_t a, uint32_t b) {
 /*
  * mode 0 = walk (all traversed edges), 1 = tree (first-visit edges only),
  * 2 = dense (every data edge among the visited vertices),
- * 3 = walk with cycle (walk mode, redrawn until |E(Q)| >= k).
+ * 3 = walk with cycle: the traversed edges plus the first data edge among the
+ *     visited vertices that the walk did not traverse (pairs in first-visit
+ *     order), so the query holds a cycle; redrawn if there is no such edge.
  * Outputs: qlabel[k], edges (qsrc,qdst,qel) with capacity k*(k-1)/2,
  * source[k] = the data vertices visited (an embedding of the query).
  * Returns the number of query edges, or -1 if no walk reached k vertices.
@@ -300,13 +302,21 @@ int64_t gen_query(void *p, uint32_t k, int mode, uint64_t seed, uint32_t *qlabel
                 for (uint32_t j = i + 1; j < k; j++)
                     if (edge_label(q, vis[i], vis[j]) >= 0) { adj[i * k + j] = 1; adj[j * k + i] = 1; }
         }
+        if (mode == 3) {
+            int added = 0;
+            for (uint32_t i = 0; i < k && !added; i++)
+                for (uint32_t j = i + 1; j < k && !added; j++)
+                    if (!adj[i * k + j] && edge_label(q, vis[i], vis[j]) >= 0) {
+                        adj[i * k + j] = 1; adj[j * k + i] = 1; added = 1;
+                    }
+            if (!added) continue;
+        }
         uint32_t ne = 0;
         for (uint32_t i = 0; i < k; i++)
             for (uint32_t j = i + 1; j < k; j++)
                 if (adj[i * k + j]) {
                     qsrc[ne] = i; qdst[ne] = j; qel[ne] = (uint32_t)edge_label(q, vis[i], vis[j]); ne++;
                 }
-        if (mode == 3 && ne < k) continue;
         for (uint32_t i = 0; i < k; i++) qlabel[i] = q->vlabel[vis[i]];
         free(adj);
         return ne;

@@ -257,16 +257,18 @@ typedef struct {
  * Algorithm 4) in LDS-staged form.  A first tier uses workgroups of
  * `threads` threads (64, 256 or 1024; tables of up to 4x`threads` rows and
  * 16x`threads` |GBA| slots per level); queries it cannot hold rerun in a
- * second tier of 1024-thread workgroups, and the rest run one by one with
- * the per-level kernels.  `grid_scale` (1..8) multiplies the number of
+ * second tier of 1024-thread workgroups, and the rest run level-synchronously
+ * together.  `grid_scale` (1..8) multiplies the number of
  * resident workgroups per compute unit that is launched, in eighths. */
 typedef struct {
     uint32_t threads;     /* first-tier workgroup size: 64, 256 or 1024 */
     uint32_t grid_scale;  /* eighths of full occupancy launched, 1..8 */
 } gsi_batch_schedule;
 
+#define GSI_BATCH_LEVELS_ONLY 0x8u /* test only: no fused tiers; every query runs
+                                      in the level-synchronous engine */
 typedef struct {
-    uint32_t flags;               /* GSI_COUNT_ONLY */
+    uint32_t flags;               /* GSI_COUNT_ONLY | GSI_BATCH_LEVELS_ONLY */
     gsi_batch_schedule schedule;  /* threads == 0: the graph's tuned schedule
                                      (gsi_batch_tune), else 256 / 8 eighths */
 } gsi_batch_options;
@@ -278,7 +280,10 @@ typedef struct gsi_batch gsi_batch;
  *      (query vertices grouped by label), one readback of all |C(u)|;
  *   2. each query's matching order (Algorithm 2) on the host;
  *   3. all root tables C(u_first) compacted in one pass;
- *   4. the fused tiers and the per-level fallback described above.
+ *   4. the fused tiers; every query they cannot hold then runs in the
+ *      level-synchronous engine: each step advances all of them by one join
+ *      level in shared launches (one global row space, one global |GBA| slot
+ *      space), with exact per-query table sizes read back once per step.
  * Every query's result is the one gsi_query_run returns (same rows, count
  * and digest; row order may differ).  Errors as gsi_query_run, for the first
  * invalid query (its index is in the message). */

@@ -25,6 +25,7 @@ GSI_GRAPH_TEST_FEW_HOME_GROUPS = 0x1
 GSI_COUNT_ONLY = 0x1
 GSI_FILTER_LABEL_ONLY = 0x2
 GSI_NO_FUSED = 0x4
+GSI_BATCH_LEVELS_ONLY = 0x8
 
 STATUS_NAMES = {0: "GSI_OK", 1: "GSI_E_INVALID", 2: "GSI_E_NOMEM", 3: "GSI_E_DEVICE", 4: "GSI_E_CAPACITY",
                 5: "GSI_E_BUSY", 6: "GSI_E_INTERNAL"}

@@ -18,6 +18,7 @@
 
 #include "fused.h"
 #include "gsi_internal.h"
+#include "wide.h"
 
 struct gsi_batch {
     gsi_ctx *ctx = nullptr;
@@ -27,19 +28,22 @@ struct gsi_batch {
         uint32_t k = 0;
         uint64_t count = 0;
         uint64_t digest[2] = {0, 0};
-        uint8_t where = 0;  // 0: no rows, 1: fused output buffer, 2: own result
+        uint8_t where = 0;  // 0: no rows, 1: fused output buffer, 2: own result, 3: own rows block
         uint64_t out_off = 0;
         gsi_result *res = nullptr;
+        uint32_t *rows = nullptr;  // where == 3
     };
     std::vector<Entry> e;
     uint32_t *out = nullptr;
     gsi_batch_info info{};
     ~gsi_batch() {
-        for (auto &x : e)
+        for (auto &x : e) {
             if (x.res) {
                 ctx->arena.release(x.res->rows);
                 delete x.res;
             }
+            if (x.rows) ctx->arena.release(x.rows);
+        }
         if (out) ctx->arena.release(out);
     }
 };
@@ -149,7 +153,8 @@ gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32
                      gsi_batch_schedule sched) {
     gsi_ctx *c = g->ctx;
     auto t0 = std::chrono::steady_clock::now();
-    if (flags & ~GSI_COUNT_ONLY) fail(GSI_E_INVALID, "unknown batch flag");
+    if (flags & ~(GSI_COUNT_ONLY | GSI_BATCH_LEVELS_ONLY)) fail(GSI_E_INVALID, "unknown batch flag");
+    const bool levels_only = (flags & GSI_BATCH_LEVELS_ONLY) != 0;
     if (sched.threads != 64 && sched.threads != 256 && sched.threads != 1024)
         fail(GSI_E_INVALID, "schedule threads must be 64, 256 or 1024");
     if (sched.grid_scale < 1 || sched.grid_scale > 8) fail(GSI_E_INVALID, "schedule grid_scale must be 1..8");
@@ -204,11 +209,14 @@ gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32
     const FTier t1 = fused_tier(sched.threads), t2 = fused_tier(TIER2_THREADS);
     std::vector<uint32_t> ks(nq);
     for (uint32_t i = 0; i < nq; i++) ks[i] = hq[i].k;
-    std::vector<FusedQuery> fused;        // tier candidates, in root order
-    std::vector<uint32_t> per_level;      // batch indices
-    std::vector<uint8_t> plan_blob;
-    std::vector<uint32_t> root_rows;      // bitset row of each fused query's root
-    uint64_t m0_total = 0, out_total = 0;
+    struct Planned {
+        uint32_t qi, a;   // batch index, index among active queries
+        std::vector<uint32_t> order, e0src;
+        uint32_t R0;
+        uint64_t m0_off;
+    };
+    std::vector<Planned> planned;          // multi-vertex queries with candidates
+    std::vector<uint32_t> single;          // one-vertex queries
     for (size_t a = 0; a < active.size(); a++) {
         const uint32_t qi = active[a];
         const HostQuery &q = hq[qi];
@@ -219,17 +227,33 @@ gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32
             b->info.empty++;
             continue;
         }
-        std::vector<uint32_t> order, e0src;
-        make_plan(g, q, cand, order, e0src);
-        const uint32_t R0 = cand[order[0]];
-        if (q.k < 2 || R0 > t2.cap_rows) {
-            per_level.push_back(qi);
+        if (q.k < 2) {
+            single.push_back(qi);
             continue;
         }
+        Planned pl;
+        pl.qi = qi;
+        pl.a = (uint32_t)a;
+        make_plan(g, q, cand, pl.order, pl.e0src);
+        pl.R0 = cand[pl.order[0]];
+        pl.m0_off = 0;
+        planned.push_back(std::move(pl));
+    }
+
+    std::vector<FusedQuery> fused;         // tier candidates
+    std::vector<uint8_t> plan_blob;
+    std::vector<uint32_t> root_rows;       // bitset row of each planned query's root
+    uint64_t m0_total = 0, out_total = 0;
+    for (auto &pl : planned) {
+        const HostQuery &q = hq[pl.qi];
+        pl.m0_off = m0_total;
+        m0_total += pl.R0;
+        root_rows.push_back(qbase[pl.a] + pl.order[0]);
+        if (levels_only || pl.R0 > t2.cap_rows) continue;
         uint32_t n_edges = 0;
         for (uint32_t j = 1; j < q.k; j++)
             for (uint32_t i = 0; i < j; i++)
-                for (auto &p : q.adj[order[j]]) n_edges += p.first == order[i];
+                for (auto &p : q.adj[pl.order[j]]) n_edges += p.first == pl.order[i];
         const size_t pb = (fplan_bytes(n_edges) + 15) & ~size_t(15);
         const uint64_t off = plan_blob.size();
         plan_blob.resize(off + pb, 0);
@@ -239,16 +263,16 @@ gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32
         hp->cap_rows = 0xFFFFFFFFu;  // the tier's own capacities apply
         hp->cap_slots = 0xFFFFFFFFu;
         std::vector<uint32_t> col(q.k);
-        for (uint32_t j = 0; j < q.k; j++) col[order[j]] = j;
+        for (uint32_t j = 0; j < q.k; j++) col[pl.order[j]] = j;
         for (uint32_t v = 0; v < q.k; v++) hp->qcol[v] = col[v];
         uint32_t ei = 0;
         for (uint32_t j = 1; j < q.k; j++) {
             hp->lv_first[j] = ei;
-            hp->Cu[j] = bits + (uint64_t)(qbase[a] + order[j]) * nwords;
+            hp->Cu[j] = bits + (uint64_t)(qbase[pl.a] + pl.order[j]) * nwords;
             uint32_t ne = 0;
             for (uint32_t i = 0; i < j; i++)
-                for (auto &p : q.adj[order[j]])
-                    if (p.first == order[i]) {
+                for (auto &p : q.adj[pl.order[j]])
+                    if (p.first == pl.order[i]) {
                         const uint32_t l = p.second;
                         FEdge &fe = hp->edges[ei + ne];
                         fe.gl = g->gl + g->group_base[l] * GROUP_WORDS;
@@ -256,32 +280,30 @@ gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32
                         fe.G = g->G[l];
                         fe.H = g->H[l];
                         fe.col = i;
-                        if (order[i] == e0src[j]) hp->lv_e0[j] = ne;
+                        if (pl.order[i] == pl.e0src[j]) hp->lv_e0[j] = ne;
                         ne++;
                     }
             hp->lv_ne[j] = ne;
             ei += ne;
         }
         FusedQuery f;
-        f.qi = qi;
-        f.R0 = R0;
+        f.qi = pl.qi;
+        f.R0 = pl.R0;
         f.plan_off = off;
-        f.m0_off = m0_total;
+        f.m0_off = pl.m0_off;
         f.out_off = out_total;
-        m0_total += R0;
         out_total += b->count_only ? 0 : (uint64_t)t2.cap_slots * q.k;
-        root_rows.push_back(qbase[a] + order[0]);
         fused.push_back(f);
     }
 
-    if (!fused.empty()) {
-        uint8_t *d_plans = s.get<uint8_t>(plan_blob.size(), "batch plans");
+    std::vector<uint32_t> to_wide;  // batch indices
+    uint32_t *d_M0 = nullptr;
+    if (!planned.empty()) {
         uint32_t *d_rows = s.get<uint32_t>(root_rows.size(), "batch root rows");
-        GSI_HIP(hipMemcpyAsync(d_plans, plan_blob.data(), plan_blob.size(), hipMemcpyHostToDevice, c->stream));
         GSI_HIP(hipMemcpyAsync(d_rows, root_rows.data(), 4 * root_rows.size(), hipMemcpyHostToDevice, c->stream));
         // all root tables in one pass
         const uint64_t tw = (uint64_t)root_rows.size() * nwords;
-        uint32_t *d_M0 = s.get<uint32_t>(m0_total, "batch root tables");
+        d_M0 = s.get<uint32_t>(m0_total, "batch root tables");
         {
             Scratch rs(c);
             uint32_t *wc = rs.get<uint32_t>(tw, "root word counts");
@@ -293,6 +315,10 @@ gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32
                    (const uint32_t *)d_rows, nwords, tw, (const uint64_t *)wo, d_M0);
             sync(c);  // host vectors copied above stay alive until here
         }
+    }
+    if (!fused.empty()) {
+        uint8_t *d_plans = s.get<uint8_t>(plan_blob.size(), "batch plans");
+        GSI_HIP(hipMemcpyAsync(d_plans, plan_blob.data(), plan_blob.size(), hipMemcpyHostToDevice, c->stream));
         if (!b->count_only && out_total) b->out = persist<uint32_t>(c, out_total, "batch rows");
         std::vector<FusedQuery> first, second;
         for (auto &f : fused) (f.R0 <= t1.cap_rows ? first : second).push_back(f);
@@ -311,16 +337,54 @@ gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32
         std::vector<FusedQuery> left2 = run_tier(g, b.get(), t2, 8, second, ks, d_plans, d_M0, s);
         b->info.tier2 = (uint32_t)(second.size() - left2.size());
         b->info.tier2_ms = ms_since(tb);
-        for (auto &f : left) per_level.push_back(f.qi);
-        for (auto &f : left2) per_level.push_back(f.qi);
+        for (auto &f : left) to_wide.push_back(f.qi);
+        for (auto &f : left2) to_wide.push_back(f.qi);
     }
+    for (auto &pl : planned)
+        if (levels_only || pl.R0 > t2.cap_rows) to_wide.push_back(pl.qi);
 
-    // the rest, one by one
-    auto tp = std::chrono::steady_clock::now();
-    std::sort(per_level.begin(), per_level.end());
-    for (uint32_t qi : per_level) {
+    // everything else: level-synchronous, all at once
+    auto tw0 = std::chrono::steady_clock::now();
+    if (!to_wide.empty()) {
+        std::sort(to_wide.begin(), to_wide.end());
+        std::vector<const Planned *> byq(nq, nullptr);
+        for (auto &pl : planned) byq[pl.qi] = &pl;
+        std::vector<WideQuery> wq;
+        wq.reserve(to_wide.size());
+        for (uint32_t qi : to_wide) {
+            const Planned &pl = *byq[qi];
+            const HostQuery &q = hq[qi];
+            WideQuery x;
+            x.ctx = c;
+            x.q = &q;
+            x.qi = qi;
+            x.order = pl.order;
+            x.e0src = pl.e0src;
+            x.col.assign(q.k, 0);
+            for (uint32_t j = 0; j < q.k; j++) x.col[pl.order[j]] = j;
+            x.Cu.assign(q.k, nullptr);
+            for (uint32_t j = 0; j < q.k; j++) x.Cu[j] = bits + (uint64_t)(qbase[pl.a] + pl.order[j]) * nwords;
+            x.M = d_M0 + pl.m0_off;
+            x.R = pl.R0;
+            wq.push_back(std::move(x));
+        }
+        wide_run(g, wq, b->count_only);
+        for (auto &x : wq) {
+            gsi_batch::Entry &en = b->e[x.qi];
+            en.count = x.count;
+            en.digest[0] = x.digest[0];
+            en.digest[1] = x.digest[1];
+            en.rows = x.take_rows();
+            en.where = en.rows && x.count ? 3 : 0;
+            b->info.per_level++;
+        }
+    }
+    b->info.per_level_ms = ms_since(tw0);
+
+    // one-vertex queries: the root table is the answer
+    for (uint32_t qi : single) {
         gsi_query_options o{};
-        o.flags = (b->count_only ? GSI_COUNT_ONLY : 0u) | GSI_NO_FUSED;
+        o.flags = b->count_only ? GSI_COUNT_ONLY : 0u;
         gsi_result *r = run_query(g, hq[qi], &o);
         gsi_batch::Entry &en = b->e[qi];
         en.res = r;
@@ -330,7 +394,6 @@ gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32
         en.where = (r->rows && r->count) ? 2 : 0;
         b->info.per_level++;
     }
-    b->info.per_level_ms = ms_since(tp);
     b->info.total_ms = ms_since(t0);
     return b.release();
 }
@@ -413,7 +476,7 @@ gsi_status gsi_batch_rows(const gsi_batch *b, uint32_t qi, uint32_t *dst, uint64
         if (!dst) fail(GSI_E_INVALID, "null buffer");
         gsi_ctx *c = b->ctx;
         GSI_HIP(hipSetDevice(c->device));
-        const uint32_t *src = e.where == 1 ? b->out + e.out_off : e.res->rows;
+        const uint32_t *src = e.where == 1 ? b->out + e.out_off : e.where == 2 ? e.res->rows : e.rows;
         GSI_HIP(hipMemcpyAsync(dst, src, e.count * e.k * 4, hipMemcpyDeviceToHost, c->stream));
         GSI_HIP(hipStreamSynchronize(c->stream));
     })

@@ -221,6 +221,8 @@ void run_filter_many(gsi_graph *g, const std::vector<const HostQuery *> &qs, con
                      uint64_t *d_bits, uint32_t *d_counts);
 void make_plan(const gsi_graph *g, const HostQuery &q, const std::vector<uint32_t> &cand,
                std::vector<uint32_t> &order, std::vector<uint32_t> &e0src);
+// tile_row[t] = row r with F[r] <= 256 t < F[r+1]; tile_row[ntiles] = R - 1
+void tile_rows(gsi_ctx *c, const uint64_t *F, uint64_t R, uint64_t ntiles, uint64_t *tile_row);
 gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options *opt);
 
 }  // namespace gsi

@@ -323,6 +323,10 @@ __global__ __launch_bounds__(QT) void k_tile_rows(const uint64_t *F, uint64_t R,
     if (i == R - 1) tile_row[ntiles] = R - 1;
 }
 
+void tile_rows(gsi_ctx *c, const uint64_t *F, uint64_t R, uint64_t ntiles, uint64_t *tile_row) {
+    launch(c, "k_tile_rows", 16.0 * R + 8.0 * ntiles, k_tile_rows, nblocks(R), QT, F, R, ntiles, tile_row);
+}
+
 // largest i in [lo, hi] with F[i] <= p (F non-decreasing, F[lo] <= p)
 __device__ __forceinline__ uint64_t row_of(const uint64_t *F, uint64_t lo, uint64_t hi, uint64_t p) {
     while (lo < hi) {

@@ -1,0 +1,445 @@
+// Level-synchronous joins of many queries at once.
+//
+// Every step advances each active query by one join level (Algorithm 3 with
+// Algorithm 4's pre-allocation), all queries sharing the same launches:
+//   rows      the tables of all active queries are one row space: query q
+//             owns global rows [rbase_q, rbase_q + R_q)
+//   k_wlocate one thread per global row: N(v, l) for every linking edge of
+//             the row's own query; bound = |N(v', l0)|
+//   scan      F over all rows -> one global slot space [0, |GBA|)
+//   k_wjoin   256-slot tiles over the global slots: the same tests as the
+//             single-query join, with each slot's query found from its row
+//   scan      survivor offsets; k_wsurv turns them into each query's first
+//             and last survivor, so every query's next table gets its exact
+//             size (host readback)
+//   k_wlink   (m_i, x) into the query's own next table, or, at a query's
+//             last level, its rows in query-vertex order plus each row's
+//             hash (digest summed per query by k_wdigest)
+// Slots of a query are contiguous and ordered by its rows, so each query's
+// result, row order included, equals the single-query path's.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+#include "join_device.h"
+#include "wide.h"
+
+namespace gsi {
+
+constexpr uint32_t WT = 256;
+
+struct WEdge {
+    const uint32_t *gl;
+    const uint32_t *ci;
+    uint32_t G, H, col, pad;
+};
+
+struct WQ {
+    const uint32_t *M;  // table, column c at M + c*R
+    uint64_t R, rbase, locbase;
+    const uint64_t *Cu;
+    uint32_t j, ne, e0, efirst, k, final_level;
+    uint32_t *Mn;   // next table (inner level)
+    uint32_t *out;  // result rows (last level)
+    uint64_t S, sbase;
+    uint32_t qcol[GSI_MAX_K];
+};
+
+static uint32_t wblocks(uint64_t n) {
+    uint64_t b = (n + WT - 1) / WT;
+    if (b == 0) b = 1;
+    if (b > 0x7FFFFFFFull) fail(GSI_E_CAPACITY, "grid too large");
+    return (uint32_t)b;
+}
+
+// largest q in [lo, hi] with qs[q].rbase <= r
+__device__ __forceinline__ uint32_t query_of(const WQ *qs, uint32_t lo, uint32_t hi, uint64_t r) {
+    while (lo < hi) {
+        uint32_t mid = (lo + hi + 1) >> 1;
+        if (qs[mid].rbase <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(WT) void k_wlocate(const WQ *qs, uint32_t nq, const WEdge *edges, uint64_t Rtot,
+                                               uint32_t *loc, uint32_t *bound) {
+    __shared__ uint32_t s_q[2];
+    const uint64_t r0 = (uint64_t)blockIdx.x * WT;
+    if (threadIdx.x == 0) {
+        const uint64_t rl = r0 + WT - 1 < Rtot ? r0 + WT - 1 : Rtot - 1;
+        s_q[0] = query_of(qs, 0, nq - 1, r0);
+        s_q[1] = query_of(qs, s_q[0], nq - 1, rl);
+    }
+    __syncthreads();
+    const uint64_t r = r0 + threadIdx.x;
+    if (r >= Rtot) return;
+    const WQ &Q = qs[query_of(qs, s_q[0], s_q[1], r)];
+    const uint64_t i = r - Q.rbase;
+    for (uint32_t e = 0; e < Q.ne; e++) {
+        const WEdge &ed = edges[Q.efirst + e];
+        const uint32_t v = Q.M[(uint64_t)ed.col * Q.R + i];
+        const uint2 f = pcsr_find(ed.gl, ed.G, ed.H, v);
+        loc[Q.locbase + (uint64_t)e * Q.R + i] = f.x;
+        loc[Q.locbase + (uint64_t)(Q.ne + e) * Q.R + i] = f.y;
+        if (e == Q.e0) bound[r] = f.y;
+    }
+}
+
+__global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, uint32_t nq, const WEdge *edges, const uint64_t *F,
+                                             const uint64_t *tile_row, uint64_t gba, const uint32_t *loc,
+                                             uint64_t *bitmap, uint32_t *tile_cnt) {
+    __shared__ uint64_t s_F[WT];
+    __shared__ uint32_t s_q[2];
+    __shared__ uint32_t s_cnt[WT / 64];
+    const uint64_t tile = blockIdx.x, p0 = tile * WT;
+    const uint64_t r_lo = tile_row[tile], r_hi = tile_row[tile + 1];
+    const uint64_t nr = r_hi - r_lo + 1;
+    const bool staged = nr <= WT;
+    if (staged && threadIdx.x < nr) s_F[threadIdx.x] = F[r_lo + threadIdx.x];
+    if (threadIdx.x == 0) {
+        s_q[0] = query_of(qs, 0, nq - 1, r_lo);
+        s_q[1] = query_of(qs, s_q[0], nq - 1, r_hi);
+    }
+    __syncthreads();
+    const uint64_t p = p0 + threadIdx.x;
+    bool keep = false;
+    if (p < gba) {
+        uint64_t r, Fr;
+        if (staged) {
+            uint32_t lo = 0, hi = (uint32_t)(nr - 1);
+            while (lo < hi) {
+                uint32_t mid = (lo + hi + 1) >> 1;
+                if (s_F[mid] <= p) lo = mid;
+                else hi = mid - 1;
+            }
+            r = r_lo + lo;
+            Fr = s_F[lo];
+        } else {
+            uint64_t lo = r_lo, hi = r_hi;
+            while (lo < hi) {
+                uint64_t mid = lo + (hi - lo + 1) / 2;
+                if (F[mid] <= p) lo = mid;
+                else hi = mid - 1;
+            }
+            r = lo;
+            Fr = F[r];
+        }
+        const WQ &Q = qs[query_of(qs, s_q[0], s_q[1], r)];
+        const uint64_t i = r - Q.rbase;
+        const WEdge &E0 = edges[Q.efirst + Q.e0];
+        const uint32_t x = E0.ci[loc[Q.locbase + (uint64_t)Q.e0 * Q.R + i] + (uint32_t)(p - Fr)];
+        keep = (Q.Cu[x >> 6] >> (x & 63)) & 1ull;
+        for (uint32_t c = 0; keep && c < Q.j; c++) keep = Q.M[(uint64_t)c * Q.R + i] != x;
+        for (uint32_t e = 0; keep && e < Q.ne; e++) {
+            if (e == Q.e0) continue;
+            keep = in_sorted(edges[Q.efirst + e].ci + loc[Q.locbase + (uint64_t)e * Q.R + i],
+                             loc[Q.locbase + (uint64_t)(Q.ne + e) * Q.R + i], x);
+        }
+    }
+    const uint64_t mask = __ballot(keep);
+    const uint32_t w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        bitmap[tile * (WT / 64) + w] = mask;
+        s_cnt[w] = (uint32_t)__popcll(mask);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int q = 0; q < WT / 64; q++) t += s_cnt[q];
+        tile_cnt[tile] = t;
+    }
+}
+
+// survivors before slot p
+__device__ __forceinline__ uint64_t survivors_before(const uint64_t *bitmap, const uint64_t *tile_off, uint64_t gba,
+                                                     uint64_t p) {
+    const uint64_t ntiles = (gba + WT - 1) / WT;
+    if (p >= gba) return tile_off[ntiles];
+    const uint64_t t = p / WT;
+    const uint32_t within = (uint32_t)(p - t * WT);
+    uint64_t r = tile_off[t];
+    for (uint32_t w = 0; w < within / 64; w++) r += (uint64_t)__popcll(bitmap[t * (WT / 64) + w]);
+    const uint32_t b = within % 64;
+    if (b) r += (uint64_t)__popcll(bitmap[t * (WT / 64) + within / 64] & ((1ull << b) - 1));
+    return r;
+}
+
+// per query: first survivor, end of its survivors, first slot, end of slots
+__global__ __launch_bounds__(WT) void k_wsurv(const WQ *qs, uint32_t nq, const uint64_t *F, const uint64_t *bitmap,
+                                             const uint64_t *tile_off, uint64_t gba, uint64_t *sb) {
+    const uint32_t q = blockIdx.x * WT + threadIdx.x;
+    if (q >= nq) return;
+    const WQ &Q = qs[q];
+    const uint64_t f0 = F[Q.rbase], f1 = F[Q.rbase + Q.R];
+    sb[4 * (uint64_t)q] = survivors_before(bitmap, tile_off, gba, f0);
+    sb[4 * (uint64_t)q + 1] = survivors_before(bitmap, tile_off, gba, f1);
+    sb[4 * (uint64_t)q + 2] = f0;
+    sb[4 * (uint64_t)q + 3] = f1;
+}
+
+__global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, uint32_t nq, const WEdge *edges, const uint64_t *F,
+                                             const uint64_t *tile_row, const uint32_t *loc, const uint64_t *bitmap,
+                                             const uint64_t *tile_off, uint64_t *hv) {
+    __shared__ uint64_t s_F[WT];
+    __shared__ uint32_t s_q[2];
+    const uint64_t tile = blockIdx.x;
+    if (tile_off[tile + 1] == tile_off[tile]) return;  // no survivor in the tile (uniform)
+    const uint64_t p0 = tile * WT;
+    const uint64_t r_lo = tile_row[tile], r_hi = tile_row[tile + 1];
+    const uint64_t nr = r_hi - r_lo + 1;
+    const bool staged = nr <= WT;
+    if (staged && threadIdx.x < nr) s_F[threadIdx.x] = F[r_lo + threadIdx.x];
+    if (threadIdx.x == 0) {
+        s_q[0] = query_of(qs, 0, nq - 1, r_lo);
+        s_q[1] = query_of(qs, s_q[0], nq - 1, r_hi);
+    }
+    __syncthreads();
+    const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+    const uint64_t *words = bitmap + tile * (WT / 64);
+    const uint64_t word = words[w];
+    if (!((word >> lane) & 1ull)) return;
+    uint64_t before = 0;
+    for (uint32_t q = 0; q < w; q++) before += (uint64_t)__popcll(words[q]);
+    const uint64_t gpos = tile_off[tile] + before + rank_below(word);
+    const uint64_t p = p0 + threadIdx.x;
+    uint64_t r, Fr;
+    if (staged) {
+        uint32_t lo = 0, hi = (uint32_t)(nr - 1);
+        while (lo < hi) {
+            uint32_t mid = (lo + hi + 1) >> 1;
+            if (s_F[mid] <= p) lo = mid;
+            else hi = mid - 1;
+        }
+        r = r_lo + lo;
+        Fr = s_F[lo];
+    } else {
+        uint64_t lo = r_lo, hi = r_hi;
+        while (lo < hi) {
+            uint64_t mid = lo + (hi - lo + 1) / 2;
+            if (F[mid] <= p) lo = mid;
+            else hi = mid - 1;
+        }
+        r = lo;
+        Fr = F[r];
+    }
+    const WQ &Q = qs[query_of(qs, s_q[0], s_q[1], r)];
+    const uint64_t i = r - Q.rbase;
+    const uint64_t pos = gpos - Q.sbase;
+    if (pos >= Q.S) return;  // never taken when the survivor ranges are consistent
+    const WEdge &E0 = edges[Q.efirst + Q.e0];
+    const uint32_t x = E0.ci[loc[Q.locbase + (uint64_t)Q.e0 * Q.R + i] + (uint32_t)(p - Fr)];
+    if (!Q.final_level) {
+        for (uint32_t c = 0; c < Q.j; c++) Q.Mn[(uint64_t)c * Q.S + pos] = Q.M[(uint64_t)c * Q.R + i];
+        Q.Mn[(uint64_t)Q.j * Q.S + pos] = x;
+    } else {
+        uint64_t f = 14695981039346656037ull;
+        for (uint32_t u = 0; u < Q.k; u++) {
+            const uint32_t c = Q.qcol[u];
+            const uint32_t val = c < Q.j ? Q.M[(uint64_t)c * Q.R + i] : x;
+            if (Q.out) Q.out[pos * Q.k + u] = val;
+            f = fnv_word(f, val);
+        }
+        hv[gpos] = mix64(f);
+    }
+}
+
+// (sum, xor) of hv[a, b) per item, one workgroup per item
+__global__ __launch_bounds__(WT) void k_wdigest(const uint64_t *items, const uint64_t *hv, uint64_t *part) {
+    __shared__ uint64_t s_s[WT / 64], s_x[WT / 64];
+    const uint64_t a = items[2 * (uint64_t)blockIdx.x], b = items[2 * (uint64_t)blockIdx.x + 1];
+    uint64_t sm = 0, xr = 0;
+    for (uint64_t t = a + threadIdx.x; t < b; t += WT) {
+        const uint64_t h = hv[t];
+        sm += h;
+        xr ^= h;
+    }
+    sm = wave_sum(sm);
+    xr = wave_xor(xr);
+    if (lane_id() == 0) {
+        s_s[threadIdx.x >> 6] = sm;
+        s_x[threadIdx.x >> 6] = xr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t ts = 0, tx = 0;
+        for (int q = 0; q < WT / 64; q++) {
+            ts += s_s[q];
+            tx ^= s_x[q];
+        }
+        part[2 * (uint64_t)blockIdx.x] = ts;
+        part[2 * (uint64_t)blockIdx.x + 1] = tx;
+    }
+}
+
+void wide_run(gsi_graph *g, std::vector<WideQuery> &wq, bool count_only) {
+    gsi_ctx *c = g->ctx;
+    constexpr uint64_t DIGEST_ITEM = 1u << 16;
+    for (;;) {
+        std::vector<WideQuery *> act;
+        for (auto &x : wq)
+            if (!x.done) act.push_back(&x);
+        if (act.empty()) break;
+        const uint32_t nq = (uint32_t)act.size();
+        Scratch s(c);
+        std::vector<WQ> hq(nq);
+        std::vector<WEdge> he;
+        uint64_t Rtot = 0, loctot = 0;
+        for (uint32_t a = 0; a < nq; a++) {
+            WideQuery &x = *act[a];
+            const HostQuery &q = *x.q;
+            const uint32_t j = x.j, u = x.order[j];
+            WQ &Q = hq[a];
+            memset(&Q, 0, sizeof(Q));
+            Q.M = x.M;
+            Q.R = x.R;
+            Q.rbase = Rtot;
+            Q.Cu = x.Cu[j];
+            Q.j = j;
+            Q.k = q.k;
+            Q.final_level = j == q.k - 1;
+            Q.efirst = (uint32_t)he.size();
+            for (uint32_t i = 0; i < j; i++)
+                for (auto &p : q.adj[u])
+                    if (p.first == x.order[i]) {
+                        const uint32_t l = p.second;
+                        WEdge ed;
+                        ed.gl = g->gl + g->group_base[l] * GROUP_WORDS;
+                        ed.ci = g->ci + g->ci_base[l];
+                        ed.G = g->G[l];
+                        ed.H = g->H[l];
+                        ed.col = i;
+                        ed.pad = 0;
+                        if (x.order[i] == x.e0src[j]) Q.e0 = Q.ne;
+                        he.push_back(ed);
+                        Q.ne++;
+                    }
+            Q.locbase = loctot;
+            for (uint32_t v = 0; v < q.k; v++) Q.qcol[v] = x.col[v];
+            x.stats_rows[j] = x.R;
+            Rtot += x.R;
+            loctot += 2ull * Q.ne * x.R;
+        }
+        WQ *d_q = s.get<WQ>(nq, "wide queries");
+        WEdge *d_e = s.get<WEdge>(he.size(), "wide edges");
+        uint32_t *loc = s.get<uint32_t>(loctot, "wide lookups");
+        uint32_t *bound = s.get<uint32_t>(Rtot, "wide bounds");
+        uint64_t *F = s.get<uint64_t>(Rtot + 1, "wide offsets F");
+        uint64_t *scal = s.get<uint64_t>(2, "wide scalars");
+        GSI_HIP(hipMemcpyAsync(d_q, hq.data(), sizeof(WQ) * nq, hipMemcpyHostToDevice, c->stream));
+        GSI_HIP(hipMemcpyAsync(d_e, he.data(), sizeof(WEdge) * he.size(), hipMemcpyHostToDevice, c->stream));
+        double lb = 0;
+        for (auto &Q : hq) lb += (double)Q.R * (4.0 * Q.ne + 128.0 * Q.ne + 8.0 * Q.ne + 4.0);
+        launch(c, "k_wlocate", lb, k_wlocate, wblocks(Rtot), WT, (const WQ *)d_q, nq, (const WEdge *)d_e, Rtot, loc,
+               bound);
+        exclusive_scan(c, bound, Rtot, F, s, scal);
+        uint64_t gba;
+        read_scalars(c, scal, &gba, 1);  // also orders the uploads above before `hq`/`he` change
+        if (gba == 0) {
+            for (auto *x : act) {
+                x->stats_gba[x->j] = 0;
+                x->levels = x->j;
+                x->finish_empty();
+            }
+            continue;
+        }
+        const uint64_t ntiles = (gba + WT - 1) / WT;
+        uint64_t *trow = s.get<uint64_t>(ntiles + 1, "wide tile rows");
+        uint64_t *bitmap = s.get<uint64_t>(ntiles * (WT / 64), "wide GBA bitmap");
+        uint32_t *tcnt = s.get<uint32_t>(ntiles, "wide tile counts");
+        uint64_t *toff = s.get<uint64_t>(ntiles + 1, "wide tile offsets");
+        uint64_t *sb = s.get<uint64_t>(4ull * nq, "wide survivor ranges");
+        tile_rows(c, F, Rtot, ntiles, trow);
+        double jb = 4.0 * gba + gba / 8.0 + 4.0 * ntiles;
+        for (auto &Q : hq) jb += (double)Q.R * (8.0 + 8.0 * Q.ne + 4.0 * Q.j);
+        launch(c, "k_wjoin", jb, k_wjoin, (uint32_t)ntiles, WT, (const WQ *)d_q, nq, (const WEdge *)d_e,
+               (const uint64_t *)F, (const uint64_t *)trow, gba, (const uint32_t *)loc, bitmap, tcnt);
+        exclusive_scan(c, tcnt, ntiles, toff, s, scal + 1);
+        launch(c, "k_wsurv", 48.0 * nq, k_wsurv, wblocks(nq), WT, (const WQ *)d_q, nq, (const uint64_t *)F,
+               (const uint64_t *)bitmap, (const uint64_t *)toff, gba, sb);
+        std::vector<uint64_t> hsb(4ull * nq);
+        GSI_HIP(hipMemcpyAsync(hsb.data(), sb, 32ull * nq, hipMemcpyDeviceToHost, c->stream));
+        uint64_t Stot;
+        read_scalars(c, scal + 1, &Stot, 1);
+        // next tables (exact sizes) and result rows
+        bool any_final = false;
+        std::vector<uint64_t> items;
+        std::vector<uint32_t> item_q;
+        double kb = gba / 8.0 + 8.0 * ntiles;
+        for (uint32_t a = 0; a < nq; a++) {
+            WideQuery &x = *act[a];
+            WQ &Q = hq[a];
+            Q.sbase = hsb[4 * a];
+            Q.S = hsb[4 * a + 1] - hsb[4 * a];
+            x.stats_gba[x.j] = hsb[4 * a + 3] - hsb[4 * a + 2];
+            x.stats_surv[x.j] = Q.S;
+            if (Q.S == 0) continue;
+            kb += (double)Q.S * (4.0 + 4.0 * Q.j);
+            if (Q.final_level) {
+                any_final = true;
+                if (!count_only) {
+                    Q.out = persist<uint32_t>(c, Q.S * Q.k, "result rows");
+                    x.rows = Q.out;
+                    kb += 4.0 * Q.k * Q.S;
+                }
+                for (uint64_t t = Q.sbase; t < Q.sbase + Q.S; t += DIGEST_ITEM) {
+                    items.push_back(t);
+                    items.push_back(std::min(t + DIGEST_ITEM, Q.sbase + Q.S));
+                    item_q.push_back(a);
+                }
+            } else {
+                x.next = c->arena.alloc(4ull * (Q.j + 1) * Q.S, false);
+                if (!x.next)
+                    fail(GSI_E_NOMEM, "arena exhausted allocating %llu bytes for a next table",
+                         (unsigned long long)(4ull * (Q.j + 1) * Q.S));
+                Q.Mn = static_cast<uint32_t *>(x.next);
+                kb += 4.0 * (Q.j + 1) * Q.S;
+            }
+        }
+        uint64_t *hv = any_final ? s.get<uint64_t>(Stot, "wide row hashes") : nullptr;
+        GSI_HIP(hipMemcpyAsync(d_q, hq.data(), sizeof(WQ) * nq, hipMemcpyHostToDevice, c->stream));
+        launch(c, "k_wlink", kb, k_wlink, (uint32_t)ntiles, WT, (const WQ *)d_q, nq, (const WEdge *)d_e,
+               (const uint64_t *)F, (const uint64_t *)trow, (const uint32_t *)loc, (const uint64_t *)bitmap,
+               (const uint64_t *)toff, hv);
+        std::vector<uint64_t> part;
+        if (any_final) {
+            const uint64_t ni = item_q.size();
+            uint64_t *d_items = s.get<uint64_t>(2 * ni, "digest items");
+            uint64_t *d_part = s.get<uint64_t>(2 * ni, "digest partials");
+            GSI_HIP(hipMemcpyAsync(d_items, items.data(), 16 * ni, hipMemcpyHostToDevice, c->stream));
+            launch(c, "k_wdigest", 8.0 * Stot, k_wdigest, (uint32_t)ni, WT, (const uint64_t *)d_items,
+                   (const uint64_t *)hv, d_part);
+            part.resize(2 * ni);
+            GSI_HIP(hipMemcpyAsync(part.data(), d_part, 16 * ni, hipMemcpyDeviceToHost, c->stream));
+        }
+        sync(c);  // uploads done, partials read
+        for (size_t t = 0; t < item_q.size(); t++) {
+            WideQuery &x = *act[item_q[t]];
+            x.digest[0] += part[2 * t];
+            x.digest[1] ^= part[2 * t + 1];
+        }
+        for (uint32_t a = 0; a < nq; a++) {
+            WideQuery &x = *act[a];
+            const WQ &Q = hq[a];
+            if (Q.S == 0) {
+                x.levels = x.j;
+                x.finish_empty();
+            } else if (Q.final_level) {
+                x.count = Q.S;
+                x.levels = x.j;
+                x.release_table();
+                x.done = true;
+            } else {
+                x.release_table();
+                x.own = x.next;
+                x.next = nullptr;
+                x.M = Q.Mn;
+                x.R = Q.S;
+                x.j++;
+            }
+        }
+    }
+}
+
+}  // namespace gsi

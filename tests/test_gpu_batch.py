@@ -39,13 +39,14 @@ def _small_set(seed, nq):
     return g, qs, want
 
 
-@pytest.mark.parametrize("threads,grid_scale", [(64, 8), (256, 8), (1024, 8), (64, 1), (256, 4)])
-def test_batch_matches_oracle(ctx, threads, grid_scale):
+@pytest.mark.parametrize("threads,grid_scale,flags", [(64, 8, 0), (256, 8, 0), (1024, 8, 0), (64, 1, 0), (256, 4, 0),
+                                                     (256, 8, 8)])
+def test_batch_matches_oracle(ctx, threads, grid_scale, flags):
     for seed in (3, 4):
         g, qs, want = _small_set(seed, 60)
         dg = ctx.load(g)
-        print("batch seed", seed, "threads", threads, flush=True)
-        b = dg.batch(qs, threads=threads, grid_scale=grid_scale)
+        print("batch seed", seed, "threads", threads, "flags", flags, flush=True)
+        b = dg.batch(qs, flags=flags, threads=threads, grid_scale=grid_scale)
         info = b.info()
         assert info["queries"] == len(qs)
         assert info["empty"] + info["tier1"] + info["tier2"] + info["per_level"] == len(qs)
@@ -94,6 +95,12 @@ def test_batch_ba1m_mixed_full(golden_dir):
     as_t = lambda a: torch.from_numpy(a.view(np.int32)).to(dev)
     with gsi.Context(64 << 30) as ctx:
         dg = ctx.load_device(g.n, as_t(g.vlabel), as_t(g.src), as_t(g.dst), as_t(g.elabel))
+        lv = dg.batch(qs, flags=gsi.GSI_BATCH_LEVELS_ONLY | gsi.GSI_COUNT_ONLY)
+        print("levels-only batch info", lv.info(), flush=True)
+        for i, x in enumerate(gold["queries"]):
+            assert lv.count(i) == x["count"], i
+            assert [str(v) for v in lv.digest(i)] == x["digest"], i
+        lv.free()
         b = dg.batch(qs)
         print("batch info", b.info(), flush=True)
         for i, x in enumerate(gold["queries"]):

@@ -3,11 +3,11 @@
 //   filter   one pass of the signature filter per 32 query vertices of the
 //            whole batch (query vertices grouped by label), one readback
 //   plan     Algorithm 2 per query on the host
-//   roots    every fused query's C(u_first) compacted in one pass
+//   roots    every query's C(u_first) compacted in one pass
 //   tier 1   persistent fused launch, workgroups of the scheduled size pull
 //            queries from a shared counter and run all levels per query
 //   tier 2   what tier 1 could not hold, in 1024-thread workgroups
-//   rest     one by one with the per-level kernels (run_query)
+//   rest     the level-synchronous engine (wide.hip), all at once
 //
 // The schedule (tier-1 workgroup size, launched occupancy) is chosen by the
 // autotuner, which times every candidate on a sample of the batch.
@@ -16,6 +16,7 @@
 #include <cstring>
 #include <memory>
 
+#include "admit.h"
 #include "fused.h"
 #include "gsi_internal.h"
 #include "wide.h"
@@ -24,28 +25,8 @@ struct gsi_batch {
     gsi_ctx *ctx = nullptr;
     uint32_t nq = 0;
     bool count_only = false;
-    struct Entry {
-        uint32_t k = 0;
-        uint64_t count = 0;
-        uint64_t digest[2] = {0, 0};
-        uint8_t where = 0;  // 0: no rows, 1: fused output buffer, 2: own result, 3: own rows block
-        uint64_t out_off = 0;
-        gsi_result *res = nullptr;
-        uint32_t *rows = nullptr;  // where == 3
-    };
-    std::vector<Entry> e;
-    uint32_t *out = nullptr;
+    std::unique_ptr<gsi::Slot[]> slots;
     gsi_batch_info info{};
-    ~gsi_batch() {
-        for (auto &x : e) {
-            if (x.res) {
-                ctx->arena.release(x.res->rows);
-                delete x.res;
-            }
-            if (x.rows) ctx->arena.release(x.rows);
-        }
-        if (out) ctx->arena.release(out);
-    }
 };
 
 namespace gsi {
@@ -102,9 +83,11 @@ struct FusedQuery {
 
 // Runs one fused tier over `list`; fills entries of finished queries and
 // returns the ones it could not hold.
-static std::vector<FusedQuery> run_tier(gsi_graph *g, gsi_batch *b, const FTier &t, uint32_t grid_scale,
-                                        const std::vector<FusedQuery> &list, const std::vector<uint32_t> &ks,
-                                        const uint8_t *d_plans, const uint32_t *d_M0, Scratch &s) {
+static std::vector<FusedQuery> run_tier(gsi_graph *g, const std::shared_ptr<Round> &rd,
+                                        const std::vector<Slot *> &slots, bool count_only, const FTier &t,
+                                        uint32_t grid_scale, const std::vector<FusedQuery> &list,
+                                        const std::vector<uint32_t> &ks, const uint8_t *d_plans,
+                                        const uint32_t *d_M0) {
     gsi_ctx *c = g->ctx;
     std::vector<FusedQuery> left;
     if (list.empty()) return left;
@@ -129,19 +112,22 @@ static std::vector<FusedQuery> run_tier(gsi_graph *g, gsi_batch *b, const FTier 
     GSI_HIP(hipMemcpyAsync(d_items, items.data(), sizeof(FBatchItem) * n, hipMemcpyHostToDevice, c->stream));
     fill_u64(c, reinterpret_cast<uint64_t *>(d_st), 0, (uint64_t)n * sizeof(FStatus) / 8);
     fill_u32(c, counter, 0, 1);
-    launch_fused_batch(c, t, grid, d_plans, d_items, n, d_M0, scratch, slot_words, kmax, b->count_only ? nullptr : b->out,
+    launch_fused_batch(c, t, grid, d_plans, d_items, n, d_M0, scratch, slot_words, kmax, count_only ? nullptr : rd->out,
                        d_st, counter, 0.0);
     std::vector<FStatus> hs(n);
     GSI_HIP(hipMemcpyAsync(hs.data(), d_st, sizeof(FStatus) * n, hipMemcpyDeviceToHost, c->stream));
     sync(c);  // also keeps `items` alive until its copy has run
     for (uint32_t i = 0; i < n; i++) {
-        gsi_batch::Entry &en = b->e[list[i].qi];
+        Slot &sl = *slots[list[i].qi];
         if (hs[i].done) {
-            en.count = hs[i].count;
-            en.digest[0] = hs[i].digest[0];
-            en.digest[1] = hs[i].digest[1];
-            en.where = (!b->count_only && hs[i].count) ? 1 : 0;
-            en.out_off = list[i].out_off;
+            sl.done = true;
+            sl.count = hs[i].count;
+            sl.digest[0] = hs[i].digest[0];
+            sl.digest[1] = hs[i].digest[1];
+            if (!count_only && hs[i].count) {
+                sl.rows = rd->out + list[i].out_off;
+                sl.keep = rd;
+            }
         } else {
             left.push_back(list[i]);
         }
@@ -149,82 +135,90 @@ static std::vector<FusedQuery> run_tier(gsi_graph *g, gsi_batch *b, const FTier 
     return left;
 }
 
-gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32_t flags,
-                     gsi_batch_schedule sched) {
-    gsi_ctx *c = g->ctx;
-    auto t0 = std::chrono::steady_clock::now();
-    if (flags & ~(GSI_COUNT_ONLY | GSI_BATCH_LEVELS_ONLY)) fail(GSI_E_INVALID, "unknown batch flag");
-    const bool levels_only = (flags & GSI_BATCH_LEVELS_ONLY) != 0;
-    if (sched.threads != 64 && sched.threads != 256 && sched.threads != 1024)
-        fail(GSI_E_INVALID, "schedule threads must be 64, 256 or 1024");
-    if (sched.grid_scale < 1 || sched.grid_scale > 8) fail(GSI_E_INVALID, "schedule grid_scale must be 1..8");
-    std::vector<HostQuery> hq(nq);
-    for (uint32_t i = 0; i < nq; i++) {
-        try {
-            hq[i] = validate_query(qd[i].k, qd[i].vertex_labels, qd[i].n_edges, qd[i].src, qd[i].dst,
-                                   qd[i].edge_labels);
-        } catch (const Fail &f) {
-            std::string m = std::string("query ") + std::to_string(i) + ": " + gsi_last_error();
-            fail(f.st, "%s", m.c_str());
-        }
-    }
-    std::unique_ptr<gsi_batch> b(new gsi_batch());
-    b->ctx = c;
-    b->nq = nq;
-    b->count_only = (flags & GSI_COUNT_ONLY) != 0;
-    b->e.resize(nq);
-    b->info.queries = nq;
-    b->info.schedule = sched;
-    for (uint32_t i = 0; i < nq; i++) b->e[i].k = hq[i].k;
 
+static void *round_block(gsi_ctx *c, uint64_t bytes, const char *what) {
+    void *p = c->arena.alloc(bytes ? bytes : 256, false);
+    if (!p)
+        fail(GSI_E_NOMEM, "arena exhausted allocating %llu bytes for %s (largest free block %llu)",
+             (unsigned long long)bytes, what, (unsigned long long)c->arena.largest_free());
+    return p;
+}
+
+void finish_slot(WideQuery &x, Slot &sl) {
+    sl.done = true;
+    sl.count = x.count;
+    sl.digest[0] = x.digest[0];
+    sl.digest[1] = x.digest[1];
+    sl.own = x.take_rows();
+    sl.rows = sl.own;
+}
+
+std::vector<WideQuery> admit_round(gsi_graph *g, const std::vector<const HostQuery *> &hq,
+                                   const std::vector<Slot *> &slots, const std::vector<uint64_t> &tags,
+                                   bool count_only, bool levels_only, gsi_batch_schedule sched, AdmitStats *st) {
+    gsi_ctx *c = g->ctx;
+    const uint32_t nq = (uint32_t)hq.size();
+    std::vector<WideQuery> wide;
+    auto rd = std::make_shared<Round>();
+    rd->ctx = c;
+    for (uint32_t i = 0; i < nq; i++) {
+        slots[i]->ctx = c;
+        slots[i]->k = hq[i]->k;
+    }
     // queries whose edge labels G lacks have no match
     std::vector<uint32_t> active;
     for (uint32_t i = 0; i < nq; i++) {
         bool ok = true;
-        for (uint32_t l : hq[i].el) ok &= l < g->nlab && g->edges[l] > 0;
-        if (ok) active.push_back(i);
-        else b->info.empty++;
+        for (uint32_t l : hq[i]->el) ok &= l < g->nlab && g->edges[l] > 0;
+        if (ok) {
+            active.push_back(i);
+        } else {
+            slots[i]->done = true;
+            st->empty++;
+        }
     }
-    Scratch s(c);
+    if (active.empty()) return wide;
     const uint64_t nwords = ((uint64_t)g->n + 63) / 64;
     std::vector<const HostQuery *> aq;
     std::vector<uint32_t> qbase{0};
     for (uint32_t i : active) {
-        aq.push_back(&hq[i]);
-        qbase.push_back(qbase.back() + hq[i].k);
+        aq.push_back(hq[i]);
+        qbase.push_back(qbase.back() + hq[i]->k);
     }
     const uint64_t nqv = qbase.back();
     auto tf = std::chrono::steady_clock::now();
-    uint64_t *bits = s.get<uint64_t>(std::max<uint64_t>(1, nqv) * nwords, "batch candidate bitsets");
-    uint32_t *dcnt = s.get<uint32_t>(std::max<uint64_t>(1, nqv), "batch candidate counts");
+    rd->bits = round_block(c, nqv * nwords * 8, "candidate bitsets");
+    uint64_t *bits = static_cast<uint64_t *>(rd->bits);
     std::vector<uint32_t> cnt(nqv);
-    if (nqv) {
+    {
+        Scratch fs(c);
+        uint32_t *dcnt = fs.get<uint32_t>(nqv, "candidate counts");
         run_filter_many(g, aq, qbase, bits, dcnt);
         GSI_HIP(hipMemcpyAsync(cnt.data(), dcnt, 4 * nqv, hipMemcpyDeviceToHost, c->stream));
         sync(c);
     }
-    b->info.filter_ms = ms_since(tf);
+    st->filter_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tf).count();
 
-    // plans, tiers
     const FTier t1 = fused_tier(sched.threads), t2 = fused_tier(TIER2_THREADS);
     std::vector<uint32_t> ks(nq);
-    for (uint32_t i = 0; i < nq; i++) ks[i] = hq[i].k;
+    for (uint32_t i = 0; i < nq; i++) ks[i] = hq[i]->k;
     struct Planned {
-        uint32_t qi, a;   // batch index, index among active queries
+        uint32_t qi, a;
         std::vector<uint32_t> order, e0src;
         uint32_t R0;
         uint64_t m0_off;
     };
-    std::vector<Planned> planned;          // multi-vertex queries with candidates
-    std::vector<uint32_t> single;          // one-vertex queries
+    std::vector<Planned> planned;
+    std::vector<uint32_t> single;
     for (size_t a = 0; a < active.size(); a++) {
         const uint32_t qi = active[a];
-        const HostQuery &q = hq[qi];
+        const HostQuery &q = *hq[qi];
         std::vector<uint32_t> cand(cnt.begin() + qbase[a], cnt.begin() + qbase[a] + q.k);
         bool empty = false;
         for (uint32_t x : cand) empty |= x == 0;
         if (empty) {
-            b->info.empty++;
+            slots[qi]->done = true;
+            st->empty++;
             continue;
         }
         if (q.k < 2) {
@@ -240,12 +234,12 @@ gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32
         planned.push_back(std::move(pl));
     }
 
-    std::vector<FusedQuery> fused;         // tier candidates
+    std::vector<FusedQuery> fused;
     std::vector<uint8_t> plan_blob;
-    std::vector<uint32_t> root_rows;       // bitset row of each planned query's root
+    std::vector<uint32_t> root_rows;
     uint64_t m0_total = 0, out_total = 0;
     for (auto &pl : planned) {
-        const HostQuery &q = hq[pl.qi];
+        const HostQuery &q = *hq[pl.qi];
         pl.m0_off = m0_total;
         m0_total += pl.R0;
         root_rows.push_back(qbase[pl.a] + pl.order[0]);
@@ -259,7 +253,7 @@ gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32
         plan_blob.resize(off + pb, 0);
         FPlan *hp = reinterpret_cast<FPlan *>(plan_blob.data() + off);
         hp->k = q.k;
-        hp->count_only = b->count_only ? 1u : 0u;
+        hp->count_only = count_only ? 1u : 0u;
         hp->cap_rows = 0xFFFFFFFFu;  // the tier's own capacities apply
         hp->cap_slots = 0xFFFFFFFFu;
         std::vector<uint32_t> col(q.k);
@@ -292,40 +286,39 @@ gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32
         f.plan_off = off;
         f.m0_off = pl.m0_off;
         f.out_off = out_total;
-        out_total += b->count_only ? 0 : (uint64_t)t2.cap_slots * q.k;
+        out_total += count_only ? 0 : (uint64_t)t2.cap_slots * q.k;
         fused.push_back(f);
     }
 
-    std::vector<uint32_t> to_wide;  // batch indices
+    std::vector<uint32_t> to_wide;
     uint32_t *d_M0 = nullptr;
     if (!planned.empty()) {
-        uint32_t *d_rows = s.get<uint32_t>(root_rows.size(), "batch root rows");
+        Scratch rs(c);
+        uint32_t *d_rows = rs.get<uint32_t>(root_rows.size(), "root rows");
         GSI_HIP(hipMemcpyAsync(d_rows, root_rows.data(), 4 * root_rows.size(), hipMemcpyHostToDevice, c->stream));
-        // all root tables in one pass
         const uint64_t tw = (uint64_t)root_rows.size() * nwords;
-        d_M0 = s.get<uint32_t>(m0_total, "batch root tables");
-        {
-            Scratch rs(c);
-            uint32_t *wc = rs.get<uint32_t>(tw, "root word counts");
-            uint64_t *wo = rs.get<uint64_t>(tw + 1, "root word offsets");
-            launch(c, "k_roots_popc", 12.0 * tw, k_roots_popc, bgrid(tw), BQT, (const uint64_t *)bits,
-                   (const uint32_t *)d_rows, nwords, tw, wc);
-            exclusive_scan(c, wc, tw, wo, rs);
-            launch(c, "k_roots_emit", 16.0 * tw + 4.0 * m0_total, k_roots_emit, bgrid(tw), BQT, (const uint64_t *)bits,
-                   (const uint32_t *)d_rows, nwords, tw, (const uint64_t *)wo, d_M0);
-            sync(c);  // host vectors copied above stay alive until here
-        }
+        rd->m0 = round_block(c, m0_total * 4, "root tables");
+        d_M0 = static_cast<uint32_t *>(rd->m0);
+        uint32_t *wc = rs.get<uint32_t>(tw, "root word counts");
+        uint64_t *wo = rs.get<uint64_t>(tw + 1, "root word offsets");
+        launch(c, "k_roots_popc", 12.0 * tw, k_roots_popc, bgrid(tw), BQT, (const uint64_t *)bits,
+               (const uint32_t *)d_rows, nwords, tw, wc);
+        exclusive_scan(c, wc, tw, wo, rs);
+        launch(c, "k_roots_emit", 16.0 * tw + 4.0 * m0_total, k_roots_emit, bgrid(tw), BQT, (const uint64_t *)bits,
+               (const uint32_t *)d_rows, nwords, tw, (const uint64_t *)wo, d_M0);
+        sync(c);  // host vectors copied above stay alive until here
     }
     if (!fused.empty()) {
-        uint8_t *d_plans = s.get<uint8_t>(plan_blob.size(), "batch plans");
+        Scratch ps(c);
+        uint8_t *d_plans = ps.get<uint8_t>(plan_blob.size(), "fused plans");
         GSI_HIP(hipMemcpyAsync(d_plans, plan_blob.data(), plan_blob.size(), hipMemcpyHostToDevice, c->stream));
-        if (!b->count_only && out_total) b->out = persist<uint32_t>(c, out_total, "batch rows");
+        if (!count_only && out_total) rd->out = static_cast<uint32_t *>(round_block(c, out_total * 4, "fused rows"));
         std::vector<FusedQuery> first, second;
         for (auto &f : fused) (f.R0 <= t1.cap_rows ? first : second).push_back(f);
         auto ta = std::chrono::steady_clock::now();
-        std::vector<FusedQuery> left = run_tier(g, b.get(), t1, sched.grid_scale, first, ks, d_plans, d_M0, s);
-        b->info.tier1 = (uint32_t)(first.size() - left.size());
-        b->info.tier1_ms = ms_since(ta);
+        std::vector<FusedQuery> left = run_tier(g, rd, slots, count_only, t1, sched.grid_scale, first, ks, d_plans, d_M0);
+        st->tier1 += (uint32_t)(first.size() - left.size());
+        st->tier1_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ta).count();
         if (t1.threads != t2.threads) {
             second.insert(second.end(), left.begin(), left.end());
             left.clear();
@@ -334,67 +327,102 @@ gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32
             second.clear();
         }
         auto tb = std::chrono::steady_clock::now();
-        std::vector<FusedQuery> left2 = run_tier(g, b.get(), t2, 8, second, ks, d_plans, d_M0, s);
-        b->info.tier2 = (uint32_t)(second.size() - left2.size());
-        b->info.tier2_ms = ms_since(tb);
+        std::vector<FusedQuery> left2 = run_tier(g, rd, slots, count_only, t2, 8, second, ks, d_plans, d_M0);
+        st->tier2 += (uint32_t)(second.size() - left2.size());
+        st->tier2_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
         for (auto &f : left) to_wide.push_back(f.qi);
         for (auto &f : left2) to_wide.push_back(f.qi);
     }
     for (auto &pl : planned)
         if (levels_only || pl.R0 > t2.cap_rows) to_wide.push_back(pl.qi);
 
-    // everything else: level-synchronous, all at once
-    auto tw0 = std::chrono::steady_clock::now();
-    if (!to_wide.empty()) {
-        std::sort(to_wide.begin(), to_wide.end());
-        std::vector<const Planned *> byq(nq, nullptr);
-        for (auto &pl : planned) byq[pl.qi] = &pl;
-        std::vector<WideQuery> wq;
-        wq.reserve(to_wide.size());
-        for (uint32_t qi : to_wide) {
-            const Planned &pl = *byq[qi];
-            const HostQuery &q = hq[qi];
-            WideQuery x;
-            x.ctx = c;
-            x.q = &q;
-            x.qi = qi;
-            x.order = pl.order;
-            x.e0src = pl.e0src;
-            x.col.assign(q.k, 0);
-            for (uint32_t j = 0; j < q.k; j++) x.col[pl.order[j]] = j;
-            x.Cu.assign(q.k, nullptr);
-            for (uint32_t j = 0; j < q.k; j++) x.Cu[j] = bits + (uint64_t)(qbase[pl.a] + pl.order[j]) * nwords;
-            x.M = d_M0 + pl.m0_off;
-            x.R = pl.R0;
-            wq.push_back(std::move(x));
-        }
-        wide_run(g, wq, b->count_only);
-        for (auto &x : wq) {
-            gsi_batch::Entry &en = b->e[x.qi];
-            en.count = x.count;
-            en.digest[0] = x.digest[0];
-            en.digest[1] = x.digest[1];
-            en.rows = x.take_rows();
-            en.where = en.rows && x.count ? 3 : 0;
-            b->info.per_level++;
-        }
-    }
-    b->info.per_level_ms = ms_since(tw0);
-
     // one-vertex queries: the root table is the answer
     for (uint32_t qi : single) {
         gsi_query_options o{};
-        o.flags = b->count_only ? GSI_COUNT_ONLY : 0u;
-        gsi_result *r = run_query(g, hq[qi], &o);
-        gsi_batch::Entry &en = b->e[qi];
-        en.res = r;
-        en.count = r->count;
-        en.digest[0] = r->digest[0];
-        en.digest[1] = r->digest[1];
-        en.where = (r->rows && r->count) ? 2 : 0;
-        b->info.per_level++;
+        o.flags = count_only ? GSI_COUNT_ONLY : 0u;
+        gsi_result *r = run_query(g, *hq[qi], &o);
+        Slot &sl = *slots[qi];
+        sl.res = r;
+        sl.done = true;
+        sl.count = r->count;
+        sl.digest[0] = r->digest[0];
+        sl.digest[1] = r->digest[1];
+        sl.rows = r->rows;
+        st->single++;
     }
-    b->info.total_ms = ms_since(t0);
+
+    std::sort(to_wide.begin(), to_wide.end());
+    std::vector<const Planned *> byq(nq, nullptr);
+    for (auto &pl : planned) byq[pl.qi] = &pl;
+    for (uint32_t qi : to_wide) {
+        const Planned &pl = *byq[qi];
+        const HostQuery &q = *hq[qi];
+        WideQuery x;
+        x.ctx = c;
+        x.q = &q;
+        x.qi = qi;
+        x.tag = tags.empty() ? qi : tags[qi];
+        x.keep = rd;
+        x.order = pl.order;
+        x.e0src = pl.e0src;
+        x.col.assign(q.k, 0);
+        for (uint32_t j = 0; j < q.k; j++) x.col[pl.order[j]] = j;
+        x.Cu.assign(q.k, nullptr);
+        for (uint32_t j = 0; j < q.k; j++) x.Cu[j] = bits + (uint64_t)(qbase[pl.a] + pl.order[j]) * nwords;
+        x.M = d_M0 + pl.m0_off;
+        x.R = pl.R0;
+        wide.push_back(std::move(x));
+    }
+    st->wide += (uint32_t)wide.size();
+    return wide;
+}
+
+gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32_t flags,
+                     gsi_batch_schedule sched) {
+    gsi_ctx *c = g->ctx;
+    auto t0 = std::chrono::steady_clock::now();
+    if (flags & ~(GSI_COUNT_ONLY | GSI_BATCH_LEVELS_ONLY)) fail(GSI_E_INVALID, "unknown batch flag");
+    if (sched.threads != 64 && sched.threads != 256 && sched.threads != 1024)
+        fail(GSI_E_INVALID, "schedule threads must be 64, 256 or 1024");
+    if (sched.grid_scale < 1 || sched.grid_scale > 8) fail(GSI_E_INVALID, "schedule grid_scale must be 1..8");
+    std::vector<HostQuery> hq(nq);
+    for (uint32_t i = 0; i < nq; i++) {
+        try {
+            hq[i] = validate_query(qd[i].k, qd[i].vertex_labels, qd[i].n_edges, qd[i].src, qd[i].dst,
+                                   qd[i].edge_labels);
+        } catch (const Fail &f) {
+            std::string m = std::string("query ") + std::to_string(i) + ": " + gsi_last_error();
+            fail(f.st, "%s", m.c_str());
+        }
+    }
+    std::unique_ptr<gsi_batch> b(new gsi_batch());
+    b->ctx = c;
+    b->nq = nq;
+    b->count_only = (flags & GSI_COUNT_ONLY) != 0;
+    b->slots.reset(new Slot[nq]);
+    b->info.queries = nq;
+    b->info.schedule = sched;
+    std::vector<const HostQuery *> hp(nq);
+    std::vector<Slot *> sp(nq);
+    for (uint32_t i = 0; i < nq; i++) {
+        hp[i] = &hq[i];
+        sp[i] = &b->slots[i];
+    }
+    AdmitStats as;
+    std::vector<WideQuery> wq = admit_round(g, hp, sp, {}, b->count_only, (flags & GSI_BATCH_LEVELS_ONLY) != 0,
+                                            sched, &as);
+    auto tw0 = std::chrono::steady_clock::now();
+    wide_run(g, wq, b->count_only);
+    for (auto &x : wq) finish_slot(x, b->slots[x.qi]);
+    b->info.empty = as.empty;
+    b->info.tier1 = as.tier1;
+    b->info.tier2 = as.tier2;
+    b->info.per_level = as.wide + as.single;
+    b->info.filter_ms = as.filter_ms;
+    b->info.tier1_ms = as.tier1_ms;
+    b->info.tier2_ms = as.tier2_ms;
+    b->info.per_level_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tw0).count();
+    b->info.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return b.release();
 }
 
@@ -426,10 +454,10 @@ struct BusyB {
     }
     ~BusyB() { c->busy.store(0); }
 };
-const gsi_batch::Entry &entry(const gsi_batch *b, uint32_t qi) {
+const Slot &entry(const gsi_batch *b, uint32_t qi) {
     if (!b) fail(GSI_E_INVALID, "null batch");
     if (qi >= b->nq) fail(GSI_E_INVALID, "query index %u out of range (batch of %u)", qi, b->nq);
-    return b->e[qi];
+    return b->slots[qi];
 }
 }  // namespace
 
@@ -476,8 +504,7 @@ gsi_status gsi_batch_rows(const gsi_batch *b, uint32_t qi, uint32_t *dst, uint64
         if (!dst) fail(GSI_E_INVALID, "null buffer");
         gsi_ctx *c = b->ctx;
         GSI_HIP(hipSetDevice(c->device));
-        const uint32_t *src = e.where == 1 ? b->out + e.out_off : e.where == 2 ? e.res->rows : e.rows;
-        GSI_HIP(hipMemcpyAsync(dst, src, e.count * e.k * 4, hipMemcpyDeviceToHost, c->stream));
+        GSI_HIP(hipMemcpyAsync(dst, e.rows, e.count * e.k * 4, hipMemcpyDeviceToHost, c->stream));
         GSI_HIP(hipStreamSynchronize(c->stream));
     })
 }

@@ -1,6 +1,8 @@
 // Level-synchronous joins of many queries (wide.hip).
 #pragma once
 
+#include <memory>
+
 #include "gsi_internal.h"
 
 namespace gsi {
@@ -10,6 +12,8 @@ struct WideQuery {
     gsi_ctx *ctx = nullptr;
     const HostQuery *q = nullptr;
     uint32_t qi = 0;                      // index in the caller's batch
+    uint64_t tag = 0;                     // caller's handle (request id)
+    std::shared_ptr<void> keep;           // keeps the bitsets / root tables alive
     std::vector<uint32_t> order, e0src;   // Algorithm 2 order, first edges
     std::vector<uint32_t> col;            // query vertex -> column
     std::vector<const uint64_t *> Cu;     // level j: bitset C(order[j])
@@ -45,7 +49,7 @@ struct WideQuery {
     WideQuery &operator=(const WideQuery &) = delete;
     WideQuery(WideQuery &&o) noexcept { *this = std::move(o); }
     WideQuery &operator=(WideQuery &&o) noexcept {
-        ctx = o.ctx; q = o.q; qi = o.qi; order = std::move(o.order); e0src = std::move(o.e0src);
+        ctx = o.ctx; q = o.q; qi = o.qi; tag = o.tag; keep = std::move(o.keep); order = std::move(o.order); e0src = std::move(o.e0src);
         col = std::move(o.col); Cu = std::move(o.Cu); j = o.j; M = o.M; R = o.R; own = o.own; next = o.next;
         done = o.done; count = o.count; digest[0] = o.digest[0]; digest[1] = o.digest[1]; rows = o.rows;
         levels = o.levels;
@@ -66,8 +70,30 @@ struct WideQuery {
     }
 };
 
+// Holds queries in flight; each step() advances the active ones by one
+// join level in shared launches (a prefix of them when the arena cannot
+// hold a step for all: a step that fails to allocate is retried on half as
+// many queries, the others keep their state).
+class WideEngine {
+  public:
+    WideEngine(gsi_graph *g, bool count_only);
+    void add(WideQuery &&q);
+    bool idle() const;
+    uint32_t step();                   // returns how many are done now
+    std::vector<WideQuery> take_done();  // removes and returns finished queries
+    size_t in_flight() const { return qs_.size(); }
+    uint64_t steps() const { return steps_; }
+    std::vector<WideQuery> &queries() { return qs_; }
+
+  private:
+    gsi_graph *g_;
+    bool count_only_;
+    std::vector<WideQuery> qs_;
+    uint64_t steps_ = 0;
+};
+
 // Runs every query of `wq` to completion (count, digest and, unless
-// count_only, rows).
+// count_only, rows); `wq` comes back holding the finished queries.
 void wide_run(gsi_graph *g, std::vector<WideQuery> &wq, bool count_only);
 
 }  // namespace gsi

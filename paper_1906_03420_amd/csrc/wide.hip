@@ -273,18 +273,38 @@ __global__ __launch_bounds__(WT) void k_wdigest(const uint64_t *items, const uin
     }
 }
 
-void wide_run(gsi_graph *g, std::vector<WideQuery> &wq, bool count_only) {
+// One join level for the queries in `act` (all of them, or none: on an
+// allocation failure everything allocated for the step is given back and
+// no query changes state).
+static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool count_only) {
     gsi_ctx *c = g->ctx;
     constexpr uint64_t DIGEST_ITEM = 1u << 16;
-    for (;;) {
-        std::vector<WideQuery *> act;
-        for (auto &x : wq)
-            if (!x.done) act.push_back(&x);
-        if (act.empty()) break;
+    {
         const uint32_t nq = (uint32_t)act.size();
         Scratch s(c);
         std::vector<WQ> hq(nq);
         std::vector<WEdge> he;
+        // per-step allocations of the queries, released unless the step
+        // commits; declared after the host arrays so that, on a failure, the
+        // stream has drained the copies out of them before they go
+        struct Pending {
+            std::vector<WideQuery *> q;
+            bool commit = false;
+            gsi_ctx *c;
+            ~Pending() {
+                if (commit) return;
+                (void)hipStreamSynchronize(c->stream);
+                for (auto *x : q) {
+                    if (x->next) c->arena.release(x->next);
+                    x->next = nullptr;
+                    if (x->rows) c->arena.release(x->rows);
+                    x->rows = nullptr;
+                    x->digest[0] = x->digest[1] = 0;
+                }
+            }
+        } pend;
+        pend.q = act;
+        pend.c = c;
         uint64_t Rtot = 0, loctot = 0;
         for (uint32_t a = 0; a < nq; a++) {
             WideQuery &x = *act[a];
@@ -337,12 +357,13 @@ void wide_run(gsi_graph *g, std::vector<WideQuery> &wq, bool count_only) {
         uint64_t gba;
         read_scalars(c, scal, &gba, 1);  // also orders the uploads above before `hq`/`he` change
         if (gba == 0) {
+            pend.commit = true;
             for (auto *x : act) {
                 x->stats_gba[x->j] = 0;
                 x->levels = x->j;
                 x->finish_empty();
             }
-            continue;
+            return;
         }
         const uint64_t ntiles = (gba + WT - 1) / WT;
         uint64_t *trow = s.get<uint64_t>(ntiles + 1, "wide tile rows");
@@ -419,6 +440,7 @@ void wide_run(gsi_graph *g, std::vector<WideQuery> &wq, bool count_only) {
             x.digest[0] += part[2 * t];
             x.digest[1] ^= part[2 * t + 1];
         }
+        pend.commit = true;
         for (uint32_t a = 0; a < nq; a++) {
             WideQuery &x = *act[a];
             const WQ &Q = hq[a];
@@ -440,6 +462,66 @@ void wide_run(gsi_graph *g, std::vector<WideQuery> &wq, bool count_only) {
             }
         }
     }
+}
+
+// Estimated scratch bytes of one step for a query (lookups, bounds, F, one
+// slot per row for the bitmap and tiles, and a next table of the same rows).
+static uint64_t step_bytes(const WideQuery &x) {
+    const uint64_t ne = x.j;  // at most j linking edges
+    return x.R * (8 * ne + 4 + 8 + 8) + 4096;
+}
+
+WideEngine::WideEngine(gsi_graph *g, bool count_only) : g_(g), count_only_(count_only) {}
+
+void WideEngine::add(WideQuery &&q) { qs_.push_back(std::move(q)); }
+
+bool WideEngine::idle() const {
+    for (auto &x : qs_)
+        if (!x.done) return false;
+    return true;
+}
+
+uint32_t WideEngine::step() {
+    std::vector<WideQuery *> act;
+    for (auto &x : qs_)
+        if (!x.done) act.push_back(&x);
+    if (act.empty()) return 0;
+    // start with the queries whose estimated step scratch fits in half the
+    // largest free block; halve on an arena failure
+    gsi_ctx *c = g_->ctx;
+    const uint64_t room = c->arena.largest_free() / 2;
+    size_t n = 0;
+    uint64_t est = 0;
+    while (n < act.size() && (n == 0 || est + step_bytes(*act[n]) <= room)) est += step_bytes(*act[n++]);
+    for (;;) {
+        std::vector<WideQuery *> part(act.begin(), act.begin() + n);
+        try {
+            wide_step(g_, part, count_only_);
+            steps_++;
+            break;
+        } catch (const Fail &f) {
+            if (f.st != GSI_E_NOMEM || n == 1) throw;
+            n = (n + 1) / 2;
+            clear_error();
+        }
+    }
+    uint32_t done = 0;
+    for (auto *x : act) done += x->done;
+    return done;
+}
+
+std::vector<WideQuery> WideEngine::take_done() {
+    std::vector<WideQuery> out, keep;
+    for (auto &x : qs_) (x.done ? out : keep).push_back(std::move(x));
+    qs_ = std::move(keep);
+    return out;
+}
+
+void wide_run(gsi_graph *g, std::vector<WideQuery> &wq, bool count_only) {
+    WideEngine e(g, count_only);
+    for (auto &x : wq) e.add(std::move(x));
+    while (!e.idle()) e.step();
+    wq = e.take_done();
 }
 
 }  // namespace gsi

@@ -2,6 +2,9 @@
 
 Calls only the CPU oracle and the seeded input generators.  Usage:
     python tests/golden/make_golden.py er1k ba1m
+The file is rewritten after every query and a rerun resumes after the last
+query present, so a long workload can be written in several sittings; tests
+check the queries the file holds.
 Each query is accepted when the generator produces it and the oracle
 finishes it within deterministic limits (at most 10^9 embeddings and a
 per-workload cap on search nodes); otherwise it is redrawn with the next
@@ -31,7 +34,14 @@ def make(name: str, threads: int):
     max_nodes = MAX_NODES[name]
     out = dict(workload=name, n=g.n, m=g.m, limits=dict(max_count=MAX_COUNT, max_nodes=max_nodes),
                queries=[], rejected=[])
-    for i in range(c["nq"]):
+    path = os.path.join(HERE, "%s.json" % name)
+    if os.path.exists(path):
+        with open(path) as f:
+            old = json.load(f)
+        if old.get("limits") == out["limits"] and old.get("n") == g.n and old.get("m") == g.m:
+            out = old
+    start = len(out["queries"])
+    for i in range(start, c["nq"]):
         attempt = 0
         while True:
             try:
@@ -50,10 +60,10 @@ def make(name: str, threads: int):
         out["queries"].append(dict(index=i, attempt=attempt, k=q.k, m=q.m, mode=q.mode, count=r.count,
                                    digest=[str(r.digest[0]), str(r.digest[1])], nodes=r.nodes,
                                    oracle_s=round(dt, 4)))
-        print(name, i, q.k, r.count, flush=True)
-    path = os.path.join(HERE, "%s.json" % name)
-    with open(path, "w") as f:
-        json.dump(out, f, indent=1)
+        print(name, i, q.k, r.count, round(dt, 1), flush=True)
+        with open(path + ".tmp", "w") as f:
+            json.dump(out, f, indent=1)
+        os.replace(path + ".tmp", path)
     print("wrote", path)
 
 

@@ -315,6 +315,97 @@ gsi_status gsi_batch_free(gsi_batch *b);
 gsi_status gsi_batch_tune(gsi_graph *g, uint32_t nq, const gsi_query_desc *queries, uint32_t sample,
                           gsi_batch_schedule *out, double *out_ms_per_query);
 
+/* ------------------------------------------------------------ serving */
+/* A request loop over one resident graph (continuous batching).  Queries
+ * are submitted at any time and wait in arrival order.  Each
+ * gsi_server_step admits waiting queries, then advances every admitted
+ * query by one join level:
+ *   admission  up to max_admit waiting queries (first come, first served)
+ *              are admitted while the in-flight count stays within
+ *              max_inflight and the predicted intermediate-table bytes of
+ *              all admitted queries stay within table_budget (a query
+ *              admitted when nothing is in flight always fits).  The
+ *              prediction follows the join of Algorithm 3: from |C(u)| (the
+ *              vertices of u's label before the filter runs, the filtered
+ *              count after), the number of PCSR vertices and edges per edge
+ *              label (Sec. IV), it estimates every level's table and |GBA|
+ *              and keeps the largest step; it is recomputed from the true
+ *              table size after every step.  The admitted set then goes
+ *              through one batched filter pass, plans (Algorithm 2) and the
+ *              fused tiers, as in gsi_batch_run;
+ *   levels     the queries the fused tiers cannot hold join the
+ *              level-synchronous engine and advance one level per step in
+ *              launches shared with every other query in flight, whatever
+ *              level each is at.  When a step does not fit the arena it runs
+ *              on fewer queries (a misprediction costs time, not a failure);
+ *              a query whose level does not fit even alone after the others
+ *              have drained finishes with status GSI_E_NOMEM.
+ * PCSR, signatures, candidate bitsets and partial tables stay on the device.
+ * Answers are the ones gsi_query_run gives for the same query alone (count,
+ * digest, rows as a set).  Calls on one server must not overlap; the server
+ * uses its graph's context (GSI_E_BUSY while another call runs on it). */
+typedef struct gsi_server gsi_server;
+
+typedef struct {
+    uint32_t flags;         /* GSI_COUNT_ONLY: answers hold count and digest */
+    uint32_t max_inflight;  /* admitted queries not yet finished; 0: 1024 */
+    uint32_t max_admit;     /* queries admitted per step; 0: 256 */
+    uint32_t reserved;
+    uint64_t table_budget;  /* bytes; 0: half of the arena's largest free block
+                               when the server is created */
+    gsi_batch_schedule schedule;  /* fused tiers; threads == 0: the graph's
+                                     tuned schedule, else 256 / 8 eighths */
+} gsi_server_options;
+
+/* Errors: GSI_E_INVALID for a bad option; GSI_E_NOMEM / GSI_E_DEVICE. */
+gsi_status gsi_server_create(gsi_graph *g, const gsi_server_options *opt, gsi_server **out);
+/* Copies and validates the query (errors as gsi_query_run) and queues it;
+ * the ticket (> 0, increasing) names it in the calls below. */
+gsi_status gsi_server_submit(gsi_server *s, const gsi_query_desc *query, uint64_t *ticket);
+/* One admission and one level step; *finished = queries answered in it. */
+gsi_status gsi_server_step(gsi_server *s, uint32_t *finished);
+/* Moves up to `capacity` answered tickets (in the order they finished) to
+ * `tickets`; *n = how many. */
+gsi_status gsi_server_poll(gsi_server *s, uint64_t *tickets, uint32_t capacity, uint32_t *n);
+
+#define GSI_PATH_EMPTY 0   /* answered by the filter (0 rows) */
+#define GSI_PATH_TIER1 1   /* first fused tier */
+#define GSI_PATH_TIER2 2   /* 1024-thread fused tier */
+#define GSI_PATH_SINGLE 3  /* one-vertex query */
+#define GSI_PATH_LEVELS 4  /* level-synchronous engine */
+typedef struct {
+    gsi_status status;         /* GSI_OK, or GSI_E_NOMEM (see above) */
+    uint32_t k;
+    uint64_t count;
+    uint64_t digest[2];        /* (sum, xor) as gsi_result_digest */
+    uint32_t path;             /* GSI_PATH_* */
+    uint32_t levels;           /* level steps taken in the engine */
+    uint64_t predicted_bytes;  /* prediction at submission */
+    uint64_t peak_table_bytes; /* largest table held between steps */
+    double submit_ms, admit_ms, done_ms;  /* host clock, since creation */
+} gsi_server_answer;
+/* Errors: GSI_E_INVALID for an unknown, released or unfinished ticket. */
+gsi_status gsi_server_answer_get(const gsi_server *s, uint64_t ticket, gsi_server_answer *out);
+/* Rows of an answered ticket, row-major in query-vertex order (sorted only
+ * as the engine left them); GSI_E_CAPACITY if capacity_rows is too small,
+ * GSI_E_INVALID for a GSI_COUNT_ONLY server. */
+gsi_status gsi_server_rows(gsi_server *s, uint64_t ticket, uint32_t *host_dst, uint64_t capacity_rows);
+/* Frees an answered ticket's rows and record. */
+gsi_status gsi_server_release(gsi_server *s, uint64_t ticket);
+
+typedef struct {
+    uint64_t submitted, admitted, answered, released;
+    uint32_t waiting, in_flight;      /* now */
+    uint64_t steps, level_steps, admit_rounds;
+    uint64_t predicted_in_flight;     /* bytes, now */
+    uint64_t peak_predicted;          /* largest admitted prediction sum */
+    uint64_t table_budget;
+    double admit_ms, level_ms;        /* host wall time in the two phases */
+} gsi_server_info;
+gsi_status gsi_server_get_info(const gsi_server *s, gsi_server_info *out);
+/* Drops every query (waiting, in flight or answered) and the server. */
+gsi_status gsi_server_free(gsi_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,4 +4,4 @@ The library itself is libgsi.so (HIP C++, C ABI in include/gsi.h); this
 package is its thin ctypes binding plus the build script.
 """
 from .binding import *  # noqa: F401,F403
-from .binding import Batch, Context, Graph, GsiError, Result, load_library  # noqa: F401
+from .binding import Batch, Context, Graph, GsiError, Result, Server, load_library  # noqa: F401

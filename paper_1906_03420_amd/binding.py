@@ -26,6 +26,9 @@ GSI_COUNT_ONLY = 0x1
 GSI_FILTER_LABEL_ONLY = 0x2
 GSI_NO_FUSED = 0x4
 GSI_BATCH_LEVELS_ONLY = 0x8
+GSI_MAX_EDGE_LABELS = 65536
+GSI_PCSR_GPN = 16
+GSI_PATH_EMPTY, GSI_PATH_TIER1, GSI_PATH_TIER2, GSI_PATH_SINGLE, GSI_PATH_LEVELS = range(5)
 
 STATUS_NAMES = {0: "GSI_OK", 1: "GSI_E_INVALID", 2: "GSI_E_NOMEM", 3: "GSI_E_DEVICE", 4: "GSI_E_CAPACITY",
                 5: "GSI_E_BUSY", 6: "GSI_E_INTERNAL"}
@@ -91,6 +94,30 @@ class gsi_batch_info(ctypes.Structure):
                 ("per_level_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
 
 
+class gsi_server_options(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32), ("max_admit", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("table_budget", ctypes.c_uint64),
+                ("schedule", gsi_batch_schedule)]
+
+
+class gsi_server_answer(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("k", ctypes.c_uint32), ("count", ctypes.c_uint64),
+                ("digest", ctypes.c_uint64 * 2), ("path", ctypes.c_uint32), ("levels", ctypes.c_uint32),
+                ("predicted_bytes", ctypes.c_uint64), ("peak_table_bytes", ctypes.c_uint64),
+                ("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double), ("done_ms", ctypes.c_double)]
+
+
+class gsi_server_info(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64), ("answered", ctypes.c_uint64),
+                ("released", ctypes.c_uint64), ("waiting", ctypes.c_uint32), ("in_flight", ctypes.c_uint32),
+                ("steps", ctypes.c_uint64), ("level_steps", ctypes.c_uint64), ("admit_rounds", ctypes.c_uint64),
+                ("predicted_in_flight", ctypes.c_uint64), ("peak_predicted", ctypes.c_uint64),
+                ("table_budget", ctypes.c_uint64), ("admit_ms", ctypes.c_double), ("level_ms", ctypes.c_double)]
+
+
+PATH_NAMES = {GSI_PATH_EMPTY: "empty", GSI_PATH_TIER1: "tier1", GSI_PATH_TIER2: "tier2",
+              GSI_PATH_SINGLE: "single", GSI_PATH_LEVELS: "levels"}
+
 # name -> (restype, argtypes) for every exported function of gsi.h
 SIGNATURES = {
     "gsi_last_error": (ctypes.c_char_p, []),
@@ -130,6 +157,15 @@ SIGNATURES = {
     "gsi_batch_free": (ctypes.c_int, [VP]),
     "gsi_batch_tune": (ctypes.c_int, [VP, ctypes.c_uint32, ctypes.POINTER(gsi_query_desc), ctypes.c_uint32,
                                       ctypes.POINTER(gsi_batch_schedule), ctypes.POINTER(ctypes.c_double)]),
+    "gsi_server_create": (ctypes.c_int, [VP, ctypes.POINTER(gsi_server_options), ctypes.POINTER(VP)]),
+    "gsi_server_submit": (ctypes.c_int, [VP, ctypes.POINTER(gsi_query_desc), U64P]),
+    "gsi_server_step": (ctypes.c_int, [VP, U32P]),
+    "gsi_server_poll": (ctypes.c_int, [VP, U64P, ctypes.c_uint32, U32P]),
+    "gsi_server_answer_get": (ctypes.c_int, [VP, ctypes.c_uint64, ctypes.POINTER(gsi_server_answer)]),
+    "gsi_server_rows": (ctypes.c_int, [VP, ctypes.c_uint64, U32P, ctypes.c_uint64]),
+    "gsi_server_release": (ctypes.c_int, [VP, ctypes.c_uint64]),
+    "gsi_server_get_info": (ctypes.c_int, [VP, ctypes.POINTER(gsi_server_info)]),
+    "gsi_server_free": (ctypes.c_int, [VP]),
 }
 
 _lib = None
@@ -390,7 +426,103 @@ def gsi_batch_tune(g: int, queries, sample: int = 128):
     return dict(threads=sc.threads, grid_scale=sc.grid_scale, ms_per_query=ms.value)
 
 
+def gsi_server_create(g: int, flags: int = 0, max_inflight: int = 0, max_admit: int = 0, table_budget: int = 0,
+                      threads: int = 0, grid_scale: int = 0) -> int:
+    o = gsi_server_options(flags, max_inflight, max_admit, 0, table_budget, gsi_batch_schedule(threads, grid_scale))
+    h = VP()
+    _check(load_library().gsi_server_create(g, ctypes.byref(o), ctypes.byref(h)))
+    return h.value
+
+
+def gsi_server_submit(s: int, q) -> int:
+    arr, keep = _descs([q])
+    t = ctypes.c_uint64()
+    _check(load_library().gsi_server_submit(s, arr, ctypes.byref(t)))
+    return t.value
+
+
+def gsi_server_step(s: int) -> int:
+    n = ctypes.c_uint32()
+    _check(load_library().gsi_server_step(s, ctypes.byref(n)))
+    return n.value
+
+
+def gsi_server_poll(s: int, capacity: int = 4096) -> list:
+    buf = (ctypes.c_uint64 * max(1, capacity))()
+    n = ctypes.c_uint32()
+    _check(load_library().gsi_server_poll(s, buf, capacity, ctypes.byref(n)))
+    return [int(buf[i]) for i in range(n.value)]
+
+
+def gsi_server_answer_get(s: int, ticket: int) -> dict:
+    a = gsi_server_answer()
+    _check(load_library().gsi_server_answer_get(s, ticket, ctypes.byref(a)))
+    d = {f: getattr(a, f) for f, _ in gsi_server_answer._fields_ if f != "digest"}
+    d["digest"] = (int(a.digest[0]), int(a.digest[1]))
+    d["path"] = PATH_NAMES.get(a.path, str(a.path))
+    return d
+
+
+def gsi_server_rows(s: int, ticket: int, k: int, count: int) -> np.ndarray:
+    out = np.zeros((count, k), np.uint32)
+    _check(load_library().gsi_server_rows(s, ticket, out.ctypes.data_as(U32P), count))
+    return out
+
+
+def gsi_server_release(s: int, ticket: int):
+    _check(load_library().gsi_server_release(s, ticket))
+
+
+def gsi_server_get_info(s: int) -> dict:
+    i = gsi_server_info()
+    _check(load_library().gsi_server_get_info(s, ctypes.byref(i)))
+    return {f: getattr(i, f) for f, _ in gsi_server_info._fields_}
+
+
+def gsi_server_free(s: int):
+    _check(load_library().gsi_server_free(s))
+
+
 # ------------------------------------------------------------ conveniences
+class Server:
+    """Continuous-batching request loop over a resident graph; the caller
+    drives it with submit / step / poll."""
+
+    def __init__(self, h: int):
+        self.h = h
+
+    def submit(self, q) -> int:
+        return gsi_server_submit(self.h, q)
+
+    def step(self) -> int:
+        return gsi_server_step(self.h)
+
+    def poll(self, capacity: int = 4096) -> list:
+        return gsi_server_poll(self.h, capacity)
+
+    def answer(self, ticket: int) -> dict:
+        return gsi_server_answer_get(self.h, ticket)
+
+    def rows(self, ticket: int) -> np.ndarray:
+        a = self.answer(ticket)
+        return gsi_server_rows(self.h, ticket, a["k"], a["count"])
+
+    def sorted_rows(self, ticket: int) -> np.ndarray:
+        r = self.rows(ticket)
+        return r[np.lexsort(r.T[::-1])] if len(r) else r
+
+    def release(self, ticket: int):
+        gsi_server_release(self.h, ticket)
+
+    def info(self) -> dict:
+        return gsi_server_get_info(self.h)
+
+    def free(self):
+        if self.h:
+            gsi_server_free(self.h)
+            self.h = 0
+
+
 class Batch:
     def __init__(self, h: int, ks):
         self.h, self.ks = h, list(ks)
@@ -472,6 +604,10 @@ class Graph:
 
     def tune(self, queries, sample: int = 128) -> dict:
         return gsi_batch_tune(self.h, queries, sample)
+
+    def server(self, flags: int = 0, max_inflight: int = 0, max_admit: int = 0, table_budget: int = 0,
+               threads: int = 0, grid_scale: int = 0) -> Server:
+        return Server(gsi_server_create(self.h, flags, max_inflight, max_admit, table_budget, threads, grid_scale))
 
     def free(self):
         if self.h:

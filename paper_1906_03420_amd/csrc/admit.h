@@ -28,9 +28,13 @@ struct Round {
 };
 
 // where one query's answer lives
+enum SlotPath : uint8_t { PATH_NONE = 0, PATH_TIER1 = 1, PATH_TIER2 = 2, PATH_SINGLE = 3, PATH_LEVELS = 4 };
+
 struct Slot {
     uint32_t k = 0;
     bool done = false;
+    uint8_t path = PATH_NONE;         // which engine produced the answer
+    gsi_status status = GSI_OK;
     uint64_t count = 0;
     uint64_t digest[2] = {0, 0};
     const uint32_t *rows = nullptr;  // device rows (count x k), if any
@@ -48,6 +52,15 @@ struct Slot {
         own = nullptr;
         rows = nullptr;
         keep.reset();
+    }
+    // back to "not answered" (an admission that has to be retried)
+    void reset() {
+        if (ctx) clear();
+        done = false;
+        path = PATH_NONE;
+        status = GSI_OK;
+        count = 0;
+        digest[0] = digest[1] = 0;
     }
     Slot() = default;
     Slot(const Slot &) = delete;

@@ -84,7 +84,8 @@ struct FusedQuery {
 // Runs one fused tier over `list`; fills entries of finished queries and
 // returns the ones it could not hold.
 static std::vector<FusedQuery> run_tier(gsi_graph *g, const std::shared_ptr<Round> &rd,
-                                        const std::vector<Slot *> &slots, bool count_only, const FTier &t,
+                                        const std::vector<Slot *> &slots, bool count_only, uint8_t path,
+                                        const FTier &t,
                                         uint32_t grid_scale, const std::vector<FusedQuery> &list,
                                         const std::vector<uint32_t> &ks, const uint8_t *d_plans,
                                         const uint32_t *d_M0) {
@@ -121,6 +122,7 @@ static std::vector<FusedQuery> run_tier(gsi_graph *g, const std::shared_ptr<Roun
         Slot &sl = *slots[list[i].qi];
         if (hs[i].done) {
             sl.done = true;
+            sl.path = path;
             sl.count = hs[i].count;
             sl.digest[0] = hs[i].digest[0];
             sl.digest[1] = hs[i].digest[1];
@@ -146,6 +148,8 @@ static void *round_block(gsi_ctx *c, uint64_t bytes, const char *what) {
 
 void finish_slot(WideQuery &x, Slot &sl) {
     sl.done = true;
+    sl.path = PATH_LEVELS;
+    sl.status = x.status;
     sl.count = x.count;
     sl.digest[0] = x.digest[0];
     sl.digest[1] = x.digest[1];
@@ -205,6 +209,7 @@ std::vector<WideQuery> admit_round(gsi_graph *g, const std::vector<const HostQue
     struct Planned {
         uint32_t qi, a;
         std::vector<uint32_t> order, e0src;
+        std::vector<uint32_t> cand;
         uint32_t R0;
         uint64_t m0_off;
     };
@@ -231,6 +236,7 @@ std::vector<WideQuery> admit_round(gsi_graph *g, const std::vector<const HostQue
         make_plan(g, q, cand, pl.order, pl.e0src);
         pl.R0 = cand[pl.order[0]];
         pl.m0_off = 0;
+        pl.cand = cand;
         planned.push_back(std::move(pl));
     }
 
@@ -316,7 +322,7 @@ std::vector<WideQuery> admit_round(gsi_graph *g, const std::vector<const HostQue
         std::vector<FusedQuery> first, second;
         for (auto &f : fused) (f.R0 <= t1.cap_rows ? first : second).push_back(f);
         auto ta = std::chrono::steady_clock::now();
-        std::vector<FusedQuery> left = run_tier(g, rd, slots, count_only, t1, sched.grid_scale, first, ks, d_plans, d_M0);
+        std::vector<FusedQuery> left = run_tier(g, rd, slots, count_only, PATH_TIER1, t1, sched.grid_scale, first, ks, d_plans, d_M0);
         st->tier1 += (uint32_t)(first.size() - left.size());
         st->tier1_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ta).count();
         if (t1.threads != t2.threads) {
@@ -327,7 +333,7 @@ std::vector<WideQuery> admit_round(gsi_graph *g, const std::vector<const HostQue
             second.clear();
         }
         auto tb = std::chrono::steady_clock::now();
-        std::vector<FusedQuery> left2 = run_tier(g, rd, slots, count_only, t2, 8, second, ks, d_plans, d_M0);
+        std::vector<FusedQuery> left2 = run_tier(g, rd, slots, count_only, PATH_TIER2, t2, 8, second, ks, d_plans, d_M0);
         st->tier2 += (uint32_t)(second.size() - left2.size());
         st->tier2_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
         for (auto &f : left) to_wide.push_back(f.qi);
@@ -344,6 +350,7 @@ std::vector<WideQuery> admit_round(gsi_graph *g, const std::vector<const HostQue
         Slot &sl = *slots[qi];
         sl.res = r;
         sl.done = true;
+        sl.path = PATH_SINGLE;
         sl.count = r->count;
         sl.digest[0] = r->digest[0];
         sl.digest[1] = r->digest[1];
@@ -365,6 +372,7 @@ std::vector<WideQuery> admit_round(gsi_graph *g, const std::vector<const HostQue
         x.keep = rd;
         x.order = pl.order;
         x.e0src = pl.e0src;
+        x.cand = pl.cand;
         x.col.assign(q.k, 0);
         for (uint32_t j = 0; j < q.k; j++) x.col[pl.order[j]] = j;
         x.Cu.assign(q.k, nullptr);
@@ -430,30 +438,7 @@ gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32
 
 using namespace gsi;
 
-#define B_TRY(...)                               \
-    try {                                         \
-        clear_error();                            \
-        __VA_ARGS__;                              \
-        return GSI_OK;                            \
-    } catch (const Fail &f_) {                    \
-        return f_.st;                             \
-    } catch (const std::bad_alloc &) {            \
-        set_error("host allocation failed");      \
-        return GSI_E_NOMEM;                       \
-    } catch (...) {                               \
-        set_error("unexpected internal exception"); \
-        return GSI_E_INTERNAL;                    \
-    }
-
 namespace {
-struct BusyB {
-    gsi_ctx *c;
-    explicit BusyB(gsi_ctx *cc) : c(cc) {
-        int z = 0;
-        if (!c->busy.compare_exchange_strong(z, 1)) fail(GSI_E_BUSY, "context is already running a call");
-    }
-    ~BusyB() { c->busy.store(0); }
-};
 const Slot &entry(const gsi_batch *b, uint32_t qi) {
     if (!b) fail(GSI_E_INVALID, "null batch");
     if (qi >= b->nq) fail(GSI_E_INVALID, "query index %u out of range (batch of %u)", qi, b->nq);
@@ -465,21 +450,21 @@ extern "C" {
 
 gsi_status gsi_batch_run(gsi_graph *g, uint32_t nq, const gsi_query_desc *qs, const gsi_batch_options *opt,
                          gsi_batch **out) {
-    B_TRY({
+    GSI_TRY({
         if (!g || !out || (nq && !qs)) fail(GSI_E_INVALID, "null argument");
         *out = nullptr;
         gsi_batch_schedule sc = opt ? opt->schedule : gsi_batch_schedule{0, 0};
         if (sc.threads == 0) sc = g->tuned;
         if (sc.threads == 0) sc = gsi_batch_schedule{256, 8};
         gsi_ctx *c = g->ctx;
-        BusyB busy(c);
+        Busy busy(c);
         GSI_HIP(hipSetDevice(c->device));
         *out = run_batch(g, nq, qs, opt ? opt->flags : 0u, sc);
     })
 }
 
 gsi_status gsi_batch_count(const gsi_batch *b, uint32_t qi, uint64_t *rows) {
-    B_TRY({
+    GSI_TRY({
         const auto &e = entry(b, qi);
         if (!rows) fail(GSI_E_INVALID, "null argument");
         *rows = e.count;
@@ -487,7 +472,7 @@ gsi_status gsi_batch_count(const gsi_batch *b, uint32_t qi, uint64_t *rows) {
 }
 
 gsi_status gsi_batch_digest(const gsi_batch *b, uint32_t qi, uint64_t out[2]) {
-    B_TRY({
+    GSI_TRY({
         const auto &e = entry(b, qi);
         if (!out) fail(GSI_E_INVALID, "null argument");
         out[0] = e.digest[0];
@@ -496,7 +481,7 @@ gsi_status gsi_batch_digest(const gsi_batch *b, uint32_t qi, uint64_t out[2]) {
 }
 
 gsi_status gsi_batch_rows(const gsi_batch *b, uint32_t qi, uint32_t *dst, uint64_t cap) {
-    B_TRY({
+    GSI_TRY({
         const auto &e = entry(b, qi);
         if (b->count_only) fail(GSI_E_INVALID, "batch was run with GSI_COUNT_ONLY");
         if (cap < e.count) fail(GSI_E_CAPACITY, "need %llu rows", (unsigned long long)e.count);
@@ -510,14 +495,14 @@ gsi_status gsi_batch_rows(const gsi_batch *b, uint32_t qi, uint32_t *dst, uint64
 }
 
 gsi_status gsi_batch_get_info(const gsi_batch *b, gsi_batch_info *out) {
-    B_TRY({
+    GSI_TRY({
         if (!b || !out) fail(GSI_E_INVALID, "null argument");
         *out = b->info;
     })
 }
 
 gsi_status gsi_batch_free(gsi_batch *b) {
-    B_TRY({
+    GSI_TRY({
         if (!b) return GSI_OK;
         gsi_ctx *c = b->ctx;
         GSI_HIP(hipSetDevice(c->device));
@@ -528,10 +513,10 @@ gsi_status gsi_batch_free(gsi_batch *b) {
 
 gsi_status gsi_batch_tune(gsi_graph *g, uint32_t nq, const gsi_query_desc *qs, uint32_t sample,
                           gsi_batch_schedule *out, double *out_ms) {
-    B_TRY({
+    GSI_TRY({
         if (!g || !out || (nq && !qs)) fail(GSI_E_INVALID, "null argument");
         gsi_ctx *c = g->ctx;
-        BusyB busy(c);
+        Busy busy(c);
         GSI_HIP(hipSetDevice(c->device));
         const uint32_t n = std::max<uint32_t>(1, std::min(nq, sample ? sample : 128u));
         if (nq == 0) fail(GSI_E_INVALID, "no queries to tune on");

@@ -172,33 +172,9 @@ void read_scalars(gsi_ctx *c, const uint64_t *dev, uint64_t *host, int n) {
 
 void sync(gsi_ctx *c) { GSI_HIP(hipStreamSynchronize(c->stream)); }
 
-struct Busy {
-    gsi_ctx *c;
-    explicit Busy(gsi_ctx *cc) : c(cc) {
-        int z = 0;
-        if (!c->busy.compare_exchange_strong(z, 1)) fail(GSI_E_BUSY, "context is already running a call");
-    }
-    ~Busy() { c->busy.store(0); }
-};
-
 }  // namespace gsi
 
 using namespace gsi;
-
-#define GSI_TRY(...)                                     \
-    try {                                                 \
-        clear_error();                                    \
-        __VA_ARGS__;                                      \
-        return GSI_OK;                                    \
-    } catch (const Fail &f_) {                            \
-        return f_.st;                                     \
-    } catch (const std::bad_alloc &) {                    \
-        set_error("host allocation failed");              \
-        return GSI_E_NOMEM;                               \
-    } catch (...) {                                       \
-        set_error("unexpected internal exception");       \
-        return GSI_E_INTERNAL;                            \
-    }
 
 #define REQUIRE(cond, ...)                   \
     do {                                     \

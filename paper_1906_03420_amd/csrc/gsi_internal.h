@@ -276,3 +276,34 @@ __device__ __host__ __forceinline__ uint32_t sig_group(uint32_t elabel, uint32_t
 }
 
 }  // namespace gsi
+
+namespace gsi {
+
+// Marks the context busy for the length of one ABI call.
+struct Busy {
+    gsi_ctx *c;
+    explicit Busy(gsi_ctx *cc) : c(cc) {
+        int z = 0;
+        if (!c->busy.compare_exchange_strong(z, 1)) fail(GSI_E_BUSY, "context is already running a call");
+    }
+    ~Busy() { c->busy.store(0); }
+};
+
+}  // namespace gsi
+
+// Body of an ABI function: exceptions become status codes and the message
+// of the thread's last error.
+#define GSI_TRY(...)                                     \
+    try {                                                 \
+        gsi::clear_error();                               \
+        __VA_ARGS__;                                      \
+        return GSI_OK;                                    \
+    } catch (const gsi::Fail &f_) {                       \
+        return f_.st;                                     \
+    } catch (const std::bad_alloc &) {                    \
+        gsi::set_error("host allocation failed");         \
+        return GSI_E_NOMEM;                               \
+    } catch (...) {                                       \
+        gsi::set_error("unexpected internal exception");  \
+        return GSI_E_INTERNAL;                            \
+    }

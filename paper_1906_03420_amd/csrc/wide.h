@@ -15,6 +15,7 @@ struct WideQuery {
     uint64_t tag = 0;                     // caller's handle (request id)
     std::shared_ptr<void> keep;           // keeps the bitsets / root tables alive
     std::vector<uint32_t> order, e0src;   // Algorithm 2 order, first edges
+    std::vector<uint32_t> cand;           // |C(u)| per query vertex
     std::vector<uint32_t> col;            // query vertex -> column
     std::vector<const uint64_t *> Cu;     // level j: bitset C(order[j])
     uint32_t j = 1;                       // next level to join
@@ -23,6 +24,7 @@ struct WideQuery {
     void *own = nullptr;                  // arena block of M when owned
     void *next = nullptr;
     bool done = false;
+    gsi_status status = GSI_OK;           // GSI_E_NOMEM: a level did not fit alone
     uint64_t count = 0;
     uint64_t digest[2] = {0, 0};
     uint32_t *rows = nullptr;             // result rows (arena, high end)
@@ -49,9 +51,9 @@ struct WideQuery {
     WideQuery &operator=(const WideQuery &) = delete;
     WideQuery(WideQuery &&o) noexcept { *this = std::move(o); }
     WideQuery &operator=(WideQuery &&o) noexcept {
-        ctx = o.ctx; q = o.q; qi = o.qi; tag = o.tag; keep = std::move(o.keep); order = std::move(o.order); e0src = std::move(o.e0src);
+        ctx = o.ctx; q = o.q; qi = o.qi; tag = o.tag; keep = std::move(o.keep); order = std::move(o.order); e0src = std::move(o.e0src); cand = std::move(o.cand);
         col = std::move(o.col); Cu = std::move(o.Cu); j = o.j; M = o.M; R = o.R; own = o.own; next = o.next;
-        done = o.done; count = o.count; digest[0] = o.digest[0]; digest[1] = o.digest[1]; rows = o.rows;
+        done = o.done; status = o.status; count = o.count; digest[0] = o.digest[0]; digest[1] = o.digest[1]; rows = o.rows;
         levels = o.levels;
         for (int i = 0; i < GSI_MAX_K; i++) {
             stats_rows[i] = o.stats_rows[i];
@@ -73,10 +75,13 @@ struct WideQuery {
 // Holds queries in flight; each step() advances the active ones by one
 // join level in shared launches (a prefix of them when the arena cannot
 // hold a step for all: a step that fails to allocate is retried on half as
-// many queries, the others keep their state).
+// many queries, the others keep their state).  A query whose level does not
+// fit even alone raises GSI_E_NOMEM, or, in a tolerant engine, is moved
+// behind the others; when it is the only query left it is finished with
+// status GSI_E_NOMEM.
 class WideEngine {
   public:
-    WideEngine(gsi_graph *g, bool count_only);
+    WideEngine(gsi_graph *g, bool count_only, bool tolerant = false);
     void add(WideQuery &&q);
     bool idle() const;
     uint32_t step();                   // returns how many are done now
@@ -87,7 +92,7 @@ class WideEngine {
 
   private:
     gsi_graph *g_;
-    bool count_only_;
+    bool count_only_, tolerant_;
     std::vector<WideQuery> qs_;
     uint64_t steps_ = 0;
 };

@@ -471,7 +471,8 @@ static uint64_t step_bytes(const WideQuery &x) {
     return x.R * (8 * ne + 4 + 8 + 8) + 4096;
 }
 
-WideEngine::WideEngine(gsi_graph *g, bool count_only) : g_(g), count_only_(count_only) {}
+WideEngine::WideEngine(gsi_graph *g, bool count_only, bool tolerant)
+    : g_(g), count_only_(count_only), tolerant_(tolerant) {}
 
 void WideEngine::add(WideQuery &&q) { qs_.push_back(std::move(q)); }
 
@@ -493,6 +494,7 @@ uint32_t WideEngine::step() {
     size_t n = 0;
     uint64_t est = 0;
     while (n < act.size() && (n == 0 || est + step_bytes(*act[n]) <= room)) est += step_bytes(*act[n++]);
+    size_t skipped = 0;  // queries moved behind the others (tolerant engine)
     for (;;) {
         std::vector<WideQuery *> part(act.begin(), act.begin() + n);
         try {
@@ -500,9 +502,25 @@ uint32_t WideEngine::step() {
             steps_++;
             break;
         } catch (const Fail &f) {
-            if (f.st != GSI_E_NOMEM || n == 1) throw;
-            n = (n + 1) / 2;
+            if (f.st != GSI_E_NOMEM || (n == 1 && !tolerant_)) throw;
             clear_error();
+            if (n > 1) {
+                n = (n + 1) / 2;
+                continue;
+            }
+            WideQuery *x = act.front();
+            if (act.size() == 1 || skipped + 1 >= act.size()) {
+                // nothing else holds step memory that could be waited for
+                x->release_table();
+                x->status = GSI_E_NOMEM;
+                x->count = 0;
+                x->levels = x->j;
+                x->done = true;
+                break;
+            }
+            act.erase(act.begin());
+            act.push_back(x);
+            skipped++;
         }
     }
     uint32_t done = 0;

@@ -36,6 +36,17 @@ def test_binding_covers_every_declared_symbol():
         assert callable(getattr(gsi.binding, name)), name
 
 
+def test_binding_constants_match_header():
+    text = open(os.path.join(ROOT, "include", "gsi.h")).read()
+    defs = re.findall(r"#define\s+(GSI_[A-Z0-9_]+)\s+(0x[0-9a-fA-F]+|\d+)u?\b", text)
+    assert len(defs) >= 10
+    for name, val in defs:
+        assert getattr(gsi.binding, name) == int(val, 0), name
+    enum = re.search(r"typedef enum \{(.*?)\} gsi_status;", text, flags=re.S).group(1)
+    for name, val in re.findall(r"(GSI_[A-Z_]+)\s*=\s*(\d+)", enum):
+        assert getattr(gsi.binding, name) == int(val), name
+
+
 def test_host_side_errors_without_gpu():
     assert "gfx950" in gsi.gsi_version()
     with pytest.raises(gsi.GsiError) as e:

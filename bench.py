@@ -18,6 +18,11 @@ Prints ONE JSON line.  Fields beyond the common contract:
                 same graph and queries, all host threads
   queries_per_s, latency_ms {p50, p99}: per query, submit -> result ready
   parity        GPU counts and digests against the stored oracle values
+  batched       1,024 mixed queries on the same graph, one at a time vs one
+                batch (fused persistent tiers + level-synchronous engine)
+  serving       the request loop on an R-MAT scale-22 graph: saturation
+                throughput, then Poisson arrivals at 0.5 / 0.8 / 1.2 times it,
+                with p50 / p99 latency (arrival -> answer ready on device)
 """
 import argparse
 import json
@@ -152,6 +157,121 @@ def batched_section(args, vl_t, s_t, d_t, l_t, g, arena):
                 else "MISMATCH")
 
 
+def progress(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def serving_section(args, arena):
+    """Continuous batching on the R-MAT scale-22 graph (50M edges, 64 vertex
+    and 16 edge labels Zipf(1.1)).  Requests ask queries of the stored pool
+    (uniform with repeats).  First every request arrives at once (saturation
+    throughput mu); then, for each factor f, requests arrive as a Poisson
+    process of rate f*mu.  Latency = answer ready on the device (rows in
+    HBM, count and digest on the host) minus arrival.  Every answer is
+    checked against the oracle's count and digest for its query."""
+    import numpy as np
+    import torch
+    import workloads as w
+    import paper_1906_03420_amd as gsi
+    name = "rmat22_serve"
+    gold = load_golden(name)
+    if not gold or not gold["queries"]:
+        return dict(skipped="no stored query pool for %s" % name)
+    c = w.CONFIGS[name]
+    t = time.perf_counter()
+    g = w.config_graph(name)
+    mk = w.QueryMaker(g)
+    pool = [w.config_query(g, name, x["index"], attempt=x["attempt"], maker=mk) for x in gold["queries"]]
+    mk.close()
+    want = [(x["count"], x["digest"]) for x in gold["queries"]]
+    gen_s = time.perf_counter() - t
+    progress("serving graph generated in %.1f s, pool of %d queries" % (gen_s, len(pool)))
+    dev = torch.device("cuda:0")
+    as_t = lambda a: torch.from_numpy(a.view(np.int32)).to(dev)
+    ctx = gsi.Context(arena)
+    tensors = [as_t(g.vlabel), as_t(g.src), as_t(g.dst), as_t(g.elabel)]
+    dg = ctx.load_device(g.n, *tensors)
+    del tensors
+    torch.cuda.synchronize()
+    n = c["requests"]
+
+    def run(reqs, arrivals):
+        srv = dg.server()
+        lat = np.zeros(len(reqs))
+        by_ticket, paths = {}, {}
+        bad = i = done = 0
+        t0 = time.perf_counter()
+        while done < len(reqs):
+            now = time.perf_counter() - t0
+            while i < len(reqs) and (arrivals is None or arrivals[i] <= now):
+                by_ticket[srv.submit(pool[reqs[i]])] = i
+                i += 1
+            if i == done:  # nothing in the server: wait for the next arrival
+                while time.perf_counter() - t0 < arrivals[i]:
+                    pass
+                continue
+            srv.step()
+            tnow = time.perf_counter() - t0
+            for tk in srv.poll():
+                j = by_ticket.pop(tk)
+                a = srv.answer(tk)
+                lat[j] = tnow - (arrivals[j] if arrivals is not None else 0.0)
+                wc, wd = want[reqs[j]]
+                bad += a["status"] != 0 or a["count"] != wc or [str(a["digest"][0]), str(a["digest"][1])] != wd
+                paths[a["path"]] = paths.get(a["path"], 0) + 1
+                srv.release(tk)
+                done += 1
+        span = time.perf_counter() - t0
+        info = srv.info()
+        srv.free()
+        return span, lat, bad, info, paths
+
+    emb_of = lambda reqs: int(sum(want[r][0] for r in reqs))
+    # one query at a time through the single-query path
+    reqs0 = w.request_stream(name, 0, n, len(pool))
+    for r in reqs0[:32]:
+        dg.query(pool[r]).free()
+    t = time.perf_counter()
+    seq_bad = 0
+    for r in reqs0:
+        res = dg.query(pool[r])
+        seq_bad += (res.count, [str(v) for v in res.digest]) != (want[r][0], want[r][1])
+        res.free()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t
+    progress("serving: one at a time %.0f q/s" % (n / t_seq))
+    run(reqs0[:256], None)  # warm-up
+    span, lat, bad, info, paths = run(reqs0, None)
+    mu = n / span
+    progress("serving: saturation %.0f q/s" % mu)
+    total_bad = bad + seq_bad
+    sat = dict(queries_per_s=mu, embeddings_per_s=emb_of(reqs0) / span, p50_ms=float(np.percentile(lat, 50) * 1e3),
+               p99_ms=float(np.percentile(lat, 99) * 1e3), steps=info["steps"], level_steps=info["level_steps"],
+               paths=paths)
+    rates = []
+    for s_i, f in enumerate((0.5, 0.8, 1.2)):
+        reqs = w.request_stream(name, s_i + 1, n, len(pool))
+        arr = np.cumsum(w.arrival_gaps(name, s_i + 1, n)) / (f * mu)
+        span, lat, bad, info, paths = run(reqs, arr)
+        total_bad += bad
+        rates.append(dict(offered_factor=f, offered_qps=f * mu, achieved_qps=n / span,
+                          p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                          max_ms=float(lat.max() * 1e3), steps=info["steps"], level_steps=info["level_steps"],
+                          admit_rounds=info["admit_rounds"], peak_predicted_mb=info["peak_predicted"] / 2**20))
+        progress("serving: %.1f x mu -> p50 %.2f ms p99 %.2f ms" % (f, rates[-1]["p50_ms"], rates[-1]["p99_ms"]))
+    dg.free()
+    ctx.close()
+    ks = sorted(set(int(q.k) for q in pool))
+    return dict(workload="R-MAT scale 22, %d vertices / %d edges, 64 vertex + 16 edge labels Zipf(1.1); pool of %d "
+                         "queries (k %d-%d, tree / walk with a cycle / dense); %d requests per rate"
+                         % (g.n, g.m, len(pool), ks[0], ks[-1], n),
+                graph_gen_s=gen_s, one_at_a_time=dict(queries_per_s=n / t_seq,
+                                                       embeddings_per_s=emb_of(reqs0) / t_seq),
+                saturation=sat, speedup_vs_one_at_a_time=mu * t_seq / n, rates=rates,
+                parity=("bit-exact counts+digests vs oracle, every request (%d)" % (4 * n + n)) if total_bad == 0
+                else "MISMATCH in %d answers" % total_bad)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +281,7 @@ def main():
     ap.add_argument("--arena-gb", type=float, default=48.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device copy of this size (a reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -281,8 +402,14 @@ def main():
                                  gbs=round(k["alg_bytes"] / (k["total_ms"] * 1e-3) / 1e9, 1) if k["total_ms"] else None)
                  for k in ks},
     )
+    progress("single-query path done: %.3g embeddings/s" % res["value"])
     if not args.no_batched:
         res["batched"] = batched_section(args, vl_t, s_t, d_t, l_t, g, arena)
+        progress("batched section done")
+    if not args.no_serving:
+        del vl_t, s_t, d_t, l_t
+        torch.cuda.empty_cache()
+        res["serving"] = serving_section(args, arena)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(g, qs, host_threads())
     print(json.dumps(res), flush=True)

@@ -13,12 +13,14 @@
  * only).  The result is the set of all such maps, one row per map.
  *
  * The search is the textbook tree search with backtracking the paper contrasts
- * its method with (Sec. I): vertices are placed in breadth-first order from the
- * query vertex whose label is rarest in G; each vertex after the first is
- * extended from the neighbour list of its already-placed BFS parent; the
- * remaining already-placed neighbours are checked by binary search in sorted
- * adjacency lists.  Candidates are pruned by label and degree only.  Nothing
- * here shares code with the GPU library.
+ * its method with (Sec. I).  The first query vertex is the one whose label is
+ * rarest in G; each next one is an unplaced vertex with the most already-placed
+ * neighbours (ties: rarer label, then smaller id), so cycles close early.  A
+ * vertex is extended from the neighbour list of whichever already-placed
+ * neighbour's image has the shortest list; the other placed neighbours are
+ * checked by binary search in sorted adjacency lists.  Candidates are pruned
+ * by label and degree only.  The order changes only the cost of the search,
+ * never the set of maps found.  Nothing here shares code with the GPU library.
  *
  * Order-independent digest of a result set: for each tuple t (query-vertex
  * order, 4k little-endian bytes) h(t) = SplitMix64-finalizer(FNV-1a-64(t));
@@ -166,11 +168,9 @@ typedef struct {
     uint32_t qlabel[MAXK];
     uint32_t qdeg[MAXK];
     uint32_t order[MAXK];      /* order[d] = query vertex placed at depth d */
-    uint32_t parent[MAXK];     /* parent query vertex of order[d], d >= 1 */
-    uint32_t plabel[MAXK];     /* label of edge (parent, order[d]) */
-    uint32_t nchk[MAXK];       /* other placed neighbours to verify */
-    uint32_t chk_u[MAXK][MAXK];
-    uint32_t chk_l[MAXK][MAXK];
+    uint32_t nlink[MAXK];      /* placed neighbours of order[d], d >= 1 */
+    uint32_t link_u[MAXK][MAXK];
+    uint32_t link_l[MAXK][MAXK];  /* label of edge (link_u, order[d]) */
 } plan_t;
 
 typedef struct {
@@ -216,17 +216,23 @@ static void dfs(worker_t *w, uint32_t d) {
         return;
     }
     uint32_t u = p->order[d];
-    uint32_t vp = w->f[p->parent[d]];
+    /* scan the shortest neighbour list among the placed neighbours' images */
+    uint32_t src = 0;
+    for (uint32_t c = 1; c < p->nlink[d]; c++) {
+        uint32_t a = w->f[p->link_u[d][c]], b = w->f[p->link_u[d][src]];
+        if (g->rp[a + 1] - g->rp[a] < g->rp[b + 1] - g->rp[b]) src = c;
+    }
+    uint32_t vp = w->f[p->link_u[d][src]];
     for (uint64_t i = g->rp[vp]; i < g->rp[vp + 1]; i++) {
-        if (g->adjl[i] != p->plabel[d]) continue;
+        if (g->adjl[i] != p->link_l[d][src]) continue;
         uint32_t x = g->adj[i];
         w->nodes++;
         if (g->vlabel[x] != p->qlabel[u]) continue;
         if (g->rp[x + 1] - g->rp[x] < p->qdeg[u]) continue;
         int ok = 1;
         for (uint32_t e = 0; e < d; e++) if (w->f[p->order[e]] == x) { ok = 0; break; }
-        for (uint32_t c = 0; ok && c < p->nchk[d]; c++)
-            if (edge_label(g, w->f[p->chk_u[d][c]], x) != (int64_t)p->chk_l[d][c]) ok = 0;
+        for (uint32_t c = 0; ok && c < p->nlink[d]; c++)
+            if (c != src && edge_label(g, w->f[p->link_u[d][c]], x) != (int64_t)p->link_l[d][c]) ok = 0;
         if (!ok) continue;
         w->f[u] = x;
         dfs(w, d + 1);
@@ -293,29 +299,36 @@ int oracle_match(const og_graph *g, uint32_t k, const uint32_t *qlabel, uint32_t
         uint64_t c = label_count(g, qlabel[u]);
         if (c < best) { best = c; first = u; }
     }
-    /* BFS order, neighbours by ascending id; parent = earliest-placed neighbour */
+    /* next vertex: most placed neighbours, then rarer label, then smaller id */
     uint32_t pos[MAXK];
     for (uint32_t u = 0; u < k; u++) pos[u] = UINT32_MAX;
     uint32_t nord = 0;
     p->order[nord] = first; pos[first] = nord++;
-    for (uint32_t h = 0; h < nord; h++) {
-        uint32_t x = p->order[h];
-        for (uint32_t y = 0; y < k; y++)
-            if (adjq[x][y] && pos[y] == UINT32_MAX) { p->order[nord] = y; pos[y] = nord++; }
+    while (nord < k) {
+        uint32_t pick = UINT32_MAX, pick_links = 0;
+        uint64_t pick_count = 0;
+        for (uint32_t y = 0; y < k; y++) {
+            if (pos[y] != UINT32_MAX) continue;
+            uint32_t links = 0;
+            for (uint32_t e = 0; e < nord; e++) links += adjq[y][p->order[e]];
+            if (links == 0) continue;
+            uint64_t c = label_count(g, qlabel[y]);
+            if (pick == UINT32_MAX || links > pick_links || (links == pick_links && c < pick_count)) {
+                pick = y; pick_links = links; pick_count = c;
+            }
+        }
+        if (pick == UINT32_MAX) break;
+        p->order[nord] = pick; pos[pick] = nord++;
     }
     if (nord != k) { free(p); return out->status = OR_INVALID; } /* disconnected */
     for (uint32_t d = 1; d < k; d++) {
         uint32_t u = p->order[d];
-        uint32_t par = UINT32_MAX;
-        for (uint32_t e = 0; e < d; e++) if (adjq[u][p->order[e]]) { par = p->order[e]; break; }
-        p->parent[d] = par;
-        p->plabel[d] = (uint32_t)lq[u][par];
         for (uint32_t e = 0; e < d; e++) {
-            uint32_t w = p->order[e];
-            if (w != par && adjq[u][w]) {
-                p->chk_u[d][p->nchk[d]] = w;
-                p->chk_l[d][p->nchk[d]] = (uint32_t)lq[u][w];
-                p->nchk[d]++;
+            uint32_t x = p->order[e];
+            if (adjq[u][x]) {
+                p->link_u[d][p->nlink[d]] = x;
+                p->link_l[d][p->nlink[d]] = (uint32_t)lq[u][x];
+                p->nlink[d]++;
             }
         }
     }

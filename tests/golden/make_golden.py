@@ -6,9 +6,10 @@ The file is rewritten after every query and a rerun resumes after the last
 query present, so a long workload can be written in several sittings; tests
 check the queries the file holds.
 Each query is accepted when the generator produces it and the oracle
-finishes it within deterministic limits (at most 10^9 embeddings and a
-per-workload cap on search nodes); otherwise it is redrawn with the next
-attempt number and the rejection is logged in the output file.
+finishes it within per-workload limits on embeddings and on search nodes
+(each of the oracle's threads gets an equal share of the node cap, so the
+thread count is recorded); otherwise it is redrawn with the next attempt
+number and the rejection is logged in the output file.
 """
 import json
 import os
@@ -21,9 +22,16 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 import workloads as w  # noqa: E402
 
-MAX_COUNT = 1_000_000_000
+MAX_COUNT = {"er1k": 1_000_000_000, "ba1m": 1_000_000_000, "ba1m_batch": 1_000_000_000,
+             "rmat23": 1_000_000_000, "rmat22_serve": 10_000_000}
 MAX_NODES = {"er1k": 20_000_000_000, "ba1m": 20_000_000_000, "ba1m_batch": 4_000_000_000,
-             "rmat23": 4_000_000_000}
+             "rmat23": 4_000_000_000, "rmat22_serve": 100_000_000}
+
+
+# workloads whose acceptance records the oracle's thread count
+NEW_STYLE = ("rmat23", "rmat22_serve")
+# after this many rejected attempts an index is dropped (recorded in the file)
+MAX_ATTEMPTS = {"rmat22_serve": 6}
 
 
 def make(name: str, threads: int):
@@ -31,19 +39,30 @@ def make(name: str, threads: int):
     g = w.config_graph(name)
     og = oracle.OracleGraph(g)
     mk = w.QueryMaker(g)
-    max_nodes = MAX_NODES[name]
-    out = dict(workload=name, n=g.n, m=g.m, limits=dict(max_count=MAX_COUNT, max_nodes=max_nodes),
-               queries=[], rejected=[])
+    max_nodes, max_count = MAX_NODES[name], MAX_COUNT[name]
+    limits = dict(max_count=max_count, max_nodes=max_nodes)
+    if name in NEW_STYLE:
+        limits["threads"] = threads
+    if name in MAX_ATTEMPTS:
+        limits["max_attempts"] = MAX_ATTEMPTS[name]
+    out = dict(workload=name, n=g.n, m=g.m, limits=limits, queries=[], rejected=[])
     path = os.path.join(HERE, "%s.json" % name)
     if os.path.exists(path):
         with open(path) as f:
             old = json.load(f)
         if old.get("limits") == out["limits"] and old.get("n") == g.n and old.get("m") == g.m:
             out = old
-    start = len(out["queries"])
+    out.setdefault("dropped", [])
+
+    def save():
+        with open(path + ".tmp", "w") as f:
+            json.dump(out, f, indent=1)
+        os.replace(path + ".tmp", path)
+
+    start = 1 + max([x["index"] for x in out["queries"]] + out["dropped"], default=-1)
     for i in range(start, c["nq"]):
         attempt = 0
-        while True:
+        while attempt < limits.get("max_attempts", 1 << 30):
             try:
                 q = w.config_query(g, name, i, attempt=attempt, maker=mk)
             except RuntimeError:
@@ -51,22 +70,27 @@ def make(name: str, threads: int):
                 attempt += 1
                 continue
             t = time.time()
-            r = og.match(q, threads=threads, tuples=False, max_count=MAX_COUNT, max_nodes=max_nodes)
+            r = og.match(q, threads=threads, tuples=False, max_count=max_count, max_nodes=max_nodes)
             dt = time.time() - t
             if r.status == oracle.OR_OK:
                 break
             out["rejected"].append(dict(index=i, attempt=attempt, status=r.status))
+            print(name, i, "rejected attempt", attempt, "status", r.status, round(dt, 1), flush=True)
             attempt += 1
+        else:
+            out["dropped"].append(i)
+            print(name, i, "dropped", flush=True)
+            save()
+            continue
         out["queries"].append(dict(index=i, attempt=attempt, k=q.k, m=q.m, mode=q.mode, count=r.count,
                                    digest=[str(r.digest[0]), str(r.digest[1])], nodes=r.nodes,
                                    oracle_s=round(dt, 4)))
         print(name, i, q.k, r.count, round(dt, 1), flush=True)
-        with open(path + ".tmp", "w") as f:
-            json.dump(out, f, indent=1)
-        os.replace(path + ".tmp", path)
+        save()
+    save()
     print("wrote", path)
 
 
 if __name__ == "__main__":
     for nm in sys.argv[1:] or ["er1k", "ba1m"]:
-        make(nm, threads=os.cpu_count() or 1)
+        make(nm, threads=8)

@@ -20,6 +20,12 @@ in Sec. VIII-A and random-walk queries as in the same section):
   RMAT-23   R-MAT scale 23, 100M edges, (a,b,c) = (0.57,0.19,0.19); 100 vertex
             labels and 20 edge labels Zipf(1.1); 50 queries of 12 vertices
             (25 walk + 25 dense).
+  RMAT-22-S R-MAT scale 22, 50M edges, the same (a,b,c); 64 vertex labels and
+            16 edge labels Zipf(1.1); a pool of 512 queries of 4..24 vertices
+            with the BA-1M-B shapes, for the serving loop: each offered rate
+            serves 2,000 requests drawn from the pool (``request_stream``),
+            arriving as a Poisson process (unit-rate gaps from
+            ``arrival_gaps``, scaled by the caller to the offered rate).
 """
 from __future__ import annotations
 
@@ -231,7 +237,21 @@ CONFIGS = {
                        modes=("tree", "walk_cycle", "dense")),
     "rmat23": dict(model="rmat", scale=23, m=100_000_000, nvl=100, nel=20, vdist="zipf", edist="zipf",
                    gseed=19, lseed=2019, qseed=1019, nq=50, kmin=12, kmax=12, modes=("walk", "dense")),
+    "rmat22_serve": dict(model="rmat", scale=22, m=50_000_000, nvl=64, nel=16, vdist="zipf", edist="zipf",
+                         gseed=21, lseed=2021, qseed=1021, nq=512, kmin=4, kmax=24,
+                         modes=("tree", "walk_cycle", "dense"), aseed=3021, requests=2000),
 }
+
+
+def arrival_gaps(name: str, stream: int, n: int) -> np.ndarray:
+    """Inter-arrival gaps of a unit-rate Poisson process (mean 1), seeded by
+    the workload's arrival seed and a stream number (one per offered rate)."""
+    return _stream(CONFIGS[name]["aseed"], stream).exponential(1.0, n)
+
+
+def request_stream(name: str, stream: int, n: int, pool: int) -> np.ndarray:
+    """Which pool query each of `n` requests asks (uniform, with repeats)."""
+    return _stream(CONFIGS[name]["aseed"] + 1, stream).integers(0, pool, n)
 
 
 def config_graph(name: str) -> Graph:

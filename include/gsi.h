@@ -161,6 +161,7 @@ gsi_status gsi_graph_copy_pcsr(const gsi_graph *g, uint32_t label, uint32_t *hos
                                       (skips the signature test) */
 #define GSI_NO_FUSED 0x4u          /* run every level with the per-level kernels
                                       (no fused small-table workgroup) */
+#define GSI_NO_CHUNKS 0x10u        /* no root chunks (see gsi_query_run) */
 
 /* Optional controls of one query run (NULL = defaults). */
 typedef struct {
@@ -175,6 +176,9 @@ typedef struct {
                                   capacity of the fused small-table workgroup */
     uint32_t fused_max_slots;  /* 0 = default (16384); test only: a lower |GBA|
                                   capacity of the fused workgroup */
+    uint32_t chunk_rows;       /* 0 = automatic; else root rows per chunk */
+    uint32_t chunk_min_rows;   /* 0 = default (64); root chunks are used when
+                                  |C(u_first)| is at least this */
 } gsi_query_options;
 
 /*
@@ -190,9 +194,16 @@ typedef struct {
  *      survivor into M' (Prealloc-Combine, one join pass);
  *   4. the last level writes rows in query-vertex order (or only counts) and
  *      the order-independent digest.
- * While the tables stay small (at most 4096 rows and 16384 |GBA| slots per
- * level) one fused workgroup runs the levels without host round trips; the
- * remaining levels run as separate kernels.  Both give identical results.
+ * Rows of M are independent at every level, so step 3 first runs on root
+ * chunks: small groups of rows of M = C(u_first), each taken by one
+ * 256-thread workgroup of a persistent launch that runs all levels of its
+ * chunk (tables of up to 1024 rows and 4096 |GBA| slots per level, with F,
+ * the keep bits and the survivor prefix sums in LDS).  The roots of chunks
+ * that do not fit continue with the per-level kernels; the rows of both
+ * parts are concatenated (chunk rows first, in root order).  Below 64 roots
+ * one fused workgroup runs the levels while the tables stay small (4096 rows,
+ * 16384 slots) and the per-level kernels continue from where it stopped.
+ * Every route gives the same rows, count and digest.
  * q_vertex_labels[k]; q_src/q_dst/q_edge_labels[q_edges] (host).
  * Errors: GSI_E_INVALID for k == 0 or k > GSI_MAX_K, an endpoint >= k, a
  * self-loop, a repeated pair, a disconnected Q or a bad option; GSI_E_NOMEM
@@ -235,6 +246,8 @@ typedef struct {
     uint64_t other_elems[GSI_MAX_K]; /* sum of non-first linking list lengths at level j
                                         (gathered in GSI_CTX_PROFILE contexts only, else 0) */
     uint64_t survivors[GSI_MAX_K];   /* rows of M' produced by level j */
+    uint32_t chunks;                 /* root chunks run (0: none) */
+    uint32_t chunks_left;            /* chunks finished by the per-level kernels */
     double filter_ms;                /* host wall time of the filter step */
     double join_ms;                  /* host wall time of the joins */
     double total_ms;                 /* host wall time of the whole call */

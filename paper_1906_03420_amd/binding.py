@@ -26,6 +26,7 @@ GSI_COUNT_ONLY = 0x1
 GSI_FILTER_LABEL_ONLY = 0x2
 GSI_NO_FUSED = 0x4
 GSI_BATCH_LEVELS_ONLY = 0x8
+GSI_NO_CHUNKS = 0x10
 GSI_MAX_EDGE_LABELS = 65536
 GSI_PCSR_GPN = 16
 GSI_PATH_EMPTY, GSI_PATH_TIER1, GSI_PATH_TIER2, GSI_PATH_SINGLE, GSI_PATH_LEVELS = range(5)
@@ -62,7 +63,8 @@ class gsi_graph_info(ctypes.Structure):
 
 class gsi_query_options(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("order", U32P), ("first_edge", U32P), ("max_rows", ctypes.c_uint64),
-                ("fused_max_rows", ctypes.c_uint32), ("fused_max_slots", ctypes.c_uint32)]
+                ("fused_max_rows", ctypes.c_uint32), ("fused_max_slots", ctypes.c_uint32),
+                ("chunk_rows", ctypes.c_uint32), ("chunk_min_rows", ctypes.c_uint32)]
 
 
 class gsi_stats(ctypes.Structure):
@@ -70,8 +72,8 @@ class gsi_stats(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("levels", ctypes.c_uint32), ("order", ctypes.c_uint32 * K),
                 ("first_edge", ctypes.c_uint32 * K), ("n_link", ctypes.c_uint32 * K), ("cand", ctypes.c_uint32 * K),
                 ("rows", ctypes.c_uint64 * K), ("gba", ctypes.c_uint64 * K), ("other_elems", ctypes.c_uint64 * K),
-                ("survivors", ctypes.c_uint64 * K), ("filter_ms", ctypes.c_double), ("join_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double)]
+                ("survivors", ctypes.c_uint64 * K), ("chunks", ctypes.c_uint32), ("chunks_left", ctypes.c_uint32),
+                ("filter_ms", ctypes.c_double), ("join_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
 
 
 class gsi_query_desc(ctypes.Structure):
@@ -293,13 +295,14 @@ def gsi_graph_copy_pcsr(g: int, label: int):
 
 
 def gsi_query_run(g: int, k: int, q_vertex_labels, q_src, q_dst, q_edge_labels, flags: int = 0, order=None,
-                  first_edge=None, max_rows: int = 0, fused_max_rows: int = 0, fused_max_slots: int = 0) -> int:
+                  first_edge=None, max_rows: int = 0, fused_max_rows: int = 0, fused_max_slots: int = 0,
+                  chunk_rows: int = 0, chunk_min_rows: int = 0) -> int:
     vl, vlp = _u32(q_vertex_labels)
     s, sp = _u32(q_src)
     d, dp = _u32(q_dst)
     l, lp = _u32(q_edge_labels)
     keep = []
-    o = gsi_query_options(flags, None, None, max_rows, fused_max_rows, fused_max_slots)
+    o = gsi_query_options(flags, None, None, max_rows, fused_max_rows, fused_max_slots, chunk_rows, chunk_min_rows)
     if order is not None:
         a, p = _u32(order)
         keep.append(a)
@@ -359,8 +362,8 @@ def gsi_result_stats(r: int) -> dict:
     lv = s.levels
     return dict(k=k, levels=lv, order=list(s.order[:k]), first_edge=list(s.first_edge[:k]),
                 n_link=list(s.n_link[:k]), cand=list(s.cand[:k]), rows=list(s.rows[:k]), gba=list(s.gba[:k]),
-                other_elems=list(s.other_elems[:k]), survivors=list(s.survivors[:k]), filter_ms=s.filter_ms,
-                join_ms=s.join_ms, total_ms=s.total_ms)
+                other_elems=list(s.other_elems[:k]), survivors=list(s.survivors[:k]), chunks=s.chunks,
+                chunks_left=s.chunks_left, filter_ms=s.filter_ms, join_ms=s.join_ms, total_ms=s.total_ms)
 
 
 def gsi_result_free(r: int):
@@ -591,9 +594,9 @@ class Graph:
         return gsi_graph_copy_pcsr(self.h, label)
 
     def query(self, q, flags: int = 0, order=None, first_edge=None, max_rows: int = 0, fused_max_rows: int = 0,
-              fused_max_slots: int = 0) -> Result:
+              fused_max_slots: int = 0, chunk_rows: int = 0, chunk_min_rows: int = 0) -> Result:
         h = gsi_query_run(self.h, q.k, q.vlabel, q.src, q.dst, q.elabel, flags, order, first_edge, max_rows,
-                          fused_max_rows, fused_max_slots)
+                          fused_max_rows, fused_max_slots, chunk_rows, chunk_min_rows)
         return Result(h, q.k)
 
     def filter(self, q):

@@ -8,6 +8,8 @@ namespace gsi {
 constexpr uint32_t FUSED_MAX_ROWS = 4096;    // rows of any table the workgroup holds
 constexpr uint32_t FUSED_MAX_SLOTS = 16384;  // |GBA| of any level it joins
 constexpr uint32_t FSTATUS_IN_FIRST = 2;     // M is still the first table
+constexpr uint32_t CHUNK_MIN_ROWS = 64;      // root chunks from this many roots on
+constexpr uint32_t CHUNK_MAX = 16384;        // chunks of one launch
 
 struct FEdge {            // one linking edge of a level
     const uint32_t *gl;   // PCSR groups of its label
@@ -39,6 +41,16 @@ struct FStatus {
     uint64_t levels;  // levels finished
     uint64_t count;
     uint64_t digest[2];
+    uint64_t out_base;  // chunked runs: first output word it reserved
+    uint64_t lv_rows[GSI_MAX_K], lv_gba[GSI_MAX_K], lv_surv[GSI_MAX_K];
+};
+
+// Totals of a chunked run (k_chunk_summary).
+struct FChunkSummary {
+    uint64_t all_done;  // every chunk finished
+    uint64_t count;
+    uint64_t digest[2];
+    uint64_t levels;    // most levels any chunk ran
     uint64_t lv_rows[GSI_MAX_K], lv_gba[GSI_MAX_K], lv_surv[GSI_MAX_K];
 };
 
@@ -62,6 +74,29 @@ FTier fused_tier(uint32_t threads);
 void launch_fused_batch(gsi_ctx *c, const FTier &t, uint32_t grid, const uint8_t *plans, const FBatchItem *items,
                         uint32_t nitems, const uint32_t *M0all, uint32_t *scratch, uint64_t slot_words, uint32_t kmax,
                         uint32_t *outall, FStatus *sts, uint32_t *counter, double bytes);
+
+// One query split into chunks of `chunk_rows` root rows (the rows of M are
+// independent at every level of Algorithm 3): a persistent launch of the
+// tier's workgroups takes chunks from `counter` and runs all levels of each.
+// Finished chunks reserve their output rows in `staging` (capacity
+// `staging_words`) through `ocount`.  A chunk that cannot hold a level, or
+// whose rows do not fit the staging buffer, is left undone; once more than
+// `max_fail` chunks are, `abort` (two words: flag, failures) is set and the
+// launch stops taking chunks.  k_chunk_summary then writes the totals of the
+// finished chunks, each chunk's first output row (chunk order) and a done
+// flag per chunk.
+void launch_fused_chunks(gsi_ctx *c, const FTier &t, uint32_t grid, const FPlan *plan, const uint32_t *M0,
+                         uint32_t R0, uint32_t chunk_rows, uint32_t nchunks, uint32_t *scratch, uint64_t slot_words,
+                         uint32_t k, uint32_t *staging, uint64_t staging_words, unsigned long long *ocount,
+                         uint32_t *abort, uint32_t max_fail, FStatus *sts, uint32_t *counter, uint64_t *offs,
+                         uint32_t *done, FChunkSummary *sum);
+// Rows of the finished chunks into `out` in chunk order, which is the order
+// the per-level path gives those roots.
+void launch_chunk_gather(gsi_ctx *c, uint32_t nchunks, const FStatus *sts, const uint64_t *offs,
+                         const uint32_t *staging, uint32_t k, uint32_t *out, uint64_t words);
+// Concatenates the root rows of the chunks in `list` (pairs: chunk, position).
+void launch_take_roots(gsi_ctx *c, uint32_t nlist, const uint32_t *M0, uint32_t R0, uint32_t chunk_rows,
+                       const uint32_t *list, uint32_t *dst, uint64_t rows);
 
 void launch_fused(gsi_ctx *c, const FPlan *d_plan, const uint32_t *M0, uint32_t R0, uint32_t *buf0, uint32_t *buf1,
                   uint32_t *loc, uint32_t *out, FStatus *d_status, double alg_bytes);

@@ -51,13 +51,17 @@ struct FusedLds {
     uint32_t wpre[CS / 64];
     uint32_t w[FT / 64];
     uint64_t d[2][FT / 64];
+    uint64_t obase;
 };
 
 // All join levels of one query in one workgroup (see the file comment).
 // FT threads; at most CR rows per table (CR = 4 FT) and CS slots per level.
+// With `ocount` set, the last level reserves its S*k output words from that
+// counter (words of `out`, at most `ocap`) instead of writing at out[0].
 template <uint32_t FT, uint32_t CR, uint32_t CS>
 __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, uint32_t *buf0, uint32_t *buf1,
-                            uint32_t *loc, uint32_t *out, FStatus *st, FusedLds<FT, CR, CS> &L) {
+                            uint32_t *loc, uint32_t *out, FStatus *st, FusedLds<FT, CR, CS> &L,
+                            unsigned long long *ocount = nullptr, uint64_t ocap = 0) {
     static_assert(CR == 4 * FT, "each thread scans four rows");
     static_assert(CS / 64 <= FT, "one thread per bitmap word in the survivor scan");
     uint32_t *s_F = L.F;
@@ -74,6 +78,14 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
     uint32_t mloc = FSTATUS_IN_FIRST;  // where M lives
     uint32_t *bufs[2] = {buf0, buf1};
     uint32_t next = 0;
+    if (R0 > cap_rows) {  // the first table does not fit
+        if (tid == 0) {
+            st->level = 1;
+            st->rows = R0;
+            st->mloc = mloc;
+        }
+        return;
+    }
 
     for (uint32_t j = 1; j < k; j++) {
         const uint32_t ne = plan->lv_ne[j], ef = plan->lv_first[j], e0 = plan->lv_e0[j];
@@ -114,7 +126,9 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
             if (tid == 0) s_F[R] = tot;
             __syncthreads();
         }
-        const uint32_t gba = s_F[R];
+        // values every thread reads from LDS are made wave-uniform, so that
+        // the exits below are uniform branches
+        const uint32_t gba = __builtin_amdgcn_readfirstlane(s_F[R]);
         if (tid == 0) st->lv_gba[j] = gba;
         if (gba > cap_slots) {
             if (tid == 0) {
@@ -159,6 +173,7 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
         {
             uint32_t c = tid < nw ? (uint32_t)__popcll(s_bits[tid]) : 0u;
             uint32_t ex = wg_exclusive_sum<FT>(c, s_w, &S);
+            S = __builtin_amdgcn_readfirstlane(S);
             if (tid < nw) s_wpre[tid] = ex;
             __syncthreads();
         }
@@ -177,6 +192,29 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
                 st->mloc = mloc;
             }
             return;
+        }
+
+        // a chunk reserves its output rows
+        if (final_level && ocount && !plan->count_only) {
+            if (tid == 0) {
+                const unsigned long long need = (unsigned long long)S * k;
+                const unsigned long long b = atomicAdd(ocount, need);
+                L.obase = (b + need <= ocap) ? (uint64_t)b : ~0ull;
+            }
+            __syncthreads();
+            const uint64_t lb = L.obase;
+            const uint64_t b = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(lb >> 32)) << 32) |
+                               __builtin_amdgcn_readfirstlane((uint32_t)lb);
+            if (b == ~0ull) {
+                if (tid == 0) {
+                    st->level = j;
+                    st->rows = R;
+                    st->mloc = mloc;
+                }
+                return;
+            }
+            out += b;
+            if (tid == 0) st->out_base = b;
         }
 
         // link: (m_i, x) at its position; the last level writes rows in
@@ -263,7 +301,7 @@ __global__ __launch_bounds__(FT) void k_fused_batch(const uint8_t *plans, const 
     for (;;) {
         if (threadIdx.x == 0) s_q = atomicAdd(counter, 1u);
         __syncthreads();
-        const uint32_t qi = s_q;
+        const uint32_t qi = __builtin_amdgcn_readfirstlane(s_q);
         __syncthreads();
         if (qi >= nitems) break;
         const FBatchItem it = items[qi];
@@ -281,6 +319,188 @@ static void launch_batch_t(gsi_ctx *c, uint32_t grid, const uint8_t *plans, cons
     launch(c, FT == 64 ? "k_fused_batch<64>" : FT == 256 ? "k_fused_batch<256>" : "k_fused_batch<1024>", bytes,
            k_fused_batch<FT, CR, CS>, grid, FT, plans, items, nitems, M0all, scratch, slot_words, kmax, outall, sts,
            counter);
+}
+
+// Chunks of one query (see launch_fused_chunks).  Every workgroup leaves
+// once the chunk counter passes nchunks or the abort flag is set.
+template <uint32_t FT, uint32_t CR, uint32_t CS>
+__global__ __launch_bounds__(FT) void k_fused_chunks(const FPlan *plan, const uint32_t *M0, uint32_t R0,
+                                                    uint32_t chunk_rows, uint32_t nchunks, uint32_t *scratch,
+                                                    uint64_t slot_words, uint32_t k, uint32_t *staging,
+                                                    uint64_t staging_words, unsigned long long *ocount,
+                                                    uint32_t *abort, uint32_t max_fail, FStatus *sts,
+                                                    uint32_t *counter) {
+    __shared__ FusedLds<FT, CR, CS> L;
+    __shared__ uint32_t s_q;
+    uint32_t *slot = scratch + (uint64_t)blockIdx.x * slot_words;
+    uint32_t *buf0 = slot, *buf1 = slot + (uint64_t)CR * k, *loc = slot + 2ull * CR * k;
+    // The only thread-0 block of the loop is at its head, and the chunk index
+    // is made wave-uniform: the loop then stays one uniform loop around the
+    // barriers (a thread-0 block after the last barrier let the compiler
+    // split it so that the other lanes of wave 0 spun without thread 0).
+    uint32_t prev = 0xFFFFFFFFu;  // chunk run last (read by thread 0 only)
+    for (;;) {
+        if (threadIdx.x == 0) {
+            // too many chunks that do not fit: leave the rest to the caller
+            if (prev != 0xFFFFFFFFu && !sts[prev].done && atomicAdd(abort + 1, 1u) + 1 > max_fail)
+                atomicOr(abort, 1u);
+            s_q = __atomic_load_n(abort, __ATOMIC_RELAXED) ? nchunks : atomicAdd(counter, 1u);
+        }
+        __syncthreads();
+        const uint32_t qi = __builtin_amdgcn_readfirstlane(s_q);
+        __syncthreads();
+        if (qi >= nchunks) break;
+        const uint32_t first = qi * chunk_rows;
+        const uint32_t rows = min(chunk_rows, R0 - first);
+        fused_query<FT, CR, CS>(plan, M0 + first, rows, buf0, buf1, loc, staging, sts + qi, L, ocount,
+                                staging_words);
+        prev = qi;
+        __syncthreads();
+    }
+}
+
+// Totals of a chunked run and each chunk's first output row (exclusive
+// prefix of the counts, chunk order).  One 1024-thread workgroup.
+__global__ __launch_bounds__(1024) void k_chunk_summary(const FStatus *sts, uint32_t n, uint32_t nlevels,
+                                                       uint64_t *offs, uint32_t *done, FChunkSummary *sum) {
+    __shared__ uint64_t s_w[16];
+    __shared__ uint64_t s_d[3][16];
+    __shared__ uint32_t s_nd[16], s_lv[16];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+    uint64_t carry = 0, ds = 0, dx = 0;
+    uint32_t notdone = 0, lv = 0;
+    for (uint32_t base = 0; base < n; base += 1024) {
+        const uint32_t i = base + tid;
+        uint64_t c = 0;
+        if (i < n) {
+            const FStatus &st = sts[i];
+            c = st.done ? st.count : 0ull;
+            done[i] = st.done ? 1u : 0u;
+            notdone += st.done ? 0u : 1u;
+            if (st.done) {
+                ds += st.digest[0];
+                dx ^= st.digest[1];
+                lv = max(lv, (uint32_t)st.levels);
+            }
+        }
+        const uint64_t inc = wave_inclusive_sum(c);
+        if (lane == 63) s_w[w] = inc;
+        __syncthreads();
+        uint64_t off = carry, tot = 0;
+        for (uint32_t q = 0; q < 16; q++) {
+            off += q < w ? s_w[q] : 0ull;
+            tot += s_w[q];
+        }
+        if (i < n) offs[i] = off + inc - c;
+        carry += tot;
+        __syncthreads();
+    }
+    ds = wave_sum(ds);
+    dx = wave_xor(dx);
+    notdone = wave_sum(notdone);
+    for (uint32_t o = 32; o; o >>= 1) lv = max(lv, (uint32_t)__shfl_xor((int)lv, (int)o));
+    if (lane == 0) {
+        s_d[0][w] = ds;
+        s_d[1][w] = dx;
+        s_nd[w] = notdone;
+        s_lv[w] = lv;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t a = 0, b = 0;
+        uint32_t nd = 0, l = 0;
+        for (uint32_t q = 0; q < 16; q++) {
+            a += s_d[0][q];
+            b ^= s_d[1][q];
+            nd += s_nd[q];
+            l = max(l, s_lv[q]);
+        }
+        offs[n] = carry;
+        sum->all_done = nd == 0 ? 1u : 0u;
+        sum->count = carry;
+        sum->digest[0] = a;
+        sum->digest[1] = b;
+        sum->levels = l;
+    }
+    // per-level sums: wave w takes levels w, w + 16
+    for (uint32_t j = w; j < nlevels; j += 16) {
+        uint64_t r = 0, gb = 0, sv = 0;
+        for (uint32_t i = lane; i < n; i += 64) {
+            const bool d = sts[i].done != 0;
+            r += d ? sts[i].lv_rows[j] : 0ull;
+            gb += d ? sts[i].lv_gba[j] : 0ull;
+            sv += d ? sts[i].lv_surv[j] : 0ull;
+        }
+        r = wave_sum(r);
+        gb = wave_sum(gb);
+        sv = wave_sum(sv);
+        if (lane == 0) {
+            sum->lv_rows[j] = r;
+            sum->lv_gba[j] = gb;
+            sum->lv_surv[j] = sv;
+        }
+    }
+}
+
+// Rows of every finished chunk into `out`, in chunk order.  One workgroup
+// per chunk.
+__global__ __launch_bounds__(256) void k_chunk_gather(const FStatus *sts, const uint64_t *offs,
+                                                     const uint32_t *staging, uint32_t k, uint32_t *out) {
+    const FStatus &st = sts[blockIdx.x];
+    if (!st.done) return;
+    const uint64_t words = st.count * k;
+    if (words == 0) return;
+    const uint32_t *src = staging + st.out_base;
+    uint32_t *dst = out + offs[blockIdx.x] * k;
+    for (uint64_t t = threadIdx.x; t < words; t += 256) dst[t] = src[t];
+}
+
+template <uint32_t FT>
+static void launch_chunks_t(gsi_ctx *c, uint32_t grid, const FPlan *plan, const uint32_t *M0, uint32_t R0,
+                            uint32_t chunk_rows, uint32_t nchunks, uint32_t *scratch, uint64_t slot_words, uint32_t k,
+                            uint32_t *staging, uint64_t staging_words, unsigned long long *ocount, uint32_t *abort,
+                            uint32_t max_fail, FStatus *sts, uint32_t *counter, double bytes) {
+    constexpr uint32_t CR = 4 * FT, CS = 16 * FT;
+    launch(c, "k_fused_chunks", bytes, k_fused_chunks<FT, CR, CS>, grid, FT, plan, M0, R0, chunk_rows, nchunks,
+           scratch, slot_words, k, staging, staging_words, ocount, abort, max_fail, sts, counter);
+}
+
+void launch_fused_chunks(gsi_ctx *c, const FTier &t, uint32_t grid, const FPlan *plan, const uint32_t *M0,
+                         uint32_t R0, uint32_t chunk_rows, uint32_t nchunks, uint32_t *scratch, uint64_t slot_words,
+                         uint32_t k, uint32_t *staging, uint64_t staging_words, unsigned long long *ocount,
+                         uint32_t *abort, uint32_t max_fail, FStatus *sts, uint32_t *counter, uint64_t *offs,
+                         uint32_t *done, FChunkSummary *sum) {
+    if (t.threads == 64)
+        launch_chunks_t<64>(c, grid, plan, M0, R0, chunk_rows, nchunks, scratch, slot_words, k, staging,
+                            staging_words, ocount, abort, max_fail, sts, counter, 0.0);
+    else if (t.threads == 256)
+        launch_chunks_t<256>(c, grid, plan, M0, R0, chunk_rows, nchunks, scratch, slot_words, k, staging,
+                             staging_words, ocount, abort, max_fail, sts, counter, 0.0);
+    else
+        launch_chunks_t<1024>(c, grid, plan, M0, R0, chunk_rows, nchunks, scratch, slot_words, k, staging,
+                              staging_words, ocount, abort, max_fail, sts, counter, 0.0);
+    launch(c, "k_chunk_summary", (double)nchunks * sizeof(FStatus), k_chunk_summary, 1, 1024, (const FStatus *)sts,
+           nchunks, k, offs, done, sum);
+}
+
+void launch_chunk_gather(gsi_ctx *c, uint32_t nchunks, const FStatus *sts, const uint64_t *offs,
+                         const uint32_t *staging, uint32_t k, uint32_t *out, uint64_t words) {
+    launch(c, "k_chunk_gather", 8.0 * words, k_chunk_gather, nchunks, 256, sts, offs, staging, k, out);
+}
+
+// Root rows of the given chunks, concatenated: workgroup i copies chunk
+// list[2i] to position list[2i+1].
+__global__ __launch_bounds__(256) void k_take_roots(const uint32_t *M0, uint32_t R0, uint32_t chunk_rows,
+                                                   const uint32_t *list, uint32_t *dst) {
+    const uint32_t ch = list[2 * blockIdx.x], at = list[2 * blockIdx.x + 1];
+    const uint32_t first = ch * chunk_rows;
+    const uint32_t rows = min(chunk_rows, R0 - first);
+    for (uint32_t t = threadIdx.x; t < rows; t += 256) dst[at + t] = M0[first + t];
+}
+
+void launch_take_roots(gsi_ctx *c, uint32_t nlist, const uint32_t *M0, uint32_t R0, uint32_t chunk_rows,
+                       const uint32_t *list, uint32_t *dst, uint64_t rows) {
+    launch(c, "k_take_roots", 8.0 * rows, k_take_roots, nlist, 256, M0, R0, chunk_rows, list, dst);
 }
 
 FTier fused_tier(uint32_t threads) {

@@ -189,9 +189,82 @@ static void launch_filter(gsi_ctx *c, gsi_graph *g, const FilterArgs &fa, uint64
     launch(c, "k_filter_counts", 4.0 * nb * fa.k, k_filter_counts, fa.k, QT, (const uint32_t *)part, nb, fa, counts);
 }
 
-// Batched filter: the query vertices of many queries, 32 per pass.  Passes
-// take query vertices sorted by label, so a pass usually covers one or two
-// labels and lanes of other labels read nothing past word 0.
+// Batched filter: the query vertices of many queries, 32 per pass, all
+// passes in one launch (blockIdx.y = pass; each workgroup copies its pass's
+// query signatures into LDS).  Passes take query vertices sorted by label,
+// so a pass usually covers one or two labels and lanes of other labels read
+// nothing past word 0, which stays in the caches across passes.
+__global__ __launch_bounds__(QT) void k_filter_multi(const uint32_t *sig, uint32_t n, uint64_t nwords,
+                                                    const FilterArgs *passes, uint64_t *bits, uint32_t *part) {
+    __shared__ FilterArgs fa;
+    __shared__ uint32_t s_cnt[GSI_MAX_K];
+    {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(passes + blockIdx.y);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(&fa);
+        for (uint32_t t = threadIdx.x; t < sizeof(FilterArgs) / 4; t += QT) dst[t] = src[t];
+    }
+    if (threadIdx.x < GSI_MAX_K) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t K = fa.k;
+    const uint32_t need = fa.word_mask;
+    const uint32_t lane = lane_id();
+    const uint64_t ntiles = ((uint64_t)n + QT - 1) / QT;
+    // workgroups stride over the 256-vertex tiles of the table
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t v = tile * QT + threadIdx.x;
+        const bool valid = v < n;
+        const uint64_t wave_first = tile * QT + (threadIdx.x & ~63u);
+        const uint32_t w0 = valid ? sig[v] : NONE32;
+        uint32_t ok = 0;
+        for (uint32_t u = 0; u < K; u++) ok |= (valid && w0 == fa.q[u][0]) ? (1u << u) : 0u;
+        uint32_t wv[GSI_SIG_WORDS];
+#pragma unroll
+        for (int i = 1; i < GSI_SIG_WORDS; i++)
+            wv[i] = (((need >> i) & 1u) && ok) ? sig[(uint64_t)i * n + v] : 0xFFFFFFFFu;
+        if (ok && need) {
+            for (uint32_t u = 0; u < K; u++) {
+                if (!((ok >> u) & 1u)) continue;
+                bool good = true;
+#pragma unroll
+                for (int i = 1; i < GSI_SIG_WORDS; i++) {
+                    const uint32_t qw = fa.q[u][i];
+                    good = good && ((wv[i] & qw) == qw);
+                }
+                if (!good) ok &= ~(1u << u);
+            }
+        }
+        for (uint32_t u = 0; u < K; u++) {
+            const uint64_t mask = __ballot((ok >> u) & 1u);
+            if (lane == 0 && wave_first < n) {
+                bits[(uint64_t)fa.dst[u] * nwords + (wave_first >> 6)] = mask;
+                if (mask) atomicAdd(&s_cnt[u], (uint32_t)__popcll(mask));
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < GSI_MAX_K)
+        part[((uint64_t)blockIdx.y * gridDim.x + blockIdx.x) * GSI_MAX_K + threadIdx.x] = s_cnt[threadIdx.x];
+}
+
+// counts of every pass: workgroup (u, pass) sums u's partial counts
+__global__ __launch_bounds__(QT) void k_filter_counts_multi(const uint32_t *part, uint32_t nb,
+                                                           const FilterArgs *passes, uint32_t *counts) {
+    __shared__ uint32_t s_w[QT / 64];
+    const uint32_t u = blockIdx.x, pass = blockIdx.y;
+    const FilterArgs &fa = passes[pass];
+    if (u >= fa.k) return;
+    uint32_t sum = 0;
+    for (uint32_t b = threadIdx.x; b < nb; b += QT) sum += part[((uint64_t)pass * nb + b) * GSI_MAX_K + u];
+    sum = wave_sum(sum);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int q = 0; q < QT / 64; q++) t += s_w[q];
+        counts[fa.dst[u]] = t;
+    }
+}
+
 void run_filter_many(gsi_graph *g, const std::vector<const HostQuery *> &qs, const std::vector<uint32_t> &qbase,
                      uint64_t *bits, uint32_t *counts) {
     gsi_ctx *c = g->ctx;
@@ -201,15 +274,19 @@ void run_filter_many(gsi_graph *g, const std::vector<const HostQuery *> &qs, con
     std::vector<QV> all;
     for (size_t i = 0; i < qs.size(); i++)
         for (uint32_t u = 0; u < qs[i]->k; u++) all.push_back({qs[i]->vl[u], (uint32_t)i, u});
+    if (all.empty()) return;
     std::stable_sort(all.begin(), all.end(), [](const QV &a, const QV &b) { return a.label < b.label; });
-    Scratch s(c);
-    uint32_t *part = s.get<uint32_t>((uint64_t)nblocks(g->n) * GSI_MAX_K, "filter partial counts");
     std::vector<FilterArgs> one(qs.size());
     for (size_t i = 0; i < qs.size(); i++) query_signatures(*qs[i], one[i]);
-    for (size_t base = 0; base < all.size(); base += GSI_MAX_K) {
-        FilterArgs fa;
+    const uint32_t npass = (uint32_t)((all.size() + GSI_MAX_K - 1) / GSI_MAX_K);
+    if (npass > 65535) fail(GSI_E_CAPACITY, "too many query vertices in one batch (%zu)", all.size());
+    std::vector<FilterArgs> passes(npass);
+    uint32_t words = 0;
+    for (uint32_t p = 0; p < npass; p++) {
+        FilterArgs &fa = passes[p];
         memset(&fa, 0, sizeof(fa));
-        uint32_t k = (uint32_t)std::min<size_t>(GSI_MAX_K, all.size() - base);
+        const size_t base = (size_t)p * GSI_MAX_K;
+        const uint32_t k = (uint32_t)std::min<size_t>(GSI_MAX_K, all.size() - base);
         fa.k = k;
         for (uint32_t t = 0; t < k; t++) {
             const QV &x = all[base + t];
@@ -218,8 +295,22 @@ void run_filter_many(gsi_graph *g, const std::vector<const HostQuery *> &qs, con
             for (int i = 1; i < GSI_SIG_WORDS; i++)
                 if (fa.q[t][i]) fa.word_mask |= 1u << i;
         }
-        launch_filter(c, g, fa, bits, counts, part);
+        words += 1 + __builtin_popcount(fa.word_mask);
     }
+    Scratch s(c);
+    const uint64_t nwords = ((uint64_t)g->n + 63) / 64;
+    // workgroups per pass: enough to fill the chip when passes are few
+    const uint32_t nb = std::min<uint32_t>(nblocks(g->n), std::max<uint32_t>(32, 8192 / npass));
+    FilterArgs *dp = reinterpret_cast<FilterArgs *>(s.get<uint32_t>((uint64_t)npass * sizeof(FilterArgs) / 4,
+                                                                    "filter passes"));
+    uint32_t *part = s.get<uint32_t>((uint64_t)npass * nb * GSI_MAX_K, "filter partial counts");
+    GSI_HIP(hipMemcpyAsync(dp, passes.data(), sizeof(FilterArgs) * npass, hipMemcpyHostToDevice, c->stream));
+    const double bytes = 4.0 * g->n * words + (double)all.size() * nwords * 8;
+    launch(c, "k_filter", bytes, k_filter_multi, dim3(nb, npass), QT, (const uint32_t *)g->sig, g->n, nwords,
+           (const FilterArgs *)dp, bits, part);
+    launch(c, "k_filter_counts", 4.0 * nb * all.size(), k_filter_counts_multi, dim3(GSI_MAX_K, npass), QT,
+           (const uint32_t *)part, nb, (const FilterArgs *)dp, counts);
+    sync(c);  // `passes` is read by the copy above
 }
 
 static void filter_impl(gsi_graph *g, const HostQuery &q, bool label_only, uint64_t *bits, uint32_t *counts) {
@@ -632,7 +723,8 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     auto t0 = std::chrono::steady_clock::now();
     const uint32_t k = q.k;
     const uint32_t flags = opt ? opt->flags : 0u;
-    if (flags & ~(GSI_COUNT_ONLY | GSI_FILTER_LABEL_ONLY | GSI_NO_FUSED)) fail(GSI_E_INVALID, "unknown query flag");
+    if (flags & ~(GSI_COUNT_ONLY | GSI_FILTER_LABEL_ONLY | GSI_NO_FUSED | GSI_NO_CHUNKS))
+        fail(GSI_E_INVALID, "unknown query flag");
     const bool count_only = (flags & GSI_COUNT_ONLY) != 0;
     const uint64_t max_rows = opt ? opt->max_rows : 0;
 
@@ -773,52 +865,214 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         return finish();
     }
 
-    // Fused small-table levels: one workgroup runs levels while they fit,
-    // then the per-level kernels continue from where it stopped.
-    uint32_t jstart = 1;
+    // Fused plan (device copy of the levels' linking edges) for the fused
+    // kernels, written into the pinned staging buffer and uploaded.
     Scratch fs(c);
-    {
+    auto fused_plan = [&](uint32_t cap_rows, uint32_t cap_slots, FPlan **host) -> FPlan * {
+        uint32_t n_edges = 0;
+        for (uint32_t j = 1; j < k; j++)
+            for (uint32_t i = 0; i < j; i++)
+                for (auto &p : q.adj[order[j]]) n_edges += p.first == order[i];
+        const size_t pb = fplan_bytes(n_edges);
+        if (pb > 56 * 1024) fail(GSI_E_INTERNAL, "query plan too large for the staging buffer");
+        FPlan *hp = reinterpret_cast<FPlan *>(reinterpret_cast<char *>(c->pinned) + 8192);
+        memset(hp, 0, pb);
+        hp->k = k;
+        hp->count_only = count_only ? 1u : 0u;
+        hp->cap_rows = cap_rows;
+        hp->cap_slots = cap_slots;
+        for (uint32_t v = 0; v < k; v++) hp->qcol[v] = col[v];
+        uint32_t ei = 0;
+        for (uint32_t j = 1; j < k; j++) {
+            hp->lv_first[j] = ei;
+            hp->Cu[j] = bits + (uint64_t)order[j] * nwords;
+            uint32_t ne = 0;
+            for (uint32_t i = 0; i < j; i++)
+                for (auto &p : q.adj[order[j]])
+                    if (p.first == order[i]) {
+                        const uint32_t l = p.second;
+                        FEdge &fe = hp->edges[ei + ne];
+                        fe.gl = g->gl + g->group_base[l] * GROUP_WORDS;
+                        fe.ci = g->ci + g->ci_base[l];
+                        fe.G = g->G[l];
+                        fe.H = g->H[l];
+                        fe.col = i;
+                        if (order[i] == e0src[j]) hp->lv_e0[j] = ne;
+                        ne++;
+                    }
+            hp->lv_ne[j] = ne;
+            st.n_link[j] = ne;
+            ei += ne;
+        }
+        FPlan *dplan = reinterpret_cast<FPlan *>(fs.get<uint8_t>(pb, "fused plan"));
+        GSI_HIP(hipMemcpyAsync(dplan, hp, pb, hipMemcpyHostToDevice, c->stream));
+        *host = hp;
+        return dplan;
+    };
+    // algorithmic bytes of a fused launch, from the per-level sizes it met
+    auto fused_bytes = [&](const FPlan *hp, uint32_t last, const uint64_t *rows, const uint64_t *gbas,
+                           const uint64_t *survs) {
+        double b = 0;
+        for (uint32_t j = 1; j <= last && j < k; j++) {
+            double Rj = (double)rows[j], Gj = (double)gbas[j], Sj = (double)survs[j];
+            double ne = hp->lv_ne[j];
+            b += Rj * (4.0 * ne + 128.0 * ne + 8.0 * ne + 4.0 * j) + 4.0 * Gj + Sj * (4.0 + 4.0 * j + 4.0 * (j + 1));
+        }
+        return b;
+    };
+
+    // Root chunks: a persistent launch runs all levels of small groups of
+    // root rows, one chunk per workgroup at a time, over the whole chip.
+    // Chunks that do not fit are finished by the per-level kernels below on
+    // their roots only; both parts are merged at the end.
+    struct ChunkPart {
+        bool active = false, merged = false;
+        uint32_t n = 0;
+        uint64_t count = 0, digest[2] = {0, 0};
+        const FStatus *sts = nullptr;
+        const uint64_t *offs = nullptr;
+        const uint32_t *staging = nullptr;
+        uint64_t rows[GSI_MAX_K] = {0}, gba[GSI_MAX_K] = {0}, surv[GSI_MAX_K] = {0};
+        uint32_t levels = 0;
+    } cp;
+    Scratch cs(c);
+    // adds the chunk part to the result; `front` (if any) already has room
+    // for the chunk rows before the per-level rows
+    auto merge_chunks = [&](uint32_t *front) {
+        if (!cp.active || cp.merged) return;
+        cp.merged = true;
+        if (!count_only && cp.count) {
+            if (!front) {
+                front = persist<uint32_t>(c, cp.count * k, "result rows");
+                res->rows = front;
+            }
+            launch_chunk_gather(c, cp.n, cp.sts, cp.offs, cp.staging, k, front, cp.count * k);
+        }
+        res->count += cp.count;
+        res->digest[0] += cp.digest[0];
+        res->digest[1] ^= cp.digest[1];
+        for (uint32_t j = 1; j < k; j++) {
+            st.rows[j] += cp.rows[j];
+            st.gba[j] += cp.gba[j];
+            st.survivors[j] += cp.surv[j];
+        }
+        st.levels = std::max(st.levels, cp.levels);
+        sync(c);
+    };
+    auto done = [&]() -> gsi_result * {
+        merge_chunks(nullptr);
+        return finish();
+    };
+
+    uint32_t jstart = 1;
+    const uint32_t chunk_min = (opt && opt->chunk_min_rows) ? opt->chunk_min_rows : CHUNK_MIN_ROWS;
+    if (!(flags & GSI_NO_FUSED) && !(flags & GSI_NO_CHUNKS) && R >= chunk_min) {
+        const FTier t = fused_tier(256);
+        const uint64_t slot_words = 2ull * t.cap_rows * k + 2ull * (k - 1) * t.cap_rows;
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || ncu < 1)
+            ncu = 1;
+        const uint64_t room = c->arena.largest_free() / 4;
+        uint64_t grid = std::min<uint64_t>((uint64_t)t.blocks_per_cu * ncu, room / (slot_words * 4));
+        uint64_t target = std::min<uint64_t>(std::max<uint64_t>(4 * grid, 1), CHUNK_MAX);
+        if (opt && opt->chunk_rows) target = (R + opt->chunk_rows - 1) / opt->chunk_rows;
+        // a chunk's first table must fit the workgroup's row capacity
+        const uint32_t chunk_rows =
+            (uint32_t)std::min<uint64_t>(t.cap_rows, std::max<uint64_t>(1, (R + target - 1) / target));
+        const uint32_t nchunks = (uint32_t)((R + chunk_rows - 1) / chunk_rows);
+        grid = std::min<uint64_t>(grid, nchunks);
+        const uint64_t ocap = count_only ? 0
+                                         : std::min<uint64_t>((uint64_t)nchunks * t.cap_slots * k,
+                                                              c->arena.largest_free() / 32);
+        if (grid >= 1 && nchunks <= CHUNK_MAX && (count_only || ocap >= 1024)) {
+            FPlan *hp;
+            FPlan *dplan = fused_plan(0xFFFFFFFFu, 0xFFFFFFFFu, &hp);
+            uint32_t *slots = cs.get<uint32_t>(slot_words * grid, "chunk tables");
+            FStatus *sts = reinterpret_cast<FStatus *>(cs.get<uint64_t>((uint64_t)nchunks * sizeof(FStatus) / 8,
+                                                                        "chunk status"));
+            uint64_t *offs = cs.get<uint64_t>((uint64_t)nchunks + 1, "chunk offsets");
+            uint32_t *dflags = cs.get<uint32_t>(nchunks, "chunk done flags");
+            uint32_t *ctr = cs.get<uint32_t>(4, "chunk counters");  // counter, abort, failures
+            unsigned long long *ocount =
+                reinterpret_cast<unsigned long long *>(cs.get<uint64_t>(1, "chunk output counter"));
+            FChunkSummary *dsum = reinterpret_cast<FChunkSummary *>(
+                cs.get<uint64_t>(sizeof(FChunkSummary) / 8, "chunk summary"));
+            uint32_t *staging = count_only ? nullptr : cs.get<uint32_t>(ocap, "chunk rows");
+            fill_u64(c, reinterpret_cast<uint64_t *>(sts), 0, (uint64_t)nchunks * sizeof(FStatus) / 8);
+            fill_u32(c, ctr, 0, 4);
+            fill_u64(c, reinterpret_cast<uint64_t *>(ocount), 0, 1);
+            const uint32_t max_fail = std::max<uint32_t>(16, nchunks / 8);
+            const size_t ri = c->recs.size();
+            launch_fused_chunks(c, t, (uint32_t)grid, dplan, M, (uint32_t)R, chunk_rows, nchunks, slots, slot_words,
+                                k, staging, ocap, ocount, ctr + 1, max_fail, sts, ctr, offs, dflags, dsum);
+            FChunkSummary *hsum = reinterpret_cast<FChunkSummary *>(reinterpret_cast<char *>(c->pinned) + 4096);
+            GSI_HIP(hipMemcpyAsync(hsum, dsum, sizeof(FChunkSummary), hipMemcpyDeviceToHost, c->stream));
+            sync(c);
+            if ((c->flags & GSI_CTX_PROFILE) && ri < c->recs.size())
+                c->recs[ri].bytes = fused_bytes(hp, (uint32_t)hsum->levels, hsum->lv_rows, hsum->lv_gba,
+                                                hsum->lv_surv);
+            cp.active = true;
+            cp.n = nchunks;
+            cp.count = hsum->count;
+            cp.digest[0] = hsum->digest[0];
+            cp.digest[1] = hsum->digest[1];
+            cp.sts = sts;
+            cp.offs = offs;
+            cp.staging = staging;
+            cp.levels = (uint32_t)hsum->levels;
+            for (uint32_t j = 1; j < k; j++) {
+                cp.rows[j] = hsum->lv_rows[j];
+                cp.gba[j] = hsum->lv_gba[j];
+                cp.surv[j] = hsum->lv_surv[j];
+            }
+            st.chunks = nchunks;
+            if (hsum->all_done) {
+                if (!count_only && cp.count) {
+                    uint32_t *out = persist<uint32_t>(c, cp.count * k, "result rows");
+                    res->rows = out;
+                    merge_chunks(out);
+                } else {
+                    merge_chunks(nullptr);
+                }
+                st.join_ms = ms_since(tj);
+                return finish();
+            }
+            // the roots of the chunks left undone continue level by level
+            std::vector<uint32_t> fl(nchunks);
+            GSI_HIP(hipMemcpyAsync(fl.data(), dflags, 4ull * nchunks, hipMemcpyDeviceToHost, c->stream));
+            sync(c);
+            std::vector<uint32_t> list;
+            uint64_t left = 0;
+            for (uint32_t ch = 0; ch < nchunks; ch++) {
+                if (fl[ch]) continue;
+                list.push_back(ch);
+                list.push_back((uint32_t)left);
+                left += std::min<uint64_t>(chunk_rows, R - (uint64_t)ch * chunk_rows);
+            }
+            st.chunks_left = (uint32_t)(list.size() / 2);
+            uint32_t *dl = cs.get<uint32_t>(list.size(), "chunks left");
+            GSI_HIP(hipMemcpyAsync(dl, list.data(), 4 * list.size(), hipMemcpyHostToDevice, c->stream));
+            Block Mr(c);
+            uint32_t *Mleft = Mr.get<uint32_t>(left, "roots left");
+            launch_take_roots(c, (uint32_t)(list.size() / 2), M, (uint32_t)R, chunk_rows, dl, Mleft, left);
+            sync(c);  // `list` is read by the copy above
+            Mb.reset();
+            Mb.p = Mr.p;
+            Mr.p = nullptr;
+            M = Mleft;
+            R = left;
+        }
+    }
+
+    // Small root sets: one workgroup runs levels while they fit, then the
+    // per-level kernels continue from where it stopped.
+    if (!cp.active) {
         uint32_t cap_rows = FUSED_MAX_ROWS, cap_slots = FUSED_MAX_SLOTS;
         if (opt && opt->fused_max_rows) cap_rows = std::min(cap_rows, opt->fused_max_rows);
         if (opt && opt->fused_max_slots) cap_slots = std::min(cap_slots, opt->fused_max_slots);
         if (!(flags & GSI_NO_FUSED) && R <= cap_rows && cap_slots >= 64) {
-            uint32_t n_edges = 0;
-            for (uint32_t j = 1; j < k; j++)
-                for (uint32_t i = 0; i < j; i++)
-                    for (auto &p : q.adj[order[j]]) n_edges += p.first == order[i];
-            const size_t pb = fplan_bytes(n_edges);
-            if (pb > 56 * 1024) fail(GSI_E_INTERNAL, "query plan too large for the staging buffer");
-            FPlan *hp = reinterpret_cast<FPlan *>(reinterpret_cast<char *>(c->pinned) + 8192);
-            memset(hp, 0, pb);
-            hp->k = k;
-            hp->count_only = count_only ? 1u : 0u;
-            hp->cap_rows = cap_rows;
-            hp->cap_slots = cap_slots;
-            for (uint32_t v = 0; v < k; v++) hp->qcol[v] = col[v];
-            uint32_t ei = 0;
-            for (uint32_t j = 1; j < k; j++) {
-                hp->lv_first[j] = ei;
-                hp->Cu[j] = bits + (uint64_t)order[j] * nwords;
-                uint32_t ne = 0;
-                for (uint32_t i = 0; i < j; i++)
-                    for (auto &p : q.adj[order[j]])
-                        if (p.first == order[i]) {
-                            const uint32_t l = p.second;
-                            FEdge &fe = hp->edges[ei + ne];
-                            fe.gl = g->gl + g->group_base[l] * GROUP_WORDS;
-                            fe.ci = g->ci + g->ci_base[l];
-                            fe.G = g->G[l];
-                            fe.H = g->H[l];
-                            fe.col = i;
-                            if (order[i] == e0src[j]) hp->lv_e0[j] = ne;
-                            ne++;
-                        }
-                hp->lv_ne[j] = ne;
-                st.n_link[j] = ne;
-                ei += ne;
-            }
-            FPlan *dplan = reinterpret_cast<FPlan *>(fs.get<uint8_t>(pb, "fused plan"));
-            GSI_HIP(hipMemcpyAsync(dplan, hp, pb, hipMemcpyHostToDevice, c->stream));
+            FPlan *hp;
+            FPlan *dplan = fused_plan(cap_rows, cap_slots, &hp);
             uint32_t *buf0 = fs.get<uint32_t>((uint64_t)cap_rows * k, "fused table 0");
             uint32_t *buf1 = fs.get<uint32_t>((uint64_t)cap_rows * k, "fused table 1");
             uint32_t *floc = fs.get<uint32_t>(2ull * (k - 1) * cap_rows, "fused lookups");
@@ -830,19 +1084,9 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
             FStatus *hs = reinterpret_cast<FStatus *>(reinterpret_cast<char *>(c->pinned) + 4096);
             GSI_HIP(hipMemcpyAsync(hs, dst, sizeof(FStatus), hipMemcpyDeviceToHost, c->stream));
             sync(c);
-            // algorithmic bytes of the fused launch, from the sizes it met
-            if ((c->flags & GSI_CTX_PROFILE) && !c->recs.empty()) {
-                double b = 0;
-                uint32_t last = hs->done ? (uint32_t)hs->levels : (uint32_t)hs->level;
-                for (uint32_t j = 1; j <= last && j < k; j++) {
-                    double Rj = (double)hs->lv_rows[j], Gj = (double)hs->lv_gba[j], Sj = (double)hs->lv_surv[j];
-                    double ne = hp->lv_ne[j];
-                    b += Rj * (4.0 * ne + 128.0 * ne + 8.0 * ne + 4.0 * j) + 4.0 * Gj +
-                         Sj * (4.0 + 4.0 * j + 4.0 * (j + 1));
-                }
-                c->recs.back().bytes = b;
-            }
             const uint32_t last = hs->done ? (uint32_t)hs->levels : (uint32_t)hs->level;
+            if ((c->flags & GSI_CTX_PROFILE) && !c->recs.empty())
+                c->recs.back().bytes = fused_bytes(hp, last, hs->lv_rows, hs->lv_gba, hs->lv_surv);
             for (uint32_t j = 1; j <= last && j < k; j++) {
                 st.rows[j] = hs->lv_rows[j];
                 st.gba[j] = hs->lv_gba[j];
@@ -922,7 +1166,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         st.levels = j;
         if (gba == 0) {
             st.survivors[j] = 0;
-            return finish();
+            return done();
         }
         a.gba = gba;
         const uint64_t ntiles = (gba + QT - 1) / QT;
@@ -939,15 +1183,18 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         uint64_t S;
         read_scalars(c, dscal + 1, &S, 1);
         st.survivors[j] = S;
-        if (S == 0) return finish();
+        if (S == 0) return done();
         if (max_rows && S > max_rows) fail(GSI_E_CAPACITY, "rows exceed max_rows at level %u", j);
         a.S = S;
         Block Mn(c);
         double lb = (double)S * (4.0 + 4.0 * j) + gba / 8.0 + 8.0 * ntiles;
+        uint32_t *front = nullptr;  // room for the chunk part's rows
         if (final_level) {
             if (!count_only) {
-                a.out = persist<uint32_t>(c, S * k, "result rows");
-                res->rows = a.out;
+                const uint64_t before = (cp.active && !cp.merged) ? cp.count : 0;
+                front = persist<uint32_t>(c, (S + before) * k, "result rows");
+                a.out = front + before * k;
+                res->rows = front;
                 lb += 4.0 * k * S;
             }
             a.dig_part = ls.get<uint64_t>(2 * ntiles, "digest partials");
@@ -960,10 +1207,11 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
             reduce_pairs(c, a.dig_part, ntiles, dscal);
             uint64_t dg[2];
             read_scalars(c, dscal, dg, 2);
-            res->rows = a.out;
+            res->rows = count_only ? nullptr : front;
             res->count = S;
             res->digest[0] = dg[0];
             res->digest[1] = dg[1];
+            merge_chunks(front);
             st.join_ms = ms_since(tj);
             return finish();
         }
@@ -974,7 +1222,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         M = a.Mn;
         R = S;
     }
-    return finish();
+    return done();
 }
 
 }  // namespace gsi

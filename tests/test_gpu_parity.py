@@ -223,8 +223,52 @@ def test_paper_example_join_numbers(ctx, golden_dir):
     dg.free()
 
 
-FUSED_MODES = [dict(), dict(flags=4), dict(fused_max_rows=64, fused_max_slots=128),
-               dict(fused_max_rows=300, fused_max_slots=64), dict(fused_max_rows=8, fused_max_slots=4096)]
+NO_CHUNKS = 0x10
+FUSED_MODES = [dict(), dict(flags=4), dict(flags=NO_CHUNKS),
+               dict(flags=NO_CHUNKS, fused_max_rows=64, fused_max_slots=128),
+               dict(flags=NO_CHUNKS, fused_max_rows=300, fused_max_slots=64),
+               dict(flags=NO_CHUNKS, fused_max_rows=8, fused_max_slots=4096),
+               dict(chunk_min_rows=1), dict(chunk_min_rows=1, chunk_rows=1), dict(chunk_min_rows=1, chunk_rows=7)]
+
+
+def test_root_chunks_partly_left_to_the_per_level_kernels(ctx):
+    """Root chunks that cannot hold a level (roots in a 40-clique) finish
+    with the per-level kernels while the others (roots on a long cycle)
+    finish in their chunks; the merged result is the oracle's."""
+    import paper_1906_03420_amd as gsi
+    n_cyc, n_cl = 200, 40
+    src = list(range(n_cyc))
+    dst = [(i + 1) % n_cyc for i in range(n_cyc)]
+    for a in range(n_cl):
+        for b in range(a + 1, n_cl):
+            src.append(n_cyc + a)
+            dst.append(n_cyc + b)
+    n = n_cyc + n_cl
+    g = w.make_graph(n, np.zeros(n, np.uint32), list(zip(src, dst)), np.zeros(len(src), np.uint32))
+    q = w.path_query(4)
+    og = oracle.OracleGraph(g)
+    want = og.match(q, threads=4, tuples=True)
+    assert want.count == 2 * n_cyc + n_cl * (n_cl - 1) * (n_cl - 2) * (n_cl - 3)
+    dg = ctx.load(g)
+    for mode in (dict(chunk_rows=1), dict(chunk_rows=3), dict()):
+        print("chunk mode", mode, flush=True)
+        res = dg.query(q, **mode)
+        stt = res.stats()
+        print("chunks", stt["chunks"], "left", stt["chunks_left"], flush=True)
+        assert stt["chunks"] > 0
+        if mode:
+            assert 0 < stt["chunks_left"] < stt["chunks"]
+        assert res.count == want.count and res.digest == want.digest
+        np.testing.assert_array_equal(res.sorted_rows(), want.tuples)
+        ref = dg.query(q, flags=gsi.GSI_NO_FUSED)
+        assert (stt["rows"], stt["gba"], stt["survivors"]) == (ref.stats()["rows"], ref.stats()["gba"],
+                                                               ref.stats()["survivors"])
+        ref.free()
+        res.free()
+        co = dg.query(q, flags=gsi.GSI_COUNT_ONLY, **mode)
+        assert (co.count, co.digest) == (want.count, want.digest)
+        co.free()
+    dg.free()
 
 
 @pytest.mark.parametrize("seed", range(10))

@@ -177,7 +177,7 @@ typedef struct {
     uint32_t fused_max_slots;  /* 0 = default (16384); test only: a lower |GBA|
                                   capacity of the fused workgroup */
     uint32_t chunk_rows;       /* 0 = automatic; else root rows per chunk */
-    uint32_t chunk_min_rows;   /* 0 = default (64); root chunks are used when
+    uint32_t chunk_min_rows;   /* 0 = default (4097); root chunks are used when
                                   |C(u_first)| is at least this */
 } gsi_query_options;
 
@@ -194,16 +194,16 @@ typedef struct {
  *      survivor into M' (Prealloc-Combine, one join pass);
  *   4. the last level writes rows in query-vertex order (or only counts) and
  *      the order-independent digest.
- * Rows of M are independent at every level, so step 3 first runs on root
- * chunks: small groups of rows of M = C(u_first), each taken by one
- * 256-thread workgroup of a persistent launch that runs all levels of its
- * chunk (tables of up to 1024 rows and 4096 |GBA| slots per level, with F,
- * the keep bits and the survivor prefix sums in LDS).  The roots of chunks
- * that do not fit continue with the per-level kernels; the rows of both
- * parts are concatenated (chunk rows first, in root order).  Below 64 roots
- * one fused workgroup runs the levels while the tables stay small (4096 rows,
- * 16384 slots) and the per-level kernels continue from where it stopped.
- * Every route gives the same rows, count and digest.
+ * Up to 4096 roots one fused workgroup runs the levels while the tables stay
+ * small (4096 rows and 16384 |GBA| slots per level, with F, the keep bits and
+ * the survivor prefix sums in LDS) and the per-level kernels continue from
+ * the first level that does not fit.  Above that, rows of M being
+ * independent at every level, step 3 first runs on root chunks: small groups
+ * of rows of M = C(u_first), each taken by one 256-thread workgroup of a
+ * persistent launch that runs all levels of its chunk (1024 rows and 4096
+ * slots per level).  The roots of chunks that do not fit continue with the
+ * per-level kernels; the rows of both parts are concatenated (chunk rows
+ * first, in root order).  Every route gives the same rows, count and digest.
  * q_vertex_labels[k]; q_src/q_dst/q_edge_labels[q_edges] (host).
  * Errors: GSI_E_INVALID for k == 0 or k > GSI_MAX_K, an endpoint >= k, a
  * self-loop, a repeated pair, a disconnected Q or a bad option; GSI_E_NOMEM

@@ -8,7 +8,7 @@ namespace gsi {
 constexpr uint32_t FUSED_MAX_ROWS = 4096;    // rows of any table the workgroup holds
 constexpr uint32_t FUSED_MAX_SLOTS = 16384;  // |GBA| of any level it joins
 constexpr uint32_t FSTATUS_IN_FIRST = 2;     // M is still the first table
-constexpr uint32_t CHUNK_MIN_ROWS = 64;      // root chunks from this many roots on
+constexpr uint32_t CHUNK_MIN_ROWS = FUSED_MAX_ROWS + 1;  // root chunks above one workgroup's rows
 constexpr uint32_t CHUNK_MAX = 16384;        // chunks of one launch
 
 struct FEdge {            // one linking edge of a level

@@ -251,12 +251,13 @@ def test_root_chunks_partly_left_to_the_per_level_kernels(ctx):
     assert want.count == 2 * n_cyc + n_cl * (n_cl - 1) * (n_cl - 2) * (n_cl - 3)
     dg = ctx.load(g)
     for mode in (dict(chunk_rows=1), dict(chunk_rows=3), dict()):
+        mode = dict(mode, chunk_min_rows=1)
         print("chunk mode", mode, flush=True)
         res = dg.query(q, **mode)
         stt = res.stats()
         print("chunks", stt["chunks"], "left", stt["chunks_left"], flush=True)
         assert stt["chunks"] > 0
-        if mode:
+        if "chunk_rows" in mode:
             assert 0 < stt["chunks_left"] < stt["chunks"]
         assert res.count == want.count and res.digest == want.digest
         np.testing.assert_array_equal(res.sorted_rows(), want.tuples)

@@ -363,7 +363,7 @@ struct LevelArgs {
     uint32_t *bound;
     uint64_t *part;            // per-workgroup partial sums of k_locate
     const uint64_t *F;
-    const uint64_t *tile_row;  // row holding element 256*t (entry ntiles = R-1)
+    const uint64_t *tile_row;  // row holding the first slot of tile t (entry ntiles = R-1)
     uint64_t gba;
     uint64_t *bitmap;
     uint32_t *tile_cnt;
@@ -405,17 +405,19 @@ __global__ __launch_bounds__(QT) void k_locate(LevelArgs a) {
     }
 }
 
-// tile_row[t] = the row whose slice of GBA holds element 256*t
-__global__ __launch_bounds__(QT) void k_tile_rows(const uint64_t *F, uint64_t R, uint64_t ntiles, uint64_t *tile_row) {
+// tile_row[t] = the row whose slice of GBA holds element ts*t
+__global__ __launch_bounds__(QT) void k_tile_rows(const uint64_t *F, uint64_t R, uint64_t ntiles, uint32_t ts,
+                                                 uint64_t *tile_row) {
     const uint64_t i = (uint64_t)blockIdx.x * QT + threadIdx.x;
     if (i >= R) return;
     const uint64_t lo = F[i], hi = F[i + 1];
-    for (uint64_t t = (lo + QT - 1) / QT; t * QT < hi; t++) tile_row[t] = i;
+    for (uint64_t t = (lo + ts - 1) / ts; t * ts < hi; t++) tile_row[t] = i;
     if (i == R - 1) tile_row[ntiles] = R - 1;
 }
 
 void tile_rows(gsi_ctx *c, const uint64_t *F, uint64_t R, uint64_t ntiles, uint64_t *tile_row) {
-    launch(c, "k_tile_rows", 16.0 * R + 8.0 * ntiles, k_tile_rows, nblocks(R), QT, F, R, ntiles, tile_row);
+    launch(c, "k_tile_rows", 16.0 * R + 8.0 * ntiles, k_tile_rows, nblocks(R), QT, F, R, ntiles, (uint32_t)QT,
+           tile_row);
 }
 
 // largest i in [lo, hi] with F[i] <= p (F non-decreasing, F[lo] <= p)
@@ -428,26 +430,35 @@ __device__ __forceinline__ uint64_t row_of(const uint64_t *F, uint64_t lo, uint6
     return lo;
 }
 
+// The per-level join and link work on tiles of SPT x 256 |GBA| slots.  On
+// large levels (SPT = 4) a 256-thread workgroup takes four consecutive
+// 256-slot rounds, issuing the loads of its four slots together, so the
+// tile's set-up (its rows staged in LDS) is paid once per 1024 slots and
+// each thread has four independent gathers in flight; small levels keep
+// one slot per thread (SPT = 1) and four times as many workgroups.
+constexpr uint64_t WIDE_TILE_SLOTS = 1ull << 22;  // |GBA| from which SPT = 4
+
 // The rows a tile touches, staged once per workgroup: F[i] and the start of
 // N(v'_i, l0) in ci for rows r_lo..r_hi.  A thread then finds its row with a
 // binary search in LDS instead of a chain of dependent global loads.  Tiles
-// spanning more than QT rows (long runs of rows with no first-edge
-// neighbours) search F in global memory instead.
+// spanning more than its slots' worth of rows (long runs of rows with no
+// first-edge neighbours) search F in global memory instead.
 struct TileRows {
     uint64_t r_lo, r_hi;
     bool staged;
 };
 
+template <uint32_t SPT>
 __device__ __forceinline__ TileRows stage_rows(const LevelArgs &a, uint64_t tile, uint64_t *s_F, uint32_t *s_st) {
     TileRows t;
     t.r_lo = a.tile_row[tile];
     t.r_hi = a.tile_row[tile + 1];
     const uint64_t nr = t.r_hi - t.r_lo + 1;
-    t.staged = nr <= QT;
+    t.staged = nr <= SPT * QT;
     if (t.staged) {
-        if (threadIdx.x < nr) {
-            s_F[threadIdx.x] = a.F[t.r_lo + threadIdx.x];
-            s_st[threadIdx.x] = a.loc[(uint64_t)a.e0 * a.R + t.r_lo + threadIdx.x];
+        for (uint32_t r = threadIdx.x; r < nr; r += QT) {
+            s_F[r] = a.F[t.r_lo + r];
+            s_st[r] = a.loc[(uint64_t)a.e0 * a.R + t.r_lo + r];
         }
         __syncthreads();
     }
@@ -474,20 +485,42 @@ __device__ __forceinline__ void find_row(const LevelArgs &a, const TileRows &t, 
     }
 }
 
+template <uint32_t SPT>
 __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
+    constexpr uint32_t TS = SPT * QT;
     __shared__ uint32_t s_cnt[QT / 64];
-    __shared__ uint64_t s_F[QT];
-    __shared__ uint32_t s_st[QT];
-    const uint64_t p0 = (uint64_t)blockIdx.x * QT;
-    const TileRows tr = stage_rows(a, blockIdx.x, s_F, s_st);
-    const uint64_t p = p0 + threadIdx.x;
-    bool keep = false;
-    if (p < a.gba) {
-        uint64_t i, Fi;
-        uint32_t st0;
-        find_row(a, tr, s_F, s_st, p, &i, &Fi, &st0);
-        const uint32_t x = a.e[a.e0].ci[st0 + (uint32_t)(p - Fi)];
-        keep = (a.Cu[x >> 6] >> (x & 63)) & 1ull;
+    __shared__ uint64_t s_F[TS];
+    __shared__ uint32_t s_st[TS];
+    const uint64_t p0 = (uint64_t)blockIdx.x * TS;
+    const TileRows tr = stage_rows<SPT>(a, blockIdx.x, s_F, s_st);
+    const uint32_t *ci0 = a.e[a.e0].ci;
+    uint64_t ri[SPT];
+    uint32_t xs[SPT];
+    bool kp[SPT];
+    // x = N(v'_i, l0)[p - F[i]] for the thread's four slots
+#pragma unroll
+    for (uint32_t r = 0; r < SPT; r++) {
+        const uint64_t p = p0 + r * QT + threadIdx.x;
+        kp[r] = p < a.gba;
+        ri[r] = 0;
+        xs[r] = 0;
+        if (kp[r]) {
+            uint64_t Fi;
+            uint32_t st0;
+            find_row(a, tr, s_F, s_st, p, &ri[r], &Fi, &st0);
+            xs[r] = ci0[st0 + (uint32_t)(p - Fi)];
+        }
+    }
+    // x in C(u)
+#pragma unroll
+    for (uint32_t r = 0; r < SPT; r++)
+        if (kp[r]) kp[r] = (a.Cu[xs[r] >> 6] >> (xs[r] & 63)) & 1ull;
+    // x not in m_i, x in every other linking list
+#pragma unroll
+    for (uint32_t r = 0; r < SPT; r++) {
+        bool keep = kp[r];
+        const uint64_t i = ri[r];
+        const uint32_t x = xs[r];
         for (uint32_t c = 0; keep && c < a.j; c++) keep = a.M[(uint64_t)c * a.R + i] != x;
         for (uint32_t e = 0; keep && e < a.ne; e++) {
             if (e == a.e0) continue;
@@ -495,13 +528,17 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
             uint32_t len = a.loc[(uint64_t)(a.ne + e) * a.R + i];
             keep = in_sorted(a.e[e].ci + st, len, x);
         }
+        kp[r] = keep;
     }
-    const uint64_t mask = __ballot(keep);
     const uint32_t w = threadIdx.x >> 6;
-    if (lane_id() == 0) {
-        a.bitmap[(uint64_t)blockIdx.x * (QT / 64) + w] = mask;
-        s_cnt[w] = (uint32_t)__popcll(mask);
+    uint32_t cnt = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < SPT; r++) {
+        const uint64_t mask = __ballot(kp[r]);
+        if (lane_id() == 0) a.bitmap[(uint64_t)blockIdx.x * (TS / 64) + r * (QT / 64) + w] = mask;
+        cnt += (uint32_t)__popcll(mask);
     }
+    if (lane_id() == 0) s_cnt[w] = cnt;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t t = 0;
@@ -511,10 +548,18 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
     }
 }
 
+// rows of the last level are staged in LDS and written out as one
+// contiguous block per round (coalesced stores) when k is at most this
+constexpr uint32_t LINK_STAGE_K = 16;
+
+template <uint32_t SPT>
 __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
+    constexpr uint32_t TS = SPT * QT;
     __shared__ uint64_t s_d[2][QT / 64];
-    __shared__ uint64_t s_F[QT];
-    __shared__ uint32_t s_st[QT];
+    __shared__ uint64_t s_F[TS];
+    __shared__ uint32_t s_st[TS];
+    __shared__ uint32_t s_rows[QT * LINK_STAGE_K];
+    __shared__ uint32_t s_pre[TS / 64 + 1];  // kept slots before each bitmap word of the tile
     const uint64_t tile = blockIdx.x;
     if (a.tile_off[tile + 1] == a.tile_off[tile]) {  // whole tile empty (uniform)
         if (a.final_level && threadIdx.x == 0) {
@@ -523,39 +568,67 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
         }
         return;
     }
-    const uint64_t p0 = tile * QT;
-    const TileRows tr = stage_rows(a, tile, s_F, s_st);
+    const uint64_t p0 = tile * TS;
+    const uint64_t *words = a.bitmap + tile * (TS / 64);
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (uint32_t q = 0; q < TS / 64; q++) {
+            s_pre[q] = run;
+            run += (uint32_t)__popcll(words[q]);
+        }
+        s_pre[TS / 64] = run;
+    }
+    const TileRows tr = stage_rows<SPT>(a, tile, s_F, s_st);  // (its barrier also publishes s_pre)
+    if (!tr.staged) __syncthreads();
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
-    const uint64_t *words = a.bitmap + tile * (QT / 64);
-    const uint64_t word = words[w];
-    const bool keep = (word >> lane) & 1ull;
-    uint64_t before = 0;
-    for (uint32_t q = 0; q < w; q++) before += (uint64_t)__popcll(words[q]);
-    const uint64_t pos = a.tile_off[tile] + before + rank_below(word);
-    uint64_t h = 0;
-    if (keep && pos < a.S) {
-        const uint64_t p = p0 + threadIdx.x;
-        uint64_t i, Fi;
-        uint32_t st0;
-        find_row(a, tr, s_F, s_st, p, &i, &Fi, &st0);
-        const uint32_t x = a.e[a.e0].ci[st0 + (uint32_t)(p - Fi)];
-        if (!a.final_level) {
-            for (uint32_t c = 0; c < a.j; c++) a.Mn[(uint64_t)c * a.S + pos] = a.M[(uint64_t)c * a.R + i];
-            a.Mn[(uint64_t)a.j * a.S + pos] = x;
-        } else {
-            uint64_t f = 14695981039346656037ull;
-            for (uint32_t u = 0; u < a.k; u++) {
-                uint32_t c = a.qcol[u];
-                uint32_t val = c < a.j ? a.M[(uint64_t)c * a.R + i] : x;
-                if (!a.count_only) a.out[pos * a.k + u] = val;
-                f = fnv_word(f, val);
+    const uint64_t tbase = a.tile_off[tile];
+    const bool stage = a.final_level && !a.count_only && a.k <= LINK_STAGE_K;
+    const uint32_t *ci0 = a.e[a.e0].ci;
+    uint64_t hs = 0, hx = 0;
+    for (uint32_t r = 0; r < SPT; r++) {
+        const uint32_t wi = r * (QT / 64) + w;
+        const uint64_t word = words[wi];
+        const bool keep = (word >> lane) & 1ull;
+        const uint32_t local = s_pre[wi] - s_pre[r * (QT / 64)] + rank_below(word);  // rank within the round
+        const uint64_t pos = tbase + s_pre[wi] + rank_below(word);
+        if (keep && pos < a.S) {
+            const uint64_t p = p0 + r * QT + threadIdx.x;
+            uint64_t i, Fi;
+            uint32_t st0;
+            find_row(a, tr, s_F, s_st, p, &i, &Fi, &st0);
+            const uint32_t x = ci0[st0 + (uint32_t)(p - Fi)];
+            if (!a.final_level) {
+                for (uint32_t c = 0; c < a.j; c++) a.Mn[(uint64_t)c * a.S + pos] = a.M[(uint64_t)c * a.R + i];
+                a.Mn[(uint64_t)a.j * a.S + pos] = x;
+            } else {
+                uint64_t f = 14695981039346656037ull;
+                for (uint32_t u = 0; u < a.k; u++) {
+                    uint32_t c = a.qcol[u];
+                    uint32_t val = c < a.j ? a.M[(uint64_t)c * a.R + i] : x;
+                    if (stage) s_rows[local * a.k + u] = val;
+                    else if (!a.count_only) a.out[pos * a.k + u] = val;
+                    f = fnv_word(f, val);
+                }
+                const uint64_t h = mix64(f);
+                hs += h;
+                hx ^= h;
             }
-            h = mix64(f);
+        }
+        if (stage) {
+            // the round's rows are one contiguous block of the output
+            __syncthreads();
+            const uint64_t first = tbase + s_pre[r * (QT / 64)];
+            uint64_t end = tbase + s_pre[(r + 1) * (QT / 64)];
+            if (end > a.S) end = a.S;
+            const uint32_t nw = first < end ? (uint32_t)(end - first) * a.k : 0u;
+            uint32_t *dst = a.out + first * a.k;
+            for (uint32_t t = threadIdx.x; t < nw; t += QT) dst[t] = s_rows[t];
+            __syncthreads();
         }
     }
     if (a.final_level) {
         // per-tile partial digest; reduced by one small kernel afterwards
-        uint64_t sum = wave_sum(h), xr = wave_xor(h);
+        uint64_t sum = wave_sum(hs), xr = wave_xor(hx);
         if (lane == 0) {
             s_d[0][w] = sum;
             s_d[1][w] = xr;
@@ -1169,16 +1242,20 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
             return done();
         }
         a.gba = gba;
-        const uint64_t ntiles = (gba + QT - 1) / QT;
-        a.bitmap = ls.get<uint64_t>(ntiles * (QT / 64), "GBA bitmap");
+        const uint32_t spt = gba >= WIDE_TILE_SLOTS ? 4u : 1u;
+        const uint32_t ts = spt * QT;
+        const uint64_t ntiles = (gba + ts - 1) / ts;
+        a.bitmap = ls.get<uint64_t>(ntiles * (ts / 64), "GBA bitmap");
         a.tile_cnt = ls.get<uint32_t>(ntiles, "tile counts");
         uint64_t *toff = ls.get<uint64_t>(ntiles + 1, "tile offsets");
         a.tile_off = toff;
         uint64_t *trow = ls.get<uint64_t>(ntiles + 1, "tile rows");
         a.tile_row = trow;
-        launch(c, "k_tile_rows", 16.0 * R + 8.0 * ntiles, k_tile_rows, nblocks(R), QT, (const uint64_t *)F, R, ntiles, trow);
+        launch(c, "k_tile_rows", 16.0 * R + 8.0 * ntiles, k_tile_rows, nblocks(R), QT, (const uint64_t *)F, R, ntiles,
+               ts, trow);
         double jb = 4.0 * gba + (double)R * (8.0 + 8.0 * ne + 4.0 * j) + 4.0 * (double)sc[0] + gba / 8.0 + 4.0 * ntiles;
-        launch(c, "k_join", jb, k_join, nblocks(gba), QT, a);
+        if (spt == 4) launch(c, "k_join", jb, k_join<4>, (uint32_t)ntiles, QT, a);
+        else launch(c, "k_join", jb, k_join<1>, (uint32_t)ntiles, QT, a);
         exclusive_scan(c, a.tile_cnt, ntiles, toff, ls, dscal + 1);
         uint64_t S;
         read_scalars(c, dscal + 1, &S, 1);
@@ -1202,7 +1279,8 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
             a.Mn = Mn.get<uint32_t>((uint64_t)(j + 1) * S, "next table");
             lb += 4.0 * (j + 1) * S;
         }
-        launch(c, "k_link", lb, k_link, (uint32_t)ntiles, QT, a);
+        if (spt == 4) launch(c, "k_link", lb, k_link<4>, (uint32_t)ntiles, QT, a);
+        else launch(c, "k_link", lb, k_link<1>, (uint32_t)ntiles, QT, a);
         if (final_level) {
             reduce_pairs(c, a.dig_part, ntiles, dscal);
             uint64_t dg[2];

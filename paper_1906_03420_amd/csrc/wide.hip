@@ -86,49 +86,92 @@ __global__ __launch_bounds__(WT) void k_wlocate(const WQ *qs, uint32_t nq, const
     }
 }
 
+// A tile's rows usually belong to one query: then that query's descriptor
+// and its rows' first-edge starts are staged in LDS once, and every slot
+// reads them there instead of through a query search and dependent global
+// loads.
+struct WTile {
+    uint64_t r_lo, r_hi, nr;
+    bool staged;  // F (and, for one query, the starts) of its rows in LDS
+    bool one;     // all rows in one query
+};
+
+__device__ __forceinline__ WTile stage_wtile(const WQ *qs, uint32_t nq, const uint64_t *F, const uint64_t *tile_row,
+                                             const uint32_t *loc, uint64_t tile, uint64_t *s_F, uint32_t *s_st,
+                                             WQ *s_Q, uint32_t *s_q) {
+    WTile t;
+    t.r_lo = tile_row[tile];
+    t.r_hi = tile_row[tile + 1];
+    t.nr = t.r_hi - t.r_lo + 1;
+    t.staged = t.nr <= WT;
+    if (threadIdx.x == 0) {
+        s_q[0] = query_of(qs, 0, nq - 1, t.r_lo);
+        s_q[1] = query_of(qs, s_q[0], nq - 1, t.r_hi);
+    }
+    if (t.staged && threadIdx.x < t.nr) s_F[threadIdx.x] = F[t.r_lo + threadIdx.x];
+    __syncthreads();
+    t.one = s_q[0] == s_q[1];
+    if (t.one) {
+        const WQ &Q = qs[s_q[0]];
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&Q);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(s_Q);
+        for (uint32_t w = threadIdx.x; w < sizeof(WQ) / 4; w += WT) dst[w] = src[w];
+        if (t.staged && threadIdx.x < t.nr)
+            s_st[threadIdx.x] = loc[Q.locbase + (uint64_t)Q.e0 * Q.R + (t.r_lo + threadIdx.x - Q.rbase)];
+    }
+    __syncthreads();
+    return t;
+}
+
+// global row r holding slot p, F[r], and the query of r
+__device__ __forceinline__ void wfind(const WQ *qs, const uint64_t *F, const WTile &t, const uint64_t *s_F,
+                                      const uint32_t *s_q, uint64_t p, uint64_t *r, uint64_t *Fr, uint32_t *lr,
+                                      uint32_t *q) {
+    if (t.staged) {
+        uint32_t lo = 0, hi = (uint32_t)(t.nr - 1);
+        while (lo < hi) {
+            uint32_t mid = (lo + hi + 1) >> 1;
+            if (s_F[mid] <= p) lo = mid;
+            else hi = mid - 1;
+        }
+        *r = t.r_lo + lo;
+        *Fr = s_F[lo];
+        *lr = lo;
+    } else {
+        uint64_t lo = t.r_lo, hi = t.r_hi;
+        while (lo < hi) {
+            uint64_t mid = lo + (hi - lo + 1) / 2;
+            if (F[mid] <= p) lo = mid;
+            else hi = mid - 1;
+        }
+        *r = lo;
+        *Fr = F[lo];
+        *lr = 0;
+    }
+    *q = t.one ? s_q[0] : query_of(qs, s_q[0], s_q[1], *r);
+}
+
 __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, uint32_t nq, const WEdge *edges, const uint64_t *F,
                                              const uint64_t *tile_row, uint64_t gba, const uint32_t *loc,
                                              uint64_t *bitmap, uint32_t *tile_cnt) {
     __shared__ uint64_t s_F[WT];
+    __shared__ uint32_t s_st[WT];
+    __shared__ WQ s_Q;
     __shared__ uint32_t s_q[2];
     __shared__ uint32_t s_cnt[WT / 64];
     const uint64_t tile = blockIdx.x, p0 = tile * WT;
-    const uint64_t r_lo = tile_row[tile], r_hi = tile_row[tile + 1];
-    const uint64_t nr = r_hi - r_lo + 1;
-    const bool staged = nr <= WT;
-    if (staged && threadIdx.x < nr) s_F[threadIdx.x] = F[r_lo + threadIdx.x];
-    if (threadIdx.x == 0) {
-        s_q[0] = query_of(qs, 0, nq - 1, r_lo);
-        s_q[1] = query_of(qs, s_q[0], nq - 1, r_hi);
-    }
-    __syncthreads();
+    const WTile t = stage_wtile(qs, nq, F, tile_row, loc, tile, s_F, s_st, &s_Q, s_q);
     const uint64_t p = p0 + threadIdx.x;
     bool keep = false;
     if (p < gba) {
         uint64_t r, Fr;
-        if (staged) {
-            uint32_t lo = 0, hi = (uint32_t)(nr - 1);
-            while (lo < hi) {
-                uint32_t mid = (lo + hi + 1) >> 1;
-                if (s_F[mid] <= p) lo = mid;
-                else hi = mid - 1;
-            }
-            r = r_lo + lo;
-            Fr = s_F[lo];
-        } else {
-            uint64_t lo = r_lo, hi = r_hi;
-            while (lo < hi) {
-                uint64_t mid = lo + (hi - lo + 1) / 2;
-                if (F[mid] <= p) lo = mid;
-                else hi = mid - 1;
-            }
-            r = lo;
-            Fr = F[r];
-        }
-        const WQ &Q = qs[query_of(qs, s_q[0], s_q[1], r)];
+        uint32_t lr, qi;
+        wfind(qs, F, t, s_F, s_q, p, &r, &Fr, &lr, &qi);
+        const WQ &Q = t.one ? s_Q : qs[qi];
         const uint64_t i = r - Q.rbase;
         const WEdge &E0 = edges[Q.efirst + Q.e0];
-        const uint32_t x = E0.ci[loc[Q.locbase + (uint64_t)Q.e0 * Q.R + i] + (uint32_t)(p - Fr)];
+        const uint32_t st0 = (t.one && t.staged) ? s_st[lr] : loc[Q.locbase + (uint64_t)Q.e0 * Q.R + i];
+        const uint32_t x = E0.ci[st0 + (uint32_t)(p - Fr)];
         keep = (Q.Cu[x >> 6] >> (x & 63)) & 1ull;
         for (uint32_t c = 0; keep && c < Q.j; c++) keep = Q.M[(uint64_t)c * Q.R + i] != x;
         for (uint32_t e = 0; keep && e < Q.ne; e++) {
@@ -145,10 +188,10 @@ __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, uint32_t nq, const W
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t t = 0;
+        uint32_t tc = 0;
 #pragma unroll
-        for (int q = 0; q < WT / 64; q++) t += s_cnt[q];
-        tile_cnt[tile] = t;
+        for (int q = 0; q < WT / 64; q++) tc += s_cnt[q];
+        tile_cnt[tile] = tc;
     }
 }
 
@@ -179,69 +222,67 @@ __global__ __launch_bounds__(WT) void k_wsurv(const WQ *qs, uint32_t nq, const u
     sb[4 * (uint64_t)q + 3] = f1;
 }
 
+// last-level rows of a one-query tile are staged in LDS and written as one
+// contiguous block when k is at most this
+constexpr uint32_t WLINK_STAGE_K = 16;
+
 __global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, uint32_t nq, const WEdge *edges, const uint64_t *F,
                                              const uint64_t *tile_row, const uint32_t *loc, const uint64_t *bitmap,
                                              const uint64_t *tile_off, uint64_t *hv) {
     __shared__ uint64_t s_F[WT];
+    __shared__ uint32_t s_st[WT];
+    __shared__ WQ s_Q;
     __shared__ uint32_t s_q[2];
+    __shared__ uint32_t s_rows[WT * WLINK_STAGE_K];
     const uint64_t tile = blockIdx.x;
     if (tile_off[tile + 1] == tile_off[tile]) return;  // no survivor in the tile (uniform)
     const uint64_t p0 = tile * WT;
-    const uint64_t r_lo = tile_row[tile], r_hi = tile_row[tile + 1];
-    const uint64_t nr = r_hi - r_lo + 1;
-    const bool staged = nr <= WT;
-    if (staged && threadIdx.x < nr) s_F[threadIdx.x] = F[r_lo + threadIdx.x];
-    if (threadIdx.x == 0) {
-        s_q[0] = query_of(qs, 0, nq - 1, r_lo);
-        s_q[1] = query_of(qs, s_q[0], nq - 1, r_hi);
-    }
-    __syncthreads();
+    const WTile t = stage_wtile(qs, nq, F, tile_row, loc, tile, s_F, s_st, &s_Q, s_q);
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
     const uint64_t *words = bitmap + tile * (WT / 64);
     const uint64_t word = words[w];
-    if (!((word >> lane) & 1ull)) return;
-    uint64_t before = 0;
-    for (uint32_t q = 0; q < w; q++) before += (uint64_t)__popcll(words[q]);
-    const uint64_t gpos = tile_off[tile] + before + rank_below(word);
-    const uint64_t p = p0 + threadIdx.x;
-    uint64_t r, Fr;
-    if (staged) {
-        uint32_t lo = 0, hi = (uint32_t)(nr - 1);
-        while (lo < hi) {
-            uint32_t mid = (lo + hi + 1) >> 1;
-            if (s_F[mid] <= p) lo = mid;
-            else hi = mid - 1;
+    uint32_t before = 0;
+    for (uint32_t q = 0; q < w; q++) before += (uint32_t)__popcll(words[q]);
+    const uint32_t local = before + rank_below(word);  // rank within the tile
+    const uint64_t gpos = tile_off[tile] + local;
+    const bool stage = t.one && s_Q.final_level && s_Q.out && s_Q.k <= WLINK_STAGE_K;
+    if ((word >> lane) & 1ull) {
+        const uint64_t p = p0 + threadIdx.x;
+        uint64_t r, Fr;
+        uint32_t lr, qi;
+        wfind(qs, F, t, s_F, s_q, p, &r, &Fr, &lr, &qi);
+        const WQ &Q = t.one ? s_Q : qs[qi];
+        const uint64_t i = r - Q.rbase;
+        const uint64_t pos = gpos - Q.sbase;
+        if (pos < Q.S) {  // always, when the survivor ranges are consistent
+            const WEdge &E0 = edges[Q.efirst + Q.e0];
+            const uint32_t st0 = (t.one && t.staged) ? s_st[lr] : loc[Q.locbase + (uint64_t)Q.e0 * Q.R + i];
+            const uint32_t x = E0.ci[st0 + (uint32_t)(p - Fr)];
+            if (!Q.final_level) {
+                for (uint32_t c = 0; c < Q.j; c++) Q.Mn[(uint64_t)c * Q.S + pos] = Q.M[(uint64_t)c * Q.R + i];
+                Q.Mn[(uint64_t)Q.j * Q.S + pos] = x;
+            } else {
+                uint64_t f = 14695981039346656037ull;
+                for (uint32_t u = 0; u < Q.k; u++) {
+                    const uint32_t c = Q.qcol[u];
+                    const uint32_t val = c < Q.j ? Q.M[(uint64_t)c * Q.R + i] : x;
+                    if (stage) s_rows[local * Q.k + u] = val;
+                    else if (Q.out) Q.out[pos * Q.k + u] = val;
+                    f = fnv_word(f, val);
+                }
+                hv[gpos] = mix64(f);
+            }
         }
-        r = r_lo + lo;
-        Fr = s_F[lo];
-    } else {
-        uint64_t lo = r_lo, hi = r_hi;
-        while (lo < hi) {
-            uint64_t mid = lo + (hi - lo + 1) / 2;
-            if (F[mid] <= p) lo = mid;
-            else hi = mid - 1;
-        }
-        r = lo;
-        Fr = F[r];
     }
-    const WQ &Q = qs[query_of(qs, s_q[0], s_q[1], r)];
-    const uint64_t i = r - Q.rbase;
-    const uint64_t pos = gpos - Q.sbase;
-    if (pos >= Q.S) return;  // never taken when the survivor ranges are consistent
-    const WEdge &E0 = edges[Q.efirst + Q.e0];
-    const uint32_t x = E0.ci[loc[Q.locbase + (uint64_t)Q.e0 * Q.R + i] + (uint32_t)(p - Fr)];
-    if (!Q.final_level) {
-        for (uint32_t c = 0; c < Q.j; c++) Q.Mn[(uint64_t)c * Q.S + pos] = Q.M[(uint64_t)c * Q.R + i];
-        Q.Mn[(uint64_t)Q.j * Q.S + pos] = x;
-    } else {
-        uint64_t f = 14695981039346656037ull;
-        for (uint32_t u = 0; u < Q.k; u++) {
-            const uint32_t c = Q.qcol[u];
-            const uint32_t val = c < Q.j ? Q.M[(uint64_t)c * Q.R + i] : x;
-            if (Q.out) Q.out[pos * Q.k + u] = val;
-            f = fnv_word(f, val);
-        }
-        hv[gpos] = mix64(f);
+    if (stage) {
+        // the tile's rows are one contiguous block of the query's result
+        __syncthreads();
+        const uint64_t first = tile_off[tile] - s_Q.sbase;
+        uint64_t end = tile_off[tile + 1] - s_Q.sbase;
+        if (end > s_Q.S) end = s_Q.S;
+        const uint32_t nw = first < end ? (uint32_t)(end - first) * s_Q.k : 0u;
+        uint32_t *dst = s_Q.out + first * s_Q.k;
+        for (uint32_t v = threadIdx.x; v < nw; v += WT) dst[v] = s_rows[v];
     }
 }
 

@@ -247,7 +247,7 @@ def serving_section(args, arena):
     total_bad = bad + seq_bad
     sat = dict(queries_per_s=mu, embeddings_per_s=emb_of(reqs0) / span, p50_ms=float(np.percentile(lat, 50) * 1e3),
                p99_ms=float(np.percentile(lat, 99) * 1e3), steps=info["steps"], level_steps=info["level_steps"],
-               paths=paths)
+               paths=paths, admit_ms=info["admit_ms"], level_ms=info["level_ms"], span_ms=span * 1e3)
     rates = []
     for s_i, f in enumerate((0.5, 0.8, 1.2)):
         reqs = w.request_stream(name, s_i + 1, n, len(pool))
@@ -257,7 +257,8 @@ def serving_section(args, arena):
         rates.append(dict(offered_factor=f, offered_qps=f * mu, achieved_qps=n / span,
                           p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
                           max_ms=float(lat.max() * 1e3), steps=info["steps"], level_steps=info["level_steps"],
-                          admit_rounds=info["admit_rounds"], peak_predicted_mb=info["peak_predicted"] / 2**20))
+                          admit_rounds=info["admit_rounds"], peak_predicted_mb=info["peak_predicted"] / 2**20,
+                          admit_ms=info["admit_ms"], level_ms=info["level_ms"], span_ms=span * 1e3))
         progress("serving: %.1f x mu -> p50 %.2f ms p99 %.2f ms" % (f, rates[-1]["p50_ms"], rates[-1]["p99_ms"]))
     dg.free()
     ctx.close()

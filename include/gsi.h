@@ -162,6 +162,9 @@ gsi_status gsi_graph_copy_pcsr(const gsi_graph *g, uint32_t label, uint32_t *hos
 #define GSI_NO_FUSED 0x4u          /* run every level with the per-level kernels
                                       (no fused small-table workgroup) */
 #define GSI_NO_CHUNKS 0x10u        /* no root chunks (see gsi_query_run) */
+#define GSI_LEVEL_FIRST_EDGE 0x20u /* every row of a level scans the list of the
+                                      level's first edge e0 (Algorithm 4), not
+                                      its shortest linking list */
 
 /* Optional controls of one query run (NULL = defaults). */
 typedef struct {
@@ -188,10 +191,13 @@ typedef struct {
  *   2. the matching order of Algorithm 2 (host, from |C(u)| and freq(l));
  *   3. M = C(u_first); then for each further query vertex u one join level
  *      (Algorithm 3 with Algorithm 4): locate N(v',l) through PCSR for every
- *      linking edge, prefix-sum the first-edge list lengths into F (|GBA|),
- *      keep x in N(v'_i,l0) iff x is not in row m_i, x is in C(u) and x is in
- *      every other linking list; prefix-sum survivors; link m_i with each
- *      survivor into M' (Prealloc-Combine, one join pass);
+ *      linking edge; each row scans its shortest located list (the list of
+ *      Algorithm 4's first edge e0 on ties, or always with
+ *      GSI_LEVEL_FIRST_EDGE or a given first_edge); prefix-sum the scanned
+ *      lengths into F (|GBA|); keep x of row m_i's scanned list iff x is not
+ *      in m_i, x is in C(u) and x is in every other linking list; prefix-sum
+ *      survivors; link m_i with each survivor into M' (Prealloc-Combine, one
+ *      join pass);
  *   4. the last level writes rows in query-vertex order (or only counts) and
  *      the order-independent digest.
  * Up to 4096 roots one fused workgroup runs the levels while the tables stay

@@ -267,11 +267,13 @@ def plan(q, cand_counts, freq: dict):
 # executed row by row as written: for each row m_i the buffer is
 #   buf_i = ((N(v'_i, l0) minus m_i) intersect C(u)) intersect every other N(.,l)
 # and M' gets (m_i, z) for each z in buf_i.
-def join_levels(g, q, cands: list, order: list, e0src: list, nbrs: dict | None = None):
+def join_levels(g, q, cands: list, order: list, e0src: list, nbrs: dict | None = None, per_row: bool = False):
     """Returns (M, levels): the final table (rows in matching-order columns,
     produced in row order then buffer order) and per level j >= 1 a dict
     with R (rows of M), GBA (|GBA| = F[|M|]), F (the offsets of Algorithm 4)
-    and S (rows of M')."""
+    and S (rows of M').  With per_row, each row's buffer starts from its
+    shortest linking list instead of e0's (e0's on ties): the buffer, being
+    the intersection of all of them, is the same; F and |GBA| shrink."""
     nbrs = nbrs if nbrs is not None else neighbour_lists(g)
     adj = defaultdict(dict)
     for a, b, l in zip(q.src.tolist(), q.dst.tolist(), q.elabel.tolist()):
@@ -294,12 +296,17 @@ def join_levels(g, q, cands: list, order: list, e0src: list, nbrs: dict | None =
         F = [0]
         new = []
         for row in M:
+            wb = w0
             base = N(row[col[w0]], l0)
+            if per_row:
+                for w in links:
+                    if w != w0 and len(N(row[col[w]], adj[u][w])) < len(base):
+                        wb, base = w, N(row[col[w]], adj[u][w])
             F.append(F[-1] + len(base))
             buf = [int(x) for x in base if int(x) not in row]
             buf = [x for x in buf if x in Cu]
             for w in links:
-                if w == w0:
+                if w == wb:
                     continue
                 other = set(int(x) for x in N(row[col[w]], adj[u][w]))
                 buf = [x for x in buf if x in other]

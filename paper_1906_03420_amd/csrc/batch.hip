@@ -104,7 +104,7 @@ static std::vector<FusedQuery> run_tier(gsi_graph *g, const std::shared_ptr<Roun
     }
     const uint64_t per_cu = std::max<uint64_t>(1, (uint64_t)t.blocks_per_cu * grid_scale / 8);
     const uint32_t grid = (uint32_t)std::min<uint64_t>(n, per_cu * cu_count(c));
-    const uint64_t slot_words = 2ull * t.cap_rows * kmax + 2ull * (kmax - 1) * t.cap_rows;
+    const uint64_t slot_words = 2ull * t.cap_rows * kmax + fused_loc_words(kmax, t.cap_rows);
     Scratch ts(c);
     FBatchItem *d_items = ts.get<FBatchItem>(n, "batch items");
     uint32_t *scratch = ts.get<uint32_t>(slot_words * grid, "batch slots");
@@ -262,6 +262,8 @@ std::vector<WideQuery> admit_round(gsi_graph *g, const std::vector<const HostQue
         hp->count_only = count_only ? 1u : 0u;
         hp->cap_rows = 0xFFFFFFFFu;  // the tier's own capacities apply
         hp->cap_slots = 0xFFFFFFFFu;
+        hp->pick = 1;
+        hp->ci_all = g->ci;
         std::vector<uint32_t> col(q.k);
         for (uint32_t j = 0; j < q.k; j++) col[pl.order[j]] = j;
         for (uint32_t v = 0; v < q.k; v++) hp->qcol[v] = col[v];
@@ -280,6 +282,7 @@ std::vector<WideQuery> admit_round(gsi_graph *g, const std::vector<const HostQue
                         fe.G = g->G[l];
                         fe.H = g->H[l];
                         fe.col = i;
+                        fe.ci_off = (uint32_t)g->ci_base[l];
                         if (pl.order[i] == pl.e0src[j]) hp->lv_e0[j] = ne;
                         ne++;
                     }

@@ -16,11 +16,17 @@ struct FEdge {            // one linking edge of a level
     const uint32_t *ci;   // neighbour lists of its label
     uint32_t G, H;        // groups, home groups
     uint32_t col;         // column of M with the placed endpoint
-    uint32_t pad;
+    uint32_t ci_off;      // offset of its label's lists in the whole ci array
 };
+
+// Lookups of the fused kernels: rows x (2 ne + 2) words per level (starts,
+// lengths, start of the scanned list in the whole ci array, its edge).
+inline uint64_t fused_loc_words(uint32_t k, uint64_t rows) { return 2ull * k * rows; }
 
 struct FPlan {
     uint32_t k, count_only, cap_rows, cap_slots;
+    uint32_t pick, pad;           // 1: each row scans its shortest linking list
+    const uint32_t *ci_all;       // every label's lists
     uint32_t qcol[GSI_MAX_K];     // query vertex -> column
     uint32_t lv_ne[GSI_MAX_K];    // level j: linking edges
     uint32_t lv_e0[GSI_MAX_K];    // level j: first edge (index within the level)

@@ -91,19 +91,37 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
         const uint32_t ne = plan->lv_ne[j], ef = plan->lv_first[j], e0 = plan->lv_e0[j];
         const uint64_t *Cu = plan->Cu[j];
         const bool final_level = (j == k - 1);
-        const FEdge &E0 = plan->edges[ef + e0];
+        const uint32_t *ci_all = plan->ci_all;
         if (tid == 0) st->lv_rows[j] = R;
 
-        // locate N(v, l) for every row and linking edge; bound = |N(v'_i, l0)|
+        // locate N(v, l) for every row and linking edge; the row scans the
+        // list of e0 (Algorithm 4) or, with `pick`, its shortest one
         for (uint32_t i = tid; i < R; i += FT) {
+            uint32_t s0 = 0, l0 = 0, ob = NONE32, os = 0, ol = 0xFFFFFFFFu;
             for (uint32_t e = 0; e < ne; e++) {
                 const FEdge &ed = plan->edges[ef + e];
                 const uint32_t v = M[(uint64_t)ed.col * R + i];
                 const uint2 r = pcsr_find(ed.gl, ed.G, ed.H, v);
                 loc[(uint64_t)e * R + i] = r.x;
                 loc[(uint64_t)(ne + e) * R + i] = r.y;
-                if (e == e0) s_F[i] = r.y;
+                if (e == e0) {
+                    s0 = r.x;
+                    l0 = r.y;
+                } else if (r.y < ol) {
+                    ob = e;
+                    os = r.x;
+                    ol = r.y;
+                }
             }
+            uint32_t be = e0, bs = s0, bl = l0;
+            if (plan->pick && ob != NONE32 && ol < l0) {
+                be = ob;
+                bs = os;
+                bl = ol;
+            }
+            s_F[i] = bl;
+            loc[(uint64_t)(2 * ne) * R + i] = plan->edges[ef + be].ci_off + bs;
+            loc[(uint64_t)(2 * ne + 1) * R + i] = be;
         }
         __syncthreads();
         // F = exclusive prefix sum of the bounds (each thread owns 4 rows)
@@ -155,11 +173,12 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
             bool keep = false;
             if (p < gba) {
                 const uint32_t i = lds_row(s_F, R, p);
-                const uint32_t x = E0.ci[loc[(uint64_t)e0 * R + i] + (p - s_F[i])];
+                const uint32_t x = ci_all[loc[(uint64_t)(2 * ne) * R + i] + (p - s_F[i])];
                 keep = (Cu[x >> 6] >> (x & 63)) & 1ull;
                 for (uint32_t c = 0; keep && c < j; c++) keep = M[(uint64_t)c * R + i] != x;
+                const uint32_t be = (keep && ne > 1) ? loc[(uint64_t)(2 * ne + 1) * R + i] : e0;
                 for (uint32_t e = 0; keep && e < ne; e++) {
-                    if (e == e0) continue;
+                    if (e == be) continue;
                     keep = in_sorted(plan->edges[ef + e].ci + loc[(uint64_t)e * R + i],
                                      loc[(uint64_t)(ne + e) * R + i], x);
                 }
@@ -227,7 +246,7 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
             const uint32_t p = word * 64 + lane;
             const uint32_t pos = s_wpre[word] + rank_below(bits);
             const uint32_t i = lds_row(s_F, R, p);
-            const uint32_t x = E0.ci[loc[(uint64_t)e0 * R + i] + (p - s_F[i])];
+            const uint32_t x = ci_all[loc[(uint64_t)(2 * ne) * R + i] + (p - s_F[i])];
             if (!final_level) {
                 for (uint32_t c = 0; c < j; c++) Mn[(uint64_t)c * S + pos] = M[(uint64_t)c * R + i];
                 Mn[(uint64_t)j * S + pos] = x;

@@ -195,14 +195,12 @@ static void launch_filter(gsi_ctx *c, gsi_graph *g, const FilterArgs &fa, uint64
 // so a pass usually covers one or two labels and lanes of other labels read
 // nothing past word 0, which stays in the caches across passes.
 __global__ __launch_bounds__(QT) void k_filter_multi(const uint32_t *sig, uint32_t n, uint64_t nwords,
-                                                    const FilterArgs *passes, uint64_t *bits, uint32_t *part) {
-    __shared__ FilterArgs fa;
+                                                    const FilterArgs *__restrict__ passes, uint64_t *bits,
+                                                    uint32_t *part) {
+    // the pass's query signatures: a uniform, read-only address, so the
+    // compiler reads them with scalar loads (as kernel arguments are)
+    const FilterArgs &fa = passes[blockIdx.y];
     __shared__ uint32_t s_cnt[GSI_MAX_K];
-    {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(passes + blockIdx.y);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(&fa);
-        for (uint32_t t = threadIdx.x; t < sizeof(FilterArgs) / 4; t += QT) dst[t] = src[t];
-    }
     if (threadIdx.x < GSI_MAX_K) s_cnt[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t K = fa.k;
@@ -350,16 +348,20 @@ struct EdgeRef {
     const uint32_t *ci;  // this label's neighbour lists
     uint32_t G, H;       // groups, home groups
     uint32_t col;        // column of M holding the placed endpoint
-    uint32_t pad;
+    uint32_t ci_off;     // offset of this label's lists in the whole ci array
 };
 
 struct LevelArgs {
     const uint32_t *M;
     uint64_t R;
     uint32_t j, ne, e0, k;
+    uint32_t pick;  // 1: each row scans its shortest linking list (else e0's)
     EdgeRef e[GSI_MAX_K];
+    const uint32_t *ci_all;  // every label's lists
     const uint64_t *Cu;
-    uint32_t *loc;  // start at [e*R + i], length at [(ne+e)*R + i]
+    // start at [e*R + i], length at [(ne+e)*R + i]; the scanned list of row
+    // i starts at ci_all[loc[2ne*R + i]] and is linking edge loc[(2ne+1)*R + i]
+    uint32_t *loc;
     uint32_t *bound;
     uint64_t *part;            // per-workgroup partial sums of k_locate
     const uint64_t *F;
@@ -376,20 +378,43 @@ struct LevelArgs {
     uint32_t final_level, count_only;
 };
 
+// The list a row scans (its slots of GBA): the first edge e0 of Algorithm 4,
+// or, with `pick`, whichever linking list of the row is shortest (e0 on
+// ties).  The row's survivors are the same either way (they lie in every
+// linking list), and, the lists being sorted, so is their order.
 __global__ __launch_bounds__(QT) void k_locate(LevelArgs a) {
     const uint64_t i = (uint64_t)blockIdx.x * QT + threadIdx.x;
     const bool valid = i < a.R;
     uint64_t other = 0;
     if (valid) {
+        uint32_t s0 = 0, l0 = 0, ob = NONE32, os = 0, ol = 0xFFFFFFFFu;
+        uint64_t all = 0;
         for (uint32_t e = 0; e < a.ne; e++) {
             const EdgeRef &er = a.e[e];
             uint32_t v = a.M[(uint64_t)er.col * a.R + i];
             uint2 r = pcsr_find(er.gl, er.G, er.H, v);
             a.loc[(uint64_t)e * a.R + i] = r.x;
             a.loc[(uint64_t)(a.ne + e) * a.R + i] = r.y;
-            if (e == a.e0) a.bound[i] = r.y;
-            else other += r.y;
+            all += r.y;
+            if (e == a.e0) {
+                s0 = r.x;
+                l0 = r.y;
+            } else if (r.y < ol) {
+                ob = e;
+                os = r.x;
+                ol = r.y;
+            }
         }
+        uint32_t be = a.e0, bs = s0, bl = l0;
+        if (a.pick && ob != NONE32 && ol < l0) {
+            be = ob;
+            bs = os;
+            bl = ol;
+        }
+        a.bound[i] = bl;
+        a.loc[(uint64_t)(2 * a.ne) * a.R + i] = a.e[be].ci_off + bs;
+        a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] = be;
+        other = all - bl;
     }
     if (!a.part) return;  // list-length totals are gathered for profiling only
     __shared__ uint64_t s_o[QT / 64];
@@ -458,14 +483,14 @@ __device__ __forceinline__ TileRows stage_rows(const LevelArgs &a, uint64_t tile
     if (t.staged) {
         for (uint32_t r = threadIdx.x; r < nr; r += QT) {
             s_F[r] = a.F[t.r_lo + r];
-            s_st[r] = a.loc[(uint64_t)a.e0 * a.R + t.r_lo + r];
+            s_st[r] = a.loc[(uint64_t)(2 * a.ne) * a.R + t.r_lo + r];
         }
         __syncthreads();
     }
     return t;
 }
 
-// row i holding slot p, with F[i] and the ci start of its first-edge list
+// row i holding slot p, with F[i] and the start (in ci_all) of its scanned list
 __device__ __forceinline__ void find_row(const LevelArgs &a, const TileRows &t, const uint64_t *s_F,
                                          const uint32_t *s_st, uint64_t p, uint64_t *i, uint64_t *Fi, uint32_t *st) {
     if (t.staged) {
@@ -481,7 +506,7 @@ __device__ __forceinline__ void find_row(const LevelArgs &a, const TileRows &t, 
     } else {
         *i = row_of(a.F, t.r_lo, t.r_hi, p);
         *Fi = a.F[*i];
-        *st = a.loc[(uint64_t)a.e0 * a.R + *i];
+        *st = a.loc[(uint64_t)(2 * a.ne) * a.R + *i];
     }
 }
 
@@ -493,7 +518,7 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
     __shared__ uint32_t s_st[TS];
     const uint64_t p0 = (uint64_t)blockIdx.x * TS;
     const TileRows tr = stage_rows<SPT>(a, blockIdx.x, s_F, s_st);
-    const uint32_t *ci0 = a.e[a.e0].ci;
+    const uint32_t *ci0 = a.ci_all;
     uint64_t ri[SPT];
     uint32_t xs[SPT];
     bool kp[SPT];
@@ -522,8 +547,9 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
         const uint64_t i = ri[r];
         const uint32_t x = xs[r];
         for (uint32_t c = 0; keep && c < a.j; c++) keep = a.M[(uint64_t)c * a.R + i] != x;
+        const uint32_t be = (keep && a.ne > 1) ? a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] : a.e0;
         for (uint32_t e = 0; keep && e < a.ne; e++) {
-            if (e == a.e0) continue;
+            if (e == be) continue;
             uint32_t st = a.loc[(uint64_t)e * a.R + i];
             uint32_t len = a.loc[(uint64_t)(a.ne + e) * a.R + i];
             keep = in_sorted(a.e[e].ci + st, len, x);
@@ -583,7 +609,7 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
     const uint64_t tbase = a.tile_off[tile];
     const bool stage = a.final_level && !a.count_only && a.k <= LINK_STAGE_K;
-    const uint32_t *ci0 = a.e[a.e0].ci;
+    const uint32_t *ci0 = a.ci_all;
     uint64_t hs = 0, hx = 0;
     for (uint32_t r = 0; r < SPT; r++) {
         const uint32_t wi = r * (QT / 64) + w;
@@ -796,9 +822,11 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     auto t0 = std::chrono::steady_clock::now();
     const uint32_t k = q.k;
     const uint32_t flags = opt ? opt->flags : 0u;
-    if (flags & ~(GSI_COUNT_ONLY | GSI_FILTER_LABEL_ONLY | GSI_NO_FUSED | GSI_NO_CHUNKS))
+    if (flags & ~(GSI_COUNT_ONLY | GSI_FILTER_LABEL_ONLY | GSI_NO_FUSED | GSI_NO_CHUNKS | GSI_LEVEL_FIRST_EDGE))
         fail(GSI_E_INVALID, "unknown query flag");
     const bool count_only = (flags & GSI_COUNT_ONLY) != 0;
+    // each row scans its shortest linking list unless the first edge is fixed
+    const bool per_row = !(flags & GSI_LEVEL_FIRST_EDGE) && !(opt && opt->first_edge);
     const uint64_t max_rows = opt ? opt->max_rows : 0;
 
     std::vector<uint32_t> order, e0src;
@@ -954,6 +982,8 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         hp->count_only = count_only ? 1u : 0u;
         hp->cap_rows = cap_rows;
         hp->cap_slots = cap_slots;
+        hp->pick = per_row ? 1u : 0u;
+        hp->ci_all = g->ci;
         for (uint32_t v = 0; v < k; v++) hp->qcol[v] = col[v];
         uint32_t ei = 0;
         for (uint32_t j = 1; j < k; j++) {
@@ -970,6 +1000,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
                         fe.G = g->G[l];
                         fe.H = g->H[l];
                         fe.col = i;
+                        fe.ci_off = (uint32_t)g->ci_base[l];
                         if (order[i] == e0src[j]) hp->lv_e0[j] = ne;
                         ne++;
                     }
@@ -1041,7 +1072,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     const uint32_t chunk_min = (opt && opt->chunk_min_rows) ? opt->chunk_min_rows : CHUNK_MIN_ROWS;
     if (!(flags & GSI_NO_FUSED) && !(flags & GSI_NO_CHUNKS) && R >= chunk_min) {
         const FTier t = fused_tier(256);
-        const uint64_t slot_words = 2ull * t.cap_rows * k + 2ull * (k - 1) * t.cap_rows;
+        const uint64_t slot_words = 2ull * t.cap_rows * k + fused_loc_words(k, t.cap_rows);
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || ncu < 1)
             ncu = 1;
@@ -1148,7 +1179,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
             FPlan *dplan = fused_plan(cap_rows, cap_slots, &hp);
             uint32_t *buf0 = fs.get<uint32_t>((uint64_t)cap_rows * k, "fused table 0");
             uint32_t *buf1 = fs.get<uint32_t>((uint64_t)cap_rows * k, "fused table 1");
-            uint32_t *floc = fs.get<uint32_t>(2ull * (k - 1) * cap_rows, "fused lookups");
+            uint32_t *floc = fs.get<uint32_t>(fused_loc_words(k, cap_rows), "fused lookups");
             FStatus *dst = reinterpret_cast<FStatus *>(fs.get<uint64_t>(sizeof(FStatus) / 8, "fused status"));
             fill_u64(c, reinterpret_cast<uint64_t *>(dst), 0, sizeof(FStatus) / 8);
             uint32_t *out = count_only ? nullptr : persist<uint32_t>(c, (uint64_t)cap_slots * k, "result rows");
@@ -1210,6 +1241,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
                     er.G = g->G[l];
                     er.H = g->H[l];
                     er.col = i;
+                    er.ci_off = (uint32_t)g->ci_base[l];
                     if (order[i] == e0src[j]) a.e0 = ne;
                     ne++;
                 }
@@ -1220,7 +1252,9 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         a.count_only = count_only ? 1u : 0u;
 
         Scratch ls(c);
-        a.loc = ls.get<uint32_t>(2ull * ne * R, "located lists");
+        a.ci_all = g->ci;
+        a.pick = per_row ? 1u : 0u;
+        a.loc = ls.get<uint32_t>((2ull * ne + 2) * R, "located lists");
         a.bound = ls.get<uint32_t>(R, "row bounds");
         uint64_t *F = ls.get<uint64_t>(R + 1, "offsets F");
         a.F = F;

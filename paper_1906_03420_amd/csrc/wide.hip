@@ -31,9 +31,13 @@ constexpr uint32_t WT = 256;
 struct WEdge {
     const uint32_t *gl;
     const uint32_t *ci;
-    uint32_t G, H, col, pad;
+    uint32_t G, H, col;
+    uint32_t ci_off;  // offset of its label's lists in the whole ci array
 };
 
+// Lookups of a query's rows at loc + locbase: start of linking edge e at
+// [e*R + i], length at [(ne+e)*R + i], start (in the whole ci array) of the
+// list the row scans at [2ne*R + i] and that list's edge at [(2ne+1)*R + i].
 struct WQ {
     const uint32_t *M;  // table, column c at M + c*R
     uint64_t R, rbase, locbase;
@@ -62,6 +66,8 @@ __device__ __forceinline__ uint32_t query_of(const WQ *qs, uint32_t lo, uint32_t
     return lo;
 }
 
+// Each row scans its shortest linking list (e0's on ties): the survivors,
+// and their order, are those of the first edge of Algorithm 4.
 __global__ __launch_bounds__(WT) void k_wlocate(const WQ *qs, uint32_t nq, const WEdge *edges, uint64_t Rtot,
                                                uint32_t *loc, uint32_t *bound) {
     __shared__ uint32_t s_q[2];
@@ -76,14 +82,31 @@ __global__ __launch_bounds__(WT) void k_wlocate(const WQ *qs, uint32_t nq, const
     if (r >= Rtot) return;
     const WQ &Q = qs[query_of(qs, s_q[0], s_q[1], r)];
     const uint64_t i = r - Q.rbase;
+    uint32_t s0 = 0, l0 = 0, ob = NONE32, os = 0, ol = 0xFFFFFFFFu;
     for (uint32_t e = 0; e < Q.ne; e++) {
         const WEdge &ed = edges[Q.efirst + e];
         const uint32_t v = Q.M[(uint64_t)ed.col * Q.R + i];
         const uint2 f = pcsr_find(ed.gl, ed.G, ed.H, v);
         loc[Q.locbase + (uint64_t)e * Q.R + i] = f.x;
         loc[Q.locbase + (uint64_t)(Q.ne + e) * Q.R + i] = f.y;
-        if (e == Q.e0) bound[r] = f.y;
+        if (e == Q.e0) {
+            s0 = f.x;
+            l0 = f.y;
+        } else if (f.y < ol) {
+            ob = e;
+            os = f.x;
+            ol = f.y;
+        }
     }
+    uint32_t be = Q.e0, bs = s0, bl = l0;
+    if (ob != NONE32 && ol < l0) {
+        be = ob;
+        bs = os;
+        bl = ol;
+    }
+    bound[r] = bl;
+    loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + i] = edges[Q.efirst + be].ci_off + bs;
+    loc[Q.locbase + (uint64_t)(2 * Q.ne + 1) * Q.R + i] = be;
 }
 
 // A tile's rows usually belong to one query: then that query's descriptor
@@ -117,7 +140,7 @@ __device__ __forceinline__ WTile stage_wtile(const WQ *qs, uint32_t nq, const ui
         uint32_t *dst = reinterpret_cast<uint32_t *>(s_Q);
         for (uint32_t w = threadIdx.x; w < sizeof(WQ) / 4; w += WT) dst[w] = src[w];
         if (t.staged && threadIdx.x < t.nr)
-            s_st[threadIdx.x] = loc[Q.locbase + (uint64_t)Q.e0 * Q.R + (t.r_lo + threadIdx.x - Q.rbase)];
+            s_st[threadIdx.x] = loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + (t.r_lo + threadIdx.x - Q.rbase)];
     }
     __syncthreads();
     return t;
@@ -151,9 +174,9 @@ __device__ __forceinline__ void wfind(const WQ *qs, const uint64_t *F, const WTi
     *q = t.one ? s_q[0] : query_of(qs, s_q[0], s_q[1], *r);
 }
 
-__global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, uint32_t nq, const WEdge *edges, const uint64_t *F,
-                                             const uint64_t *tile_row, uint64_t gba, const uint32_t *loc,
-                                             uint64_t *bitmap, uint32_t *tile_cnt) {
+__global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, uint32_t nq, const WEdge *edges, const uint32_t *ci_all,
+                                             const uint64_t *F, const uint64_t *tile_row, uint64_t gba,
+                                             const uint32_t *loc, uint64_t *bitmap, uint32_t *tile_cnt) {
     __shared__ uint64_t s_F[WT];
     __shared__ uint32_t s_st[WT];
     __shared__ WQ s_Q;
@@ -169,13 +192,13 @@ __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, uint32_t nq, const W
         wfind(qs, F, t, s_F, s_q, p, &r, &Fr, &lr, &qi);
         const WQ &Q = t.one ? s_Q : qs[qi];
         const uint64_t i = r - Q.rbase;
-        const WEdge &E0 = edges[Q.efirst + Q.e0];
-        const uint32_t st0 = (t.one && t.staged) ? s_st[lr] : loc[Q.locbase + (uint64_t)Q.e0 * Q.R + i];
-        const uint32_t x = E0.ci[st0 + (uint32_t)(p - Fr)];
+        const uint32_t st0 = (t.one && t.staged) ? s_st[lr] : loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + i];
+        const uint32_t x = ci_all[st0 + (uint32_t)(p - Fr)];
         keep = (Q.Cu[x >> 6] >> (x & 63)) & 1ull;
         for (uint32_t c = 0; keep && c < Q.j; c++) keep = Q.M[(uint64_t)c * Q.R + i] != x;
+        const uint32_t be = (keep && Q.ne > 1) ? loc[Q.locbase + (uint64_t)(2 * Q.ne + 1) * Q.R + i] : Q.e0;
         for (uint32_t e = 0; keep && e < Q.ne; e++) {
-            if (e == Q.e0) continue;
+            if (e == be) continue;
             keep = in_sorted(edges[Q.efirst + e].ci + loc[Q.locbase + (uint64_t)e * Q.R + i],
                              loc[Q.locbase + (uint64_t)(Q.ne + e) * Q.R + i], x);
         }
@@ -226,7 +249,7 @@ __global__ __launch_bounds__(WT) void k_wsurv(const WQ *qs, uint32_t nq, const u
 // contiguous block when k is at most this
 constexpr uint32_t WLINK_STAGE_K = 16;
 
-__global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, uint32_t nq, const WEdge *edges, const uint64_t *F,
+__global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, uint32_t nq, const uint32_t *ci_all, const uint64_t *F,
                                              const uint64_t *tile_row, const uint32_t *loc, const uint64_t *bitmap,
                                              const uint64_t *tile_off, uint64_t *hv) {
     __shared__ uint64_t s_F[WT];
@@ -255,9 +278,9 @@ __global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, uint32_t nq, const W
         const uint64_t i = r - Q.rbase;
         const uint64_t pos = gpos - Q.sbase;
         if (pos < Q.S) {  // always, when the survivor ranges are consistent
-            const WEdge &E0 = edges[Q.efirst + Q.e0];
-            const uint32_t st0 = (t.one && t.staged) ? s_st[lr] : loc[Q.locbase + (uint64_t)Q.e0 * Q.R + i];
-            const uint32_t x = E0.ci[st0 + (uint32_t)(p - Fr)];
+            const uint32_t st0 =
+                (t.one && t.staged) ? s_st[lr] : loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + i];
+            const uint32_t x = ci_all[st0 + (uint32_t)(p - Fr)];
             if (!Q.final_level) {
                 for (uint32_t c = 0; c < Q.j; c++) Q.Mn[(uint64_t)c * Q.S + pos] = Q.M[(uint64_t)c * Q.R + i];
                 Q.Mn[(uint64_t)Q.j * Q.S + pos] = x;
@@ -371,7 +394,7 @@ static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool co
                         ed.G = g->G[l];
                         ed.H = g->H[l];
                         ed.col = i;
-                        ed.pad = 0;
+                        ed.ci_off = (uint32_t)g->ci_base[l];
                         if (x.order[i] == x.e0src[j]) Q.e0 = Q.ne;
                         he.push_back(ed);
                         Q.ne++;
@@ -380,7 +403,7 @@ static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool co
             for (uint32_t v = 0; v < q.k; v++) Q.qcol[v] = x.col[v];
             x.stats_rows[j] = x.R;
             Rtot += x.R;
-            loctot += 2ull * Q.ne * x.R;
+            loctot += (2ull * Q.ne + 2) * x.R;
         }
         WQ *d_q = s.get<WQ>(nq, "wide queries");
         WEdge *d_e = s.get<WEdge>(he.size(), "wide edges");
@@ -416,7 +439,8 @@ static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool co
         double jb = 4.0 * gba + gba / 8.0 + 4.0 * ntiles;
         for (auto &Q : hq) jb += (double)Q.R * (8.0 + 8.0 * Q.ne + 4.0 * Q.j);
         launch(c, "k_wjoin", jb, k_wjoin, (uint32_t)ntiles, WT, (const WQ *)d_q, nq, (const WEdge *)d_e,
-               (const uint64_t *)F, (const uint64_t *)trow, gba, (const uint32_t *)loc, bitmap, tcnt);
+               (const uint32_t *)g->ci, (const uint64_t *)F, (const uint64_t *)trow, gba, (const uint32_t *)loc, bitmap,
+               tcnt);
         exclusive_scan(c, tcnt, ntiles, toff, s, scal + 1);
         launch(c, "k_wsurv", 48.0 * nq, k_wsurv, wblocks(nq), WT, (const WQ *)d_q, nq, (const uint64_t *)F,
                (const uint64_t *)bitmap, (const uint64_t *)toff, gba, sb);
@@ -461,7 +485,7 @@ static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool co
         }
         uint64_t *hv = any_final ? s.get<uint64_t>(Stot, "wide row hashes") : nullptr;
         GSI_HIP(hipMemcpyAsync(d_q, hq.data(), sizeof(WQ) * nq, hipMemcpyHostToDevice, c->stream));
-        launch(c, "k_wlink", kb, k_wlink, (uint32_t)ntiles, WT, (const WQ *)d_q, nq, (const WEdge *)d_e,
+        launch(c, "k_wlink", kb, k_wlink, (uint32_t)ntiles, WT, (const WQ *)d_q, nq, (const uint32_t *)g->ci,
                (const uint64_t *)F, (const uint64_t *)trow, (const uint32_t *)loc, (const uint64_t *)bitmap,
                (const uint64_t *)toff, hv);
         std::vector<uint64_t> part;

@@ -185,6 +185,7 @@ def test_edge_cases(ctx):
 
 
 def test_levels_match_spec(ctx):
+    import paper_1906_03420_amd as gsi
     g = w.config_graph("er1k")
     dg = ctx.load(g)
     sig = spec.signature_table(g)
@@ -193,15 +194,18 @@ def test_levels_match_spec(ctx):
     for i in range(8):
         q = w.config_query(g, "er1k", i, maker=mk)
         cands = spec.filter_candidates(sig, spec.query_signatures(q))
-        r = dg.query(q)
-        st = r.stats()
         order, e0 = spec.plan(q, [len(c) for c in cands], spec.label_frequency(g))
-        assert st["order"] == order
-        assert st["first_edge"][1:] == e0[1:]
-        M, lev = spec.join_levels(g, q, cands, order, e0, nb)
-        for j, L in enumerate(lev, start=1):
-            assert (st["rows"][j], st["gba"][j], st["survivors"][j]) == (L["R"], L["GBA"], L["S"])
-        r.free()
+        # Algorithm 4's first edge for every row, then each row's shortest list
+        for flags, per_row in ((gsi.GSI_LEVEL_FIRST_EDGE, False), (0, True)):
+            r = dg.query(q, flags=flags)
+            st = r.stats()
+            assert st["order"] == order
+            assert st["first_edge"][1:] == e0[1:]
+            M, lev = spec.join_levels(g, q, cands, order, e0, nb, per_row=per_row)
+            for j, L in enumerate(lev, start=1):
+                assert (st["rows"][j], st["gba"][j], st["survivors"][j]) == (L["R"], L["GBA"], L["S"])
+            np.testing.assert_array_equal(r.rows(), spec.to_query_order(M, order))
+            r.free()
     dg.free()
 
 

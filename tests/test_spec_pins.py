@@ -206,6 +206,12 @@ def test_join_levels_equal_oracle(seed):
             inC &= np.isin(rows[:, i], cands[u])
         assert L["R"] == int(inC.sum())
         assert L["S"] <= L["GBA"]
+    # scanning each row's shortest linking list: same table, same row order,
+    # no larger pre-allocation, and exactly the sum of per-row minima
+    M2, lev2 = spec.join_levels(g, q, cands, order, e0, per_row=True)
+    assert M2 == M
+    for a, b in zip(lev, lev2):
+        assert (a["R"], a["S"]) == (b["R"], b["S"]) and b["GBA"] <= a["GBA"]
 
 
 def test_plan_prefix_connected_and_e0_linking():

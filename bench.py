@@ -40,6 +40,40 @@ HBM_PEAK_GBS = 8000.0
 # the fused workgroup that runs locate/join/link for small tables
 HOT_KERNELS = ("k_filter", "k_locate", "k_join", "k_link", "k_fused_levels")
 
+# sources each kernel is compiled from: the stored HBM counter readings of a
+# kernel (profiles/traffic.json) are used only while these files are unchanged
+CSRC = os.path.join(ROOT, "paper_1906_03420_amd", "csrc")
+KERNEL_SOURCES = {
+    "k_fused_levels": ("fused.hip", "fused.h", "join_device.h", "gsi_internal.h"),
+    "k_fused_chunks": ("fused.hip", "fused.h", "join_device.h", "gsi_internal.h"),
+    "k_filter": ("query.hip", "gsi_internal.h"),
+    "k_locate": ("query.hip", "join_device.h", "gsi_internal.h"),
+    "k_join": ("query.hip", "join_device.h", "gsi_internal.h"),
+    "k_link": ("query.hip", "join_device.h", "gsi_internal.h"),
+}
+
+
+def sources_digest(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kernel, ()):
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, scaled by the copy
+    probe) from the committed counter runs, or None when the kernel's
+    sources changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get("kernels", {}).get(kernel)
+    if not rec or rec.get("sources_sha256") != sources_digest(kernel):
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 WORKLOAD_TEXT = {
     "ba1m": "BA graph 1,000,000 vertices / 9,999,945 edges, 32 vertex labels Zipf(1.1), 8 edge labels uniform; "
             "100 random-walk queries of 6-12 vertices; single-query path",
@@ -393,7 +427,8 @@ def main():
         parity=("bit-exact counts+digests vs oracle, %d/%d queries" % (len(qs), len(qs))) if parity_ok
         else ("MISMATCH" if parity_ok is False else "no stored oracle values"),
         roofline=dict(kernel=dom["name"], bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=achieved / HBM_PEAK_GBS, traffic=None, launches=dom["launches"],
+                      frac=achieved / HBM_PEAK_GBS, traffic=stored_traffic(dom["name"]),
+                      alg_bytes_per_launch=dom["alg_bytes"] / dom["launches"], launches=dom["launches"],
                       avg_launch_us=dom["total_ms"] / dom["launches"] * 1e3,
                       share_of_device_time=dom["total_ms"] / dev_ms if dev_ms else None,
                       measured="HIP events around every launch in %d profiled steps (%.1f ms/step with events)"

@@ -165,6 +165,10 @@ gsi_status gsi_graph_copy_pcsr(const gsi_graph *g, uint32_t label, uint32_t *hos
 #define GSI_LEVEL_FIRST_EDGE 0x20u /* every row of a level scans the list of the
                                       level's first edge e0 (Algorithm 4), not
                                       its shortest linking list */
+#define GSI_HOMOMORPHISM 0x40u     /* homomorphism semantics (Sec. VII-A): query
+                                      vertices may share a data vertex; the join
+                                      drops the subtraction of m_i and the filter
+                                      asks for one neighbour per signature group */
 
 /* Optional controls of one query run (NULL = defaults). */
 typedef struct {

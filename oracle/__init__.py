@@ -68,7 +68,7 @@ def _load():
         lib.oracle_graph_free.argtypes = [ctypes.c_void_p]
         lib.oracle_graph_free.restype = None
         lib.oracle_match.argtypes = [ctypes.c_void_p, ctypes.c_uint32, U32P, ctypes.c_uint32, U32P, U32P, U32P,
-                                     ctypes.c_uint32, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                     ctypes.c_uint32, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
                                      ctypes.POINTER(OracleResultC)]
         lib.oracle_match.restype = ctypes.c_int
         lib.oracle_free.argtypes = [ctypes.c_void_p]
@@ -136,7 +136,10 @@ class OracleGraph:
     def __del__(self):
         self.close()
 
-    def match(self, q, threads: int = 1, tuples: bool = True, max_count: int = 0, max_nodes: int = 0) -> MatchResult:
+    def match(self, q, threads: int = 1, tuples: bool = True, max_count: int = 0, max_nodes: int = 0,
+              homomorphism: bool = False) -> MatchResult:
+        """All embeddings of q (Definitions 1-3), or, with homomorphism, all
+        label- and edge-preserving maps, injective or not (Sec. VII-A)."""
         lib = _load()
         ql, qlp = _p(q.vlabel)
         qs, qsp = _p(q.src)
@@ -144,7 +147,7 @@ class OracleGraph:
         qe, qep = _p(q.elabel)
         r = OracleResultC()
         lib.oracle_match(self._h, q.k, qlp, qs.shape[0], qsp, qdp, qep, threads, 1 if tuples else 0,
-                         max_count, max_nodes, ctypes.byref(r))
+                         max_count, max_nodes, 1 if homomorphism else 0, ctypes.byref(r))
         t = None
         if r.tuples:
             if r.status == OR_OK:

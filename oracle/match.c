@@ -12,6 +12,11 @@
  * Non-edges of Q are not constrained (the join of Sec. V checks query edges
  * only).  The result is the set of all such maps, one row per map.
  *
+ * Homomorphism mode (Sec. VII-A): condition (1) is dropped, so two query
+ * vertices may share a data vertex (adjacent ones cannot, G having no
+ * self-loops).  The degree pruning below is dropped with it, since query
+ * neighbours may then share one data neighbour.
+ *
  * The search is the textbook tree search with backtracking the paper contrasts
  * its method with (Sec. I).  The first query vertex is the one whose label is
  * rarest in G; each next one is an unplaced vertex with the most already-placed
@@ -165,6 +170,7 @@ static int64_t edge_label(const og_graph *g, uint32_t a, uint32_t b) {
 #define MAXK 64
 typedef struct {
     uint32_t k;
+    int homo;                  /* homomorphism mode */
     uint32_t qlabel[MAXK];
     uint32_t qdeg[MAXK];
     uint32_t order[MAXK];      /* order[d] = query vertex placed at depth d */
@@ -228,9 +234,9 @@ static void dfs(worker_t *w, uint32_t d) {
         uint32_t x = g->adj[i];
         w->nodes++;
         if (g->vlabel[x] != p->qlabel[u]) continue;
-        if (g->rp[x + 1] - g->rp[x] < p->qdeg[u]) continue;
+        if (!p->homo && g->rp[x + 1] - g->rp[x] < p->qdeg[u]) continue;
         int ok = 1;
-        for (uint32_t e = 0; e < d; e++) if (w->f[p->order[e]] == x) { ok = 0; break; }
+        for (uint32_t e = 0; !p->homo && e < d; e++) if (w->f[p->order[e]] == x) { ok = 0; break; }
         for (uint32_t c = 0; ok && c < p->nlink[d]; c++)
             if (c != src && edge_label(g, w->f[p->link_u[d][c]], x) != (int64_t)p->link_l[d][c]) ok = 0;
         if (!ok) continue;
@@ -275,12 +281,13 @@ static pthread_mutex_t g_sort_lock = PTHREAD_MUTEX_INITIALIZER;
  * meaningless. */
 int oracle_match(const og_graph *g, uint32_t k, const uint32_t *qlabel, uint32_t qm, const uint32_t *qsrc,
                  const uint32_t *qdst, const uint32_t *qelabel, uint32_t nthreads, int want_tuples,
-                 uint64_t max_count, uint64_t max_nodes, oracle_result *out) {
+                 uint64_t max_count, uint64_t max_nodes, int homomorphism, oracle_result *out) {
     memset(out, 0, sizeof(*out));
     if (k < 1 || k > MAXK || nthreads < 1) return out->status = OR_INVALID;
     plan_t *p = (plan_t *)calloc(1, sizeof(plan_t));
     if (!p) return out->status = OR_NOMEM;
     p->k = k;
+    p->homo = homomorphism ? 1 : 0;
     uint8_t adjq[MAXK][MAXK];
     int32_t lq[MAXK][MAXK];
     memset(adjq, 0, sizeof(adjq));
@@ -337,7 +344,7 @@ int oracle_match(const og_graph *g, uint32_t k, const uint32_t *qlabel, uint32_t
     uint64_t nroots = 0;
     uint32_t *roots = (uint32_t *)malloc((size_t)g->n * 4 + 4);
     for (uint32_t v = 0; v < g->n; v++)
-        if (g->vlabel[v] == qlabel[u0] && g->rp[v + 1] - g->rp[v] >= p->qdeg[u0]) roots[nroots++] = v;
+        if (g->vlabel[v] == qlabel[u0] && (p->homo || g->rp[v + 1] - g->rp[v] >= p->qdeg[u0])) roots[nroots++] = v;
 
     volatile int stop = 0;
     worker_t *ws = (worker_t *)calloc(nthreads, sizeof(worker_t));

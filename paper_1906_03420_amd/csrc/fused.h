@@ -25,7 +25,8 @@ inline uint64_t fused_loc_words(uint32_t k, uint64_t rows) { return 2ull * k * r
 
 struct FPlan {
     uint32_t k, count_only, cap_rows, cap_slots;
-    uint32_t pick, pad;           // 1: each row scans its shortest linking list
+    uint32_t pick;                // 1: each row scans its shortest linking list
+    uint32_t homo;                // 1: homomorphism (no subtraction of m_i)
     const uint32_t *ci_all;       // every label's lists
     uint32_t qcol[GSI_MAX_K];     // query vertex -> column
     uint32_t lv_ne[GSI_MAX_K];    // level j: linking edges

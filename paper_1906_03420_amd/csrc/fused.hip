@@ -175,7 +175,7 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
                 const uint32_t i = lds_row(s_F, R, p);
                 const uint32_t x = ci_all[loc[(uint64_t)(2 * ne) * R + i] + (p - s_F[i])];
                 keep = (Cu[x >> 6] >> (x & 63)) & 1ull;
-                for (uint32_t c = 0; keep && c < j; c++) keep = M[(uint64_t)c * R + i] != x;
+                for (uint32_t c = 0; keep && !plan->homo && c < j; c++) keep = M[(uint64_t)c * R + i] != x;
                 const uint32_t be = (keep && ne > 1) ? loc[(uint64_t)(2 * ne + 1) * R + i] : e0;
                 for (uint32_t e = 0; keep && e < ne; e++) {
                     if (e == be) continue;

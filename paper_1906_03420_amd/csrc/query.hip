@@ -98,7 +98,10 @@ struct FilterArgs {
 };
 
 // Query signatures with the same encoding as the data table (Sec. III-A).
-static void query_signatures(const HostQuery &q, FilterArgs &fa) {
+// Under homomorphism two query neighbours with one (edge label, vertex
+// label) key may map to one data neighbour, so a group asks for one
+// neighbour at most (code 01): the "two or more" code would not be sound.
+static void query_signatures(const HostQuery &q, FilterArgs &fa, bool homo = false) {
     memset(&fa, 0, sizeof(fa));
     fa.k = q.k;
     for (uint32_t u = 0; u < q.k; u++) {
@@ -107,7 +110,7 @@ static void query_signatures(const HostQuery &q, FilterArgs &fa) {
         uint32_t cnt[SIG_GROUPS] = {0};
         for (auto &p : q.adj[u]) cnt[sig_group(p.second, q.vl[p.first])]++;
         for (uint32_t g = 0; g < SIG_GROUPS; g++)
-            if (cnt[g]) fa.q[u][1 + g / 16] |= (cnt[g] == 1 ? 1u : 3u) << (2 * (g % 16));
+            if (cnt[g]) fa.q[u][1 + g / 16] |= (cnt[g] == 1 || homo ? 1u : 3u) << (2 * (g % 16));
         for (int i = 1; i < GSI_SIG_WORDS; i++)
             if (fa.q[u][i]) fa.word_mask |= 1u << i;
     }
@@ -311,10 +314,11 @@ void run_filter_many(gsi_graph *g, const std::vector<const HostQuery *> &qs, con
     sync(c);  // `passes` is read by the copy above
 }
 
-static void filter_impl(gsi_graph *g, const HostQuery &q, bool label_only, uint64_t *bits, uint32_t *counts) {
+static void filter_impl(gsi_graph *g, const HostQuery &q, bool label_only, uint64_t *bits, uint32_t *counts,
+                        bool homo = false) {
     gsi_ctx *c = g->ctx;
     FilterArgs fa;
-    query_signatures(q, fa);
+    query_signatures(q, fa, homo);
     fa.label_only = label_only ? 1u : 0u;
     Scratch s(c);
     uint32_t *part = s.get<uint32_t>((uint64_t)nblocks(g->n) * GSI_MAX_K, "filter partial counts");
@@ -356,6 +360,7 @@ struct LevelArgs {
     uint64_t R;
     uint32_t j, ne, e0, k;
     uint32_t pick;  // 1: each row scans its shortest linking list (else e0's)
+    uint32_t homo;  // 1: homomorphism (no subtraction of m_i, Sec. VII-A)
     EdgeRef e[GSI_MAX_K];
     const uint32_t *ci_all;  // every label's lists
     const uint64_t *Cu;
@@ -546,7 +551,7 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
         bool keep = kp[r];
         const uint64_t i = ri[r];
         const uint32_t x = xs[r];
-        for (uint32_t c = 0; keep && c < a.j; c++) keep = a.M[(uint64_t)c * a.R + i] != x;
+        for (uint32_t c = 0; keep && !a.homo && c < a.j; c++) keep = a.M[(uint64_t)c * a.R + i] != x;
         const uint32_t be = (keep && a.ne > 1) ? a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] : a.e0;
         for (uint32_t e = 0; keep && e < a.ne; e++) {
             if (e == be) continue;
@@ -822,9 +827,11 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     auto t0 = std::chrono::steady_clock::now();
     const uint32_t k = q.k;
     const uint32_t flags = opt ? opt->flags : 0u;
-    if (flags & ~(GSI_COUNT_ONLY | GSI_FILTER_LABEL_ONLY | GSI_NO_FUSED | GSI_NO_CHUNKS | GSI_LEVEL_FIRST_EDGE))
+    if (flags & ~(GSI_COUNT_ONLY | GSI_FILTER_LABEL_ONLY | GSI_NO_FUSED | GSI_NO_CHUNKS | GSI_LEVEL_FIRST_EDGE |
+                  GSI_HOMOMORPHISM))
         fail(GSI_E_INVALID, "unknown query flag");
     const bool count_only = (flags & GSI_COUNT_ONLY) != 0;
+    const bool homo = (flags & GSI_HOMOMORPHISM) != 0;
     // each row scans its shortest linking list unless the first edge is fixed
     const bool per_row = !(flags & GSI_LEVEL_FIRST_EDGE) && !(opt && opt->first_edge);
     const uint64_t max_rows = opt ? opt->max_rows : 0;
@@ -895,7 +902,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     uint32_t *dcnt = s.get<uint32_t>(k, "candidate counts");
     uint64_t *dscal = s.get<uint64_t>(4, "level scalars");
     auto tf = std::chrono::steady_clock::now();
-    filter_impl(g, q, (flags & GSI_FILTER_LABEL_ONLY) != 0, bits, dcnt);
+    filter_impl(g, q, (flags & GSI_FILTER_LABEL_ONLY) != 0, bits, dcnt, homo);
     std::vector<uint32_t> cand(k);
     {
         uint64_t tmp[GSI_MAX_K / 2 + 1];
@@ -983,6 +990,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         hp->cap_rows = cap_rows;
         hp->cap_slots = cap_slots;
         hp->pick = per_row ? 1u : 0u;
+        hp->homo = homo ? 1u : 0u;
         hp->ci_all = g->ci;
         for (uint32_t v = 0; v < k; v++) hp->qcol[v] = col[v];
         uint32_t ei = 0;
@@ -1254,6 +1262,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         Scratch ls(c);
         a.ci_all = g->ci;
         a.pick = per_row ? 1u : 0u;
+        a.homo = homo ? 1u : 0u;
         a.loc = ls.get<uint32_t>((2ull * ne + 2) * R, "located lists");
         a.bound = ls.get<uint32_t>(R, "row bounds");
         uint64_t *F = ls.get<uint64_t>(R + 1, "offsets F");

@@ -331,3 +331,56 @@ def test_fused_path_er1k_and_count_only(ctx):
             a.free(); b.free()
     live, _ = ctx.memory()
     dg.free()
+
+
+# ------------------------------------------------------------- homomorphism
+@pytest.mark.parametrize("seed", range(8))
+def test_homomorphism_matches_oracle(ctx, seed):
+    """Homomorphism semantics (Sec. VII-A) through every join route."""
+    import paper_1906_03420_amd as gsi
+    r = np.random.default_rng(3000 + seed)
+    n = int(r.integers(20, 200))
+    g = w.random_small_graph(n, float(r.uniform(0.03, 0.12)), int(r.integers(1, 3)), int(r.integers(1, 3)), seed + 40)
+    if g.m == 0:
+        return
+    dg = ctx.load(g)
+    og = oracle.OracleGraph(g)
+    H = gsi.GSI_HOMOMORPHISM
+    for t in range(3):
+        q = w.random_connected_query(int(r.integers(2, 7)), int(r.integers(0, 3)), int(g.vlabel.max()) + 1,
+                                     int(g.elabel.max()) + 1, seed * 100 + t + 7)
+        want = og.match(q, threads=4, homomorphism=True, max_count=3_000_000)
+        if want.status != 0:
+            continue
+        for mode in (dict(flags=H), dict(flags=H | 4), dict(flags=H | NO_CHUNKS, fused_max_rows=64,
+                     fused_max_slots=128), dict(flags=H, chunk_min_rows=1, chunk_rows=2),
+                     dict(flags=H | gsi.GSI_LEVEL_FIRST_EDGE)):
+            print("homomorphism seed", seed, "query", t, "k", q.k, "mode", mode, flush=True)
+            res = dg.query(q, **mode)
+            assert (res.count, res.digest) == (want.count, want.digest)
+            np.testing.assert_array_equal(res.sorted_rows(), want.tuples)
+            res.free()
+    dg.free()
+
+
+def test_homomorphism_closed_forms(ctx):
+    import paper_1906_03420_amd as gsi
+    H = gsi.GSI_HOMOMORPHISM
+    n = 9
+    dg = ctx.load(w.complete_graph(n))
+    for k in range(2, 8):
+        for q in (w.path_query(k), w.star_query(k)):
+            r = dg.query(q, flags=H | gsi.GSI_COUNT_ONLY)
+            assert r.count == n * (n - 1) ** (k - 1)
+            r.free()
+        if k >= 3:
+            r = dg.query(w.cycle_query(k), flags=H | gsi.GSI_COUNT_ONLY)
+            assert r.count == (n - 1) ** k + (-1) ** k * (n - 1)
+            r.free()
+    dg.free()
+    dg = ctx.load(w.cycle_graph(12))
+    for k in (2, 5, 11):
+        r = dg.query(w.path_query(k), flags=H)
+        assert r.count == 12 * 2 ** (k - 1)
+        r.free()
+    dg.free()

@@ -193,3 +193,54 @@ def test_walk_query_contains_its_source():
         r = oracle.match(g, q)
         assert r.count >= 1
         assert any((r.tuples == q.source).all(axis=1))
+
+
+# ------------------------------------------------------------ homomorphism
+def brute_force_hom(g, q):
+    """Every map V(Q)->V(G), injective or not, that keeps vertex labels and
+    maps each query edge onto a data edge of the same label (Sec. VII-A)."""
+    E = {}
+    for a, b, l in zip(g.src.tolist(), g.dst.tolist(), g.elabel.tolist()):
+        E[frozenset((a, b))] = l
+    out = []
+    for f in itertools.product(range(g.n), repeat=q.k):
+        if any(int(g.vlabel[f[u]]) != int(q.vlabel[u]) for u in range(q.k)):
+            continue
+        if all(f[a] != f[b] and E.get(frozenset((f[a], f[b]))) == l
+               for a, b, l in zip(q.src.tolist(), q.dst.tolist(), q.elabel.tolist())):
+            out.append(f)
+    return np.array(sorted(out), np.uint32).reshape(-1, q.k)
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_oracle_homomorphism_matches_brute_force(seed):
+    r = np.random.default_rng(500 + seed)
+    n = int(r.integers(3, 7))
+    g = w.random_small_graph(n, float(r.uniform(0.3, 0.9)), int(r.integers(1, 3)), int(r.integers(1, 3)), seed)
+    k = int(r.integers(1, 5))
+    q = w.random_connected_query(k, int(r.integers(0, 3)), int(g.vlabel.max()) + 1, int(g.elabel.max()) + 1 if g.m else 1, seed + 2000)
+    want = brute_force_hom(g, q)
+    for threads in (1, 2):
+        got = oracle.match(g, q, threads=threads, homomorphism=True)
+        assert got.status == oracle.OR_OK
+        np.testing.assert_array_equal(got.tuples, want)
+        assert got.digest == oracle.digest_rows(want)
+    # every embedding is a homomorphism
+    inj = oracle.match(g, q)
+    assert inj.count <= len(want)
+
+
+@pytest.mark.parametrize("n", [3, 4, 6, 9])
+def test_homomorphism_closed_forms(n):
+    g = w.complete_graph(n)
+    for k in range(1, 6):
+        # trees into K_n: n (n-1)^(k-1); cycles: the chromatic polynomial of C_k
+        assert oracle.match(g, w.path_query(k), tuples=False, homomorphism=True).count == n * (n - 1) ** (k - 1)
+        assert oracle.match(g, w.star_query(k), tuples=False, homomorphism=True).count == n * (n - 1) ** (k - 1)
+        if k >= 3:
+            want = (n - 1) ** k + (-1) ** k * (n - 1)
+            assert oracle.match(g, w.cycle_query(k), tuples=False, homomorphism=True).count == want
+    c = w.cycle_graph(n + 2)
+    for k in range(1, 7):
+        # a walk of k vertices on a cycle: a start, then two ways each step
+        assert oracle.match(c, w.path_query(k), tuples=False, homomorphism=True).count == (n + 2) * 2 ** (k - 1)

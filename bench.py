@@ -20,6 +20,8 @@ Prints ONE JSON line.  Fields beyond the common contract:
   parity        GPU counts and digests against the stored oracle values
   batched       1,024 mixed queries on the same graph, one at a time vs one
                 batch (fused persistent tiers + level-synchronous engine)
+  ablations     the paper's join ablations and this design's switches on the
+                single-query workload
   serving       the request loop on an R-MAT scale-22 graph: saturation
                 throughput, then Poisson arrivals at 0.5 / 0.8 / 1.2 times it,
                 with p50 / p99 latency (arrival -> answer ready on device)
@@ -191,6 +193,54 @@ def batched_section(args, vl_t, s_t, d_t, l_t, g, arena):
                 else "MISMATCH")
 
 
+def ablation_section(args, vl_t, s_t, d_t, l_t, g, qs, gold, arena):
+    """The paper's ablations (Tables V-VII) on the same 100 queries, one at a
+    time: the per-level kernels as built, then with N(v,l) found by binary
+    search in the compressed representation instead of PCSR, with two-step
+    output instead of Prealloc-Combine, and without LDS-staged row writes;
+    plus this design's own switches (fused small-table workgroup off, the
+    first edge of Algorithm 4 for every row).  Each variant must give the
+    oracle's counts and digests."""
+    import torch
+    import paper_1906_03420_amd as gsi
+    ctx = gsi.Context(arena)
+    dg = ctx.load_device(g.n, vl_t, s_t, d_t, l_t, gsi.GSI_GRAPH_KEEP_CR)
+    variants = [("default", 0), ("level_first_edge", gsi.GSI_LEVEL_FIRST_EDGE), ("per_level", gsi.GSI_NO_FUSED),
+                ("per_level+cr_lookup", gsi.GSI_NO_FUSED | gsi.GSI_ABL_CR),
+                ("per_level+two_step_output", gsi.GSI_NO_FUSED | gsi.GSI_ABL_TWO_STEP),
+                ("per_level+unstaged_rows", gsi.GSI_NO_FUSED | gsi.GSI_ABL_NO_STAGING)]
+
+    def run(flags):
+        out = []
+        t0 = time.perf_counter()
+        for q in qs:
+            r = dg.query(q, flags=flags)
+            out.append((r.count, r.digest))
+            r.free()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    res = {}
+    ok = True
+    for name, flags in variants:
+        run(flags)  # warm-up
+        best = None
+        for _ in range(max(1, args.steps)):
+            dt, out = run(flags)
+            best = dt if best is None else min(best, dt)
+            ok &= all(c == x["count"] and [str(d[0]), str(d[1])] == x["digest"]
+                      for (c, d), x in zip(out, gold["queries"]))
+        res[name] = dict(ms_per_pass=best * 1e3)
+    base = res["per_level"]["ms_per_pass"]
+    for name in res:
+        res[name]["vs_per_level"] = res[name]["ms_per_pass"] / base
+    dg.free()
+    ctx.close()
+    return dict(workload="the single-query workload above (100 queries, rows written), best of %d passes"
+                         % max(1, args.steps), variants=res,
+                parity="bit-exact counts+digests vs oracle in every variant" if ok else "MISMATCH")
+
+
 def progress(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -317,6 +367,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--no-ablations", action="store_true", help="skip the ablation runs")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device copy of this size (a reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -442,6 +493,9 @@ def main():
     if not args.no_batched:
         res["batched"] = batched_section(args, vl_t, s_t, d_t, l_t, g, arena)
         progress("batched section done")
+    if not args.no_ablations and gold:
+        res["ablations"] = ablation_section(args, vl_t, s_t, d_t, l_t, g, qs, gold, arena)
+        progress("ablations done")
     if not args.no_serving:
         del vl_t, s_t, d_t, l_t
         torch.cuda.empty_cache()

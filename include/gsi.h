@@ -107,6 +107,9 @@ gsi_status gsi_graph_bytes_needed(uint32_t n_vertices, uint64_t n_edges, uint64_
 /* Graph flags */
 #define GSI_GRAPH_TEST_FEW_HOME_GROUPS 0x1u  /* test only: hash PCSR keys into
     ceil(|V(D)|/16) home groups so overflow chains form (same lookups) */
+#define GSI_GRAPH_KEEP_CR 0x2u  /* also keep the compressed representation
+                                    (per label: ascending vertex IDs and list
+                                    starts) for the GSI_ABL_CR ablation */
 
 /*
  * Loads a data graph and builds, on the device, everything a query needs
@@ -165,6 +168,16 @@ gsi_status gsi_graph_copy_pcsr(const gsi_graph *g, uint32_t label, uint32_t *hos
 #define GSI_LEVEL_FIRST_EDGE 0x20u /* every row of a level scans the list of the
                                       level's first edge e0 (Algorithm 4), not
                                       its shortest linking list */
+/* Ablations (measurement and tests only; each implies GSI_NO_FUSED, since
+ * they change the per-level kernels): */
+#define GSI_ABL_CR 0x100u          /* N(v,l) by binary search in the compressed
+                                      representation instead of PCSR (the graph
+                                      needs GSI_GRAPH_KEEP_CR) */
+#define GSI_ABL_TWO_STEP 0x200u    /* two-step output instead of Prealloc-
+                                      Combine: the join only counts survivors,
+                                      the write pass repeats the join */
+#define GSI_ABL_NO_STAGING 0x400u  /* last-level rows written straight from each
+                                      thread (no LDS staging) */
 #define GSI_HOMOMORPHISM 0x40u     /* homomorphism semantics (Sec. VII-A): query
                                       vertices may share a data vertex; the join
                                       drops the subtraction of m_i and the filter

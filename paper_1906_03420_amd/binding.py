@@ -29,6 +29,10 @@ GSI_BATCH_LEVELS_ONLY = 0x8
 GSI_NO_CHUNKS = 0x10
 GSI_LEVEL_FIRST_EDGE = 0x20
 GSI_HOMOMORPHISM = 0x40
+GSI_ABL_CR = 0x100
+GSI_ABL_TWO_STEP = 0x200
+GSI_ABL_NO_STAGING = 0x400
+GSI_GRAPH_KEEP_CR = 0x2
 GSI_MAX_EDGE_LABELS = 65536
 GSI_PCSR_GPN = 16
 GSI_PATH_EMPTY, GSI_PATH_TIER1, GSI_PATH_TIER2, GSI_PATH_SINGLE, GSI_PATH_LEVELS = range(5)

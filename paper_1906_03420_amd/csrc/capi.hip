@@ -279,7 +279,7 @@ static gsi_status load_common(gsi_ctx *c, uint32_t n, const uint32_t *vl, uint64
         REQUIRE(n > 0 && n < 0xFFFFFFFFu, "n_vertices must be in [1, 2^32-2]");
         REQUIRE(m <= 0x7FFFFFFFull, "at most 2^31-1 edges");
         REQUIRE(vl && (m == 0 || (s && d && l)), "null input array");
-        REQUIRE((flags & ~GSI_GRAPH_TEST_FEW_HOME_GROUPS) == 0, "unknown graph flag");
+        REQUIRE((flags & ~(GSI_GRAPH_TEST_FEW_HOME_GROUPS | GSI_GRAPH_KEEP_CR)) == 0, "unknown graph flag");
         Busy busy(c);
         GSI_HIP(hipSetDevice(c->device));
         gsi_graph *g = new gsi_graph();
@@ -310,6 +310,9 @@ static gsi_status load_common(gsi_ctx *c, uint32_t n, const uint32_t *vl, uint64
             c->arena.release(g->sig);
             c->arena.release(g->gl);
             c->arena.release(g->ci);
+            c->arena.release(g->cr_vid);
+            c->arena.release(g->cr_start);
+            c->arena.release(g->cr_off);
             delete g;
             throw;
         }
@@ -338,6 +341,9 @@ gsi_status gsi_graph_free(gsi_graph *g) {
         c->arena.release(g->sig);
         c->arena.release(g->gl);
         c->arena.release(g->ci);
+        c->arena.release(g->cr_vid);
+        c->arena.release(g->cr_start);
+        c->arena.release(g->cr_off);
         c->graphs.erase(g);
         delete g;
     })

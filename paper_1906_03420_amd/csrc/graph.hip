@@ -401,8 +401,13 @@ void build_graph(gsi_graph *g, const uint32_t *vl, const uint32_t *src, const ui
     uint64_t R;
     read_scalars(c, hscan + nd, &R, 1);
     g->total_groups = R;
-    uint32_t *run_start = s.get<uint32_t>(R, "run start");
-    uint32_t *run_vid = s.get<uint32_t>(R, "run vertex");
+    const bool keep_cr = (g->flags & GSI_GRAPH_KEEP_CR) != 0;
+    uint32_t *run_start = keep_cr ? persist<uint32_t>(c, R ? R : 1, "cr starts") : s.get<uint32_t>(R, "run start");
+    uint32_t *run_vid = keep_cr ? persist<uint32_t>(c, R ? R : 1, "cr vertices") : s.get<uint32_t>(R, "run vertex");
+    if (keep_cr) {
+        g->cr_start = run_start;
+        g->cr_vid = run_vid;
+    }
     uint32_t *run_lab = s.get<uint32_t>(R, "run label");
     if (m)
         launch(c, "k_runs", 12.0 * nd, k_runs, blocks(nd), BT, S, L, head, hscan, nd, run_start, run_vid, run_lab);
@@ -503,7 +508,8 @@ void build_graph(gsi_graph *g, const uint32_t *vl, const uint32_t *src, const ui
         launch(c, "k_group_keys", 32.0 * R, k_group_keys, blocks(R), BT, cnt, gstart, owner, cidx, sorted_rid, run_start, R, nd, d_rb, d_G, nlab, kfirst, nkeys, gdeg);
         uint64_t *gci = s.get<uint64_t>(R + 1, "group ci start");
         exclusive_scan(c, gdeg, R, gci, s);
-        uint32_t *run_off = s.get<uint32_t>(R, "run offset");
+        uint32_t *run_off = keep_cr ? persist<uint32_t>(c, R, "cr offsets") : s.get<uint32_t>(R, "run offset");
+        if (keep_cr) g->cr_off = run_off;
         launch(c, "k_write_groups", 128.0 * R + 24.0 * R, k_write_groups, blocks(R), BT, kfirst, nkeys, gci, next, sorted_rid, run_start, run_vid, R, nd, d_rb, d_G, d_seg, nlab, g->gl, run_off);
         launch(c, "k_scatter_ci", 24.0 * nd, k_scatter_ci, blocks(nd), BT, D, L, hscan, run_start, run_off, d_seg, nd, g->ci);
     }

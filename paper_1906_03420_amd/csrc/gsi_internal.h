@@ -94,6 +94,12 @@ struct gsi_graph {
     uint32_t flags = 0;
     uint32_t *sig = nullptr;  // [16 * n] column-first
     uint32_t *gl = nullptr;   // [total_groups * 32]
+    // compressed representation, kept with GSI_GRAPH_KEEP_CR: per label
+    // (from group_base[l], G[l] entries) its vertices ascending, the offset
+    // of each one's list in the label's ci, and where each one's entries
+    // start among all directed edges sorted by (label, source, target), whose
+    // differences are the list lengths
+    uint32_t *cr_vid = nullptr, *cr_start = nullptr, *cr_off = nullptr;
     uint32_t *ci = nullptr;   // [2m]
     std::vector<uint64_t> group_base;  // per label: first global group
     std::vector<uint32_t> G;           // per label: |V(D)| groups

@@ -353,6 +353,13 @@ struct EdgeRef {
     uint32_t G, H;       // groups, home groups
     uint32_t col;        // column of M holding the placed endpoint
     uint32_t ci_off;     // offset of this label's lists in the whole ci array
+    // compressed representation (ablation): the label's vertices in
+    // ascending order, each one's list offset in the label's ci, and the
+    // start of its entries in the (label, source, target) order of all
+    // directed edges, whose differences give the lengths
+    const uint32_t *cr_vid, *cr_start, *cr_off;
+    uint32_t cr_end;     // end of the label's entries in that order
+    uint32_t pad;
 };
 
 struct LevelArgs {
@@ -361,6 +368,10 @@ struct LevelArgs {
     uint32_t j, ne, e0, k;
     uint32_t pick;  // 1: each row scans its shortest linking list (else e0's)
     uint32_t homo;  // 1: homomorphism (no subtraction of m_i, Sec. VII-A)
+    // ablations: lists located by binary search in the compressed
+    // representation; survivors counted, then the join repeated to write
+    // (two-step output); last-level rows written without LDS staging
+    uint32_t abl_cr, abl_two_step, abl_no_stage;
     EdgeRef e[GSI_MAX_K];
     const uint32_t *ci_all;  // every label's lists
     const uint64_t *Cu;
@@ -383,6 +394,20 @@ struct LevelArgs {
     uint32_t final_level, count_only;
 };
 
+// N(v, l) by binary search over the label's ascending vertex IDs (the
+// compressed representation the paper compares PCSR with, Sec. IV)
+__device__ __forceinline__ uint2 cr_find(const EdgeRef &er, uint32_t v) {
+    uint32_t lo = 0, hi = er.G;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (er.cr_vid[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo >= er.G || er.cr_vid[lo] != v) return make_uint2(0, 0);
+    const uint32_t b = er.cr_start[lo], e = lo + 1 < er.G ? er.cr_start[lo + 1] : er.cr_end;
+    return make_uint2(er.cr_off[lo], e - b);
+}
+
 // The list a row scans (its slots of GBA): the first edge e0 of Algorithm 4,
 // or, with `pick`, whichever linking list of the row is shortest (e0 on
 // ties).  The row's survivors are the same either way (they lie in every
@@ -397,7 +422,7 @@ __global__ __launch_bounds__(QT) void k_locate(LevelArgs a) {
         for (uint32_t e = 0; e < a.ne; e++) {
             const EdgeRef &er = a.e[e];
             uint32_t v = a.M[(uint64_t)er.col * a.R + i];
-            uint2 r = pcsr_find(er.gl, er.G, er.H, v);
+            uint2 r = a.abl_cr ? cr_find(er, v) : pcsr_find(er.gl, er.G, er.H, v);
             a.loc[(uint64_t)e * a.R + i] = r.x;
             a.loc[(uint64_t)(a.ne + e) * a.R + i] = r.y;
             all += r.y;
@@ -515,6 +540,21 @@ __device__ __forceinline__ void find_row(const LevelArgs &a, const TileRows &t, 
     }
 }
 
+// slot x of row i survives: x in C(u), x not in m_i, x in every other
+// linking list of the row
+__device__ __forceinline__ bool slot_keep(const LevelArgs &a, uint64_t i, uint32_t x) {
+    bool keep = (a.Cu[x >> 6] >> (x & 63)) & 1ull;
+    for (uint32_t c = 0; keep && !a.homo && c < a.j; c++) keep = a.M[(uint64_t)c * a.R + i] != x;
+    const uint32_t be = (keep && a.ne > 1) ? a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] : a.e0;
+    for (uint32_t e = 0; keep && e < a.ne; e++) {
+        if (e == be) continue;
+        uint32_t st = a.loc[(uint64_t)e * a.R + i];
+        uint32_t len = a.loc[(uint64_t)(a.ne + e) * a.R + i];
+        keep = in_sorted(a.e[e].ci + st, len, x);
+    }
+    return keep;
+}
+
 template <uint32_t SPT>
 __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
     constexpr uint32_t TS = SPT * QT;
@@ -566,7 +606,7 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
 #pragma unroll
     for (uint32_t r = 0; r < SPT; r++) {
         const uint64_t mask = __ballot(kp[r]);
-        if (lane_id() == 0) a.bitmap[(uint64_t)blockIdx.x * (TS / 64) + r * (QT / 64) + w] = mask;
+        if (lane_id() == 0 && !a.abl_two_step) a.bitmap[(uint64_t)blockIdx.x * (TS / 64) + r * (QT / 64) + w] = mask;
         cnt += (uint32_t)__popcll(mask);
     }
     if (lane_id() == 0) s_cnt[w] = cnt;
@@ -591,6 +631,7 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
     __shared__ uint32_t s_st[TS];
     __shared__ uint32_t s_rows[QT * LINK_STAGE_K];
     __shared__ uint32_t s_pre[TS / 64 + 1];  // kept slots before each bitmap word of the tile
+    __shared__ uint64_t s_w[TS / 64];        // the tile's keep bits (two-step ablation)
     const uint64_t tile = blockIdx.x;
     if (a.tile_off[tile + 1] == a.tile_off[tile]) {  // whole tile empty (uniform)
         if (a.final_level && threadIdx.x == 0) {
@@ -601,7 +642,7 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
     }
     const uint64_t p0 = tile * TS;
     const uint64_t *words = a.bitmap + tile * (TS / 64);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && !a.abl_two_step) {
         uint32_t run = 0;
         for (uint32_t q = 0; q < TS / 64; q++) {
             s_pre[q] = run;
@@ -612,8 +653,34 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
     const TileRows tr = stage_rows<SPT>(a, tile, s_F, s_st);  // (its barrier also publishes s_pre)
     if (!tr.staged) __syncthreads();
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+    if (a.abl_two_step) {
+        // two-step output: the join only counted; find the survivors again
+        for (uint32_t r = 0; r < SPT; r++) {
+            const uint64_t p = p0 + r * QT + threadIdx.x;
+            bool keep = false;
+            if (p < a.gba) {
+                uint64_t i, Fi;
+                uint32_t st0;
+                find_row(a, tr, s_F, s_st, p, &i, &Fi, &st0);
+                keep = slot_keep(a, i, a.ci_all[st0 + (uint32_t)(p - Fi)]);
+            }
+            const uint64_t mask = __ballot(keep);
+            if (lane == 0) s_w[r * (QT / 64) + w] = mask;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t run = 0;
+            for (uint32_t q = 0; q < TS / 64; q++) {
+                s_pre[q] = run;
+                run += (uint32_t)__popcll(s_w[q]);
+            }
+            s_pre[TS / 64] = run;
+        }
+        __syncthreads();
+        words = s_w;
+    }
     const uint64_t tbase = a.tile_off[tile];
-    const bool stage = a.final_level && !a.count_only && a.k <= LINK_STAGE_K;
+    const bool stage = a.final_level && !a.count_only && a.k <= LINK_STAGE_K && !a.abl_no_stage;
     const uint32_t *ci0 = a.ci_all;
     uint64_t hs = 0, hx = 0;
     for (uint32_t r = 0; r < SPT; r++) {
@@ -826,10 +893,14 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     gsi_ctx *c = g->ctx;
     auto t0 = std::chrono::steady_clock::now();
     const uint32_t k = q.k;
-    const uint32_t flags = opt ? opt->flags : 0u;
-    if (flags & ~(GSI_COUNT_ONLY | GSI_FILTER_LABEL_ONLY | GSI_NO_FUSED | GSI_NO_CHUNKS | GSI_LEVEL_FIRST_EDGE |
-                  GSI_HOMOMORPHISM))
+    const uint32_t flags = (opt ? opt->flags : 0u) |
+                           ((opt && (opt->flags & (GSI_ABL_CR | GSI_ABL_TWO_STEP | GSI_ABL_NO_STAGING))) ? GSI_NO_FUSED
+                                                                                                         : 0u);
+    constexpr uint32_t ABL = GSI_ABL_CR | GSI_ABL_TWO_STEP | GSI_ABL_NO_STAGING;
+    if (opt && (opt->flags & ~(GSI_COUNT_ONLY | GSI_FILTER_LABEL_ONLY | GSI_NO_FUSED | GSI_NO_CHUNKS |
+                               GSI_LEVEL_FIRST_EDGE | GSI_HOMOMORPHISM | ABL)))
         fail(GSI_E_INVALID, "unknown query flag");
+    if ((flags & GSI_ABL_CR) && !g->cr_vid) fail(GSI_E_INVALID, "GSI_ABL_CR needs a graph loaded with GSI_GRAPH_KEEP_CR");
     const bool count_only = (flags & GSI_COUNT_ONLY) != 0;
     const bool homo = (flags & GSI_HOMOMORPHISM) != 0;
     // each row scans its shortest linking list unless the first edge is fixed
@@ -1250,6 +1321,12 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
                     er.H = g->H[l];
                     er.col = i;
                     er.ci_off = (uint32_t)g->ci_base[l];
+                    if (g->cr_vid) {
+                        er.cr_vid = g->cr_vid + g->group_base[l];
+                        er.cr_start = g->cr_start + g->group_base[l];
+                        er.cr_off = g->cr_off + g->group_base[l];
+                    }
+                    er.cr_end = (uint32_t)(g->ci_base[l] + 2 * g->edges[l]);
                     if (order[i] == e0src[j]) a.e0 = ne;
                     ne++;
                 }
@@ -1263,6 +1340,9 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         a.ci_all = g->ci;
         a.pick = per_row ? 1u : 0u;
         a.homo = homo ? 1u : 0u;
+        a.abl_cr = (flags & GSI_ABL_CR) ? 1u : 0u;
+        a.abl_two_step = (flags & GSI_ABL_TWO_STEP) ? 1u : 0u;
+        a.abl_no_stage = (flags & GSI_ABL_NO_STAGING) ? 1u : 0u;
         a.loc = ls.get<uint32_t>((2ull * ne + 2) * R, "located lists");
         a.bound = ls.get<uint32_t>(R, "row bounds");
         uint64_t *F = ls.get<uint64_t>(R + 1, "offsets F");

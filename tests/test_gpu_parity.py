@@ -384,3 +384,39 @@ def test_homomorphism_closed_forms(ctx):
         assert r.count == 12 * 2 ** (k - 1)
         r.free()
     dg.free()
+
+
+# ------------------------------------------------------------------ ablations
+def test_ablations_give_identical_results(ctx):
+    """Compressed-representation lookup, two-step output and unstaged row
+    writes change only how the per-level kernels work, never the result."""
+    import paper_1906_03420_amd as gsi
+    modes = [dict(flags=gsi.GSI_ABL_CR), dict(flags=gsi.GSI_ABL_TWO_STEP), dict(flags=gsi.GSI_ABL_NO_STAGING),
+             dict(flags=gsi.GSI_ABL_CR | gsi.GSI_ABL_TWO_STEP | gsi.GSI_ABL_NO_STAGING | gsi.GSI_COUNT_ONLY)]
+    for seed in range(6):
+        r = np.random.default_rng(4000 + seed)
+        n = int(r.integers(50, 400))
+        g = w.random_small_graph(n, float(r.uniform(0.01, 0.05)), int(r.integers(1, 3)), int(r.integers(1, 3)),
+                                 seed + 60)
+        if g.m == 0:
+            continue
+        dg = ctx.load(g, gsi.GSI_GRAPH_KEEP_CR)
+        plain = ctx.load(g)
+        og = oracle.OracleGraph(g)
+        for t in range(3):
+            q = w.random_connected_query(int(r.integers(2, 8)), int(r.integers(0, 3)), int(g.vlabel.max()) + 1,
+                                         int(g.elabel.max()) + 1, seed * 100 + t + 9)
+            want = og.match(q, threads=4, max_count=3_000_000)
+            if want.status != 0:
+                continue
+            for mode in modes:
+                print("ablation seed", seed, "query", t, "mode", mode, flush=True)
+                res = dg.query(q, **mode)
+                assert (res.count, res.digest) == (want.count, want.digest)
+                if not mode["flags"] & gsi.GSI_COUNT_ONLY:
+                    np.testing.assert_array_equal(res.sorted_rows(), want.tuples)
+                res.free()
+            with pytest.raises(gsi.GsiError):
+                plain.query(q, flags=gsi.GSI_ABL_CR)
+        plain.free()
+        dg.free()

@@ -43,24 +43,28 @@ __device__ __forceinline__ uint32_t lds_row(const uint32_t *F, uint32_t R, uint3
     return lo;
 }
 
-// LDS of one fused workgroup with FT threads, CR rows and CS slots
-template <uint32_t FT, uint32_t CR, uint32_t CS>
+// LDS of one fused workgroup with FT threads, CR rows and CS slots: F, the
+// start of each row's scanned list, the keep bits and their prefix sums,
+// and (XS) each slot's element x, so that the link re-reads no list
+template <uint32_t FT, uint32_t CR, uint32_t CS, bool XS>
 struct FusedLds {
     uint32_t F[CR + 1];
+    uint32_t st[CR];
     uint64_t bits[CS / 64];
     uint32_t wpre[CS / 64];
     uint32_t w[FT / 64];
     uint64_t d[2][FT / 64];
     uint64_t obase;
+    uint32_t x[XS ? CS : 1];
 };
 
 // All join levels of one query in one workgroup (see the file comment).
 // FT threads; at most CR rows per table (CR = 4 FT) and CS slots per level.
 // With `ocount` set, the last level reserves its S*k output words from that
 // counter (words of `out`, at most `ocap`) instead of writing at out[0].
-template <uint32_t FT, uint32_t CR, uint32_t CS>
+template <uint32_t FT, uint32_t CR, uint32_t CS, bool XS>
 __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, uint32_t *buf0, uint32_t *buf1,
-                            uint32_t *loc, uint32_t *out, FStatus *st, FusedLds<FT, CR, CS> &L,
+                            uint32_t *loc, uint32_t *out, FStatus *st, FusedLds<FT, CR, CS, XS> &L,
                             unsigned long long *ocount = nullptr, uint64_t ocap = 0) {
     static_assert(CR == 4 * FT, "each thread scans four rows");
     static_assert(CS / 64 <= FT, "one thread per bitmap word in the survivor scan");
@@ -120,8 +124,8 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
                 bl = ol;
             }
             s_F[i] = bl;
-            loc[(uint64_t)(2 * ne) * R + i] = plan->edges[ef + be].ci_off + bs;
-            loc[(uint64_t)(2 * ne + 1) * R + i] = be;
+            L.st[i] = plan->edges[ef + be].ci_off + bs;
+            if (ne > 1) loc[(uint64_t)(2 * ne + 1) * R + i] = be;
         }
         __syncthreads();
         // F = exclusive prefix sum of the bounds (each thread owns 4 rows)
@@ -173,7 +177,8 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
             bool keep = false;
             if (p < gba) {
                 const uint32_t i = lds_row(s_F, R, p);
-                const uint32_t x = ci_all[loc[(uint64_t)(2 * ne) * R + i] + (p - s_F[i])];
+                const uint32_t x = ci_all[L.st[i] + (p - s_F[i])];
+                if (XS) L.x[p] = x;
                 keep = (Cu[x >> 6] >> (x & 63)) & 1ull;
                 for (uint32_t c = 0; keep && !plan->homo && c < j; c++) keep = M[(uint64_t)c * R + i] != x;
                 const uint32_t be = (keep && ne > 1) ? loc[(uint64_t)(2 * ne + 1) * R + i] : e0;
@@ -246,7 +251,7 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
             const uint32_t p = word * 64 + lane;
             const uint32_t pos = s_wpre[word] + rank_below(bits);
             const uint32_t i = lds_row(s_F, R, p);
-            const uint32_t x = ci_all[loc[(uint64_t)(2 * ne) * R + i] + (p - s_F[i])];
+            const uint32_t x = XS ? L.x[p] : ci_all[L.st[i] + (p - s_F[i])];
             if (!final_level) {
                 for (uint32_t c = 0; c < j; c++) Mn[(uint64_t)c * S + pos] = M[(uint64_t)c * R + i];
                 Mn[(uint64_t)j * S + pos] = x;
@@ -296,8 +301,8 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
 __global__ __launch_bounds__(1024) void k_fused_levels(const FPlan *plan, const uint32_t *M0, uint32_t R0,
                                                       uint32_t *buf0, uint32_t *buf1, uint32_t *loc, uint32_t *out,
                                                       FStatus *st) {
-    __shared__ FusedLds<1024, FUSED_MAX_ROWS, FUSED_MAX_SLOTS> L;
-    fused_query<1024, FUSED_MAX_ROWS, FUSED_MAX_SLOTS>(plan, M0, R0, buf0, buf1, loc, out, st, L);
+    __shared__ FusedLds<1024, FUSED_MAX_ROWS, FUSED_MAX_SLOTS, true> L;
+    fused_query<1024, FUSED_MAX_ROWS, FUSED_MAX_SLOTS, true>(plan, M0, R0, buf0, buf1, loc, out, st, L);
 }
 
 void launch_fused(gsi_ctx *c, const FPlan *d_plan, const uint32_t *M0, uint32_t R0, uint32_t *buf0, uint32_t *buf1,
@@ -313,7 +318,7 @@ __global__ __launch_bounds__(FT) void k_fused_batch(const uint8_t *plans, const 
                                                    const uint32_t *M0all, uint32_t *scratch, uint64_t slot_words,
                                                    uint32_t kmax, uint32_t *outall, FStatus *sts,
                                                    uint32_t *counter) {
-    __shared__ FusedLds<FT, CR, CS> L;
+    __shared__ FusedLds<FT, CR, CS, false> L;
     __shared__ uint32_t s_q;
     uint32_t *slot = scratch + (uint64_t)blockIdx.x * slot_words;
     uint32_t *buf0 = slot, *buf1 = slot + (uint64_t)CR * kmax, *loc = slot + 2ull * CR * kmax;
@@ -324,7 +329,7 @@ __global__ __launch_bounds__(FT) void k_fused_batch(const uint8_t *plans, const 
         __syncthreads();
         if (qi >= nitems) break;
         const FBatchItem it = items[qi];
-        fused_query<FT, CR, CS>(reinterpret_cast<const FPlan *>(plans + it.plan_off), M0all + it.m0_off, it.R0,
+        fused_query<FT, CR, CS, false>(reinterpret_cast<const FPlan *>(plans + it.plan_off), M0all + it.m0_off, it.R0,
                                 buf0, buf1, loc, outall ? outall + it.out_off : nullptr, sts + qi, L);
         __syncthreads();
     }
@@ -349,7 +354,7 @@ __global__ __launch_bounds__(FT) void k_fused_chunks(const FPlan *plan, const ui
                                                     uint64_t staging_words, unsigned long long *ocount,
                                                     uint32_t *abort, uint32_t max_fail, FStatus *sts,
                                                     uint32_t *counter) {
-    __shared__ FusedLds<FT, CR, CS> L;
+    __shared__ FusedLds<FT, CR, CS, true> L;
     __shared__ uint32_t s_q;
     uint32_t *slot = scratch + (uint64_t)blockIdx.x * slot_words;
     uint32_t *buf0 = slot, *buf1 = slot + (uint64_t)CR * k, *loc = slot + 2ull * CR * k;
@@ -371,8 +376,8 @@ __global__ __launch_bounds__(FT) void k_fused_chunks(const FPlan *plan, const ui
         if (qi >= nchunks) break;
         const uint32_t first = qi * chunk_rows;
         const uint32_t rows = min(chunk_rows, R0 - first);
-        fused_query<FT, CR, CS>(plan, M0 + first, rows, buf0, buf1, loc, staging, sts + qi, L, ocount,
-                                staging_words);
+        fused_query<FT, CR, CS, true>(plan, M0 + first, rows, buf0, buf1, loc, staging, sts + qi, L, ocount,
+                                      staging_words);
         prev = qi;
         __syncthreads();
     }

@@ -443,7 +443,7 @@ __global__ __launch_bounds__(QT) void k_locate(LevelArgs a) {
         }
         a.bound[i] = bl;
         a.loc[(uint64_t)(2 * a.ne) * a.R + i] = a.e[be].ci_off + bs;
-        a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] = be;
+        if (a.ne > 1) a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] = be;
         other = all - bl;
     }
     if (!a.part) return;  // list-length totals are gathered for profiling only

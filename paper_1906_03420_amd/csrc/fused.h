@@ -105,7 +105,9 @@ void launch_chunk_gather(gsi_ctx *c, uint32_t nchunks, const FStatus *sts, const
 void launch_take_roots(gsi_ctx *c, uint32_t nlist, const uint32_t *M0, uint32_t R0, uint32_t chunk_rows,
                        const uint32_t *list, uint32_t *dst, uint64_t rows);
 
-void launch_fused(gsi_ctx *c, const FPlan *d_plan, const uint32_t *M0, uint32_t R0, uint32_t *buf0, uint32_t *buf1,
-                  uint32_t *loc, uint32_t *out, FStatus *d_status, double alg_bytes);
+// The single-workgroup fused kernel; with b0 (the bitset of C(u_first),
+// nwords words) it also writes M0 itself.
+void launch_fused(gsi_ctx *c, const FPlan *d_plan, uint32_t *M0, uint32_t R0, const uint64_t *b0, uint64_t nwords,
+                  uint32_t *buf0, uint32_t *buf1, uint32_t *loc, uint32_t *out, FStatus *d_status, double alg_bytes);
 
 }  // namespace gsi

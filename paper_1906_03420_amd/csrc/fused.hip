@@ -298,16 +298,54 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
     }
 }
 
-__global__ __launch_bounds__(1024) void k_fused_levels(const FPlan *plan, const uint32_t *M0, uint32_t R0,
-                                                      uint32_t *buf0, uint32_t *buf1, uint32_t *loc, uint32_t *out,
-                                                      FStatus *st) {
+// One query in one workgroup.  The status is cleared here (no separate
+// fill), and, when `b0` is given, the first table M0 = C(u_first) is
+// written here too from its bitset (ascending vertex order, R0 entries):
+// each thread counts the set bits of a run of bitset words, an exclusive
+// scan over the workgroup places the runs, and each thread writes its ids.
+__global__ __launch_bounds__(1024) void k_fused_levels(const FPlan *plan, uint32_t *M0, uint32_t R0,
+                                                      const uint64_t *b0, uint64_t nwords, uint32_t *buf0,
+                                                      uint32_t *buf1, uint32_t *loc, uint32_t *out, FStatus *st) {
     __shared__ FusedLds<1024, FUSED_MAX_ROWS, FUSED_MAX_SLOTS, true> L;
+    uint64_t *sw = reinterpret_cast<uint64_t *>(st);
+    for (uint32_t t = threadIdx.x; t < sizeof(FStatus) / 8; t += 1024) sw[t] = 0;
+    if (b0) {
+        // each wave owns a contiguous run of words, read 64 at a time
+        // (coalesced): count, place the runs, then emit with wave scans
+        const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
+        const uint64_t per = (nwords + 15) / 16;
+        const uint64_t ws = per * wv < nwords ? per * wv : nwords;
+        const uint64_t we = ws + per < nwords ? ws + per : nwords;
+        uint32_t cnt = 0;
+        for (uint64_t q = ws + lane; q < we; q += 64) cnt += (uint32_t)__popcll(b0[q]);
+        cnt = wave_sum(cnt);
+        if (lane == 0) L.w[wv] = cnt;
+        __syncthreads();
+        uint32_t at = 0;
+        for (uint32_t v = 0; v < wv; v++) at += L.w[v];
+        for (uint64_t base = ws; base < we; base += 64) {
+            const uint64_t q = base + lane;
+            uint64_t m = q < we ? b0[q] : 0ull;
+            const uint32_t pc = (uint32_t)__popcll(m);
+            const uint32_t inc = wave_inclusive_sum(pc);
+            uint32_t o = at + inc - pc;
+            while (m) {
+                const uint32_t b = (uint32_t)__builtin_ctzll(m);
+                if (o < R0) M0[o] = (uint32_t)(q * 64 + b);
+                o++;
+                m &= m - 1;
+            }
+            at += __shfl(inc, 63, 64);
+        }
+    }
+    __syncthreads();  // status cleared and M0 written before the levels read them
     fused_query<1024, FUSED_MAX_ROWS, FUSED_MAX_SLOTS, true>(plan, M0, R0, buf0, buf1, loc, out, st, L);
 }
 
-void launch_fused(gsi_ctx *c, const FPlan *d_plan, const uint32_t *M0, uint32_t R0, uint32_t *buf0, uint32_t *buf1,
-                  uint32_t *loc, uint32_t *out, FStatus *d_status, double alg_bytes) {
-    launch(c, "k_fused_levels", alg_bytes, k_fused_levels, 1, 1024, d_plan, M0, R0, buf0, buf1, loc, out, d_status);
+void launch_fused(gsi_ctx *c, const FPlan *d_plan, uint32_t *M0, uint32_t R0, const uint64_t *b0, uint64_t nwords,
+                  uint32_t *buf0, uint32_t *buf1, uint32_t *loc, uint32_t *out, FStatus *d_status, double alg_bytes) {
+    launch(c, "k_fused_levels", alg_bytes, k_fused_levels, 1, 1024, d_plan, M0, R0, b0, nwords, buf0, buf1, loc, out,
+           d_status);
 }
 
 // Persistent batch: each workgroup takes the next query from a shared

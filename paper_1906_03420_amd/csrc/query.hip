@@ -1011,16 +1011,24 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
 
     auto tj = std::chrono::steady_clock::now();
 
-    // M0 = C(order[0]), ascending
+    // M0 = C(order[0]), ascending.  When the single fused workgroup will run
+    // the levels, it writes M0 itself (saving three launches).
     uint64_t R = cand[order[0]];
     if (max_rows && R > max_rows) fail(GSI_E_CAPACITY, "rows exceed max_rows");
     Block Mb(c);
     uint32_t *M = Mb.get<uint32_t>(R, "first table");
-    {
+    const uint64_t *b0 = bits + (uint64_t)order[0] * nwords;
+    uint32_t fcap_rows = FUSED_MAX_ROWS, fcap_slots = FUSED_MAX_SLOTS;
+    if (opt && opt->fused_max_rows) fcap_rows = std::min(fcap_rows, opt->fused_max_rows);
+    if (opt && opt->fused_max_slots) fcap_slots = std::min(fcap_slots, opt->fused_max_slots);
+    const uint32_t chunk_min = (opt && opt->chunk_min_rows) ? opt->chunk_min_rows : CHUNK_MIN_ROWS;
+    const bool try_chunks = !(flags & GSI_NO_FUSED) && !(flags & GSI_NO_CHUNKS) && R >= chunk_min;
+    const bool m0_in_fused =
+        k >= 2 && !try_chunks && !(flags & GSI_NO_FUSED) && R <= fcap_rows && fcap_slots >= 64;
+    if (!m0_in_fused) {
         Scratch s0(c);
         uint32_t *wc = s0.get<uint32_t>(nwords, "word counts");
         uint64_t *wo = s0.get<uint64_t>(nwords + 1, "word offsets");
-        const uint64_t *b0 = bits + (uint64_t)order[0] * nwords;
         launch(c, "k_word_popc", 8.0 * nwords, k_word_popc, nblocks(nwords), QT, b0, nwords, wc);
         exclusive_scan(c, wc, nwords, wo, s0);
         launch(c, "k_word_emit", 16.0 * nwords + 4.0 * R, k_word_emit, nblocks(nwords), QT, b0, nwords, (const uint64_t *)wo, M);
@@ -1148,8 +1156,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     };
 
     uint32_t jstart = 1;
-    const uint32_t chunk_min = (opt && opt->chunk_min_rows) ? opt->chunk_min_rows : CHUNK_MIN_ROWS;
-    if (!(flags & GSI_NO_FUSED) && !(flags & GSI_NO_CHUNKS) && R >= chunk_min) {
+    if (try_chunks) {
         const FTier t = fused_tier(256);
         const uint64_t slot_words = 2ull * t.cap_rows * k + fused_loc_words(k, t.cap_rows);
         int ncu = 0;
@@ -1250,9 +1257,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     // Small root sets: one workgroup runs levels while they fit, then the
     // per-level kernels continue from where it stopped.
     if (!cp.active) {
-        uint32_t cap_rows = FUSED_MAX_ROWS, cap_slots = FUSED_MAX_SLOTS;
-        if (opt && opt->fused_max_rows) cap_rows = std::min(cap_rows, opt->fused_max_rows);
-        if (opt && opt->fused_max_slots) cap_slots = std::min(cap_slots, opt->fused_max_slots);
+        const uint32_t cap_rows = fcap_rows, cap_slots = fcap_slots;
         if (!(flags & GSI_NO_FUSED) && R <= cap_rows && cap_slots >= 64) {
             FPlan *hp;
             FPlan *dplan = fused_plan(cap_rows, cap_slots, &hp);
@@ -1260,10 +1265,9 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
             uint32_t *buf1 = fs.get<uint32_t>((uint64_t)cap_rows * k, "fused table 1");
             uint32_t *floc = fs.get<uint32_t>(fused_loc_words(k, cap_rows), "fused lookups");
             FStatus *dst = reinterpret_cast<FStatus *>(fs.get<uint64_t>(sizeof(FStatus) / 8, "fused status"));
-            fill_u64(c, reinterpret_cast<uint64_t *>(dst), 0, sizeof(FStatus) / 8);
             uint32_t *out = count_only ? nullptr : persist<uint32_t>(c, (uint64_t)cap_slots * k, "result rows");
             res->rows = out;
-            launch_fused(c, dplan, M, (uint32_t)R, buf0, buf1, floc, out, dst, 0.0);
+            launch_fused(c, dplan, M, (uint32_t)R, m0_in_fused ? b0 : nullptr, nwords, buf0, buf1, floc, out, dst, 0.0);
             FStatus *hs = reinterpret_cast<FStatus *>(reinterpret_cast<char *>(c->pinned) + 4096);
             GSI_HIP(hipMemcpyAsync(hs, dst, sizeof(FStatus), hipMemcpyDeviceToHost, c->stream));
             sync(c);

@@ -482,6 +482,8 @@ def main():
                       alg_bytes_per_launch=dom["alg_bytes"] / dom["launches"], launches=dom["launches"],
                       avg_launch_us=dom["total_ms"] / dom["launches"] * 1e3,
                       share_of_device_time=dom["total_ms"] / dev_ms if dev_ms else None,
+                      limiter=("latency: one 1024-thread workgroup runs every level of a small query"
+                               if dom["name"] == "k_fused_levels" else "hbm"),
                       measured="HIP events around every launch in %d profiled steps (%.1f ms/step with events)"
                                % (args.steps, prof_ms),
                       large_launches=large_lines),

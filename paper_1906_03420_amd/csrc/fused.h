@@ -82,17 +82,19 @@ void launch_fused_batch(gsi_ctx *c, const FTier &t, uint32_t grid, const uint8_t
                         uint32_t nitems, const uint32_t *M0all, uint32_t *scratch, uint64_t slot_words, uint32_t kmax,
                         uint32_t *outall, FStatus *sts, uint32_t *counter, double bytes);
 
-// One query split into chunks of `chunk_rows` root rows (the rows of M are
-// independent at every level of Algorithm 3): a persistent launch of the
-// tier's workgroups takes chunks from `counter` and runs all levels of each.
+// One query split into chunks of `chunk_rows` rows of its table M0 (R0
+// rows, j0 columns, column stride R0; the rows of M are independent at
+// every level of Algorithm 3): a persistent launch of the tier's workgroups
+// takes chunks from `counter` and runs levels j0 .. k-1 of each.
 // Finished chunks reserve their output rows in `staging` (capacity
 // `staging_words`) through `ocount`.  A chunk that cannot hold a level, or
 // whose rows do not fit the staging buffer, is left undone; once more than
 // `max_fail` chunks are, `abort` (two words: flag, failures) is set and the
-// launch stops taking chunks.  k_chunk_summary then writes the totals of the
-// finished chunks, each chunk's first output row (chunk order) and a done
-// flag per chunk.
-void launch_fused_chunks(gsi_ctx *c, const FTier &t, uint32_t grid, const FPlan *plan, const uint32_t *M0,
+// launch stops taking chunks.  The totals of the finished chunks are added
+// into `sum` (zeroed by the caller) as they finish; k_chunk_summary then
+// writes each chunk's first output row (chunk order), a done flag per chunk
+// and the row total.
+void launch_fused_chunks(gsi_ctx *c, const FTier &t, uint32_t grid, const FPlan *plan, uint32_t j0, const uint32_t *M0,
                          uint32_t R0, uint32_t chunk_rows, uint32_t nchunks, uint32_t *scratch, uint64_t slot_words,
                          uint32_t k, uint32_t *staging, uint64_t staging_words, unsigned long long *ocount,
                          uint32_t *abort, uint32_t max_fail, FStatus *sts, uint32_t *counter, uint64_t *offs,
@@ -101,13 +103,16 @@ void launch_fused_chunks(gsi_ctx *c, const FTier &t, uint32_t grid, const FPlan 
 // the per-level path gives those roots.
 void launch_chunk_gather(gsi_ctx *c, uint32_t nchunks, const FStatus *sts, const uint64_t *offs,
                          const uint32_t *staging, uint32_t k, uint32_t *out, uint64_t words);
-// Concatenates the root rows of the chunks in `list` (pairs: chunk, position).
-void launch_take_roots(gsi_ctx *c, uint32_t nlist, const uint32_t *M0, uint32_t R0, uint32_t chunk_rows,
-                       const uint32_t *list, uint32_t *dst, uint64_t rows);
+// Concatenates the rows (`ncols` columns) of the chunks in `list` (pairs:
+// chunk, position) into dst, a table of `rows` rows.
+void launch_take_rows(gsi_ctx *c, uint32_t nlist, const uint32_t *M0, uint32_t R0, uint32_t ncols,
+                      uint32_t chunk_rows, const uint32_t *list, uint32_t *dst, uint64_t rows);
 
-// The single-workgroup fused kernel; with b0 (the bitset of C(u_first),
-// nwords words) it also writes M0 itself.
-void launch_fused(gsi_ctx *c, const FPlan *d_plan, uint32_t *M0, uint32_t R0, const uint64_t *b0, uint64_t nwords,
-                  uint32_t *buf0, uint32_t *buf1, uint32_t *loc, uint32_t *out, FStatus *d_status, double alg_bytes);
+// The single-workgroup fused kernel, levels j0.. of the table M0 (R0 rows,
+// j0 columns, column stride R0); with b0 (the bitset of C(u_first), nwords
+// words; j0 = 1 only) it also writes M0 itself.
+void launch_fused(gsi_ctx *c, const FPlan *d_plan, uint32_t j0, uint32_t *M0, uint32_t R0, const uint64_t *b0,
+                  uint64_t nwords, uint32_t *buf0, uint32_t *buf1, uint32_t *loc, uint32_t *out, FStatus *d_status,
+                  double alg_bytes);
 
 }  // namespace gsi

@@ -32,16 +32,34 @@ __device__ __forceinline__ uint32_t wg_exclusive_sum(uint32_t v, uint32_t *s_w, 
     return off + inc - v;
 }
 
-// largest i in [0, R) with F[i] <= p (F in LDS, F[0] = 0 <= p)
-__device__ __forceinline__ uint32_t lds_row(const uint32_t *F, uint32_t R, uint32_t p) {
-    uint32_t lo = 0, hi = R - 1;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi + 1) >> 1;
-        if (F[mid] <= p) lo = mid;
-        else hi = mid - 1;
+// Rows of U slots at once: for each r, the largest i < R with F[i] <= p[r]
+// (F in LDS, non-decreasing, F[0] = 0), with Fi[r] = F[i].  A branch-free
+// binary lifting with the same number of steps for every lane, so the U
+// searches interleave their LDS reads.  F[R] (|GBA|) is read in place of
+// indices past the table; it exceeds every slot below |GBA|.
+template <uint32_t U>
+__device__ __forceinline__ void lds_rows(const uint32_t *F, uint32_t R, const uint32_t *p, uint32_t *row,
+                                         uint32_t *Fi) {
+#pragma unroll
+    for (uint32_t r = 0; r < U; r++) {
+        row[r] = 0;
+        Fi[r] = 0;
     }
-    return lo;
+    for (uint32_t b = R > 1 ? 1u << (31 - __builtin_clz(R - 1)) : 0u; b; b >>= 1) {
+#pragma unroll
+        for (uint32_t r = 0; r < U; r++) {
+            const uint32_t m = row[r] + b;
+            const uint32_t f = F[m < R ? m : R];
+            if (m < R && f <= p[r]) {
+                row[r] = m;
+                Fi[r] = f;
+            }
+        }
+    }
 }
+
+// bitmap words a wave takes per round of the fused join and link
+constexpr uint32_t FU = 2;
 
 // LDS of one fused workgroup with FT threads, CR rows and CS slots: F, the
 // start of each row's scanned list, the keep bits and their prefix sums,
@@ -58,14 +76,17 @@ struct FusedLds {
     uint32_t x[XS ? CS : 1];
 };
 
-// All join levels of one query in one workgroup (see the file comment).
-// FT threads; at most CR rows per table (CR = 4 FT) and CS slots per level.
-// With `ocount` set, the last level reserves its S*k output words from that
-// counter (words of `out`, at most `ocap`) instead of writing at out[0].
+// Join levels j0 .. k-1 of one query in one workgroup (see the file
+// comment), starting from the table M0 of R0 rows and j0 columns (column c
+// at M0 + c * ld0).  FT threads; at most CR rows per table (CR = 4 FT) and
+// CS slots per level.  With `ocount` set, the last level reserves its S*k
+// output words from that counter (words of `out`, at most `ocap`) instead of
+// writing at out[0].
 template <uint32_t FT, uint32_t CR, uint32_t CS, bool XS>
-__device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, uint32_t *buf0, uint32_t *buf1,
-                            uint32_t *loc, uint32_t *out, FStatus *st, FusedLds<FT, CR, CS, XS> &L,
-                            unsigned long long *ocount = nullptr, uint64_t ocap = 0) {
+__device__ __forceinline__ void fused_query(const FPlan *plan, uint32_t j0, const uint32_t *M0, uint32_t R0,
+                                            uint32_t ld0, uint32_t *buf0, uint32_t *buf1, uint32_t *loc,
+                                            uint32_t *out, FStatus *st, FusedLds<FT, CR, CS, XS> &L,
+                                            unsigned long long *ocount = nullptr, uint64_t ocap = 0) {
     static_assert(CR == 4 * FT, "each thread scans four rows");
     static_assert(CS / 64 <= FT, "one thread per bitmap word in the survivor scan");
     uint32_t *s_F = L.F;
@@ -79,19 +100,24 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
     const uint32_t cap_slots = plan->cap_slots < CS ? plan->cap_slots : CS;
     const uint32_t *M = M0;
     uint32_t R = R0;
+    uint32_t ld = ld0;  // column stride of M
     uint32_t mloc = FSTATUS_IN_FIRST;  // where M lives
     uint32_t *bufs[2] = {buf0, buf1};
     uint32_t next = 0;
-    if (R0 > cap_rows) {  // the first table does not fit
+    // level j does not fit: record where, and where its input M lives
+    auto stop = [&](uint32_t j) {
         if (tid == 0) {
-            st->level = 1;
-            st->rows = R0;
+            st->level = j;
+            st->rows = R;
             st->mloc = mloc;
         }
+    };
+    if (R0 > cap_rows) {  // the first table does not fit
+        stop(j0);
         return;
     }
 
-    for (uint32_t j = 1; j < k; j++) {
+    for (uint32_t j = j0; j < k; j++) {
         const uint32_t ne = plan->lv_ne[j], ef = plan->lv_first[j], e0 = plan->lv_e0[j];
         const uint64_t *Cu = plan->Cu[j];
         const bool final_level = (j == k - 1);
@@ -104,7 +130,7 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
             uint32_t s0 = 0, l0 = 0, ob = NONE32, os = 0, ol = 0xFFFFFFFFu;
             for (uint32_t e = 0; e < ne; e++) {
                 const FEdge &ed = plan->edges[ef + e];
-                const uint32_t v = M[(uint64_t)ed.col * R + i];
+                const uint32_t v = M[(uint64_t)ed.col * ld + i];
                 const uint2 r = pcsr_find(ed.gl, ed.G, ed.H, v);
                 loc[(uint64_t)e * R + i] = r.x;
                 loc[(uint64_t)(ne + e) * R + i] = r.y;
@@ -153,11 +179,7 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
         const uint32_t gba = __builtin_amdgcn_readfirstlane(s_F[R]);
         if (tid == 0) st->lv_gba[j] = gba;
         if (gba > cap_slots) {
-            if (tid == 0) {
-                st->level = j;
-                st->rows = R;
-                st->mloc = mloc;
-            }
+            stop(j);
             return;
         }
         if (gba == 0) {
@@ -171,25 +193,62 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
         const uint32_t nw = (gba + 63) / 64;
 
         // join: keep x = N(v'_i, l0)[p - F[i]] iff x not in m_i, x in C(u),
-        // x in every other linking list; one ballot word per 64 slots
-        for (uint32_t word = w; word < nw; word += FT / 64) {
-            const uint32_t p = word * 64 + lane;
-            bool keep = false;
-            if (p < gba) {
-                const uint32_t i = lds_row(s_F, R, p);
-                const uint32_t x = ci_all[L.st[i] + (p - s_F[i])];
-                if (XS) L.x[p] = x;
-                keep = (Cu[x >> 6] >> (x & 63)) & 1ull;
-                for (uint32_t c = 0; keep && !plan->homo && c < j; c++) keep = M[(uint64_t)c * R + i] != x;
-                const uint32_t be = (keep && ne > 1) ? loc[(uint64_t)(2 * ne + 1) * R + i] : e0;
-                for (uint32_t e = 0; keep && e < ne; e++) {
-                    if (e == be) continue;
-                    keep = in_sorted(plan->edges[ef + e].ci + loc[(uint64_t)e * R + i],
-                                     loc[(uint64_t)(ne + e) * R + i], x);
+        // x in every other linking list; one ballot word per 64 slots.  A
+        // wave takes FU words per round (words base + r * waves + w) and
+        // issues each step's loads for all of them together, so a round
+        // costs one chain of dependent loads, not FU.
+        for (uint32_t base = 0; base < nw; base += FU * (FT / 64)) {
+            uint32_t pr[FU], ir[FU], fr[FU], xr[FU];
+            bool kp[FU];
+#pragma unroll
+            for (uint32_t r = 0; r < FU; r++) {
+                pr[r] = (base + r * (FT / 64) + w) * 64 + lane;
+                kp[r] = pr[r] < gba;
+                xr[r] = 0;
+            }
+            lds_rows<FU>(s_F, R, pr, ir, fr);
+#pragma unroll
+            for (uint32_t r = 0; r < FU; r++)
+                if (kp[r]) xr[r] = ci_all[L.st[ir[r]] + (pr[r] - fr[r])];
+#pragma unroll
+            for (uint32_t r = 0; r < FU; r++) {
+                if (XS && kp[r]) L.x[pr[r]] = xr[r];
+                if (kp[r]) kp[r] = (Cu[xr[r] >> 6] >> (xr[r] & 63)) & 1ull;
+            }
+            if (!plan->homo) {
+                for (uint32_t c = 0; c < j; c += 4) {
+                    uint32_t mv[FU][4];
+#pragma unroll
+                    for (uint32_t r = 0; r < FU; r++)
+#pragma unroll
+                        for (uint32_t q = 0; q < 4; q++)
+                            mv[r][q] = (kp[r] && c + q < j) ? M[(uint64_t)(c + q) * ld + ir[r]] : ~xr[r];
+#pragma unroll
+                    for (uint32_t r = 0; r < FU; r++)
+#pragma unroll
+                        for (uint32_t q = 0; q < 4; q++) kp[r] = kp[r] && mv[r][q] != xr[r];
                 }
             }
-            const uint64_t mask = __ballot(keep);
-            if (lane == 0) s_bits[word] = mask;
+            if (ne > 1) {
+#pragma unroll
+                for (uint32_t r = 0; r < FU; r++) {
+                    bool keep = kp[r];
+                    const uint32_t i = ir[r];
+                    const uint32_t be = keep ? loc[(uint64_t)(2 * ne + 1) * R + i] : e0;
+                    for (uint32_t e = 0; keep && e < ne; e++) {
+                        if (e == be) continue;
+                        keep = in_sorted(plan->edges[ef + e].ci + loc[(uint64_t)e * R + i],
+                                         loc[(uint64_t)(ne + e) * R + i], xr[r]);
+                    }
+                    kp[r] = keep;
+                }
+            }
+#pragma unroll
+            for (uint32_t r = 0; r < FU; r++) {
+                const uint64_t mask = __ballot(kp[r]);
+                const uint32_t word = base + r * (FT / 64) + w;
+                if (lane == 0 && word < nw) s_bits[word] = mask;
+            }
         }
         __syncthreads();
         // survivor positions: prefix sum of the words' popcounts
@@ -210,11 +269,7 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
             return;
         }
         if (!final_level && S > cap_rows) {
-            if (tid == 0) {
-                st->level = j;
-                st->rows = R;
-                st->mloc = mloc;
-            }
+            stop(j);
             return;
         }
 
@@ -230,11 +285,7 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
             const uint64_t b = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(lb >> 32)) << 32) |
                                __builtin_amdgcn_readfirstlane((uint32_t)lb);
             if (b == ~0ull) {
-                if (tid == 0) {
-                    st->level = j;
-                    st->rows = R;
-                    st->mloc = mloc;
-                }
+                stop(j);
                 return;
             }
             out += b;
@@ -242,30 +293,73 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
         }
 
         // link: (m_i, x) at its position; the last level writes rows in
-        // query-vertex order and hashes them
+        // query-vertex order and hashes them.  FU words per wave and round,
+        // as in the join.
         uint32_t *Mn = bufs[next];
         uint64_t hs = 0, hx = 0;
-        for (uint32_t word = w; word < nw; word += FT / 64) {
-            const uint64_t bits = s_bits[word];
-            if (!((bits >> lane) & 1ull)) continue;
-            const uint32_t p = word * 64 + lane;
-            const uint32_t pos = s_wpre[word] + rank_below(bits);
-            const uint32_t i = lds_row(s_F, R, p);
-            const uint32_t x = XS ? L.x[p] : ci_all[L.st[i] + (p - s_F[i])];
+        for (uint32_t base = 0; base < nw; base += FU * (FT / 64)) {
+            uint32_t pr[FU], ir[FU], fr[FU], pos[FU], xr[FU];
+            bool kp[FU];
+#pragma unroll
+            for (uint32_t r = 0; r < FU; r++) {
+                const uint32_t word = base + r * (FT / 64) + w;
+                const uint64_t bits = word < nw ? s_bits[word] : 0ull;
+                pr[r] = word * 64 + lane;
+                kp[r] = (bits >> lane) & 1ull;
+                pos[r] = kp[r] ? s_wpre[word] + rank_below(bits) : 0u;
+            }
+            lds_rows<FU>(s_F, R, pr, ir, fr);
+#pragma unroll
+            for (uint32_t r = 0; r < FU; r++) {
+                xr[r] = 0;
+                if (kp[r]) xr[r] = XS ? L.x[pr[r]] : ci_all[L.st[ir[r]] + (pr[r] - fr[r])];
+            }
             if (!final_level) {
-                for (uint32_t c = 0; c < j; c++) Mn[(uint64_t)c * S + pos] = M[(uint64_t)c * R + i];
-                Mn[(uint64_t)j * S + pos] = x;
-            } else {
-                uint64_t f = 14695981039346656037ull;
-                for (uint32_t u = 0; u < k; u++) {
-                    const uint32_t c = plan->qcol[u];
-                    const uint32_t val = c < j ? M[(uint64_t)c * R + i] : x;
-                    if (!plan->count_only) out[(uint64_t)pos * k + u] = val;
-                    f = fnv_word(f, val);
+                for (uint32_t c = 0; c < j; c += 4) {
+                    uint32_t mv[FU][4];
+#pragma unroll
+                    for (uint32_t r = 0; r < FU; r++)
+#pragma unroll
+                        for (uint32_t q = 0; q < 4; q++)
+                            mv[r][q] = (kp[r] && c + q < j) ? M[(uint64_t)(c + q) * ld + ir[r]] : 0u;
+#pragma unroll
+                    for (uint32_t r = 0; r < FU; r++)
+#pragma unroll
+                        for (uint32_t q = 0; q < 4; q++)
+                            if (kp[r] && c + q < j) Mn[(uint64_t)(c + q) * S + pos[r]] = mv[r][q];
                 }
-                const uint64_t h = mix64(f);
-                hs += h;
-                hx ^= h;
+#pragma unroll
+                for (uint32_t r = 0; r < FU; r++)
+                    if (kp[r]) Mn[(uint64_t)j * S + pos[r]] = xr[r];
+            } else {
+                uint64_t f[FU];
+#pragma unroll
+                for (uint32_t r = 0; r < FU; r++) f[r] = 14695981039346656037ull;
+                for (uint32_t u0 = 0; u0 < k; u0 += 4) {
+                    uint32_t val[FU][4];
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; q++) {
+                        const uint32_t c = u0 + q < k ? plan->qcol[u0 + q] : j;
+#pragma unroll
+                        for (uint32_t r = 0; r < FU; r++)
+                            val[r][q] = (kp[r] && c < j) ? M[(uint64_t)c * ld + ir[r]] : xr[r];
+                    }
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; q++)
+#pragma unroll
+                        for (uint32_t r = 0; r < FU; r++) {
+                            if (!kp[r] || u0 + q >= k) continue;
+                            if (!plan->count_only) out[(uint64_t)pos[r] * k + u0 + q] = val[r][q];
+                            f[r] = fnv_word(f[r], val[r][q]);
+                        }
+                }
+#pragma unroll
+                for (uint32_t r = 0; r < FU; r++) {
+                    if (!kp[r]) continue;
+                    const uint64_t h = mix64(f[r]);
+                    hs += h;
+                    hx ^= h;
+                }
             }
         }
         if (final_level) {
@@ -293,6 +387,7 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
         __syncthreads();  // M' complete before it is read as M
         M = Mn;
         R = S;
+        ld = S;
         mloc = next;
         next ^= 1u;
     }
@@ -303,7 +398,7 @@ __device__ void fused_query(const FPlan *plan, const uint32_t *M0, uint32_t R0, 
 // written here too from its bitset (ascending vertex order, R0 entries):
 // each thread counts the set bits of a run of bitset words, an exclusive
 // scan over the workgroup places the runs, and each thread writes its ids.
-__global__ __launch_bounds__(1024) void k_fused_levels(const FPlan *plan, uint32_t *M0, uint32_t R0,
+__global__ __launch_bounds__(1024) void k_fused_levels(const FPlan *plan, uint32_t j0, uint32_t *M0, uint32_t R0,
                                                       const uint64_t *b0, uint64_t nwords, uint32_t *buf0,
                                                       uint32_t *buf1, uint32_t *loc, uint32_t *out, FStatus *st) {
     __shared__ FusedLds<1024, FUSED_MAX_ROWS, FUSED_MAX_SLOTS, true> L;
@@ -311,41 +406,55 @@ __global__ __launch_bounds__(1024) void k_fused_levels(const FPlan *plan, uint32
     for (uint32_t t = threadIdx.x; t < sizeof(FStatus) / 8; t += 1024) sw[t] = 0;
     if (b0) {
         // each wave owns a contiguous run of words, read 64 at a time
-        // (coalesced): count, place the runs, then emit with wave scans
+        // (coalesced) and four such reads in flight: count, place the runs,
+        // then emit with wave scans
         const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
         const uint64_t per = (nwords + 15) / 16;
         const uint64_t ws = per * wv < nwords ? per * wv : nwords;
         const uint64_t we = ws + per < nwords ? ws + per : nwords;
         uint32_t cnt = 0;
-        for (uint64_t q = ws + lane; q < we; q += 64) cnt += (uint32_t)__popcll(b0[q]);
+        uint64_t q = ws + lane;
+        for (; q + 192 < we; q += 256)
+            cnt += (uint32_t)(__popcll(b0[q]) + __popcll(b0[q + 64]) + __popcll(b0[q + 128]) + __popcll(b0[q + 192]));
+        for (; q < we; q += 64) cnt += (uint32_t)__popcll(b0[q]);
         cnt = wave_sum(cnt);
         if (lane == 0) L.w[wv] = cnt;
         __syncthreads();
         uint32_t at = 0;
         for (uint32_t v = 0; v < wv; v++) at += L.w[v];
-        for (uint64_t base = ws; base < we; base += 64) {
-            const uint64_t q = base + lane;
-            uint64_t m = q < we ? b0[q] : 0ull;
-            const uint32_t pc = (uint32_t)__popcll(m);
-            const uint32_t inc = wave_inclusive_sum(pc);
-            uint32_t o = at + inc - pc;
-            while (m) {
-                const uint32_t b = (uint32_t)__builtin_ctzll(m);
-                if (o < R0) M0[o] = (uint32_t)(q * 64 + b);
-                o++;
-                m &= m - 1;
+        for (uint64_t base = ws; base < we; base += 256) {
+            uint64_t m[4];
+#pragma unroll
+            for (uint32_t t = 0; t < 4; t++) {
+                const uint64_t qq = base + 64 * t + lane;
+                m[t] = qq < we ? b0[qq] : 0ull;
             }
-            at += __shfl(inc, 63, 64);
+#pragma unroll
+            for (uint32_t t = 0; t < 4; t++) {
+                const uint32_t pc = (uint32_t)__popcll(m[t]);
+                const uint32_t inc = wave_inclusive_sum(pc);
+                uint32_t o = at + inc - pc;
+                uint64_t mm = m[t];
+                const uint64_t qq = base + 64 * t + lane;
+                while (mm) {
+                    const uint32_t b = (uint32_t)__builtin_ctzll(mm);
+                    if (o < R0) M0[o] = (uint32_t)(qq * 64 + b);
+                    o++;
+                    mm &= mm - 1;
+                }
+                at += __shfl(inc, 63, 64);
+            }
         }
     }
     __syncthreads();  // status cleared and M0 written before the levels read them
-    fused_query<1024, FUSED_MAX_ROWS, FUSED_MAX_SLOTS, true>(plan, M0, R0, buf0, buf1, loc, out, st, L);
+    fused_query<1024, FUSED_MAX_ROWS, FUSED_MAX_SLOTS, true>(plan, j0, M0, R0, R0, buf0, buf1, loc, out, st, L);
 }
 
-void launch_fused(gsi_ctx *c, const FPlan *d_plan, uint32_t *M0, uint32_t R0, const uint64_t *b0, uint64_t nwords,
-                  uint32_t *buf0, uint32_t *buf1, uint32_t *loc, uint32_t *out, FStatus *d_status, double alg_bytes) {
-    launch(c, "k_fused_levels", alg_bytes, k_fused_levels, 1, 1024, d_plan, M0, R0, b0, nwords, buf0, buf1, loc, out,
-           d_status);
+void launch_fused(gsi_ctx *c, const FPlan *d_plan, uint32_t j0, uint32_t *M0, uint32_t R0, const uint64_t *b0,
+                  uint64_t nwords, uint32_t *buf0, uint32_t *buf1, uint32_t *loc, uint32_t *out, FStatus *d_status,
+                  double alg_bytes) {
+    launch(c, "k_fused_levels", alg_bytes, k_fused_levels, 1, 1024, d_plan, j0, M0, R0, b0, nwords, buf0, buf1, loc,
+           out, d_status);
 }
 
 // Persistent batch: each workgroup takes the next query from a shared
@@ -367,8 +476,9 @@ __global__ __launch_bounds__(FT) void k_fused_batch(const uint8_t *plans, const 
         __syncthreads();
         if (qi >= nitems) break;
         const FBatchItem it = items[qi];
-        fused_query<FT, CR, CS, false>(reinterpret_cast<const FPlan *>(plans + it.plan_off), M0all + it.m0_off, it.R0,
-                                buf0, buf1, loc, outall ? outall + it.out_off : nullptr, sts + qi, L);
+        fused_query<FT, CR, CS, false>(reinterpret_cast<const FPlan *>(plans + it.plan_off), 1, M0all + it.m0_off,
+                                       it.R0, it.R0, buf0, buf1, loc, outall ? outall + it.out_off : nullptr,
+                                       sts + qi, L);
         __syncthreads();
     }
 }
@@ -386,12 +496,12 @@ static void launch_batch_t(gsi_ctx *c, uint32_t grid, const uint8_t *plans, cons
 // Chunks of one query (see launch_fused_chunks).  Every workgroup leaves
 // once the chunk counter passes nchunks or the abort flag is set.
 template <uint32_t FT, uint32_t CR, uint32_t CS>
-__global__ __launch_bounds__(FT) void k_fused_chunks(const FPlan *plan, const uint32_t *M0, uint32_t R0,
+__global__ __launch_bounds__(FT) void k_fused_chunks(const FPlan *plan, uint32_t j0, const uint32_t *M0, uint32_t R0,
                                                     uint32_t chunk_rows, uint32_t nchunks, uint32_t *scratch,
                                                     uint64_t slot_words, uint32_t k, uint32_t *staging,
                                                     uint64_t staging_words, unsigned long long *ocount,
                                                     uint32_t *abort, uint32_t max_fail, FStatus *sts,
-                                                    uint32_t *counter) {
+                                                    uint32_t *counter, FChunkSummary *sum) {
     __shared__ FusedLds<FT, CR, CS, true> L;
     __shared__ uint32_t s_q;
     uint32_t *slot = scratch + (uint64_t)blockIdx.x * slot_words;
@@ -403,9 +513,24 @@ __global__ __launch_bounds__(FT) void k_fused_chunks(const FPlan *plan, const ui
     uint32_t prev = 0xFFFFFFFFu;  // chunk run last (read by thread 0 only)
     for (;;) {
         if (threadIdx.x == 0) {
-            // too many chunks that do not fit: leave the rest to the caller
-            if (prev != 0xFFFFFFFFu && !sts[prev].done && atomicAdd(abort + 1, 1u) + 1 > max_fail)
-                atomicOr(abort, 1u);
+            if (prev != 0xFFFFFFFFu) {
+                // thread 0 wrote the chunk's status itself
+                const FStatus &p = sts[prev];
+                if (p.done) {
+                    // totals of the finished chunks
+                    atomicAdd(&sum->digest[0], p.digest[0]);
+                    atomicXor(&sum->digest[1], p.digest[1]);
+                    atomicMax(&sum->levels, p.levels);
+                    for (uint32_t j = j0; j <= p.levels && j < k; j++) {
+                        atomicAdd(&sum->lv_rows[j], p.lv_rows[j]);
+                        atomicAdd(&sum->lv_gba[j], p.lv_gba[j]);
+                        atomicAdd(&sum->lv_surv[j], p.lv_surv[j]);
+                    }
+                } else if (atomicAdd(abort + 1, 1u) + 1 > max_fail) {
+                    // too many chunks that do not fit: leave the rest to the caller
+                    atomicOr(abort, 1u);
+                }
+            }
             s_q = __atomic_load_n(abort, __ATOMIC_RELAXED) ? nchunks : atomicAdd(counter, 1u);
         }
         __syncthreads();
@@ -414,36 +539,32 @@ __global__ __launch_bounds__(FT) void k_fused_chunks(const FPlan *plan, const ui
         if (qi >= nchunks) break;
         const uint32_t first = qi * chunk_rows;
         const uint32_t rows = min(chunk_rows, R0 - first);
-        fused_query<FT, CR, CS, true>(plan, M0 + first, rows, buf0, buf1, loc, staging, sts + qi, L, ocount,
-                                      staging_words);
+        fused_query<FT, CR, CS, true>(plan, j0, M0 + first, rows, R0, buf0, buf1, loc, staging, sts + qi, L,
+                                      ocount, staging_words);
         prev = qi;
         __syncthreads();
     }
 }
 
-// Totals of a chunked run and each chunk's first output row (exclusive
-// prefix of the counts, chunk order).  One 1024-thread workgroup.
-__global__ __launch_bounds__(1024) void k_chunk_summary(const FStatus *sts, uint32_t n, uint32_t nlevels,
-                                                       uint64_t *offs, uint32_t *done, FChunkSummary *sum) {
+// Each chunk's first output row (exclusive prefix of the counts, chunk
+// order), its done flag, the row total and whether every chunk finished.
+// The other totals were added by the chunk kernel.  One 1024-thread
+// workgroup.
+__global__ __launch_bounds__(1024) void k_chunk_summary(const FStatus *sts, uint32_t n, uint64_t *offs, uint32_t *done,
+                                                       FChunkSummary *sum) {
     __shared__ uint64_t s_w[16];
-    __shared__ uint64_t s_d[3][16];
-    __shared__ uint32_t s_nd[16], s_lv[16];
+    __shared__ uint32_t s_nd[16];
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
-    uint64_t carry = 0, ds = 0, dx = 0;
-    uint32_t notdone = 0, lv = 0;
+    uint64_t carry = 0;
+    uint32_t notdone = 0;
     for (uint32_t base = 0; base < n; base += 1024) {
         const uint32_t i = base + tid;
         uint64_t c = 0;
         if (i < n) {
-            const FStatus &st = sts[i];
-            c = st.done ? st.count : 0ull;
-            done[i] = st.done ? 1u : 0u;
-            notdone += st.done ? 0u : 1u;
-            if (st.done) {
-                ds += st.digest[0];
-                dx ^= st.digest[1];
-                lv = max(lv, (uint32_t)st.levels);
-            }
+            const bool d = sts[i].done != 0;
+            c = d ? sts[i].count : 0ull;
+            done[i] = d ? 1u : 0u;
+            notdone += d ? 0u : 1u;
         }
         const uint64_t inc = wave_inclusive_sum(c);
         if (lane == 63) s_w[w] = inc;
@@ -457,50 +578,15 @@ __global__ __launch_bounds__(1024) void k_chunk_summary(const FStatus *sts, uint
         carry += tot;
         __syncthreads();
     }
-    ds = wave_sum(ds);
-    dx = wave_xor(dx);
     notdone = wave_sum(notdone);
-    for (uint32_t o = 32; o; o >>= 1) lv = max(lv, (uint32_t)__shfl_xor((int)lv, (int)o));
-    if (lane == 0) {
-        s_d[0][w] = ds;
-        s_d[1][w] = dx;
-        s_nd[w] = notdone;
-        s_lv[w] = lv;
-    }
+    if (lane == 0) s_nd[w] = notdone;
     __syncthreads();
     if (tid == 0) {
-        uint64_t a = 0, b = 0;
-        uint32_t nd = 0, l = 0;
-        for (uint32_t q = 0; q < 16; q++) {
-            a += s_d[0][q];
-            b ^= s_d[1][q];
-            nd += s_nd[q];
-            l = max(l, s_lv[q]);
-        }
+        uint32_t nd = 0;
+        for (uint32_t q = 0; q < 16; q++) nd += s_nd[q];
         offs[n] = carry;
         sum->all_done = nd == 0 ? 1u : 0u;
         sum->count = carry;
-        sum->digest[0] = a;
-        sum->digest[1] = b;
-        sum->levels = l;
-    }
-    // per-level sums: wave w takes levels w, w + 16
-    for (uint32_t j = w; j < nlevels; j += 16) {
-        uint64_t r = 0, gb = 0, sv = 0;
-        for (uint32_t i = lane; i < n; i += 64) {
-            const bool d = sts[i].done != 0;
-            r += d ? sts[i].lv_rows[j] : 0ull;
-            gb += d ? sts[i].lv_gba[j] : 0ull;
-            sv += d ? sts[i].lv_surv[j] : 0ull;
-        }
-        r = wave_sum(r);
-        gb = wave_sum(gb);
-        sv = wave_sum(sv);
-        if (lane == 0) {
-            sum->lv_rows[j] = r;
-            sum->lv_gba[j] = gb;
-            sum->lv_surv[j] = sv;
-        }
     }
 }
 
@@ -518,31 +604,31 @@ __global__ __launch_bounds__(256) void k_chunk_gather(const FStatus *sts, const 
 }
 
 template <uint32_t FT>
-static void launch_chunks_t(gsi_ctx *c, uint32_t grid, const FPlan *plan, const uint32_t *M0, uint32_t R0,
+static void launch_chunks_t(gsi_ctx *c, uint32_t grid, const FPlan *plan, uint32_t j0, const uint32_t *M0, uint32_t R0,
                             uint32_t chunk_rows, uint32_t nchunks, uint32_t *scratch, uint64_t slot_words, uint32_t k,
                             uint32_t *staging, uint64_t staging_words, unsigned long long *ocount, uint32_t *abort,
-                            uint32_t max_fail, FStatus *sts, uint32_t *counter, double bytes) {
+                            uint32_t max_fail, FStatus *sts, uint32_t *counter, FChunkSummary *sum, double bytes) {
     constexpr uint32_t CR = 4 * FT, CS = 16 * FT;
-    launch(c, "k_fused_chunks", bytes, k_fused_chunks<FT, CR, CS>, grid, FT, plan, M0, R0, chunk_rows, nchunks,
-           scratch, slot_words, k, staging, staging_words, ocount, abort, max_fail, sts, counter);
+    launch(c, "k_fused_chunks", bytes, k_fused_chunks<FT, CR, CS>, grid, FT, plan, j0, M0, R0, chunk_rows, nchunks,
+           scratch, slot_words, k, staging, staging_words, ocount, abort, max_fail, sts, counter, sum);
 }
 
-void launch_fused_chunks(gsi_ctx *c, const FTier &t, uint32_t grid, const FPlan *plan, const uint32_t *M0,
+void launch_fused_chunks(gsi_ctx *c, const FTier &t, uint32_t grid, const FPlan *plan, uint32_t j0, const uint32_t *M0,
                          uint32_t R0, uint32_t chunk_rows, uint32_t nchunks, uint32_t *scratch, uint64_t slot_words,
                          uint32_t k, uint32_t *staging, uint64_t staging_words, unsigned long long *ocount,
                          uint32_t *abort, uint32_t max_fail, FStatus *sts, uint32_t *counter, uint64_t *offs,
                          uint32_t *done, FChunkSummary *sum) {
     if (t.threads == 64)
-        launch_chunks_t<64>(c, grid, plan, M0, R0, chunk_rows, nchunks, scratch, slot_words, k, staging,
-                            staging_words, ocount, abort, max_fail, sts, counter, 0.0);
+        launch_chunks_t<64>(c, grid, plan, j0, M0, R0, chunk_rows, nchunks, scratch, slot_words, k, staging,
+                            staging_words, ocount, abort, max_fail, sts, counter, sum, 0.0);
     else if (t.threads == 256)
-        launch_chunks_t<256>(c, grid, plan, M0, R0, chunk_rows, nchunks, scratch, slot_words, k, staging,
-                             staging_words, ocount, abort, max_fail, sts, counter, 0.0);
+        launch_chunks_t<256>(c, grid, plan, j0, M0, R0, chunk_rows, nchunks, scratch, slot_words, k, staging,
+                             staging_words, ocount, abort, max_fail, sts, counter, sum, 0.0);
     else
-        launch_chunks_t<1024>(c, grid, plan, M0, R0, chunk_rows, nchunks, scratch, slot_words, k, staging,
-                              staging_words, ocount, abort, max_fail, sts, counter, 0.0);
-    launch(c, "k_chunk_summary", (double)nchunks * sizeof(FStatus), k_chunk_summary, 1, 1024, (const FStatus *)sts,
-           nchunks, k, offs, done, sum);
+        launch_chunks_t<1024>(c, grid, plan, j0, M0, R0, chunk_rows, nchunks, scratch, slot_words, k, staging,
+                              staging_words, ocount, abort, max_fail, sts, counter, sum, 0.0);
+    launch(c, "k_chunk_summary", 16.0 * nchunks, k_chunk_summary, 1, 1024, (const FStatus *)sts, nchunks, offs, done,
+           sum);
 }
 
 void launch_chunk_gather(gsi_ctx *c, uint32_t nchunks, const FStatus *sts, const uint64_t *offs,
@@ -550,19 +636,23 @@ void launch_chunk_gather(gsi_ctx *c, uint32_t nchunks, const FStatus *sts, const
     launch(c, "k_chunk_gather", 8.0 * words, k_chunk_gather, nchunks, 256, sts, offs, staging, k, out);
 }
 
-// Root rows of the given chunks, concatenated: workgroup i copies chunk
-// list[2i] to position list[2i+1].
-__global__ __launch_bounds__(256) void k_take_roots(const uint32_t *M0, uint32_t R0, uint32_t chunk_rows,
-                                                   const uint32_t *list, uint32_t *dst) {
+// Rows of the given chunks, concatenated: workgroup i copies the `ncols`
+// columns of chunk list[2i] to row list[2i+1] of dst (column stride `rows`).
+__global__ __launch_bounds__(256) void k_take_rows(const uint32_t *M0, uint32_t R0, uint32_t ncols,
+                                                  uint32_t chunk_rows, const uint32_t *list, uint32_t *dst,
+                                                  uint64_t rows) {
     const uint32_t ch = list[2 * blockIdx.x], at = list[2 * blockIdx.x + 1];
     const uint32_t first = ch * chunk_rows;
-    const uint32_t rows = min(chunk_rows, R0 - first);
-    for (uint32_t t = threadIdx.x; t < rows; t += 256) dst[at + t] = M0[first + t];
+    const uint32_t n = min(chunk_rows, R0 - first);
+    for (uint32_t col = 0; col < ncols; col++)
+        for (uint32_t t = threadIdx.x; t < n; t += 256)
+            dst[(uint64_t)col * rows + at + t] = M0[(uint64_t)col * R0 + first + t];
 }
 
-void launch_take_roots(gsi_ctx *c, uint32_t nlist, const uint32_t *M0, uint32_t R0, uint32_t chunk_rows,
-                       const uint32_t *list, uint32_t *dst, uint64_t rows) {
-    launch(c, "k_take_roots", 8.0 * rows, k_take_roots, nlist, 256, M0, R0, chunk_rows, list, dst);
+void launch_take_rows(gsi_ctx *c, uint32_t nlist, const uint32_t *M0, uint32_t R0, uint32_t ncols,
+                      uint32_t chunk_rows, const uint32_t *list, uint32_t *dst, uint64_t rows) {
+    launch(c, "k_take_rows", 8.0 * rows * ncols, k_take_rows, nlist, 256, M0, R0, ncols, chunk_rows, list, dst,
+           rows);
 }
 
 FTier fused_tier(uint32_t threads) {

@@ -585,13 +585,22 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
 #pragma unroll
     for (uint32_t r = 0; r < SPT; r++)
         if (kp[r]) kp[r] = (a.Cu[xs[r] >> 6] >> (xs[r] & 63)) & 1ull;
-    // x not in m_i, x in every other linking list
+    // x not in m_i (the row's values are loaded four at a time, not one
+    // dependent load per column), x in every other linking list
 #pragma unroll
     for (uint32_t r = 0; r < SPT; r++) {
         bool keep = kp[r];
         const uint64_t i = ri[r];
         const uint32_t x = xs[r];
-        for (uint32_t c = 0; keep && !a.homo && c < a.j; c++) keep = a.M[(uint64_t)c * a.R + i] != x;
+        if (keep && !a.homo) {
+            for (uint32_t c = 0; c < a.j; c += 4) {
+                uint32_t m0 = a.M[(uint64_t)c * a.R + i];
+                uint32_t m1 = c + 1 < a.j ? a.M[(uint64_t)(c + 1) * a.R + i] : ~x;
+                uint32_t m2 = c + 2 < a.j ? a.M[(uint64_t)(c + 2) * a.R + i] : ~x;
+                uint32_t m3 = c + 3 < a.j ? a.M[(uint64_t)(c + 3) * a.R + i] : ~x;
+                keep = keep && m0 != x && m1 != x && m2 != x && m3 != x;
+            }
+        }
         const uint32_t be = (keep && a.ne > 1) ? a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] : a.e0;
         for (uint32_t e = 0; keep && e < a.ne; e++) {
             if (e == be) continue;
@@ -1155,8 +1164,11 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         return finish();
     };
 
-    uint32_t jstart = 1;
-    if (try_chunks) {
+    // Runs the chunks from level j0 on M (R rows, j0 columns, column stride
+    // R).  Returns 0 when they could not be set up (M unchanged), 1 when
+    // every chunk finished (the result is complete), 2 when some did not:
+    // M and R then hold those chunks' rows, for the per-level kernels.
+    auto run_chunks = [&](uint32_t j0) -> int {
         const FTier t = fused_tier(256);
         const uint64_t slot_words = 2ull * t.cap_rows * k + fused_loc_words(k, t.cap_rows);
         int ncu = 0;
@@ -1174,133 +1186,151 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         const uint64_t ocap = count_only ? 0
                                          : std::min<uint64_t>((uint64_t)nchunks * t.cap_slots * k,
                                                               c->arena.largest_free() / 32);
-        if (grid >= 1 && nchunks <= CHUNK_MAX && (count_only || ocap >= 1024)) {
-            FPlan *hp;
-            FPlan *dplan = fused_plan(0xFFFFFFFFu, 0xFFFFFFFFu, &hp);
-            uint32_t *slots = cs.get<uint32_t>(slot_words * grid, "chunk tables");
-            FStatus *sts = reinterpret_cast<FStatus *>(cs.get<uint64_t>((uint64_t)nchunks * sizeof(FStatus) / 8,
-                                                                        "chunk status"));
-            uint64_t *offs = cs.get<uint64_t>((uint64_t)nchunks + 1, "chunk offsets");
-            uint32_t *dflags = cs.get<uint32_t>(nchunks, "chunk done flags");
-            uint32_t *ctr = cs.get<uint32_t>(4, "chunk counters");  // counter, abort, failures
-            unsigned long long *ocount =
-                reinterpret_cast<unsigned long long *>(cs.get<uint64_t>(1, "chunk output counter"));
-            FChunkSummary *dsum = reinterpret_cast<FChunkSummary *>(
-                cs.get<uint64_t>(sizeof(FChunkSummary) / 8, "chunk summary"));
-            uint32_t *staging = count_only ? nullptr : cs.get<uint32_t>(ocap, "chunk rows");
-            fill_u64(c, reinterpret_cast<uint64_t *>(sts), 0, (uint64_t)nchunks * sizeof(FStatus) / 8);
-            fill_u32(c, ctr, 0, 4);
-            fill_u64(c, reinterpret_cast<uint64_t *>(ocount), 0, 1);
-            const uint32_t max_fail = std::max<uint32_t>(16, nchunks / 8);
-            const size_t ri = c->recs.size();
-            launch_fused_chunks(c, t, (uint32_t)grid, dplan, M, (uint32_t)R, chunk_rows, nchunks, slots, slot_words,
-                                k, staging, ocap, ocount, ctr + 1, max_fail, sts, ctr, offs, dflags, dsum);
-            FChunkSummary *hsum = reinterpret_cast<FChunkSummary *>(reinterpret_cast<char *>(c->pinned) + 4096);
-            GSI_HIP(hipMemcpyAsync(hsum, dsum, sizeof(FChunkSummary), hipMemcpyDeviceToHost, c->stream));
-            sync(c);
-            if ((c->flags & GSI_CTX_PROFILE) && ri < c->recs.size())
-                c->recs[ri].bytes = fused_bytes(hp, (uint32_t)hsum->levels, hsum->lv_rows, hsum->lv_gba,
-                                                hsum->lv_surv);
-            cp.active = true;
-            cp.n = nchunks;
-            cp.count = hsum->count;
-            cp.digest[0] = hsum->digest[0];
-            cp.digest[1] = hsum->digest[1];
-            cp.sts = sts;
-            cp.offs = offs;
-            cp.staging = staging;
-            cp.levels = (uint32_t)hsum->levels;
-            for (uint32_t j = 1; j < k; j++) {
-                cp.rows[j] = hsum->lv_rows[j];
-                cp.gba[j] = hsum->lv_gba[j];
-                cp.surv[j] = hsum->lv_surv[j];
-            }
-            st.chunks = nchunks;
-            if (hsum->all_done) {
-                if (!count_only && cp.count) {
-                    uint32_t *out = persist<uint32_t>(c, cp.count * k, "result rows");
-                    res->rows = out;
-                    merge_chunks(out);
-                } else {
-                    merge_chunks(nullptr);
-                }
-                st.join_ms = ms_since(tj);
-                return finish();
-            }
-            // the roots of the chunks left undone continue level by level
-            std::vector<uint32_t> fl(nchunks);
-            GSI_HIP(hipMemcpyAsync(fl.data(), dflags, 4ull * nchunks, hipMemcpyDeviceToHost, c->stream));
-            sync(c);
-            std::vector<uint32_t> list;
-            uint64_t left = 0;
-            for (uint32_t ch = 0; ch < nchunks; ch++) {
-                if (fl[ch]) continue;
-                list.push_back(ch);
-                list.push_back((uint32_t)left);
-                left += std::min<uint64_t>(chunk_rows, R - (uint64_t)ch * chunk_rows);
-            }
-            st.chunks_left = (uint32_t)(list.size() / 2);
-            uint32_t *dl = cs.get<uint32_t>(list.size(), "chunks left");
-            GSI_HIP(hipMemcpyAsync(dl, list.data(), 4 * list.size(), hipMemcpyHostToDevice, c->stream));
-            Block Mr(c);
-            uint32_t *Mleft = Mr.get<uint32_t>(left, "roots left");
-            launch_take_roots(c, (uint32_t)(list.size() / 2), M, (uint32_t)R, chunk_rows, dl, Mleft, left);
-            sync(c);  // `list` is read by the copy above
-            Mb.reset();
-            Mb.p = Mr.p;
-            Mr.p = nullptr;
-            M = Mleft;
-            R = left;
+        if (!(grid >= 1 && nchunks <= CHUNK_MAX && (count_only || ocap >= 1024))) return 0;
+        FPlan *hp;
+        FPlan *dplan = fused_plan(0xFFFFFFFFu, 0xFFFFFFFFu, &hp);
+        uint32_t *slots = cs.get<uint32_t>(slot_words * grid, "chunk tables");
+        FStatus *sts = reinterpret_cast<FStatus *>(cs.get<uint64_t>((uint64_t)nchunks * sizeof(FStatus) / 8,
+                                                                    "chunk status"));
+        uint64_t *offs = cs.get<uint64_t>((uint64_t)nchunks + 1, "chunk offsets");
+        uint32_t *dflags = cs.get<uint32_t>(nchunks, "chunk done flags");
+        // one zeroed block: counters (next chunk, abort, failures), the
+        // output counter and the summary
+        const uint64_t zwords = 3 + sizeof(FChunkSummary) / 8;
+        uint64_t *zb = cs.get<uint64_t>(zwords, "chunk counters");
+        uint32_t *ctr = reinterpret_cast<uint32_t *>(zb);
+        unsigned long long *ocount = reinterpret_cast<unsigned long long *>(zb + 2);
+        FChunkSummary *dsum = reinterpret_cast<FChunkSummary *>(zb + 3);
+        uint32_t *staging = count_only ? nullptr : cs.get<uint32_t>(ocap, "chunk rows");
+        fill_u64(c, reinterpret_cast<uint64_t *>(sts), 0, (uint64_t)nchunks * sizeof(FStatus) / 8);
+        fill_u64(c, zb, 0, zwords);
+        const uint32_t max_fail = std::max<uint32_t>(16, nchunks / 8);
+        const size_t ri = c->recs.size();
+        launch_fused_chunks(c, t, (uint32_t)grid, dplan, j0, M, (uint32_t)R, chunk_rows, nchunks, slots, slot_words,
+                            k, staging, ocap, ocount, ctr + 1, max_fail, sts, ctr, offs, dflags, dsum);
+        FChunkSummary *hsum = reinterpret_cast<FChunkSummary *>(reinterpret_cast<char *>(c->pinned) + 4096);
+        GSI_HIP(hipMemcpyAsync(hsum, dsum, sizeof(FChunkSummary), hipMemcpyDeviceToHost, c->stream));
+        sync(c);
+        if ((c->flags & GSI_CTX_PROFILE) && ri < c->recs.size())
+            c->recs[ri].bytes = fused_bytes(hp, (uint32_t)hsum->levels, hsum->lv_rows, hsum->lv_gba,
+                                            hsum->lv_surv);
+        cp.active = true;
+        cp.n = nchunks;
+        cp.count = hsum->count;
+        cp.digest[0] = hsum->digest[0];
+        cp.digest[1] = hsum->digest[1];
+        cp.sts = sts;
+        cp.offs = offs;
+        cp.staging = staging;
+        cp.levels = (uint32_t)hsum->levels;
+        for (uint32_t j = 1; j < k; j++) {
+            cp.rows[j] = hsum->lv_rows[j];
+            cp.gba[j] = hsum->lv_gba[j];
+            cp.surv[j] = hsum->lv_surv[j];
         }
-    }
+        st.chunks = nchunks;
+        if (hsum->all_done) {
+            if (!count_only && cp.count) {
+                uint32_t *out = persist<uint32_t>(c, cp.count * k, "result rows");
+                res->rows = out;
+                merge_chunks(out);
+            } else {
+                merge_chunks(nullptr);
+            }
+            st.join_ms = ms_since(tj);
+            return 1;
+        }
+        // the rows of the chunks left undone continue level by level
+        std::vector<uint32_t> fl(nchunks);
+        GSI_HIP(hipMemcpyAsync(fl.data(), dflags, 4ull * nchunks, hipMemcpyDeviceToHost, c->stream));
+        sync(c);
+        std::vector<uint32_t> list;
+        uint64_t left = 0;
+        for (uint32_t ch = 0; ch < nchunks; ch++) {
+            if (fl[ch]) continue;
+            list.push_back(ch);
+            list.push_back((uint32_t)left);
+            left += std::min<uint64_t>(chunk_rows, R - (uint64_t)ch * chunk_rows);
+        }
+        st.chunks_left = (uint32_t)(list.size() / 2);
+        uint32_t *dl = cs.get<uint32_t>(list.size(), "chunks left");
+        GSI_HIP(hipMemcpyAsync(dl, list.data(), 4 * list.size(), hipMemcpyHostToDevice, c->stream));
+        Block Mr(c);
+        uint32_t *Mleft = Mr.get<uint32_t>(left * j0, "rows left");
+        launch_take_rows(c, (uint32_t)(list.size() / 2), M, (uint32_t)R, j0, chunk_rows, dl, Mleft, left);
+        sync(c);  // `list` is read by the copy above
+        Mb.reset();
+        Mb.p = Mr.p;
+        Mr.p = nullptr;
+        M = Mleft;
+        R = left;
+        return 2;
+    };
 
-    // Small root sets: one workgroup runs levels while they fit, then the
-    // per-level kernels continue from where it stopped.
-    if (!cp.active) {
-        const uint32_t cap_rows = fcap_rows, cap_slots = fcap_slots;
-        if (!(flags & GSI_NO_FUSED) && R <= cap_rows && cap_slots >= 64) {
-            FPlan *hp;
-            FPlan *dplan = fused_plan(cap_rows, cap_slots, &hp);
-            uint32_t *buf0 = fs.get<uint32_t>((uint64_t)cap_rows * k, "fused table 0");
-            uint32_t *buf1 = fs.get<uint32_t>((uint64_t)cap_rows * k, "fused table 1");
-            uint32_t *floc = fs.get<uint32_t>(fused_loc_words(k, cap_rows), "fused lookups");
-            FStatus *dst = reinterpret_cast<FStatus *>(fs.get<uint64_t>(sizeof(FStatus) / 8, "fused status"));
-            uint32_t *out = count_only ? nullptr : persist<uint32_t>(c, (uint64_t)cap_slots * k, "result rows");
-            res->rows = out;
-            launch_fused(c, dplan, M, (uint32_t)R, m0_in_fused ? b0 : nullptr, nwords, buf0, buf1, floc, out, dst, 0.0);
-            FStatus *hs = reinterpret_cast<FStatus *>(reinterpret_cast<char *>(c->pinned) + 4096);
-            GSI_HIP(hipMemcpyAsync(hs, dst, sizeof(FStatus), hipMemcpyDeviceToHost, c->stream));
-            sync(c);
-            const uint32_t last = hs->done ? (uint32_t)hs->levels : (uint32_t)hs->level;
-            if ((c->flags & GSI_CTX_PROFILE) && !c->recs.empty())
-                c->recs.back().bytes = fused_bytes(hp, last, hs->lv_rows, hs->lv_gba, hs->lv_surv);
-            for (uint32_t j = 1; j <= last && j < k; j++) {
-                st.rows[j] = hs->lv_rows[j];
-                st.gba[j] = hs->lv_gba[j];
-                st.survivors[j] = hs->lv_surv[j];
-            }
-            if (hs->done) {
-                st.levels = (uint32_t)hs->levels;
-                res->count = hs->count;
-                res->digest[0] = hs->digest[0];
-                res->digest[1] = hs->digest[1];
-                if (out && hs->count == 0) {
-                    c->arena.release(out);
-                    res->rows = nullptr;
-                } else if (out) {
-                    c->arena.shrink(out, hs->count * k * 4);
-                }
-                st.join_ms = ms_since(tj);
-                return finish();
-            }
-            if (out) c->arena.release(out);
-            res->rows = nullptr;
-            jstart = (uint32_t)hs->level;
-            R = hs->rows;
-            if (hs->mloc == 0) M = buf0;
-            else if (hs->mloc == 1) M = buf1;
+    uint32_t jstart = 1;
+    if (try_chunks && run_chunks(1) == 1) return finish();
+
+    // One workgroup runs levels j0.. of M (R rows, j0 columns) while they
+    // fit.  Returns true when it finished the query (the result is
+    // complete); otherwise M and R hold the input of the level it stopped
+    // at, returned in `stop`.
+    const uint32_t cap_rows = fcap_rows, cap_slots = fcap_slots;
+    FPlan *fhp = nullptr, *fdplan = nullptr;
+    uint32_t *fbuf0 = nullptr, *fbuf1 = nullptr, *floc = nullptr;
+    FStatus *fdst = nullptr;
+    auto run_fused = [&](uint32_t j0, const uint64_t *root_bits, uint32_t &stop) -> bool {
+        if (!fdplan) {
+            fdplan = fused_plan(cap_rows, cap_slots, &fhp);
+            fbuf0 = fs.get<uint32_t>((uint64_t)cap_rows * k, "fused table 0");
+            fbuf1 = fs.get<uint32_t>((uint64_t)cap_rows * k, "fused table 1");
+            floc = fs.get<uint32_t>(fused_loc_words(k, cap_rows), "fused lookups");
+            fdst = reinterpret_cast<FStatus *>(fs.get<uint64_t>(sizeof(FStatus) / 8, "fused status"));
         }
+        uint32_t *out = count_only ? nullptr : persist<uint32_t>(c, (uint64_t)cap_slots * k, "result rows");
+        res->rows = out;
+        launch_fused(c, fdplan, j0, M, (uint32_t)R, root_bits, nwords, fbuf0, fbuf1, floc, out, fdst, 0.0);
+        FStatus *hs = reinterpret_cast<FStatus *>(reinterpret_cast<char *>(c->pinned) + 4096);
+        GSI_HIP(hipMemcpyAsync(hs, fdst, sizeof(FStatus), hipMemcpyDeviceToHost, c->stream));
+        sync(c);
+        const uint32_t last = hs->done ? (uint32_t)hs->levels : (uint32_t)hs->level;
+        if ((c->flags & GSI_CTX_PROFILE) && !c->recs.empty())
+            c->recs.back().bytes = fused_bytes(fhp, last, hs->lv_rows, hs->lv_gba, hs->lv_surv);
+        for (uint32_t j = j0; j <= last && j < k; j++) {
+            st.rows[j] = hs->lv_rows[j];
+            st.gba[j] = hs->lv_gba[j];
+            st.survivors[j] = hs->lv_surv[j];
+        }
+        if (hs->done) {
+            st.levels = (uint32_t)hs->levels;
+            res->count = hs->count;
+            res->digest[0] = hs->digest[0];
+            res->digest[1] = hs->digest[1];
+            if (out && hs->count == 0) {
+                c->arena.release(out);
+                res->rows = nullptr;
+            } else if (out) {
+                c->arena.shrink(out, hs->count * k * 4);
+            }
+            st.join_ms = ms_since(tj);
+            return true;
+        }
+        if (out) c->arena.release(out);
+        res->rows = nullptr;
+        stop = (uint32_t)hs->level;
+        R = hs->rows;
+        if (hs->mloc == 0) M = fbuf0;
+        else if (hs->mloc == 1) M = fbuf1;
+        return false;
+    };
+    const bool fused_ok = !(flags & GSI_NO_FUSED) && cap_slots >= 64;
+
+    // Small root sets: the workgroup starts; the per-level kernels continue
+    // from where it stopped, and hand the query back to it once the table
+    // fits again.
+    if (!cp.active && fused_ok && R <= cap_rows) {
+        if (run_fused(1, m0_in_fused ? b0 : nullptr, jstart)) return finish();
     }
+    uint32_t fused_stuck = NONE32;  // level at which the workgroup last stopped without progress
 
     for (uint32_t j = jstart; j < k; j++) {
         const uint32_t u = order[j];
@@ -1354,7 +1384,12 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         const uint64_t nbr = nblocks(R);
         const bool prof = (c->flags & GSI_CTX_PROFILE) != 0;
         a.part = prof ? ls.get<uint64_t>(2 * nbr, "locate partials") : nullptr;
-        launch(c, "k_locate", (double)R * (4.0 * ne + 128.0 * ne + 8.0 * ne + 4.0), k_locate, (uint32_t)nbr, QT, a);
+        // row values, the located lists and offsets written, and one 128 B
+        // group per lookup, counted at most once per group of the label
+        // (rows repeat vertices, and a repeated group is a cache hit)
+        double lbytes = (double)R * (4.0 * ne + 4.0 * (2.0 * ne + 2.0) + 4.0 + 8.0);
+        for (uint32_t i = 0; i < ne; i++) lbytes += 128.0 * (double)std::min<uint64_t>(R, a.e[i].G);
+        launch(c, "k_locate", lbytes, k_locate, (uint32_t)nbr, QT, a);
         if (prof) reduce_pairs(c, a.part, nbr, dscal + 2);
         exclusive_scan(c, a.bound, R, F, ls, dscal + 3);
         uint64_t sc[2];
@@ -1425,7 +1460,17 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         Mb.p = Mn.p;
         Mn.p = nullptr;
         M = a.Mn;
+        const double slots_per_row = (double)gba / (double)R;
         R = S;
+        // back to the single workgroup when the table fits and, at this
+        // level's slots per row, so would the next level's |GBA|; not right
+        // after it stopped without finishing a level
+        if (!cp.active && fused_ok && R <= cap_rows && (double)R * slots_per_row <= cap_slots && fused_stuck != j) {
+            uint32_t stop = 0;
+            if (run_fused(j + 1, nullptr, stop)) return finish();
+            if (stop == j + 1) fused_stuck = j + 1;
+            j = stop - 1;  // the loop continues with level `stop`
+        }
     }
     return done();
 }

@@ -219,8 +219,10 @@ typedef struct {
  *      the order-independent digest.
  * Up to 4096 roots one fused workgroup runs the levels while the tables stay
  * small (4096 rows and 16384 |GBA| slots per level, with F, the keep bits and
- * the survivor prefix sums in LDS) and the per-level kernels continue from
- * the first level that does not fit.  Above that, rows of M being
+ * the survivor prefix sums in LDS); the per-level kernels run a level that
+ * does not fit, and the workgroup takes the query back once the new table
+ * fits and the next level's |GBA|, estimated at the current slots per row,
+ * would fit too.  Above that, rows of M being
  * independent at every level, step 3 first runs on root chunks: small groups
  * of rows of M = C(u_first), each taken by one 256-thread workgroup of a
  * persistent launch that runs all levels of its chunk (1024 rows and 4096

@@ -61,9 +61,17 @@ __device__ __forceinline__ void lds_rows(const uint32_t *F, uint32_t R, const ui
 // bitmap words a wave takes per round of the fused join and link
 constexpr uint32_t FU = 2;
 
+// Words of each of the two LDS buffers that hold intermediate tables small
+// enough (rows x columns), sized to what the workgroup's LDS has left.
+template <uint32_t FT, bool XS>
+constexpr uint32_t fused_table_words() {
+    return FT == 1024 ? (XS ? 7168u : 14336u) : FT == 256 ? 1536u : 384u;
+}
+
 // LDS of one fused workgroup with FT threads, CR rows and CS slots: F, the
 // start of each row's scanned list, the keep bits and their prefix sums,
-// and (XS) each slot's element x, so that the link re-reads no list
+// (XS) each slot's element x, so that the link re-reads no list, and two
+// table buffers
 template <uint32_t FT, uint32_t CR, uint32_t CS, bool XS>
 struct FusedLds {
     uint32_t F[CR + 1];
@@ -74,7 +82,9 @@ struct FusedLds {
     uint64_t d[2][FT / 64];
     uint64_t obase;
     uint32_t x[XS ? CS : 1];
+    uint32_t mt[2][fused_table_words<FT, XS>()];
 };
+static_assert(sizeof(FusedLds<1024, 4096, 16384, true>) <= 160 * 1024, "fused workgroup LDS");
 
 // Join levels j0 .. k-1 of one query in one workgroup (see the file
 // comment), starting from the table M0 of R0 rows and j0 columns (column c
@@ -102,10 +112,19 @@ __device__ __forceinline__ void fused_query(const FPlan *plan, uint32_t j0, cons
     uint32_t R = R0;
     uint32_t ld = ld0;  // column stride of M
     uint32_t mloc = FSTATUS_IN_FIRST;  // where M lives
-    uint32_t *bufs[2] = {buf0, buf1};
+    // A table of at most MT words is written to (and read from) LDS instead
+    // of global memory; M then has column stride R.  M sits at index
+    // next ^ 1 of its space (global or LDS), M' goes to index `next`.
+    constexpr uint32_t MT = fused_table_words<FT, XS>();
+    bool m_lds = false;
     uint32_t next = 0;
-    // level j does not fit: record where, and where its input M lives
+    // level j does not fit: record where, and where its input M lives (a
+    // table in LDS is copied to buf0 for the caller)
     auto stop = [&](uint32_t j) {
+        if (m_lds) {
+            for (uint32_t t = tid; t < R * j; t += FT) buf0[t] = M[t];
+            mloc = 0;
+        }
         if (tid == 0) {
             st->level = j;
             st->rows = R;
@@ -295,7 +314,9 @@ __device__ __forceinline__ void fused_query(const FPlan *plan, uint32_t j0, cons
         // link: (m_i, x) at its position; the last level writes rows in
         // query-vertex order and hashes them.  FU words per wave and round,
         // as in the join.
-        uint32_t *Mn = bufs[next];
+        const bool n_lds = !final_level && (uint64_t)S * (j + 1) <= MT;
+        // (selects, not an indexed pointer array, which would live in scratch)
+        uint32_t *Mn = n_lds ? (next ? L.mt[1] : L.mt[0]) : (next ? buf1 : buf0);
         uint64_t hs = 0, hx = 0;
         for (uint32_t base = 0; base < nw; base += FU * (FT / 64)) {
             uint32_t pr[FU], ir[FU], fr[FU], pos[FU], xr[FU];
@@ -388,7 +409,8 @@ __device__ __forceinline__ void fused_query(const FPlan *plan, uint32_t j0, cons
         M = Mn;
         R = S;
         ld = S;
-        mloc = next;
+        m_lds = n_lds;
+        if (!n_lds) mloc = next;
         next ^= 1u;
     }
 }

@@ -116,154 +116,90 @@ static void query_signatures(const HostQuery &q, FilterArgs &fa, bool homo = fal
     }
 }
 
-// One pass over the column-first table for all query vertices.  A lane owns
-// one data vertex and a bit mask of the query vertices whose label it
-// carries.  It then issues, back to back, the loads of every signature word
-// some query vertex uses (a wave reads word i of 64 consecutive vertices in
-// one 256-byte access; a lane whose label matched no query vertex fetches
-// nothing) and tests each candidate query vertex against the words.  The
-// wave's ballot of "v in C(u)" is the bitset word of its 64 vertices.
-__global__ __launch_bounds__(QT) void k_filter(const uint32_t *sig, uint32_t n, uint64_t nwords, FilterArgs fa,
-                                              uint64_t *bits, uint32_t *part) {
-    __shared__ uint32_t s_cnt[GSI_MAX_K];
-    if (threadIdx.x < GSI_MAX_K) s_cnt[threadIdx.x] = 0;
-    __syncthreads();
-    const uint64_t v = (uint64_t)blockIdx.x * QT + threadIdx.x;
+// One tile of 256 data vertices against the query vertices of `fa`: a lane
+// owns one data vertex and reads its label and every signature word some
+// query vertex uses, all in one batch of loads (a wave reads word i of 64
+// consecutive vertices in one 256-byte access; since 32 vertices share a
+// 128-byte line, skipping the words of vertices whose label matches no query
+// vertex would save no traffic, only add a second round trip).  The wave's
+// ballot of "v in C(u)" is the bitset word of its 64 vertices; lane u stores
+// the word of query vertex u, so one store instruction writes them all.
+__device__ __forceinline__ void filter_tile(const uint32_t *sig, uint32_t n, uint64_t nwords, const FilterArgs &fa,
+                                            uint32_t need, uint64_t tile, uint64_t *bits) {
+    const uint64_t v = tile * QT + threadIdx.x;
     const bool valid = v < n;
-    const uint32_t lane = lane_id();
-    const uint64_t wave_first = (uint64_t)blockIdx.x * QT + (threadIdx.x & ~63u);
-    const uint32_t w0 = valid ? sig[v] : NONE32;
-    uint32_t ok = 0;
-    for (uint32_t u = 0; u < fa.k; u++) ok |= (valid && w0 == fa.q[u][0]) ? (1u << u) : 0u;
-    const uint32_t need = fa.label_only ? 0u : fa.word_mask;
     uint32_t wv[GSI_SIG_WORDS];
+    wv[0] = valid ? sig[v] : NONE32;
 #pragma unroll
-    for (int i = 1; i < GSI_SIG_WORDS; i++)
-        wv[i] = (((need >> i) & 1u) && ok) ? sig[(uint64_t)i * n + v] : 0xFFFFFFFFu;
-    if (ok && need) {
-        for (uint32_t u = 0; u < fa.k; u++) {
-            if (!((ok >> u) & 1u)) continue;
-            bool good = true;
+    for (int i = 1; i < GSI_SIG_WORDS; i++) wv[i] = (((need >> i) & 1u) && valid) ? sig[(uint64_t)i * n + v] : NONE32;
+    const uint32_t K = fa.k;
+    uint32_t ok = 0;
+    for (uint32_t u = 0; u < K; u++) {
+        bool good = valid && wv[0] == fa.q[u][0];
 #pragma unroll
-            for (int i = 1; i < GSI_SIG_WORDS; i++) {
-                const uint32_t qw = fa.q[u][i];
-                good = good && ((wv[i] & qw) == qw);
-            }
-            if (!good) ok &= ~(1u << u);
+        for (int i = 1; i < GSI_SIG_WORDS; i++) {
+            const uint32_t qw = need ? fa.q[u][i] : 0u;
+            good = good && ((wv[i] & qw) == qw);
         }
+        ok |= good ? (1u << u) : 0u;
     }
-    for (uint32_t u = 0; u < fa.k; u++) {
-        const uint64_t mask = __ballot((ok >> u) & 1u);
-        if (lane == 0 && wave_first < n) {
-            bits[(uint64_t)fa.dst[u] * nwords + (wave_first >> 6)] = mask;
-            if (mask) atomicAdd(&s_cnt[u], (uint32_t)__popcll(mask));
-        }
+    const uint32_t lane = lane_id();
+    uint64_t mine = 0;
+    for (uint32_t u = 0; u < K; u++) {
+        const uint64_t m = __ballot((ok >> u) & 1u);
+        if (lane == u) mine = m;
     }
-    __syncthreads();
-    // one partial count per workgroup and query vertex (summed by
-    // k_filter_counts; no same-address atomics across workgroups)
-    if (threadIdx.x < GSI_MAX_K) part[(uint64_t)blockIdx.x * GSI_MAX_K + threadIdx.x] = s_cnt[threadIdx.x];
+    const uint64_t wave_first = tile * QT + (threadIdx.x & ~63u);
+    if (lane < K && wave_first < n) bits[(uint64_t)fa.dst[lane] * nwords + (wave_first >> 6)] = mine;
 }
 
-// counts[dst[u]] = sum over workgroups of the partial counts of u; one
-// workgroup per query vertex
-__global__ __launch_bounds__(QT) void k_filter_counts(const uint32_t *part, uint32_t nb, FilterArgs fa,
-                                                     uint32_t *counts) {
-    __shared__ uint32_t s_w[QT / 64];
-    const uint32_t u = blockIdx.x;
+// the filter for one query: one tile per workgroup
+__global__ __launch_bounds__(QT) void k_filter(const uint32_t *sig, uint32_t n, uint64_t nwords, FilterArgs fa,
+                                              uint64_t *bits) {
+    filter_tile(sig, n, nwords, fa, fa.label_only ? 0u : fa.word_mask, blockIdx.x, bits);
+}
+
+// counts[r] = set bits of bitset row r (one 1024-thread workgroup per row)
+__global__ __launch_bounds__(1024) void k_bit_counts(const uint64_t *bits, uint64_t nwords, uint32_t *counts) {
+    __shared__ uint32_t s_w[16];
+    const uint64_t *row = bits + (uint64_t)blockIdx.x * nwords;
     uint32_t sum = 0;
-    for (uint32_t b = threadIdx.x; b < nb; b += QT) sum += part[(uint64_t)b * GSI_MAX_K + u];
+    uint64_t q = threadIdx.x;
+    for (; q + 3072 < nwords; q += 4096)
+        sum += (uint32_t)(__popcll(row[q]) + __popcll(row[q + 1024]) + __popcll(row[q + 2048]) + __popcll(row[q + 3072]));
+    for (; q < nwords; q += 1024) sum += (uint32_t)__popcll(row[q]);
     sum = wave_sum(sum);
     if (lane_id() == 0) s_w[threadIdx.x >> 6] = sum;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t t = 0;
-        for (int q = 0; q < QT / 64; q++) t += s_w[q];
-        counts[fa.dst[u]] = t;
+        for (int w = 0; w < 16; w++) t += s_w[w];
+        counts[blockIdx.x] = t;
     }
 }
 
-static void launch_filter(gsi_ctx *c, gsi_graph *g, const FilterArgs &fa, uint64_t *bits, uint32_t *counts,
-                          uint32_t *part) {
+static void launch_filter(gsi_ctx *c, gsi_graph *g, const FilterArgs &fa, uint64_t *bits, uint32_t *counts) {
     const uint64_t nwords = ((uint64_t)g->n + 63) / 64;
     const uint32_t nb = nblocks(g->n);
-    double bytes = 4.0 * g->n * (1 + __builtin_popcount(fa.word_mask)) + (double)fa.k * nwords * 8;
-    launch(c, "k_filter", bytes, k_filter, nb, QT, (const uint32_t *)g->sig, g->n, nwords, fa, bits, part);
-    launch(c, "k_filter_counts", 4.0 * nb * fa.k, k_filter_counts, fa.k, QT, (const uint32_t *)part, nb, fa, counts);
+    const uint32_t need = fa.label_only ? 0u : fa.word_mask;
+    double bytes = 4.0 * g->n * (1 + __builtin_popcount(need)) + (double)fa.k * nwords * 8;
+    launch(c, "k_filter", bytes, k_filter, nb, QT, (const uint32_t *)g->sig, g->n, nwords, fa, bits);
+    launch(c, "k_filter_counts", 8.0 * fa.k * nwords, k_bit_counts, fa.k, 1024, (const uint64_t *)bits, nwords,
+           counts);
 }
 
 // Batched filter: the query vertices of many queries, 32 per pass, all
-// passes in one launch (blockIdx.y = pass; each workgroup copies its pass's
-// query signatures into LDS).  Passes take query vertices sorted by label,
-// so a pass usually covers one or two labels and lanes of other labels read
-// nothing past word 0, which stays in the caches across passes.
+// passes in one launch (blockIdx.y = pass; workgroups stride over the
+// tiles).  Passes take query vertices sorted by label, so a pass usually
+// covers few labels and few signature words.
 __global__ __launch_bounds__(QT) void k_filter_multi(const uint32_t *sig, uint32_t n, uint64_t nwords,
-                                                    const FilterArgs *__restrict__ passes, uint64_t *bits,
-                                                    uint32_t *part) {
+                                                    const FilterArgs *__restrict__ passes, uint64_t *bits) {
     // the pass's query signatures: a uniform, read-only address, so the
     // compiler reads them with scalar loads (as kernel arguments are)
     const FilterArgs &fa = passes[blockIdx.y];
-    __shared__ uint32_t s_cnt[GSI_MAX_K];
-    if (threadIdx.x < GSI_MAX_K) s_cnt[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t K = fa.k;
-    const uint32_t need = fa.word_mask;
-    const uint32_t lane = lane_id();
     const uint64_t ntiles = ((uint64_t)n + QT - 1) / QT;
-    // workgroups stride over the 256-vertex tiles of the table
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint64_t v = tile * QT + threadIdx.x;
-        const bool valid = v < n;
-        const uint64_t wave_first = tile * QT + (threadIdx.x & ~63u);
-        const uint32_t w0 = valid ? sig[v] : NONE32;
-        uint32_t ok = 0;
-        for (uint32_t u = 0; u < K; u++) ok |= (valid && w0 == fa.q[u][0]) ? (1u << u) : 0u;
-        uint32_t wv[GSI_SIG_WORDS];
-#pragma unroll
-        for (int i = 1; i < GSI_SIG_WORDS; i++)
-            wv[i] = (((need >> i) & 1u) && ok) ? sig[(uint64_t)i * n + v] : 0xFFFFFFFFu;
-        if (ok && need) {
-            for (uint32_t u = 0; u < K; u++) {
-                if (!((ok >> u) & 1u)) continue;
-                bool good = true;
-#pragma unroll
-                for (int i = 1; i < GSI_SIG_WORDS; i++) {
-                    const uint32_t qw = fa.q[u][i];
-                    good = good && ((wv[i] & qw) == qw);
-                }
-                if (!good) ok &= ~(1u << u);
-            }
-        }
-        for (uint32_t u = 0; u < K; u++) {
-            const uint64_t mask = __ballot((ok >> u) & 1u);
-            if (lane == 0 && wave_first < n) {
-                bits[(uint64_t)fa.dst[u] * nwords + (wave_first >> 6)] = mask;
-                if (mask) atomicAdd(&s_cnt[u], (uint32_t)__popcll(mask));
-            }
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < GSI_MAX_K)
-        part[((uint64_t)blockIdx.y * gridDim.x + blockIdx.x) * GSI_MAX_K + threadIdx.x] = s_cnt[threadIdx.x];
-}
-
-// counts of every pass: workgroup (u, pass) sums u's partial counts
-__global__ __launch_bounds__(QT) void k_filter_counts_multi(const uint32_t *part, uint32_t nb,
-                                                           const FilterArgs *passes, uint32_t *counts) {
-    __shared__ uint32_t s_w[QT / 64];
-    const uint32_t u = blockIdx.x, pass = blockIdx.y;
-    const FilterArgs &fa = passes[pass];
-    if (u >= fa.k) return;
-    uint32_t sum = 0;
-    for (uint32_t b = threadIdx.x; b < nb; b += QT) sum += part[((uint64_t)pass * nb + b) * GSI_MAX_K + u];
-    sum = wave_sum(sum);
-    if (lane_id() == 0) s_w[threadIdx.x >> 6] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = 0;
-        for (int q = 0; q < QT / 64; q++) t += s_w[q];
-        counts[fa.dst[u]] = t;
-    }
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+        filter_tile(sig, n, nwords, fa, fa.word_mask, tile, bits);
 }
 
 void run_filter_many(gsi_graph *g, const std::vector<const HostQuery *> &qs, const std::vector<uint32_t> &qbase,
@@ -304,13 +240,12 @@ void run_filter_many(gsi_graph *g, const std::vector<const HostQuery *> &qs, con
     const uint32_t nb = std::min<uint32_t>(nblocks(g->n), std::max<uint32_t>(32, 8192 / npass));
     FilterArgs *dp = reinterpret_cast<FilterArgs *>(s.get<uint32_t>((uint64_t)npass * sizeof(FilterArgs) / 4,
                                                                     "filter passes"));
-    uint32_t *part = s.get<uint32_t>((uint64_t)npass * nb * GSI_MAX_K, "filter partial counts");
     GSI_HIP(hipMemcpyAsync(dp, passes.data(), sizeof(FilterArgs) * npass, hipMemcpyHostToDevice, c->stream));
     const double bytes = 4.0 * g->n * words + (double)all.size() * nwords * 8;
     launch(c, "k_filter", bytes, k_filter_multi, dim3(nb, npass), QT, (const uint32_t *)g->sig, g->n, nwords,
-           (const FilterArgs *)dp, bits, part);
-    launch(c, "k_filter_counts", 4.0 * nb * all.size(), k_filter_counts_multi, dim3(GSI_MAX_K, npass), QT,
-           (const uint32_t *)part, nb, (const FilterArgs *)dp, counts);
+           (const FilterArgs *)dp, bits);
+    launch(c, "k_filter_counts", 8.0 * all.size() * nwords, k_bit_counts, (uint32_t)all.size(), 1024,
+           (const uint64_t *)bits, nwords, counts);
     sync(c);  // `passes` is read by the copy above
 }
 
@@ -320,9 +255,7 @@ static void filter_impl(gsi_graph *g, const HostQuery &q, bool label_only, uint6
     FilterArgs fa;
     query_signatures(q, fa, homo);
     fa.label_only = label_only ? 1u : 0u;
-    Scratch s(c);
-    uint32_t *part = s.get<uint32_t>((uint64_t)nblocks(g->n) * GSI_MAX_K, "filter partial counts");
-    launch_filter(c, g, fa, bits, counts, part);
+    launch_filter(c, g, fa, bits, counts);
 }
 
 void run_filter(gsi_graph *g, const HostQuery &q, uint64_t *bits, uint32_t *counts) {

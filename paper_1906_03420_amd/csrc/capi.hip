@@ -165,6 +165,11 @@ static void drain_records(gsi_ctx *c) {
 }
 
 void read_scalars(gsi_ctx *c, const uint64_t *dev, uint64_t *host, int n) {
+    if (c->mbox_dev && dev >= c->mbox_dev && dev + n <= c->mbox_dev + MAILBOX_WORDS) {
+        GSI_HIP(hipStreamSynchronize(c->stream));
+        memcpy(host, c->mbox_host + (dev - c->mbox_dev), sizeof(uint64_t) * n);
+        return;
+    }
     GSI_HIP(hipMemcpyAsync(c->pinned, dev, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, c->stream));
     GSI_HIP(hipStreamSynchronize(c->stream));
     memcpy(host, c->pinned, sizeof(uint64_t) * n);
@@ -199,7 +204,12 @@ gsi_status gsi_ctx_create(const gsi_options *o, gsi_ctx **out) {
         c->flags = o->flags;
         c->arena.init(o->arena_ptr, o->arena_bytes);
         hipError_t e = hipHostMalloc((void **)&c->pinned, 65536, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&c->mbox_host, MAILBOX_WORDS * 8, hipHostMallocCoherent | hipHostMallocMapped);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&c->mbox_dev, c->mbox_host, 0);
         if (e != hipSuccess) {
+            if (c->pinned) (void)hipHostFree(c->pinned);
+            if (c->mbox_host) (void)hipHostFree(c->mbox_host);
             delete c;
             fail(GSI_E_DEVICE, "hipHostMalloc failed: %s", hipGetErrorString(e));
         }
@@ -220,6 +230,7 @@ gsi_status gsi_ctx_destroy(gsi_ctx *c) {
         }
         for (auto e : c->free_events) (void)hipEventDestroy(e);
         if (c->pinned) (void)hipHostFree(c->pinned);
+        if (c->mbox_host) (void)hipHostFree(c->mbox_host);
         delete c;
     })
 }

@@ -76,6 +76,11 @@ struct gsi_ctx {
     uint32_t flags = 0;
     gsi::Arena arena;
     uint64_t *pinned = nullptr;  // host-pinned staging: scalars [0,4K), status [4K,8K), plans [8K,64K)
+    // Host-coherent mailbox (MAILBOX_WORDS words) that kernels write the
+    // scalars the host waits for straight into: after a stream sync the host
+    // reads them without a device-to-host copy.  mbox_dev is its device
+    // address, mbox_host the host one.
+    uint64_t *mbox_host = nullptr, *mbox_dev = nullptr;
     std::atomic<int> busy{0};
     std::set<gsi_graph *> graphs;
     std::set<gsi_result *> results;
@@ -189,6 +194,12 @@ T *persist(gsi_ctx *c, uint64_t count, const char *what) {
 }
 
 // Reads back `n` uint64 values from device memory (synchronises the stream).
+constexpr uint64_t MAILBOX_WORDS = 512;
+// mailbox words of one query: candidate counts (32 x u32), level scalars,
+// the fused workgroup's status
+constexpr uint64_t MBOX_COUNTS = 0, MBOX_SCALARS = 16, MBOX_STATUS = 32;
+// Reads back `n` uint64 values from device memory, or from the mailbox
+// without a copy (synchronises the stream either way).
 void read_scalars(gsi_ctx *c, const uint64_t *dev, uint64_t *host, int n);
 void sync(gsi_ctx *c);
 

@@ -912,8 +912,10 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     Scratch s(c);
     const uint64_t nwords = ((uint64_t)g->n + 63) / 64;
     uint64_t *bits = s.get<uint64_t>(nwords * k, "candidate bitsets");
-    uint32_t *dcnt = s.get<uint32_t>(k, "candidate counts");
-    uint64_t *dscal = s.get<uint64_t>(4, "level scalars");
+    static_assert(MBOX_STATUS + sizeof(FStatus) / 8 <= MAILBOX_WORDS, "mailbox holds the fused status");
+    // counts and level scalars go straight to the host mailbox
+    uint32_t *dcnt = reinterpret_cast<uint32_t *>(c->mbox_dev + MBOX_COUNTS);
+    uint64_t *dscal = c->mbox_dev + MBOX_SCALARS;
     auto tf = std::chrono::steady_clock::now();
     filter_impl(g, q, (flags & GSI_FILTER_LABEL_ONLY) != 0, bits, dcnt, homo);
     std::vector<uint32_t> cand(k);
@@ -1217,13 +1219,12 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
             fbuf0 = fs.get<uint32_t>((uint64_t)cap_rows * k, "fused table 0");
             fbuf1 = fs.get<uint32_t>((uint64_t)cap_rows * k, "fused table 1");
             floc = fs.get<uint32_t>(fused_loc_words(k, cap_rows), "fused lookups");
-            fdst = reinterpret_cast<FStatus *>(fs.get<uint64_t>(sizeof(FStatus) / 8, "fused status"));
+            fdst = reinterpret_cast<FStatus *>(c->mbox_dev + MBOX_STATUS);
         }
         uint32_t *out = count_only ? nullptr : persist<uint32_t>(c, (uint64_t)cap_slots * k, "result rows");
         res->rows = out;
         launch_fused(c, fdplan, j0, M, (uint32_t)R, root_bits, nwords, fbuf0, fbuf1, floc, out, fdst, 0.0);
-        FStatus *hs = reinterpret_cast<FStatus *>(reinterpret_cast<char *>(c->pinned) + 4096);
-        GSI_HIP(hipMemcpyAsync(hs, fdst, sizeof(FStatus), hipMemcpyDeviceToHost, c->stream));
+        FStatus *hs = reinterpret_cast<FStatus *>(c->mbox_host + MBOX_STATUS);
         sync(c);
         const uint32_t last = hs->done ? (uint32_t)hs->levels : (uint32_t)hs->level;
         if ((c->flags & GSI_CTX_PROFILE) && !c->recs.empty())

@@ -36,9 +36,19 @@ struct FPlan {
     FEdge edges[1];               // all levels' edges follow
 };
 
-inline size_t fplan_bytes(uint32_t n_edges) {
+constexpr size_t fplan_bytes(uint32_t n_edges) {
     return sizeof(FPlan) + (n_edges ? n_edges - 1 : 0) * sizeof(FEdge);
 }
+
+// A plan of up to FPLAN_ARG_EDGES edges passed by value as a kernel argument
+// (no upload before the launch); its edges continue into `more`.
+constexpr uint32_t FPLAN_ARG_EDGES = 64;
+struct FPlanArg {
+    FPlan p;
+    FEdge more[FPLAN_ARG_EDGES - 1];
+};
+static_assert(sizeof(FPlanArg) == fplan_bytes(FPLAN_ARG_EDGES), "plan edges are contiguous");
+static_assert(sizeof(FPlanArg) <= 3072, "kernel arguments stay under 4 KiB");
 
 struct FStatus {
     uint64_t done;    // 1: every level finished (count/digest valid)
@@ -110,8 +120,10 @@ void launch_take_rows(gsi_ctx *c, uint32_t nlist, const uint32_t *M0, uint32_t R
 
 // The single-workgroup fused kernel, levels j0.. of the table M0 (R0 rows,
 // j0 columns, column stride R0); with b0 (the bitset of C(u_first), nwords
-// words; j0 = 1 only) it also writes M0 itself.
-void launch_fused(gsi_ctx *c, const FPlan *d_plan, uint32_t j0, uint32_t *M0, uint32_t R0, const uint64_t *b0,
+// words; j0 = 1 only) it also writes M0 itself.  The plan is d_plan in
+// device memory or, when d_plan is null, `inl`.
+void launch_fused(gsi_ctx *c, const FPlan *d_plan, const FPlanArg &inl, uint32_t j0, uint32_t *M0, uint32_t R0,
+                  const uint64_t *b0,
                   uint64_t nwords, uint32_t *buf0, uint32_t *buf1, uint32_t *loc, uint32_t *out, FStatus *d_status,
                   double alg_bytes);
 

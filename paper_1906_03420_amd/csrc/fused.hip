@@ -420,10 +420,17 @@ __device__ __forceinline__ void fused_query(const FPlan *plan, uint32_t j0, cons
 // written here too from its bitset (ascending vertex order, R0 entries):
 // each thread counts the set bits of a run of bitset words, an exclusive
 // scan over the workgroup places the runs, and each thread writes its ids.
-__global__ __launch_bounds__(1024) void k_fused_levels(const FPlan *plan, uint32_t j0, uint32_t *M0, uint32_t R0,
+// INL: the plan is the kernel argument `inl` (read with scalar loads from
+// the argument segment), else d_plan in device memory.  Two instances, not a
+// select: a pointer that may address either space is generic, and every
+// plan field would be read with vector loads.
+template <bool INL>
+__global__ __launch_bounds__(1024) void k_fused_levels(const FPlan *d_plan, FPlanArg inl, uint32_t j0, uint32_t *M0,
+                                                      uint32_t R0,
                                                       const uint64_t *b0, uint64_t nwords, uint32_t *buf0,
                                                       uint32_t *buf1, uint32_t *loc, uint32_t *out, FStatus *st) {
     __shared__ FusedLds<1024, FUSED_MAX_ROWS, FUSED_MAX_SLOTS, true> L;
+    const FPlan *plan = INL ? &inl.p : d_plan;
     uint64_t *sw = reinterpret_cast<uint64_t *>(st);
     for (uint32_t t = threadIdx.x; t < sizeof(FStatus) / 8; t += 1024) sw[t] = 0;
     if (b0) {
@@ -472,11 +479,15 @@ __global__ __launch_bounds__(1024) void k_fused_levels(const FPlan *plan, uint32
     fused_query<1024, FUSED_MAX_ROWS, FUSED_MAX_SLOTS, true>(plan, j0, M0, R0, R0, buf0, buf1, loc, out, st, L);
 }
 
-void launch_fused(gsi_ctx *c, const FPlan *d_plan, uint32_t j0, uint32_t *M0, uint32_t R0, const uint64_t *b0,
-                  uint64_t nwords, uint32_t *buf0, uint32_t *buf1, uint32_t *loc, uint32_t *out, FStatus *d_status,
-                  double alg_bytes) {
-    launch(c, "k_fused_levels", alg_bytes, k_fused_levels, 1, 1024, d_plan, j0, M0, R0, b0, nwords, buf0, buf1, loc,
-           out, d_status);
+void launch_fused(gsi_ctx *c, const FPlan *d_plan, const FPlanArg &inl, uint32_t j0, uint32_t *M0, uint32_t R0,
+                  const uint64_t *b0, uint64_t nwords, uint32_t *buf0, uint32_t *buf1, uint32_t *loc, uint32_t *out,
+                  FStatus *d_status, double alg_bytes) {
+    if (d_plan)
+        launch(c, "k_fused_levels", alg_bytes, k_fused_levels<false>, 1, 1024, d_plan, inl, j0, M0, R0, b0, nwords,
+               buf0, buf1, loc, out, d_status);
+    else
+        launch(c, "k_fused_levels", alg_bytes, k_fused_levels<true>, 1, 1024, d_plan, inl, j0, M0, R0, b0, nwords,
+               buf0, buf1, loc, out, d_status);
 }
 
 // Persistent batch: each workgroup takes the next query from a shared

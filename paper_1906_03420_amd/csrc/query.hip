@@ -999,7 +999,10 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     // Fused plan (device copy of the levels' linking edges) for the fused
     // kernels, written into the pinned staging buffer and uploaded.
     Scratch fs(c);
-    auto fused_plan = [&](uint32_t cap_rows, uint32_t cap_slots, FPlan **host) -> FPlan * {
+    // With `inl`, a plan of at most FPLAN_ARG_EDGES edges is copied there (it
+    // travels as a kernel argument) and nullptr is returned instead of a
+    // device copy.
+    auto fused_plan = [&](uint32_t cap_rows, uint32_t cap_slots, FPlan **host, FPlanArg *inl = nullptr) -> FPlan * {
         uint32_t n_edges = 0;
         for (uint32_t j = 1; j < k; j++)
             for (uint32_t i = 0; i < j; i++)
@@ -1039,9 +1042,13 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
             st.n_link[j] = ne;
             ei += ne;
         }
+        *host = hp;
+        if (inl && n_edges <= FPLAN_ARG_EDGES) {
+            memcpy(inl, hp, pb);
+            return nullptr;
+        }
         FPlan *dplan = reinterpret_cast<FPlan *>(fs.get<uint8_t>(pb, "fused plan"));
         GSI_HIP(hipMemcpyAsync(dplan, hp, pb, hipMemcpyHostToDevice, c->stream));
-        *host = hp;
         return dplan;
     };
     // algorithmic bytes of a fused launch, from the per-level sizes it met
@@ -1211,11 +1218,13 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     // at, returned in `stop`.
     const uint32_t cap_rows = fcap_rows, cap_slots = fcap_slots;
     FPlan *fhp = nullptr, *fdplan = nullptr;
+    std::unique_ptr<FPlanArg> finl;  // the plan as a kernel argument, when it fits
     uint32_t *fbuf0 = nullptr, *fbuf1 = nullptr, *floc = nullptr;
     FStatus *fdst = nullptr;
     auto run_fused = [&](uint32_t j0, const uint64_t *root_bits, uint32_t &stop) -> bool {
-        if (!fdplan) {
-            fdplan = fused_plan(cap_rows, cap_slots, &fhp);
+        if (!fhp) {
+            finl.reset(new FPlanArg());
+            fdplan = fused_plan(cap_rows, cap_slots, &fhp, finl.get());
             fbuf0 = fs.get<uint32_t>((uint64_t)cap_rows * k, "fused table 0");
             fbuf1 = fs.get<uint32_t>((uint64_t)cap_rows * k, "fused table 1");
             floc = fs.get<uint32_t>(fused_loc_words(k, cap_rows), "fused lookups");
@@ -1223,7 +1232,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         }
         uint32_t *out = count_only ? nullptr : persist<uint32_t>(c, (uint64_t)cap_slots * k, "result rows");
         res->rows = out;
-        launch_fused(c, fdplan, j0, M, (uint32_t)R, root_bits, nwords, fbuf0, fbuf1, floc, out, fdst, 0.0);
+        launch_fused(c, fdplan, *finl, j0, M, (uint32_t)R, root_bits, nwords, fbuf0, fbuf1, floc, out, fdst, 0.0);
         FStatus *hs = reinterpret_cast<FStatus *>(c->mbox_host + MBOX_STATUS);
         sync(c);
         const uint32_t last = hs->done ? (uint32_t)hs->levels : (uint32_t)hs->level;

@@ -120,10 +120,11 @@ void launch_take_rows(gsi_ctx *c, uint32_t nlist, const uint32_t *M0, uint32_t R
 
 // The single-workgroup fused kernel, levels j0.. of the table M0 (R0 rows,
 // j0 columns, column stride R0); with b0 (the bitset of C(u_first), nwords
-// words; j0 = 1 only) it also writes M0 itself.  The plan is d_plan in
+// words; j0 = 1 only) it also writes M0 itself, `b0_runs` being the set bits
+// of each of the BITS_RUNS runs of that bitset.  The plan is d_plan in
 // device memory or, when d_plan is null, `inl`.
 void launch_fused(gsi_ctx *c, const FPlan *d_plan, const FPlanArg &inl, uint32_t j0, uint32_t *M0, uint32_t R0,
-                  const uint64_t *b0,
+                  const uint32_t *b0_runs, const uint64_t *b0,
                   uint64_t nwords, uint32_t *buf0, uint32_t *buf1, uint32_t *loc, uint32_t *out, FStatus *d_status,
                   double alg_bytes);
 

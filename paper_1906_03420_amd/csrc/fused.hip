@@ -426,7 +426,7 @@ __device__ __forceinline__ void fused_query(const FPlan *plan, uint32_t j0, cons
 // plan field would be read with vector loads.
 template <bool INL>
 __global__ __launch_bounds__(1024) void k_fused_levels(const FPlan *d_plan, FPlanArg inl, uint32_t j0, uint32_t *M0,
-                                                      uint32_t R0,
+                                                      uint32_t R0, const uint32_t *b0_runs,
                                                       const uint64_t *b0, uint64_t nwords, uint32_t *buf0,
                                                       uint32_t *buf1, uint32_t *loc, uint32_t *out, FStatus *st) {
     __shared__ FusedLds<1024, FUSED_MAX_ROWS, FUSED_MAX_SLOTS, true> L;
@@ -434,32 +434,24 @@ __global__ __launch_bounds__(1024) void k_fused_levels(const FPlan *d_plan, FPla
     uint64_t *sw = reinterpret_cast<uint64_t *>(st);
     for (uint32_t t = threadIdx.x; t < sizeof(FStatus) / 8; t += 1024) sw[t] = 0;
     if (b0) {
-        // each wave owns a contiguous run of words, read 64 at a time
-        // (coalesced) and four such reads in flight: count, place the runs,
-        // then emit with wave scans
+        // each wave owns a contiguous run of words (the split the filter's
+        // counts used, whose per-run set bits `b0_runs` give the wave its
+        // first output row), read 64 at a time (coalesced) with eight such
+        // reads in flight, and emits with wave scans
         const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
-        const uint64_t per = (nwords + 15) / 16;
+        const uint64_t per = (nwords + BITS_RUNS - 1) / BITS_RUNS;
         const uint64_t ws = per * wv < nwords ? per * wv : nwords;
         const uint64_t we = ws + per < nwords ? ws + per : nwords;
-        uint32_t cnt = 0;
-        uint64_t q = ws + lane;
-        for (; q + 192 < we; q += 256)
-            cnt += (uint32_t)(__popcll(b0[q]) + __popcll(b0[q + 64]) + __popcll(b0[q + 128]) + __popcll(b0[q + 192]));
-        for (; q < we; q += 64) cnt += (uint32_t)__popcll(b0[q]);
-        cnt = wave_sum(cnt);
-        if (lane == 0) L.w[wv] = cnt;
-        __syncthreads();
-        uint32_t at = 0;
-        for (uint32_t v = 0; v < wv; v++) at += L.w[v];
-        for (uint64_t base = ws; base < we; base += 256) {
-            uint64_t m[4];
+        uint32_t at = wave_sum(lane < wv ? b0_runs[lane] : 0u);
+        for (uint64_t base = ws; base < we; base += 512) {
+            uint64_t m[8];
 #pragma unroll
-            for (uint32_t t = 0; t < 4; t++) {
+            for (uint32_t t = 0; t < 8; t++) {
                 const uint64_t qq = base + 64 * t + lane;
                 m[t] = qq < we ? b0[qq] : 0ull;
             }
 #pragma unroll
-            for (uint32_t t = 0; t < 4; t++) {
+            for (uint32_t t = 0; t < 8; t++) {
                 const uint32_t pc = (uint32_t)__popcll(m[t]);
                 const uint32_t inc = wave_inclusive_sum(pc);
                 uint32_t o = at + inc - pc;
@@ -480,14 +472,14 @@ __global__ __launch_bounds__(1024) void k_fused_levels(const FPlan *d_plan, FPla
 }
 
 void launch_fused(gsi_ctx *c, const FPlan *d_plan, const FPlanArg &inl, uint32_t j0, uint32_t *M0, uint32_t R0,
-                  const uint64_t *b0, uint64_t nwords, uint32_t *buf0, uint32_t *buf1, uint32_t *loc, uint32_t *out,
+                  const uint32_t *b0_runs, const uint64_t *b0, uint64_t nwords, uint32_t *buf0, uint32_t *buf1, uint32_t *loc, uint32_t *out,
                   FStatus *d_status, double alg_bytes) {
     if (d_plan)
-        launch(c, "k_fused_levels", alg_bytes, k_fused_levels<false>, 1, 1024, d_plan, inl, j0, M0, R0, b0, nwords,
-               buf0, buf1, loc, out, d_status);
+        launch(c, "k_fused_levels", alg_bytes, k_fused_levels<false>, 1, 1024, d_plan, inl, j0, M0, R0, b0_runs, b0,
+               nwords, buf0, buf1, loc, out, d_status);
     else
-        launch(c, "k_fused_levels", alg_bytes, k_fused_levels<true>, 1, 1024, d_plan, inl, j0, M0, R0, b0, nwords,
-               buf0, buf1, loc, out, d_status);
+        launch(c, "k_fused_levels", alg_bytes, k_fused_levels<true>, 1, 1024, d_plan, inl, j0, M0, R0, b0_runs, b0,
+               nwords, buf0, buf1, loc, out, d_status);
 }
 
 // Persistent batch: each workgroup takes the next query from a shared

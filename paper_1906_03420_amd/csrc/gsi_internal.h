@@ -195,6 +195,9 @@ T *persist(gsi_ctx *c, uint64_t count, const char *what) {
 
 // Reads back `n` uint64 values from device memory (synchronises the stream).
 constexpr uint64_t MAILBOX_WORDS = 512;
+// a candidate bitset is counted in this many consecutive runs of words (one
+// per wave of a 1024-thread workgroup)
+constexpr uint32_t BITS_RUNS = 16;
 // mailbox words of one query: candidate counts (32 x u32), level scalars,
 // the fused workgroup's status
 constexpr uint64_t MBOX_COUNTS = 0, MBOX_SCALARS = 16, MBOX_STATUS = 32;

@@ -159,16 +159,25 @@ __global__ __launch_bounds__(QT) void k_filter(const uint32_t *sig, uint32_t n, 
     filter_tile(sig, n, nwords, fa, fa.label_only ? 0u : fa.word_mask, blockIdx.x, bits);
 }
 
-// counts[r] = set bits of bitset row r (one 1024-thread workgroup per row)
-__global__ __launch_bounds__(1024) void k_bit_counts(const uint64_t *bits, uint64_t nwords, uint32_t *counts) {
+// counts[r] = set bits of bitset row r (one 1024-thread workgroup per row);
+// wave w counts run w of the row's words (BITS_RUNS runs of equal length)
+// and, with `runs`, writes that count to runs[r * BITS_RUNS + w]
+__global__ __launch_bounds__(1024) void k_bit_counts(const uint64_t *bits, uint64_t nwords, uint32_t *counts,
+                                                    uint32_t *runs) {
+    static_assert(BITS_RUNS == 1024 / 64, "one run per wave");
     __shared__ uint32_t s_w[16];
     const uint64_t *row = bits + (uint64_t)blockIdx.x * nwords;
+    const uint32_t wv = threadIdx.x >> 6;
+    const uint64_t per = (nwords + BITS_RUNS - 1) / BITS_RUNS;
+    const uint64_t ws = per * wv < nwords ? per * wv : nwords;
+    const uint64_t we = ws + per < nwords ? ws + per : nwords;
     uint32_t sum = 0;
-    uint64_t q = threadIdx.x;
-    for (; q + 3072 < nwords; q += 4096)
-        sum += (uint32_t)(__popcll(row[q]) + __popcll(row[q + 1024]) + __popcll(row[q + 2048]) + __popcll(row[q + 3072]));
-    for (; q < nwords; q += 1024) sum += (uint32_t)__popcll(row[q]);
+    uint64_t q = ws + lane_id();
+    for (; q + 192 < we; q += 256)
+        sum += (uint32_t)(__popcll(row[q]) + __popcll(row[q + 64]) + __popcll(row[q + 128]) + __popcll(row[q + 192]));
+    for (; q < we; q += 64) sum += (uint32_t)__popcll(row[q]);
     sum = wave_sum(sum);
+    if (lane_id() == 0 && runs) runs[(uint64_t)blockIdx.x * BITS_RUNS + wv] = sum;
     if (lane_id() == 0) s_w[threadIdx.x >> 6] = sum;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -178,14 +187,15 @@ __global__ __launch_bounds__(1024) void k_bit_counts(const uint64_t *bits, uint6
     }
 }
 
-static void launch_filter(gsi_ctx *c, gsi_graph *g, const FilterArgs &fa, uint64_t *bits, uint32_t *counts) {
+static void launch_filter(gsi_ctx *c, gsi_graph *g, const FilterArgs &fa, uint64_t *bits, uint32_t *counts,
+                          uint32_t *runs) {
     const uint64_t nwords = ((uint64_t)g->n + 63) / 64;
     const uint32_t nb = nblocks(g->n);
     const uint32_t need = fa.label_only ? 0u : fa.word_mask;
     double bytes = 4.0 * g->n * (1 + __builtin_popcount(need)) + (double)fa.k * nwords * 8;
     launch(c, "k_filter", bytes, k_filter, nb, QT, (const uint32_t *)g->sig, g->n, nwords, fa, bits);
     launch(c, "k_filter_counts", 8.0 * fa.k * nwords, k_bit_counts, fa.k, 1024, (const uint64_t *)bits, nwords,
-           counts);
+           counts, runs);
 }
 
 // Batched filter: the query vertices of many queries, 32 per pass, all
@@ -245,17 +255,17 @@ void run_filter_many(gsi_graph *g, const std::vector<const HostQuery *> &qs, con
     launch(c, "k_filter", bytes, k_filter_multi, dim3(nb, npass), QT, (const uint32_t *)g->sig, g->n, nwords,
            (const FilterArgs *)dp, bits);
     launch(c, "k_filter_counts", 8.0 * all.size() * nwords, k_bit_counts, (uint32_t)all.size(), 1024,
-           (const uint64_t *)bits, nwords, counts);
+           (const uint64_t *)bits, nwords, counts, (uint32_t *)nullptr);
     sync(c);  // `passes` is read by the copy above
 }
 
 static void filter_impl(gsi_graph *g, const HostQuery &q, bool label_only, uint64_t *bits, uint32_t *counts,
-                        bool homo = false) {
+                        bool homo = false, uint32_t *runs = nullptr) {
     gsi_ctx *c = g->ctx;
     FilterArgs fa;
     query_signatures(q, fa, homo);
     fa.label_only = label_only ? 1u : 0u;
-    launch_filter(c, g, fa, bits, counts);
+    launch_filter(c, g, fa, bits, counts, runs);
 }
 
 void run_filter(gsi_graph *g, const HostQuery &q, uint64_t *bits, uint32_t *counts) {
@@ -917,7 +927,8 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     uint32_t *dcnt = reinterpret_cast<uint32_t *>(c->mbox_dev + MBOX_COUNTS);
     uint64_t *dscal = c->mbox_dev + MBOX_SCALARS;
     auto tf = std::chrono::steady_clock::now();
-    filter_impl(g, q, (flags & GSI_FILTER_LABEL_ONLY) != 0, bits, dcnt, homo);
+    uint32_t *druns = s.get<uint32_t>((uint64_t)k * BITS_RUNS, "candidate run counts");
+    filter_impl(g, q, (flags & GSI_FILTER_LABEL_ONLY) != 0, bits, dcnt, homo, druns);
     std::vector<uint32_t> cand(k);
     {
         uint64_t tmp[GSI_MAX_K / 2 + 1];
@@ -1232,7 +1243,8 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         }
         uint32_t *out = count_only ? nullptr : persist<uint32_t>(c, (uint64_t)cap_slots * k, "result rows");
         res->rows = out;
-        launch_fused(c, fdplan, *finl, j0, M, (uint32_t)R, root_bits, nwords, fbuf0, fbuf1, floc, out, fdst, 0.0);
+        launch_fused(c, fdplan, *finl, j0, M, (uint32_t)R, druns + (uint64_t)order[0] * BITS_RUNS, root_bits, nwords,
+                     fbuf0, fbuf1, floc, out, fdst, 0.0);
         FStatus *hs = reinterpret_cast<FStatus *>(c->mbox_host + MBOX_STATUS);
         sync(c);
         const uint32_t last = hs->done ? (uint32_t)hs->levels : (uint32_t)hs->level;

@@ -200,16 +200,81 @@ static void launch_filter(gsi_ctx *c, gsi_graph *g, const FilterArgs &fa, uint64
 
 // Batched filter: the query vertices of many queries, 32 per pass, all
 // passes in one launch (blockIdx.y = pass; workgroups stride over the
-// tiles).  Passes take query vertices sorted by label, so a pass usually
-// covers few labels and few signature words.
+// tiles).  Passes take query vertices sorted by label, so a pass covers few
+// labels: here a lane whose label matches no query vertex of the pass reads
+// no other word, and most lines of those words are never fetched (unlike
+// the single-query filter, whose query vertices usually span the frequent
+// labels).  Each workgroup keeps per query vertex counts in LDS and writes
+// them to part[(pass * 32 + u) * gridDim.x + workgroup].
 __global__ __launch_bounds__(QT) void k_filter_multi(const uint32_t *sig, uint32_t n, uint64_t nwords,
-                                                    const FilterArgs *__restrict__ passes, uint64_t *bits) {
+                                                    const FilterArgs *__restrict__ passes, uint64_t *bits,
+                                                    uint32_t *part) {
     // the pass's query signatures: a uniform, read-only address, so the
     // compiler reads them with scalar loads (as kernel arguments are)
     const FilterArgs &fa = passes[blockIdx.y];
+    __shared__ uint32_t s_cnt[GSI_MAX_K];
+    if (threadIdx.x < GSI_MAX_K) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t K = fa.k;
+    const uint32_t need = fa.word_mask;
+    const uint32_t lane = lane_id();
     const uint64_t ntiles = ((uint64_t)n + QT - 1) / QT;
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-        filter_tile(sig, n, nwords, fa, fa.word_mask, tile, bits);
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t v = tile * QT + threadIdx.x;
+        const bool valid = v < n;
+        const uint32_t w0 = valid ? sig[v] : NONE32;
+        uint32_t ok = 0;
+        for (uint32_t u = 0; u < K; u++) ok |= (valid && w0 == fa.q[u][0]) ? (1u << u) : 0u;
+        uint32_t wv[GSI_SIG_WORDS];
+#pragma unroll
+        for (int i = 1; i < GSI_SIG_WORDS; i++)
+            wv[i] = (((need >> i) & 1u) && ok) ? sig[(uint64_t)i * n + v] : NONE32;
+        if (ok && need) {
+            for (uint32_t u = 0; u < K; u++) {
+                if (!((ok >> u) & 1u)) continue;
+                bool good = true;
+#pragma unroll
+                for (int i = 1; i < GSI_SIG_WORDS; i++) {
+                    const uint32_t qw = fa.q[u][i];
+                    good = good && ((wv[i] & qw) == qw);
+                }
+                if (!good) ok &= ~(1u << u);
+            }
+        }
+        uint64_t mine = 0;
+        for (uint32_t u = 0; u < K; u++) {
+            const uint64_t m = __ballot((ok >> u) & 1u);
+            if (lane == u) mine = m;
+        }
+        const uint64_t wave_first = tile * QT + (threadIdx.x & ~63u);
+        if (lane < K && wave_first < n) {
+            bits[(uint64_t)fa.dst[lane] * nwords + (wave_first >> 6)] = mine;
+            if (mine) atomicAdd(&s_cnt[lane], (uint32_t)__popcll(mine));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < GSI_MAX_K)
+        part[((uint64_t)blockIdx.y * GSI_MAX_K + threadIdx.x) * gridDim.x + blockIdx.x] = s_cnt[threadIdx.x];
+}
+
+// counts of every pass: workgroup (u, pass) sums u's partial counts
+__global__ __launch_bounds__(QT) void k_filter_counts_multi(const uint32_t *part, uint32_t nb,
+                                                           const FilterArgs *passes, uint32_t *counts) {
+    __shared__ uint32_t s_w[QT / 64];
+    const uint32_t u = blockIdx.x, pass = blockIdx.y;
+    const FilterArgs &fa = passes[pass];
+    if (u >= fa.k) return;
+    const uint32_t *row = part + ((uint64_t)pass * GSI_MAX_K + u) * nb;
+    uint32_t sum = 0;
+    for (uint32_t b = threadIdx.x; b < nb; b += QT) sum += row[b];
+    sum = wave_sum(sum);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int q = 0; q < QT / 64; q++) t += s_w[q];
+        counts[fa.dst[u]] = t;
+    }
 }
 
 void run_filter_many(gsi_graph *g, const std::vector<const HostQuery *> &qs, const std::vector<uint32_t> &qbase,
@@ -250,12 +315,13 @@ void run_filter_many(gsi_graph *g, const std::vector<const HostQuery *> &qs, con
     const uint32_t nb = std::min<uint32_t>(nblocks(g->n), std::max<uint32_t>(32, 8192 / npass));
     FilterArgs *dp = reinterpret_cast<FilterArgs *>(s.get<uint32_t>((uint64_t)npass * sizeof(FilterArgs) / 4,
                                                                     "filter passes"));
+    uint32_t *part = s.get<uint32_t>((uint64_t)npass * GSI_MAX_K * nb, "filter partial counts");
     GSI_HIP(hipMemcpyAsync(dp, passes.data(), sizeof(FilterArgs) * npass, hipMemcpyHostToDevice, c->stream));
     const double bytes = 4.0 * g->n * words + (double)all.size() * nwords * 8;
     launch(c, "k_filter", bytes, k_filter_multi, dim3(nb, npass), QT, (const uint32_t *)g->sig, g->n, nwords,
-           (const FilterArgs *)dp, bits);
-    launch(c, "k_filter_counts", 8.0 * all.size() * nwords, k_bit_counts, (uint32_t)all.size(), 1024,
-           (const uint64_t *)bits, nwords, counts, (uint32_t *)nullptr);
+           (const FilterArgs *)dp, bits, part);
+    launch(c, "k_filter_counts", 4.0 * nb * all.size(), k_filter_counts_multi, dim3(GSI_MAX_K, npass), QT,
+           (const uint32_t *)part, nb, (const FilterArgs *)dp, counts);
     sync(c);  // `passes` is read by the copy above
 }
 

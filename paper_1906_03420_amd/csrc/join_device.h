@@ -35,14 +35,28 @@ __device__ __forceinline__ uint2 pcsr_find(const uint32_t *gl, uint32_t G, uint3
     return make_uint2(0, 0);
 }
 
-__device__ __forceinline__ bool in_sorted(const uint32_t *list, uint32_t len, uint32_t x) {
-    uint32_t lo = 0, hi = len;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (list[mid] < x) lo = mid + 1;
-        else hi = mid;
+// x in the ascending list[0, len)?  An 8-ary search: each step reads 7
+// probes at once (independent loads) and keeps the eighth of the range that
+// can hold x, then the last <= 8 elements are read at once, so a list of L
+// elements costs about log8(L) + 1 dependent round trips to memory, not
+// log2(L).
+__host__ __device__ __forceinline__ bool in_sorted(const uint32_t *list, uint32_t len, uint32_t x) {
+    uint32_t lo = 0, n = len;  // x, if present, is in [lo, lo + n)
+    while (n > 8) {
+        const uint32_t s = (n + 7) / 8;  // 8 segments of s (the last may be shorter)
+        uint32_t v[7];
+#pragma unroll
+        for (uint32_t t = 1; t < 8; t++) v[t - 1] = s * t < n ? list[lo + s * t] : 0xFFFFFFFFu;
+        uint32_t c = 0;  // segments whose first element is <= x, after the first
+#pragma unroll
+        for (uint32_t t = 1; t < 8; t++) c += (s * t < n && v[t - 1] <= x) ? 1u : 0u;
+        lo += s * c;
+        n = (n - s * c) < s ? (n - s * c) : s;
     }
-    return lo < len && list[lo] == x;
+    bool hit = false;
+#pragma unroll
+    for (uint32_t t = 0; t < 8; t++) hit |= t < n && list[lo + t] == x;
+    return hit;
 }
 
 // FNV-1a-64 over the four little-endian bytes of one 32-bit word

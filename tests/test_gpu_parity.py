@@ -143,6 +143,33 @@ def test_closed_forms(ctx):
     dg.free()
 
 
+def test_dense_queries_past_the_inline_plan(ctx):
+    """K_12 has 66 linking edges, more than a plan passed as a kernel argument
+    holds (64): the fused workgroup then reads its plan from device memory.
+    K_11 (55 edges) takes the argument route.  Both against the oracle."""
+    r = np.random.default_rng(77)
+    n_cl, n_rest = 14, 200
+    vl = list(range(12)) + [0, 1] + [int(x) for x in r.integers(0, 12, n_rest)]
+    edges = [(a, b) for a in range(n_cl) for b in range(a + 1, n_cl)]
+    seen = set(edges)
+    while len(edges) < 91 + 600:  # the clique's 91 edges and 600 random ones
+        a, b = sorted(int(x) for x in r.integers(0, n_cl + n_rest, 2))
+        if a != b and (a, b) not in seen:
+            seen.add((a, b))
+            edges.append((a, b))
+    g = w.make_graph(n_cl + n_rest, vl, edges, [0] * len(edges))
+    dg = ctx.load(g)
+    og = oracle.OracleGraph(g)
+    import paper_1906_03420_amd as gsi
+    for k in (11, 12):
+        e = [(a, b) for a in range(k) for b in range(a + 1, k)]
+        q = w.make_query(list(range(k)), e, [0] * len(e))
+        for flags in (0, gsi.GSI_NO_FUSED, gsi.GSI_COUNT_ONLY):
+            st = check_query(dg, g, q, og, flags=flags)
+            assert st["k"] == k
+    dg.free()
+
+
 def test_edge_cases(ctx):
     import paper_1906_03420_amd as gsi
     g = w.config_graph("er1k")

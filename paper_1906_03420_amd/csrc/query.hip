@@ -713,17 +713,35 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
             uint32_t st0;
             find_row(a, tr, s_F, s_st, p, &i, &Fi, &st0);
             const uint32_t x = ci0[st0 + (uint32_t)(p - Fi)];
+            // the row's values are loaded four at a time (independent
+            // loads), not one dependent round trip per column
             if (!a.final_level) {
-                for (uint32_t c = 0; c < a.j; c++) a.Mn[(uint64_t)c * a.S + pos] = a.M[(uint64_t)c * a.R + i];
+                for (uint32_t c = 0; c < a.j; c += 4) {
+                    uint32_t m[4];
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; q++) m[q] = c + q < a.j ? a.M[(uint64_t)(c + q) * a.R + i] : 0u;
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; q++)
+                        if (c + q < a.j) a.Mn[(uint64_t)(c + q) * a.S + pos] = m[q];
+                }
                 a.Mn[(uint64_t)a.j * a.S + pos] = x;
             } else {
                 uint64_t f = 14695981039346656037ull;
-                for (uint32_t u = 0; u < a.k; u++) {
-                    uint32_t c = a.qcol[u];
-                    uint32_t val = c < a.j ? a.M[(uint64_t)c * a.R + i] : x;
-                    if (stage) s_rows[local * a.k + u] = val;
-                    else if (!a.count_only) a.out[pos * a.k + u] = val;
-                    f = fnv_word(f, val);
+                for (uint32_t u0 = 0; u0 < a.k; u0 += 4) {
+                    uint32_t val[4];
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; q++) {
+                        const uint32_t c = u0 + q < a.k ? a.qcol[u0 + q] : a.j;
+                        val[q] = c < a.j ? a.M[(uint64_t)c * a.R + i] : x;
+                    }
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; q++) {
+                        const uint32_t u = u0 + q;
+                        if (u >= a.k) break;
+                        if (stage) s_rows[local * a.k + u] = val[q];
+                        else if (!a.count_only) a.out[pos * a.k + u] = val[q];
+                        f = fnv_word(f, val[q]);
+                    }
                 }
                 const uint64_t h = mix64(f);
                 hs += h;

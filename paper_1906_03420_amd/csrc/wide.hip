@@ -195,7 +195,14 @@ __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, uint32_t nq, const W
         const uint32_t st0 = (t.one && t.staged) ? s_st[lr] : loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + i];
         const uint32_t x = ci_all[st0 + (uint32_t)(p - Fr)];
         keep = (Q.Cu[x >> 6] >> (x & 63)) & 1ull;
-        for (uint32_t c = 0; keep && c < Q.j; c++) keep = Q.M[(uint64_t)c * Q.R + i] != x;
+        // x not in m_i: the row's values four at a time (independent loads)
+        for (uint32_t c = 0; keep && c < Q.j; c += 4) {
+            uint32_t m[4];
+#pragma unroll
+            for (uint32_t q = 0; q < 4; q++) m[q] = c + q < Q.j ? Q.M[(uint64_t)(c + q) * Q.R + i] : ~x;
+#pragma unroll
+            for (uint32_t q = 0; q < 4; q++) keep = keep && m[q] != x;
+        }
         const uint32_t be = (keep && Q.ne > 1) ? loc[Q.locbase + (uint64_t)(2 * Q.ne + 1) * Q.R + i] : Q.e0;
         for (uint32_t e = 0; keep && e < Q.ne; e++) {
             if (e == be) continue;
@@ -281,17 +288,35 @@ __global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, uint32_t nq, const u
             const uint32_t st0 =
                 (t.one && t.staged) ? s_st[lr] : loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + i];
             const uint32_t x = ci_all[st0 + (uint32_t)(p - Fr)];
+            // the row's values are loaded four at a time (independent
+            // loads), not one dependent round trip per column
             if (!Q.final_level) {
-                for (uint32_t c = 0; c < Q.j; c++) Q.Mn[(uint64_t)c * Q.S + pos] = Q.M[(uint64_t)c * Q.R + i];
+                for (uint32_t c = 0; c < Q.j; c += 4) {
+                    uint32_t m[4];
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; q++) m[q] = c + q < Q.j ? Q.M[(uint64_t)(c + q) * Q.R + i] : 0u;
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; q++)
+                        if (c + q < Q.j) Q.Mn[(uint64_t)(c + q) * Q.S + pos] = m[q];
+                }
                 Q.Mn[(uint64_t)Q.j * Q.S + pos] = x;
             } else {
                 uint64_t f = 14695981039346656037ull;
-                for (uint32_t u = 0; u < Q.k; u++) {
-                    const uint32_t c = Q.qcol[u];
-                    const uint32_t val = c < Q.j ? Q.M[(uint64_t)c * Q.R + i] : x;
-                    if (stage) s_rows[local * Q.k + u] = val;
-                    else if (Q.out) Q.out[pos * Q.k + u] = val;
-                    f = fnv_word(f, val);
+                for (uint32_t u0 = 0; u0 < Q.k; u0 += 4) {
+                    uint32_t val[4];
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; q++) {
+                        const uint32_t c = u0 + q < Q.k ? Q.qcol[u0 + q] : Q.j;
+                        val[q] = c < Q.j ? Q.M[(uint64_t)c * Q.R + i] : x;
+                    }
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; q++) {
+                        const uint32_t u = u0 + q;
+                        if (u >= Q.k) break;
+                        if (stage) s_rows[local * Q.k + u] = val[q];
+                        else if (Q.out) Q.out[pos * Q.k + u] = val[q];
+                        f = fnv_word(f, val[q]);
+                    }
                 }
                 hv[gpos] = mix64(f);
             }

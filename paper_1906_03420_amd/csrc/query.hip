@@ -1423,11 +1423,12 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         const uint64_t nbr = nblocks(R);
         const bool prof = (c->flags & GSI_CTX_PROFILE) != 0;
         a.part = prof ? ls.get<uint64_t>(2 * nbr, "locate partials") : nullptr;
-        // row values, the located lists and offsets written, and one 128 B
-        // group per lookup, counted at most once per group of the label
-        // (rows repeat vertices, and a repeated group is a cache hit)
-        double lbytes = (double)R * (4.0 * ne + 4.0 * (2.0 * ne + 2.0) + 4.0 + 8.0);
-        for (uint32_t i = 0; i < ne; i++) lbytes += 128.0 * (double)std::min<uint64_t>(R, a.e[i].G);
+        // the streamed bytes: row values read, located lists, bound and F
+        // written.  The 128 B PCSR groups are not counted: rows repeat few
+        // distinct vertices, so all but the first read of a group hit L2
+        // (counting every read, or every group of the label, gives rates
+        // above what HBM can deliver).
+        const double lbytes = (double)R * (4.0 * ne + 4.0 * (2.0 * ne + 2.0) + 4.0 + 8.0);
         launch(c, "k_locate", lbytes, k_locate, (uint32_t)nbr, QT, a);
         if (prof) reduce_pairs(c, a.part, nbr, dscal + 2);
         exclusive_scan(c, a.bound, R, F, ls, dscal + 3);

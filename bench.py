@@ -83,6 +83,8 @@ WORKLOAD_TEXT = {
             "100 random-walk queries of 6-12 vertices; single-query path",
     "er1k": "ER graph 1,000 vertices / 5,000 edges, 4 vertex labels, 2 edge labels; 8 random-walk queries of 4 "
             "vertices; single-query path",
+    "rmat23": "R-MAT scale 23, 8,388,608 vertices / 100,000,000 edges, 100 vertex + 20 edge labels Zipf(1.1); "
+              "the 12-vertex walk and dense queries with stored oracle values; single-query path",
 }
 
 
@@ -102,22 +104,26 @@ def load_golden(name):
 
 
 def make_workload(name):
+    """The workload's graph and queries; with stored oracle values, exactly
+    the queries they cover (index and accepted attempt of each)."""
     import workloads as w
     g = w.config_graph(name)
     mk = w.QueryMaker(g)
     gold = load_golden(name)
     qs = []
-    nq = w.CONFIGS[name]["nq"]
-    for i in range(nq):
-        attempt = gold["queries"][i]["attempt"] if gold else 0
-        qs.append(w.config_query(g, name, i, attempt=attempt, maker=mk))
+    if gold:
+        for x in gold["queries"]:
+            qs.append(w.config_query(g, name, x["index"], attempt=x["attempt"], maker=mk))
+    else:
+        for i in range(w.CONFIGS[name]["nq"]):
+            qs.append(w.config_query(g, name, i, maker=mk))
     mk.close()
     return g, qs, gold
 
 
 def cpu_baseline(g, qs, threads, min_s=10.0):
     """The oracle on the same graph and queries: adjacency build once, then
-    whole passes over the 100 queries until at least min_s seconds."""
+    whole passes over the queries until at least min_s seconds."""
     import oracle
     t0 = time.perf_counter()
     og = oracle.OracleGraph(g)
@@ -131,8 +137,8 @@ def cpu_baseline(g, qs, threads, min_s=10.0):
     dt = time.perf_counter() - t1
     og.close()
     return dict(value=total / dt, unit="embeddings/s", cores=threads, kind="oracle",
-                sample="%d whole passes over the 100 queries (count + digest of every embedding), %.1f s; "
-                       "adjacency build %.2f s not counted" % (passes, dt, tb))
+                sample="%d whole passes over the %d queries (count + digest of every embedding), %.1f s; "
+                       "adjacency build %.2f s not counted" % (passes, len(qs), dt, tb))
 
 
 def batched_section(args, vl_t, s_t, d_t, l_t, g, arena):

@@ -701,18 +701,34 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
     const bool stage = a.final_level && !a.count_only && a.k <= LINK_STAGE_K && !a.abl_no_stage;
     const uint32_t *ci0 = a.ci_all;
     uint64_t hs = 0, hx = 0;
+    // first, for all SPT slots of the thread: keep bit, position, row and x
+    // (the rows' searches and the x gathers of the rounds overlap)
+    bool kr[SPT];
+    uint32_t lr[SPT], xr[SPT];
+    uint64_t pr[SPT], ir[SPT];
+#pragma unroll
     for (uint32_t r = 0; r < SPT; r++) {
         const uint32_t wi = r * (QT / 64) + w;
         const uint64_t word = words[wi];
-        const bool keep = (word >> lane) & 1ull;
-        const uint32_t local = s_pre[wi] - s_pre[r * (QT / 64)] + rank_below(word);  // rank within the round
-        const uint64_t pos = tbase + s_pre[wi] + rank_below(word);
-        if (keep && pos < a.S) {
+        lr[r] = s_pre[wi] - s_pre[r * (QT / 64)] + rank_below(word);  // rank within the round
+        pr[r] = tbase + s_pre[wi] + rank_below(word);
+        kr[r] = ((word >> lane) & 1ull) && pr[r] < a.S;
+        ir[r] = 0;
+        xr[r] = 0;
+        if (kr[r]) {
             const uint64_t p = p0 + r * QT + threadIdx.x;
-            uint64_t i, Fi;
+            uint64_t Fi;
             uint32_t st0;
-            find_row(a, tr, s_F, s_st, p, &i, &Fi, &st0);
-            const uint32_t x = ci0[st0 + (uint32_t)(p - Fi)];
+            find_row(a, tr, s_F, s_st, p, &ir[r], &Fi, &st0);
+            xr[r] = ci0[st0 + (uint32_t)(p - Fi)];
+        }
+    }
+    for (uint32_t r = 0; r < SPT; r++) {
+        const uint32_t local = lr[r];
+        const uint64_t pos = pr[r];
+        if (kr[r]) {
+            const uint64_t i = ir[r];
+            const uint32_t x = xr[r];
             // the row's values are loaded four at a time (independent
             // loads), not one dependent round trip per column
             if (!a.final_level) {

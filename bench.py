@@ -376,6 +376,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ba1m", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--queries", type=int, default=0, help="use only the first N queries of the workload (0: all)")
     ap.add_argument("--arena-gb", type=float, default=48.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential comparison")
@@ -395,6 +396,10 @@ def main():
     import paper_1906_03420_amd as gsi
 
     g, qs, gold = make_workload(args.workload)
+    if args.queries and args.queries < len(qs):
+        qs = qs[:args.queries]
+        if gold:
+            gold = dict(gold, queries=gold["queries"][:args.queries])
     dev = torch.device("cuda:0")
     as_t = lambda a: torch.from_numpy(a.view(np.int32)).to(dev)
     vl_t, s_t, d_t, l_t = as_t(g.vlabel), as_t(g.src), as_t(g.dst), as_t(g.elabel)

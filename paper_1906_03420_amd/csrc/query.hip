@@ -650,6 +650,7 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
     __shared__ uint32_t s_rows[QT * LINK_STAGE_K];
     __shared__ uint32_t s_pre[TS / 64 + 1];  // kept slots before each bitmap word of the tile
     __shared__ uint64_t s_w[TS / 64];        // the tile's keep bits (two-step ablation)
+    __shared__ uint16_t s_list[TS];          // the tile's kept slots, compacted
     const uint64_t tile = blockIdx.x;
     if (a.tile_off[tile + 1] == a.tile_off[tile]) {  // whole tile empty (uniform)
         if (a.final_level && threadIdx.x == 0) {
@@ -701,62 +702,58 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
     const bool stage = a.final_level && !a.count_only && a.k <= LINK_STAGE_K && !a.abl_no_stage;
     const uint32_t *ci0 = a.ci_all;
     uint64_t hs = 0, hx = 0;
-    // first, for all SPT slots of the thread: keep bit, position, row and x
-    // (the rows' searches and the x gathers of the rounds overlap)
-    bool kr[SPT];
-    uint32_t lr[SPT], xr[SPT];
-    uint64_t pr[SPT], ir[SPT];
+    // The tile's kept slots, compacted in slot order into s_list, so that
+    // the waves that gather, write and hash are dense: in a sparse last level
+    // nearly every wave holds some kept slot, and would run the whole
+    // survivor path for a few lanes.  Survivor q of the tile (its q-th kept
+    // slot) is row tbase + q of M'.
 #pragma unroll
     for (uint32_t r = 0; r < SPT; r++) {
         const uint32_t wi = r * (QT / 64) + w;
         const uint64_t word = words[wi];
-        lr[r] = s_pre[wi] - s_pre[r * (QT / 64)] + rank_below(word);  // rank within the round
-        pr[r] = tbase + s_pre[wi] + rank_below(word);
-        kr[r] = ((word >> lane) & 1ull) && pr[r] < a.S;
-        ir[r] = 0;
-        xr[r] = 0;
-        if (kr[r]) {
-            const uint64_t p = p0 + r * QT + threadIdx.x;
-            uint64_t Fi;
-            uint32_t st0;
-            find_row(a, tr, s_F, s_st, p, &ir[r], &Fi, &st0);
-            xr[r] = ci0[st0 + (uint32_t)(p - Fi)];
-        }
+        if ((word >> lane) & 1ull) s_list[s_pre[wi] + rank_below(word)] = (uint16_t)(r * QT + threadIdx.x);
     }
-    for (uint32_t r = 0; r < SPT; r++) {
-        const uint32_t local = lr[r];
-        const uint64_t pos = pr[r];
-        if (kr[r]) {
-            const uint64_t i = ir[r];
-            const uint32_t x = xr[r];
+    __syncthreads();
+    // the same count in every lane (the loop holds barriers)
+    const uint32_t n = __builtin_amdgcn_readfirstlane(s_pre[TS / 64]);
+    for (uint32_t q0 = 0; q0 < n; q0 += QT) {
+        const uint32_t q = q0 + threadIdx.x;
+        const uint64_t pos = tbase + q;
+        if (q < n && pos < a.S) {
+            const uint64_t p = p0 + s_list[q];
+            uint64_t i, Fi;
+            uint32_t st0;
+            find_row(a, tr, s_F, s_st, p, &i, &Fi, &st0);
+            const uint32_t x = ci0[st0 + (uint32_t)(p - Fi)];
             // the row's values are loaded four at a time (independent
             // loads), not one dependent round trip per column
             if (!a.final_level) {
                 for (uint32_t c = 0; c < a.j; c += 4) {
                     uint32_t m[4];
 #pragma unroll
-                    for (uint32_t q = 0; q < 4; q++) m[q] = c + q < a.j ? a.M[(uint64_t)(c + q) * a.R + i] : 0u;
+                    for (uint32_t k4 = 0; k4 < 4; k4++) m[k4] = c + k4 < a.j ? a.M[(uint64_t)(c + k4) * a.R + i] : 0u;
 #pragma unroll
-                    for (uint32_t q = 0; q < 4; q++)
-                        if (c + q < a.j) a.Mn[(uint64_t)(c + q) * a.S + pos] = m[q];
+                    for (uint32_t k4 = 0; k4 < 4; k4++)
+                        if (c + k4 < a.j) a.Mn[(uint64_t)(c + k4) * a.S + pos] = m[k4];
                 }
                 a.Mn[(uint64_t)a.j * a.S + pos] = x;
             } else {
+                const uint32_t local = threadIdx.x;  // row within this round's block
                 uint64_t f = 14695981039346656037ull;
                 for (uint32_t u0 = 0; u0 < a.k; u0 += 4) {
                     uint32_t val[4];
 #pragma unroll
-                    for (uint32_t q = 0; q < 4; q++) {
-                        const uint32_t c = u0 + q < a.k ? a.qcol[u0 + q] : a.j;
-                        val[q] = c < a.j ? a.M[(uint64_t)c * a.R + i] : x;
+                    for (uint32_t k4 = 0; k4 < 4; k4++) {
+                        const uint32_t c = u0 + k4 < a.k ? a.qcol[u0 + k4] : a.j;
+                        val[k4] = c < a.j ? a.M[(uint64_t)c * a.R + i] : x;
                     }
 #pragma unroll
-                    for (uint32_t q = 0; q < 4; q++) {
-                        const uint32_t u = u0 + q;
+                    for (uint32_t k4 = 0; k4 < 4; k4++) {
+                        const uint32_t u = u0 + k4;
                         if (u >= a.k) break;
-                        if (stage) s_rows[local * a.k + u] = val[q];
-                        else if (!a.count_only) a.out[pos * a.k + u] = val[q];
-                        f = fnv_word(f, val[q]);
+                        if (stage) s_rows[local * a.k + u] = val[k4];
+                        else if (!a.count_only) a.out[pos * a.k + u] = val[k4];
+                        f = fnv_word(f, val[k4]);
                     }
                 }
                 const uint64_t h = mix64(f);
@@ -767,8 +764,8 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
         if (stage) {
             // the round's rows are one contiguous block of the output
             __syncthreads();
-            const uint64_t first = tbase + s_pre[r * (QT / 64)];
-            uint64_t end = tbase + s_pre[(r + 1) * (QT / 64)];
+            const uint64_t first = tbase + q0;
+            uint64_t end = tbase + (q0 + QT < n ? q0 + QT : n);
             if (end > a.S) end = a.S;
             const uint32_t nw = first < end ? (uint32_t)(end - first) * a.k : 0u;
             uint32_t *dst = a.out + first * a.k;

@@ -58,6 +58,45 @@ __device__ __forceinline__ void lds_rows(const uint32_t *F, uint32_t R, const ui
     }
 }
 
+// Position of the r-th set bit (r from 0) of m, which has more than r set bits.
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t r) {
+    uint32_t pos = 0;
+#pragma unroll
+    for (uint32_t sh = 32; sh; sh >>= 1) {
+        const uint32_t c = (uint32_t)__popcll(m & ((1ull << sh) - 1));
+        if (r >= c) {
+            r -= c;
+            m >>= sh;
+            pos += sh;
+        }
+    }
+    return pos;
+}
+
+// For U survivors q[r] < S: the bitmap word holding each (the largest w <
+// nw with pre[w] <= q, pre being the exclusive prefix of the words' set
+// bits, in LDS) and the survivor's rank within it.  Branch-free, as lds_rows.
+template <uint32_t U>
+__device__ __forceinline__ void lds_words(const uint32_t *pre, uint32_t nw, const uint32_t *q, uint32_t *wd,
+                                          uint32_t *rk) {
+#pragma unroll
+    for (uint32_t r = 0; r < U; r++) {
+        wd[r] = 0;
+        rk[r] = q[r];
+    }
+    for (uint32_t b = nw > 1 ? 1u << (31 - __builtin_clz(nw - 1)) : 0u; b; b >>= 1) {
+#pragma unroll
+        for (uint32_t r = 0; r < U; r++) {
+            const uint32_t m = wd[r] + b;
+            const uint32_t f = pre[m < nw ? m : nw - 1];
+            if (m < nw && f <= q[r]) {
+                wd[r] = m;
+                rk[r] = q[r] - f;
+            }
+        }
+    }
+}
+
 // bitmap words a wave takes per round of the fused join and link
 constexpr uint32_t FU = 2;
 
@@ -312,23 +351,25 @@ __device__ __forceinline__ void fused_query(const FPlan *plan, uint32_t j0, cons
         }
 
         // link: (m_i, x) at its position; the last level writes rows in
-        // query-vertex order and hashes them.  FU words per wave and round,
-        // as in the join.
+        // query-vertex order and hashes them.  Threads take survivors, not
+        // slots (survivor q is at position q; its slot is found from the
+        // keep bits' prefix sums), so the waves are dense however sparse the
+        // keep bits are; FU survivors per thread and round.
         const bool n_lds = !final_level && (uint64_t)S * (j + 1) <= MT;
         // (selects, not an indexed pointer array, which would live in scratch)
         uint32_t *Mn = n_lds ? (next ? L.mt[1] : L.mt[0]) : (next ? buf1 : buf0);
         uint64_t hs = 0, hx = 0;
-        for (uint32_t base = 0; base < nw; base += FU * (FT / 64)) {
-            uint32_t pr[FU], ir[FU], fr[FU], pos[FU], xr[FU];
+        for (uint32_t base = 0; base < S; base += FU * FT) {
+            uint32_t pr[FU], ir[FU], fr[FU], pos[FU], xr[FU], wd[FU], rk[FU];
             bool kp[FU];
 #pragma unroll
             for (uint32_t r = 0; r < FU; r++) {
-                const uint32_t word = base + r * (FT / 64) + w;
-                const uint64_t bits = word < nw ? s_bits[word] : 0ull;
-                pr[r] = word * 64 + lane;
-                kp[r] = (bits >> lane) & 1ull;
-                pos[r] = kp[r] ? s_wpre[word] + rank_below(bits) : 0u;
+                pos[r] = base + r * FT + tid;
+                kp[r] = pos[r] < S;
             }
+            lds_words<FU>(s_wpre, nw, pos, wd, rk);
+#pragma unroll
+            for (uint32_t r = 0; r < FU; r++) pr[r] = kp[r] ? wd[r] * 64 + nth_set_bit(s_bits[wd[r]], rk[r]) : 0u;
             lds_rows<FU>(s_F, R, pr, ir, fr);
 #pragma unroll
             for (uint32_t r = 0; r < FU; r++) {

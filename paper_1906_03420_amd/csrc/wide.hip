@@ -264,20 +264,26 @@ __global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, uint32_t nq, const u
     __shared__ WQ s_Q;
     __shared__ uint32_t s_q[2];
     __shared__ uint32_t s_rows[WT * WLINK_STAGE_K];
+    __shared__ uint16_t s_list[WT];  // the tile's kept slots, compacted
     const uint64_t tile = blockIdx.x;
     if (tile_off[tile + 1] == tile_off[tile]) return;  // no survivor in the tile (uniform)
     const uint64_t p0 = tile * WT;
-    const WTile t = stage_wtile(qs, nq, F, tile_row, loc, tile, s_F, s_st, &s_Q, s_q);
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
     const uint64_t *words = bitmap + tile * (WT / 64);
-    const uint64_t word = words[w];
-    uint32_t before = 0;
-    for (uint32_t q = 0; q < w; q++) before += (uint32_t)__popcll(words[q]);
-    const uint32_t local = before + rank_below(word);  // rank within the tile
+    {
+        // the kept slots in slot order, so that the waves below are dense
+        const uint64_t word = words[w];
+        uint32_t before = 0;
+        for (uint32_t q = 0; q < w; q++) before += (uint32_t)__popcll(words[q]);
+        if ((word >> lane) & 1ull) s_list[before + rank_below(word)] = (uint16_t)threadIdx.x;
+    }
+    const WTile t = stage_wtile(qs, nq, F, tile_row, loc, tile, s_F, s_st, &s_Q, s_q);  // (its barrier publishes s_list)
+    const uint32_t n = (uint32_t)(tile_off[tile + 1] - tile_off[tile]);
+    const uint32_t local = threadIdx.x;  // survivor `local` of the tile
     const uint64_t gpos = tile_off[tile] + local;
     const bool stage = t.one && s_Q.final_level && s_Q.out && s_Q.k <= WLINK_STAGE_K;
-    if ((word >> lane) & 1ull) {
-        const uint64_t p = p0 + threadIdx.x;
+    if (local < n) {
+        const uint64_t p = p0 + s_list[local];
         uint64_t r, Fr;
         uint32_t lr, qi;
         wfind(qs, F, t, s_F, s_q, p, &r, &Fr, &lr, &qi);

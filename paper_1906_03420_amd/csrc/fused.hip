@@ -527,7 +527,9 @@ void launch_fused(gsi_ctx *c, const FPlan *d_plan, const FPlanArg &inl, uint32_t
 // counter until none is left (every workgroup leaves once the counter passes
 // the item count), and runs all its levels in its own scratch slot.
 template <uint32_t FT, uint32_t CR, uint32_t CS>
-__global__ __launch_bounds__(FT) void k_fused_batch(const uint8_t *plans, const FBatchItem *items, uint32_t nitems,
+// (the 256-thread tier is held to four waves per SIMD: left alone the
+// compiler takes a few more registers and one workgroup per CU fewer fits)
+__global__ __launch_bounds__(FT, FT == 256 ? 4 : 1) void k_fused_batch(const uint8_t *plans, const FBatchItem *items, uint32_t nitems,
                                                    const uint32_t *M0all, uint32_t *scratch, uint64_t slot_words,
                                                    uint32_t kmax, uint32_t *outall, FStatus *sts,
                                                    uint32_t *counter) {

@@ -567,13 +567,19 @@ __device__ __forceinline__ bool slot_keep(const LevelArgs &a, uint64_t i, uint32
 template <uint32_t SPT>
 __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
     constexpr uint32_t TS = SPT * QT;
-    __shared__ uint32_t s_cnt[QT / 64];
     __shared__ uint64_t s_F[TS];
     __shared__ uint32_t s_st[TS];
+    __shared__ uint32_t s_x[TS];      // elements that passed the C(u) test, compacted
+    __shared__ uint16_t s_slot[TS];   // and their slots in the tile
+    __shared__ uint64_t s_keep[TS / 64];
+    __shared__ uint32_t s_n;
+    if (threadIdx.x == 0) s_n = 0;
+    if (threadIdx.x < TS / 64) s_keep[threadIdx.x] = 0;
+    __syncthreads();
     const uint64_t p0 = (uint64_t)blockIdx.x * TS;
     const TileRows tr = stage_rows<SPT>(a, blockIdx.x, s_F, s_st);
     const uint32_t *ci0 = a.ci_all;
-    uint64_t ri[SPT];
+    const uint32_t lane = lane_id();
     uint32_t xs[SPT];
     bool kp[SPT];
     // x = N(v'_i, l0)[p - F[i]] for the thread's four slots
@@ -581,27 +587,42 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
     for (uint32_t r = 0; r < SPT; r++) {
         const uint64_t p = p0 + r * QT + threadIdx.x;
         kp[r] = p < a.gba;
-        ri[r] = 0;
         xs[r] = 0;
         if (kp[r]) {
-            uint64_t Fi;
+            uint64_t i, Fi;
             uint32_t st0;
-            find_row(a, tr, s_F, s_st, p, &ri[r], &Fi, &st0);
+            find_row(a, tr, s_F, s_st, p, &i, &Fi, &st0);
             xs[r] = ci0[st0 + (uint32_t)(p - Fi)];
         }
     }
-    // x in C(u)
-#pragma unroll
-    for (uint32_t r = 0; r < SPT; r++)
-        if (kp[r]) kp[r] = (a.Cu[xs[r] >> 6] >> (xs[r] & 63)) & 1ull;
-    // x not in m_i (the row's values are loaded four at a time, not one
-    // dependent load per column), x in every other linking list
+    // x in C(u); the slots that pass are compacted (in no particular order)
+    // so that the remaining tests, the costly ones, run in dense waves
 #pragma unroll
     for (uint32_t r = 0; r < SPT; r++) {
-        bool keep = kp[r];
-        const uint64_t i = ri[r];
-        const uint32_t x = xs[r];
-        if (keep && !a.homo) {
+        if (kp[r]) kp[r] = (a.Cu[xs[r] >> 6] >> (xs[r] & 63)) & 1ull;
+        const uint64_t mask = __ballot(kp[r]);
+        if (mask) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&s_n, (uint32_t)__popcll(mask));
+            base = __shfl(base, 0, 64);
+            if (kp[r]) {
+                const uint32_t idx = base + rank_below(mask);
+                s_slot[idx] = (uint16_t)(r * QT + threadIdx.x);
+                s_x[idx] = xs[r];
+            }
+        }
+    }
+    __syncthreads();
+    // x not in m_i (the row's values are loaded four at a time, not one
+    // dependent load per column), x in every other linking list
+    const uint32_t n = __builtin_amdgcn_readfirstlane(s_n);
+    for (uint32_t e = threadIdx.x; e < n; e += QT) {
+        const uint32_t slot = s_slot[e], x = s_x[e];
+        uint64_t i, Fi;
+        uint32_t st0;
+        find_row(a, tr, s_F, s_st, p0 + slot, &i, &Fi, &st0);
+        bool keep = true;
+        if (!a.homo) {
             for (uint32_t c = 0; c < a.j; c += 4) {
                 uint32_t m0 = a.M[(uint64_t)c * a.R + i];
                 uint32_t m1 = c + 1 < a.j ? a.M[(uint64_t)(c + 1) * a.R + i] : ~x;
@@ -611,29 +632,21 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
             }
         }
         const uint32_t be = (keep && a.ne > 1) ? a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] : a.e0;
-        for (uint32_t e = 0; keep && e < a.ne; e++) {
-            if (e == be) continue;
-            uint32_t st = a.loc[(uint64_t)e * a.R + i];
-            uint32_t len = a.loc[(uint64_t)(a.ne + e) * a.R + i];
-            keep = in_sorted(a.e[e].ci + st, len, x);
+        for (uint32_t e2 = 0; keep && e2 < a.ne; e2++) {
+            if (e2 == be) continue;
+            uint32_t st = a.loc[(uint64_t)e2 * a.R + i];
+            uint32_t len = a.loc[(uint64_t)(a.ne + e2) * a.R + i];
+            keep = in_sorted(a.e[e2].ci + st, len, x);
         }
-        kp[r] = keep;
+        if (keep) atomicOr(&s_keep[slot >> 6], 1ull << (slot & 63));
     }
-    const uint32_t w = threadIdx.x >> 6;
-    uint32_t cnt = 0;
-#pragma unroll
-    for (uint32_t r = 0; r < SPT; r++) {
-        const uint64_t mask = __ballot(kp[r]);
-        if (lane_id() == 0 && !a.abl_two_step) a.bitmap[(uint64_t)blockIdx.x * (TS / 64) + r * (QT / 64) + w] = mask;
-        cnt += (uint32_t)__popcll(mask);
-    }
-    if (lane_id() == 0) s_cnt[w] = cnt;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = 0;
-#pragma unroll
-        for (int q = 0; q < QT / 64; q++) t += s_cnt[q];
-        a.tile_cnt[blockIdx.x] = t;
+    // the tile's keep bits (one word per 64 slots) and their count
+    if (threadIdx.x < 64) {
+        const uint64_t word = threadIdx.x < TS / 64 ? s_keep[threadIdx.x] : 0ull;
+        if (threadIdx.x < TS / 64 && !a.abl_two_step) a.bitmap[(uint64_t)blockIdx.x * (TS / 64) + threadIdx.x] = word;
+        const uint32_t t = wave_sum((uint32_t)__popcll(word));
+        if (threadIdx.x == 0) a.tile_cnt[blockIdx.x] = t;
     }
 }
 

@@ -181,11 +181,18 @@ __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, uint32_t nq, const W
     __shared__ uint32_t s_st[WT];
     __shared__ WQ s_Q;
     __shared__ uint32_t s_q[2];
-    __shared__ uint32_t s_cnt[WT / 64];
+    __shared__ uint32_t s_x[WT];     // elements that passed the C(u) test, compacted
+    __shared__ uint16_t s_slot[WT];  // and their slots in the tile
+    __shared__ uint64_t s_keep[WT / 64];
+    __shared__ uint32_t s_n;
+    if (threadIdx.x == 0) s_n = 0;
+    if (threadIdx.x < WT / 64) s_keep[threadIdx.x] = 0;
     const uint64_t tile = blockIdx.x, p0 = tile * WT;
-    const WTile t = stage_wtile(qs, nq, F, tile_row, loc, tile, s_F, s_st, &s_Q, s_q);
+    const WTile t = stage_wtile(qs, nq, F, tile_row, loc, tile, s_F, s_st, &s_Q, s_q);  // (its barriers publish the above)
     const uint64_t p = p0 + threadIdx.x;
-    bool keep = false;
+    const uint32_t lane = lane_id();
+    bool pass = false;
+    uint32_t x = 0;
     if (p < gba) {
         uint64_t r, Fr;
         uint32_t lr, qi;
@@ -193,35 +200,53 @@ __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, uint32_t nq, const W
         const WQ &Q = t.one ? s_Q : qs[qi];
         const uint64_t i = r - Q.rbase;
         const uint32_t st0 = (t.one && t.staged) ? s_st[lr] : loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + i];
-        const uint32_t x = ci_all[st0 + (uint32_t)(p - Fr)];
-        keep = (Q.Cu[x >> 6] >> (x & 63)) & 1ull;
+        x = ci_all[st0 + (uint32_t)(p - Fr)];
+        pass = (Q.Cu[x >> 6] >> (x & 63)) & 1ull;
+    }
+    // the slots that pass are compacted, so that the costly tests below run
+    // in dense waves
+    const uint64_t pm = __ballot(pass);
+    if (pm) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&s_n, (uint32_t)__popcll(pm));
+        base = __shfl(base, 0, 64);
+        if (pass) {
+            s_slot[base + rank_below(pm)] = (uint16_t)threadIdx.x;
+            s_x[base + rank_below(pm)] = x;
+        }
+    }
+    __syncthreads();
+    const uint32_t n = __builtin_amdgcn_readfirstlane(s_n);
+    if (threadIdx.x < n) {
+        const uint32_t slot = s_slot[threadIdx.x], xv = s_x[threadIdx.x];
+        uint64_t r, Fr;
+        uint32_t lr, qi;
+        wfind(qs, F, t, s_F, s_q, p0 + slot, &r, &Fr, &lr, &qi);
+        const WQ &Q = t.one ? s_Q : qs[qi];
+        const uint64_t i = r - Q.rbase;
+        bool keep = true;
         // x not in m_i: the row's values four at a time (independent loads)
         for (uint32_t c = 0; keep && c < Q.j; c += 4) {
             uint32_t m[4];
 #pragma unroll
-            for (uint32_t q = 0; q < 4; q++) m[q] = c + q < Q.j ? Q.M[(uint64_t)(c + q) * Q.R + i] : ~x;
+            for (uint32_t q = 0; q < 4; q++) m[q] = c + q < Q.j ? Q.M[(uint64_t)(c + q) * Q.R + i] : ~xv;
 #pragma unroll
-            for (uint32_t q = 0; q < 4; q++) keep = keep && m[q] != x;
+            for (uint32_t q = 0; q < 4; q++) keep = keep && m[q] != xv;
         }
         const uint32_t be = (keep && Q.ne > 1) ? loc[Q.locbase + (uint64_t)(2 * Q.ne + 1) * Q.R + i] : Q.e0;
         for (uint32_t e = 0; keep && e < Q.ne; e++) {
             if (e == be) continue;
             keep = in_sorted(edges[Q.efirst + e].ci + loc[Q.locbase + (uint64_t)e * Q.R + i],
-                             loc[Q.locbase + (uint64_t)(Q.ne + e) * Q.R + i], x);
+                             loc[Q.locbase + (uint64_t)(Q.ne + e) * Q.R + i], xv);
         }
-    }
-    const uint64_t mask = __ballot(keep);
-    const uint32_t w = threadIdx.x >> 6;
-    if (lane_id() == 0) {
-        bitmap[tile * (WT / 64) + w] = mask;
-        s_cnt[w] = (uint32_t)__popcll(mask);
+        if (keep) atomicOr(&s_keep[slot >> 6], 1ull << (slot & 63));
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t tc = 0;
-#pragma unroll
-        for (int q = 0; q < WT / 64; q++) tc += s_cnt[q];
-        tile_cnt[tile] = tc;
+    if (threadIdx.x < 64) {
+        const uint64_t word = threadIdx.x < WT / 64 ? s_keep[threadIdx.x] : 0ull;
+        if (threadIdx.x < WT / 64) bitmap[tile * (WT / 64) + threadIdx.x] = word;
+        const uint32_t tc = wave_sum((uint32_t)__popcll(word));
+        if (threadIdx.x == 0) tile_cnt[tile] = tc;
     }
 }
 

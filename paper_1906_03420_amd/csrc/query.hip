@@ -502,11 +502,13 @@ __device__ __forceinline__ uint64_t row_of(const uint64_t *F, uint64_t lo, uint6
 // one slot per thread (SPT = 1) and four times as many workgroups.
 constexpr uint64_t WIDE_TILE_SLOTS = 1ull << 22;  // |GBA| from which SPT = 4
 
-// The rows a tile touches, staged once per workgroup: F[i] and the start of
-// N(v'_i, l0) in ci for rows r_lo..r_hi.  A thread then finds its row with a
-// binary search in LDS instead of a chain of dependent global loads.  Tiles
-// spanning more than its slots' worth of rows (long runs of rows with no
-// first-edge neighbours) search F in global memory instead.
+// The rows r_lo..r_hi a tile touches.  When they are at most the tile's slot
+// count they are staged in LDS; tiles spanning more rows (long runs of rows
+// with no first-edge neighbours) search F in global memory instead.  The
+// link stages F[i] and the start of N(v'_i, l0) in ci and finds the row of
+// each survivor by a binary search in LDS (stage_rows, find_row): its
+// survivors are often few.  The join, which needs the row of every slot,
+// builds a map from slot to row once per tile (stage_slot_rows).
 struct TileRows {
     uint64_t r_lo, r_hi;
     bool staged;
@@ -549,6 +551,53 @@ __device__ __forceinline__ void find_row(const LevelArgs &a, const TileRows &t, 
     }
 }
 
+// The join's view of a tile's rows.  When they fit (staged), every slot's
+// row is found once for the whole tile instead of by a binary search per
+// slot: each row after the first marks the slot where its slice of GBA
+// starts (the largest row wins where empty rows share a start), and a
+// max-scan over the tile's slots carries each mark forward, so s_row[s] is
+// the largest row whose slice starts at or before slot s.  s_base[r] is the
+// position in ci_all of the tile's slot 0 as seen from row r (mod 2^32), so
+// slot s reads ci_all[s_base[s_row[s]] + s].  s_row must be zero on entry,
+// published by a barrier.
+template <uint32_t SPT>
+__device__ __forceinline__ TileRows stage_slot_rows(const LevelArgs &a, uint64_t tile, uint32_t *s_row,
+                                                    uint32_t *s_base, uint32_t *s_w) {
+    constexpr uint32_t TS = SPT * QT;
+    TileRows t;
+    t.r_lo = a.tile_row[tile];
+    t.r_hi = a.tile_row[tile + 1];
+    const uint64_t nr = t.r_hi - t.r_lo + 1;
+    t.staged = nr <= TS;
+    if (t.staged) {
+        const uint64_t p0 = tile * TS;
+        for (uint32_t r = threadIdx.x; r < nr; r += QT) {
+            const uint64_t F = a.F[t.r_lo + r];
+            s_base[r] = a.loc[(uint64_t)(2 * a.ne) * a.R + t.r_lo + r] + (uint32_t)(p0 - F);
+            // rows after the first start past p0 (the first holds slot 0)
+            if (r > 0 && F - p0 < TS) atomicMax(&s_row[F - p0], r);
+        }
+        __syncthreads();
+        block_max_scan<QT, SPT>(s_row, s_w);
+    }
+    return t;
+}
+
+// row i of the tile's slot s and the position of its element in ci_all
+__device__ __forceinline__ void slot_row(const LevelArgs &a, const TileRows &t, const uint32_t *s_row,
+                                         const uint32_t *s_base, uint64_t p0, uint32_t s, uint64_t *i,
+                                         uint32_t *pos) {
+    if (t.staged) {
+        const uint32_t r = s_row[s];
+        *i = t.r_lo + r;
+        *pos = s_base[r] + s;
+    } else {
+        const uint64_t p = p0 + s;
+        *i = row_of(a.F, t.r_lo, t.r_hi, p);
+        *pos = a.loc[(uint64_t)(2 * a.ne) * a.R + *i] + (uint32_t)(p - a.F[*i]);
+    }
+}
+
 // slot x of row i survives: x in C(u), x not in m_i, x in every other
 // linking list of the row
 __device__ __forceinline__ bool slot_keep(const LevelArgs &a, uint64_t i, uint32_t x) {
@@ -567,32 +616,37 @@ __device__ __forceinline__ bool slot_keep(const LevelArgs &a, uint64_t i, uint32
 template <uint32_t SPT>
 __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
     constexpr uint32_t TS = SPT * QT;
-    __shared__ uint64_t s_F[TS];
-    __shared__ uint32_t s_st[TS];
+    __shared__ uint32_t s_row[TS];    // row of each slot of the tile (staged tiles)
+    __shared__ uint32_t s_base[TS];   // per row: ci_all position of slot 0
     __shared__ uint32_t s_x[TS];      // elements that passed the C(u) test, compacted
+    __shared__ uint32_t s_ri[TS];     // and their rows (from r_lo)
     __shared__ uint16_t s_slot[TS];   // and their slots in the tile
     __shared__ uint64_t s_keep[TS / 64];
+    __shared__ uint32_t s_w[QT / 64];
     __shared__ uint32_t s_n;
     if (threadIdx.x == 0) s_n = 0;
     if (threadIdx.x < TS / 64) s_keep[threadIdx.x] = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < SPT; k++) s_row[threadIdx.x * SPT + k] = 0;
     __syncthreads();
     const uint64_t p0 = (uint64_t)blockIdx.x * TS;
-    const TileRows tr = stage_rows<SPT>(a, blockIdx.x, s_F, s_st);
+    const TileRows tr = stage_slot_rows<SPT>(a, blockIdx.x, s_row, s_base, s_w);
     const uint32_t *ci0 = a.ci_all;
     const uint32_t lane = lane_id();
     uint32_t xs[SPT];
+    uint64_t is[SPT];
     bool kp[SPT];
-    // x = N(v'_i, l0)[p - F[i]] for the thread's four slots
+    // x = N(v'_i, l0)[p - F[i]] for the thread's slots
 #pragma unroll
     for (uint32_t r = 0; r < SPT; r++) {
-        const uint64_t p = p0 + r * QT + threadIdx.x;
-        kp[r] = p < a.gba;
+        const uint32_t sl = r * QT + threadIdx.x;
+        kp[r] = p0 + sl < a.gba;
         xs[r] = 0;
+        is[r] = 0;
         if (kp[r]) {
-            uint64_t i, Fi;
-            uint32_t st0;
-            find_row(a, tr, s_F, s_st, p, &i, &Fi, &st0);
-            xs[r] = ci0[st0 + (uint32_t)(p - Fi)];
+            uint32_t pos;
+            slot_row(a, tr, s_row, s_base, p0, sl, &is[r], &pos);
+            xs[r] = ci0[pos];
         }
     }
     // x in C(u); the slots that pass are compacted (in no particular order)
@@ -609,6 +663,7 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
                 const uint32_t idx = base + rank_below(mask);
                 s_slot[idx] = (uint16_t)(r * QT + threadIdx.x);
                 s_x[idx] = xs[r];
+                s_ri[idx] = (uint32_t)(is[r] - tr.r_lo);
             }
         }
     }
@@ -618,9 +673,7 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
     const uint32_t n = __builtin_amdgcn_readfirstlane(s_n);
     for (uint32_t e = threadIdx.x; e < n; e += QT) {
         const uint32_t slot = s_slot[e], x = s_x[e];
-        uint64_t i, Fi;
-        uint32_t st0;
-        find_row(a, tr, s_F, s_st, p0 + slot, &i, &Fi, &st0);
+        const uint64_t i = tr.r_lo + s_ri[e];
         bool keep = true;
         if (!a.homo) {
             for (uint32_t c = 0; c < a.j; c += 4) {

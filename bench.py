@@ -52,7 +52,7 @@ KERNEL_SOURCES = {
     "k_fused_chunks": ("fused.hip", "fused.h", "join_device.h", "gsi_internal.h"),
     "k_filter": ("query.hip", "gsi_internal.h"),
     "k_locate": ("query.hip", "join_device.h", "gsi_internal.h"),
-    "k_join": ("query.hip", "join_device.h", "gsi_internal.h"),
+    "k_join": ("query.hip", "join_device.h", "scan_device.h", "gsi_internal.h"),
     "k_link": ("query.hip", "join_device.h", "gsi_internal.h"),
 }
 

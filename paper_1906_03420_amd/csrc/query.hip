@@ -33,6 +33,7 @@
 #include "gsi_internal.h"
 #include "fused.h"
 #include "join_device.h"
+#include "scan_device.h"
 
 namespace gsi {
 

@@ -200,60 +200,122 @@ static void launch_filter(gsi_ctx *c, gsi_graph *g, const FilterArgs &fa, uint64
 }
 
 // Batched filter: the query vertices of many queries, 32 per pass, all
-// passes in one launch (blockIdx.y = pass; workgroups stride over the
-// tiles).  Passes take query vertices sorted by label, so a pass covers few
-// labels: here a lane whose label matches no query vertex of the pass reads
-// no other word, and most lines of those words are never fetched (unlike
-// the single-query filter, whose query vertices usually span the frequent
-// labels).  Each workgroup keeps per query vertex counts in LDS and writes
+// passes in one launch (blockIdx.y = pass; workgroups stride over rounds of
+// FM_TILE data vertices).  A pass takes query vertices sorted by label, so
+// its vertices form a few groups of one label each.  A round first finds,
+// per data vertex, the group of its label (most vertices have none), and
+// compacts the vertices that have one into a list in LDS; the signature
+// test then runs on that list in dense waves, each thread testing its
+// vertex against the query vertices of its group only (testing in place,
+// a wave would run the test of every query vertex its lanes match for the
+// few lanes that match).  Passing pairs set bits of the round's bitset
+// words in LDS, which are then written out one 128-byte line per query
+// vertex.  Each workgroup keeps per query vertex counts in LDS and writes
 // them to part[(pass * 32 + u) * gridDim.x + workgroup].
+constexpr uint32_t FM_TILE = 1024;
+
 __global__ __launch_bounds__(QT) void k_filter_multi(const uint32_t *sig, uint32_t n, uint64_t nwords,
                                                     const FilterArgs *__restrict__ passes, uint64_t *bits,
                                                     uint32_t *part) {
-    // the pass's query signatures: a uniform, read-only address, so the
-    // compiler reads them with scalar loads (as kernel arguments are)
+    constexpr uint32_t TW = FM_TILE / 64;  // bitset words per round
     const FilterArgs &fa = passes[blockIdx.y];
+    __shared__ uint32_t s_q[GSI_MAX_K][GSI_SIG_WORDS];
+    __shared__ uint32_t s_dst[GSI_MAX_K];
     __shared__ uint32_t s_cnt[GSI_MAX_K];
-    if (threadIdx.x < GSI_MAX_K) s_cnt[threadIdx.x] = 0;
-    __syncthreads();
+    __shared__ uint32_t s_glab[GSI_MAX_K];      // label of group g
+    __shared__ uint32_t s_gbeg[GSI_MAX_K + 1];  // its query vertices: s_gbeg[g] .. s_gbeg[g+1]-1
+    __shared__ uint32_t s_ng, s_n;
+    __shared__ uint64_t s_res[GSI_MAX_K][TW];   // the round's bitset words
+    __shared__ uint16_t s_v[FM_TILE];           // vertices with a group (offset in the round)
+    __shared__ uint8_t s_g[FM_TILE];            // and their groups
     const uint32_t K = fa.k;
     const uint32_t need = fa.word_mask;
+    for (uint32_t t = threadIdx.x; t < K * GSI_SIG_WORDS; t += QT)
+        s_q[t / GSI_SIG_WORDS][t % GSI_SIG_WORDS] = fa.q[t / GSI_SIG_WORDS][t % GSI_SIG_WORDS];
+    for (uint32_t t = threadIdx.x; t < GSI_MAX_K * TW; t += QT) s_res[t / TW][t % TW] = 0;
+    if (threadIdx.x < GSI_MAX_K) {
+        s_cnt[threadIdx.x] = 0;
+        s_dst[threadIdx.x] = threadIdx.x < K ? fa.dst[threadIdx.x] : 0u;
+    }
+    if (threadIdx.x == 0) {
+        uint32_t ng = 0;
+        for (uint32_t u = 0; u < K; u++) {
+            if (u == 0 || fa.q[u][0] != fa.q[u - 1][0]) {
+                s_glab[ng] = fa.q[u][0];
+                s_gbeg[ng] = u;
+                ng++;
+            }
+        }
+        s_gbeg[ng] = K;
+        s_ng = ng;
+        s_n = 0;
+    }
+    __syncthreads();
+    const uint32_t ng = __builtin_amdgcn_readfirstlane(s_ng);
     const uint32_t lane = lane_id();
-    const uint64_t ntiles = ((uint64_t)n + QT - 1) / QT;
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint64_t v = tile * QT + threadIdx.x;
-        const bool valid = v < n;
-        const uint32_t w0 = valid ? sig[v] : NONE32;
-        uint32_t ok = 0;
-        for (uint32_t u = 0; u < K; u++) ok |= (valid && w0 == fa.q[u][0]) ? (1u << u) : 0u;
-        uint32_t wv[GSI_SIG_WORDS];
+    const uint64_t nrounds = ((uint64_t)n + FM_TILE - 1) / FM_TILE;
+    for (uint64_t round = blockIdx.x; round < nrounds; round += gridDim.x) {
+        const uint64_t v0 = round * FM_TILE;
+        // labels of the round's vertices (all loads first), their groups
+        uint32_t w0[FM_TILE / QT];
 #pragma unroll
-        for (int i = 1; i < GSI_SIG_WORDS; i++)
-            wv[i] = (((need >> i) & 1u) && ok) ? sig[(uint64_t)i * n + v] : NONE32;
-        if (ok && need) {
-            for (uint32_t u = 0; u < K; u++) {
-                if (!((ok >> u) & 1u)) continue;
+        for (uint32_t r = 0; r < FM_TILE / QT; r++) {
+            const uint64_t v = v0 + r * QT + threadIdx.x;
+            w0[r] = v < n ? sig[v] : NONE32;
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < FM_TILE / QT; r++) {
+            // (groups are runs of equal labels: the host sorts by label)
+            uint32_t gi = NONE32;
+            for (uint32_t g = 0; g < ng; g++)
+                if (w0[r] == s_glab[g]) gi = g;
+            const bool has = gi != NONE32 && v0 + r * QT + threadIdx.x < n;
+            const uint64_t mask = __ballot(has);
+            if (mask) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&s_n, (uint32_t)__popcll(mask));
+                base = __shfl(base, 0, 64);
+                if (has) {
+                    const uint32_t idx = base + rank_below(mask);
+                    s_v[idx] = (uint16_t)(r * QT + threadIdx.x);
+                    s_g[idx] = (uint8_t)gi;
+                }
+            }
+        }
+        __syncthreads();
+        // signature test of the listed vertices against their groups
+        const uint32_t nm = __builtin_amdgcn_readfirstlane(s_n);
+        for (uint32_t e = threadIdx.x; e < nm; e += QT) {
+            const uint32_t off = s_v[e], gi = s_g[e];
+            const uint64_t v = v0 + off;
+            uint32_t wv[GSI_SIG_WORDS];
+#pragma unroll
+            for (int i = 1; i < GSI_SIG_WORDS; i++) wv[i] = ((need >> i) & 1u) ? sig[(uint64_t)i * n + v] : 0u;
+            const uint32_t ue = s_gbeg[gi + 1];
+            for (uint32_t u = s_gbeg[gi]; u < ue; u++) {
                 bool good = true;
 #pragma unroll
                 for (int i = 1; i < GSI_SIG_WORDS; i++) {
-                    const uint32_t qw = fa.q[u][i];
+                    if (!((need >> i) & 1u)) continue;
+                    const uint32_t qw = s_q[u][i];
                     good = good && ((wv[i] & qw) == qw);
                 }
-                if (!good) ok &= ~(1u << u);
+                if (good) atomicOr(&s_res[u][off >> 6], 1ull << (off & 63));
             }
         }
-        uint64_t mine = 0;
-        for (uint32_t u = 0; u < K; u++) {
-            const uint64_t m = __ballot((ok >> u) & 1u);
-            if (lane == u) mine = m;
+        __syncthreads();
+        // the round's words of every query vertex of the pass, then cleared
+        const uint64_t wbase = round * TW;
+        for (uint32_t t = threadIdx.x; t < K * TW; t += QT) {
+            const uint32_t u = t / TW, q = t % TW;
+            const uint64_t word = s_res[u][q];
+            if (wbase + q < nwords) bits[(uint64_t)s_dst[u] * nwords + wbase + q] = word;
+            if (word) atomicAdd(&s_cnt[u], (uint32_t)__popcll(word));
+            s_res[u][q] = 0;
         }
-        const uint64_t wave_first = tile * QT + (threadIdx.x & ~63u);
-        if (lane < K && wave_first < n) {
-            bits[(uint64_t)fa.dst[lane] * nwords + (wave_first >> 6)] = mine;
-            if (mine) atomicAdd(&s_cnt[lane], (uint32_t)__popcll(mine));
-        }
+        if (threadIdx.x == 0) s_n = 0;
+        __syncthreads();
     }
-    __syncthreads();
     if (threadIdx.x < GSI_MAX_K)
         part[((uint64_t)blockIdx.y * GSI_MAX_K + threadIdx.x) * gridDim.x + blockIdx.x] = s_cnt[threadIdx.x];
 }
@@ -313,7 +375,8 @@ void run_filter_many(gsi_graph *g, const std::vector<const HostQuery *> &qs, con
     Scratch s(c);
     const uint64_t nwords = ((uint64_t)g->n + 63) / 64;
     // workgroups per pass: enough to fill the chip when passes are few
-    const uint32_t nb = std::min<uint32_t>(nblocks(g->n), std::max<uint32_t>(32, 8192 / npass));
+    const uint32_t nrounds = (uint32_t)(((uint64_t)g->n + FM_TILE - 1) / FM_TILE);
+    const uint32_t nb = std::max<uint32_t>(1, std::min<uint32_t>(nrounds, std::max<uint32_t>(32, 8192 / npass)));
     FilterArgs *dp = reinterpret_cast<FilterArgs *>(s.get<uint32_t>((uint64_t)npass * sizeof(FilterArgs) / 4,
                                                                     "filter passes"));
     uint32_t *part = s.get<uint32_t>((uint64_t)npass * GSI_MAX_K * nb, "filter partial counts");

@@ -69,7 +69,7 @@ __device__ __forceinline__ uint32_t query_of(const WQ *qs, uint32_t lo, uint32_t
 // Each row scans its shortest linking list (e0's on ties): the survivors,
 // and their order, are those of the first edge of Algorithm 4.
 __global__ __launch_bounds__(WT) void k_wlocate(const WQ *qs, uint32_t nq, const WEdge *edges, uint64_t Rtot,
-                                               uint32_t *loc, uint32_t *bound) {
+                                               uint32_t *loc, uint32_t *bound, uint32_t *rowq) {
     __shared__ uint32_t s_q[2];
     const uint64_t r0 = (uint64_t)blockIdx.x * WT;
     if (threadIdx.x == 0) {
@@ -80,7 +80,9 @@ __global__ __launch_bounds__(WT) void k_wlocate(const WQ *qs, uint32_t nq, const
     __syncthreads();
     const uint64_t r = r0 + threadIdx.x;
     if (r >= Rtot) return;
-    const WQ &Q = qs[query_of(qs, s_q[0], s_q[1], r)];
+    const uint32_t qi = query_of(qs, s_q[0], s_q[1], r);
+    rowq[r] = qi;  // the row's query, for the join and link of this step
+    const WQ &Q = qs[qi];
     const uint64_t i = r - Q.rbase;
     uint32_t s0 = 0, l0 = 0, ob = NONE32, os = 0, ol = 0xFFFFFFFFu;
     for (uint32_t e = 0; e < Q.ne; e++) {
@@ -119,17 +121,17 @@ struct WTile {
     bool one;     // all rows in one query
 };
 
-__device__ __forceinline__ WTile stage_wtile(const WQ *qs, uint32_t nq, const uint64_t *F, const uint64_t *tile_row,
-                                             const uint32_t *loc, uint64_t tile, uint64_t *s_F, uint32_t *s_st,
-                                             WQ *s_Q, uint32_t *s_q) {
+__device__ __forceinline__ WTile stage_wtile(const WQ *qs, const uint32_t *rowq, const uint64_t *F,
+                                             const uint64_t *tile_row, const uint32_t *loc, uint64_t tile,
+                                             uint64_t *s_F, uint32_t *s_st, WQ *s_Q, uint32_t *s_q) {
     WTile t;
     t.r_lo = tile_row[tile];
     t.r_hi = tile_row[tile + 1];
     t.nr = t.r_hi - t.r_lo + 1;
     t.staged = t.nr <= WT;
     if (threadIdx.x == 0) {
-        s_q[0] = query_of(qs, 0, nq - 1, t.r_lo);
-        s_q[1] = query_of(qs, s_q[0], nq - 1, t.r_hi);
+        s_q[0] = rowq[t.r_lo];
+        s_q[1] = rowq[t.r_hi];
     }
     if (t.staged && threadIdx.x < t.nr) s_F[threadIdx.x] = F[t.r_lo + threadIdx.x];
     __syncthreads();
@@ -147,7 +149,7 @@ __device__ __forceinline__ WTile stage_wtile(const WQ *qs, uint32_t nq, const ui
 }
 
 // global row r holding slot p, F[r], and the query of r
-__device__ __forceinline__ void wfind(const WQ *qs, const uint64_t *F, const WTile &t, const uint64_t *s_F,
+__device__ __forceinline__ void wfind(const uint32_t *rowq, const uint64_t *F, const WTile &t, const uint64_t *s_F,
                                       const uint32_t *s_q, uint64_t p, uint64_t *r, uint64_t *Fr, uint32_t *lr,
                                       uint32_t *q) {
     if (t.staged) {
@@ -171,10 +173,10 @@ __device__ __forceinline__ void wfind(const WQ *qs, const uint64_t *F, const WTi
         *Fr = F[lo];
         *lr = 0;
     }
-    *q = t.one ? s_q[0] : query_of(qs, s_q[0], s_q[1], *r);
+    *q = t.one ? s_q[0] : rowq[*r];
 }
 
-__global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, uint32_t nq, const WEdge *edges, const uint32_t *ci_all,
+__global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, const uint32_t *rowq, const WEdge *edges, const uint32_t *ci_all,
                                              const uint64_t *F, const uint64_t *tile_row, uint64_t gba,
                                              const uint32_t *loc, uint64_t *bitmap, uint32_t *tile_cnt) {
     __shared__ uint64_t s_F[WT];
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, uint32_t nq, const W
     if (threadIdx.x == 0) s_n = 0;
     if (threadIdx.x < WT / 64) s_keep[threadIdx.x] = 0;
     const uint64_t tile = blockIdx.x, p0 = tile * WT;
-    const WTile t = stage_wtile(qs, nq, F, tile_row, loc, tile, s_F, s_st, &s_Q, s_q);  // (its barriers publish the above)
+    const WTile t = stage_wtile(qs, rowq, F, tile_row, loc, tile, s_F, s_st, &s_Q, s_q);  // (its barriers publish the above)
     const uint64_t p = p0 + threadIdx.x;
     const uint32_t lane = lane_id();
     bool pass = false;
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, uint32_t nq, const W
     if (p < gba) {
         uint64_t r, Fr;
         uint32_t lr, qi;
-        wfind(qs, F, t, s_F, s_q, p, &r, &Fr, &lr, &qi);
+        wfind(rowq, F, t, s_F, s_q, p, &r, &Fr, &lr, &qi);
         const WQ &Q = t.one ? s_Q : qs[qi];
         const uint64_t i = r - Q.rbase;
         const uint32_t st0 = (t.one && t.staged) ? s_st[lr] : loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + i];
@@ -221,7 +223,7 @@ __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, uint32_t nq, const W
         const uint32_t slot = s_slot[threadIdx.x], xv = s_x[threadIdx.x];
         uint64_t r, Fr;
         uint32_t lr, qi;
-        wfind(qs, F, t, s_F, s_q, p0 + slot, &r, &Fr, &lr, &qi);
+        wfind(rowq, F, t, s_F, s_q, p0 + slot, &r, &Fr, &lr, &qi);
         const WQ &Q = t.one ? s_Q : qs[qi];
         const uint64_t i = r - Q.rbase;
         bool keep = true;
@@ -281,7 +283,7 @@ __global__ __launch_bounds__(WT) void k_wsurv(const WQ *qs, uint32_t nq, const u
 // contiguous block when k is at most this
 constexpr uint32_t WLINK_STAGE_K = 16;
 
-__global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, uint32_t nq, const uint32_t *ci_all, const uint64_t *F,
+__global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, const uint32_t *rowq, const uint32_t *ci_all, const uint64_t *F,
                                              const uint64_t *tile_row, const uint32_t *loc, const uint64_t *bitmap,
                                              const uint64_t *tile_off, uint64_t *hv) {
     __shared__ uint64_t s_F[WT];
@@ -302,7 +304,7 @@ __global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, uint32_t nq, const u
         for (uint32_t q = 0; q < w; q++) before += (uint32_t)__popcll(words[q]);
         if ((word >> lane) & 1ull) s_list[before + rank_below(word)] = (uint16_t)threadIdx.x;
     }
-    const WTile t = stage_wtile(qs, nq, F, tile_row, loc, tile, s_F, s_st, &s_Q, s_q);  // (its barrier publishes s_list)
+    const WTile t = stage_wtile(qs, rowq, F, tile_row, loc, tile, s_F, s_st, &s_Q, s_q);  // (its barrier publishes s_list)
     const uint32_t n = (uint32_t)(tile_off[tile + 1] - tile_off[tile]);
     const uint32_t local = threadIdx.x;  // survivor `local` of the tile
     const uint64_t gpos = tile_off[tile] + local;
@@ -311,7 +313,7 @@ __global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, uint32_t nq, const u
         const uint64_t p = p0 + s_list[local];
         uint64_t r, Fr;
         uint32_t lr, qi;
-        wfind(qs, F, t, s_F, s_q, p, &r, &Fr, &lr, &qi);
+        wfind(rowq, F, t, s_F, s_q, p, &r, &Fr, &lr, &qi);
         const WQ &Q = t.one ? s_Q : qs[qi];
         const uint64_t i = r - Q.rbase;
         const uint64_t pos = gpos - Q.sbase;
@@ -465,6 +467,7 @@ static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool co
         WEdge *d_e = s.get<WEdge>(he.size(), "wide edges");
         uint32_t *loc = s.get<uint32_t>(loctot, "wide lookups");
         uint32_t *bound = s.get<uint32_t>(Rtot, "wide bounds");
+        uint32_t *rowq = s.get<uint32_t>(Rtot, "wide row queries");
         uint64_t *F = s.get<uint64_t>(Rtot + 1, "wide offsets F");
         uint64_t *scal = s.get<uint64_t>(2, "wide scalars");
         GSI_HIP(hipMemcpyAsync(d_q, hq.data(), sizeof(WQ) * nq, hipMemcpyHostToDevice, c->stream));
@@ -472,7 +475,7 @@ static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool co
         double lb = 0;
         for (auto &Q : hq) lb += (double)Q.R * (4.0 * Q.ne + 128.0 * Q.ne + 8.0 * Q.ne + 4.0);
         launch(c, "k_wlocate", lb, k_wlocate, wblocks(Rtot), WT, (const WQ *)d_q, nq, (const WEdge *)d_e, Rtot, loc,
-               bound);
+               bound, rowq);
         exclusive_scan(c, bound, Rtot, F, s, scal);
         uint64_t gba;
         read_scalars(c, scal, &gba, 1);  // also orders the uploads above before `hq`/`he` change
@@ -494,7 +497,7 @@ static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool co
         tile_rows(c, F, Rtot, ntiles, trow);
         double jb = 4.0 * gba + gba / 8.0 + 4.0 * ntiles;
         for (auto &Q : hq) jb += (double)Q.R * (8.0 + 8.0 * Q.ne + 4.0 * Q.j);
-        launch(c, "k_wjoin", jb, k_wjoin, (uint32_t)ntiles, WT, (const WQ *)d_q, nq, (const WEdge *)d_e,
+        launch(c, "k_wjoin", jb, k_wjoin, (uint32_t)ntiles, WT, (const WQ *)d_q, (const uint32_t *)rowq, (const WEdge *)d_e,
                (const uint32_t *)g->ci, (const uint64_t *)F, (const uint64_t *)trow, gba, (const uint32_t *)loc, bitmap,
                tcnt);
         exclusive_scan(c, tcnt, ntiles, toff, s, scal + 1);
@@ -541,7 +544,8 @@ static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool co
         }
         uint64_t *hv = any_final ? s.get<uint64_t>(Stot, "wide row hashes") : nullptr;
         GSI_HIP(hipMemcpyAsync(d_q, hq.data(), sizeof(WQ) * nq, hipMemcpyHostToDevice, c->stream));
-        launch(c, "k_wlink", kb, k_wlink, (uint32_t)ntiles, WT, (const WQ *)d_q, nq, (const uint32_t *)g->ci,
+        launch(c, "k_wlink", kb, k_wlink, (uint32_t)ntiles, WT, (const WQ *)d_q, (const uint32_t *)rowq,
+               (const uint32_t *)g->ci,
                (const uint64_t *)F, (const uint64_t *)trow, (const uint32_t *)loc, (const uint64_t *)bitmap,
                (const uint64_t *)toff, hv);
         std::vector<uint64_t> part;

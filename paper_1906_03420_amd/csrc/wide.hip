@@ -22,6 +22,7 @@
 #include <cstring>
 
 #include "join_device.h"
+#include "scan_device.h"
 #include "wide.h"
 
 namespace gsi {
@@ -176,55 +177,130 @@ __device__ __forceinline__ void wfind(const uint32_t *rowq, const uint64_t *F, c
     *q = t.one ? s_q[0] : rowq[*r];
 }
 
-__global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, const uint32_t *rowq, const WEdge *edges, const uint32_t *ci_all,
-                                             const uint64_t *F, const uint64_t *tile_row, uint64_t gba,
-                                             const uint32_t *loc, uint64_t *bitmap, uint32_t *tile_cnt) {
-    __shared__ uint64_t s_F[WT];
-    __shared__ uint32_t s_st[WT];
+// The join of WJ_TILES consecutive 256-slot tiles per workgroup: each
+// thread takes one slot of each tile and issues their loads together, and
+// the set-up (rows staged in LDS, the query's descriptor) is paid once per
+// WJ_TILES tiles.  Outputs stay per 256-slot tile: WT/64 bitmap words and
+// one survivor count each.  When the rows fit (staged), each slot's row
+// comes from a map built once per workgroup: each row after the first
+// marks the slot where its slice starts (the largest row wins where empty
+// rows share a start) and a max-scan carries the marks forward.
+constexpr uint32_t WJ_TILES = 4;
+constexpr uint32_t WJS = WJ_TILES * WT;  // slots per workgroup
+
+__global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, const uint32_t *rowq, const WEdge *edges,
+                                             const uint32_t *ci_all, const uint64_t *F, const uint64_t *tile_row,
+                                             uint64_t ntiles, uint64_t gba, const uint32_t *loc, uint64_t *bitmap,
+                                             uint32_t *tile_cnt) {
+    __shared__ uint64_t s_F[WJS];
+    __shared__ uint32_t s_st[WJS];
+    __shared__ uint32_t s_row[WJS];  // row (from r_lo) of each slot, staged groups
+    __shared__ uint32_t s_w[WT / 64];
     __shared__ WQ s_Q;
     __shared__ uint32_t s_q[2];
-    __shared__ uint32_t s_x[WT];     // elements that passed the C(u) test, compacted
-    __shared__ uint16_t s_slot[WT];  // and their slots in the tile
-    __shared__ uint64_t s_keep[WT / 64];
+    __shared__ uint32_t s_x[WJS];    // elements that passed the C(u) test, compacted
+    __shared__ uint32_t s_r[WJS];    // and their rows (from r_lo)
+    __shared__ uint16_t s_slot[WJS]; // and their slots in the group
+    __shared__ uint64_t s_keep[WJS / 64];
     __shared__ uint32_t s_n;
-    if (threadIdx.x == 0) s_n = 0;
-    if (threadIdx.x < WT / 64) s_keep[threadIdx.x] = 0;
-    const uint64_t tile = blockIdx.x, p0 = tile * WT;
-    const WTile t = stage_wtile(qs, rowq, F, tile_row, loc, tile, s_F, s_st, &s_Q, s_q);  // (its barriers publish the above)
-    const uint64_t p = p0 + threadIdx.x;
-    const uint32_t lane = lane_id();
-    bool pass = false;
-    uint32_t x = 0;
-    if (p < gba) {
-        uint64_t r, Fr;
-        uint32_t lr, qi;
-        wfind(rowq, F, t, s_F, s_q, p, &r, &Fr, &lr, &qi);
-        const WQ &Q = t.one ? s_Q : qs[qi];
-        const uint64_t i = r - Q.rbase;
-        const uint32_t st0 = (t.one && t.staged) ? s_st[lr] : loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + i];
-        x = ci_all[st0 + (uint32_t)(p - Fr)];
-        pass = (Q.Cu[x >> 6] >> (x & 63)) & 1ull;
+    const uint64_t t0 = (uint64_t)blockIdx.x * WJ_TILES;
+    const uint64_t t1 = t0 + WJ_TILES < ntiles ? t0 + WJ_TILES : ntiles;
+    const uint64_t p0 = t0 * WT;
+    const uint64_t r_lo = tile_row[t0], r_hi = tile_row[t1];
+    const uint64_t nr = r_hi - r_lo + 1;
+    const bool staged = nr <= WJS;
+    if (threadIdx.x == 0) {
+        s_n = 0;
+        s_q[0] = rowq[r_lo];
+        s_q[1] = rowq[r_hi];
     }
-    // the slots that pass are compacted, so that the costly tests below run
-    // in dense waves
-    const uint64_t pm = __ballot(pass);
-    if (pm) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&s_n, (uint32_t)__popcll(pm));
-        base = __shfl(base, 0, 64);
-        if (pass) {
-            s_slot[base + rank_below(pm)] = (uint16_t)threadIdx.x;
-            s_x[base + rank_below(pm)] = x;
+    if (threadIdx.x < WJS / 64) s_keep[threadIdx.x] = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < WJ_TILES; k++) s_row[threadIdx.x * WJ_TILES + k] = 0;
+    if (staged)
+        for (uint32_t r = threadIdx.x; r < nr; r += WT) s_F[r] = F[r_lo + r];
+    __syncthreads();
+    const bool one = s_q[0] == s_q[1];
+    if (one) {
+        const WQ &Q = qs[s_q[0]];
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&Q);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(&s_Q);
+        for (uint32_t w = threadIdx.x; w < sizeof(WQ) / 4; w += WT) dst[w] = src[w];
+        if (staged)
+            for (uint32_t r = threadIdx.x; r < nr; r += WT)
+                s_st[r] = loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + (r_lo + r - Q.rbase)];
+    }
+    if (staged)
+        for (uint32_t r = threadIdx.x; r < nr; r += WT) {
+            // rows after the first start past p0 (the first holds slot p0)
+            const uint64_t pos = s_F[r] - p0;
+            if (r > 0 && pos < WJS) atomicMax(&s_row[pos], r);
+        }
+    __syncthreads();
+    if (staged) block_max_scan<WT, WJ_TILES>(s_row, s_w);
+    const uint32_t lane = lane_id();
+    // x = N(v'_i, l0)[p - F[i]] for the thread's slot of each tile, then the
+    // C(u) test; the slots that pass are compacted so that the costly tests
+    // below run in dense waves
+    uint32_t xs[WJ_TILES], rs[WJ_TILES];
+    bool kp[WJ_TILES];
+#pragma unroll
+    for (uint32_t k = 0; k < WJ_TILES; k++) {
+        const uint32_t sl = k * WT + threadIdx.x;
+        const uint64_t p = p0 + sl;
+        kp[k] = p < gba;
+        xs[k] = 0;
+        rs[k] = 0;
+        if (kp[k]) {
+            uint64_t r, Fr;
+            uint32_t lr;
+            if (staged) {
+                lr = s_row[sl];
+                r = r_lo + lr;
+                Fr = s_F[lr];
+            } else {
+                uint64_t lo = r_lo, hi = r_hi;
+                while (lo < hi) {
+                    const uint64_t mid = lo + (hi - lo + 1) / 2;
+                    if (F[mid] <= p) lo = mid;
+                    else hi = mid - 1;
+                }
+                r = lo;
+                Fr = F[lo];
+                lr = 0;
+            }
+            rs[k] = (uint32_t)(r - r_lo);
+            const WQ &Q = one ? s_Q : qs[rowq[r]];
+            const uint64_t i = r - Q.rbase;
+            const uint32_t st0 = (one && staged) ? s_st[lr] : loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + i];
+            xs[k] = ci_all[st0 + (uint32_t)(p - Fr)];
+        }
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < WJ_TILES; k++) {
+        if (kp[k]) {
+            const uint64_t *Cu = one ? s_Q.Cu : qs[rowq[r_lo + rs[k]]].Cu;
+            kp[k] = (Cu[xs[k] >> 6] >> (xs[k] & 63)) & 1ull;
+        }
+        const uint64_t pm = __ballot(kp[k]);
+        if (pm) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&s_n, (uint32_t)__popcll(pm));
+            base = __shfl(base, 0, 64);
+            if (kp[k]) {
+                const uint32_t idx = base + rank_below(pm);
+                s_slot[idx] = (uint16_t)(k * WT + threadIdx.x);
+                s_x[idx] = xs[k];
+                s_r[idx] = rs[k];
+            }
         }
     }
     __syncthreads();
     const uint32_t n = __builtin_amdgcn_readfirstlane(s_n);
-    if (threadIdx.x < n) {
-        const uint32_t slot = s_slot[threadIdx.x], xv = s_x[threadIdx.x];
-        uint64_t r, Fr;
-        uint32_t lr, qi;
-        wfind(rowq, F, t, s_F, s_q, p0 + slot, &r, &Fr, &lr, &qi);
-        const WQ &Q = t.one ? s_Q : qs[qi];
+    for (uint32_t e = threadIdx.x; e < n; e += WT) {
+        const uint32_t slot = s_slot[e], xv = s_x[e];
+        const uint64_t r = r_lo + s_r[e];
+        const WQ &Q = one ? s_Q : qs[rowq[r]];
         const uint64_t i = r - Q.rbase;
         bool keep = true;
         // x not in m_i: the row's values four at a time (independent loads)
@@ -236,19 +312,23 @@ __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, const uint32_t *rowq
             for (uint32_t q = 0; q < 4; q++) keep = keep && m[q] != xv;
         }
         const uint32_t be = (keep && Q.ne > 1) ? loc[Q.locbase + (uint64_t)(2 * Q.ne + 1) * Q.R + i] : Q.e0;
-        for (uint32_t e = 0; keep && e < Q.ne; e++) {
-            if (e == be) continue;
-            keep = in_sorted(edges[Q.efirst + e].ci + loc[Q.locbase + (uint64_t)e * Q.R + i],
-                             loc[Q.locbase + (uint64_t)(Q.ne + e) * Q.R + i], xv);
+        for (uint32_t e2 = 0; keep && e2 < Q.ne; e2++) {
+            if (e2 == be) continue;
+            keep = in_sorted(edges[Q.efirst + e2].ci + loc[Q.locbase + (uint64_t)e2 * Q.R + i],
+                             loc[Q.locbase + (uint64_t)(Q.ne + e2) * Q.R + i], xv);
         }
         if (keep) atomicOr(&s_keep[slot >> 6], 1ull << (slot & 63));
     }
     __syncthreads();
+    // per 256-slot tile: its WT/64 bitmap words and their count
     if (threadIdx.x < 64) {
-        const uint64_t word = threadIdx.x < WT / 64 ? s_keep[threadIdx.x] : 0ull;
-        if (threadIdx.x < WT / 64) bitmap[tile * (WT / 64) + threadIdx.x] = word;
-        const uint32_t tc = wave_sum((uint32_t)__popcll(word));
-        if (threadIdx.x == 0) tile_cnt[tile] = tc;
+        const uint32_t tk = threadIdx.x / (WT / 64);  // tile of the group
+        const uint64_t word = threadIdx.x < WJS / 64 ? s_keep[threadIdx.x] : 0ull;
+        if (threadIdx.x < WJS / 64 && t0 + tk < t1) bitmap[p0 / 64 + threadIdx.x] = word;
+        uint32_t c = (uint32_t)__popcll(word);
+#pragma unroll
+        for (uint32_t o = 1; o < WT / 64; o <<= 1) c += __shfl_xor(c, o, 64);
+        if (threadIdx.x < WJS / 64 && threadIdx.x % (WT / 64) == 0 && t0 + tk < t1) tile_cnt[t0 + tk] = c;
     }
 }
 
@@ -497,9 +577,9 @@ static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool co
         tile_rows(c, F, Rtot, ntiles, trow);
         double jb = 4.0 * gba + gba / 8.0 + 4.0 * ntiles;
         for (auto &Q : hq) jb += (double)Q.R * (8.0 + 8.0 * Q.ne + 4.0 * Q.j);
-        launch(c, "k_wjoin", jb, k_wjoin, (uint32_t)ntiles, WT, (const WQ *)d_q, (const uint32_t *)rowq, (const WEdge *)d_e,
-               (const uint32_t *)g->ci, (const uint64_t *)F, (const uint64_t *)trow, gba, (const uint32_t *)loc, bitmap,
-               tcnt);
+        launch(c, "k_wjoin", jb, k_wjoin, (uint32_t)((ntiles + WJ_TILES - 1) / WJ_TILES), WT, (const WQ *)d_q,
+               (const uint32_t *)rowq, (const WEdge *)d_e, (const uint32_t *)g->ci, (const uint64_t *)F,
+               (const uint64_t *)trow, ntiles, gba, (const uint32_t *)loc, bitmap, tcnt);
         exclusive_scan(c, tcnt, ntiles, toff, s, scal + 1);
         launch(c, "k_wsurv", 48.0 * nq, k_wsurv, wblocks(nq), WT, (const WQ *)d_q, nq, (const uint64_t *)F,
                (const uint64_t *)bitmap, (const uint64_t *)toff, gba, sb);

@@ -112,71 +112,6 @@ __global__ __launch_bounds__(WT) void k_wlocate(const WQ *qs, uint32_t nq, const
     loc[Q.locbase + (uint64_t)(2 * Q.ne + 1) * Q.R + i] = be;
 }
 
-// A tile's rows usually belong to one query: then that query's descriptor
-// and its rows' first-edge starts are staged in LDS once, and every slot
-// reads them there instead of through a query search and dependent global
-// loads.
-struct WTile {
-    uint64_t r_lo, r_hi, nr;
-    bool staged;  // F (and, for one query, the starts) of its rows in LDS
-    bool one;     // all rows in one query
-};
-
-__device__ __forceinline__ WTile stage_wtile(const WQ *qs, const uint32_t *rowq, const uint64_t *F,
-                                             const uint64_t *tile_row, const uint32_t *loc, uint64_t tile,
-                                             uint64_t *s_F, uint32_t *s_st, WQ *s_Q, uint32_t *s_q) {
-    WTile t;
-    t.r_lo = tile_row[tile];
-    t.r_hi = tile_row[tile + 1];
-    t.nr = t.r_hi - t.r_lo + 1;
-    t.staged = t.nr <= WT;
-    if (threadIdx.x == 0) {
-        s_q[0] = rowq[t.r_lo];
-        s_q[1] = rowq[t.r_hi];
-    }
-    if (t.staged && threadIdx.x < t.nr) s_F[threadIdx.x] = F[t.r_lo + threadIdx.x];
-    __syncthreads();
-    t.one = s_q[0] == s_q[1];
-    if (t.one) {
-        const WQ &Q = qs[s_q[0]];
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(&Q);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(s_Q);
-        for (uint32_t w = threadIdx.x; w < sizeof(WQ) / 4; w += WT) dst[w] = src[w];
-        if (t.staged && threadIdx.x < t.nr)
-            s_st[threadIdx.x] = loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + (t.r_lo + threadIdx.x - Q.rbase)];
-    }
-    __syncthreads();
-    return t;
-}
-
-// global row r holding slot p, F[r], and the query of r
-__device__ __forceinline__ void wfind(const uint32_t *rowq, const uint64_t *F, const WTile &t, const uint64_t *s_F,
-                                      const uint32_t *s_q, uint64_t p, uint64_t *r, uint64_t *Fr, uint32_t *lr,
-                                      uint32_t *q) {
-    if (t.staged) {
-        uint32_t lo = 0, hi = (uint32_t)(t.nr - 1);
-        while (lo < hi) {
-            uint32_t mid = (lo + hi + 1) >> 1;
-            if (s_F[mid] <= p) lo = mid;
-            else hi = mid - 1;
-        }
-        *r = t.r_lo + lo;
-        *Fr = s_F[lo];
-        *lr = lo;
-    } else {
-        uint64_t lo = t.r_lo, hi = t.r_hi;
-        while (lo < hi) {
-            uint64_t mid = lo + (hi - lo + 1) / 2;
-            if (F[mid] <= p) lo = mid;
-            else hi = mid - 1;
-        }
-        *r = lo;
-        *Fr = F[lo];
-        *lr = 0;
-    }
-    *q = t.one ? s_q[0] : rowq[*r];
-}
-
 // The join of WJ_TILES consecutive 256-slot tiles per workgroup: each
 // thread takes one slot of each tile and issues their loads together, and
 // the set-up (rows staged in LDS, the query's descriptor) is paid once per
@@ -363,87 +298,150 @@ __global__ __launch_bounds__(WT) void k_wsurv(const WQ *qs, uint32_t nq, const u
 // contiguous block when k is at most this
 constexpr uint32_t WLINK_STAGE_K = 16;
 
-__global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, const uint32_t *rowq, const uint32_t *ci_all, const uint64_t *F,
-                                             const uint64_t *tile_row, const uint32_t *loc, const uint64_t *bitmap,
-                                             const uint64_t *tile_off, uint64_t *hv) {
-    __shared__ uint64_t s_F[WT];
-    __shared__ uint32_t s_st[WT];
+// (m_i, x) of every survivor into its query's next table, or, at a query's
+// last level, the row in query-vertex order and its hash.  A workgroup
+// takes the same WJ_TILES consecutive tiles as the join: their kept slots
+// are listed in slot order in LDS first, so that the waves that gather,
+// write and hash are dense, and survivor q of the list is survivor
+// tile_off[t0] + q of the step.  The row of a survivor's slot is found by a
+// binary search over the group's rows in LDS (survivors are often few, so
+// a map of every slot would not pay).
+__global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, const uint32_t *rowq, const uint32_t *ci_all,
+                                             const uint64_t *F, const uint64_t *tile_row, uint64_t ntiles,
+                                             const uint32_t *loc, const uint64_t *bitmap, const uint64_t *tile_off,
+                                             uint64_t *hv) {
+    __shared__ uint64_t s_F[WJS];
+    __shared__ uint32_t s_st[WJS];
     __shared__ WQ s_Q;
     __shared__ uint32_t s_q[2];
     __shared__ uint32_t s_rows[WT * WLINK_STAGE_K];
-    __shared__ uint16_t s_list[WT];  // the tile's kept slots, compacted
-    const uint64_t tile = blockIdx.x;
-    if (tile_off[tile + 1] == tile_off[tile]) return;  // no survivor in the tile (uniform)
-    const uint64_t p0 = tile * WT;
-    const uint32_t w = threadIdx.x >> 6, lane = lane_id();
-    const uint64_t *words = bitmap + tile * (WT / 64);
-    {
-        // the kept slots in slot order, so that the waves below are dense
-        const uint64_t word = words[w];
-        uint32_t before = 0;
-        for (uint32_t q = 0; q < w; q++) before += (uint32_t)__popcll(words[q]);
-        if ((word >> lane) & 1ull) s_list[before + rank_below(word)] = (uint16_t)threadIdx.x;
+    __shared__ uint16_t s_list[WJS];          // the group's kept slots, in slot order
+    __shared__ uint32_t s_pre[WJS / 64 + 1];  // kept slots before each bitmap word
+    const uint64_t t0 = (uint64_t)blockIdx.x * WJ_TILES;
+    const uint64_t t1 = t0 + WJ_TILES < ntiles ? t0 + WJ_TILES : ntiles;
+    const uint64_t gbase = tile_off[t0];
+    if (tile_off[t1] == gbase) return;  // no survivor in the group (uniform)
+    const uint64_t p0 = t0 * WT;
+    const uint32_t nwords = (uint32_t)(t1 - t0) * (WT / 64);
+    const uint64_t *words = bitmap + p0 / 64;
+    const uint64_t r_lo = tile_row[t0], r_hi = tile_row[t1];
+    const uint64_t nr = r_hi - r_lo + 1;
+    const bool staged = nr <= WJS;
+    if (threadIdx.x == 0) {
+        s_q[0] = rowq[r_lo];
+        s_q[1] = rowq[r_hi];
+        uint32_t run = 0;
+        for (uint32_t q = 0; q < WJS / 64; q++) {
+            s_pre[q] = run;
+            if (q < nwords) run += (uint32_t)__popcll(words[q]);
+        }
+        s_pre[WJS / 64] = run;
     }
-    const WTile t = stage_wtile(qs, rowq, F, tile_row, loc, tile, s_F, s_st, &s_Q, s_q);  // (its barrier publishes s_list)
-    const uint32_t n = (uint32_t)(tile_off[tile + 1] - tile_off[tile]);
-    const uint32_t local = threadIdx.x;  // survivor `local` of the tile
-    const uint64_t gpos = tile_off[tile] + local;
-    const bool stage = t.one && s_Q.final_level && s_Q.out && s_Q.k <= WLINK_STAGE_K;
-    if (local < n) {
-        const uint64_t p = p0 + s_list[local];
-        uint64_t r, Fr;
-        uint32_t lr, qi;
-        wfind(rowq, F, t, s_F, s_q, p, &r, &Fr, &lr, &qi);
-        const WQ &Q = t.one ? s_Q : qs[qi];
-        const uint64_t i = r - Q.rbase;
-        const uint64_t pos = gpos - Q.sbase;
-        if (pos < Q.S) {  // always, when the survivor ranges are consistent
-            const uint32_t st0 =
-                (t.one && t.staged) ? s_st[lr] : loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + i];
-            const uint32_t x = ci_all[st0 + (uint32_t)(p - Fr)];
-            // the row's values are loaded four at a time (independent
-            // loads), not one dependent round trip per column
-            if (!Q.final_level) {
-                for (uint32_t c = 0; c < Q.j; c += 4) {
-                    uint32_t m[4];
+    if (staged)
+        for (uint32_t r = threadIdx.x; r < nr; r += WT) s_F[r] = F[r_lo + r];
+    __syncthreads();
+    const bool one = s_q[0] == s_q[1];
+    if (one) {
+        const WQ &Q = qs[s_q[0]];
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&Q);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(&s_Q);
+        for (uint32_t w = threadIdx.x; w < sizeof(WQ) / 4; w += WT) dst[w] = src[w];
+        if (staged)
+            for (uint32_t r = threadIdx.x; r < nr; r += WT)
+                s_st[r] = loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + (r_lo + r - Q.rbase)];
+    }
+    {
+        const uint32_t w = threadIdx.x >> 6, lane = lane_id();
 #pragma unroll
-                    for (uint32_t q = 0; q < 4; q++) m[q] = c + q < Q.j ? Q.M[(uint64_t)(c + q) * Q.R + i] : 0u;
-#pragma unroll
-                    for (uint32_t q = 0; q < 4; q++)
-                        if (c + q < Q.j) Q.Mn[(uint64_t)(c + q) * Q.S + pos] = m[q];
-                }
-                Q.Mn[(uint64_t)Q.j * Q.S + pos] = x;
-            } else {
-                uint64_t f = 14695981039346656037ull;
-                for (uint32_t u0 = 0; u0 < Q.k; u0 += 4) {
-                    uint32_t val[4];
-#pragma unroll
-                    for (uint32_t q = 0; q < 4; q++) {
-                        const uint32_t c = u0 + q < Q.k ? Q.qcol[u0 + q] : Q.j;
-                        val[q] = c < Q.j ? Q.M[(uint64_t)c * Q.R + i] : x;
-                    }
-#pragma unroll
-                    for (uint32_t q = 0; q < 4; q++) {
-                        const uint32_t u = u0 + q;
-                        if (u >= Q.k) break;
-                        if (stage) s_rows[local * Q.k + u] = val[q];
-                        else if (Q.out) Q.out[pos * Q.k + u] = val[q];
-                        f = fnv_word(f, val[q]);
-                    }
-                }
-                hv[gpos] = mix64(f);
-            }
+        for (uint32_t k = 0; k < WJ_TILES; k++) {
+            const uint32_t wi = k * (WT / 64) + w;
+            const uint64_t word = wi < nwords ? words[wi] : 0ull;
+            if ((word >> lane) & 1ull) s_list[s_pre[wi] + rank_below(word)] = (uint16_t)(k * WT + threadIdx.x);
         }
     }
-    if (stage) {
-        // the tile's rows are one contiguous block of the query's result
-        __syncthreads();
-        const uint64_t first = tile_off[tile] - s_Q.sbase;
-        uint64_t end = tile_off[tile + 1] - s_Q.sbase;
-        if (end > s_Q.S) end = s_Q.S;
-        const uint32_t nw = first < end ? (uint32_t)(end - first) * s_Q.k : 0u;
-        uint32_t *dst = s_Q.out + first * s_Q.k;
-        for (uint32_t v = threadIdx.x; v < nw; v += WT) dst[v] = s_rows[v];
+    __syncthreads();
+    // the same count in every lane (the loop holds barriers)
+    const uint32_t n = __builtin_amdgcn_readfirstlane(s_pre[WJS / 64]);
+    const bool stage = one && s_Q.final_level && s_Q.out && s_Q.k <= WLINK_STAGE_K;
+    for (uint32_t q0 = 0; q0 < n; q0 += WT) {
+        const uint32_t local = threadIdx.x;  // survivor q0 + local of the group
+        const uint32_t q = q0 + local;
+        const uint64_t gpos = gbase + q;
+        if (q < n) {
+            const uint64_t p = p0 + s_list[q];
+            uint64_t r, Fr;
+            uint32_t lr = 0;
+            if (staged) {
+                uint32_t lo = 0, hi = (uint32_t)(nr - 1);
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (s_F[mid] <= p) lo = mid;
+                    else hi = mid - 1;
+                }
+                lr = lo;
+                r = r_lo + lo;
+                Fr = s_F[lo];
+            } else {
+                uint64_t lo = r_lo, hi = r_hi;
+                while (lo < hi) {
+                    const uint64_t mid = lo + (hi - lo + 1) / 2;
+                    if (F[mid] <= p) lo = mid;
+                    else hi = mid - 1;
+                }
+                r = lo;
+                Fr = F[lo];
+            }
+            const WQ &Q = one ? s_Q : qs[rowq[r]];
+            const uint64_t i = r - Q.rbase;
+            const uint64_t pos = gpos - Q.sbase;
+            if (pos < Q.S) {  // always, when the survivor ranges are consistent
+                const uint32_t st0 = (one && staged) ? s_st[lr] : loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + i];
+                const uint32_t x = ci_all[st0 + (uint32_t)(p - Fr)];
+                // the row's values are loaded four at a time (independent
+                // loads), not one dependent round trip per column
+                if (!Q.final_level) {
+                    for (uint32_t c = 0; c < Q.j; c += 4) {
+                        uint32_t m[4];
+#pragma unroll
+                        for (uint32_t k4 = 0; k4 < 4; k4++) m[k4] = c + k4 < Q.j ? Q.M[(uint64_t)(c + k4) * Q.R + i] : 0u;
+#pragma unroll
+                        for (uint32_t k4 = 0; k4 < 4; k4++)
+                            if (c + k4 < Q.j) Q.Mn[(uint64_t)(c + k4) * Q.S + pos] = m[k4];
+                    }
+                    Q.Mn[(uint64_t)Q.j * Q.S + pos] = x;
+                } else {
+                    uint64_t f = 14695981039346656037ull;
+                    for (uint32_t u0 = 0; u0 < Q.k; u0 += 4) {
+                        uint32_t val[4];
+#pragma unroll
+                        for (uint32_t k4 = 0; k4 < 4; k4++) {
+                            const uint32_t c = u0 + k4 < Q.k ? Q.qcol[u0 + k4] : Q.j;
+                            val[k4] = c < Q.j ? Q.M[(uint64_t)c * Q.R + i] : x;
+                        }
+#pragma unroll
+                        for (uint32_t k4 = 0; k4 < 4; k4++) {
+                            const uint32_t u = u0 + k4;
+                            if (u >= Q.k) break;
+                            if (stage) s_rows[local * Q.k + u] = val[k4];
+                            else if (Q.out) Q.out[pos * Q.k + u] = val[k4];
+                            f = fnv_word(f, val[k4]);
+                        }
+                    }
+                    hv[gpos] = mix64(f);
+                }
+            }
+        }
+        if (stage) {
+            // the round's rows are one contiguous block of the query's result
+            __syncthreads();
+            const uint64_t first = gbase + q0 - s_Q.sbase;
+            uint64_t end = gbase + (q0 + WT < n ? q0 + WT : n) - s_Q.sbase;
+            if (end > s_Q.S) end = s_Q.S;
+            const uint32_t nw = first < end ? (uint32_t)(end - first) * s_Q.k : 0u;
+            uint32_t *dst = s_Q.out + first * s_Q.k;
+            for (uint32_t v = threadIdx.x; v < nw; v += WT) dst[v] = s_rows[v];
+            __syncthreads();
+        }
     }
 }
 
@@ -624,10 +622,9 @@ static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool co
         }
         uint64_t *hv = any_final ? s.get<uint64_t>(Stot, "wide row hashes") : nullptr;
         GSI_HIP(hipMemcpyAsync(d_q, hq.data(), sizeof(WQ) * nq, hipMemcpyHostToDevice, c->stream));
-        launch(c, "k_wlink", kb, k_wlink, (uint32_t)ntiles, WT, (const WQ *)d_q, (const uint32_t *)rowq,
-               (const uint32_t *)g->ci,
-               (const uint64_t *)F, (const uint64_t *)trow, (const uint32_t *)loc, (const uint64_t *)bitmap,
-               (const uint64_t *)toff, hv);
+        launch(c, "k_wlink", kb, k_wlink, (uint32_t)((ntiles + WJ_TILES - 1) / WJ_TILES), WT, (const WQ *)d_q,
+               (const uint32_t *)rowq, (const uint32_t *)g->ci, (const uint64_t *)F, (const uint64_t *)trow, ntiles,
+               (const uint32_t *)loc, (const uint64_t *)bitmap, (const uint64_t *)toff, hv);
         std::vector<uint64_t> part;
         if (any_final) {
             const uint64_t ni = item_q.size();

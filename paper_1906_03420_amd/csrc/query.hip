@@ -288,19 +288,19 @@ __global__ __launch_bounds__(QT) void k_filter_multi(const uint32_t *sig, uint32
         for (uint32_t e = threadIdx.x; e < nm; e += QT) {
             const uint32_t off = s_v[e], gi = s_g[e];
             const uint64_t v = v0 + off;
-            uint32_t wv[GSI_SIG_WORDS];
+            // complemented words: a query word's bits missing from the
+            // vertex's are then (~w & q), one and-or per word, with no
+            // per-word branch or mask arithmetic; words no query vertex of
+            // the pass uses are zero in every query signature
+            uint32_t nw[GSI_SIG_WORDS];
 #pragma unroll
-            for (int i = 1; i < GSI_SIG_WORDS; i++) wv[i] = ((need >> i) & 1u) ? sig[(uint64_t)i * n + v] : 0u;
+            for (int i = 1; i < GSI_SIG_WORDS; i++) nw[i] = ((need >> i) & 1u) ? ~sig[(uint64_t)i * n + v] : 0u;
             const uint32_t ue = s_gbeg[gi + 1];
             for (uint32_t u = s_gbeg[gi]; u < ue; u++) {
-                bool good = true;
+                uint32_t miss = 0;
 #pragma unroll
-                for (int i = 1; i < GSI_SIG_WORDS; i++) {
-                    if (!((need >> i) & 1u)) continue;
-                    const uint32_t qw = s_q[u][i];
-                    good = good && ((wv[i] & qw) == qw);
-                }
-                if (good) atomicOr(&s_res[u][off >> 6], 1ull << (off & 63));
+                for (int i = 1; i < GSI_SIG_WORDS; i++) miss |= nw[i] & s_q[u][i];
+                if (miss == 0) atomicOr(&s_res[u][off >> 6], 1ull << (off & 63));
             }
         }
         __syncthreads();

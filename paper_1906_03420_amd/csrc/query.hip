@@ -117,47 +117,53 @@ static void query_signatures(const HostQuery &q, FilterArgs &fa, bool homo = fal
     }
 }
 
-// One tile of 256 data vertices against the query vertices of `fa`: a lane
-// owns one data vertex and reads its label and every signature word some
-// query vertex uses, all in one batch of loads (a wave reads word i of 64
-// consecutive vertices in one 256-byte access; since 32 vertices share a
-// 128-byte line, skipping the words of vertices whose label matches no query
-// vertex would save no traffic, only add a second round trip).  The wave's
-// ballot of "v in C(u)" is the bitset word of its 64 vertices; lane u stores
-// the word of query vertex u, so one store instruction writes them all.
-__device__ __forceinline__ void filter_tile(const uint32_t *sig, uint32_t n, uint64_t nwords, const FilterArgs &fa,
-                                            uint32_t need, uint64_t tile, uint64_t *bits) {
-    const uint64_t v = tile * QT + threadIdx.x;
-    const bool valid = v < n;
-    uint32_t wv[GSI_SIG_WORDS];
-    wv[0] = valid ? sig[v] : NONE32;
-#pragma unroll
-    for (int i = 1; i < GSI_SIG_WORDS; i++) wv[i] = (((need >> i) & 1u) && valid) ? sig[(uint64_t)i * n + v] : NONE32;
-    const uint32_t K = fa.k;
-    uint32_t ok = 0;
-    for (uint32_t u = 0; u < K; u++) {
-        bool good = valid && wv[0] == fa.q[u][0];
-#pragma unroll
-        for (int i = 1; i < GSI_SIG_WORDS; i++) {
-            const uint32_t qw = need ? fa.q[u][i] : 0u;
-            good = good && ((wv[i] & qw) == qw);
-        }
-        ok |= good ? (1u << u) : 0u;
-    }
-    const uint32_t lane = lane_id();
-    uint64_t mine = 0;
-    for (uint32_t u = 0; u < K; u++) {
-        const uint64_t m = __ballot((ok >> u) & 1u);
-        if (lane == u) mine = m;
-    }
-    const uint64_t wave_first = tile * QT + (threadIdx.x & ~63u);
-    if (lane < K && wave_first < n) bits[(uint64_t)fa.dst[lane] * nwords + (wave_first >> 6)] = mine;
-}
+// The filter for one query.  A workgroup takes FILTER_TILES tiles of 256
+// data vertices; a lane owns one data vertex of each and reads their labels
+// and every signature word some query vertex uses, all in one batch of
+// loads (a wave reads word i of 64 consecutive vertices in one 256-byte
+// access; since 32 vertices share a 128-byte line, skipping the words of
+// vertices whose label matches no query vertex would save no traffic, only
+// add a second round trip).  The words are kept complemented, so the bits
+// of query word q that the vertex lacks are (~w & q), one and-or per word.
+// The wave's ballot of "v in C(u)" is the bitset word of its 64 vertices;
+// lane u stores the word of query vertex u, so one store instruction
+// writes them all.
+constexpr uint32_t FILTER_TILES = 4;
 
-// the filter for one query: one tile per workgroup
 __global__ __launch_bounds__(QT) void k_filter(const uint32_t *sig, uint32_t n, uint64_t nwords, FilterArgs fa,
                                               uint64_t *bits) {
-    filter_tile(sig, n, nwords, fa, fa.label_only ? 0u : fa.word_mask, blockIdx.x, bits);
+    const uint32_t need = fa.label_only ? 0u : fa.word_mask;
+    const uint32_t K = fa.k;
+    const uint32_t lane = lane_id();
+    uint32_t w0[FILTER_TILES], nw[FILTER_TILES][GSI_SIG_WORDS];
+#pragma unroll
+    for (uint32_t r = 0; r < FILTER_TILES; r++) {
+        const uint64_t v = ((uint64_t)blockIdx.x * FILTER_TILES + r) * QT + threadIdx.x;
+        const bool valid = v < n;
+        w0[r] = valid ? sig[v] : NONE32;
+#pragma unroll
+        for (int i = 1; i < GSI_SIG_WORDS; i++)
+            nw[r][i] = (((need >> i) & 1u) && valid) ? ~sig[(uint64_t)i * n + v] : 0u;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < FILTER_TILES; r++) {
+        const uint64_t tile = (uint64_t)blockIdx.x * FILTER_TILES + r;
+        const bool valid = tile * QT + threadIdx.x < n;
+        uint32_t ok = 0;
+        for (uint32_t u = 0; u < K; u++) {
+            uint32_t miss = 0;
+#pragma unroll
+            for (int i = 1; i < GSI_SIG_WORDS; i++) miss |= nw[r][i] & fa.q[u][i];
+            ok |= (valid && w0[r] == fa.q[u][0] && miss == 0) ? (1u << u) : 0u;
+        }
+        uint64_t mine = 0;
+        for (uint32_t u = 0; u < K; u++) {
+            const uint64_t m = __ballot((ok >> u) & 1u);
+            if (lane == u) mine = m;
+        }
+        const uint64_t wave_first = tile * QT + (threadIdx.x & ~63u);
+        if (lane < K && wave_first < n) bits[(uint64_t)fa.dst[lane] * nwords + (wave_first >> 6)] = mine;
+    }
 }
 
 // counts[r] = set bits of bitset row r (one 1024-thread workgroup per row);
@@ -194,7 +200,8 @@ static void launch_filter(gsi_ctx *c, gsi_graph *g, const FilterArgs &fa, uint64
     const uint32_t nb = nblocks(g->n);
     const uint32_t need = fa.label_only ? 0u : fa.word_mask;
     double bytes = 4.0 * g->n * (1 + __builtin_popcount(need)) + (double)fa.k * nwords * 8;
-    launch(c, "k_filter", bytes, k_filter, nb, QT, (const uint32_t *)g->sig, g->n, nwords, fa, bits);
+    const uint32_t nfb = (nb + FILTER_TILES - 1) / FILTER_TILES;
+    launch(c, "k_filter", bytes, k_filter, nfb, QT, (const uint32_t *)g->sig, g->n, nwords, fa, bits);
     launch(c, "k_filter_counts", 8.0 * fa.k * nwords, k_bit_counts, fa.k, 1024, (const uint64_t *)bits, nwords,
            counts, runs);
 }

@@ -136,6 +136,24 @@ gsi_status gsi_graph_load_device(gsi_ctx *ctx, uint32_t n_vertices, const uint32
                                  const uint32_t *edge_labels, uint32_t flags, gsi_graph **out);
 gsi_status gsi_graph_free(gsi_graph *g);
 
+/*
+ * Multi-labelled data graph (Sec. VII-B).  Vertex v carries the label set
+ * labels[label_offsets[v] .. label_offsets[v+1]) (any order; repeats are
+ * merged; label_offsets has n_vertices + 1 entries, starting at 0); a vertex
+ * pair may be joined by several edges with distinct labels, one entry per
+ * label (the multigraph form of a multi-labelled edge).  The structures are
+ * those of gsi_graph_load: PCSR per edge label (each partition stays simple),
+ * and signatures in which word 0 holds every vertex label hashed to one of
+ * 32 bits and each neighbour contributes one (edge label, vertex label) pair
+ * per label it carries.  Host memory.  Queries on it: gsi_query_run_multi (or
+ * gsi_query_run, read as singleton label sets); the batched path and the
+ * server take single-label graphs only.  Errors as gsi_graph_load, with
+ * GSI_E_INVALID for the same (pair, label) given twice.
+ */
+gsi_status gsi_graph_load_multi(gsi_ctx *ctx, uint32_t n_vertices, const uint64_t *label_offsets,
+                                const uint32_t *labels, uint64_t n_edges, const uint32_t *src, const uint32_t *dst,
+                                const uint32_t *edge_labels, uint32_t flags, gsi_graph **out);
+
 typedef struct {
     uint32_t n_vertices;
     uint64_t n_edges;
@@ -178,6 +196,20 @@ gsi_status gsi_graph_copy_pcsr(const gsi_graph *g, uint32_t label, uint32_t *hos
                                       the write pass repeats the join */
 #define GSI_ABL_NO_STAGING 0x400u  /* last-level rows written straight from each
                                       thread (no LDS staging) */
+#define GSI_ABL_NAIVE_SETOPS 0x800u  /* one kernel per set operation (subtraction,
+                                      C(u), each further linking edge) over a
+                                      vertex-id buffer in GBA, instead of the
+                                      fused, LDS-staged join (Sec. V) */
+#define GSI_ABL_ROW_PER_WAVE 0x1000u /* one wave per row of M scans the row's list
+                                      (Algorithm 3 without load balance) instead
+                                      of equal tiles over the |GBA| slots */
+#define GSI_ABL_FOUR_LAYER 0x2000u   /* the 4-layer load balance of Sec. VI-A
+                                      (1024-thread workgroups; W1 = 4096,
+                                      W2 = 1024, W3 = 256) instead of equal tiles */
+#define GSI_ABL_DUP_REMOVAL 0x4000u  /* with GSI_ABL_ROW_PER_WAVE or
+                                      GSI_ABL_FOUR_LAYER: waves of a workgroup
+                                      whose rows scan the same list share its
+                                      reads through LDS (Algorithm 5, Sec. VI-B) */
 #define GSI_HOMOMORPHISM 0x40u     /* homomorphism semantics (Sec. VII-A): query
                                       vertices may share a data vertex; the join
                                       drops the subtraction of m_i and the filter
@@ -238,6 +270,25 @@ typedef struct {
 gsi_status gsi_query_run(gsi_graph *g, uint32_t k, const uint32_t *q_vertex_labels, uint32_t q_edges,
                          const uint32_t *q_src, const uint32_t *q_dst, const uint32_t *q_edge_labels,
                          const gsi_query_options *opts, gsi_result **out);
+
+/*
+ * Runs a multi-labelled query (Sec. VII-B): f is an embedding iff it is
+ * injective, the label set of every query vertex u is contained in that of
+ * f(u), and the labels of the query edges between every vertex pair are
+ * among the labels of the data edges between their images.  Query vertex u
+ * carries labels[label_offsets[u] .. label_offsets[u+1]) (label_offsets has
+ * k + 1 entries, starting at 0; at most 256 labels in all); a query pair may
+ * appear in several edges with distinct labels.  The path is gsi_query_run's
+ * with the filter testing containment: the signature test, then each
+ * candidate's label set checked exactly; the join then intersects the
+ * partitions of every labelled edge to a placed vertex, so a pair with two
+ * labels needs both.  On a single-label graph a vertex set of two or more
+ * labels, or a pair with two labels, has no match (0 rows).  Options, result
+ * and errors as gsi_query_run.
+ */
+gsi_status gsi_query_run_multi(gsi_graph *g, uint32_t k, const uint32_t *label_offsets, const uint32_t *labels,
+                               uint32_t q_edges, const uint32_t *q_src, const uint32_t *q_dst,
+                               const uint32_t *q_edge_labels, const gsi_query_options *opts, gsi_result **out);
 
 /* Runs only the signature filter (step 1 above) and copies C(u) bitsets
  * (k x ceil(n/64) uint64, bit v%64 of word v/64 set iff v in C(u)) and

@@ -8,6 +8,9 @@ library: the two meet only on inputs made by ``workloads``.
 Contents
   match.c   plain backtracking enumeration of all embeddings (Sec. II-A,
             Definitions 1-3) plus the order-independent result digest.
+  multi.c   the same enumeration under multi-labels (Sec. VII-B): label sets
+            on vertices, several labelled edges per vertex pair, containment
+            instead of equality; written separately from match.c.
   spec.py   plain numpy/Python statements of the intermediate steps of the
             paper's method: vertex signatures and the signature filter
             (Sec. III-A), the PCSR layout (Sec. IV, Definition 4, Algorithm 1),
@@ -26,6 +29,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "match.c")
+_SRCS = [_SRC, os.path.join(_HERE, "multi.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -42,9 +46,9 @@ class OracleResultC(ctypes.Structure):
 
 def build(force: bool = False) -> str:
     """Compile match.c with gcc (host code only)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O3", "-fPIC", "-shared", "-pthread", "-o", tmp] + _SRCS)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -73,6 +77,15 @@ def _load():
         lib.oracle_match.restype = ctypes.c_int
         lib.oracle_free.argtypes = [ctypes.c_void_p]
         lib.oracle_free.restype = None
+        lib.oracle_mgraph_build.argtypes = [ctypes.c_uint32, U64P, U32P, ctypes.c_uint64, U32P, U32P, U32P,
+                                            ctypes.POINTER(ctypes.c_int)]
+        lib.oracle_mgraph_build.restype = ctypes.c_void_p
+        lib.oracle_mgraph_free.argtypes = [ctypes.c_void_p]
+        lib.oracle_mgraph_free.restype = None
+        lib.oracle_mmatch.argtypes = [ctypes.c_void_p, ctypes.c_uint32, U32P, U32P, ctypes.c_uint32, U32P, U32P,
+                                      U32P, ctypes.c_uint32, ctypes.c_int, ctypes.c_uint64,
+                                      ctypes.POINTER(OracleResultC)]
+        lib.oracle_mmatch.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -161,6 +174,61 @@ class OracleGraph:
 
 def match(g, q, threads: int = 1, tuples: bool = True, **kw) -> MatchResult:
     og = OracleGraph(g)
+    try:
+        return og.match(q, threads=threads, tuples=tuples, **kw)
+    finally:
+        og.close()
+
+
+class OracleMultiGraph:
+    """A multi-labelled data graph (Sec. VII-B) held by the C oracle: vertex
+    label sets vlab[voff[v]:voff[v+1]], one edge entry per label of a pair."""
+
+    def __init__(self, g):
+        lib = _load()
+        self.n = g.n
+        voff = np.ascontiguousarray(g.voff, dtype=np.uint64)
+        keep = [_p(g.vlab), _p(g.src), _p(g.dst), _p(g.elabel)]
+        st = ctypes.c_int(0)
+        self._h = lib.oracle_mgraph_build(g.n, voff.ctypes.data_as(U64P), keep[0][1], g.m, keep[1][1], keep[2][1],
+                                          keep[3][1], ctypes.byref(st))
+        if not self._h:
+            raise ValueError("oracle rejected the multi-labelled graph (status %d)" % st.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().oracle_mgraph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def match(self, q, threads: int = 1, tuples: bool = True, max_count: int = 0) -> MatchResult:
+        """All embeddings of the multi-labelled query q: injective, each query
+        vertex's labels contained in its image's, each query pair's edge
+        labels contained in its image pair's."""
+        lib = _load()
+        qo, qop = _p(q.qoff)
+        ql, qlp = _p(q.qlab)
+        qs, qsp = _p(q.src)
+        qd, qdp = _p(q.dst)
+        qe, qep = _p(q.elabel)
+        r = OracleResultC()
+        lib.oracle_mmatch(self._h, q.k, qop, qlp, qs.shape[0], qsp, qdp, qep, threads, 1 if tuples else 0,
+                          max_count, ctypes.byref(r))
+        t = None
+        if r.tuples:
+            if r.status == OR_OK:
+                buf = (ctypes.c_uint32 * (r.count * q.k)).from_address(r.tuples)
+                t = np.frombuffer(buf, dtype=np.uint32).reshape(r.count, q.k).copy()
+            lib.oracle_free(r.tuples)
+        elif tuples and r.status == OR_OK:
+            t = np.zeros((0, q.k), np.uint32)
+        return MatchResult(int(r.status), int(r.count), (int(r.dsum), int(r.dxor)), 0, t)
+
+
+def match_multi(g, q, threads: int = 1, tuples: bool = True, **kw) -> MatchResult:
+    og = OracleMultiGraph(g)
     try:
         return og.match(q, threads=threads, tuples=tuples, **kw)
     finally:

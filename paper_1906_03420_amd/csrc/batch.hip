@@ -455,6 +455,7 @@ gsi_status gsi_batch_run(gsi_graph *g, uint32_t nq, const gsi_query_desc *qs, co
                          gsi_batch **out) {
     GSI_TRY({
         if (!g || !out || (nq && !qs)) fail(GSI_E_INVALID, "null argument");
+        if (g->multi) fail(GSI_E_INVALID, "multi-labelled graphs run through gsi_query_run_multi only");
         *out = nullptr;
         gsi_batch_schedule sc = opt ? opt->schedule : gsi_batch_schedule{0, 0};
         if (sc.threads == 0) sc = g->tuned;
@@ -518,6 +519,7 @@ gsi_status gsi_batch_tune(gsi_graph *g, uint32_t nq, const gsi_query_desc *qs, u
                           gsi_batch_schedule *out, double *out_ms) {
     GSI_TRY({
         if (!g || !out || (nq && !qs)) fail(GSI_E_INVALID, "null argument");
+        if (g->multi) fail(GSI_E_INVALID, "multi-labelled graphs run through gsi_query_run_multi only");
         gsi_ctx *c = g->ctx;
         Busy busy(c);
         GSI_HIP(hipSetDevice(c->device));

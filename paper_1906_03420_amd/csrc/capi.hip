@@ -1,5 +1,8 @@
 // C ABI entry points, error reporting, the device arena and kernel timing.
+#include <algorithm>
 #include <cstdarg>
+#include <set>
+#include <vector>
 #include <cstdio>
 #include <cstring>
 
@@ -318,6 +321,8 @@ static gsi_status load_common(gsi_ctx *c, uint32_t n, const uint32_t *vl, uint64
             }
         } catch (...) {
             (void)hipStreamSynchronize(c->stream);
+            c->arena.release(g->vl_off);
+            c->arena.release(g->vl_lab);
             c->arena.release(g->sig);
             c->arena.release(g->gl);
             c->arena.release(g->ci);
@@ -342,6 +347,72 @@ gsi_status gsi_graph_load_device(gsi_ctx *c, uint32_t n, const uint32_t *vl, uin
     return load_common(c, n, vl, m, s, d, l, flags, out, true);
 }
 
+gsi_status gsi_graph_load_multi(gsi_ctx *c, uint32_t n, const uint64_t *off, const uint32_t *lab, uint64_t m,
+                                const uint32_t *s, const uint32_t *d, const uint32_t *l, uint32_t flags,
+                                gsi_graph **out) {
+    GSI_TRY({
+        REQUIRE(c && out, "null argument");
+        *out = nullptr;
+        REQUIRE(n > 0 && n < 0xFFFFFFFFu, "n_vertices must be in [1, 2^32-2]");
+        REQUIRE(m <= 0x7FFFFFFFull, "at most 2^31-1 edges");
+        REQUIRE(off && (off[n] == 0 || lab) && (m == 0 || (s && d && l)), "null input array");
+        REQUIRE(off[0] == 0 && off[n] < 0xFFFFFFFFull, "label offsets must start at 0 and stay below 2^32-1");
+        REQUIRE((flags & ~(GSI_GRAPH_TEST_FEW_HOME_GROUPS | GSI_GRAPH_KEEP_CR)) == 0, "unknown graph flag");
+        // label sets, each sorted and without repeats, as 32-bit offsets
+        std::vector<uint32_t> hoff(n + 1), hlab;
+        hlab.reserve(off[n]);
+        for (uint32_t v = 0; v < n; v++) {
+            REQUIRE(off[v + 1] >= off[v], "label offsets must not decrease");
+            std::vector<uint32_t> ls(lab + off[v], lab + off[v + 1]);
+            std::sort(ls.begin(), ls.end());
+            ls.erase(std::unique(ls.begin(), ls.end()), ls.end());
+            hoff[v] = (uint32_t)hlab.size();
+            hlab.insert(hlab.end(), ls.begin(), ls.end());
+        }
+        hoff[n] = (uint32_t)hlab.size();
+        Busy busy(c);
+        GSI_HIP(hipSetDevice(c->device));
+        gsi_graph *g = new gsi_graph();
+        g->ctx = c;
+        g->n = n;
+        g->m = m;
+        g->flags = flags;
+        g->multi = true;
+        try {
+            g->vl_off = persist<uint32_t>(c, n + 1ull, "vertex label offsets");
+            g->vl_lab = persist<uint32_t>(c, hlab.size() + 1, "vertex label sets");
+            GSI_HIP(hipMemcpyAsync(g->vl_off, hoff.data(), 4ull * (n + 1), hipMemcpyHostToDevice, c->stream));
+            if (!hlab.empty())
+                GSI_HIP(hipMemcpyAsync(g->vl_lab, hlab.data(), 4ull * hlab.size(), hipMemcpyHostToDevice, c->stream));
+            Scratch sc(c);
+            uint32_t *ds = sc.get<uint32_t>(m, "src");
+            uint32_t *dd = sc.get<uint32_t>(m, "dst");
+            uint32_t *de = sc.get<uint32_t>(m, "edge labels");
+            if (m) {
+                GSI_HIP(hipMemcpyAsync(ds, s, 4ull * m, hipMemcpyHostToDevice, c->stream));
+                GSI_HIP(hipMemcpyAsync(dd, d, 4ull * m, hipMemcpyHostToDevice, c->stream));
+                GSI_HIP(hipMemcpyAsync(de, l, 4ull * m, hipMemcpyHostToDevice, c->stream));
+            }
+            build_graph(g, nullptr, ds, dd, de);
+            sync(c);
+        } catch (...) {
+            (void)hipStreamSynchronize(c->stream);
+            c->arena.release(g->vl_off);
+            c->arena.release(g->vl_lab);
+            c->arena.release(g->sig);
+            c->arena.release(g->gl);
+            c->arena.release(g->ci);
+            c->arena.release(g->cr_vid);
+            c->arena.release(g->cr_start);
+            c->arena.release(g->cr_off);
+            delete g;
+            throw;
+        }
+        c->graphs.insert(g);
+        *out = g;
+    })
+}
+
 gsi_status gsi_graph_free(gsi_graph *g) {
     GSI_TRY({
         if (!g) return GSI_OK;
@@ -349,6 +420,8 @@ gsi_status gsi_graph_free(gsi_graph *g) {
         Busy busy(c);
         GSI_HIP(hipSetDevice(c->device));
         GSI_HIP(hipStreamSynchronize(c->stream));
+        c->arena.release(g->vl_off);
+        c->arena.release(g->vl_lab);
         c->arena.release(g->sig);
         c->arena.release(g->gl);
         c->arena.release(g->ci);
@@ -422,10 +495,56 @@ gsi_status gsi_query_run(gsi_graph *g, uint32_t k, const uint32_t *vl, uint32_t 
         REQUIRE(g && out, "null argument");
         *out = nullptr;
         HostQuery q = validate_query(k, vl, qm, s, d, l);
+        if (g->multi) make_multi(q);
         gsi_ctx *c = g->ctx;
         Busy busy(c);
         GSI_HIP(hipSetDevice(c->device));
         gsi_result *r = run_query(g, q, opt);
+        c->results.insert(r);
+        *out = r;
+    })
+}
+
+gsi_status gsi_query_run_multi(gsi_graph *g, uint32_t k, const uint32_t *off, const uint32_t *lab, uint32_t qm,
+                               const uint32_t *s, const uint32_t *d, const uint32_t *l, const gsi_query_options *opt,
+                               gsi_result **out) {
+    GSI_TRY({
+        REQUIRE(g && out, "null argument");
+        *out = nullptr;
+        HostQuery q = validate_query_multi(k, off, lab, qm, s, d, l);
+        gsi_ctx *c = g->ctx;
+        Busy busy(c);
+        GSI_HIP(hipSetDevice(c->device));
+        gsi_result *r = nullptr;
+        bool single = !g->multi;
+        for (uint32_t u = 0; single && u < k; u++) single = q.vls[u].size() == 1;
+        if (!g->multi && !single) {
+            // one label per data vertex: a query vertex asking two or none
+            // (a pair asking two labels fails the same way below) has no image
+            r = new gsi_result();
+            r->ctx = c;
+            r->k = k;
+            r->count_only = opt && (opt->flags & GSI_COUNT_ONLY);
+            r->stats.k = k;
+        } else {
+            if (!g->multi) {
+                // pairs with two labels cannot match a single-label graph
+                std::set<std::pair<uint32_t, uint32_t>> seen;
+                bool parallel = false;
+                for (uint32_t e = 0; e < q.src.size(); e++)
+                    parallel |= !seen.insert({std::min(q.src[e], q.dst[e]), std::max(q.src[e], q.dst[e])}).second;
+                if (parallel) {
+                    r = new gsi_result();
+                    r->ctx = c;
+                    r->k = k;
+                    r->count_only = opt && (opt->flags & GSI_COUNT_ONLY);
+                    r->stats.k = k;
+                } else {
+                    q.multi = false;
+                }
+            }
+            if (!r) r = run_query(g, q, opt);
+        }
         c->results.insert(r);
         *out = r;
     })
@@ -444,6 +563,7 @@ gsi_status gsi_query_filter(gsi_graph *g, uint32_t k, const uint32_t *vl, uint32
         Scratch sc(c);
         uint64_t *bits = sc.get<uint64_t>(words * k, "candidate bitsets");
         uint32_t *cnt = sc.get<uint32_t>(k, "candidate counts");
+        if (g->multi) make_multi(q);
         run_filter(g, q, bits, cnt);
         GSI_HIP(hipMemcpyAsync(hbits, bits, words * k * 8, hipMemcpyDeviceToHost, c->stream));
         GSI_HIP(hipMemcpyAsync(hcounts, cnt, 4ull * k, hipMemcpyDeviceToHost, c->stream));

@@ -114,6 +114,15 @@ __global__ void k_check_dup(const uint32_t *s, const uint32_t *d, uint64_t nd, u
     if (s[p] == s[p - 1] && d[p] == d[p - 1]) atomicOr(err, (uint32_t)ERR_DUP);
 }
 
+// multi-labelled graphs, after sorting by (label, src, dst): equal
+// neighbours with equal labels are the same labelled edge given twice
+__global__ void k_check_dup_labelled(const uint32_t *s, const uint32_t *d, const uint32_t *l, uint64_t nd,
+                                     uint32_t *err) {
+    uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0 || p >= nd) return;
+    if (s[p] == s[p - 1] && d[p] == d[p - 1] && l[p] == l[p - 1]) atomicOr(err, (uint32_t)ERR_DUP);
+}
+
 // label segment bounds in the (label, src, dst)-sorted entries, and run heads
 __global__ void k_segments(const uint32_t *s, const uint32_t *l, uint64_t nd, uint64_t *seg_lo, uint64_t *seg_hi,
                            uint32_t *head) {
@@ -320,6 +329,34 @@ __global__ void k_sig_labels(const uint32_t *vl, uint32_t n, uint32_t *sig) {
     for (int w = 1; w < GSI_SIG_WORDS; w++) sig[(uint64_t)w * n + v] = 0;
 }
 
+// Multi-labelled vertices (Sec. VII-B): word 0 holds every label of v
+// hashed to one of its 32 bits, so the filter tests containment there and a
+// refinement pass checks the label sets exactly.
+__global__ void k_sig_labels_multi(const uint32_t *off, const uint32_t *lab, uint32_t n, uint32_t *sig) {
+    uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    uint32_t b = 0;
+    for (uint32_t t = off[v]; t < off[v + 1]; t++) b |= label_bit(lab[t]);
+    sig[v] = b;
+#pragma unroll
+    for (int w = 1; w < GSI_SIG_WORDS; w++) sig[(uint64_t)w * n + v] = 0;
+}
+
+// every directed entry (v -> w, l) adds the pair (l, x) for each label x of w
+__global__ void k_sig_pairs_multi(const uint32_t *s, const uint32_t *d, const uint32_t *l, const uint32_t *off,
+                                  const uint32_t *lab, uint64_t nd, uint32_t n, uint32_t *sig) {
+    uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nd) return;
+    const uint32_t w = d[p];
+    for (uint32_t t = off[w]; t < off[w + 1]; t++) {
+        uint32_t g = sig_group(l[p], lab[t]);
+        uint32_t *word = sig + (uint64_t)(1 + g / 16) * n + s[p];
+        uint32_t lo = 1u << (2 * (g % 16));
+        uint32_t old = atomicOr(word, lo);
+        if (old & lo) atomicOr(word, lo << 1);
+    }
+}
+
 __global__ void k_sig_pairs(const uint32_t *s, const uint32_t *d, const uint32_t *l, const uint32_t *vl, uint64_t nd,
                             uint32_t n, uint32_t *sig) {
     uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -379,14 +416,19 @@ void build_graph(gsi_graph *g, const uint32_t *vl, const uint32_t *src, const ui
         bool t = radix_sort(c, (uint32_t)nd, 3, A, B, passes, s);
         cur = t ? B : A;
         uint32_t **other = t ? A : B;
-        launch(c, "k_check_dup", 8.0 * nd, k_check_dup, blocks(nd), BT, cur[0], cur[1], nd, err);
+        if (!g->multi) launch(c, "k_check_dup", 8.0 * nd, k_check_dup, blocks(nd), BT, cur[0], cur[1], nd, err);
         std::vector<SortPass> lp;
         for (int sh = 0; sh < lb; sh += 8) lp.push_back({2, sh});
         bool t2 = radix_sort(c, (uint32_t)nd, 3, cur, other, lp, s);
         if (t2) cur = other;
+        if (g->multi)
+            launch(c, "k_check_dup", 12.0 * nd, k_check_dup_labelled, blocks(nd), BT, cur[0], cur[1], cur[2], nd,
+                   err);
     }
     read_scalars(c, scal, hs, 1);
-    if ((uint32_t)hs[0] & ERR_DUP) fail(GSI_E_INVALID, "repeated vertex pair (parallel edge) in data graph");
+    if ((uint32_t)hs[0] & ERR_DUP)
+        fail(GSI_E_INVALID, g->multi ? "the same labelled edge is given twice in the data graph"
+                                     : "repeated vertex pair (parallel edge) in data graph");
     uint32_t *S = cur[0], *D = cur[1], *L = cur[2];
 
     // label segments and runs
@@ -513,9 +555,17 @@ void build_graph(gsi_graph *g, const uint32_t *vl, const uint32_t *src, const ui
         launch(c, "k_write_groups", 128.0 * R + 24.0 * R, k_write_groups, blocks(R), BT, kfirst, nkeys, gci, next, sorted_rid, run_start, run_vid, R, nd, d_rb, d_G, d_seg, nlab, g->gl, run_off);
         launch(c, "k_scatter_ci", 24.0 * nd, k_scatter_ci, blocks(nd), BT, D, L, hscan, run_start, run_off, d_seg, nd, g->ci);
     }
-    launch(c, "k_sig_labels", 8.0 * n + 60.0 * n, k_sig_labels, blocks(n), BT, vl, n, g->sig);
-    if (nd)
-        launch(c, "k_sig_pairs", 20.0 * nd, k_sig_pairs, blocks(nd), BT, S, D, L, vl, nd, n, g->sig);
+    if (g->multi) {
+        launch(c, "k_sig_labels", 8.0 * n + 64.0 * n, k_sig_labels_multi, blocks(n), BT, (const uint32_t *)g->vl_off,
+               (const uint32_t *)g->vl_lab, n, g->sig);
+        if (nd)
+            launch(c, "k_sig_pairs", 24.0 * nd, k_sig_pairs_multi, blocks(nd), BT, S, D, L,
+                   (const uint32_t *)g->vl_off, (const uint32_t *)g->vl_lab, nd, n, g->sig);
+    } else {
+        launch(c, "k_sig_labels", 8.0 * n + 60.0 * n, k_sig_labels, blocks(n), BT, vl, n, g->sig);
+        if (nd)
+            launch(c, "k_sig_pairs", 20.0 * nd, k_sig_pairs, blocks(nd), BT, S, D, L, vl, nd, n, g->sig);
+    }
     read_scalars(c, scal, hs, 3);
     if ((uint32_t)hs[0] & ERR_CLAIM1) fail(GSI_E_INTERNAL, "PCSR: not enough empty groups (Claim 1)");
     g->max_chain = R ? (uint32_t)hs[2] : 0;

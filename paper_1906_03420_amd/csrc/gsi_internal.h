@@ -106,6 +106,11 @@ struct gsi_graph {
     // differences are the list lengths
     uint32_t *cr_vid = nullptr, *cr_start = nullptr, *cr_off = nullptr;
     uint32_t *ci = nullptr;   // [2m]
+    // multi-labelled graphs (Sec. VII-B): vertex v's labels, ascending, at
+    // vl_lab[vl_off[v] .. vl_off[v+1]); a vertex pair may carry several edge
+    // labels (one entry per label in its partitions)
+    bool multi = false;
+    uint32_t *vl_off = nullptr, *vl_lab = nullptr;
     std::vector<uint64_t> group_base;  // per label: first global group
     std::vector<uint32_t> G;           // per label: |V(D)| groups
     std::vector<uint32_t> H;           // per label: home groups the hash spreads over
@@ -225,6 +230,8 @@ bool radix_sort(gsi_ctx *c, uint32_t n, int na, uint32_t *const *a, uint32_t *co
                 const std::vector<SortPass> &passes, Scratch &s);
 
 // --------------------------------------------------------------- pieces
+// d_vlabel: one label per vertex; for a multi-labelled graph (g->multi) it
+// is unused and g->vl_off / g->vl_lab hold the label sets already.
 void build_graph(gsi_graph *g, const uint32_t *d_vlabel, const uint32_t *d_src, const uint32_t *d_dst,
                  const uint32_t *d_elabel);
 
@@ -232,9 +239,22 @@ struct HostQuery {
     uint32_t k = 0;
     std::vector<uint32_t> vl, src, dst, el;
     std::vector<std::vector<std::pair<uint32_t, uint32_t>>> adj;  // (neighbour, label)
+    // multi-label queries (Sec. VII-B): label set of each vertex (ascending);
+    // a vertex pair may have several edges, one per label
+    bool multi = false;
+    std::vector<std::vector<uint32_t>> vls;
 };
 HostQuery validate_query(uint32_t k, const uint32_t *vl, uint32_t qm, const uint32_t *s, const uint32_t *d,
                          const uint32_t *l);
+// label sets lab[off[u] .. off[u+1]); repeated vertex pairs allowed with
+// distinct labels
+HostQuery validate_query_multi(uint32_t k, const uint32_t *off, const uint32_t *lab, uint32_t qm, const uint32_t *s,
+                               const uint32_t *d, const uint32_t *l);
+// a single-label query as the multi-label query with singleton sets
+void make_multi(HostQuery &q);
+// the bit of a vertex label in word 0 of a multi-labelled signature
+__host__ __device__ __forceinline__ uint32_t label_bit(uint32_t x) { return 1u << ((x * 0x9E3779B1u) >> 27); }
+constexpr uint32_t MULTI_MAX_QUERY_LABELS = 256;  // labels over all vertices of one query
 void run_filter(gsi_graph *g, const HostQuery &q, uint64_t *d_bits, uint32_t *d_counts);
 // query vertex u of query i has bitset row / count slot qbase[i] + u
 void run_filter_many(gsi_graph *g, const std::vector<const HostQuery *> &qs, const std::vector<uint32_t> &qbase,

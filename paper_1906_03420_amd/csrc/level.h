@@ -1,0 +1,102 @@
+// Arguments of one join level of the per-level kernels (Algorithms 3-4) and
+// device helpers shared by the join variants.
+#pragma once
+
+#include "gsi_internal.h"
+#include "join_device.h"
+
+namespace gsi {
+
+struct EdgeRef {
+    const uint32_t *gl;  // this label's groups
+    const uint32_t *ci;  // this label's neighbour lists
+    uint32_t G, H;       // groups, home groups
+    uint32_t col;        // column of M holding the placed endpoint
+    uint32_t ci_off;     // offset of this label's lists in the whole ci array
+    // compressed representation (ablation): the label's vertices in
+    // ascending order, each one's list offset in the label's ci, and the
+    // start of its entries in the (label, source, target) order of all
+    // directed edges, whose differences give the lengths
+    const uint32_t *cr_vid, *cr_start, *cr_off;
+    uint32_t cr_end;     // end of the label's entries in that order
+    uint32_t pad;
+};
+
+struct LevelArgs {
+    const uint32_t *M;
+    uint64_t R;
+    uint32_t j, ne, e0, k;
+    uint32_t pick;  // 1: each row scans its shortest linking list (else e0's)
+    uint32_t homo;  // 1: homomorphism (no subtraction of m_i, Sec. VII-A)
+    // ablations: lists located by binary search in the compressed
+    // representation; survivors counted, then the join repeated to write
+    // (two-step output); last-level rows written without LDS staging
+    uint32_t abl_cr, abl_two_step, abl_no_stage;
+    EdgeRef e[GSI_MAX_K];
+    const uint32_t *ci_all;  // every label's lists
+    const uint64_t *Cu;
+    // start at [e*R + i], length at [(ne+e)*R + i]; the scanned list of row
+    // i starts at ci_all[loc[2ne*R + i]] and is linking edge loc[(2ne+1)*R + i]
+    uint32_t *loc;
+    uint32_t *bound;
+    uint64_t *part;            // per-workgroup partial sums of k_locate
+    const uint64_t *F;
+    const uint64_t *tile_row;  // row holding the first slot of tile t (entry ntiles = R-1)
+    uint64_t gba;
+    uint64_t *bitmap;
+    uint32_t *tile_cnt;
+    const uint64_t *tile_off;
+    uint32_t *Mn;
+    uint64_t S;
+    uint32_t *out;
+    uint64_t *dig_part;  // per tile (sum, xor) of the tuple hashes (last level)
+    uint32_t qcol[GSI_MAX_K];  // query vertex -> column (last level)
+    uint32_t final_level, count_only;
+};
+
+// N(v, l) by binary search over the label's ascending vertex IDs (the
+// compressed representation the paper compares PCSR with, Sec. IV)
+__device__ __forceinline__ uint2 cr_find(const EdgeRef &er, uint32_t v) {
+    uint32_t lo = 0, hi = er.G;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (er.cr_vid[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo >= er.G || er.cr_vid[lo] != v) return make_uint2(0, 0);
+    const uint32_t b = er.cr_start[lo], e = lo + 1 < er.G ? er.cr_start[lo + 1] : er.cr_end;
+    return make_uint2(er.cr_off[lo], e - b);
+}
+
+// largest i in [lo, hi] with F[i] <= p (F non-decreasing, F[lo] <= p)
+__device__ __forceinline__ uint64_t row_of(const uint64_t *F, uint64_t lo, uint64_t hi, uint64_t p) {
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo + 1) / 2;
+        if (F[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// slot x of row i survives: x in C(u), x not in m_i, x in every other
+// linking list of the row
+__device__ __forceinline__ bool slot_keep(const LevelArgs &a, uint64_t i, uint32_t x) {
+    bool keep = (a.Cu[x >> 6] >> (x & 63)) & 1ull;
+    for (uint32_t c = 0; keep && !a.homo && c < a.j; c++) keep = a.M[(uint64_t)c * a.R + i] != x;
+    const uint32_t be = (keep && a.ne > 1) ? a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] : a.e0;
+    for (uint32_t e = 0; keep && e < a.ne; e++) {
+        if (e == be) continue;
+        uint32_t st = a.loc[(uint64_t)e * a.R + i];
+        uint32_t len = a.loc[(uint64_t)(a.ne + e) * a.R + i];
+        keep = in_sorted(a.e[e].ci + st, len, x);
+    }
+    return keep;
+}
+
+// The paper's ablations of the join step (GSI_ABL_NAIVE_SETOPS,
+// GSI_ABL_ROW_PER_WAVE, GSI_ABL_FOUR_LAYER, GSI_ABL_DUP_REMOVAL): fills
+// a.bitmap and a.tile_cnt for the level exactly as k_join does.
+void run_join_ablation(gsi_ctx *c, const LevelArgs &a, uint32_t flags, uint64_t ntiles, uint32_t ts,
+                       double join_bytes, Scratch &s);
+
+}  // namespace gsi

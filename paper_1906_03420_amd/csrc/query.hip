@@ -33,6 +33,7 @@
 #include "gsi_internal.h"
 #include "fused.h"
 #include "join_device.h"
+#include "level.h"
 #include "scan_device.h"
 
 namespace gsi {
@@ -89,10 +90,75 @@ HostQuery validate_query(uint32_t k, const uint32_t *vl, uint32_t qm, const uint
     return q;
 }
 
+// Multi-label query (Sec. VII-B): label sets per vertex; a vertex pair may
+// carry several edges, one per label (the same pair and label twice is
+// rejected); Q connected.
+HostQuery validate_query_multi(uint32_t k, const uint32_t *off, const uint32_t *lab, uint32_t qm, const uint32_t *s,
+                               const uint32_t *d, const uint32_t *l) {
+    if (k == 0 || k > GSI_MAX_K) fail(GSI_E_INVALID, "k must be in [1, %u]", (unsigned)GSI_MAX_K);
+    if (!off || !lab) fail(GSI_E_INVALID, "null query label sets");
+    if (qm && (!s || !d || !l)) fail(GSI_E_INVALID, "null query edge array");
+    if (off[0] != 0 || off[k] > MULTI_MAX_QUERY_LABELS)
+        fail(GSI_E_INVALID, "label offsets must start at 0 and hold at most %u labels", MULTI_MAX_QUERY_LABELS);
+    if (qm > 8u * k * (k - 1) / 2) fail(GSI_E_INVALID, "more than 8 labelled edges per query vertex pair");
+    HostQuery q;
+    q.k = k;
+    q.multi = true;
+    q.vl.assign(k, 0);
+    q.vls.assign(k, {});
+    for (uint32_t u = 0; u < k; u++) {
+        if (off[u + 1] < off[u]) fail(GSI_E_INVALID, "label offsets must not decrease");
+        std::vector<uint32_t> ls(lab + off[u], lab + off[u + 1]);
+        std::sort(ls.begin(), ls.end());
+        ls.erase(std::unique(ls.begin(), ls.end()), ls.end());
+        q.vls[u] = ls;
+        q.vl[u] = ls.empty() ? 0u : ls[0];
+    }
+    q.adj.assign(k, {});
+    std::vector<uint8_t> linked((size_t)k * k, 0);
+    for (uint32_t e = 0; e < qm; e++) {
+        uint32_t a = s[e], b = d[e];
+        if (a >= k || b >= k) fail(GSI_E_INVALID, "query edge %u has an endpoint >= k", e);
+        if (a == b) fail(GSI_E_INVALID, "query edge %u is a self-loop", e);
+        for (auto &p : q.adj[a])
+            if (p.first == b && p.second == l[e]) fail(GSI_E_INVALID, "query edge %u repeats a labelled edge", e);
+        q.src.push_back(a);
+        q.dst.push_back(b);
+        q.el.push_back(l[e]);
+        q.adj[a].push_back({b, l[e]});
+        q.adj[b].push_back({a, l[e]});
+        linked[(size_t)a * k + b] = linked[(size_t)b * k + a] = 1;
+    }
+    std::vector<uint8_t> vis(k, 0);
+    std::vector<uint32_t> st{0};
+    vis[0] = 1;
+    uint32_t reached = 1;
+    while (!st.empty()) {
+        uint32_t x = st.back();
+        st.pop_back();
+        for (uint32_t y = 0; y < k; y++)
+            if (linked[(size_t)x * k + y] && !vis[y]) {
+                vis[y] = 1;
+                reached++;
+                st.push_back(y);
+            }
+    }
+    if (reached != k) fail(GSI_E_INVALID, "query graph is not connected");
+    return q;
+}
+
+void make_multi(HostQuery &q) {
+    if (q.multi) return;
+    q.multi = true;
+    q.vls.assign(q.k, {});
+    for (uint32_t u = 0; u < q.k; u++) q.vls[u] = {q.vl[u]};
+}
+
 // ------------------------------------------------------------------ filter
 struct FilterArgs {
     uint32_t k;
     uint32_t label_only;
+    uint32_t subset0;              // word 0: containment (multi-label) instead of equality
     uint32_t word_mask;            // bit i set when some query vertex has bits in word i
     uint32_t dst[GSI_MAX_K];       // bitset row / count slot of query vertex u
     uint32_t q[GSI_MAX_K][GSI_SIG_WORDS];
@@ -107,9 +173,18 @@ static void query_signatures(const HostQuery &q, FilterArgs &fa, bool homo = fal
     fa.k = q.k;
     for (uint32_t u = 0; u < q.k; u++) {
         fa.dst[u] = u;
-        fa.q[u][0] = q.vl[u];
         uint32_t cnt[SIG_GROUPS] = {0};
-        for (auto &p : q.adj[u]) cnt[sig_group(p.second, q.vl[p.first])]++;
+        if (q.multi) {
+            // every label of u in word 0; a neighbour contributes the pair
+            // (edge label, x) for each of its labels x
+            fa.subset0 = 1;
+            for (uint32_t x : q.vls[u]) fa.q[u][0] |= label_bit(x);
+            for (auto &p : q.adj[u])
+                for (uint32_t x : q.vls[p.first]) cnt[sig_group(p.second, x)]++;
+        } else {
+            fa.q[u][0] = q.vl[u];
+            for (auto &p : q.adj[u]) cnt[sig_group(p.second, q.vl[p.first])]++;
+        }
         for (uint32_t g = 0; g < SIG_GROUPS; g++)
             if (cnt[g]) fa.q[u][1 + g / 16] |= (cnt[g] == 1 || homo ? 1u : 3u) << (2 * (g % 16));
         for (int i = 1; i < GSI_SIG_WORDS; i++)
@@ -154,7 +229,8 @@ __global__ __launch_bounds__(QT) void k_filter(const uint32_t *sig, uint32_t n, 
             uint32_t miss = 0;
 #pragma unroll
             for (int i = 1; i < GSI_SIG_WORDS; i++) miss |= nw[r][i] & fa.q[u][i];
-            ok |= (valid && w0[r] == fa.q[u][0] && miss == 0) ? (1u << u) : 0u;
+            const bool lab_ok = fa.subset0 ? (~w0[r] & fa.q[u][0]) == 0 : w0[r] == fa.q[u][0];
+            ok |= (valid && lab_ok && miss == 0) ? (1u << u) : 0u;
         }
         uint64_t mine = 0;
         for (uint32_t u = 0; u < K; u++) {
@@ -194,14 +270,62 @@ __global__ __launch_bounds__(1024) void k_bit_counts(const uint64_t *bits, uint6
     }
 }
 
+// Multi-labelled graphs (Sec. VII-B): the signature test lets through the
+// vertices whose hashed label bits contain u's; each candidate v of C(u)
+// then stays only if its label set contains u's (both ascending).  One
+// thread per (query vertex, bitset word).
+struct RefineArgs {
+    uint32_t k;
+    uint32_t dst[GSI_MAX_K];
+    uint32_t off[GSI_MAX_K + 1];
+    uint32_t lab[MULTI_MAX_QUERY_LABELS];
+};
+
+__global__ __launch_bounds__(QT) void k_label_refine(uint64_t *bits, uint64_t nwords, const uint32_t *voff,
+                                                    const uint32_t *vlab, RefineArgs ra) {
+    const uint64_t w = (uint64_t)blockIdx.x * QT + threadIdx.x;
+    const uint32_t u = blockIdx.y;
+    if (w >= nwords) return;
+    uint64_t *word = bits + (uint64_t)ra.dst[u] * nwords + w;
+    uint64_t b = *word, keep = b;
+    while (b) {
+        const uint32_t t = (uint32_t)__ffsll((unsigned long long)b) - 1;
+        b &= b - 1;
+        const uint32_t v = (uint32_t)(w * 64 + t);
+        uint32_t j = voff[v];
+        const uint32_t je = voff[v + 1];
+        bool ok = true;
+        for (uint32_t i = ra.off[u]; ok && i < ra.off[u + 1]; i++) {
+            while (j < je && vlab[j] < ra.lab[i]) j++;
+            ok = j < je && vlab[j] == ra.lab[i];
+        }
+        if (!ok) keep &= ~(1ull << t);
+    }
+    if (keep != *word) *word = keep;
+}
+
 static void launch_filter(gsi_ctx *c, gsi_graph *g, const FilterArgs &fa, uint64_t *bits, uint32_t *counts,
-                          uint32_t *runs) {
+                          uint32_t *runs, const HostQuery *mq = nullptr) {
     const uint64_t nwords = ((uint64_t)g->n + 63) / 64;
     const uint32_t nb = nblocks(g->n);
     const uint32_t need = fa.label_only ? 0u : fa.word_mask;
     double bytes = 4.0 * g->n * (1 + __builtin_popcount(need)) + (double)fa.k * nwords * 8;
     const uint32_t nfb = (nb + FILTER_TILES - 1) / FILTER_TILES;
     launch(c, "k_filter", bytes, k_filter, nfb, QT, (const uint32_t *)g->sig, g->n, nwords, fa, bits);
+    if (g->multi && mq) {
+        RefineArgs ra;
+        memset(&ra, 0, sizeof(ra));
+        ra.k = fa.k;
+        uint32_t o = 0;
+        for (uint32_t u = 0; u < fa.k; u++) {
+            ra.dst[u] = fa.dst[u];
+            ra.off[u] = o;
+            for (uint32_t x : mq->vls[u]) ra.lab[o++] = x;
+        }
+        ra.off[fa.k] = o;
+        launch(c, "k_label_refine", 16.0 * fa.k * nwords, k_label_refine, dim3(nblocks(nwords), fa.k), QT, bits,
+               nwords, (const uint32_t *)g->vl_off, (const uint32_t *)g->vl_lab, ra);
+    }
     launch(c, "k_filter_counts", 8.0 * fa.k * nwords, k_bit_counts, fa.k, 1024, (const uint64_t *)bits, nwords,
            counts, runs);
 }
@@ -402,7 +526,7 @@ static void filter_impl(gsi_graph *g, const HostQuery &q, bool label_only, uint6
     FilterArgs fa;
     query_signatures(q, fa, homo);
     fa.label_only = label_only ? 1u : 0u;
-    launch_filter(c, g, fa, bits, counts, runs);
+    launch_filter(c, g, fa, bits, counts, runs, q.multi ? &q : nullptr);
 }
 
 void run_filter(gsi_graph *g, const HostQuery &q, uint64_t *bits, uint32_t *counts) {
@@ -427,67 +551,6 @@ __global__ void k_word_emit(const uint64_t *bits, uint64_t nwords, const uint64_
 }
 
 // ------------------------------------------------------------ join level
-struct EdgeRef {
-    const uint32_t *gl;  // this label's groups
-    const uint32_t *ci;  // this label's neighbour lists
-    uint32_t G, H;       // groups, home groups
-    uint32_t col;        // column of M holding the placed endpoint
-    uint32_t ci_off;     // offset of this label's lists in the whole ci array
-    // compressed representation (ablation): the label's vertices in
-    // ascending order, each one's list offset in the label's ci, and the
-    // start of its entries in the (label, source, target) order of all
-    // directed edges, whose differences give the lengths
-    const uint32_t *cr_vid, *cr_start, *cr_off;
-    uint32_t cr_end;     // end of the label's entries in that order
-    uint32_t pad;
-};
-
-struct LevelArgs {
-    const uint32_t *M;
-    uint64_t R;
-    uint32_t j, ne, e0, k;
-    uint32_t pick;  // 1: each row scans its shortest linking list (else e0's)
-    uint32_t homo;  // 1: homomorphism (no subtraction of m_i, Sec. VII-A)
-    // ablations: lists located by binary search in the compressed
-    // representation; survivors counted, then the join repeated to write
-    // (two-step output); last-level rows written without LDS staging
-    uint32_t abl_cr, abl_two_step, abl_no_stage;
-    EdgeRef e[GSI_MAX_K];
-    const uint32_t *ci_all;  // every label's lists
-    const uint64_t *Cu;
-    // start at [e*R + i], length at [(ne+e)*R + i]; the scanned list of row
-    // i starts at ci_all[loc[2ne*R + i]] and is linking edge loc[(2ne+1)*R + i]
-    uint32_t *loc;
-    uint32_t *bound;
-    uint64_t *part;            // per-workgroup partial sums of k_locate
-    const uint64_t *F;
-    const uint64_t *tile_row;  // row holding the first slot of tile t (entry ntiles = R-1)
-    uint64_t gba;
-    uint64_t *bitmap;
-    uint32_t *tile_cnt;
-    const uint64_t *tile_off;
-    uint32_t *Mn;
-    uint64_t S;
-    uint32_t *out;
-    uint64_t *dig_part;  // per tile (sum, xor) of the tuple hashes (last level)
-    uint32_t qcol[GSI_MAX_K];  // query vertex -> column (last level)
-    uint32_t final_level, count_only;
-};
-
-// N(v, l) by binary search over the label's ascending vertex IDs (the
-// compressed representation the paper compares PCSR with, Sec. IV)
-__device__ __forceinline__ uint2 cr_find(const EdgeRef &er, uint32_t v) {
-    uint32_t lo = 0, hi = er.G;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (er.cr_vid[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    if (lo >= er.G || er.cr_vid[lo] != v) return make_uint2(0, 0);
-    const uint32_t b = er.cr_start[lo], e = lo + 1 < er.G ? er.cr_start[lo + 1] : er.cr_end;
-    return make_uint2(er.cr_off[lo], e - b);
-}
-
 // The list a row scans (its slots of GBA): the first edge e0 of Algorithm 4,
 // or, with `pick`, whichever linking list of the row is shortest (e0 on
 // ties).  The row's survivors are the same either way (they lie in every
@@ -551,18 +614,8 @@ __global__ __launch_bounds__(QT) void k_tile_rows(const uint64_t *F, uint64_t R,
 }
 
 void tile_rows(gsi_ctx *c, const uint64_t *F, uint64_t R, uint64_t ntiles, uint64_t *tile_row) {
-    launch(c, "k_tile_rows", 16.0 * R + 8.0 * ntiles, k_tile_rows, nblocks(R), QT, F, R, ntiles, (uint32_t)QT,
+    launch(c, "k_tile_rows", 8.0 * (R + 1) + 8.0 * (ntiles + 1), k_tile_rows, nblocks(R), QT, F, R, ntiles, (uint32_t)QT,
            tile_row);
-}
-
-// largest i in [lo, hi] with F[i] <= p (F non-decreasing, F[lo] <= p)
-__device__ __forceinline__ uint64_t row_of(const uint64_t *F, uint64_t lo, uint64_t hi, uint64_t p) {
-    while (lo < hi) {
-        uint64_t mid = lo + (hi - lo + 1) / 2;
-        if (F[mid] <= p) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
 }
 
 // The per-level join and link work on tiles of SPT x 256 |GBA| slots.  On
@@ -667,21 +720,6 @@ __device__ __forceinline__ void slot_row(const LevelArgs &a, const TileRows &t, 
         *i = row_of(a.F, t.r_lo, t.r_hi, p);
         *pos = a.loc[(uint64_t)(2 * a.ne) * a.R + *i] + (uint32_t)(p - a.F[*i]);
     }
-}
-
-// slot x of row i survives: x in C(u), x not in m_i, x in every other
-// linking list of the row
-__device__ __forceinline__ bool slot_keep(const LevelArgs &a, uint64_t i, uint32_t x) {
-    bool keep = (a.Cu[x >> 6] >> (x & 63)) & 1ull;
-    for (uint32_t c = 0; keep && !a.homo && c < a.j; c++) keep = a.M[(uint64_t)c * a.R + i] != x;
-    const uint32_t be = (keep && a.ne > 1) ? a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] : a.e0;
-    for (uint32_t e = 0; keep && e < a.ne; e++) {
-        if (e == be) continue;
-        uint32_t st = a.loc[(uint64_t)e * a.R + i];
-        uint32_t len = a.loc[(uint64_t)(a.ne + e) * a.R + i];
-        keep = in_sorted(a.e[e].ci + st, len, x);
-    }
-    return keep;
 }
 
 template <uint32_t SPT>
@@ -1079,13 +1117,17 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     gsi_ctx *c = g->ctx;
     auto t0 = std::chrono::steady_clock::now();
     const uint32_t k = q.k;
-    const uint32_t flags = (opt ? opt->flags : 0u) |
-                           ((opt && (opt->flags & (GSI_ABL_CR | GSI_ABL_TWO_STEP | GSI_ABL_NO_STAGING))) ? GSI_NO_FUSED
-                                                                                                         : 0u);
-    constexpr uint32_t ABL = GSI_ABL_CR | GSI_ABL_TWO_STEP | GSI_ABL_NO_STAGING;
+    // join-step ablations (each replaces k_join by a variant with the same output)
+    constexpr uint32_t JOIN_ABL = GSI_ABL_NAIVE_SETOPS | GSI_ABL_ROW_PER_WAVE | GSI_ABL_FOUR_LAYER;
+    constexpr uint32_t ABL = GSI_ABL_CR | GSI_ABL_TWO_STEP | GSI_ABL_NO_STAGING | JOIN_ABL | GSI_ABL_DUP_REMOVAL;
+    const uint32_t flags = (opt ? opt->flags : 0u) | ((opt && (opt->flags & ABL)) ? GSI_NO_FUSED : 0u);
     if (opt && (opt->flags & ~(GSI_COUNT_ONLY | GSI_FILTER_LABEL_ONLY | GSI_NO_FUSED | GSI_NO_CHUNKS |
                                GSI_LEVEL_FIRST_EDGE | GSI_HOMOMORPHISM | ABL)))
         fail(GSI_E_INVALID, "unknown query flag");
+    if (__builtin_popcount(flags & JOIN_ABL) > 1 || ((flags & JOIN_ABL) && (flags & GSI_ABL_TWO_STEP)))
+        fail(GSI_E_INVALID, "at most one join ablation, and not with GSI_ABL_TWO_STEP");
+    if ((flags & GSI_ABL_DUP_REMOVAL) && !(flags & (GSI_ABL_ROW_PER_WAVE | GSI_ABL_FOUR_LAYER)))
+        fail(GSI_E_INVALID, "GSI_ABL_DUP_REMOVAL needs GSI_ABL_ROW_PER_WAVE or GSI_ABL_FOUR_LAYER");
     if ((flags & GSI_ABL_CR) && !g->cr_vid) fail(GSI_E_INVALID, "GSI_ABL_CR needs a graph loaded with GSI_GRAPH_KEEP_CR");
     const bool count_only = (flags & GSI_COUNT_ONLY) != 0;
     const bool homo = (flags & GSI_HOMOMORPHISM) != 0;
@@ -1603,10 +1645,11 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         a.tile_off = toff;
         uint64_t *trow = ls.get<uint64_t>(ntiles + 1, "tile rows");
         a.tile_row = trow;
-        launch(c, "k_tile_rows", 16.0 * R + 8.0 * ntiles, k_tile_rows, nblocks(R), QT, (const uint64_t *)F, R, ntiles,
+        launch(c, "k_tile_rows", 8.0 * (R + 1) + 8.0 * (ntiles + 1), k_tile_rows, nblocks(R), QT, (const uint64_t *)F, R, ntiles,
                ts, trow);
         double jb = 4.0 * gba + (double)R * (8.0 + 8.0 * ne + 4.0 * j) + 4.0 * (double)sc[0] + gba / 8.0 + 4.0 * ntiles;
-        if (spt == 4) launch(c, "k_join", jb, k_join<4>, (uint32_t)ntiles, QT, a);
+        if (flags & JOIN_ABL) run_join_ablation(c, a, flags, ntiles, ts, jb, ls);
+        else if (spt == 4) launch(c, "k_join", jb, k_join<4>, (uint32_t)ntiles, QT, a);
         else launch(c, "k_join", jb, k_join<1>, (uint32_t)ntiles, QT, a);
         exclusive_scan(c, a.tile_cnt, ntiles, toff, ls, dscal + 1);
         uint64_t S;

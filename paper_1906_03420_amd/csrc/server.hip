@@ -250,6 +250,7 @@ extern "C" {
 gsi_status gsi_server_create(gsi_graph *g, const gsi_server_options *opt, gsi_server **out) {
     GSI_TRY({
         if (!g || !out) fail(GSI_E_INVALID, "null argument");
+        if (g->multi) fail(GSI_E_INVALID, "multi-labelled graphs run through gsi_query_run_multi only");
         *out = nullptr;
         gsi_server_options o = opt ? *opt : gsi_server_options{};
         if (o.flags & ~GSI_COUNT_ONLY) fail(GSI_E_INVALID, "unknown server flag");

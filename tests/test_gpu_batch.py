@@ -82,9 +82,13 @@ def test_batch_count_only_and_tune(ctx):
     assert ctx.memory()[0] == 0
 
 
-def test_batch_ba1m_mixed_full(golden_dir):
-    """The batched BA-1M workload (1,024 mixed queries) against the stored
-    oracle counts and digests, and against the single-query path."""
+BA1M_BATCH_PARTS = 4
+
+
+@pytest.fixture(scope="module")
+def ba1m_batch(golden_dir):
+    """The batched BA-1M workload (1,024 mixed queries) run once as a batch
+    with rows written; the graph and results stay resident for the tests."""
     import torch
     import paper_1906_03420_amd as gsi
     gold = json.load(open(os.path.join(golden_dir, "ba1m_batch.json")))
@@ -93,25 +97,58 @@ def test_batch_ba1m_mixed_full(golden_dir):
     qs = [w.config_query(g, "ba1m_batch", x["index"], attempt=x["attempt"], maker=mk) for x in gold["queries"]]
     dev = torch.device("cuda:0")
     as_t = lambda a: torch.from_numpy(a.view(np.int32)).to(dev)
-    with gsi.Context(64 << 30) as ctx:
-        dg = ctx.load_device(g.n, as_t(g.vlabel), as_t(g.src), as_t(g.dst), as_t(g.elabel))
-        lv = dg.batch(qs, flags=gsi.GSI_BATCH_LEVELS_ONLY | gsi.GSI_COUNT_ONLY)
-        print("levels-only batch info", lv.info(), flush=True)
-        for i, x in enumerate(gold["queries"]):
-            assert lv.count(i) == x["count"], i
-            assert [str(v) for v in lv.digest(i)] == x["digest"], i
-        lv.free()
-        b = dg.batch(qs)
-        print("batch info", b.info(), flush=True)
-        for i, x in enumerate(gold["queries"]):
-            assert b.count(i) == x["count"], i
-            assert [str(v) for v in b.digest(i)] == x["digest"], i
-        # single-query path on a sample: identical counts and digests
-        for i in range(0, len(qs), 37):
-            r = dg.query(qs[i])
-            assert (r.count, r.digest) == (b.count(i), b.digest(i))
-            if r.count <= 200_000:
-                np.testing.assert_array_equal(r.sorted_rows(), b.sorted_rows(i))
-            r.free()
-        b.free()
-        dg.free()
+    ctx = gsi.Context(64 << 30)
+    dg = ctx.load_device(g.n, as_t(g.vlabel), as_t(g.src), as_t(g.dst), as_t(g.elabel))
+    b = dg.batch(qs)
+    print("batch info", b.info(), flush=True)
+    state = dict(g=g, qs=qs, gold=gold["queries"], ctx=ctx, dg=dg, b=b, og=None)
+    yield state
+    if state["og"] is not None:
+        state["og"].close()
+    b.free()
+    dg.free()
+    ctx.close()
+
+
+def test_batch_ba1m_mixed_full(ba1m_batch):
+    """The batched BA-1M workload against the stored oracle counts and
+    digests (fused tiers + engine, and the engine alone), and against the
+    single-query path."""
+    import paper_1906_03420_amd as gsi
+    qs, gold, dg, b = ba1m_batch["qs"], ba1m_batch["gold"], ba1m_batch["dg"], ba1m_batch["b"]
+    lv = dg.batch(qs, flags=gsi.GSI_BATCH_LEVELS_ONLY | gsi.GSI_COUNT_ONLY)
+    print("levels-only batch info", lv.info(), flush=True)
+    for i, x in enumerate(gold):
+        assert lv.count(i) == x["count"], i
+        assert [str(v) for v in lv.digest(i)] == x["digest"], i
+    lv.free()
+    for i, x in enumerate(gold):
+        assert b.count(i) == x["count"], i
+        assert [str(v) for v in b.digest(i)] == x["digest"], i
+    # single-query path on a sample: identical counts, digests and tuples
+    for i in range(0, len(qs), 37):
+        r = dg.query(qs[i])
+        assert (r.count, r.digest) == (b.count(i), b.digest(i))
+        if r.count <= 200_000:
+            np.testing.assert_array_equal(r.sorted_rows(), b.sorted_rows(i))
+        r.free()
+
+
+@pytest.mark.parametrize("part", range(BA1M_BATCH_PARTS))
+def test_batch_ba1m_tuples(ba1m_batch, part):
+    """Sorted tuples of every batched query whose output is at most 2 GiB
+    equal the live oracle's (queries split in parts by index)."""
+    if ba1m_batch["og"] is None:
+        ba1m_batch["og"] = oracle.OracleGraph(ba1m_batch["g"])
+    og, qs, gold, b = ba1m_batch["og"], ba1m_batch["qs"], ba1m_batch["gold"], ba1m_batch["b"]
+    threads = max(1, min(16, os.cpu_count() or 1))
+    n = 0
+    for i in range(part, len(qs), BA1M_BATCH_PARTS):
+        x = gold[i]
+        if x["count"] * x["k"] * 4 > (2 << 30):
+            continue
+        want = og.match(qs[i], threads=threads)
+        assert want.status == oracle.OR_OK and want.count == x["count"], i
+        np.testing.assert_array_equal(b.sorted_rows(i), want.tuples)
+        n += 1
+    print("part", part, "compared", n, "queries tuple by tuple", flush=True)

@@ -414,12 +414,67 @@ def test_homomorphism_closed_forms(ctx):
 
 
 # ------------------------------------------------------------------ ablations
+def JOIN_ABLATIONS(gsi):
+    return [gsi.GSI_ABL_NAIVE_SETOPS, gsi.GSI_ABL_ROW_PER_WAVE, gsi.GSI_ABL_ROW_PER_WAVE | gsi.GSI_ABL_DUP_REMOVAL,
+            gsi.GSI_ABL_FOUR_LAYER, gsi.GSI_ABL_FOUR_LAYER | gsi.GSI_ABL_DUP_REMOVAL,
+            gsi.GSI_ABL_NAIVE_SETOPS | gsi.GSI_LEVEL_FIRST_EDGE, gsi.GSI_ABL_FOUR_LAYER | gsi.GSI_HOMOMORPHISM]
+
+
+def hub_graph(degrees, every=50):
+    """Hubs 0..h-1 of the given degrees over shared leaves h, h+1, ...: hub
+    t is joined to the first degrees[t] leaves.  Hubs and leaves have vertex
+    label 0, except every `every`-th leaf (label 1); one edge label."""
+    h = len(degrees)
+    edges = [(t, h + x) for t, d in enumerate(degrees) for x in range(d)]
+    n = h + max(degrees)
+    vl = [0] * h + [1 if x % every == 0 else 0 for x in range(n - h)]
+    return w.make_graph(n, vl, edges, [0] * len(edges), "hubs")
+
+
+def test_join_ablations_on_hub_rows(ctx):
+    """Rows whose scanned lists cross every threshold of the 4-layer balance
+    (over W1 = 4096, over W2 = 1024, over W3 = 256, short), with rows that
+    scan the same hub list close together (shared by duplicate removal):
+    every join variant gives the oracle's rows for the path label 0 - label
+    0 - label 1 (closed form: the sum over hubs of their label-0 times their
+    label-1 neighbours) and the same per-level sizes."""
+    import paper_1906_03420_amd as gsi
+    degs = [5000, 2000, 600, 100]
+    g = hub_graph(degs)
+    closed = sum((d - (d + 49) // 50) * ((d + 49) // 50) for d in degs)
+    q = w.make_query([0, 0, 1], [(0, 1), (1, 2)], [0, 0])
+    want = oracle.match(g, q, threads=8)
+    assert want.count == closed == 575652
+    dg = ctx.load(g)
+    ref = None
+    for f in [gsi.GSI_NO_FUSED] + JOIN_ABLATIONS(gsi):
+        for co in (gsi.GSI_COUNT_ONLY, 0):
+            print("hub rows, flags", hex(f | co), flush=True)
+            r = dg.query(q, flags=f | co)
+            assert (r.count, r.digest) == (want.count, want.digest), hex(f)
+            if not co:
+                np.testing.assert_array_equal(r.sorted_rows(), want.tuples)
+            st = r.stats()
+            sizes = (st["rows"], st["gba"], st["survivors"])
+            if not f & gsi.GSI_LEVEL_FIRST_EDGE:
+                ref = ref or sizes
+                assert sizes == ref
+            r.free()
+    assert max(ref[1]) > 4096 * 100  # the heavy rows were there
+    with pytest.raises(gsi.GsiError):
+        dg.query(q, flags=gsi.GSI_ABL_DUP_REMOVAL)
+    with pytest.raises(gsi.GsiError):
+        dg.query(q, flags=gsi.GSI_ABL_NAIVE_SETOPS | gsi.GSI_ABL_FOUR_LAYER)
+    dg.free()
+
+
 def test_ablations_give_identical_results(ctx):
     """Compressed-representation lookup, two-step output and unstaged row
     writes change only how the per-level kernels work, never the result."""
     import paper_1906_03420_amd as gsi
     modes = [dict(flags=gsi.GSI_ABL_CR), dict(flags=gsi.GSI_ABL_TWO_STEP), dict(flags=gsi.GSI_ABL_NO_STAGING),
              dict(flags=gsi.GSI_ABL_CR | gsi.GSI_ABL_TWO_STEP | gsi.GSI_ABL_NO_STAGING | gsi.GSI_COUNT_ONLY)]
+    modes += [dict(flags=f) for f in JOIN_ABLATIONS(gsi)]
     for seed in range(6):
         r = np.random.default_rng(4000 + seed)
         n = int(r.integers(50, 400))

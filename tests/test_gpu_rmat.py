@@ -1,27 +1,37 @@
-"""Full-size R-MAT workloads against the stored oracle values: the serving
-pool on the scale-22 graph (50M edges) through the server, the
-single-query path and a batch; and the scale-23 graph (100M edges) through
-the single-query path.  Each test checks the queries its golden file holds
-(the files are written query by query)."""
+"""Full-size R-MAT workloads against the oracle.
+
+Scale 23 (8,388,608 vertices, 100M edges; 50 twelve-vertex walk and dense
+queries): every query's count and digest against the stored oracle values,
+on the single-query path with rows written, in the launch configuration the
+benchmark times; and, for every query whose output is at most 2 GiB, the
+full sorted tuple set against the live oracle (one test per query).
+
+Scale 22 (50M edges; the serving pool): every pool query through the
+server, the single-query path and a batch, each compared with the live
+oracle's sorted tuples (every pool output is below 2 GiB).
+"""
 import json
 import os
 
 import numpy as np
 import pytest
 
+import oracle
 import workloads as w
 
 pytestmark = pytest.mark.gpu
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TUPLE_BYTES = 2 << 30  # outputs up to this size are compared tuple by tuple
 
-def _gold(golden_dir, name):
-    path = os.path.join(golden_dir, "%s.json" % name)
-    if not os.path.exists(path):
-        pytest.skip("no stored oracle values for %s" % name)
-    gold = json.load(open(path))
-    if not gold["queries"]:
-        pytest.skip("no stored oracle values for %s" % name)
-    return gold
+
+def _gold_queries(name):
+    path = os.path.join(GOLDEN, "%s.json" % name)
+    return json.load(open(path))["queries"] if os.path.exists(path) else []
+
+
+def _threads():
+    return max(1, min(16, os.cpu_count() or 1))
 
 
 def _load(ctx, g):
@@ -31,62 +41,109 @@ def _load(ctx, g):
     return ctx.load_device(g.n, as_t(g.vlabel), as_t(g.src), as_t(g.dst), as_t(g.elabel))
 
 
-def test_rmat22_serving_pool(golden_dir):
+def test_rmat22_serving_pool_tuples():
+    """The serving pool through the server (seeded bursts, answers kept until
+    compared), the single-query path and a batch: sorted tuples equal the
+    live oracle's for every pool query."""
     import paper_1906_03420_amd as gsi
-    gold = _gold(golden_dir, "rmat22_serve")["queries"]
+    gold = _gold_queries("rmat22_serve")
+    if not gold:
+        pytest.skip("no stored oracle values for rmat22_serve")
     print("generating the scale-22 graph", flush=True)
     g = w.config_graph("rmat22_serve")
     mk = w.QueryMaker(g)
     qs = [w.config_query(g, "rmat22_serve", x["index"], attempt=x["attempt"], maker=mk) for x in gold]
     mk.close()
-    want = [(x["count"], x["digest"]) for x in gold]
+    og = oracle.OracleGraph(g)
+    print("oracle tuples for", len(qs), "pool queries", flush=True)
+    want = []
+    for q, x in zip(qs, gold):
+        r = og.match(q, threads=_threads())
+        assert r.status == oracle.OR_OK and r.count == x["count"]
+        assert [str(v) for v in r.digest] == x["digest"]
+        want.append(r.tuples)
+    og.close()
     with gsi.Context(96 << 30) as ctx:
         dg = _load(ctx, g)
-        print("pool of", len(qs), "queries; serving", flush=True)
+        print("serving", flush=True)
         srv = dg.server()
-        r = np.random.default_rng(5)
-        tickets, ans, i = [], {}, 0
-        while len(ans) < len(qs):
-            b = min(len(qs) - i, int(r.integers(0, 24)))
+        rng = np.random.default_rng(5)
+        tickets, done, i = [], set(), 0
+        while len(done) < len(qs):
+            b = min(len(qs) - i, int(rng.integers(0, 24)))
             tickets += [srv.submit(q) for q in qs[i:i + b]]
             i += b
             srv.step()
-            for t in srv.poll():
-                ans[t] = srv.answer(t)
-                if ans[t]["count"] > 200_000:
-                    srv.release(t)
-        for t, (c, d) in zip(tickets, want):
-            assert ans[t]["status"] == 0 and ans[t]["count"] == c and [str(v) for v in ans[t]["digest"]] == d
+            done.update(srv.poll())
+        for t, x, wt in zip(tickets, gold, want):
+            a = srv.answer(t)
+            assert a["status"] == 0 and a["count"] == x["count"] and [str(v) for v in a["digest"]] == x["digest"]
+            np.testing.assert_array_equal(srv.sorted_rows(t), wt)
+            srv.release(t)
         print("server info", srv.info(), flush=True)
         srv.free()
         print("single-query path", flush=True)
-        for q, (c, d) in zip(qs, want):
-            res = dg.query(q, flags=gsi.GSI_COUNT_ONLY)
-            assert res.count == c and [str(v) for v in res.digest] == d
+        for q, wt in zip(qs, want):
+            res = dg.query(q)
+            np.testing.assert_array_equal(res.sorted_rows(), wt)
             res.free()
         print("batch", flush=True)
-        b = dg.batch(qs, flags=gsi.GSI_COUNT_ONLY)
-        for i, (c, d) in enumerate(want):
-            assert b.count(i) == c and [str(v) for v in b.digest(i)] == d
+        b = dg.batch(qs)
+        for i, wt in enumerate(want):
+            np.testing.assert_array_equal(b.sorted_rows(i), wt)
         print("batch info", b.info(), flush=True)
         b.free()
         dg.free()
 
 
-def test_rmat23_single_query_path(golden_dir):
+RMAT23 = _gold_queries("rmat23")
+RMAT23_TUPLES = [x["index"] for x in RMAT23 if x["count"] * x["k"] * 4 <= TUPLE_BYTES]
+
+
+@pytest.fixture(scope="module")
+def rmat23():
     import paper_1906_03420_amd as gsi
-    gold = _gold(golden_dir, "rmat23")["queries"]
+    if not RMAT23:
+        pytest.skip("no stored oracle values for rmat23")
     print("generating the scale-23 graph", flush=True)
     g = w.config_graph("rmat23")
     mk = w.QueryMaker(g)
-    qs = [w.config_query(g, "rmat23", x["index"], attempt=x["attempt"], maker=mk) for x in gold]
+    qs = {x["index"]: w.config_query(g, "rmat23", x["index"], attempt=x["attempt"], maker=mk) for x in RMAT23}
     mk.close()
-    with gsi.Context(160 << 30) as ctx:
-        dg = _load(ctx, g)
-        for q, x in zip(qs, gold):
-            print("rmat23 query", x["index"], "k", q.k, "count", x["count"], flush=True)
-            res = dg.query(q)
-            assert res.count == x["count"]
-            assert [str(v) for v in res.digest] == x["digest"]
-            res.free()
-        dg.free()
+    ctx = gsi.Context(160 << 30)
+    dg = _load(ctx, g)
+    state = dict(g=g, qs=qs, gold={x["index"]: x for x in RMAT23}, ctx=ctx, dg=dg, og=None)
+    yield state
+    if state["og"] is not None:
+        state["og"].close()
+    dg.free()
+    ctx.close()
+
+
+def test_rmat23_all_queries_counts_digests(rmat23):
+    """All 50 queries, rows written, count and digest equal to the oracle's."""
+    assert len(RMAT23) == w.CONFIGS["rmat23"]["nq"]
+    dg = rmat23["dg"]
+    for ix, x in rmat23["gold"].items():
+        q = rmat23["qs"][ix]
+        print("rmat23 query", ix, "k", q.k, "count", x["count"], flush=True)
+        res = dg.query(q)
+        assert res.count == x["count"]
+        assert [str(v) for v in res.digest] == x["digest"]
+        res.free()
+
+
+@pytest.mark.parametrize("ix", RMAT23_TUPLES)
+def test_rmat23_tuples(rmat23, ix):
+    """Sorted embedding tuples equal the live oracle's (outputs <= 2 GiB)."""
+    if rmat23["og"] is None:
+        rmat23["og"] = oracle.OracleGraph(rmat23["g"])
+    q, x = rmat23["qs"][ix], rmat23["gold"][ix]
+    print("rmat23 query", ix, "count", x["count"], "oracle threads", _threads(), flush=True)
+    res = rmat23["dg"].query(q)
+    got = res.sorted_rows()
+    res.free()
+    want = rmat23["og"].match(q, threads=_threads())
+    assert want.status == oracle.OR_OK and want.count == x["count"]
+    assert got.shape == want.tuples.shape
+    np.testing.assert_array_equal(got, want.tuples)

@@ -227,3 +227,38 @@ def test_plan_prefix_connected_and_e0_linking():
         for j in range(1, q.k):
             assert e0[j] in order[:j]
             assert frozenset((e0[j], order[j])) in edges
+
+
+def test_plan_worked_example_hand_derived():
+    """Algorithm 2 on the running example, derived by hand.  Label-only
+    candidate counts |C(u)| = 1, 100, 101, 101 and query degrees 2, 3, 2, 1
+    give scores 1/2, 100/3, 101/2, 101: u0 goes first.  freq(a) = 200/202
+    and freq(b) = 2/202 (ratio reading); placing u0 multiplies u1's score by
+    freq(a) (33.0) and u2's by freq(b) (0.5), so u2 is next; placing u2
+    leaves u1 (32.7) as the only vertex adjacent to the placed ones, then u3.
+    e0 (Algorithm 4, least freq(l)): u2 links only to u0; u1 links to u0 and
+    u2 by label a (a tie, taken by the end placed first, u0); u3 links to u1.
+    Under the count reading of freq (200 and 2) the order is the same here;
+    the hand derivation pins the scoring, the frontier rule and the ties."""
+    g, q = w.paper_example()
+    counts = [int((g.vlabel == q.vlabel[u]).sum()) for u in range(q.k)]
+    assert counts == [1, 100, 101, 101]
+    freq = spec.label_frequency(g)
+    assert abs(freq[0] - 200 / 202) < 1e-12 and abs(freq[1] - 2 / 202) < 1e-12
+    order, e0 = spec.plan(q, counts, freq)
+    assert order == [0, 2, 1, 3]
+    assert e0 == [None, 0, 0, 1]
+
+
+def test_row_sort_helper_orders_lexicographically():
+    """The byte-string row sort used to compare result tables equals a
+    k-key lexsort, zeros and full-range values included."""
+    from paper_1906_03420_amd.binding import sort_rows
+    r = np.random.default_rng(11)
+    for k in (1, 2, 4, 12):
+        a = r.integers(0, 3, size=(4000, k), dtype=np.uint32)
+        a[::5, -1] = 0
+        np.testing.assert_array_equal(sort_rows(a), a[np.lexsort(a.T[::-1])])
+        b = r.integers(0, 2**32, size=(4000, k), dtype=np.uint64).astype(np.uint32)
+        np.testing.assert_array_equal(sort_rows(b), b[np.lexsort(b.T[::-1])])
+    assert sort_rows(np.zeros((0, 3), np.uint32)).shape == (0, 3)

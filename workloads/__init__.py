@@ -255,6 +255,26 @@ def request_stream(name: str, stream: int, n: int, pool: int) -> np.ndarray:
 
 
 def config_graph(name: str) -> Graph:
+    """The named workload's data graph.  With GSI_GRAPH_CACHE set to a
+    directory, the generated arrays are kept there as .npy files and later
+    calls (other processes included) load them instead of regenerating."""
+    cache = os.environ.get("GSI_GRAPH_CACHE")
+    if cache:
+        base = os.path.join(cache, "%s_" % name)
+        files = [base + x + ".npy" for x in ("vl", "src", "dst", "el")]
+        if all(os.path.exists(f) for f in files):
+            vl, src, dst, el = (np.load(f) for f in files)
+            return Graph(int(vl.shape[0]), vl, src, dst, el, name)
+        g = _generate(name)
+        os.makedirs(cache, exist_ok=True)
+        for f, a in zip(files, (g.vlabel, g.src, g.dst, g.elabel)):
+            np.save(f + ".tmp.npy", a)
+            os.replace(f + ".tmp.npy", f)
+        return g
+    return _generate(name)
+
+
+def _generate(name: str) -> Graph:
     c = CONFIGS[name]
     if c["model"] == "er":
         src, dst = er_edges(c["n"], c["m"], c["gseed"])
@@ -372,3 +392,135 @@ def paper_example():
     g = make_graph(202, vl, edges, el, "paper_example")
     q = make_query([A, B, C, C], [(0, 1), (0, 2), (1, 2), (1, 3)], [a, b, a, a], "paper_example")
     return g, q
+
+
+# ------------------------------------------------------- multi-labelled inputs
+# Sec. VII-B: a vertex may carry several labels, and a vertex pair several
+# edge labels (given as one edge entry per label).  Label sets are stored as
+# offsets into one label array.
+@dataclass
+class MGraph:
+    n: int
+    voff: np.ndarray   # uint64[n+1]
+    vlab: np.ndarray   # uint32[voff[n]]
+    src: np.ndarray    # uint32[m], one entry per (pair, label)
+    dst: np.ndarray
+    elabel: np.ndarray
+    name: str = ""
+
+    @property
+    def m(self) -> int:
+        return int(self.src.shape[0])
+
+    def labels(self, v: int) -> list:
+        return self.vlab[self.voff[v]:self.voff[v + 1]].tolist()
+
+
+@dataclass
+class MQuery:
+    k: int
+    qoff: np.ndarray   # uint32[k+1]
+    qlab: np.ndarray   # uint32[qoff[k]]
+    src: np.ndarray    # uint32, one entry per (pair, label)
+    dst: np.ndarray
+    elabel: np.ndarray
+    mode: str = ""
+
+    @property
+    def m(self) -> int:
+        return int(self.src.shape[0])
+
+    def labels(self, u: int) -> list:
+        return self.qlab[self.qoff[u]:self.qoff[u + 1]].tolist()
+
+
+def make_mgraph(n, label_sets, edges, name="") -> MGraph:
+    """label_sets[v]: labels of v; edges: (a, b, label) triples."""
+    off = np.zeros(n + 1, np.uint64)
+    off[1:] = np.cumsum([len(s) for s in label_sets])
+    lab = _u32([x for s in label_sets for x in s])
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 3)
+    return MGraph(int(n), off, lab, _u32(e[:, 0]), _u32(e[:, 1]), _u32(e[:, 2]), name)
+
+
+def make_mquery(label_sets, edges, mode="manual") -> MQuery:
+    k = len(label_sets)
+    off = np.zeros(k + 1, np.uint32)
+    off[1:] = np.cumsum([len(s) for s in label_sets])
+    lab = _u32([x for s in label_sets for x in s])
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 3)
+    return MQuery(k, off, lab, _u32(e[:, 0]), _u32(e[:, 1]), _u32(e[:, 2]), mode)
+
+
+def mgraph_from_single(g: Graph) -> MGraph:
+    """The same graph with one label per vertex and per pair."""
+    return MGraph(g.n, np.arange(g.n + 1, dtype=np.uint64), g.vlabel.copy(), g.src.copy(), g.dst.copy(),
+                  g.elabel.copy(), g.name)
+
+
+def mquery_from_single(q: Query) -> MQuery:
+    return MQuery(q.k, np.arange(q.k + 1, dtype=np.uint32), q.vlabel.copy(), q.src.copy(), q.dst.copy(),
+                  q.elabel.copy(), q.mode)
+
+
+def random_multi_graph(n: int, p: float, nvl: int, nel: int, max_vl: int, max_el: int, seed: int) -> MGraph:
+    """Each vertex gets 1..max_vl distinct labels of nvl; each pair is an edge
+    with probability p and then gets 1..max_el distinct labels of nel."""
+    r = _stream(seed, 7)
+    sets = [sorted(r.choice(nvl, size=int(r.integers(1, max_vl + 1)), replace=False).tolist()) for _ in range(n)]
+    a, b = np.triu_indices(n, 1)
+    keep = r.random(a.shape[0]) < p
+    edges = []
+    for x, y in zip(a[keep].tolist(), b[keep].tolist()):
+        for l in sorted(r.choice(nel, size=int(r.integers(1, max_el + 1)), replace=False).tolist()):
+            edges.append((x, y, l))
+    return make_mgraph(n, sets, edges, "multi%d" % seed)
+
+
+def multi_walk_query(g: MGraph, k: int, seed: int, dense: bool = False) -> MQuery:
+    """A random walk over g until k distinct vertices are visited; each query
+    vertex keeps a non-empty random subset of its data vertex's labels, each
+    traversed pair (with dense, every pair of visited vertices joined in g)
+    a non-empty random subset of the pair's labels.  The walk's own vertices
+    are an embedding, so the result is never empty."""
+    r = _stream(seed, 8)
+    pairs = {}
+    for x, y, l in zip(g.src.tolist(), g.dst.tolist(), g.elabel.tolist()):
+        pairs.setdefault((min(x, y), max(x, y)), []).append(l)
+    nbr = {}
+    for (x, y) in pairs:
+        nbr.setdefault(x, []).append(y)
+        nbr.setdefault(y, []).append(x)
+    starts = sorted(nbr)
+    if not starts:
+        raise RuntimeError("graph has no edges")
+    for _ in range(100):
+        v = starts[int(r.integers(0, len(starts)))]
+        seen, walk = [v], set()
+        for _ in range(100 * k):
+            if len(seen) == k:
+                break
+            w = nbr[v][int(r.integers(0, len(nbr[v])))]
+            walk.add((min(v, w), max(v, w)))
+            if w not in seen:
+                seen.append(w)
+            v = w
+        if len(seen) == k:
+            break
+    else:
+        raise RuntimeError("no walk reached %d vertices" % k)
+    idx = {v: i for i, v in enumerate(seen)}
+    if dense:
+        walk = {(x, y) for (x, y) in pairs if x in idx and y in idx}
+    sets = []
+    for v in seen:
+        ls = g.labels(v)
+        sets.append(sorted(r.choice(ls, size=int(r.integers(1, len(ls) + 1)), replace=False).tolist()))
+    edges = []
+    for (x, y) in sorted(walk):
+        ls = pairs[(x, y)]
+        for l in sorted(r.choice(ls, size=int(r.integers(1, len(ls) + 1)), replace=False).tolist()):
+            edges.append((idx[x], idx[y], l))
+    q = make_mquery(sets, edges, "dense" if dense else "walk")
+    q.source = np.array(seen, np.uint32)
+    return q

@@ -240,8 +240,8 @@ def batched_section(args, vl_t, s_t, d_t, l_t, g, arena):
         torch.cuda.synchronize()
         return out
 
-    def batched():
-        b = dg.batch(qs)
+    def batched(**sched):
+        b = dg.batch(qs, **sched)
         out = [(b.count(i), b.digest(i)) for i in range(len(qs))]
         info = b.info()
         b.free()
@@ -264,6 +264,15 @@ def batched_section(args, vl_t, s_t, d_t, l_t, g, arena):
         out, info = batched()
         parity &= ok(out)
     t_bat = (time.perf_counter() - t0) / args.steps
+    # the untuned default schedule (256-thread first tier, full occupancy,
+    # 4 engine tiles per workgroup) over the same passes
+    default = dict(threads=256, grid_scale=8, engine_tiles=4)
+    batched(**default)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out, _ = batched(**default)
+        parity &= ok(out)
+    t_def = (time.perf_counter() - t0) / args.steps
     dg.free()
     ctx.close()
     # one batched pass again with HIP events around every launch
@@ -282,28 +291,46 @@ def batched_section(args, vl_t, s_t, d_t, l_t, g, arena):
                 sequential=dict(queries_per_s=len(qs) / t_seq, embeddings_per_s=emb / t_seq, ms_per_pass=t_seq * 1e3),
                 batched=dict(queries_per_s=len(qs) / t_bat, embeddings_per_s=emb / t_bat, ms_per_pass=t_bat * 1e3),
                 speedup=t_seq / t_bat, schedule=info["schedule"], autotune=tune,
+                default_schedule=dict(default, ms_per_pass=t_def * 1e3, tuned_vs_default=t_def / t_bat),
                 tiers=dict(empty=info["empty"], tier1=info["tier1"], tier2=info["tier2"], per_level=info["per_level"]),
                 roofline=engine_roofline(ks, 1, prof_ms),
                 parity="bit-exact counts+digests vs oracle, both paths, %d/%d" % (len(qs), len(qs)) if parity
                 else "MISMATCH")
 
 
-def ablation_section(args, vl_t, s_t, d_t, l_t, g, qs, gold, arena):
-    """The paper's ablations (Tables V-VII) on the same 100 queries, one at a
-    time: the per-level kernels as built, then with N(v,l) found by binary
-    search in the compressed representation instead of PCSR, with two-step
-    output instead of Prealloc-Combine, and without LDS-staged row writes;
-    plus this design's own switches (fused small-table workgroup off, the
-    first edge of Algorithm 4 for every row).  Each variant must give the
-    oracle's counts and digests."""
+def ablation_variants(gsi):
+    """(name, flags): the design as built, the per-level kernels as the
+    paper describes them (the reference, 1.0), this design's departures, and
+    the paper's ablations (Tables V-IX) on top of the per-level kernels."""
+    PL = gsi.GSI_NO_FUSED | gsi.GSI_NO_LIST_FILTER
+    return [("default", 0), ("per_level", PL), ("per_level+list_filter", gsi.GSI_NO_FUSED),
+            ("level_first_edge", gsi.GSI_LEVEL_FIRST_EDGE),
+            ("per_level+cr_lookup", PL | gsi.GSI_ABL_CR),
+            ("per_level+two_step_output", PL | gsi.GSI_ABL_TWO_STEP),
+            ("per_level+unstaged_rows", PL | gsi.GSI_ABL_NO_STAGING),
+            ("per_level+naive_set_ops", PL | gsi.GSI_ABL_NAIVE_SETOPS),
+            ("per_level+row_per_wave", PL | gsi.GSI_ABL_ROW_PER_WAVE),
+            ("per_level+row_per_wave+dup_removal", PL | gsi.GSI_ABL_ROW_PER_WAVE | gsi.GSI_ABL_DUP_REMOVAL),
+            ("per_level+four_layer", PL | gsi.GSI_ABL_FOUR_LAYER),
+            ("per_level+four_layer+dup_removal", PL | gsi.GSI_ABL_FOUR_LAYER | gsi.GSI_ABL_DUP_REMOVAL)]
+
+
+PAPER_TABLES = {
+    "per_level+cr_lookup": "Table VI: CR -> PCSR, 1.1-1.4x",
+    "per_level+two_step_output": "Table V +PC: two-step output -> Prealloc-Combine, 1.2-2.0x",
+    "per_level+unstaged_rows": "Table VII: write cache off -> on, 1.0-4.2x",
+    "per_level+naive_set_ops": "Table V +SO: naive -> GPU-friendly set operations, 1.0-6.3x",
+    "per_level+four_layer": "Table VIII: GSI -> +LB (4-layer balance), 1.0-3.4x",
+    "per_level+four_layer+dup_removal": "Table VIII +DR: on top of +LB, 1.0-1.3x (Table IX: 3-23% fewer loads)",
+}
+
+
+def run_ablations(dg, qs, gold_q, passes):
+    """Each variant over the queries, one at a time (rows written): one
+    warm-up pass, then the best of `passes`; every variant's counts and
+    digests must equal the oracle's."""
     import torch
     import paper_1906_03420_amd as gsi
-    ctx = gsi.Context(arena)
-    dg = ctx.load_device(g.n, vl_t, s_t, d_t, l_t, gsi.GSI_GRAPH_KEEP_CR)
-    variants = [("default", 0), ("level_first_edge", gsi.GSI_LEVEL_FIRST_EDGE), ("per_level", gsi.GSI_NO_FUSED),
-                ("per_level+cr_lookup", gsi.GSI_NO_FUSED | gsi.GSI_ABL_CR),
-                ("per_level+two_step_output", gsi.GSI_NO_FUSED | gsi.GSI_ABL_TWO_STEP),
-                ("per_level+unstaged_rows", gsi.GSI_NO_FUSED | gsi.GSI_ABL_NO_STAGING)]
 
     def run(flags):
         out = []
@@ -315,25 +342,61 @@ def ablation_section(args, vl_t, s_t, d_t, l_t, g, qs, gold, arena):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, out
 
-    res = {}
-    ok = True
-    for name, flags in variants:
-        run(flags)  # warm-up
+    res, ok = {}, True
+    for name, flags in ablation_variants(gsi):
+        run(flags)
         best = None
-        for _ in range(max(1, args.steps)):
+        for _ in range(max(1, passes)):
             dt, out = run(flags)
             best = dt if best is None else min(best, dt)
-            ok &= all(c == x["count"] and [str(d[0]), str(d[1])] == x["digest"]
-                      for (c, d), x in zip(out, gold["queries"]))
+            ok &= all(c == x["count"] and [str(d[0]), str(d[1])] == x["digest"] for (c, d), x in zip(out, gold_q))
         res[name] = dict(ms_per_pass=best * 1e3)
     base = res["per_level"]["ms_per_pass"]
     for name in res:
         res[name]["vs_per_level"] = res[name]["ms_per_pass"] / base
+        if name in PAPER_TABLES:
+            res[name]["paper"] = PAPER_TABLES[name]
+    return res, ok
+
+
+def ablation_section(args, vl_t, s_t, d_t, l_t, g, qs, gold, arena):
+    """The paper's ablations on the BA-1M single-query workload (100 queries):
+    time per pass relative to the per-level kernels as the paper describes
+    them (per_level = 1.0)."""
+    import paper_1906_03420_amd as gsi
+    ctx = gsi.Context(arena)
+    dg = ctx.load_device(g.n, vl_t, s_t, d_t, l_t, gsi.GSI_GRAPH_KEEP_CR)
+    res, ok = run_ablations(dg, qs, gold["queries"], args.steps)
     dg.free()
     ctx.close()
-    return dict(workload="the single-query workload above (100 queries, rows written), best of %d passes"
+    return dict(workload="the BA-1M single-query workload (100 queries, rows written), best of %d passes"
                          % max(1, args.steps), variants=res,
                 parity="bit-exact counts+digests vs oracle in every variant" if ok else "MISMATCH")
+
+
+def ablation_section_c2(hx, arena, nq=8):
+    """The same ablations on the R-MAT-23 queries whose joins are largest
+    (the nq with the most embeddings below 10^8), where the join, not the
+    per-query fixed cost, sets the time."""
+    import numpy as np
+    import torch
+    import paper_1906_03420_amd as gsi
+    gold = hx["gold"]["queries"]
+    pick = sorted(range(len(gold)), key=lambda i: -gold[i]["count"])
+    pick = [i for i in pick if gold[i]["count"] < 100_000_000][:nq]
+    g = hx["g"]
+    dev = torch.device("cuda:0")
+    as_t = lambda a: torch.from_numpy(a.view(np.int32)).to(dev)
+    ctx = gsi.Context(arena)
+    dg = ctx.load_device(g.n, as_t(g.vlabel), as_t(g.src), as_t(g.dst), as_t(g.elabel), gsi.GSI_GRAPH_KEEP_CR)
+    res, ok = run_ablations(dg, [hx["qs"][i] for i in pick], [gold[i] for i in pick], 1)
+    dg.free()
+    ctx.close()
+    torch.cuda.empty_cache()
+    return dict(workload="R-MAT-23, the %d queries with the most embeddings below 10^8 (indices %s; %d embeddings "
+                         "per pass), rows written, best of 1 pass after a warm-up" %
+                         (len(pick), [gold[i]["index"] for i in pick], sum(gold[i]["count"] for i in pick)),
+                variants=res, parity="bit-exact counts+digests vs oracle in every variant" if ok else "MISMATCH")
 
 
 def progress(msg):
@@ -703,6 +766,9 @@ def main():
         del vl_t, s_t, d_t, l_t
         bx.pop("tensors")
         torch.cuda.empty_cache()
+    if not args.no_ablations and args.workload == "rmat23" and hx["gold"]:
+        res["ablations_rmat23"] = ablation_section_c2(hx, int(gb * (1 << 30)))
+        progress("R-MAT-23 ablations done")
     if not args.no_serving:
         res["serving"] = serving_section(args, int(96 * (1 << 30)))
     if not args.no_cpu_baseline and hx["gold"]:

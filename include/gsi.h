@@ -186,6 +186,11 @@ gsi_status gsi_graph_copy_pcsr(const gsi_graph *g, uint32_t label, uint32_t *hos
 #define GSI_LEVEL_FIRST_EDGE 0x20u /* every row of a level scans the list of the
                                       level's first edge e0 (Algorithm 4), not
                                       its shortest linking list */
+#define GSI_NO_LIST_FILTER 0x8000u /* no level-wide filtering of first-edge lists
+                                      (see gsi_query_run) */
+#define GSI_NO_SINGLE_PASS 0x10000u /* the last per-level level as separate join,
+                                      scan and link launches instead of one
+                                      pass (see gsi_query_run) */
 /* Ablations (measurement and tests only; each implies GSI_NO_FUSED, since
  * they change the per-level kernels): */
 #define GSI_ABL_CR 0x100u          /* N(v,l) by binary search in the compressed
@@ -249,6 +254,15 @@ typedef struct {
  *      join pass);
  *   4. the last level writes rows in query-vertex order (or only counts) and
  *      the order-independent digest.
+ * A per-level level whose |GBA| exceeds twice the directed entries of its
+ * first edge's label l0 (rows repeating hub vertices rescan the same lists)
+ * first filters l0's lists by C(u) once for the level, in order, and its
+ * rows scan the filtered lists (e0's for every row); the rows, count and
+ * digest are unchanged, only |GBA| shrinks (GSI_NO_LIST_FILTER turns this
+ * off).  The last per-level level runs in one launch: each tile joins, finds
+ * the rows before it by a decoupled look-back over the tiles started before
+ * it, and writes its rows at once (output sized at |GBA| rows, then shrunk;
+ * GSI_NO_SINGLE_PASS keeps the separate join, scan and link).
  * Up to 4096 roots one fused workgroup runs the levels while the tables stay
  * small (4096 rows and 16384 |GBA| slots per level, with F, the keep bits and
  * the survivor prefix sums in LDS); the per-level kernels run a level that
@@ -327,6 +341,7 @@ typedef struct {
     double filter_ms;                /* host wall time of the filter step */
     double join_ms;                  /* host wall time of the joins */
     double total_ms;                 /* host wall time of the whole call */
+    uint32_t filtered_levels;        /* bit j: level j scanned filtered first-edge lists */
 } gsi_stats;
 gsi_status gsi_result_stats(const gsi_result *r, gsi_stats *out);
 gsi_status gsi_result_free(gsi_result *r);
@@ -352,6 +367,9 @@ typedef struct {
 typedef struct {
     uint32_t threads;     /* first-tier workgroup size: 64, 256 or 1024 */
     uint32_t grid_scale;  /* eighths of full occupancy launched, 1..8 */
+    uint32_t engine_tiles;/* 256-slot tiles per workgroup of the level-
+                             synchronous join and link: 1, 2, 4 or 8 (each
+                             thread then takes that many slots); 0 = 4 */
 } gsi_batch_schedule;
 
 #define GSI_BATCH_LEVELS_ONLY 0x8u /* test only: no fused tiers; every query runs
@@ -397,10 +415,13 @@ gsi_status gsi_batch_get_info(const gsi_batch *b, gsi_batch_info *out);
 gsi_status gsi_batch_free(gsi_batch *b);
 
 /* Autotuner: runs a sample of the batch (the first min(nq, sample) queries,
- * counts only) under every candidate schedule — first-tier sizes 64, 256
- * and 1024 threads at full and half occupancy — and keeps the fastest as the
+ * counts only) under candidate schedules and keeps the fastest as the
  * graph's tuned schedule (used when gsi_batch_options.schedule.threads is
- * 0).  The winner and its time per query are returned. */
+ * 0): first the fused tiers — first-tier sizes 64, 256 and 1024 threads
+ * (one, four or sixteen wavefronts per query) at full and half occupancy —
+ * then, with the winner, the level-synchronous engine's tiles per workgroup
+ * (1, 2, 4, 8: slots per thread).  The winner and its time per query are
+ * returned. */
 gsi_status gsi_batch_tune(gsi_graph *g, uint32_t nq, const gsi_query_desc *queries, uint32_t sample,
                           gsi_batch_schedule *out, double *out_ms_per_query);
 

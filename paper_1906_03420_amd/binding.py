@@ -28,6 +28,8 @@ GSI_NO_FUSED = 0x4
 GSI_BATCH_LEVELS_ONLY = 0x8
 GSI_NO_CHUNKS = 0x10
 GSI_LEVEL_FIRST_EDGE = 0x20
+GSI_NO_LIST_FILTER = 0x8000
+GSI_NO_SINGLE_PASS = 0x10000
 GSI_HOMOMORPHISM = 0x40
 GSI_ABL_CR = 0x100
 GSI_ABL_TWO_STEP = 0x200
@@ -83,7 +85,8 @@ class gsi_stats(ctypes.Structure):
                 ("first_edge", ctypes.c_uint32 * K), ("n_link", ctypes.c_uint32 * K), ("cand", ctypes.c_uint32 * K),
                 ("rows", ctypes.c_uint64 * K), ("gba", ctypes.c_uint64 * K), ("other_elems", ctypes.c_uint64 * K),
                 ("survivors", ctypes.c_uint64 * K), ("chunks", ctypes.c_uint32), ("chunks_left", ctypes.c_uint32),
-                ("filter_ms", ctypes.c_double), ("join_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+                ("filter_ms", ctypes.c_double), ("join_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("filtered_levels", ctypes.c_uint32)]
 
 
 class gsi_query_desc(ctypes.Structure):
@@ -92,7 +95,7 @@ class gsi_query_desc(ctypes.Structure):
 
 
 class gsi_batch_schedule(ctypes.Structure):
-    _fields_ = [("threads", ctypes.c_uint32), ("grid_scale", ctypes.c_uint32)]
+    _fields_ = [("threads", ctypes.c_uint32), ("grid_scale", ctypes.c_uint32), ("engine_tiles", ctypes.c_uint32)]
 
 
 class gsi_batch_options(ctypes.Structure):
@@ -420,7 +423,8 @@ def gsi_result_stats(r: int) -> dict:
     return dict(k=k, levels=lv, order=list(s.order[:k]), first_edge=list(s.first_edge[:k]),
                 n_link=list(s.n_link[:k]), cand=list(s.cand[:k]), rows=list(s.rows[:k]), gba=list(s.gba[:k]),
                 other_elems=list(s.other_elems[:k]), survivors=list(s.survivors[:k]), chunks=s.chunks,
-                chunks_left=s.chunks_left, filter_ms=s.filter_ms, join_ms=s.join_ms, total_ms=s.total_ms)
+                chunks_left=s.chunks_left, filter_ms=s.filter_ms, join_ms=s.join_ms, total_ms=s.total_ms,
+                filtered_levels=s.filtered_levels)
 
 
 def gsi_result_free(r: int):
@@ -439,9 +443,10 @@ def _descs(queries):
     return arr, keep
 
 
-def gsi_batch_run(g: int, queries, flags: int = 0, threads: int = 0, grid_scale: int = 0) -> int:
+def gsi_batch_run(g: int, queries, flags: int = 0, threads: int = 0, grid_scale: int = 0,
+                  engine_tiles: int = 0) -> int:
     arr, keep = _descs(queries)
-    o = gsi_batch_options(flags, gsi_batch_schedule(threads, grid_scale))
+    o = gsi_batch_options(flags, gsi_batch_schedule(threads, grid_scale, engine_tiles))
     h = VP()
     _check(load_library().gsi_batch_run(g, len(queries), arr, ctypes.byref(o), ctypes.byref(h)))
     return h.value
@@ -470,7 +475,8 @@ def gsi_batch_get_info(b: int) -> dict:
     i = gsi_batch_info()
     _check(load_library().gsi_batch_get_info(b, ctypes.byref(i)))
     d = {f: getattr(i, f) for f, _ in gsi_batch_info._fields_ if f != "schedule"}
-    d["schedule"] = dict(threads=i.schedule.threads, grid_scale=i.schedule.grid_scale)
+    d["schedule"] = dict(threads=i.schedule.threads, grid_scale=i.schedule.grid_scale,
+                         engine_tiles=i.schedule.engine_tiles)
     return d
 
 
@@ -483,12 +489,13 @@ def gsi_batch_tune(g: int, queries, sample: int = 128):
     sc = gsi_batch_schedule()
     ms = ctypes.c_double()
     _check(load_library().gsi_batch_tune(g, len(queries), arr, sample, ctypes.byref(sc), ctypes.byref(ms)))
-    return dict(threads=sc.threads, grid_scale=sc.grid_scale, ms_per_query=ms.value)
+    return dict(threads=sc.threads, grid_scale=sc.grid_scale, engine_tiles=sc.engine_tiles, ms_per_query=ms.value)
 
 
 def gsi_server_create(g: int, flags: int = 0, max_inflight: int = 0, max_admit: int = 0, table_budget: int = 0,
-                      threads: int = 0, grid_scale: int = 0) -> int:
-    o = gsi_server_options(flags, max_inflight, max_admit, 0, table_budget, gsi_batch_schedule(threads, grid_scale))
+                      threads: int = 0, grid_scale: int = 0, engine_tiles: int = 0) -> int:
+    o = gsi_server_options(flags, max_inflight, max_admit, 0, table_budget,
+                           gsi_batch_schedule(threads, grid_scale, engine_tiles))
     h = VP()
     _check(load_library().gsi_server_create(g, ctypes.byref(o), ctypes.byref(h)))
     return h.value
@@ -666,15 +673,16 @@ class Graph:
     def filter(self, q):
         return gsi_query_filter(self.h, self.n, q.k, q.vlabel, q.src, q.dst, q.elabel)
 
-    def batch(self, queries, flags: int = 0, threads: int = 0, grid_scale: int = 0) -> Batch:
-        return Batch(gsi_batch_run(self.h, queries, flags, threads, grid_scale), [q.k for q in queries])
+    def batch(self, queries, flags: int = 0, threads: int = 0, grid_scale: int = 0, engine_tiles: int = 0) -> Batch:
+        return Batch(gsi_batch_run(self.h, queries, flags, threads, grid_scale, engine_tiles), [q.k for q in queries])
 
     def tune(self, queries, sample: int = 128) -> dict:
         return gsi_batch_tune(self.h, queries, sample)
 
     def server(self, flags: int = 0, max_inflight: int = 0, max_admit: int = 0, table_budget: int = 0,
-               threads: int = 0, grid_scale: int = 0) -> Server:
-        return Server(gsi_server_create(self.h, flags, max_inflight, max_admit, table_budget, threads, grid_scale))
+               threads: int = 0, grid_scale: int = 0, engine_tiles: int = 0) -> Server:
+        return Server(gsi_server_create(self.h, flags, max_inflight, max_admit, table_budget, threads, grid_scale,
+                                        engine_tiles))
 
     def free(self):
         if self.h:

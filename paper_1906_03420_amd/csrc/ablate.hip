@@ -209,7 +209,7 @@ __global__ __launch_bounds__(NT) void k_abl_naive_sub(LevelArgs a, uint32_t *buf
     const uint64_t i = row_of(a.F, 0, a.R - 1, p);
     const uint32_t x = a.ci_all[a.loc[(uint64_t)(2 * a.ne) * a.R + i] + (uint32_t)(p - a.F[i])];
     bool in_m = false;
-    for (uint32_t c = 0; !a.homo && c < a.j; c++) in_m |= a.M[(uint64_t)c * a.R + i] == x;
+    for (uint32_t c = 0; !a.homo && c < a.j; c++) in_m |= a.M[(uint64_t)c * a.ldm + i] == x;
     buf[p] = in_m ? NONE32 : x;
 }
 

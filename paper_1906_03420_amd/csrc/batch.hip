@@ -396,6 +396,8 @@ gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32
     if (sched.threads != 64 && sched.threads != 256 && sched.threads != 1024)
         fail(GSI_E_INVALID, "schedule threads must be 64, 256 or 1024");
     if (sched.grid_scale < 1 || sched.grid_scale > 8) fail(GSI_E_INVALID, "schedule grid_scale must be 1..8");
+    if (sched.engine_tiles > 8 || (sched.engine_tiles & (sched.engine_tiles - 1)))
+        fail(GSI_E_INVALID, "schedule engine_tiles must be 0, 1, 2, 4 or 8");
     std::vector<HostQuery> hq(nq);
     for (uint32_t i = 0; i < nq; i++) {
         try {
@@ -423,7 +425,7 @@ gsi_batch *run_batch(gsi_graph *g, uint32_t nq, const gsi_query_desc *qd, uint32
     std::vector<WideQuery> wq = admit_round(g, hp, sp, {}, b->count_only, (flags & GSI_BATCH_LEVELS_ONLY) != 0,
                                             sched, &as);
     auto tw0 = std::chrono::steady_clock::now();
-    wide_run(g, wq, b->count_only);
+    wide_run(g, wq, b->count_only, sched.engine_tiles);
     for (auto &x : wq) finish_slot(x, b->slots[x.qi]);
     b->info.empty = as.empty;
     b->info.tier1 = as.tier1;
@@ -459,7 +461,7 @@ gsi_status gsi_batch_run(gsi_graph *g, uint32_t nq, const gsi_query_desc *qs, co
         *out = nullptr;
         gsi_batch_schedule sc = opt ? opt->schedule : gsi_batch_schedule{0, 0};
         if (sc.threads == 0) sc = g->tuned;
-        if (sc.threads == 0) sc = gsi_batch_schedule{256, 8};
+        if (sc.threads == 0) sc = gsi_batch_schedule{256, 8, 0};
         gsi_ctx *c = g->ctx;
         Busy busy(c);
         GSI_HIP(hipSetDevice(c->device));
@@ -525,10 +527,11 @@ gsi_status gsi_batch_tune(gsi_graph *g, uint32_t nq, const gsi_query_desc *qs, u
         GSI_HIP(hipSetDevice(c->device));
         const uint32_t n = std::max<uint32_t>(1, std::min(nq, sample ? sample : 128u));
         if (nq == 0) fail(GSI_E_INVALID, "no queries to tune on");
-        const gsi_batch_schedule cands[] = {{64, 8}, {64, 4}, {256, 8}, {256, 4}, {1024, 8}, {1024, 4}};
+        const gsi_batch_schedule cands[] = {{64, 8, 0},  {64, 4, 0},   {256, 8, 0},
+                                            {256, 4, 0}, {1024, 8, 0}, {1024, 4, 0}};
         double best = 1e300;
-        gsi_batch_schedule win{256, 8};
-        for (const auto &sc : cands) {
+        gsi_batch_schedule win{256, 8, 0};
+        auto trial = [&](const gsi_batch_schedule &sc) {
             auto t0 = std::chrono::steady_clock::now();
             gsi_batch *b = run_batch(g, n, qs, GSI_COUNT_ONLY, sc);
             double ms = ms_since(t0);
@@ -537,7 +540,12 @@ gsi_status gsi_batch_tune(gsi_graph *g, uint32_t nq, const gsi_query_desc *qs, u
                 best = ms;
                 win = sc;
             }
-        }
+        };
+        for (const auto &sc : cands) trial(sc);
+        // the engine's tiles per workgroup, with the fused tiers chosen
+        const gsi_batch_schedule tiers = win;
+        for (uint32_t tiles : {1u, 2u, 8u}) trial(gsi_batch_schedule{tiers.threads, tiers.grid_scale, tiles});
+        if (win.engine_tiles == 0) win.engine_tiles = 4;
         g->tuned = win;
         *out = win;
         if (out_ms) *out_ms = best / n;

@@ -25,6 +25,7 @@ struct EdgeRef {
 struct LevelArgs {
     const uint32_t *M;
     uint64_t R;
+    uint64_t ldm;  // column stride of M (>= R): column c of row i at M[c * ldm + i]
     uint32_t j, ne, e0, k;
     uint32_t pick;  // 1: each row scans its shortest linking list (else e0's)
     uint32_t homo;  // 1: homomorphism (no subtraction of m_i, Sec. VII-A)
@@ -32,6 +33,16 @@ struct LevelArgs {
     // representation; survivors counted, then the join repeated to write
     // (two-step output); last-level rows written without LDS staging
     uint32_t abl_cr, abl_two_step, abl_no_stage;
+    // 1: every row scans its e0 list already filtered by C(u) (held in
+    // ci_all for this level), so the join skips the C(u) test
+    uint32_t prefiltered;
+    // single-pass last level (k_join_last): per-tile look-back status words,
+    // the dynamic tile counter and a failure flag (both zeroed before the
+    // launch), and where the last tile writes the total row count
+    unsigned long long *tstat;
+    uint32_t *tctr;
+    uint64_t *total;
+    uint64_t out_cap;  // rows the output can hold
     EdgeRef e[GSI_MAX_K];
     const uint32_t *ci_all;  // every label's lists
     const uint64_t *Cu;
@@ -82,7 +93,7 @@ __device__ __forceinline__ uint64_t row_of(const uint64_t *F, uint64_t lo, uint6
 // linking list of the row
 __device__ __forceinline__ bool slot_keep(const LevelArgs &a, uint64_t i, uint32_t x) {
     bool keep = (a.Cu[x >> 6] >> (x & 63)) & 1ull;
-    for (uint32_t c = 0; keep && !a.homo && c < a.j; c++) keep = a.M[(uint64_t)c * a.R + i] != x;
+    for (uint32_t c = 0; keep && !a.homo && c < a.j; c++) keep = a.M[(uint64_t)c * a.ldm + i] != x;
     const uint32_t be = (keep && a.ne > 1) ? a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] : a.e0;
     for (uint32_t e = 0; keep && e < a.ne; e++) {
         if (e == be) continue;

@@ -564,7 +564,7 @@ __global__ __launch_bounds__(QT) void k_locate(LevelArgs a) {
         uint64_t all = 0;
         for (uint32_t e = 0; e < a.ne; e++) {
             const EdgeRef &er = a.e[e];
-            uint32_t v = a.M[(uint64_t)er.col * a.R + i];
+            uint32_t v = a.M[(uint64_t)er.col * a.ldm + i];
             uint2 r = a.abl_cr ? cr_find(er, v) : pcsr_find(er.gl, er.G, er.H, v);
             a.loc[(uint64_t)e * a.R + i] = r.x;
             a.loc[(uint64_t)(a.ne + e) * a.R + i] = r.y;
@@ -617,6 +617,63 @@ void tile_rows(gsi_ctx *c, const uint64_t *F, uint64_t R, uint64_t ntiles, uint6
     launch(c, "k_tile_rows", 8.0 * (R + 1) + 8.0 * (ntiles + 1), k_tile_rows, nblocks(R), QT, F, R, ntiles, (uint32_t)QT,
            tile_row);
 }
+
+// Level-wide filtering of the first-edge lists.  When the rows of a level
+// scan far more list elements than label l0 holds (rows repeat hub
+// vertices: Sec. VI-B's duplicate reads, level-wide), the C(u) test is run
+// once per element of l0's lists instead of once per slot: keep bits over
+// l0's ci, their per-word prefix counts, and the kept elements compacted in
+// order (every list stays contiguous and ascending, so list [s, s+len)
+// becomes [rank(s), rank(s+len)) of the compacted array).  Each row then
+// scans its list's members of C(u) only; the survivors, and their order,
+// are unchanged.
+__global__ __launch_bounds__(QT) void k_fn_bits(const uint32_t *ci, uint64_t n, const uint64_t *Cu, uint64_t *bits,
+                                               uint32_t *wcnt) {
+    const uint64_t p = (uint64_t)blockIdx.x * QT + threadIdx.x;
+    bool keep = false;
+    if (p < n) {
+        const uint32_t x = ci[p];
+        keep = (Cu[x >> 6] >> (x & 63)) & 1ull;
+    }
+    const uint64_t m = __ballot(keep);
+    if (lane_id() == 0 && p < n) {
+        bits[p >> 6] = m;
+        wcnt[p >> 6] = (uint32_t)__popcll(m);
+    }
+}
+
+__global__ __launch_bounds__(QT) void k_fn_compact(const uint32_t *ci, uint64_t n, const uint64_t *bits,
+                                                  const uint64_t *wpre, uint32_t *fn) {
+    const uint64_t p = (uint64_t)blockIdx.x * QT + threadIdx.x;
+    if (p >= n) return;
+    const uint64_t m = bits[p >> 6];
+    if ((m >> (p & 63)) & 1ull) fn[wpre[p >> 6] + (uint64_t)__popcll(m & ((1ull << (p & 63)) - 1))] = ci[p];
+}
+
+// kept elements of l0's lists before position p
+__device__ __forceinline__ uint64_t fn_rank(const uint64_t *bits, const uint64_t *wpre, uint64_t p) {
+    const uint64_t w = p >> 6;
+    const uint32_t b = (uint32_t)(p & 63);
+    return b ? wpre[w] + (uint64_t)__popcll(bits[w] & ((1ull << b) - 1)) : wpre[w];
+}
+
+// every row scans its e0 list, filtered: its slots are that list's members
+// of C(u)
+__global__ __launch_bounds__(QT) void k_fn_relocate(LevelArgs a, const uint64_t *bits, const uint64_t *wpre) {
+    const uint64_t i = (uint64_t)blockIdx.x * QT + threadIdx.x;
+    if (i >= a.R) return;
+    const uint32_t s = a.loc[(uint64_t)a.e0 * a.R + i];
+    const uint32_t len = a.loc[(uint64_t)(a.ne + a.e0) * a.R + i];
+    const uint64_t fs = len ? fn_rank(bits, wpre, s) : 0;
+    const uint64_t fe = len ? fn_rank(bits, wpre, (uint64_t)s + len) : 0;
+    a.bound[i] = (uint32_t)(fe - fs);
+    a.loc[(uint64_t)(2 * a.ne) * a.R + i] = (uint32_t)fs;
+    if (a.ne > 1) a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] = a.e0;
+}
+
+// |GBA| over the label's directed entries from which the level filters its
+// first-edge lists once for the whole level
+constexpr double FN_FACTOR = 2.0;
 
 // The per-level join and link work on tiles of SPT x 256 |GBA| slots.  On
 // large levels (SPT = 4) a 256-thread workgroup takes four consecutive
@@ -762,7 +819,7 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
     // so that the remaining tests, the costly ones, run in dense waves
 #pragma unroll
     for (uint32_t r = 0; r < SPT; r++) {
-        if (kp[r]) kp[r] = (a.Cu[xs[r] >> 6] >> (xs[r] & 63)) & 1ull;
+        if (kp[r] && !a.prefiltered) kp[r] = (a.Cu[xs[r] >> 6] >> (xs[r] & 63)) & 1ull;
         const uint64_t mask = __ballot(kp[r]);
         if (mask) {
             uint32_t base = 0;
@@ -786,10 +843,10 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
         bool keep = true;
         if (!a.homo) {
             for (uint32_t c = 0; c < a.j; c += 4) {
-                uint32_t m0 = a.M[(uint64_t)c * a.R + i];
-                uint32_t m1 = c + 1 < a.j ? a.M[(uint64_t)(c + 1) * a.R + i] : ~x;
-                uint32_t m2 = c + 2 < a.j ? a.M[(uint64_t)(c + 2) * a.R + i] : ~x;
-                uint32_t m3 = c + 3 < a.j ? a.M[(uint64_t)(c + 3) * a.R + i] : ~x;
+                uint32_t m0 = a.M[(uint64_t)c * a.ldm + i];
+                uint32_t m1 = c + 1 < a.j ? a.M[(uint64_t)(c + 1) * a.ldm + i] : ~x;
+                uint32_t m2 = c + 2 < a.j ? a.M[(uint64_t)(c + 2) * a.ldm + i] : ~x;
+                uint32_t m3 = c + 3 < a.j ? a.M[(uint64_t)(c + 3) * a.ldm + i] : ~x;
                 keep = keep && m0 != x && m1 != x && m2 != x && m3 != x;
             }
         }
@@ -906,7 +963,7 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
                 for (uint32_t c = 0; c < a.j; c += 4) {
                     uint32_t m[4];
 #pragma unroll
-                    for (uint32_t k4 = 0; k4 < 4; k4++) m[k4] = c + k4 < a.j ? a.M[(uint64_t)(c + k4) * a.R + i] : 0u;
+                    for (uint32_t k4 = 0; k4 < 4; k4++) m[k4] = c + k4 < a.j ? a.M[(uint64_t)(c + k4) * a.ldm + i] : 0u;
 #pragma unroll
                     for (uint32_t k4 = 0; k4 < 4; k4++)
                         if (c + k4 < a.j) a.Mn[(uint64_t)(c + k4) * a.S + pos] = m[k4];
@@ -920,7 +977,7 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
 #pragma unroll
                     for (uint32_t k4 = 0; k4 < 4; k4++) {
                         const uint32_t c = u0 + k4 < a.k ? a.qcol[u0 + k4] : a.j;
-                        val[k4] = c < a.j ? a.M[(uint64_t)c * a.R + i] : x;
+                        val[k4] = c < a.j ? a.M[(uint64_t)c * a.ldm + i] : x;
                     }
 #pragma unroll
                     for (uint32_t k4 = 0; k4 < 4; k4++) {
@@ -966,6 +1023,258 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
             a.dig_part[2 * tile] = ts;
             a.dig_part[2 * tile + 1] = tx;
         }
+    }
+}
+
+// ------------------------------------------ single-pass last level
+// The last join level in one launch: each workgroup joins its tile (as
+// k_join), learns where its survivors start in the output from the tiles
+// before it by a decoupled look-back (Merrill and Garland, "Single-pass
+// Parallel Prefix Scan with Decoupled Look-back", 2016), and writes its rows
+// there at once (as k_link), so the keep bitmap, the tile-count scan, the
+// link's second gather of x and its row search all go away.  Tiles are
+// numbered in the order workgroups start (an atomic counter), so a tile
+// only ever waits for tiles that are already running; each publishes its
+// own count before it waits.  A status word holds the value in bits 0..61
+// and a flag in bits 62..63: 1 = the tile's count, 2 = the count of every
+// row up to and including the tile.
+constexpr uint64_t LB_AGG = 1ull << 62, LB_PRE = 2ull << 62, LB_VAL = (1ull << 62) - 1;
+constexpr uint32_t LB_SPIN_MAX = 1u << 22;  // re-reads of an unpublished predecessor before giving up
+
+// wave 0 of the workgroup: rows before this tile (uniform in the wave)
+__device__ __forceinline__ uint64_t lookback(unsigned long long *st, uint64_t tile, uint64_t count, uint32_t *err) {
+    const uint32_t lane = lane_id();
+    if (tile == 0) {
+        if (lane == 0) __hip_atomic_store(st, LB_PRE | count, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        return 0;
+    }
+    if (lane == 0) __hip_atomic_store(st + tile, LB_AGG | count, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t excl = 0;
+    int64_t t = (int64_t)tile - 1;  // nearest predecessor not yet added
+    uint32_t spins = 0;
+    for (;;) {
+        const int64_t idx = t - (int64_t)lane;
+        const uint64_t v = idx >= 0 ? __hip_atomic_load(st + idx, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
+                                    : LB_PRE;  // before tile 0: a prefix of 0
+        const uint32_t flag = (uint32_t)(v >> 62);
+        const uint64_t val = v & LB_VAL;
+        const uint64_t isP = __ballot(flag == 2), isZ = __ballot(flag == 0);
+        const uint32_t p = isP ? (uint32_t)__ffsll((unsigned long long)isP) - 1 : 64u;
+        const uint64_t before = p == 64 ? ~0ull : ((1ull << p) - 1);
+        const uint64_t zb = isZ & before;
+        if (zb) {
+            // add the published counts up to the first unpublished tile
+            const uint32_t z = (uint32_t)__ffsll((unsigned long long)zb) - 1;
+            excl += wave_sum(lane < z ? val : 0ull);
+            t -= z;
+            if (++spins > LB_SPIN_MAX) {
+                if (lane == 0) atomicOr(err, 1u);
+                break;
+            }
+            continue;
+        }
+        excl += wave_sum(lane <= p ? val : 0ull);
+        if (p < 64) break;
+        t -= 64;
+    }
+    if (lane == 0) __hip_atomic_store(st + tile, LB_PRE | (excl + count), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
+}
+
+// FINAL: rows in query-vertex order to a.out (row-major) and the digest;
+// else the next table to a.Mn, column-major with column stride a.out_cap.
+template <uint32_t SPT, bool FINAL>
+__global__ __launch_bounds__(QT) void k_join_pass(LevelArgs a) {
+    constexpr uint32_t TS = SPT * QT;
+    __shared__ uint32_t s_row[TS];    // row of each slot (staged tiles)
+    __shared__ uint32_t s_base[TS];   // per row: ci_all position of slot 0
+    __shared__ uint32_t s_xv[TS];     // element of each slot
+    __shared__ uint32_t s_x[TS];      // elements that passed C(u), compacted
+    __shared__ uint32_t s_ri[TS];     // and their rows
+    __shared__ uint16_t s_slot[TS];   // and their slots
+    __shared__ uint16_t s_list[TS];   // kept slots in slot order
+    __shared__ uint64_t s_keep[TS / 64];
+    __shared__ uint32_t s_pre[TS / 64 + 1];
+    __shared__ uint32_t s_w[QT / 64];
+    __shared__ uint32_t s_rows[QT * LINK_STAGE_K];
+    __shared__ uint64_t s_d[2][QT / 64];
+    __shared__ uint32_t s_n;
+    __shared__ uint64_t s_tile, s_off;
+    if (threadIdx.x == 0) {
+        s_n = 0;
+        s_tile = atomicAdd(a.tctr, 1u);
+    }
+    if (threadIdx.x < TS / 64) s_keep[threadIdx.x] = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < SPT; k++) s_row[threadIdx.x * SPT + k] = 0;
+    __syncthreads();
+    const uint64_t tile = s_tile;
+    const uint64_t p0 = tile * TS;
+    const TileRows tr = stage_slot_rows<SPT>(a, tile, s_row, s_base, s_w);
+    const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t xs[SPT];
+    uint64_t is[SPT];
+    bool kp[SPT];
+#pragma unroll
+    for (uint32_t r = 0; r < SPT; r++) {
+        const uint32_t sl = r * QT + threadIdx.x;
+        kp[r] = p0 + sl < a.gba;
+        xs[r] = 0;
+        is[r] = 0;
+        if (kp[r]) {
+            uint32_t pos;
+            slot_row(a, tr, s_row, s_base, p0, sl, &is[r], &pos);
+            xs[r] = a.ci_all[pos];
+        }
+        s_xv[sl] = xs[r];
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < SPT; r++) {
+        if (kp[r] && !a.prefiltered) kp[r] = (a.Cu[xs[r] >> 6] >> (xs[r] & 63)) & 1ull;
+        const uint64_t mask = __ballot(kp[r]);
+        if (mask) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&s_n, (uint32_t)__popcll(mask));
+            base = __shfl(base, 0, 64);
+            if (kp[r]) {
+                const uint32_t idx = base + rank_below(mask);
+                s_slot[idx] = (uint16_t)(r * QT + threadIdx.x);
+                s_x[idx] = xs[r];
+                s_ri[idx] = (uint32_t)(is[r] - tr.r_lo);
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t nc = __builtin_amdgcn_readfirstlane(s_n);
+    for (uint32_t e = threadIdx.x; e < nc; e += QT) {
+        const uint32_t slot = s_slot[e], x = s_x[e];
+        const uint64_t i = tr.r_lo + s_ri[e];
+        bool keep = true;
+        if (!a.homo) {
+            for (uint32_t c = 0; c < a.j; c += 4) {
+                uint32_t m0 = a.M[(uint64_t)c * a.ldm + i];
+                uint32_t m1 = c + 1 < a.j ? a.M[(uint64_t)(c + 1) * a.ldm + i] : ~x;
+                uint32_t m2 = c + 2 < a.j ? a.M[(uint64_t)(c + 2) * a.ldm + i] : ~x;
+                uint32_t m3 = c + 3 < a.j ? a.M[(uint64_t)(c + 3) * a.ldm + i] : ~x;
+                keep = keep && m0 != x && m1 != x && m2 != x && m3 != x;
+            }
+        }
+        const uint32_t be = (keep && a.ne > 1) ? a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] : a.e0;
+        for (uint32_t e2 = 0; keep && e2 < a.ne; e2++) {
+            if (e2 == be) continue;
+            uint32_t st = a.loc[(uint64_t)e2 * a.R + i];
+            uint32_t len = a.loc[(uint64_t)(a.ne + e2) * a.R + i];
+            keep = in_sorted(a.e[e2].ci + st, len, x);
+        }
+        if (keep) atomicOr(&s_keep[slot >> 6], 1ull << (slot & 63));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (uint32_t q = 0; q < TS / 64; q++) {
+            s_pre[q] = run;
+            run += (uint32_t)__popcll(s_keep[q]);
+        }
+        s_pre[TS / 64] = run;
+    }
+    __syncthreads();
+    const uint32_t n = __builtin_amdgcn_readfirstlane(s_pre[TS / 64]);
+    if (w == 0) {
+        const uint64_t off = lookback(a.tstat, tile, n, a.tctr + 1);
+        if (lane == 0) {
+            s_off = off;
+            if (tile + 1 == (a.gba + TS - 1) / TS) *a.total = off + n;
+        }
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < SPT; r++) {
+        const uint32_t wi = r * (QT / 64) + w;
+        const uint64_t word = s_keep[wi];
+        if ((word >> lane) & 1ull) s_list[s_pre[wi] + rank_below(word)] = (uint16_t)(r * QT + threadIdx.x);
+    }
+    __syncthreads();
+    const uint64_t tbase = s_off;
+    if (!FINAL) {
+        // the next table: survivor q of the tile is row tbase + q of M'
+        for (uint32_t q = threadIdx.x; q < n; q += QT) {
+            const uint64_t pos = tbase + q;
+            if (pos >= a.out_cap) break;
+            const uint32_t slot = s_list[q];
+            const uint64_t i = tr.staged ? tr.r_lo + s_row[slot] : row_of(a.F, tr.r_lo, tr.r_hi, p0 + slot);
+            for (uint32_t c = 0; c < a.j; c += 4) {
+                uint32_t m[4];
+#pragma unroll
+                for (uint32_t k4 = 0; k4 < 4; k4++) m[k4] = c + k4 < a.j ? a.M[(uint64_t)(c + k4) * a.ldm + i] : 0u;
+#pragma unroll
+                for (uint32_t k4 = 0; k4 < 4; k4++)
+                    if (c + k4 < a.j) a.Mn[(uint64_t)(c + k4) * a.out_cap + pos] = m[k4];
+            }
+            a.Mn[(uint64_t)a.j * a.out_cap + pos] = s_xv[slot];
+        }
+        return;
+    }
+    const bool stage = !a.count_only && a.k <= LINK_STAGE_K;
+    uint64_t hs = 0, hx = 0;
+    for (uint32_t q0 = 0; q0 < n; q0 += QT) {
+        const uint32_t q = q0 + threadIdx.x;
+        const uint64_t pos = tbase + q;
+        const bool mine = q < n && (a.count_only || pos < a.out_cap);
+        if (mine) {
+            const uint32_t slot = s_list[q];
+            uint64_t i;
+            if (tr.staged) {
+                i = tr.r_lo + s_row[slot];
+            } else {
+                i = row_of(a.F, tr.r_lo, tr.r_hi, p0 + slot);
+            }
+            const uint32_t x = s_xv[slot];
+            uint64_t f = 14695981039346656037ull;
+            for (uint32_t u0 = 0; u0 < a.k; u0 += 4) {
+                uint32_t val[4];
+#pragma unroll
+                for (uint32_t k4 = 0; k4 < 4; k4++) {
+                    const uint32_t c = u0 + k4 < a.k ? a.qcol[u0 + k4] : a.j;
+                    val[k4] = c < a.j ? a.M[(uint64_t)c * a.ldm + i] : x;
+                }
+#pragma unroll
+                for (uint32_t k4 = 0; k4 < 4; k4++) {
+                    const uint32_t u = u0 + k4;
+                    if (u >= a.k) break;
+                    if (stage) s_rows[threadIdx.x * a.k + u] = val[k4];
+                    else if (!a.count_only) a.out[pos * a.k + u] = val[k4];
+                    f = fnv_word(f, val[k4]);
+                }
+            }
+            const uint64_t h = mix64(f);
+            hs += h;
+            hx ^= h;
+        }
+        if (stage) {
+            __syncthreads();
+            const uint64_t first = tbase + q0;
+            uint64_t end = tbase + (q0 + QT < n ? q0 + QT : n);
+            if (end > a.out_cap) end = a.out_cap;
+            const uint32_t nw = first < end ? (uint32_t)(end - first) * a.k : 0u;
+            uint32_t *dst = a.out + first * a.k;
+            for (uint32_t t = threadIdx.x; t < nw; t += QT) dst[t] = s_rows[t];
+            __syncthreads();
+        }
+    }
+    const uint64_t sum = wave_sum(hs), xr = wave_xor(hx);
+    if (lane == 0) {
+        s_d[0][w] = sum;
+        s_d[1][w] = xr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t ts = 0, tx = 0;
+#pragma unroll
+        for (int q = 0; q < QT / 64; q++) {
+            ts += s_d[0][q];
+            tx ^= s_d[1][q];
+        }
+        a.dig_part[2 * tile] = ts;
+        a.dig_part[2 * tile + 1] = tx;
     }
 }
 
@@ -1122,7 +1431,8 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     constexpr uint32_t ABL = GSI_ABL_CR | GSI_ABL_TWO_STEP | GSI_ABL_NO_STAGING | JOIN_ABL | GSI_ABL_DUP_REMOVAL;
     const uint32_t flags = (opt ? opt->flags : 0u) | ((opt && (opt->flags & ABL)) ? GSI_NO_FUSED : 0u);
     if (opt && (opt->flags & ~(GSI_COUNT_ONLY | GSI_FILTER_LABEL_ONLY | GSI_NO_FUSED | GSI_NO_CHUNKS |
-                               GSI_LEVEL_FIRST_EDGE | GSI_HOMOMORPHISM | ABL)))
+                               GSI_LEVEL_FIRST_EDGE | GSI_HOMOMORPHISM | GSI_NO_LIST_FILTER | GSI_NO_SINGLE_PASS |
+                               ABL)))
         fail(GSI_E_INVALID, "unknown query flag");
     if (__builtin_popcount(flags & JOIN_ABL) > 1 || ((flags & JOIN_ABL) && (flags & GSI_ABL_TWO_STEP)))
         fail(GSI_E_INVALID, "at most one join ablation, and not with GSI_ABL_TWO_STEP");
@@ -1133,6 +1443,8 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     const bool homo = (flags & GSI_HOMOMORPHISM) != 0;
     // each row scans its shortest linking list unless the first edge is fixed
     const bool per_row = !(flags & GSI_LEVEL_FIRST_EDGE) && !(opt && opt->first_edge);
+    // level-wide filtered first-edge lists; off for the paper's ablations
+    const bool level_filter = !(flags & (GSI_NO_LIST_FILTER | ABL));
     const uint64_t max_rows = opt ? opt->max_rows : 0;
 
     std::vector<uint32_t> order, e0src;
@@ -1562,6 +1874,8 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         if (run_fused(1, m0_in_fused ? b0 : nullptr, jstart)) return finish();
     }
     uint32_t fused_stuck = NONE32;  // level at which the workgroup last stopped without progress
+    // column stride of M when a one-pass level wrote it at its capacity (0: R)
+    uint64_t Mld = 0;
 
     for (uint32_t j = jstart; j < k; j++) {
         const uint32_t u = order[j];
@@ -1571,10 +1885,12 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         memset(&a, 0, sizeof(a));
         a.M = M;
         a.R = R;
+        a.ldm = Mld ? Mld : R;
         a.j = j;
         a.k = k;
         a.Cu = bits + (uint64_t)u * nwords;
         uint32_t ne = 0;
+        uint32_t elab[GSI_MAX_K] = {0};  // label of each linking edge
         for (uint32_t i = 0; i < j; i++)
             for (auto &p : q.adj[u])
                 if (p.first == order[i]) {
@@ -1592,6 +1908,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
                         er.cr_off = g->cr_off + g->group_base[l];
                     }
                     er.cr_end = (uint32_t)(g->ci_base[l] + 2 * g->edges[l]);
+                    elab[ne] = l;
                     if (order[i] == e0src[j]) a.e0 = ne;
                     ne++;
                 }
@@ -1627,7 +1944,36 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         uint64_t sc[2];
         read_scalars(c, dscal + 2, sc, 2);
         if (!prof) sc[0] = 0;
-        const uint64_t gba = sc[1];
+        uint64_t gba = sc[1];
+        // a level whose rows rescan l0's lists many times over: filter those
+        // lists by C(u) once and let the rows scan the filtered copies
+        Block fnb(c);
+        if (level_filter && gba) {
+            const uint32_t l0 = elab[a.e0];
+            const uint64_t El = 2 * g->edges[l0];
+            if (El && (double)gba > FN_FACTOR * (double)El && El < 0xFFFFFFFFull) {
+                const uint64_t nw = (El + 63) / 64;
+                uint64_t *fbits = ls.get<uint64_t>(nw, "filtered-list bits");
+                uint32_t *wcnt = ls.get<uint32_t>(nw, "filtered-list word counts");
+                uint64_t *wpre = ls.get<uint64_t>(nw + 1, "filtered-list word offsets");
+                const uint32_t *ci_l0 = a.e[a.e0].ci;
+                launch(c, "k_fn_bits", 4.0 * El + El / 8.0 + 4.0 * nw, k_fn_bits, nblocks(El), QT, ci_l0, El, a.Cu,
+                       fbits, wcnt);
+                exclusive_scan(c, wcnt, nw, wpre, ls, dscal + 3);
+                uint64_t kept;
+                read_scalars(c, dscal + 3, &kept, 1);
+                uint32_t *fn = fnb.get<uint32_t>(kept ? kept : 1, "filtered lists");
+                launch(c, "k_fn_compact", 4.0 * El + El / 8.0 + 8.0 * nw + 4.0 * kept, k_fn_compact, nblocks(El), QT,
+                       ci_l0, El, (const uint64_t *)fbits, (const uint64_t *)wpre, fn);
+                launch(c, "k_fn_relocate", (double)R * (8.0 + 4.0 + 8.0 + 32.0), k_fn_relocate, (uint32_t)nbr, QT, a,
+                       (const uint64_t *)fbits, (const uint64_t *)wpre);
+                exclusive_scan(c, a.bound, R, F, ls, dscal + 3);
+                read_scalars(c, dscal + 3, &gba, 1);
+                a.ci_all = fn;
+                a.prefiltered = 1;
+                st.filtered_levels |= 1u << j;
+            }
+        }
         st.gba[j] = gba;
         st.other_elems[j] = sc[0];
         st.levels = j;
@@ -1639,6 +1985,99 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         const uint32_t spt = gba >= WIDE_TILE_SLOTS ? 4u : 1u;
         const uint32_t ts = spt * QT;
         const uint64_t ntiles = (gba + ts - 1) / ts;
+        // The last level in one pass (join, look-back, rows) when the output
+        // can be sized at |GBA| rows, its survivors' upper bound.
+        const uint64_t before_rows = (cp.active && !cp.merged) ? cp.count : 0;
+        const bool single_pass = final_level && !(flags & (ABL | GSI_NO_SINGLE_PASS)) &&
+                                 (count_only || (gba + before_rows) * k * 4 <= c->arena.largest_free() / 2);
+        if (single_pass) {
+            uint64_t *trow = ls.get<uint64_t>(ntiles + 1, "tile rows");
+            a.tile_row = trow;
+            launch(c, "k_tile_rows", 8.0 * (R + 1) + 8.0 * (ntiles + 1), k_tile_rows, nblocks(R), QT,
+                   (const uint64_t *)F, R, ntiles, ts, trow);
+            // look-back status words, then [tile counter, failure flag] and the total
+            uint64_t *lbw = ls.get<uint64_t>(ntiles + 2, "look-back words");
+            fill_u64(c, lbw, 0, ntiles + 2);
+            a.tstat = reinterpret_cast<unsigned long long *>(lbw);
+            a.tctr = reinterpret_cast<uint32_t *>(lbw + ntiles);
+            a.total = lbw + ntiles + 1;
+            a.dig_part = ls.get<uint64_t>(2 * ntiles, "digest partials");
+            uint32_t *front = nullptr;
+            if (!count_only) {
+                front = persist<uint32_t>(c, (gba + before_rows) * k, "result rows");
+                a.out = front + before_rows * k;
+                res->rows = front;
+            }
+            a.out_cap = count_only ? 0 : gba;
+            // join bytes, plus the rows written and the row values they read
+            const double jb = 4.0 * gba + (double)R * (8.0 + 8.0 * ne + 4.0 * j) + 4.0 * (double)sc[0] + 16.0 * ntiles;
+            if (spt == 4) launch(c, "k_join_last", jb, k_join_pass<4, true>, (uint32_t)ntiles, QT, a);
+            else launch(c, "k_join_last", jb, k_join_pass<1, true>, (uint32_t)ntiles, QT, a);
+            uint64_t tw[2];
+            read_scalars(c, lbw + ntiles, tw, 2);
+            if (tw[0] >> 32) fail(GSI_E_INTERNAL, "look-back of the last level did not complete");
+            const uint64_t S = tw[1];
+            st.survivors[j] = S;
+            if ((c->flags & GSI_CTX_PROFILE) && !c->recs.empty())
+                c->recs.back().bytes = jb + (count_only ? 0.0 : 4.0 * k * S) + 4.0 * j * S;
+            if (max_rows && S > max_rows) fail(GSI_E_CAPACITY, "rows exceed max_rows at level %u", j);
+            reduce_pairs(c, a.dig_part, ntiles, dscal);
+            uint64_t dg[2];
+            read_scalars(c, dscal, dg, 2);
+            if (front) {
+                if (S + before_rows == 0) {
+                    c->arena.release(front);
+                    front = nullptr;
+                } else {
+                    c->arena.shrink(front, (S + before_rows) * k * 4);
+                }
+            }
+            res->rows = front;
+            res->count = S;
+            res->digest[0] = dg[0];
+            res->digest[1] = dg[1];
+            merge_chunks(front);
+            st.join_ms = ms_since(tj);
+            return finish();
+        }
+        // An inner level in one pass too, when its rows scan filtered lists
+        // and have one linking edge (nearly every slot survives, so the
+        // next table, written at |GBA| rows per column, wastes little).
+        const bool inner_pass = !final_level && a.prefiltered && ne == 1 && !(flags & (ABL | GSI_NO_SINGLE_PASS)) &&
+                                (uint64_t)(j + 1) * gba * 4 <= c->arena.largest_free() / 2;
+        if (inner_pass) {
+            uint64_t *trow = ls.get<uint64_t>(ntiles + 1, "tile rows");
+            a.tile_row = trow;
+            launch(c, "k_tile_rows", 8.0 * (R + 1) + 8.0 * (ntiles + 1), k_tile_rows, nblocks(R), QT,
+                   (const uint64_t *)F, R, ntiles, ts, trow);
+            uint64_t *lbw = ls.get<uint64_t>(ntiles + 2, "look-back words");
+            fill_u64(c, lbw, 0, ntiles + 2);
+            a.tstat = reinterpret_cast<unsigned long long *>(lbw);
+            a.tctr = reinterpret_cast<uint32_t *>(lbw + ntiles);
+            a.total = lbw + ntiles + 1;
+            Block Mn(c);
+            a.Mn = Mn.get<uint32_t>((uint64_t)(j + 1) * gba, "next table");
+            a.out_cap = gba;
+            const double jb = 4.0 * gba + (double)R * (8.0 + 8.0 * ne + 4.0 * j) + 16.0 * ntiles;
+            if (spt == 4) launch(c, "k_join_pass", jb, k_join_pass<4, false>, (uint32_t)ntiles, QT, a);
+            else launch(c, "k_join_pass", jb, k_join_pass<1, false>, (uint32_t)ntiles, QT, a);
+            uint64_t tw[2];
+            read_scalars(c, lbw + ntiles, tw, 2);
+            if (tw[0] >> 32) fail(GSI_E_INTERNAL, "look-back of level %u did not complete", j);
+            const uint64_t S = tw[1];
+            st.survivors[j] = S;
+            if ((c->flags & GSI_CTX_PROFILE) && !c->recs.empty())
+                c->recs.back().bytes = jb + 4.0 * (j + 1) * S + 4.0 * j * S;
+            if (S == 0) return done();
+            if (max_rows && S > max_rows) fail(GSI_E_CAPACITY, "rows exceed max_rows at level %u", j);
+            Mb.reset();
+            Mb.p = Mn.p;
+            Mn.p = nullptr;
+            M = a.Mn;
+            Mld = gba;
+            R = S;
+            continue;  // the fused workgroup is not taken back after a one-pass level
+        }
         a.bitmap = ls.get<uint64_t>(ntiles * (ts / 64), "GBA bitmap");
         a.tile_cnt = ls.get<uint32_t>(ntiles, "tile counts");
         uint64_t *toff = ls.get<uint64_t>(ntiles + 1, "tile offsets");
@@ -1693,6 +2132,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         Mb.p = Mn.p;
         Mn.p = nullptr;
         M = a.Mn;
+        Mld = 0;
         const double slots_per_row = (double)gba / (double)R;
         R = S;
         // back to the single workgroup when the table fits and, at this

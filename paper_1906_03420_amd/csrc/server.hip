@@ -37,7 +37,7 @@ struct gsi_server {
     bool count_only = false;
     uint32_t max_inflight = 1024, max_admit = 256;
     uint64_t budget = 0;
-    gsi_batch_schedule sched{256, 8};
+    gsi_batch_schedule sched{256, 8, 0};
     std::vector<uint64_t> nv;  // vertices per vertex label
     std::unordered_map<uint64_t, std::unique_ptr<gsi::Request>> reqs;
     std::deque<uint64_t> waiting, answered;
@@ -256,10 +256,12 @@ gsi_status gsi_server_create(gsi_graph *g, const gsi_server_options *opt, gsi_se
         if (o.flags & ~GSI_COUNT_ONLY) fail(GSI_E_INVALID, "unknown server flag");
         gsi_batch_schedule sc = o.schedule;
         if (sc.threads == 0) sc = g->tuned;
-        if (sc.threads == 0) sc = gsi_batch_schedule{256, 8};
+        if (sc.threads == 0) sc = gsi_batch_schedule{256, 8, 0};
         if (sc.threads != 64 && sc.threads != 256 && sc.threads != 1024)
             fail(GSI_E_INVALID, "schedule threads must be 64, 256 or 1024");
         if (sc.grid_scale < 1 || sc.grid_scale > 8) fail(GSI_E_INVALID, "schedule grid_scale must be 1..8");
+        if (sc.engine_tiles > 8 || (sc.engine_tiles & (sc.engine_tiles - 1)))
+            fail(GSI_E_INVALID, "schedule engine_tiles must be 0, 1, 2, 4 or 8");
         gsi_ctx *c = g->ctx;
         Busy busy(c);
         GSI_HIP(hipSetDevice(c->device));
@@ -271,7 +273,7 @@ gsi_status gsi_server_create(gsi_graph *g, const gsi_server_options *opt, gsi_se
         s->max_admit = o.max_admit ? o.max_admit : 256u;
         s->budget = o.table_budget ? o.table_budget : c->arena.largest_free() / 2;
         s->sched = sc;
-        s->engine.reset(new WideEngine(g, s->count_only, true));
+        s->engine.reset(new WideEngine(g, s->count_only, true, sc.engine_tiles));
         // vertices per label: word 0 of every signature is the exact label
         std::vector<uint32_t> lab(g->n);
         GSI_HIP(hipMemcpyAsync(lab.data(), g->sig, 4ull * g->n, hipMemcpyDeviceToHost, c->stream));

@@ -81,7 +81,9 @@ struct WideQuery {
 // status GSI_E_NOMEM.
 class WideEngine {
   public:
-    WideEngine(gsi_graph *g, bool count_only, bool tolerant = false);
+    // tiles: 256-slot tiles per workgroup of the join and link (1, 2, 4 or
+    // 8; anything else: 4)
+    WideEngine(gsi_graph *g, bool count_only, bool tolerant = false, uint32_t tiles = 0);
     void add(WideQuery &&q);
     bool idle() const;
     uint32_t step();                   // returns how many are done now
@@ -93,12 +95,13 @@ class WideEngine {
   private:
     gsi_graph *g_;
     bool count_only_, tolerant_;
+    uint32_t tpw_;
     std::vector<WideQuery> qs_;
     uint64_t steps_ = 0;
 };
 
 // Runs every query of `wq` to completion (count, digest and, unless
 // count_only, rows); `wq` comes back holding the finished queries.
-void wide_run(gsi_graph *g, std::vector<WideQuery> &wq, bool count_only);
+void wide_run(gsi_graph *g, std::vector<WideQuery> &wq, bool count_only, uint32_t tiles = 0);
 
 }  // namespace gsi

@@ -120,38 +120,39 @@ __global__ __launch_bounds__(WT) void k_wlocate(const WQ *qs, uint32_t nq, const
 // comes from a map built once per workgroup: each row after the first
 // marks the slot where its slice starts (the largest row wins where empty
 // rows share a start) and a max-scan carries the marks forward.
+// (WJ_TILES by default; the batch schedule may pick 1, 2, 4 or 8, tuned)
 constexpr uint32_t WJ_TILES = 4;
-constexpr uint32_t WJS = WJ_TILES * WT;  // slots per workgroup
 
+template <uint32_t TPW>
 __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, const uint32_t *rowq, const WEdge *edges,
                                              const uint32_t *ci_all, const uint64_t *F, const uint64_t *tile_row,
                                              uint64_t ntiles, uint64_t gba, const uint32_t *loc, uint64_t *bitmap,
                                              uint32_t *tile_cnt) {
-    __shared__ uint64_t s_F[WJS];
-    __shared__ uint32_t s_st[WJS];
-    __shared__ uint32_t s_row[WJS];  // row (from r_lo) of each slot, staged groups
+    __shared__ uint64_t s_F[(TPW * WT)];
+    __shared__ uint32_t s_st[(TPW * WT)];
+    __shared__ uint32_t s_row[(TPW * WT)];  // row (from r_lo) of each slot, staged groups
     __shared__ uint32_t s_w[WT / 64];
     __shared__ WQ s_Q;
     __shared__ uint32_t s_q[2];
-    __shared__ uint32_t s_x[WJS];    // elements that passed the C(u) test, compacted
-    __shared__ uint32_t s_r[WJS];    // and their rows (from r_lo)
-    __shared__ uint16_t s_slot[WJS]; // and their slots in the group
-    __shared__ uint64_t s_keep[WJS / 64];
+    __shared__ uint32_t s_x[(TPW * WT)];    // elements that passed the C(u) test, compacted
+    __shared__ uint32_t s_r[(TPW * WT)];    // and their rows (from r_lo)
+    __shared__ uint16_t s_slot[(TPW * WT)]; // and their slots in the group
+    __shared__ uint64_t s_keep[(TPW * WT) / 64];
     __shared__ uint32_t s_n;
-    const uint64_t t0 = (uint64_t)blockIdx.x * WJ_TILES;
-    const uint64_t t1 = t0 + WJ_TILES < ntiles ? t0 + WJ_TILES : ntiles;
+    const uint64_t t0 = (uint64_t)blockIdx.x * TPW;
+    const uint64_t t1 = t0 + TPW < ntiles ? t0 + TPW : ntiles;
     const uint64_t p0 = t0 * WT;
     const uint64_t r_lo = tile_row[t0], r_hi = tile_row[t1];
     const uint64_t nr = r_hi - r_lo + 1;
-    const bool staged = nr <= WJS;
+    const bool staged = nr <= (TPW * WT);
     if (threadIdx.x == 0) {
         s_n = 0;
         s_q[0] = rowq[r_lo];
         s_q[1] = rowq[r_hi];
     }
-    if (threadIdx.x < WJS / 64) s_keep[threadIdx.x] = 0;
+    if (threadIdx.x < (TPW * WT) / 64) s_keep[threadIdx.x] = 0;
 #pragma unroll
-    for (uint32_t k = 0; k < WJ_TILES; k++) s_row[threadIdx.x * WJ_TILES + k] = 0;
+    for (uint32_t k = 0; k < TPW; k++) s_row[threadIdx.x * TPW + k] = 0;
     if (staged)
         for (uint32_t r = threadIdx.x; r < nr; r += WT) s_F[r] = F[r_lo + r];
     __syncthreads();
@@ -169,18 +170,18 @@ __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, const uint32_t *rowq
         for (uint32_t r = threadIdx.x; r < nr; r += WT) {
             // rows after the first start past p0 (the first holds slot p0)
             const uint64_t pos = s_F[r] - p0;
-            if (r > 0 && pos < WJS) atomicMax(&s_row[pos], r);
+            if (r > 0 && pos < (TPW * WT)) atomicMax(&s_row[pos], r);
         }
     __syncthreads();
-    if (staged) block_max_scan<WT, WJ_TILES>(s_row, s_w);
+    if (staged) block_max_scan<WT, TPW>(s_row, s_w);
     const uint32_t lane = lane_id();
     // x = N(v'_i, l0)[p - F[i]] for the thread's slot of each tile, then the
     // C(u) test; the slots that pass are compacted so that the costly tests
     // below run in dense waves
-    uint32_t xs[WJ_TILES], rs[WJ_TILES];
-    bool kp[WJ_TILES];
+    uint32_t xs[TPW], rs[TPW];
+    bool kp[TPW];
 #pragma unroll
-    for (uint32_t k = 0; k < WJ_TILES; k++) {
+    for (uint32_t k = 0; k < TPW; k++) {
         const uint32_t sl = k * WT + threadIdx.x;
         const uint64_t p = p0 + sl;
         kp[k] = p < gba;
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, const uint32_t *rowq
         }
     }
 #pragma unroll
-    for (uint32_t k = 0; k < WJ_TILES; k++) {
+    for (uint32_t k = 0; k < TPW; k++) {
         if (kp[k]) {
             const uint64_t *Cu = one ? s_Q.Cu : qs[rowq[r_lo + rs[k]]].Cu;
             kp[k] = (Cu[xs[k] >> 6] >> (xs[k] & 63)) & 1ull;
@@ -258,12 +259,12 @@ __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, const uint32_t *rowq
     // per 256-slot tile: its WT/64 bitmap words and their count
     if (threadIdx.x < 64) {
         const uint32_t tk = threadIdx.x / (WT / 64);  // tile of the group
-        const uint64_t word = threadIdx.x < WJS / 64 ? s_keep[threadIdx.x] : 0ull;
-        if (threadIdx.x < WJS / 64 && t0 + tk < t1) bitmap[p0 / 64 + threadIdx.x] = word;
+        const uint64_t word = threadIdx.x < (TPW * WT) / 64 ? s_keep[threadIdx.x] : 0ull;
+        if (threadIdx.x < (TPW * WT) / 64 && t0 + tk < t1) bitmap[p0 / 64 + threadIdx.x] = word;
         uint32_t c = (uint32_t)__popcll(word);
 #pragma unroll
         for (uint32_t o = 1; o < WT / 64; o <<= 1) c += __shfl_xor(c, o, 64);
-        if (threadIdx.x < WJS / 64 && threadIdx.x % (WT / 64) == 0 && t0 + tk < t1) tile_cnt[t0 + tk] = c;
+        if (threadIdx.x < (TPW * WT) / 64 && threadIdx.x % (WT / 64) == 0 && t0 + tk < t1) tile_cnt[t0 + tk] = c;
     }
 }
 
@@ -306,19 +307,20 @@ constexpr uint32_t WLINK_STAGE_K = 16;
 // tile_off[t0] + q of the step.  The row of a survivor's slot is found by a
 // binary search over the group's rows in LDS (survivors are often few, so
 // a map of every slot would not pay).
+template <uint32_t TPW>
 __global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, const uint32_t *rowq, const uint32_t *ci_all,
                                              const uint64_t *F, const uint64_t *tile_row, uint64_t ntiles,
                                              const uint32_t *loc, const uint64_t *bitmap, const uint64_t *tile_off,
                                              uint64_t *hv) {
-    __shared__ uint64_t s_F[WJS];
-    __shared__ uint32_t s_st[WJS];
+    __shared__ uint64_t s_F[(TPW * WT)];
+    __shared__ uint32_t s_st[(TPW * WT)];
     __shared__ WQ s_Q;
     __shared__ uint32_t s_q[2];
     __shared__ uint32_t s_rows[WT * WLINK_STAGE_K];
-    __shared__ uint16_t s_list[WJS];          // the group's kept slots, in slot order
-    __shared__ uint32_t s_pre[WJS / 64 + 1];  // kept slots before each bitmap word
-    const uint64_t t0 = (uint64_t)blockIdx.x * WJ_TILES;
-    const uint64_t t1 = t0 + WJ_TILES < ntiles ? t0 + WJ_TILES : ntiles;
+    __shared__ uint16_t s_list[(TPW * WT)];          // the group's kept slots, in slot order
+    __shared__ uint32_t s_pre[(TPW * WT) / 64 + 1];  // kept slots before each bitmap word
+    const uint64_t t0 = (uint64_t)blockIdx.x * TPW;
+    const uint64_t t1 = t0 + TPW < ntiles ? t0 + TPW : ntiles;
     const uint64_t gbase = tile_off[t0];
     if (tile_off[t1] == gbase) return;  // no survivor in the group (uniform)
     const uint64_t p0 = t0 * WT;
@@ -326,16 +328,16 @@ __global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, const uint32_t *rowq
     const uint64_t *words = bitmap + p0 / 64;
     const uint64_t r_lo = tile_row[t0], r_hi = tile_row[t1];
     const uint64_t nr = r_hi - r_lo + 1;
-    const bool staged = nr <= WJS;
+    const bool staged = nr <= (TPW * WT);
     if (threadIdx.x == 0) {
         s_q[0] = rowq[r_lo];
         s_q[1] = rowq[r_hi];
         uint32_t run = 0;
-        for (uint32_t q = 0; q < WJS / 64; q++) {
+        for (uint32_t q = 0; q < (TPW * WT) / 64; q++) {
             s_pre[q] = run;
             if (q < nwords) run += (uint32_t)__popcll(words[q]);
         }
-        s_pre[WJS / 64] = run;
+        s_pre[(TPW * WT) / 64] = run;
     }
     if (staged)
         for (uint32_t r = threadIdx.x; r < nr; r += WT) s_F[r] = F[r_lo + r];
@@ -353,7 +355,7 @@ __global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, const uint32_t *rowq
     {
         const uint32_t w = threadIdx.x >> 6, lane = lane_id();
 #pragma unroll
-        for (uint32_t k = 0; k < WJ_TILES; k++) {
+        for (uint32_t k = 0; k < TPW; k++) {
             const uint32_t wi = k * (WT / 64) + w;
             const uint64_t word = wi < nwords ? words[wi] : 0ull;
             if ((word >> lane) & 1ull) s_list[s_pre[wi] + rank_below(word)] = (uint16_t)(k * WT + threadIdx.x);
@@ -361,7 +363,7 @@ __global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, const uint32_t *rowq
     }
     __syncthreads();
     // the same count in every lane (the loop holds barriers)
-    const uint32_t n = __builtin_amdgcn_readfirstlane(s_pre[WJS / 64]);
+    const uint32_t n = __builtin_amdgcn_readfirstlane(s_pre[(TPW * WT) / 64]);
     const bool stage = one && s_Q.final_level && s_Q.out && s_Q.k <= WLINK_STAGE_K;
     for (uint32_t q0 = 0; q0 < n; q0 += WT) {
         const uint32_t local = threadIdx.x;  // survivor q0 + local of the group
@@ -476,7 +478,7 @@ __global__ __launch_bounds__(WT) void k_wdigest(const uint64_t *items, const uin
 // One join level for the queries in `act` (all of them, or none: on an
 // allocation failure everything allocated for the step is given back and
 // no query changes state).
-static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool count_only) {
+static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool count_only, uint32_t tpw) {
     gsi_ctx *c = g->ctx;
     constexpr uint64_t DIGEST_ITEM = 1u << 16;
     {
@@ -575,9 +577,18 @@ static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool co
         tile_rows(c, F, Rtot, ntiles, trow);
         double jb = 4.0 * gba + gba / 8.0 + 4.0 * ntiles;
         for (auto &Q : hq) jb += (double)Q.R * (8.0 + 8.0 * Q.ne + 4.0 * Q.j);
-        launch(c, "k_wjoin", jb, k_wjoin, (uint32_t)((ntiles + WJ_TILES - 1) / WJ_TILES), WT, (const WQ *)d_q,
-               (const uint32_t *)rowq, (const WEdge *)d_e, (const uint32_t *)g->ci, (const uint64_t *)F,
-               (const uint64_t *)trow, ntiles, gba, (const uint32_t *)loc, bitmap, tcnt);
+        {
+            const uint32_t grid = (uint32_t)((ntiles + tpw - 1) / tpw);
+            auto join = [&](auto kern) {
+                launch(c, "k_wjoin", jb, kern, grid, WT, (const WQ *)d_q, (const uint32_t *)rowq, (const WEdge *)d_e,
+                       (const uint32_t *)g->ci, (const uint64_t *)F, (const uint64_t *)trow, ntiles, gba,
+                       (const uint32_t *)loc, bitmap, tcnt);
+            };
+            if (tpw == 1) join(k_wjoin<1>);
+            else if (tpw == 2) join(k_wjoin<2>);
+            else if (tpw == 8) join(k_wjoin<8>);
+            else join(k_wjoin<4>);
+        }
         exclusive_scan(c, tcnt, ntiles, toff, s, scal + 1);
         launch(c, "k_wsurv", 48.0 * nq, k_wsurv, wblocks(nq), WT, (const WQ *)d_q, nq, (const uint64_t *)F,
                (const uint64_t *)bitmap, (const uint64_t *)toff, gba, sb);
@@ -622,9 +633,18 @@ static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool co
         }
         uint64_t *hv = any_final ? s.get<uint64_t>(Stot, "wide row hashes") : nullptr;
         GSI_HIP(hipMemcpyAsync(d_q, hq.data(), sizeof(WQ) * nq, hipMemcpyHostToDevice, c->stream));
-        launch(c, "k_wlink", kb, k_wlink, (uint32_t)((ntiles + WJ_TILES - 1) / WJ_TILES), WT, (const WQ *)d_q,
-               (const uint32_t *)rowq, (const uint32_t *)g->ci, (const uint64_t *)F, (const uint64_t *)trow, ntiles,
-               (const uint32_t *)loc, (const uint64_t *)bitmap, (const uint64_t *)toff, hv);
+        {
+            const uint32_t grid = (uint32_t)((ntiles + tpw - 1) / tpw);
+            auto link = [&](auto kern) {
+                launch(c, "k_wlink", kb, kern, grid, WT, (const WQ *)d_q, (const uint32_t *)rowq,
+                       (const uint32_t *)g->ci, (const uint64_t *)F, (const uint64_t *)trow, ntiles,
+                       (const uint32_t *)loc, (const uint64_t *)bitmap, (const uint64_t *)toff, hv);
+            };
+            if (tpw == 1) link(k_wlink<1>);
+            else if (tpw == 2) link(k_wlink<2>);
+            else if (tpw == 8) link(k_wlink<8>);
+            else link(k_wlink<4>);
+        }
         std::vector<uint64_t> part;
         if (any_final) {
             const uint64_t ni = item_q.size();
@@ -673,8 +693,9 @@ static uint64_t step_bytes(const WideQuery &x) {
     return x.R * (8 * ne + 4 + 8 + 8) + 4096;
 }
 
-WideEngine::WideEngine(gsi_graph *g, bool count_only, bool tolerant)
-    : g_(g), count_only_(count_only), tolerant_(tolerant) {}
+WideEngine::WideEngine(gsi_graph *g, bool count_only, bool tolerant, uint32_t tiles)
+    : g_(g), count_only_(count_only), tolerant_(tolerant),
+      tpw_(tiles == 1 || tiles == 2 || tiles == 8 ? tiles : WJ_TILES) {}
 
 void WideEngine::add(WideQuery &&q) { qs_.push_back(std::move(q)); }
 
@@ -700,7 +721,7 @@ uint32_t WideEngine::step() {
     for (;;) {
         std::vector<WideQuery *> part(act.begin(), act.begin() + n);
         try {
-            wide_step(g_, part, count_only_);
+            wide_step(g_, part, count_only_, tpw_);
             steps_++;
             break;
         } catch (const Fail &f) {
@@ -737,8 +758,8 @@ std::vector<WideQuery> WideEngine::take_done() {
     return out;
 }
 
-void wide_run(gsi_graph *g, std::vector<WideQuery> &wq, bool count_only) {
-    WideEngine e(g, count_only);
+void wide_run(gsi_graph *g, std::vector<WideQuery> &wq, bool count_only, uint32_t tiles) {
+    WideEngine e(g, count_only, false, tiles);
     for (auto &x : wq) e.add(std::move(x));
     while (!e.idle()) e.step();
     wq = e.take_done();

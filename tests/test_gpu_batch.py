@@ -39,14 +39,17 @@ def _small_set(seed, nq):
     return g, qs, want
 
 
-@pytest.mark.parametrize("threads,grid_scale,flags", [(64, 8, 0), (256, 8, 0), (1024, 8, 0), (64, 1, 0), (256, 4, 0),
-                                                     (256, 8, 8)])
-def test_batch_matches_oracle(ctx, threads, grid_scale, flags):
+@pytest.mark.parametrize("threads,grid_scale,flags,tiles", [(64, 8, 0, 0), (256, 8, 0, 0), (1024, 8, 0, 0),
+                                                           (64, 1, 0, 0), (256, 4, 0, 0), (256, 8, 8, 0),
+                                                           (256, 8, 8, 1), (256, 8, 8, 2), (256, 8, 8, 8),
+                                                           (64, 8, 0, 8)])
+def test_batch_matches_oracle(ctx, threads, grid_scale, flags, tiles):
     for seed in (3, 4):
         g, qs, want = _small_set(seed, 60)
         dg = ctx.load(g)
-        print("batch seed", seed, "threads", threads, "flags", flags, flush=True)
-        b = dg.batch(qs, flags=flags, threads=threads, grid_scale=grid_scale)
+        print("batch seed", seed, "threads", threads, "flags", flags, "engine tiles", tiles, flush=True)
+        b = dg.batch(qs, flags=flags, threads=threads, grid_scale=grid_scale, engine_tiles=tiles)
+        assert b.info()["schedule"]["engine_tiles"] == tiles
         info = b.info()
         assert info["queries"] == len(qs)
         assert info["empty"] + info["tier1"] + info["tier2"] + info["per_level"] == len(qs)
@@ -64,6 +67,9 @@ def test_batch_count_only_and_tune(ctx):
     dg = ctx.load(g)
     sched = dg.tune(qs, sample=40)
     assert sched["threads"] in (64, 256, 1024) and sched["grid_scale"] in (4, 8)
+    assert sched["engine_tiles"] in (1, 2, 4, 8)
+    with pytest.raises(gsi.GsiError):
+        dg.batch(qs, threads=256, grid_scale=8, engine_tiles=3)
     b = dg.batch(qs, flags=gsi.GSI_COUNT_ONLY)  # tuned schedule
     assert b.info()["schedule"]["threads"] == sched["threads"]
     for i, wnt in enumerate(want):

@@ -224,7 +224,7 @@ def test_levels_match_spec(ctx):
         order, e0 = spec.plan(q, [len(c) for c in cands], spec.label_frequency(g))
         # Algorithm 4's first edge for every row, then each row's shortest list
         for flags, per_row in ((gsi.GSI_LEVEL_FIRST_EDGE, False), (0, True)):
-            r = dg.query(q, flags=flags)
+            r = dg.query(q, flags=flags | gsi.GSI_NO_LIST_FILTER)
             st = r.stats()
             assert st["order"] == order
             assert st["first_edge"][1:] == e0[1:]
@@ -282,7 +282,7 @@ def test_root_chunks_partly_left_to_the_per_level_kernels(ctx):
     assert want.count == 2 * n_cyc + n_cl * (n_cl - 1) * (n_cl - 2) * (n_cl - 3)
     dg = ctx.load(g)
     for mode in (dict(chunk_rows=1), dict(chunk_rows=3), dict()):
-        mode = dict(mode, chunk_min_rows=1)
+        mode = dict(mode, chunk_min_rows=1, flags=gsi.GSI_NO_LIST_FILTER)
         print("chunk mode", mode, flush=True)
         res = dg.query(q, **mode)
         stt = res.stats()
@@ -292,12 +292,12 @@ def test_root_chunks_partly_left_to_the_per_level_kernels(ctx):
             assert 0 < stt["chunks_left"] < stt["chunks"]
         assert res.count == want.count and res.digest == want.digest
         np.testing.assert_array_equal(res.sorted_rows(), want.tuples)
-        ref = dg.query(q, flags=gsi.GSI_NO_FUSED)
+        ref = dg.query(q, flags=gsi.GSI_NO_FUSED | gsi.GSI_NO_LIST_FILTER)
         assert (stt["rows"], stt["gba"], stt["survivors"]) == (ref.stats()["rows"], ref.stats()["gba"],
                                                                ref.stats()["survivors"])
         ref.free()
         res.free()
-        co = dg.query(q, flags=gsi.GSI_COUNT_ONLY, **mode)
+        co = dg.query(q, **dict(mode, flags=mode["flags"] | gsi.GSI_COUNT_ONLY))
         assert (co.count, co.digest) == (want.count, want.digest)
         co.free()
     dg.free()
@@ -325,7 +325,8 @@ def test_fused_and_per_level_paths_agree(ctx, seed):
         ref = None
         for mode in FUSED_MODES:
             print("seed", seed, "query", t, "k", k, "mode", mode, flush=True)
-            res = dg.query(q, **mode)
+            # per-level sizes are compared as Algorithm 4 defines them
+            res = dg.query(q, **dict(mode, flags=mode.get("flags", 0) | 0x8000))
             assert res.count == want.count
             np.testing.assert_array_equal(res.sorted_rows(), want.tuples)
             assert res.digest == want.digest
@@ -456,6 +457,13 @@ def test_join_ablations_on_hub_rows(ctx):
                 np.testing.assert_array_equal(r.sorted_rows(), want.tuples)
             st = r.stats()
             sizes = (st["rows"], st["gba"], st["survivors"])
+            if f == gsi.GSI_NO_FUSED:
+                # the level-wide filtered lists: level 2's rows scan the
+                # label-0 leaves of their hub only
+                assert st["filtered_levels"] == 1 << 2
+                assert st["gba"][2] == closed
+                r.free()
+                continue
             if not f & gsi.GSI_LEVEL_FIRST_EDGE:
                 ref = ref or sizes
                 assert sizes == ref
@@ -502,3 +510,68 @@ def test_ablations_give_identical_results(ctx):
                 plain.query(q, flags=gsi.GSI_ABL_CR)
         plain.free()
         dg.free()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_single_pass_last_level_and_list_filter(ctx, seed):
+    """The one-pass last level (decoupled look-back) and the level-wide
+    filtered lists give the same rows in the same order as the separate
+    join / scan / link launches on unfiltered lists, and the oracle's set."""
+    import paper_1906_03420_amd as gsi
+    r = np.random.default_rng(9000 + seed)
+    n = int(r.integers(200, 2000))
+    g = w.random_small_graph(n, float(r.uniform(0.005, 0.03)), int(r.integers(1, 3)), int(r.integers(1, 3)),
+                             seed + 90)
+    if g.m == 0:
+        return
+    dg = ctx.load(g)
+    og = oracle.OracleGraph(g)
+    base = gsi.GSI_NO_FUSED
+    for t in range(4):
+        q = w.random_connected_query(int(r.integers(2, 7)), int(r.integers(0, 3)), int(g.vlabel.max()) + 1,
+                                     int(g.elabel.max()) + 1, seed * 77 + t)
+        want = og.match(q, threads=4, max_count=3_000_000)
+        if want.status != 0:
+            continue
+        ref = dg.query(q, flags=base | gsi.GSI_NO_SINGLE_PASS | gsi.GSI_NO_LIST_FILTER)
+        rows = ref.rows()
+        for f in (base, base | gsi.GSI_NO_SINGLE_PASS, base | gsi.GSI_NO_LIST_FILTER, 0):
+            res = dg.query(q, flags=f)
+            assert (res.count, res.digest) == (want.count, want.digest)
+            if f & gsi.GSI_NO_FUSED:
+                np.testing.assert_array_equal(res.rows(), rows)  # same order
+            np.testing.assert_array_equal(res.sorted_rows(), want.tuples)
+            res.free()
+            co = dg.query(q, flags=f | gsi.GSI_COUNT_ONLY)
+            assert (co.count, co.digest) == (want.count, want.digest)
+            co.free()
+        ref.free()
+    dg.free()
+
+
+def test_one_pass_levels_on_a_clique(ctx):
+    """K_20 and a 5-vertex path (20!/15! embeddings): levels 2-4 rescan the
+    same 19-element lists, so all three filter them level-wide and run in one
+    pass (levels 2-3 write the next table at |GBA| rows per column, level 4
+    the rows); rows in the same order as the separate launches, the oracle's
+    set."""
+    import paper_1906_03420_amd as gsi
+    g = w.complete_graph(20)
+    q = w.path_query(5)
+    want = oracle.match(g, q, threads=4)
+    assert want.count == math.perm(20, 5)
+    dg = ctx.load(g)
+    ref = dg.query(q, flags=gsi.GSI_NO_FUSED | gsi.GSI_NO_SINGLE_PASS | gsi.GSI_NO_LIST_FILTER)
+    r = dg.query(q, flags=gsi.GSI_NO_FUSED)
+    st = r.stats()
+    assert st["filtered_levels"] == 0b11100
+    # every vertex is a candidate here, so the filtered lists are whole
+    assert st["gba"][4] == math.perm(20, 4) * 19
+    assert (st["rows"], st["gba"], st["survivors"]) == (ref.stats()["rows"], ref.stats()["gba"],
+                                                       ref.stats()["survivors"])
+    np.testing.assert_array_equal(r.rows(), ref.rows())
+    np.testing.assert_array_equal(r.sorted_rows(), want.tuples)
+    assert r.digest == want.digest
+    r.free()
+    ref.free()
+    dg.free()

@@ -450,17 +450,27 @@ gsi_status gsi_batch_tune(gsi_graph *g, uint32_t nq, const gsi_query_desc *queri
  *              on fewer queries (a misprediction costs time, not a failure);
  *              a query whose level does not fit even alone after the others
  *              have drained finishes with status GSI_E_NOMEM.
+ *   solo       at low load — nothing in flight and at most solo_queue
+ *              requests waiting — the step instead answers the oldest request
+ *              alone through gsi_query_run's path (fused workgroup, root
+ *              chunks, per-level kernels), which has the lowest latency; once
+ *              the queue grows past solo_queue, requests are admitted in
+ *              batches as above (throughput).  GSI_SERVER_NO_SOLO turns this
+ *              off.
  * PCSR, signatures, candidate bitsets and partial tables stay on the device.
  * Answers are the ones gsi_query_run gives for the same query alone (count,
  * digest, rows as a set).  Calls on one server must not overlap; the server
  * uses its graph's context (GSI_E_BUSY while another call runs on it). */
 typedef struct gsi_server gsi_server;
 
+#define GSI_SERVER_NO_SOLO 0x2u    /* server flag: never answer a request alone */
 typedef struct {
-    uint32_t flags;         /* GSI_COUNT_ONLY: answers hold count and digest */
+    uint32_t flags;         /* GSI_COUNT_ONLY: answers hold count and digest;
+                               GSI_SERVER_NO_SOLO */
     uint32_t max_inflight;  /* admitted queries not yet finished; 0: 1024 */
     uint32_t max_admit;     /* queries admitted per step; 0: 256 */
-    uint32_t reserved;
+    uint32_t solo_queue;    /* longest queue still served one request at a
+                               time when nothing is in flight; 0: 2 */
     uint64_t table_budget;  /* bytes; 0: half of the arena's largest free block
                                when the server is created */
     gsi_batch_schedule schedule;  /* fused tiers; threads == 0: the graph's
@@ -483,6 +493,7 @@ gsi_status gsi_server_poll(gsi_server *s, uint64_t *tickets, uint32_t capacity, 
 #define GSI_PATH_TIER2 2   /* 1024-thread fused tier */
 #define GSI_PATH_SINGLE 3  /* one-vertex query */
 #define GSI_PATH_LEVELS 4  /* level-synchronous engine */
+#define GSI_PATH_SOLO 5    /* alone, through gsi_query_run's path (low load) */
 typedef struct {
     gsi_status status;         /* GSI_OK, or GSI_E_NOMEM (see above) */
     uint32_t k;
@@ -511,6 +522,7 @@ typedef struct {
     uint64_t peak_predicted;          /* largest admitted prediction sum */
     uint64_t table_budget;
     double admit_ms, level_ms;        /* host wall time in the two phases */
+    uint64_t solo;                    /* requests answered alone (low load) */
 } gsi_server_info;
 gsi_status gsi_server_get_info(const gsi_server *s, gsi_server_info *out);
 /* Drops every query (waiting, in flight or answered) and the server. */

@@ -41,7 +41,8 @@ GSI_ABL_DUP_REMOVAL = 0x4000
 GSI_GRAPH_KEEP_CR = 0x2
 GSI_MAX_EDGE_LABELS = 65536
 GSI_PCSR_GPN = 16
-GSI_PATH_EMPTY, GSI_PATH_TIER1, GSI_PATH_TIER2, GSI_PATH_SINGLE, GSI_PATH_LEVELS = range(5)
+GSI_PATH_EMPTY, GSI_PATH_TIER1, GSI_PATH_TIER2, GSI_PATH_SINGLE, GSI_PATH_LEVELS, GSI_PATH_SOLO = range(6)
+GSI_SERVER_NO_SOLO = 0x2
 
 STATUS_NAMES = {0: "GSI_OK", 1: "GSI_E_INVALID", 2: "GSI_E_NOMEM", 3: "GSI_E_DEVICE", 4: "GSI_E_CAPACITY",
                 5: "GSI_E_BUSY", 6: "GSI_E_INTERNAL"}
@@ -111,7 +112,7 @@ class gsi_batch_info(ctypes.Structure):
 
 class gsi_server_options(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32), ("max_admit", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("table_budget", ctypes.c_uint64),
+                ("solo_queue", ctypes.c_uint32), ("table_budget", ctypes.c_uint64),
                 ("schedule", gsi_batch_schedule)]
 
 
@@ -127,11 +128,11 @@ class gsi_server_info(ctypes.Structure):
                 ("released", ctypes.c_uint64), ("waiting", ctypes.c_uint32), ("in_flight", ctypes.c_uint32),
                 ("steps", ctypes.c_uint64), ("level_steps", ctypes.c_uint64), ("admit_rounds", ctypes.c_uint64),
                 ("predicted_in_flight", ctypes.c_uint64), ("peak_predicted", ctypes.c_uint64),
-                ("table_budget", ctypes.c_uint64), ("admit_ms", ctypes.c_double), ("level_ms", ctypes.c_double)]
+                ("table_budget", ctypes.c_uint64), ("admit_ms", ctypes.c_double), ("level_ms", ctypes.c_double), ("solo", ctypes.c_uint64)]
 
 
 PATH_NAMES = {GSI_PATH_EMPTY: "empty", GSI_PATH_TIER1: "tier1", GSI_PATH_TIER2: "tier2",
-              GSI_PATH_SINGLE: "single", GSI_PATH_LEVELS: "levels"}
+              GSI_PATH_SINGLE: "single", GSI_PATH_LEVELS: "levels", GSI_PATH_SOLO: "solo"}
 
 # name -> (restype, argtypes) for every exported function of gsi.h
 SIGNATURES = {
@@ -493,8 +494,8 @@ def gsi_batch_tune(g: int, queries, sample: int = 128):
 
 
 def gsi_server_create(g: int, flags: int = 0, max_inflight: int = 0, max_admit: int = 0, table_budget: int = 0,
-                      threads: int = 0, grid_scale: int = 0, engine_tiles: int = 0) -> int:
-    o = gsi_server_options(flags, max_inflight, max_admit, 0, table_budget,
+                      threads: int = 0, grid_scale: int = 0, engine_tiles: int = 0, solo_queue: int = 0) -> int:
+    o = gsi_server_options(flags, max_inflight, max_admit, solo_queue, table_budget,
                            gsi_batch_schedule(threads, grid_scale, engine_tiles))
     h = VP()
     _check(load_library().gsi_server_create(g, ctypes.byref(o), ctypes.byref(h)))
@@ -680,9 +681,9 @@ class Graph:
         return gsi_batch_tune(self.h, queries, sample)
 
     def server(self, flags: int = 0, max_inflight: int = 0, max_admit: int = 0, table_budget: int = 0,
-               threads: int = 0, grid_scale: int = 0, engine_tiles: int = 0) -> Server:
+               threads: int = 0, grid_scale: int = 0, engine_tiles: int = 0, solo_queue: int = 0) -> Server:
         return Server(gsi_server_create(self.h, flags, max_inflight, max_admit, table_budget, threads, grid_scale,
-                                        engine_tiles))
+                                        engine_tiles, solo_queue))
 
     def free(self):
         if self.h:

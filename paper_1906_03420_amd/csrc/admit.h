@@ -28,7 +28,9 @@ struct Round {
 };
 
 // where one query's answer lives
-enum SlotPath : uint8_t { PATH_NONE = 0, PATH_TIER1 = 1, PATH_TIER2 = 2, PATH_SINGLE = 3, PATH_LEVELS = 4 };
+enum SlotPath : uint8_t {
+    PATH_NONE = 0, PATH_TIER1 = 1, PATH_TIER2 = 2, PATH_SINGLE = 3, PATH_LEVELS = 4, PATH_SOLO = 5
+};
 
 struct Slot {
     uint32_t k = 0;

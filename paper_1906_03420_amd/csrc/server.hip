@@ -34,8 +34,8 @@ struct Request {
 struct gsi_server {
     gsi_graph *g = nullptr;
     gsi_ctx *ctx = nullptr;
-    bool count_only = false;
-    uint32_t max_inflight = 1024, max_admit = 256;
+    bool count_only = false, solo = true;
+    uint32_t max_inflight = 1024, max_admit = 256, solo_queue = 2;
     uint64_t budget = 0;
     gsi_batch_schedule sched{256, 8, 0};
     std::vector<uint64_t> nv;  // vertices per vertex label
@@ -198,7 +198,43 @@ static uint32_t admit(gsi_server *s, std::vector<Request *> adm) {
     return finished;
 }
 
+// Low load: the oldest request alone through the single-query path.
+static uint32_t solo_step(gsi_server *s) {
+    const auto ta = std::chrono::steady_clock::now();
+    Request &r = *s->reqs.at(s->waiting.front());
+    s->waiting.pop_front();
+    r.t_admit = now_ms(s);
+    s->info.admitted++;
+    s->info.solo++;
+    r.slot.ctx = s->ctx;
+    r.slot.k = r.q.k;
+    gsi_query_options o{};
+    o.flags = s->count_only ? GSI_COUNT_ONLY : 0u;
+    try {
+        gsi_result *res = run_query(s->g, r.q, &o);
+        r.slot.res = res;
+        r.slot.rows = res->rows;
+        r.slot.count = res->count;
+        r.slot.digest[0] = res->digest[0];
+        r.slot.digest[1] = res->digest[1];
+        r.peak = 0;
+    } catch (const Fail &f) {
+        if (f.st != GSI_E_NOMEM) throw;
+        clear_error();
+        r.slot.status = GSI_E_NOMEM;
+        r.slot.count = 0;
+    }
+    r.slot.path = PATH_SOLO;
+    r.slot.done = true;
+    answer(s, r);
+    s->info.admit_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ta).count();
+    s->info.steps++;
+    return 1;
+}
+
 static uint32_t server_step(gsi_server *s) {
+    if (s->solo && s->engine->in_flight() == 0 && !s->waiting.empty() && s->waiting.size() <= s->solo_queue)
+        return solo_step(s);
     uint32_t finished = 0;
     const auto ta = std::chrono::steady_clock::now();
     std::vector<Request *> adm;
@@ -253,7 +289,7 @@ gsi_status gsi_server_create(gsi_graph *g, const gsi_server_options *opt, gsi_se
         if (g->multi) fail(GSI_E_INVALID, "multi-labelled graphs run through gsi_query_run_multi only");
         *out = nullptr;
         gsi_server_options o = opt ? *opt : gsi_server_options{};
-        if (o.flags & ~GSI_COUNT_ONLY) fail(GSI_E_INVALID, "unknown server flag");
+        if (o.flags & ~(GSI_COUNT_ONLY | GSI_SERVER_NO_SOLO)) fail(GSI_E_INVALID, "unknown server flag");
         gsi_batch_schedule sc = o.schedule;
         if (sc.threads == 0) sc = g->tuned;
         if (sc.threads == 0) sc = gsi_batch_schedule{256, 8, 0};
@@ -271,6 +307,8 @@ gsi_status gsi_server_create(gsi_graph *g, const gsi_server_options *opt, gsi_se
         s->count_only = (o.flags & GSI_COUNT_ONLY) != 0;
         s->max_inflight = o.max_inflight ? o.max_inflight : 1024u;
         s->max_admit = o.max_admit ? o.max_admit : 256u;
+        s->solo = !(o.flags & GSI_SERVER_NO_SOLO);
+        s->solo_queue = o.solo_queue ? o.solo_queue : 2u;
         s->budget = o.table_budget ? o.table_budget : c->arena.largest_free() / 2;
         s->sched = sc;
         s->engine.reset(new WideEngine(g, s->count_only, true, sc.engine_tiles));

@@ -60,8 +60,9 @@ def drive(srv, qs, seed, burst=6):
     return tickets, answers
 
 
-@pytest.mark.parametrize("opts", [dict(), dict(table_budget=1, max_admit=1), dict(max_inflight=3, max_admit=2),
-                                  dict(threads=64, grid_scale=4)])
+@pytest.mark.parametrize("opts", [dict(), dict(table_budget=1, max_admit=1, flags=2), dict(max_inflight=3, max_admit=2),
+                                  dict(threads=64, grid_scale=4, flags=2), dict(solo_queue=1000),
+                                  dict(flags=2, engine_tiles=8)])
 def test_server_matches_oracle(ctx, opts):
     for seed in (5, 6):
         g, qs, want = _small_set(seed, 50)
@@ -81,6 +82,11 @@ def test_server_matches_oracle(ctx, opts):
         info = srv.info()
         print("paths", paths, "info", info, flush=True)
         assert info["answered"] == info["admitted"] == info["submitted"] == len(qs)
+        if opts.get("flags", 0) & 2:
+            assert info["solo"] == 0 and "solo" not in paths
+        if opts.get("solo_queue") == 1000:
+            # nothing is ever in flight: every request is answered alone
+            assert paths == {"solo": len(qs)}
         assert info["waiting"] == 0 and info["in_flight"] == 0
         if opts.get("table_budget") == 1:
             # nothing is admitted beside a query still in the level engine
@@ -134,22 +140,23 @@ def test_server_query_too_large_for_the_arena():
     ws = og.match(small, threads=2)
     with gsi.Context(256 << 20) as c:
         dg = c.load(g)
-        srv = dg.server()
-        tb, ts = srv.submit(big), srv.submit(small)
-        ans = {}
-        for _ in range(200):
-            srv.step()
-            for t in srv.poll():
-                ans[t] = srv.answer(t)
-            if len(ans) == 2:
-                break
-        assert ans[tb]["status"] == gsi.GSI_E_NOMEM and ans[tb]["path"] == "levels"
-        assert ans[ts]["status"] == 0 and ans[ts]["count"] == 40 * 39 * 38 == ws.count
-        assert ans[ts]["digest"] == ws.digest
-        np.testing.assert_array_equal(srv.sorted_rows(ts), og.match(small, threads=2, tuples=True).tuples)
-        srv.release(tb)
-        srv.release(ts)
-        srv.free()
+        for flags, path in ((gsi.GSI_SERVER_NO_SOLO, "levels"), (0, "solo")):
+            srv = dg.server(flags=flags)
+            tb, ts = srv.submit(big), srv.submit(small)
+            ans = {}
+            for _ in range(200):
+                srv.step()
+                for t in srv.poll():
+                    ans[t] = srv.answer(t)
+                if len(ans) == 2:
+                    break
+            assert ans[tb]["status"] == gsi.GSI_E_NOMEM and ans[tb]["path"] == path
+            assert ans[ts]["status"] == 0 and ans[ts]["count"] == 40 * 39 * 38 == ws.count
+            assert ans[ts]["digest"] == ws.digest
+            np.testing.assert_array_equal(srv.sorted_rows(ts), og.match(small, threads=2, tuples=True).tuples)
+            srv.release(tb)
+            srv.release(ts)
+            srv.free()
         dg.free()
         assert c.memory()[0] == 0
 

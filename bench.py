@@ -50,9 +50,11 @@ sys.path.insert(0, ROOT)
 METRIC = "embeddings/s and queries/s (batched vs single) on one MI355X; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 # kernels of the path's own steps: signature filter, PCSR locate, join
-# (set subtraction + intersections), link (Prealloc-Combine table write), and
-# the fused workgroup that runs locate/join/link for small tables
-HOT_KERNELS = ("k_filter", "k_locate", "k_join", "k_link", "k_fused_levels")
+# (set subtraction + intersections), link (Prealloc-Combine table write), the
+# one-pass levels (join, look-back and link in one launch: k_join_pass for an
+# inner level, k_join_last for the last), and the fused workgroup that runs
+# locate/join/link for small tables
+HOT_KERNELS = ("k_filter", "k_locate", "k_join", "k_link", "k_join_pass", "k_join_last", "k_fused_levels")
 
 # sources each kernel is compiled from: the stored HBM counter readings of a
 # kernel (profiles/traffic.json) are used only while these files are unchanged
@@ -64,6 +66,8 @@ KERNEL_SOURCES = {
     "k_locate": ("query.hip", "join_device.h", "gsi_internal.h"),
     "k_join": ("query.hip", "join_device.h", "scan_device.h", "gsi_internal.h"),
     "k_link": ("query.hip", "join_device.h", "gsi_internal.h"),
+    "k_join_pass": ("query.hip", "join_device.h", "scan_device.h", "gsi_internal.h"),
+    "k_join_last": ("query.hip", "join_device.h", "scan_device.h", "gsi_internal.h"),
 }
 
 

@@ -465,14 +465,16 @@ def mquery_from_single(q: Query) -> MQuery:
 
 def random_multi_graph(n: int, p: float, nvl: int, nel: int, max_vl: int, max_el: int, seed: int) -> MGraph:
     """Each vertex gets 1..max_vl distinct labels of nvl; each pair is an edge
-    with probability p and then gets 1..max_el distinct labels of nel."""
+    with probability p and then gets 1..max_el distinct labels of nel (at most
+    nvl and nel of them)."""
     r = _stream(seed, 7)
-    sets = [sorted(r.choice(nvl, size=int(r.integers(1, max_vl + 1)), replace=False).tolist()) for _ in range(n)]
+    sets = [sorted(r.choice(nvl, size=min(nvl, int(r.integers(1, max_vl + 1))), replace=False).tolist())
+            for _ in range(n)]
     a, b = np.triu_indices(n, 1)
     keep = r.random(a.shape[0]) < p
     edges = []
     for x, y in zip(a[keep].tolist(), b[keep].tolist()):
-        for l in sorted(r.choice(nel, size=int(r.integers(1, max_el + 1)), replace=False).tolist()):
+        for l in sorted(r.choice(nel, size=min(nel, int(r.integers(1, max_el + 1))), replace=False).tolist()):
             edges.append((x, y, l))
     return make_mgraph(n, sets, edges, "multi%d" % seed)
 

@@ -311,6 +311,36 @@ gsi_status gsi_query_filter(gsi_graph *g, uint32_t k, const uint32_t *q_vertex_l
                             const uint32_t *q_src, const uint32_t *q_dst, const uint32_t *q_edge_labels,
                             uint64_t *host_bitsets, uint64_t capacity_words, uint32_t *host_counts);
 
+/*
+ * For callers that cannot allocate device memory during a call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * gsi_query_run without any device allocation.  Every scratch buffer of the
+ * query comes from a fixed array of GSI_NOALLOC_SCRATCH_BYTES in the
+ * library's own device memory (one per GPU, held until the process ends; its
+ * address is taken when the first context on that GPU is created), and the
+ * rows are copied into the caller's device buffer.  Results (rows as a set,
+ * count, digest) are those of gsi_query_run with the same flags.
+ *   flags           GSI_COUNT_ONLY and the other gsi_query_options flags
+ *   dev_rows        device memory on the context's GPU, capacity_rows x k
+ *                   uint32, row-major, column j = f(j) (ignored with
+ *                   GSI_COUNT_ONLY); written on the context's stream, complete
+ *                   when the call returns
+ *   out_count, out_digest  the row count and the (sum, xor) digest
+ * Single-label graphs only.  Every call on one GPU shares its scratch array
+ * and finds it as the previous call left it; calls on one context are
+ * serialised (GSI_E_BUSY), calls on two contexts of one GPU overlapping in
+ * time race on the array and must be serialised by the caller.
+ * Errors: as gsi_query_run; GSI_E_CAPACITY when the query needs more scratch
+ * than the array holds (its candidate bitsets alone, k x |V|/8 bytes, may
+ * take at most half of it) or when the rows exceed capacity_rows
+ * (*out_count then holds the row count).
+ */
+#define GSI_NOALLOC_SCRATCH_BYTES (128ull << 20)
+gsi_status gsi_query_run_noalloc(gsi_graph *g, uint32_t k, const uint32_t *q_vertex_labels, uint32_t q_edges,
+                                 const uint32_t *q_src, const uint32_t *q_dst, const uint32_t *q_edge_labels,
+                                 uint32_t flags, uint32_t *dev_rows, uint64_t capacity_rows, uint64_t *out_count,
+                                 uint64_t out_digest[2]);
+
 /* Number of embeddings (rows). */
 gsi_status gsi_result_count(const gsi_result *r, uint64_t *rows);
 /* Copies the rows (row-major, rows x k uint32, column j = f(j)) to host memory

@@ -43,6 +43,7 @@ GSI_MAX_EDGE_LABELS = 65536
 GSI_PCSR_GPN = 16
 GSI_PATH_EMPTY, GSI_PATH_TIER1, GSI_PATH_TIER2, GSI_PATH_SINGLE, GSI_PATH_LEVELS, GSI_PATH_SOLO = range(6)
 GSI_SERVER_NO_SOLO = 0x2
+GSI_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 STATUS_NAMES = {0: "GSI_OK", 1: "GSI_E_INVALID", 2: "GSI_E_NOMEM", 3: "GSI_E_DEVICE", 4: "GSI_E_CAPACITY",
                 5: "GSI_E_BUSY", 6: "GSI_E_INTERNAL"}
@@ -162,6 +163,8 @@ SIGNATURES = {
                                      ctypes.POINTER(gsi_query_options), ctypes.POINTER(VP)]),
     "gsi_query_filter": (ctypes.c_int, [VP, ctypes.c_uint32, U32P, ctypes.c_uint32, U32P, U32P, U32P, U64P,
                                         ctypes.c_uint64, U32P]),
+    "gsi_query_run_noalloc": (ctypes.c_int, [VP, ctypes.c_uint32, U32P, ctypes.c_uint32, U32P, U32P, U32P,
+                                             ctypes.c_uint32, VP, ctypes.c_uint64, U64P, U64P]),
     "gsi_result_count": (ctypes.c_int, [VP, U64P]),
     "gsi_result_rows": (ctypes.c_int, [VP, U32P, ctypes.c_uint64]),
     "gsi_result_device_rows": (ctypes.c_int, [VP, ctypes.POINTER(VP)]),
@@ -389,6 +392,21 @@ def gsi_query_filter(g: int, n_vertices: int, k: int, q_vertex_labels, q_src, q_
     _check(load_library().gsi_query_filter(g, k, vlp, s.shape[0], sp, dp, lp, bits.ctypes.data_as(U64P), bits.size,
                                            cnt.ctypes.data_as(U32P)))
     return bits, cnt
+
+
+def gsi_query_run_noalloc(g: int, k: int, q_vertex_labels, q_src, q_dst, q_edge_labels, flags: int,
+                          dev_rows_ptr: int, capacity_rows: int):
+    """Runs a query with no device allocation (rows into the caller's device
+    buffer); returns (count, (digest sum, digest xor))."""
+    vl, vlp = _u32(q_vertex_labels)
+    s, sp = _u32(q_src)
+    d, dp = _u32(q_dst)
+    l, lp = _u32(q_edge_labels)
+    cnt = ctypes.c_uint64()
+    dig = (ctypes.c_uint64 * 2)()
+    _check(load_library().gsi_query_run_noalloc(g, k, vlp, s.shape[0], sp, dp, lp, flags, dev_rows_ptr or None,
+                                                capacity_rows, ctypes.byref(cnt), dig))
+    return cnt.value, (int(dig[0]), int(dig[1]))
 
 
 def gsi_result_count(r: int) -> int:
@@ -673,6 +691,13 @@ class Graph:
 
     def filter(self, q):
         return gsi_query_filter(self.h, self.n, q.k, q.vlabel, q.src, q.dst, q.elabel)
+
+    def query_noalloc(self, q, rows_t, flags: int = 0):
+        """Query with no device allocation: rows into `rows_t` (a device
+        tensor of at least k x capacity 32-bit words, capacity = its size //
+        k); returns (count, digest)."""
+        cap = rows_t.numel() * rows_t.element_size() // (4 * q.k)
+        return gsi_query_run_noalloc(self.h, q.k, q.vlabel, q.src, q.dst, q.elabel, flags, rows_t.data_ptr(), cap)
 
     def batch(self, queries, flags: int = 0, threads: int = 0, grid_scale: int = 0, engine_tiles: int = 0) -> Batch:
         return Batch(gsi_batch_run(self.h, queries, flags, threads, grid_scale, engine_tiles), [q.k for q in queries])

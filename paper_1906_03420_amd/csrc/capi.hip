@@ -201,6 +201,7 @@ gsi_status gsi_ctx_create(const gsi_options *o, gsi_ctx **out) {
         REQUIRE(o->arena_ptr && ((uintptr_t)o->arena_ptr % 256) == 0, "arena must be non-null and 256-byte aligned");
         REQUIRE(o->arena_bytes >= (1ull << 20), "arena must hold at least 1 MiB");
         GSI_HIP(hipSetDevice(o->device));
+        noalloc_init(o->device);
         gsi_ctx *c = new gsi_ctx();
         c->device = o->device;
         c->stream = (hipStream_t)o->hip_stream;

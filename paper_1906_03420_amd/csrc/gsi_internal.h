@@ -264,6 +264,9 @@ void make_plan(const gsi_graph *g, const HostQuery &q, const std::vector<uint32_
 // tile_row[t] = row r with F[r] <= 256 t < F[r+1]; tile_row[ntiles] = R - 1
 void tile_rows(gsi_ctx *c, const uint64_t *F, uint64_t R, uint64_t ntiles, uint64_t *tile_row);
 gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options *opt);
+// takes the device address of the fixed scratch of gsi_query_run_noalloc on
+// `device` (current), once per device
+void noalloc_init(int device);
 
 }  // namespace gsi
 

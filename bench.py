@@ -308,7 +308,7 @@ def ablation_variants(gsi):
     the paper's ablations (Tables V-IX) on top of the per-level kernels."""
     PL = gsi.GSI_NO_FUSED | gsi.GSI_NO_LIST_FILTER
     return [("default", 0), ("per_level", PL), ("per_level+list_filter", gsi.GSI_NO_FUSED),
-            ("level_first_edge", gsi.GSI_LEVEL_FIRST_EDGE),
+            ("level_first_edge", gsi.GSI_LEVEL_FIRST_EDGE), ("single_pass", gsi.GSI_SINGLE_PASS),
             ("per_level+cr_lookup", PL | gsi.GSI_ABL_CR),
             ("per_level+two_step_output", PL | gsi.GSI_ABL_TWO_STEP),
             ("per_level+unstaged_rows", PL | gsi.GSI_ABL_NO_STAGING),

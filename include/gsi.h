@@ -188,9 +188,11 @@ gsi_status gsi_graph_copy_pcsr(const gsi_graph *g, uint32_t label, uint32_t *hos
                                       its shortest linking list */
 #define GSI_NO_LIST_FILTER 0x8000u /* no level-wide filtering of first-edge lists
                                       (see gsi_query_run) */
-#define GSI_NO_SINGLE_PASS 0x10000u /* the last per-level level as separate join,
-                                      scan and link launches instead of one
-                                      pass (see gsi_query_run) */
+#define GSI_SINGLE_PASS 0x20000u    /* the last per-level level (and inner levels
+                                      with filtered lists and one linking edge)
+                                      in one launch with a decoupled look-back
+                                      instead of separate join, scan and link
+                                      launches (see gsi_query_run) */
 /* Ablations (measurement and tests only; each implies GSI_NO_FUSED, since
  * they change the per-level kernels): */
 #define GSI_ABL_CR 0x100u          /* N(v,l) by binary search in the compressed
@@ -259,10 +261,12 @@ typedef struct {
  * first filters l0's lists by C(u) once for the level, in order, and its
  * rows scan the filtered lists (e0's for every row); the rows, count and
  * digest are unchanged, only |GBA| shrinks (GSI_NO_LIST_FILTER turns this
- * off).  The last per-level level runs in one launch: each tile joins, finds
- * the rows before it by a decoupled look-back over the tiles started before
- * it, and writes its rows at once (output sized at |GBA| rows, then shrunk;
- * GSI_NO_SINGLE_PASS keeps the separate join, scan and link).
+ * off).  With GSI_SINGLE_PASS the last per-level level runs in one launch:
+ * each tile joins, finds the rows before it by a decoupled look-back over the
+ * tiles started before it, and writes its rows at once (output sized at |GBA|
+ * rows, then shrunk); by default it runs as separate join, scan and link
+ * launches, which measure faster (a tile's rows wait on the slowest join
+ * before it).
  * Up to 4096 roots one fused workgroup runs the levels while the tables stay
  * small (4096 rows and 16384 |GBA| slots per level, with F, the keep bits and
  * the survivor prefix sums in LDS); the per-level kernels run a level that

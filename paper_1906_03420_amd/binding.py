@@ -29,7 +29,7 @@ GSI_BATCH_LEVELS_ONLY = 0x8
 GSI_NO_CHUNKS = 0x10
 GSI_LEVEL_FIRST_EDGE = 0x20
 GSI_NO_LIST_FILTER = 0x8000
-GSI_NO_SINGLE_PASS = 0x10000
+GSI_SINGLE_PASS = 0x20000
 GSI_HOMOMORPHISM = 0x40
 GSI_ABL_CR = 0x100
 GSI_ABL_TWO_STEP = 0x200

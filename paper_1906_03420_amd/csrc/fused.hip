@@ -265,13 +265,24 @@ __device__ __forceinline__ void fused_query(const FPlan *plan, uint32_t j0, cons
                 xr[r] = 0;
             }
             lds_rows<FU>(s_F, R, pr, ir, fr);
-#pragma unroll
-            for (uint32_t r = 0; r < FU; r++)
-                if (kp[r]) xr[r] = ci_all[L.st[ir[r]] + (pr[r] - fr[r])];
+            // Loads are issued unconditionally, a slot past |GBA| reading
+            // valid addresses (element 0, row 0, column j - 1), and masked
+            // afterwards: a load behind a branch waits for the one before.
 #pragma unroll
             for (uint32_t r = 0; r < FU; r++) {
-                if (XS && kp[r]) L.x[pr[r]] = xr[r];
-                if (kp[r]) kp[r] = (Cu[xr[r] >> 6] >> (xr[r] & 63)) & 1ull;
+                if (!kp[r]) ir[r] = 0;
+                xr[r] = ci_all[kp[r] ? L.st[ir[r]] + (pr[r] - fr[r]) : 0u];
+                if (!kp[r]) xr[r] = 0;
+            }
+            {
+                uint64_t cw[FU];
+#pragma unroll
+                for (uint32_t r = 0; r < FU; r++) cw[r] = Cu[xr[r] >> 6];
+#pragma unroll
+                for (uint32_t r = 0; r < FU; r++) {
+                    if (XS && kp[r]) L.x[pr[r]] = xr[r];
+                    kp[r] = kp[r] && ((cw[r] >> (xr[r] & 63)) & 1ull);
+                }
             }
             if (!plan->homo) {
                 for (uint32_t c = 0; c < j; c += 4) {
@@ -280,7 +291,7 @@ __device__ __forceinline__ void fused_query(const FPlan *plan, uint32_t j0, cons
                     for (uint32_t r = 0; r < FU; r++)
 #pragma unroll
                         for (uint32_t q = 0; q < 4; q++)
-                            mv[r][q] = (kp[r] && c + q < j) ? M[(uint64_t)(c + q) * ld + ir[r]] : ~xr[r];
+                            mv[r][q] = M[(uint64_t)(c + q < j ? c + q : j - 1) * ld + ir[r]];
 #pragma unroll
                     for (uint32_t r = 0; r < FU; r++)
 #pragma unroll
@@ -371,10 +382,13 @@ __device__ __forceinline__ void fused_query(const FPlan *plan, uint32_t j0, cons
 #pragma unroll
             for (uint32_t r = 0; r < FU; r++) pr[r] = kp[r] ? wd[r] * 64 + nth_set_bit(s_bits[wd[r]], rk[r]) : 0u;
             lds_rows<FU>(s_F, R, pr, ir, fr);
+            // unconditional loads from valid addresses, masked afterwards
 #pragma unroll
             for (uint32_t r = 0; r < FU; r++) {
-                xr[r] = 0;
-                if (kp[r]) xr[r] = XS ? L.x[pr[r]] : ci_all[L.st[ir[r]] + (pr[r] - fr[r])];
+                if (!kp[r]) ir[r] = 0;
+                if (XS) xr[r] = L.x[kp[r] ? pr[r] : 0u];
+                else xr[r] = ci_all[kp[r] ? L.st[ir[r]] + (pr[r] - fr[r]) : 0u];
+                if (!kp[r]) xr[r] = 0;
             }
             if (!final_level) {
                 for (uint32_t c = 0; c < j; c += 4) {
@@ -383,7 +397,7 @@ __device__ __forceinline__ void fused_query(const FPlan *plan, uint32_t j0, cons
                     for (uint32_t r = 0; r < FU; r++)
 #pragma unroll
                         for (uint32_t q = 0; q < 4; q++)
-                            mv[r][q] = (kp[r] && c + q < j) ? M[(uint64_t)(c + q) * ld + ir[r]] : 0u;
+                            mv[r][q] = M[(uint64_t)(c + q < j ? c + q : j - 1) * ld + ir[r]];
 #pragma unroll
                     for (uint32_t r = 0; r < FU; r++)
 #pragma unroll
@@ -403,8 +417,10 @@ __device__ __forceinline__ void fused_query(const FPlan *plan, uint32_t j0, cons
                     for (uint32_t q = 0; q < 4; q++) {
                         const uint32_t c = u0 + q < k ? plan->qcol[u0 + q] : j;
 #pragma unroll
-                        for (uint32_t r = 0; r < FU; r++)
-                            val[r][q] = (kp[r] && c < j) ? M[(uint64_t)c * ld + ir[r]] : xr[r];
+                        for (uint32_t r = 0; r < FU; r++) {
+                            const uint32_t mv = M[(uint64_t)(c < j ? c : 0u) * ld + ir[r]];
+                            val[r][q] = c < j ? mv : xr[r];
+                        }
                     }
 #pragma unroll
                     for (uint32_t q = 0; q < 4; q++)

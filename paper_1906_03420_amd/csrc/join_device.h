@@ -59,6 +59,58 @@ __host__ __device__ __forceinline__ bool in_sorted(const uint32_t *list, uint32_
     return hit;
 }
 
+// in_sorted for U (list, x) pairs at once: list u is base[st[u] ..
+// st[u] + len[u]).  Each round issues the probes of every pair before any
+// is compared, so a thread waits for one chain of dependent loads instead
+// of U.  A pair whose range is already down to 8 (or an empty list) probes
+// base[lo] again, a valid address: base[0] when the list is empty, which
+// every label holding an edge has.
+template <uint32_t U>
+__device__ __forceinline__ void in_sorted_many(const uint32_t *base, const uint32_t *st, const uint32_t *len,
+                                               const uint32_t *x, bool *hit) {
+    uint32_t lo[U], n[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; u++) {
+        lo[u] = len[u] ? st[u] : 0u;
+        n[u] = len[u];
+    }
+    for (;;) {
+        bool more = false;
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) more |= n[u] > 8;
+        if (!more) break;
+        uint32_t v[U][7];
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) {
+            const uint32_t s = (n[u] + 7) / 8;
+#pragma unroll
+            for (uint32_t t = 1; t < 8; t++) v[u][t - 1] = base[lo[u] + (n[u] > 8 && s * t < n[u] ? s * t : 0u)];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) {
+            if (n[u] <= 8) continue;
+            const uint32_t s = (n[u] + 7) / 8;
+            uint32_t c = 0;
+#pragma unroll
+            for (uint32_t t = 1; t < 8; t++) c += (s * t < n[u] && v[u][t - 1] <= x[u]) ? 1u : 0u;
+            lo[u] += s * c;
+            n[u] = (n[u] - s * c) < s ? (n[u] - s * c) : s;
+        }
+    }
+    uint32_t w[U][8];
+#pragma unroll
+    for (uint32_t u = 0; u < U; u++)
+#pragma unroll
+        for (uint32_t t = 0; t < 8; t++) w[u][t] = base[lo[u] + (t < n[u] ? t : 0u)];
+#pragma unroll
+    for (uint32_t u = 0; u < U; u++) {
+        bool h = false;
+#pragma unroll
+        for (uint32_t t = 0; t < 8; t++) h |= t < n[u] && w[u][t] == x[u];
+        hit[u] = h;
+    }
+}
+
 // FNV-1a-64 over the four little-endian bytes of one 32-bit word
 __device__ __forceinline__ uint64_t fnv_word(uint64_t h, uint32_t v) {
 #pragma unroll

@@ -89,6 +89,87 @@ __device__ __forceinline__ uint64_t row_of(const uint64_t *F, uint64_t lo, uint6
     return lo;
 }
 
+// x among the j values of row i (m_i).  The values are loaded eight at a
+// time, every load issued before the compares: a column past j re-reads
+// column j - 1 (a valid address) instead of branching around the load,
+// which would make each load wait for the one before it.
+__device__ __forceinline__ bool in_row(const LevelArgs &a, uint64_t i, uint32_t x) {
+    bool hit = false;
+    for (uint32_t c = 0; c < a.j; c += 8) {
+        uint32_t m[8];
+#pragma unroll
+        for (uint32_t t = 0; t < 8; t++) {
+            const uint32_t cc = c + t < a.j ? c + t : a.j - 1;
+            m[t] = a.M[(uint64_t)cc * a.ldm + i];
+        }
+#pragma unroll
+        for (uint32_t t = 0; t < 8; t++) hit |= m[t] == x;
+    }
+    return hit;
+}
+
+// The costly tests of U candidates at once: keep[u] (on entry: whether
+// candidate u is live) becomes x[u] not in m_i of row i[u] and x[u] in
+// every other linking list of that row.  Every step issues the loads of
+// all U candidates before using any (the row's values, the scanned edge,
+// the lists' bounds, each search round), so a thread waits for one chain of
+// dependent loads per step instead of U.
+template <uint32_t U>
+__device__ __forceinline__ void keep_many(const LevelArgs &a, const uint32_t *x, const uint64_t *i, bool *keep) {
+    if (!a.homo) {
+        for (uint32_t c = 0; c < a.j; c += 8) {
+            uint32_t m[U][8];
+#pragma unroll
+            for (uint32_t u = 0; u < U; u++)
+#pragma unroll
+                for (uint32_t t = 0; t < 8; t++) m[u][t] = a.M[(uint64_t)(c + t < a.j ? c + t : a.j - 1) * a.ldm + i[u]];
+#pragma unroll
+            for (uint32_t u = 0; u < U; u++)
+#pragma unroll
+                for (uint32_t t = 0; t < 8; t++) keep[u] = keep[u] && m[u][t] != x[u];
+        }
+    }
+    if (a.ne < 2) return;
+    uint32_t be[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; u++) be[u] = a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i[u]];
+    for (uint32_t e2 = 0; e2 < a.ne; e2++) {
+        uint32_t st[U], len[U];
+        bool act[U], hit[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) {
+            st[u] = a.loc[(uint64_t)e2 * a.R + i[u]];
+            len[u] = a.loc[(uint64_t)(a.ne + e2) * a.R + i[u]];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) {
+            act[u] = keep[u] && e2 != be[u];
+            if (!act[u]) len[u] = 0;
+        }
+        in_sorted_many<U>(a.e[e2].ci, st, len, x, hit);
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++)
+            if (act[u]) keep[u] = hit[u];
+    }
+}
+
+// Copies the j values of row i to column-major dst (column c at
+// dst[c * stride + pos]), loads issued eight at a time as in in_row.
+__device__ __forceinline__ void copy_row(const LevelArgs &a, uint64_t i, uint32_t *dst, uint64_t stride,
+                                         uint64_t pos) {
+    for (uint32_t c = 0; c < a.j; c += 8) {
+        uint32_t m[8];
+#pragma unroll
+        for (uint32_t t = 0; t < 8; t++) {
+            const uint32_t cc = c + t < a.j ? c + t : a.j - 1;
+            m[t] = a.M[(uint64_t)cc * a.ldm + i];
+        }
+#pragma unroll
+        for (uint32_t t = 0; t < 8; t++)
+            if (c + t < a.j) dst[(uint64_t)(c + t) * stride + pos] = m[t];
+    }
+}
+
 // slot x of row i survives: x in C(u), x not in m_i, x in every other
 // linking list of the row
 __device__ __forceinline__ bool slot_keep(const LevelArgs &a, uint64_t i, uint32_t x) {

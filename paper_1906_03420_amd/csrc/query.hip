@@ -202,8 +202,10 @@ static void query_signatures(const HostQuery &q, FilterArgs &fa, bool homo = fal
 // of query word q that the vertex lacks are (~w & q), one and-or per word.
 // The wave's ballot of "v in C(u)" is the bitset word of its 64 vertices;
 // lane u stores the word of query vertex u, so one store instruction
-// writes them all.
-constexpr uint32_t FILTER_TILES = 4;
+// writes them all.  One tile per workgroup: on an 8.4M-vertex table with
+// every word in use the launch takes 118 us (4.6 TB/s), 133 us with four
+// tiles (fewer workgroups in flight, more registers each).
+constexpr uint32_t FILTER_TILES = 1;
 
 __global__ __launch_bounds__(QT) void k_filter(const uint32_t *sig, uint32_t n, uint64_t nwords, FilterArgs fa,
                                               uint64_t *bits) {
@@ -211,14 +213,23 @@ __global__ __launch_bounds__(QT) void k_filter(const uint32_t *sig, uint32_t n, 
     const uint32_t K = fa.k;
     const uint32_t lane = lane_id();
     uint32_t w0[FILTER_TILES], nw[FILTER_TILES][GSI_SIG_WORDS];
+    // Every load is issued unconditionally (a word no query vertex uses, or
+    // a lane past n, re-reads a valid word-0 address, a cache hit) and only
+    // then masked: branching around a load makes it wait for the one before.
 #pragma unroll
     for (uint32_t r = 0; r < FILTER_TILES; r++) {
         const uint64_t v = ((uint64_t)blockIdx.x * FILTER_TILES + r) * QT + threadIdx.x;
-        const bool valid = v < n;
-        w0[r] = valid ? sig[v] : NONE32;
+        const uint64_t vv = v < n ? v : (uint64_t)n - 1;
+        w0[r] = sig[vv];
 #pragma unroll
-        for (int i = 1; i < GSI_SIG_WORDS; i++)
-            nw[r][i] = (((need >> i) & 1u) && valid) ? ~sig[(uint64_t)i * n + v] : 0u;
+        for (int i = 1; i < GSI_SIG_WORDS; i++) nw[r][i] = sig[((need >> i) & 1u) ? (uint64_t)i * n + vv : vv];
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < FILTER_TILES; r++) {
+        const bool valid = ((uint64_t)blockIdx.x * FILTER_TILES + r) * QT + threadIdx.x < n;
+        if (!valid) w0[r] = NONE32;
+#pragma unroll
+        for (int i = 1; i < GSI_SIG_WORDS; i++) nw[r][i] = (((need >> i) & 1u) && valid) ? ~nw[r][i] : 0u;
     }
 #pragma unroll
     for (uint32_t r = 0; r < FILTER_TILES; r++) {
@@ -392,7 +403,8 @@ __global__ __launch_bounds__(QT) void k_filter_multi(const uint32_t *sig, uint32
 #pragma unroll
         for (uint32_t r = 0; r < FM_TILE / QT; r++) {
             const uint64_t v = v0 + r * QT + threadIdx.x;
-            w0[r] = v < n ? sig[v] : NONE32;
+            w0[r] = sig[v < n ? v : (uint64_t)n - 1];
+            if (v >= n) w0[r] = NONE32;
         }
 #pragma unroll
         for (uint32_t r = 0; r < FM_TILE / QT; r++) {
@@ -423,9 +435,14 @@ __global__ __launch_bounds__(QT) void k_filter_multi(const uint32_t *sig, uint32
             // vertex's are then (~w & q), one and-or per word, with no
             // per-word branch or mask arithmetic; words no query vertex of
             // the pass uses are zero in every query signature
+            // (every load issued unconditionally, an unused word re-reading
+            // word 0 of the vertex, then masked: a load behind a branch
+            // waits for the one before)
             uint32_t nw[GSI_SIG_WORDS];
 #pragma unroll
-            for (int i = 1; i < GSI_SIG_WORDS; i++) nw[i] = ((need >> i) & 1u) ? ~sig[(uint64_t)i * n + v] : 0u;
+            for (int i = 1; i < GSI_SIG_WORDS; i++) nw[i] = sig[((need >> i) & 1u) ? (uint64_t)i * n + v : v];
+#pragma unroll
+            for (int i = 1; i < GSI_SIG_WORDS; i++) nw[i] = ((need >> i) & 1u) ? ~nw[i] : 0u;
             const uint32_t ue = s_gbeg[gi + 1];
             for (uint32_t u = s_gbeg[gi]; u < ue; u++) {
                 uint32_t miss = 0;
@@ -587,7 +604,17 @@ __global__ __launch_bounds__(QT) void k_locate(LevelArgs a) {
         a.bound[i] = bl;
         a.loc[(uint64_t)(2 * a.ne) * a.R + i] = a.e[be].ci_off + bs;
         if (a.ne > 1) a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] = be;
-        other = all - bl;
+        // elements of the other linking lists the join must read at least:
+        // testing at most bl candidates against a list of L entries touches
+        // at least min(L, bl) of them (one per candidate, or the whole list)
+        if (a.part) {
+            (void)all;
+            for (uint32_t e = 0; e < a.ne; e++) {
+                if (e == be) continue;
+                const uint64_t L = a.loc[(uint64_t)(a.ne + e) * a.R + i];
+                other += L < (uint64_t)bl ? L : (uint64_t)bl;
+            }
+        }
     }
     if (!a.part) return;  // list-length totals are gathered for profiling only
     __shared__ uint64_t s_o[QT / 64];
@@ -682,6 +709,8 @@ constexpr double FN_FACTOR = 2.0;
 // each thread has four independent gathers in flight; small levels keep
 // one slot per thread (SPT = 1) and four times as many workgroups.
 constexpr uint64_t WIDE_TILE_SLOTS = 1ull << 22;  // |GBA| from which SPT = 4
+// candidates a join thread tests at once (keep_many)
+constexpr uint32_t JU = 4;
 
 // The rows r_lo..r_hi a tile touches.  When they are at most the tile's slot
 // count they are staged in LDS; tiles spanning more rows (long runs of rows
@@ -817,9 +846,17 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
     }
     // x in C(u); the slots that pass are compacted (in no particular order)
     // so that the remaining tests, the costly ones, run in dense waves
+    if (!a.prefiltered) {
+        // every slot's C(u) word is loaded before any is tested (an invalid
+        // slot has x = 0, a valid word)
+        uint64_t cw[SPT];
+#pragma unroll
+        for (uint32_t r = 0; r < SPT; r++) cw[r] = a.Cu[xs[r] >> 6];
+#pragma unroll
+        for (uint32_t r = 0; r < SPT; r++) kp[r] = kp[r] && ((cw[r] >> (xs[r] & 63)) & 1ull);
+    }
 #pragma unroll
     for (uint32_t r = 0; r < SPT; r++) {
-        if (kp[r] && !a.prefiltered) kp[r] = (a.Cu[xs[r] >> 6] >> (xs[r] & 63)) & 1ull;
         const uint64_t mask = __ballot(kp[r]);
         if (mask) {
             uint32_t base = 0;
@@ -837,27 +874,24 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
     // x not in m_i (the row's values are loaded four at a time, not one
     // dependent load per column), x in every other linking list
     const uint32_t n = __builtin_amdgcn_readfirstlane(s_n);
-    for (uint32_t e = threadIdx.x; e < n; e += QT) {
-        const uint32_t slot = s_slot[e], x = s_x[e];
-        const uint64_t i = tr.r_lo + s_ri[e];
-        bool keep = true;
-        if (!a.homo) {
-            for (uint32_t c = 0; c < a.j; c += 4) {
-                uint32_t m0 = a.M[(uint64_t)c * a.ldm + i];
-                uint32_t m1 = c + 1 < a.j ? a.M[(uint64_t)(c + 1) * a.ldm + i] : ~x;
-                uint32_t m2 = c + 2 < a.j ? a.M[(uint64_t)(c + 2) * a.ldm + i] : ~x;
-                uint32_t m3 = c + 3 < a.j ? a.M[(uint64_t)(c + 3) * a.ldm + i] : ~x;
-                keep = keep && m0 != x && m1 != x && m2 != x && m3 != x;
-            }
+    // JU candidates per thread at a time, their loads issued together
+    for (uint32_t e0 = 0; e0 < n; e0 += JU * QT) {
+        uint32_t xs[JU], sl[JU];
+        uint64_t is[JU];
+        bool kp[JU];
+#pragma unroll
+        for (uint32_t u = 0; u < JU; u++) {
+            const uint32_t e = e0 + u * QT + threadIdx.x;
+            kp[u] = e < n;
+            const uint32_t c = kp[u] ? e : 0u;  // a past-the-end thread reads candidate 0
+            sl[u] = s_slot[c];
+            xs[u] = s_x[c];
+            is[u] = tr.r_lo + s_ri[c];
         }
-        const uint32_t be = (keep && a.ne > 1) ? a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] : a.e0;
-        for (uint32_t e2 = 0; keep && e2 < a.ne; e2++) {
-            if (e2 == be) continue;
-            uint32_t st = a.loc[(uint64_t)e2 * a.R + i];
-            uint32_t len = a.loc[(uint64_t)(a.ne + e2) * a.R + i];
-            keep = in_sorted(a.e[e2].ci + st, len, x);
-        }
-        if (keep) atomicOr(&s_keep[slot >> 6], 1ull << (slot & 63));
+        keep_many<JU>(a, xs, is, kp);
+#pragma unroll
+        for (uint32_t u = 0; u < JU; u++)
+            if (kp[u]) atomicOr(&s_keep[sl[u] >> 6], 1ull << (sl[u] & 63));
     }
     __syncthreads();
     // the tile's keep bits (one word per 64 slots) and their count
@@ -883,7 +917,11 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
     __shared__ uint32_t s_pre[TS / 64 + 1];  // kept slots before each bitmap word of the tile
     __shared__ uint64_t s_w[TS / 64];        // the tile's keep bits (two-step ablation)
     __shared__ uint16_t s_list[TS];          // the tile's kept slots, compacted
+    __shared__ uint32_t s_qc[GSI_MAX_K];     // query vertex -> column (last level)
     const uint64_t tile = blockIdx.x;
+    // the column map is read from LDS in the row loop: from the argument
+    // segment each column would be a scalar load waited on in turn
+    if (threadIdx.x < GSI_MAX_K) s_qc[threadIdx.x] = a.qcol[threadIdx.x];
     if (a.tile_off[tile + 1] == a.tile_off[tile]) {  // whole tile empty (uniform)
         if (a.final_level && threadIdx.x == 0) {
             a.dig_part[2 * tile] = 0;
@@ -960,27 +998,21 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
             // the row's values are loaded four at a time (independent
             // loads), not one dependent round trip per column
             if (!a.final_level) {
-                for (uint32_t c = 0; c < a.j; c += 4) {
-                    uint32_t m[4];
-#pragma unroll
-                    for (uint32_t k4 = 0; k4 < 4; k4++) m[k4] = c + k4 < a.j ? a.M[(uint64_t)(c + k4) * a.ldm + i] : 0u;
-#pragma unroll
-                    for (uint32_t k4 = 0; k4 < 4; k4++)
-                        if (c + k4 < a.j) a.Mn[(uint64_t)(c + k4) * a.S + pos] = m[k4];
-                }
+                copy_row(a, i, a.Mn, a.S, pos);
                 a.Mn[(uint64_t)a.j * a.S + pos] = x;
             } else {
                 const uint32_t local = threadIdx.x;  // row within this round's block
                 uint64_t f = 14695981039346656037ull;
-                for (uint32_t u0 = 0; u0 < a.k; u0 += 4) {
-                    uint32_t val[4];
+                for (uint32_t u0 = 0; u0 < a.k; u0 += 8) {
+                    uint32_t val[8];
 #pragma unroll
-                    for (uint32_t k4 = 0; k4 < 4; k4++) {
-                        const uint32_t c = u0 + k4 < a.k ? a.qcol[u0 + k4] : a.j;
-                        val[k4] = c < a.j ? a.M[(uint64_t)c * a.ldm + i] : x;
+                    for (uint32_t k4 = 0; k4 < 8; k4++) {
+                        const uint32_t c = u0 + k4 < a.k ? s_qc[u0 + k4] : a.j;
+                        const uint32_t mv = a.M[(uint64_t)(c < a.j ? c : 0u) * a.ldm + i];
+                        val[k4] = c < a.j ? mv : x;
                     }
 #pragma unroll
-                    for (uint32_t k4 = 0; k4 < 4; k4++) {
+                    for (uint32_t k4 = 0; k4 < 8; k4++) {
                         const uint32_t u = u0 + k4;
                         if (u >= a.k) break;
                         if (stage) s_rows[local * a.k + u] = val[k4];
@@ -1086,24 +1118,30 @@ __device__ __forceinline__ uint64_t lookback(unsigned long long *st, uint64_t ti
 template <uint32_t SPT, bool FINAL>
 __global__ __launch_bounds__(QT) void k_join_pass(LevelArgs a) {
     constexpr uint32_t TS = SPT * QT;
+    // The join's arrays and the write's share one LDS block (the join's are
+    // dead once the keep bits are summed), so that more workgroups fit a CU.
+    constexpr uint32_t JOIN_WORDS = 3 * TS + TS / 2, WRITE_WORDS = (FINAL ? QT * LINK_STAGE_K : 0) + TS / 2;
+    __shared__ uint32_t s_u[JOIN_WORDS > WRITE_WORDS ? JOIN_WORDS : WRITE_WORDS];
     __shared__ uint32_t s_row[TS];    // row of each slot (staged tiles)
-    __shared__ uint32_t s_base[TS];   // per row: ci_all position of slot 0
     __shared__ uint32_t s_xv[TS];     // element of each slot
-    __shared__ uint32_t s_x[TS];      // elements that passed C(u), compacted
-    __shared__ uint32_t s_ri[TS];     // and their rows
-    __shared__ uint16_t s_slot[TS];   // and their slots
-    __shared__ uint16_t s_list[TS];   // kept slots in slot order
+    uint32_t *s_base = s_u;           // join: per row, ci_all position of slot 0
+    uint32_t *s_x = s_u + TS;         // join: elements that passed C(u), compacted
+    uint32_t *s_ri = s_u + 2 * TS;    // join: and their rows
+    uint16_t *s_slot = reinterpret_cast<uint16_t *>(s_u + 3 * TS);  // join: and their slots
+    uint32_t *s_rows = s_u;           // write: the round's rows, staged
+    uint16_t *s_list = reinterpret_cast<uint16_t *>(s_u + (FINAL ? QT * LINK_STAGE_K : 0));  // write: kept slots
     __shared__ uint64_t s_keep[TS / 64];
     __shared__ uint32_t s_pre[TS / 64 + 1];
     __shared__ uint32_t s_w[QT / 64];
-    __shared__ uint32_t s_rows[QT * LINK_STAGE_K];
     __shared__ uint64_t s_d[2][QT / 64];
+    __shared__ uint32_t s_qc[GSI_MAX_K];  // query vertex -> column (read from LDS in the row loop)
     __shared__ uint32_t s_n;
     __shared__ uint64_t s_tile, s_off;
     if (threadIdx.x == 0) {
         s_n = 0;
         s_tile = atomicAdd(a.tctr, 1u);
     }
+    if (FINAL && threadIdx.x < GSI_MAX_K) s_qc[threadIdx.x] = a.qcol[threadIdx.x];
     if (threadIdx.x < TS / 64) s_keep[threadIdx.x] = 0;
 #pragma unroll
     for (uint32_t k = 0; k < SPT; k++) s_row[threadIdx.x * SPT + k] = 0;
@@ -1128,9 +1166,17 @@ __global__ __launch_bounds__(QT) void k_join_pass(LevelArgs a) {
         }
         s_xv[sl] = xs[r];
     }
+    if (!a.prefiltered) {
+        // every slot's C(u) word is loaded before any is tested (an invalid
+        // slot has x = 0, a valid word)
+        uint64_t cw[SPT];
+#pragma unroll
+        for (uint32_t r = 0; r < SPT; r++) cw[r] = a.Cu[xs[r] >> 6];
+#pragma unroll
+        for (uint32_t r = 0; r < SPT; r++) kp[r] = kp[r] && ((cw[r] >> (xs[r] & 63)) & 1ull);
+    }
 #pragma unroll
     for (uint32_t r = 0; r < SPT; r++) {
-        if (kp[r] && !a.prefiltered) kp[r] = (a.Cu[xs[r] >> 6] >> (xs[r] & 63)) & 1ull;
         const uint64_t mask = __ballot(kp[r]);
         if (mask) {
             uint32_t base = 0;
@@ -1146,27 +1192,24 @@ __global__ __launch_bounds__(QT) void k_join_pass(LevelArgs a) {
     }
     __syncthreads();
     const uint32_t nc = __builtin_amdgcn_readfirstlane(s_n);
-    for (uint32_t e = threadIdx.x; e < nc; e += QT) {
-        const uint32_t slot = s_slot[e], x = s_x[e];
-        const uint64_t i = tr.r_lo + s_ri[e];
-        bool keep = true;
-        if (!a.homo) {
-            for (uint32_t c = 0; c < a.j; c += 4) {
-                uint32_t m0 = a.M[(uint64_t)c * a.ldm + i];
-                uint32_t m1 = c + 1 < a.j ? a.M[(uint64_t)(c + 1) * a.ldm + i] : ~x;
-                uint32_t m2 = c + 2 < a.j ? a.M[(uint64_t)(c + 2) * a.ldm + i] : ~x;
-                uint32_t m3 = c + 3 < a.j ? a.M[(uint64_t)(c + 3) * a.ldm + i] : ~x;
-                keep = keep && m0 != x && m1 != x && m2 != x && m3 != x;
-            }
+    // JU candidates per thread at a time, their loads issued together
+    for (uint32_t e0 = 0; e0 < nc; e0 += JU * QT) {
+        uint32_t xs[JU], sl[JU];
+        uint64_t is[JU];
+        bool kp[JU];
+#pragma unroll
+        for (uint32_t u = 0; u < JU; u++) {
+            const uint32_t e = e0 + u * QT + threadIdx.x;
+            kp[u] = e < nc;
+            const uint32_t c = kp[u] ? e : 0u;  // a past-the-end thread reads candidate 0
+            sl[u] = s_slot[c];
+            xs[u] = s_x[c];
+            is[u] = tr.r_lo + s_ri[c];
         }
-        const uint32_t be = (keep && a.ne > 1) ? a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] : a.e0;
-        for (uint32_t e2 = 0; keep && e2 < a.ne; e2++) {
-            if (e2 == be) continue;
-            uint32_t st = a.loc[(uint64_t)e2 * a.R + i];
-            uint32_t len = a.loc[(uint64_t)(a.ne + e2) * a.R + i];
-            keep = in_sorted(a.e[e2].ci + st, len, x);
-        }
-        if (keep) atomicOr(&s_keep[slot >> 6], 1ull << (slot & 63));
+        keep_many<JU>(a, xs, is, kp);
+#pragma unroll
+        for (uint32_t u = 0; u < JU; u++)
+            if (kp[u]) atomicOr(&s_keep[sl[u] >> 6], 1ull << (sl[u] & 63));
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1201,14 +1244,7 @@ __global__ __launch_bounds__(QT) void k_join_pass(LevelArgs a) {
             if (pos >= a.out_cap) break;
             const uint32_t slot = s_list[q];
             const uint64_t i = tr.staged ? tr.r_lo + s_row[slot] : row_of(a.F, tr.r_lo, tr.r_hi, p0 + slot);
-            for (uint32_t c = 0; c < a.j; c += 4) {
-                uint32_t m[4];
-#pragma unroll
-                for (uint32_t k4 = 0; k4 < 4; k4++) m[k4] = c + k4 < a.j ? a.M[(uint64_t)(c + k4) * a.ldm + i] : 0u;
-#pragma unroll
-                for (uint32_t k4 = 0; k4 < 4; k4++)
-                    if (c + k4 < a.j) a.Mn[(uint64_t)(c + k4) * a.out_cap + pos] = m[k4];
-            }
+            copy_row(a, i, a.Mn, a.out_cap, pos);
             a.Mn[(uint64_t)a.j * a.out_cap + pos] = s_xv[slot];
         }
         return;
@@ -1229,15 +1265,16 @@ __global__ __launch_bounds__(QT) void k_join_pass(LevelArgs a) {
             }
             const uint32_t x = s_xv[slot];
             uint64_t f = 14695981039346656037ull;
-            for (uint32_t u0 = 0; u0 < a.k; u0 += 4) {
-                uint32_t val[4];
+            for (uint32_t u0 = 0; u0 < a.k; u0 += 8) {
+                uint32_t val[8];
 #pragma unroll
-                for (uint32_t k4 = 0; k4 < 4; k4++) {
-                    const uint32_t c = u0 + k4 < a.k ? a.qcol[u0 + k4] : a.j;
-                    val[k4] = c < a.j ? a.M[(uint64_t)c * a.ldm + i] : x;
+                for (uint32_t k4 = 0; k4 < 8; k4++) {
+                    const uint32_t c = u0 + k4 < a.k ? s_qc[u0 + k4] : a.j;
+                    const uint32_t mv = a.M[(uint64_t)(c < a.j ? c : 0u) * a.ldm + i];
+                    val[k4] = c < a.j ? mv : x;
                 }
 #pragma unroll
-                for (uint32_t k4 = 0; k4 < 4; k4++) {
+                for (uint32_t k4 = 0; k4 < 8; k4++) {
                     const uint32_t u = u0 + k4;
                     if (u >= a.k) break;
                     if (stage) s_rows[threadIdx.x * a.k + u] = val[k4];
@@ -1431,7 +1468,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     constexpr uint32_t ABL = GSI_ABL_CR | GSI_ABL_TWO_STEP | GSI_ABL_NO_STAGING | JOIN_ABL | GSI_ABL_DUP_REMOVAL;
     const uint32_t flags = (opt ? opt->flags : 0u) | ((opt && (opt->flags & ABL)) ? GSI_NO_FUSED : 0u);
     if (opt && (opt->flags & ~(GSI_COUNT_ONLY | GSI_FILTER_LABEL_ONLY | GSI_NO_FUSED | GSI_NO_CHUNKS |
-                               GSI_LEVEL_FIRST_EDGE | GSI_HOMOMORPHISM | GSI_NO_LIST_FILTER | GSI_NO_SINGLE_PASS |
+                               GSI_LEVEL_FIRST_EDGE | GSI_HOMOMORPHISM | GSI_NO_LIST_FILTER | GSI_SINGLE_PASS |
                                ABL)))
         fail(GSI_E_INVALID, "unknown query flag");
     if (__builtin_popcount(flags & JOIN_ABL) > 1 || ((flags & JOIN_ABL) && (flags & GSI_ABL_TWO_STEP)))
@@ -1988,7 +2025,7 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         // The last level in one pass (join, look-back, rows) when the output
         // can be sized at |GBA| rows, its survivors' upper bound.
         const uint64_t before_rows = (cp.active && !cp.merged) ? cp.count : 0;
-        const bool single_pass = final_level && !(flags & (ABL | GSI_NO_SINGLE_PASS)) &&
+        const bool single_pass = final_level && (flags & GSI_SINGLE_PASS) && !(flags & ABL) &&
                                  (count_only || (gba + before_rows) * k * 4 <= c->arena.largest_free() / 2);
         if (single_pass) {
             uint64_t *trow = ls.get<uint64_t>(ntiles + 1, "tile rows");
@@ -2043,7 +2080,8 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         // An inner level in one pass too, when its rows scan filtered lists
         // and have one linking edge (nearly every slot survives, so the
         // next table, written at |GBA| rows per column, wastes little).
-        const bool inner_pass = !final_level && a.prefiltered && ne == 1 && !(flags & (ABL | GSI_NO_SINGLE_PASS)) &&
+        const bool inner_pass = !final_level && a.prefiltered && ne == 1 && (flags & GSI_SINGLE_PASS) &&
+                                !(flags & ABL) &&
                                 (uint64_t)(j + 1) * gba * 4 <= c->arena.largest_free() / 2;
         if (inner_pass) {
             uint64_t *trow = ls.get<uint64_t>(ntiles + 1, "tile rows");

@@ -50,6 +50,51 @@ struct WQ {
     uint32_t qcol[GSI_MAX_K];
 };
 
+// candidates a join thread tests at once (wkeep_many)
+constexpr uint32_t WU = 4;
+
+// The costly tests of U candidates of query Q at once (rows i[u] of Q's
+// table): keep[u] (on entry: candidate u is live) becomes x[u] not in the
+// row's values and x[u] in every other linking list of the row.  Every step
+// issues the loads of all U candidates before using any.
+template <uint32_t U>
+__device__ __forceinline__ void wkeep_many(const WQ &Q, const uint32_t *loc, const WEdge *edges, const uint32_t *x,
+                                           const uint64_t *i, bool *keep) {
+    for (uint32_t c = 0; c < Q.j; c += 8) {
+        uint32_t m[U][8];
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++)
+#pragma unroll
+            for (uint32_t t = 0; t < 8; t++) m[u][t] = Q.M[(uint64_t)(c + t < Q.j ? c + t : Q.j - 1) * Q.R + i[u]];
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++)
+#pragma unroll
+            for (uint32_t t = 0; t < 8; t++) keep[u] = keep[u] && m[u][t] != x[u];
+    }
+    if (Q.ne < 2) return;
+    uint32_t be[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; u++) be[u] = loc[Q.locbase + (uint64_t)(2 * Q.ne + 1) * Q.R + i[u]];
+    for (uint32_t e2 = 0; e2 < Q.ne; e2++) {
+        uint32_t st[U], len[U];
+        bool act[U], hit[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) {
+            st[u] = loc[Q.locbase + (uint64_t)e2 * Q.R + i[u]];
+            len[u] = loc[Q.locbase + (uint64_t)(Q.ne + e2) * Q.R + i[u]];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) {
+            act[u] = keep[u] && e2 != be[u];
+            if (!act[u]) len[u] = 0;
+        }
+        in_sorted_many<U>(edges[Q.efirst + e2].ci, st, len, x, hit);
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++)
+            if (act[u]) keep[u] = hit[u];
+    }
+}
+
 static uint32_t wblocks(uint64_t n) {
     uint64_t b = (n + WT - 1) / WT;
     if (b == 0) b = 1;
@@ -212,12 +257,20 @@ __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, const uint32_t *rowq
             xs[k] = ci_all[st0 + (uint32_t)(p - Fr)];
         }
     }
+    {
+        // every slot's C(u) word is loaded before any is tested (a slot past
+        // |GBA| has x = 0 and row r_lo: valid addresses)
+        uint64_t cw[TPW];
+#pragma unroll
+        for (uint32_t k = 0; k < TPW; k++) {
+            const uint64_t *Cu = one ? s_Q.Cu : qs[rowq[r_lo + rs[k]]].Cu;
+            cw[k] = Cu[xs[k] >> 6];
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < TPW; k++) kp[k] = kp[k] && ((cw[k] >> (xs[k] & 63)) & 1ull);
+    }
 #pragma unroll
     for (uint32_t k = 0; k < TPW; k++) {
-        if (kp[k]) {
-            const uint64_t *Cu = one ? s_Q.Cu : qs[rowq[r_lo + rs[k]]].Cu;
-            kp[k] = (Cu[xs[k] >> 6] >> (xs[k] & 63)) & 1ull;
-        }
         const uint64_t pm = __ballot(kp[k]);
         if (pm) {
             uint32_t base = 0;
@@ -233,19 +286,42 @@ __global__ __launch_bounds__(WT) void k_wjoin(const WQ *qs, const uint32_t *rowq
     }
     __syncthreads();
     const uint32_t n = __builtin_amdgcn_readfirstlane(s_n);
-    for (uint32_t e = threadIdx.x; e < n; e += WT) {
+    if (one) {
+        // one query in the tile: WU candidates per thread at a time, their
+        // loads issued together
+        for (uint32_t e0 = 0; e0 < n; e0 += WU * WT) {
+            uint32_t xs2[WU], sl[WU];
+            uint64_t is[WU];
+            bool kq[WU];
+#pragma unroll
+            for (uint32_t u = 0; u < WU; u++) {
+                const uint32_t e = e0 + u * WT + threadIdx.x;
+                kq[u] = e < n;
+                const uint32_t c = kq[u] ? e : 0u;  // a past-the-end thread reads candidate 0
+                sl[u] = s_slot[c];
+                xs2[u] = s_x[c];
+                is[u] = r_lo + s_r[c] - s_Q.rbase;
+            }
+            wkeep_many<WU>(s_Q, loc, edges, xs2, is, kq);
+#pragma unroll
+            for (uint32_t u = 0; u < WU; u++)
+                if (kq[u]) atomicOr(&s_keep[sl[u] >> 6], 1ull << (sl[u] & 63));
+        }
+    }
+    for (uint32_t e = one ? n : threadIdx.x; e < n; e += WT) {
         const uint32_t slot = s_slot[e], xv = s_x[e];
         const uint64_t r = r_lo + s_r[e];
         const WQ &Q = one ? s_Q : qs[rowq[r]];
         const uint64_t i = r - Q.rbase;
         bool keep = true;
-        // x not in m_i: the row's values four at a time (independent loads)
-        for (uint32_t c = 0; keep && c < Q.j; c += 4) {
-            uint32_t m[4];
+        // x not in m_i: the row's values eight at a time, every load issued
+        // before the compares (a column past j re-reads column j - 1)
+        for (uint32_t c = 0; keep && c < Q.j; c += 8) {
+            uint32_t m[8];
 #pragma unroll
-            for (uint32_t q = 0; q < 4; q++) m[q] = c + q < Q.j ? Q.M[(uint64_t)(c + q) * Q.R + i] : ~xv;
+            for (uint32_t q = 0; q < 8; q++) m[q] = Q.M[(uint64_t)(c + q < Q.j ? c + q : Q.j - 1) * Q.R + i];
 #pragma unroll
-            for (uint32_t q = 0; q < 4; q++) keep = keep && m[q] != xv;
+            for (uint32_t q = 0; q < 8; q++) keep = keep && m[q] != xv;
         }
         const uint32_t be = (keep && Q.ne > 1) ? loc[Q.locbase + (uint64_t)(2 * Q.ne + 1) * Q.R + i] : Q.e0;
         for (uint32_t e2 = 0; keep && e2 < Q.ne; e2++) {
@@ -399,29 +475,33 @@ __global__ __launch_bounds__(WT) void k_wlink(const WQ *qs, const uint32_t *rowq
             if (pos < Q.S) {  // always, when the survivor ranges are consistent
                 const uint32_t st0 = (one && staged) ? s_st[lr] : loc[Q.locbase + (uint64_t)(2 * Q.ne) * Q.R + i];
                 const uint32_t x = ci_all[st0 + (uint32_t)(p - Fr)];
-                // the row's values are loaded four at a time (independent
-                // loads), not one dependent round trip per column
+                // the row's values are loaded eight at a time, every load
+                // issued before any is used (clamped columns: valid
+                // addresses), not one dependent round trip per column
                 if (!Q.final_level) {
-                    for (uint32_t c = 0; c < Q.j; c += 4) {
-                        uint32_t m[4];
+                    for (uint32_t c = 0; c < Q.j; c += 8) {
+                        uint32_t m[8];
 #pragma unroll
-                        for (uint32_t k4 = 0; k4 < 4; k4++) m[k4] = c + k4 < Q.j ? Q.M[(uint64_t)(c + k4) * Q.R + i] : 0u;
+                        for (uint32_t k4 = 0; k4 < 8; k4++)
+                            m[k4] = Q.M[(uint64_t)(c + k4 < Q.j ? c + k4 : Q.j - 1) * Q.R + i];
 #pragma unroll
-                        for (uint32_t k4 = 0; k4 < 4; k4++)
+                        for (uint32_t k4 = 0; k4 < 8; k4++)
                             if (c + k4 < Q.j) Q.Mn[(uint64_t)(c + k4) * Q.S + pos] = m[k4];
                     }
                     Q.Mn[(uint64_t)Q.j * Q.S + pos] = x;
                 } else {
                     uint64_t f = 14695981039346656037ull;
-                    for (uint32_t u0 = 0; u0 < Q.k; u0 += 4) {
-                        uint32_t val[4];
+                    for (uint32_t u0 = 0; u0 < Q.k; u0 += 8) {
+                        uint32_t val[8];
 #pragma unroll
-                        for (uint32_t k4 = 0; k4 < 4; k4++) {
-                            const uint32_t c = u0 + k4 < Q.k ? Q.qcol[u0 + k4] : Q.j;
-                            val[k4] = c < Q.j ? Q.M[(uint64_t)c * Q.R + i] : x;
+                        for (uint32_t k4 = 0; k4 < 8; k4++) {
+                            const uint32_t qc = Q.qcol[u0 + k4 < GSI_MAX_K ? u0 + k4 : GSI_MAX_K - 1];
+                            const uint32_t c = u0 + k4 < Q.k ? qc : Q.j;
+                            const uint32_t mv = Q.M[(uint64_t)(c < Q.j ? c : 0u) * Q.R + i];
+                            val[k4] = c < Q.j ? mv : x;
                         }
 #pragma unroll
-                        for (uint32_t k4 = 0; k4 < 4; k4++) {
+                        for (uint32_t k4 = 0; k4 < 8; k4++) {
                             const uint32_t u = u0 + k4;
                             if (u >= Q.k) break;
                             if (stage) s_rows[local * Q.k + u] = val[k4];

@@ -543,9 +543,10 @@ def test_single_pass_last_level_and_list_filter(ctx, seed):
         want = og.match(q, threads=4, max_count=3_000_000)
         if want.status != 0:
             continue
-        ref = dg.query(q, flags=base | gsi.GSI_NO_SINGLE_PASS | gsi.GSI_NO_LIST_FILTER)
+        ref = dg.query(q, flags=base | gsi.GSI_NO_LIST_FILTER)
         rows = ref.rows()
-        for f in (base, base | gsi.GSI_NO_SINGLE_PASS, base | gsi.GSI_NO_LIST_FILTER, 0):
+        for f in (base, base | gsi.GSI_SINGLE_PASS, base | gsi.GSI_SINGLE_PASS | gsi.GSI_NO_LIST_FILTER, 0,
+                  gsi.GSI_SINGLE_PASS):
             res = dg.query(q, flags=f)
             assert (res.count, res.digest) == (want.count, want.digest)
             if f & gsi.GSI_NO_FUSED:
@@ -571,8 +572,8 @@ def test_one_pass_levels_on_a_clique(ctx):
     want = oracle.match(g, q, threads=4)
     assert want.count == math.perm(20, 5)
     dg = ctx.load(g)
-    ref = dg.query(q, flags=gsi.GSI_NO_FUSED | gsi.GSI_NO_SINGLE_PASS | gsi.GSI_NO_LIST_FILTER)
-    r = dg.query(q, flags=gsi.GSI_NO_FUSED)
+    ref = dg.query(q, flags=gsi.GSI_NO_FUSED | gsi.GSI_NO_LIST_FILTER)
+    r = dg.query(q, flags=gsi.GSI_NO_FUSED | gsi.GSI_SINGLE_PASS)
     st = r.stats()
     assert st["filtered_levels"] == 0b11100
     # every vertex is a candidate here, so the filtered lists are whole

@@ -670,7 +670,7 @@ def single_query_section(name, args, arena, steps, warmup, keep_tensors=False):
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     # D2H-inclusive latency: the same queries with the rows copied to host
-    lat_d2h, _ = step(dg, rows_to_host=True)
+    lat_d2h, _ = step(dg, rows_to_host=True) if not args.no_d2h_pass else ([float("nan")] * len(qs), None)
     dg.free()
     ctx.close()
 
@@ -725,6 +725,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-ablations", action="store_true", help="skip the ablation runs")
+    ap.add_argument("--no-d2h-pass", action="store_true",
+                    help="skip the pass that copies every result's rows to host memory (D2H-inclusive latency)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device copy of this size (a reference kernel for HBM counters)")
     args = ap.parse_args()

@@ -287,6 +287,9 @@ std::vector<WideQuery> admit_round(gsi_graph *g, const std::vector<const HostQue
                         ne++;
                     }
             hp->lv_ne[j] = ne;
+            hp->lv_mmask[j] = 0;
+            for (uint32_t c = 0; c < j; c++)
+                if (q.multi || q.vl[pl.order[c]] == q.vl[pl.order[j]]) hp->lv_mmask[j] |= 1u << c;
             ei += ne;
         }
         FusedQuery f;

@@ -32,6 +32,8 @@ struct FPlan {
     uint32_t lv_ne[GSI_MAX_K];    // level j: linking edges
     uint32_t lv_e0[GSI_MAX_K];    // level j: first edge (index within the level)
     uint32_t lv_first[GSI_MAX_K]; // level j: first entry in edges[]
+    uint32_t lv_mmask[GSI_MAX_K]; // level j: columns of m_i whose query vertex
+                                  // has u's label (all on multi-labelled graphs)
     const uint64_t *Cu[GSI_MAX_K];
     FEdge edges[1];               // all levels' edges follow
 };

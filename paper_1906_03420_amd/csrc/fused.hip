@@ -285,13 +285,23 @@ __device__ __forceinline__ void fused_query(const FPlan *plan, uint32_t j0, cons
                 }
             }
             if (!plan->homo) {
-                for (uint32_t c = 0; c < j; c += 4) {
+                // x not among the row's values in the columns that can hold
+                // it (those of u's label), four columns at a time; past the
+                // last one the last is read again
+                uint32_t mm = plan->lv_mmask[j];
+                const uint32_t last = mm ? 31u - (uint32_t)__builtin_clz(mm) : 0u;
+                while (mm) {
+                    uint32_t cq[4];
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; q++) {
+                        cq[q] = mm ? (uint32_t)__builtin_ctz(mm) : last;
+                        mm &= mm - 1;
+                    }
                     uint32_t mv[FU][4];
 #pragma unroll
                     for (uint32_t r = 0; r < FU; r++)
 #pragma unroll
-                        for (uint32_t q = 0; q < 4; q++)
-                            mv[r][q] = M[(uint64_t)(c + q < j ? c + q : j - 1) * ld + ir[r]];
+                        for (uint32_t q = 0; q < 4; q++) mv[r][q] = M[(uint64_t)cq[q] * ld + ir[r]];
 #pragma unroll
                     for (uint32_t r = 0; r < FU; r++)
 #pragma unroll

@@ -56,12 +56,21 @@ struct LevelArgs {
     uint64_t gba;
     uint64_t *bitmap;
     uint32_t *tile_cnt;
+    // survivor records (when set, instead of the bitmap): the q-th kept slot
+    // of tile t, in slot order, has its element at rec_x[t * TS + q] and its
+    // row, less the tile's first row, at rec_r[t * TS + q]
+    uint32_t *rec_x, *rec_r;
     const uint64_t *tile_off;
     uint32_t *Mn;
     uint64_t S;
     uint32_t *out;
     uint64_t *dig_part;  // per tile (sum, xor) of the tuple hashes (last level)
     uint32_t qcol[GSI_MAX_K];  // query vertex -> column (last level)
+    // the columns of m_i that can hold a candidate x: those whose query
+    // vertex has u's label (a single-label graph's C(u) holds only vertices
+    // with u's label); every column on a multi-labelled graph
+    uint32_t nmc;
+    uint8_t mcol[GSI_MAX_K];
     uint32_t final_level, count_only;
 };
 
@@ -89,25 +98,6 @@ __device__ __forceinline__ uint64_t row_of(const uint64_t *F, uint64_t lo, uint6
     return lo;
 }
 
-// x among the j values of row i (m_i).  The values are loaded eight at a
-// time, every load issued before the compares: a column past j re-reads
-// column j - 1 (a valid address) instead of branching around the load,
-// which would make each load wait for the one before it.
-__device__ __forceinline__ bool in_row(const LevelArgs &a, uint64_t i, uint32_t x) {
-    bool hit = false;
-    for (uint32_t c = 0; c < a.j; c += 8) {
-        uint32_t m[8];
-#pragma unroll
-        for (uint32_t t = 0; t < 8; t++) {
-            const uint32_t cc = c + t < a.j ? c + t : a.j - 1;
-            m[t] = a.M[(uint64_t)cc * a.ldm + i];
-        }
-#pragma unroll
-        for (uint32_t t = 0; t < 8; t++) hit |= m[t] == x;
-    }
-    return hit;
-}
-
 // The costly tests of U candidates at once: keep[u] (on entry: whether
 // candidate u is live) becomes x[u] not in m_i of row i[u] and x[u] in
 // every other linking list of that row.  Every step issues the loads of
@@ -117,12 +107,16 @@ __device__ __forceinline__ bool in_row(const LevelArgs &a, uint64_t i, uint32_t 
 template <uint32_t U>
 __device__ __forceinline__ void keep_many(const LevelArgs &a, const uint32_t *x, const uint64_t *i, bool *keep) {
     if (!a.homo) {
-        for (uint32_t c = 0; c < a.j; c += 8) {
-            uint32_t m[U][8];
+        // x not among the row's values in the columns that can hold it (a
+        // past-the-end slot re-reads the last such column)
+        for (uint32_t c = 0; c < a.nmc; c += 8) {
+            uint32_t col[8], m[U][8];
+#pragma unroll
+            for (uint32_t t = 0; t < 8; t++) col[t] = a.mcol[c + t < a.nmc ? c + t : a.nmc - 1];
 #pragma unroll
             for (uint32_t u = 0; u < U; u++)
 #pragma unroll
-                for (uint32_t t = 0; t < 8; t++) m[u][t] = a.M[(uint64_t)(c + t < a.j ? c + t : a.j - 1) * a.ldm + i[u]];
+                for (uint32_t t = 0; t < 8; t++) m[u][t] = a.M[(uint64_t)col[t] * a.ldm + i[u]];
 #pragma unroll
             for (uint32_t u = 0; u < U; u++)
 #pragma unroll
@@ -154,7 +148,9 @@ __device__ __forceinline__ void keep_many(const LevelArgs &a, const uint32_t *x,
 }
 
 // Copies the j values of row i to column-major dst (column c at
-// dst[c * stride + pos]), loads issued eight at a time as in in_row.
+// dst[c * stride + pos]), loads issued eight at a time, a column past j
+// re-reading column j - 1 (a valid address) instead of branching around
+// the load, which would make each load wait for the one before it.
 __device__ __forceinline__ void copy_row(const LevelArgs &a, uint64_t i, uint32_t *dst, uint64_t stride,
                                          uint64_t pos) {
     for (uint32_t c = 0; c < a.j; c += 8) {

@@ -654,18 +654,30 @@ void tile_rows(gsi_ctx *c, const uint64_t *F, uint64_t R, uint64_t ntiles, uint6
 // becomes [rank(s), rank(s+len)) of the compacted array).  Each row then
 // scans its list's members of C(u) only; the survivors, and their order,
 // are unchanged.
+// Each thread takes FN_TILES elements (one per 256-element tile of its
+// workgroup) and issues their loads, then their C(u) word loads, together.
+constexpr uint32_t FN_TILES = 4;
+
 __global__ __launch_bounds__(QT) void k_fn_bits(const uint32_t *ci, uint64_t n, const uint64_t *Cu, uint64_t *bits,
                                                uint32_t *wcnt) {
-    const uint64_t p = (uint64_t)blockIdx.x * QT + threadIdx.x;
-    bool keep = false;
-    if (p < n) {
-        const uint32_t x = ci[p];
-        keep = (Cu[x >> 6] >> (x & 63)) & 1ull;
+    uint32_t x[FN_TILES];
+    uint64_t cw[FN_TILES];
+#pragma unroll
+    for (uint32_t r = 0; r < FN_TILES; r++) {
+        const uint64_t p = ((uint64_t)blockIdx.x * FN_TILES + r) * QT + threadIdx.x;
+        x[r] = ci[p < n ? p : n - 1];
     }
-    const uint64_t m = __ballot(keep);
-    if (lane_id() == 0 && p < n) {
-        bits[p >> 6] = m;
-        wcnt[p >> 6] = (uint32_t)__popcll(m);
+#pragma unroll
+    for (uint32_t r = 0; r < FN_TILES; r++) cw[r] = Cu[x[r] >> 6];
+#pragma unroll
+    for (uint32_t r = 0; r < FN_TILES; r++) {
+        const uint64_t p = ((uint64_t)blockIdx.x * FN_TILES + r) * QT + threadIdx.x;
+        const bool keep = p < n && ((cw[r] >> (x[r] & 63)) & 1ull);
+        const uint64_t m = __ballot(keep);
+        if (lane_id() == 0 && p < n) {
+            bits[p >> 6] = m;
+            wcnt[p >> 6] = (uint32_t)__popcll(m);
+        }
     }
 }
 
@@ -711,6 +723,9 @@ constexpr double FN_FACTOR = 2.0;
 constexpr uint64_t WIDE_TILE_SLOTS = 1ull << 22;  // |GBA| from which SPT = 4
 // candidates a join thread tests at once (keep_many)
 constexpr uint32_t JU = 4;
+// rows of the last level are staged in LDS and written out as one
+// contiguous block per round (coalesced stores) when k is at most this
+constexpr uint32_t LINK_STAGE_K = 16;
 
 // The rows r_lo..r_hi a tile touches.  When they are at most the tile's slot
 // count they are staged in LDS; tiles spanning more rows (long runs of rows
@@ -894,6 +909,36 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
             if (kp[u]) atomicOr(&s_keep[sl[u] >> 6], 1ull << (sl[u] & 63));
     }
     __syncthreads();
+    if (a.rec_x) {
+        // the tile's survivors as records in slot order (element, row from
+        // r_lo), so that the link reads them instead of searching rows and
+        // re-gathering elements
+        __shared__ uint32_t s_pre[TS / 64 + 1];
+        if (threadIdx.x < 64) {
+            const uint32_t c = threadIdx.x < TS / 64 ? (uint32_t)__popcll(s_keep[threadIdx.x]) : 0u;
+            const uint32_t inc = wave_inclusive_sum(c);
+            if (threadIdx.x < TS / 64) s_pre[threadIdx.x] = inc - c;
+            if (threadIdx.x == 63) {
+                s_pre[TS / 64] = inc;
+                a.tile_cnt[blockIdx.x] = inc;
+            }
+        }
+        __syncthreads();
+        // every kept slot was a candidate: its element and row are in the
+        // compacted lists (read from LDS, not held in registers across the
+        // tests); its record goes to its rank among the tile's kept slots
+        const uint64_t rb = (uint64_t)blockIdx.x * TS;
+        for (uint32_t e = threadIdx.x; e < n; e += QT) {
+            const uint32_t sl = s_slot[e];
+            const uint64_t word = s_keep[sl >> 6];
+            if ((word >> (sl & 63)) & 1ull) {
+                const uint32_t q = s_pre[sl >> 6] + (uint32_t)__popcll(word & ((1ull << (sl & 63)) - 1));
+                a.rec_x[rb + q] = s_x[e];
+                a.rec_r[rb + q] = s_ri[e];
+            }
+        }
+        return;
+    }
     // the tile's keep bits (one word per 64 slots) and their count
     if (threadIdx.x < 64) {
         const uint64_t word = threadIdx.x < TS / 64 ? s_keep[threadIdx.x] : 0ull;
@@ -903,9 +948,100 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
     }
 }
 
-// rows of the last level are staged in LDS and written out as one
-// contiguous block per round (coalesced stores) when k is at most this
-constexpr uint32_t LINK_STAGE_K = 16;
+// The link over survivor records (k_join wrote each tile's kept slots in
+// slot order as (element, row) records): survivor q of tile t is row
+// tile_off[t] + q of M', extended from row tile_row[t] + rec_r of M by
+// rec_x.  No row search and no second gather of the element.
+template <uint32_t SPT>
+__global__ __launch_bounds__(QT) void k_link_rec(LevelArgs a) {
+    constexpr uint32_t TS = SPT * QT;
+    __shared__ uint64_t s_d[2][QT / 64];
+    __shared__ uint32_t s_rows[QT * LINK_STAGE_K];
+    __shared__ uint32_t s_qc[GSI_MAX_K];  // query vertex -> column (last level)
+    const uint64_t tile = blockIdx.x;
+    const uint64_t tbase = a.tile_off[tile];
+    const uint32_t n = (uint32_t)(a.tile_off[tile + 1] - tbase);
+    if (n == 0) {  // uniform
+        if (a.final_level && threadIdx.x == 0) {
+            a.dig_part[2 * tile] = 0;
+            a.dig_part[2 * tile + 1] = 0;
+        }
+        return;
+    }
+    if (threadIdx.x < GSI_MAX_K) s_qc[threadIdx.x] = a.qcol[threadIdx.x];
+    __syncthreads();
+    const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+    const uint64_t r_lo = a.tile_row[tile];
+    const uint64_t rb = tile * TS;
+    const bool stage = a.final_level && !a.count_only && a.k <= LINK_STAGE_K;
+    uint64_t hs = 0, hx = 0;
+    for (uint32_t q0 = 0; q0 < n; q0 += QT) {
+        const uint32_t q = q0 + threadIdx.x;
+        const uint64_t pos = tbase + q;
+        const bool mine = q < n && pos < a.S;
+        const uint32_t qq = mine ? q : 0u;  // a past-the-end thread reads record 0
+        const uint32_t x = a.rec_x[rb + qq];
+        const uint64_t i = r_lo + a.rec_r[rb + qq];
+        if (!a.final_level) {
+            if (mine) {
+                copy_row(a, i, a.Mn, a.S, pos);
+                a.Mn[(uint64_t)a.j * a.S + pos] = x;
+            }
+        } else if (mine) {
+            uint64_t f = 14695981039346656037ull;
+            for (uint32_t u0 = 0; u0 < a.k; u0 += 8) {
+                uint32_t val[8];
+#pragma unroll
+                for (uint32_t k4 = 0; k4 < 8; k4++) {
+                    const uint32_t c = u0 + k4 < a.k ? s_qc[u0 + k4] : a.j;
+                    const uint32_t mv = a.M[(uint64_t)(c < a.j ? c : 0u) * a.ldm + i];
+                    val[k4] = c < a.j ? mv : x;
+                }
+#pragma unroll
+                for (uint32_t k4 = 0; k4 < 8; k4++) {
+                    const uint32_t u = u0 + k4;
+                    if (u >= a.k) break;
+                    if (stage) s_rows[threadIdx.x * a.k + u] = val[k4];
+                    else if (!a.count_only) a.out[pos * a.k + u] = val[k4];
+                    f = fnv_word(f, val[k4]);
+                }
+            }
+            const uint64_t h = mix64(f);
+            hs += h;
+            hx ^= h;
+        }
+        if (stage) {
+            // the round's rows are one contiguous block of the output
+            __syncthreads();
+            const uint64_t first = tbase + q0;
+            uint64_t end = tbase + (q0 + QT < n ? q0 + QT : n);
+            if (end > a.S) end = a.S;
+            const uint32_t nw = first < end ? (uint32_t)(end - first) * a.k : 0u;
+            uint32_t *dst = a.out + first * a.k;
+            for (uint32_t t = threadIdx.x; t < nw; t += QT) dst[t] = s_rows[t];
+            __syncthreads();
+        }
+    }
+    if (a.final_level) {
+        const uint64_t sum = wave_sum(hs), xr = wave_xor(hx);
+        if (lane == 0) {
+            s_d[0][w] = sum;
+            s_d[1][w] = xr;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t ts = 0, tx = 0;
+#pragma unroll
+            for (int q = 0; q < QT / 64; q++) {
+                ts += s_d[0][q];
+                tx ^= s_d[1][q];
+            }
+            a.dig_part[2 * tile] = ts;
+            a.dig_part[2 * tile + 1] = tx;
+        }
+    }
+}
+
 
 template <uint32_t SPT>
 __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
@@ -1675,6 +1811,9 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
                         ne++;
                     }
             hp->lv_ne[j] = ne;
+            hp->lv_mmask[j] = 0;
+            for (uint32_t c = 0; c < j; c++)
+                if (q.multi || q.vl[order[c]] == q.vl[order[j]]) hp->lv_mmask[j] |= 1u << c;
             st.n_link[j] = ne;
             ei += ne;
         }
@@ -1952,6 +2091,9 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         a.ne = ne;
         st.n_link[j] = ne;
         for (uint32_t v = 0; v < k; v++) a.qcol[v] = col[v];
+        // columns of m_i the subtraction has to look at
+        for (uint32_t c = 0; c < j; c++)
+            if (q.multi || q.vl[order[c]] == q.vl[u]) a.mcol[a.nmc++] = (uint8_t)c;
         a.final_level = final_level ? 1u : 0u;
         a.count_only = count_only ? 1u : 0u;
 
@@ -1994,7 +2136,8 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
                 uint32_t *wcnt = ls.get<uint32_t>(nw, "filtered-list word counts");
                 uint64_t *wpre = ls.get<uint64_t>(nw + 1, "filtered-list word offsets");
                 const uint32_t *ci_l0 = a.e[a.e0].ci;
-                launch(c, "k_fn_bits", 4.0 * El + El / 8.0 + 4.0 * nw, k_fn_bits, nblocks(El), QT, ci_l0, El, a.Cu,
+                launch(c, "k_fn_bits", 4.0 * El + El / 8.0 + 4.0 * nw, k_fn_bits, nblocks(El, QT * FN_TILES), QT,
+                       ci_l0, El, a.Cu,
                        fbits, wcnt);
                 exclusive_scan(c, wcnt, nw, wpre, ls, dscal + 3);
                 uint64_t kept;
@@ -2116,7 +2259,18 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
             R = S;
             continue;  // the fused workgroup is not taken back after a one-pass level
         }
-        a.bitmap = ls.get<uint64_t>(ntiles * (ts / 64), "GBA bitmap");
+        // survivors as (element, row) records when they fit comfortably
+        // (8 bytes per |GBA| slot), else as a keep bitmap (and always for the
+        // join ablations, which write the bitmap)
+        const bool recs = !(flags & ABL) && 8.0 * (double)(ntiles * ts) <= (double)c->arena.largest_free() / 4;
+        a.rec_x = a.rec_r = nullptr;
+        a.bitmap = nullptr;
+        if (recs) {
+            a.rec_x = ls.get<uint32_t>(ntiles * ts, "survivor elements");
+            a.rec_r = ls.get<uint32_t>(ntiles * ts, "survivor rows");
+        } else {
+            a.bitmap = ls.get<uint64_t>(ntiles * (ts / 64), "GBA bitmap");
+        }
         a.tile_cnt = ls.get<uint32_t>(ntiles, "tile counts");
         uint64_t *toff = ls.get<uint64_t>(ntiles + 1, "tile offsets");
         a.tile_off = toff;
@@ -2128,15 +2282,22 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         if (flags & JOIN_ABL) run_join_ablation(c, a, flags, ntiles, ts, jb, ls);
         else if (spt == 4) launch(c, "k_join", jb, k_join<4>, (uint32_t)ntiles, QT, a);
         else launch(c, "k_join", jb, k_join<1>, (uint32_t)ntiles, QT, a);
+        const size_t join_rec = c->recs.size();
         exclusive_scan(c, a.tile_cnt, ntiles, toff, ls, dscal + 1);
         uint64_t S;
         read_scalars(c, dscal + 1, &S, 1);
         st.survivors[j] = S;
+        // the join wrote 8 bytes per survivor, not the keep bitmap
+        if (recs && (c->flags & GSI_CTX_PROFILE) && join_rec > 0 && join_rec <= c->recs.size())
+            c->recs[join_rec - 1].bytes += 8.0 * S - gba / 8.0;
         if (S == 0) return done();
         if (max_rows && S > max_rows) fail(GSI_E_CAPACITY, "rows exceed max_rows at level %u", j);
         a.S = S;
         Block Mn(c);
-        double lb = (double)S * (4.0 + 4.0 * j) + gba / 8.0 + 8.0 * ntiles;
+        // the link reads each survivor's record (or re-reads its element and
+        // the keep bitmap) and its parent row's j values
+        double lb = recs ? (double)S * (8.0 + 4.0 * j) + 8.0 * ntiles
+                         : (double)S * (4.0 + 4.0 * j) + gba / 8.0 + 8.0 * ntiles;
         uint32_t *front = nullptr;  // room for the chunk part's rows
         if (final_level) {
             if (!count_only) {
@@ -2151,8 +2312,14 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
             a.Mn = Mn.get<uint32_t>((uint64_t)(j + 1) * S, "next table");
             lb += 4.0 * (j + 1) * S;
         }
-        if (spt == 4) launch(c, "k_link", lb, k_link<4>, (uint32_t)ntiles, QT, a);
-        else launch(c, "k_link", lb, k_link<1>, (uint32_t)ntiles, QT, a);
+        if (recs) {
+            if (spt == 4) launch(c, "k_link", lb, k_link_rec<4>, (uint32_t)ntiles, QT, a);
+            else launch(c, "k_link", lb, k_link_rec<1>, (uint32_t)ntiles, QT, a);
+        } else if (spt == 4) {
+            launch(c, "k_link", lb, k_link<4>, (uint32_t)ntiles, QT, a);
+        } else {
+            launch(c, "k_link", lb, k_link<1>, (uint32_t)ntiles, QT, a);
+        }
         if (final_level) {
             reduce_pairs(c, a.dig_part, ntiles, dscal);
             uint64_t dg[2];

@@ -48,6 +48,7 @@ struct WQ {
     uint32_t *out;  // result rows (last level)
     uint64_t S, sbase;
     uint32_t qcol[GSI_MAX_K];
+    uint32_t mmask;  // columns of m_i whose query vertex has u's label
 };
 
 // candidates a join thread tests at once (wkeep_many)
@@ -60,16 +61,25 @@ constexpr uint32_t WU = 4;
 template <uint32_t U>
 __device__ __forceinline__ void wkeep_many(const WQ &Q, const uint32_t *loc, const WEdge *edges, const uint32_t *x,
                                            const uint64_t *i, bool *keep) {
-    for (uint32_t c = 0; c < Q.j; c += 8) {
-        uint32_t m[U][8];
+    // only the columns of u's label can hold x; four at a time, the last
+    // one read again past the end
+    uint32_t mm = Q.mmask;
+    const uint32_t last = mm ? 31u - (uint32_t)__builtin_clz(mm) : 0u;
+    while (mm) {
+        uint32_t cq[4], m[U][4];
+#pragma unroll
+        for (uint32_t t = 0; t < 4; t++) {
+            cq[t] = mm ? (uint32_t)__builtin_ctz(mm) : last;
+            mm &= mm - 1;
+        }
 #pragma unroll
         for (uint32_t u = 0; u < U; u++)
 #pragma unroll
-            for (uint32_t t = 0; t < 8; t++) m[u][t] = Q.M[(uint64_t)(c + t < Q.j ? c + t : Q.j - 1) * Q.R + i[u]];
+            for (uint32_t t = 0; t < 4; t++) m[u][t] = Q.M[(uint64_t)cq[t] * Q.R + i[u]];
 #pragma unroll
         for (uint32_t u = 0; u < U; u++)
 #pragma unroll
-            for (uint32_t t = 0; t < 8; t++) keep[u] = keep[u] && m[u][t] != x[u];
+            for (uint32_t t = 0; t < 4; t++) keep[u] = keep[u] && m[u][t] != x[u];
     }
     if (Q.ne < 2) return;
     uint32_t be[U];
@@ -619,6 +629,8 @@ static void wide_step(gsi_graph *g, const std::vector<WideQuery *> &act, bool co
                     }
             Q.locbase = loctot;
             for (uint32_t v = 0; v < q.k; v++) Q.qcol[v] = x.col[v];
+            for (uint32_t c = 0; c < j; c++)
+                if (q.multi || q.vl[x.order[c]] == q.vl[u]) Q.mmask |= 1u << c;
             x.stats_rows[j] = x.R;
             Rtot += x.R;
             loctot += (2ull * Q.ne + 2) * x.R;

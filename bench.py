@@ -297,6 +297,8 @@ def batched_section(args, vl_t, s_t, d_t, l_t, g, arena):
                 speedup=t_seq / t_bat, schedule=info["schedule"], autotune=tune,
                 default_schedule=dict(default, ms_per_pass=t_def * 1e3, tuned_vs_default=t_def / t_bat),
                 tiers=dict(empty=info["empty"], tier1=info["tier1"], tier2=info["tier2"], per_level=info["per_level"]),
+                phases_ms={p: round(info[p], 3) for p in ("filter_ms", "tier1_ms", "tier2_ms", "per_level_ms",
+                                                          "total_ms")},
                 roofline=engine_roofline(ks, 1, prof_ms),
                 parity="bit-exact counts+digests vs oracle, both paths, %d/%d" % (len(qs), len(qs)) if parity
                 else "MISMATCH")

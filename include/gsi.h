@@ -354,8 +354,8 @@ gsi_status gsi_result_rows(const gsi_result *r, uint32_t *host_dst, uint64_t cap
 /* Borrowed device pointer to the same rows; valid until gsi_result_free. */
 gsi_status gsi_result_device_rows(const gsi_result *r, const uint32_t **dev_rows);
 /* Order-independent digest: for each row t, h(t) = SplitMix64 finalizer of
- * FNV-1a-64 over the 4k little-endian bytes of t; out = {sum of h mod 2^64,
- * xor of h}. */
+ * FNV-1a-64 over t's k values taken as 32-bit symbols (h ^= t[j], h *= prime,
+ * j = 0..k-1); out = {sum of h mod 2^64, xor of h}. */
 gsi_status gsi_result_digest(const gsi_result *r, uint64_t out_sum_xor[2]);
 
 typedef struct {

@@ -60,6 +60,8 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         lib.oracle_fnv1a64.argtypes = [ctypes.c_char_p, ctypes.c_uint64]
         lib.oracle_fnv1a64.restype = ctypes.c_uint64
+        lib.oracle_fnv1a64_words.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+        lib.oracle_fnv1a64_words.restype = ctypes.c_uint64
         lib.oracle_sm64_finalize.argtypes = [ctypes.c_uint64]
         lib.oracle_sm64_finalize.restype = ctypes.c_uint64
         lib.oracle_tuple_hash.argtypes = [U32P, ctypes.c_uint32]
@@ -97,6 +99,12 @@ def _p(a):
 
 def fnv1a64(data: bytes) -> int:
     return int(_load().oracle_fnv1a64(data, len(data)))
+
+
+def fnv1a64_words(words) -> int:
+    """FNV-1a-64 with each 32-bit value as one symbol."""
+    a = np.ascontiguousarray(words, dtype=np.uint32)
+    return int(_load().oracle_fnv1a64_words(a.ctypes.data, a.shape[0]))
 
 
 def splitmix64_finalize(z: int) -> int:

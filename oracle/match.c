@@ -28,11 +28,13 @@
  * never the set of maps found.  Nothing here shares code with the GPU library.
  *
  * Order-independent digest of a result set: for each tuple t (query-vertex
- * order, 4k little-endian bytes) h(t) = SplitMix64-finalizer(FNV-1a-64(t));
- * the digest is (sum of h mod 2^64, xor of h).  FNV-1a is Fowler/Noll/Vo's
- * published hash (offset basis 14695981039346656037, prime 1099511628211);
- * the finalizer is the output mixing function of SplitMix64 (Steele et al.,
- * OOPSLA 2014).
+ * order) h(t) = SplitMix64-finalizer(FNV-1a-64 of t with its k 32-bit values
+ * as the symbols); the digest is (sum of h mod 2^64, xor of h).  FNV-1a is
+ * Fowler/Noll/Vo's published hash (offset basis 14695981039346656037, prime
+ * 1099511628211: h ^= symbol, h *= prime, for each symbol); taken over 32-bit
+ * symbols instead of octets it needs k steps per tuple instead of 4k, and
+ * with symbols below 256 it is the octet form.  The finalizer is the output
+ * mixing function of SplitMix64 (Steele et al., OOPSLA 2014).
  *
  * Only tests/, the smoke check and the benchmark's CPU-baseline leg may load
  * this file.
@@ -53,20 +55,18 @@ uint64_t oracle_fnv1a64(const uint8_t *p, uint64_t n) {
     for (uint64_t i = 0; i < n; i++) { h ^= p[i]; h *= 1099511628211ULL; }
     return h;
 }
+uint64_t oracle_fnv1a64_words(const uint32_t *w, uint64_t n) {
+    uint64_t h = 14695981039346656037ULL;
+    for (uint64_t i = 0; i < n; i++) { h ^= w[i]; h *= 1099511628211ULL; }
+    return h;
+}
 uint64_t oracle_sm64_finalize(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
     return z ^ (z >> 31);
 }
 uint64_t oracle_tuple_hash(const uint32_t *t, uint32_t k) {
-    uint8_t buf[4 * 64];
-    for (uint32_t i = 0; i < k; i++) {
-        buf[4 * i + 0] = (uint8_t)(t[i]);
-        buf[4 * i + 1] = (uint8_t)(t[i] >> 8);
-        buf[4 * i + 2] = (uint8_t)(t[i] >> 16);
-        buf[4 * i + 3] = (uint8_t)(t[i] >> 24);
-    }
-    return oracle_sm64_finalize(oracle_fnv1a64(buf, 4ULL * k));
+    return oracle_sm64_finalize(oracle_fnv1a64_words(t, k));
 }
 /* digest of `rows` tuples laid out row-major (rows x k) */
 void oracle_digest_rows(const uint32_t *rows, uint64_t nrows, uint32_t k, uint64_t out[2]) {

@@ -111,13 +111,11 @@ __device__ __forceinline__ void in_sorted_many(const uint32_t *base, const uint3
     }
 }
 
-// FNV-1a-64 over the four little-endian bytes of one 32-bit word
+// One FNV-1a-64 step with a 32-bit value as the symbol (the tuple hash takes
+// a row's k values as k symbols)
 __device__ __forceinline__ uint64_t fnv_word(uint64_t h, uint32_t v) {
-#pragma unroll
-    for (int b = 0; b < 4; b++) {
-        h ^= (v >> (8 * b)) & 0xFFu;
-        h *= 1099511628211ull;
-    }
+    h ^= v;
+    h *= 1099511628211ull;
     return h;
 }
 // SplitMix64 output mixing (Steele, Lea, Flood 2014)

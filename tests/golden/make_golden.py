@@ -2,6 +2,7 @@
 
 Calls only the CPU oracle and the seeded input generators.  Usage:
     python tests/golden/make_golden.py er1k ba1m
+    python tests/golden/make_golden.py --redigest er1k ba1m   (digests only)
 The file is rewritten after every query and a rerun resumes after the last
 query present, so a long workload can be written in several sittings; tests
 check the queries the file holds.
@@ -91,6 +92,36 @@ def make(name: str, threads: int):
     print("wrote", path)
 
 
+def redigest(name: str, threads: int):
+    """Recomputes the digest of every stored query (same index and accepted
+    attempt, same limits) after a change of the digest's definition; the
+    counts must not change."""
+    path = os.path.join(HERE, "%s.json" % name)
+    with open(path) as f:
+        out = json.load(f)
+    lim = out["limits"]
+    g = w.config_graph(name)
+    og = oracle.OracleGraph(g)
+    mk = w.QueryMaker(g)
+    for x in out["queries"]:
+        q = w.config_query(g, name, x["index"], attempt=x["attempt"], maker=mk)
+        r = og.match(q, threads=threads, tuples=False, max_count=lim["max_count"], max_nodes=lim["max_nodes"])
+        if r.status != oracle.OR_OK or r.count != x["count"]:
+            raise SystemExit("%s query %d: status %d count %d, stored %d" % (name, x["index"], r.status, r.count,
+                                                                            x["count"]))
+        x["digest"] = [str(r.digest[0]), str(r.digest[1])]
+        print(name, x["index"], r.count, flush=True)
+    with open(path + ".tmp", "w") as f:
+        json.dump(out, f, indent=1)
+    os.replace(path + ".tmp", path)
+    print("rewrote digests of", path)
+
+
 if __name__ == "__main__":
-    for nm in sys.argv[1:] or ["er1k", "ba1m"]:
-        make(nm, threads=8)
+    args = sys.argv[1:]
+    if args and args[0] == "--redigest":
+        for nm in args[1:]:
+            redigest(nm, threads=8)
+    else:
+        for nm in args or ["er1k", "ba1m"]:
+            make(nm, threads=8)

@@ -147,6 +147,11 @@ def test_hash_test_vectors():
     assert oracle.fnv1a64(b"foobar") == 0x85944171F73967E8
     # first SplitMix64 output from state 0 = finalizer(golden gamma)
     assert oracle.splitmix64_finalize(0x9E3779B97F4A7C15) == 0xE220A8397B1DCDAF
+    # FNV-1a over 32-bit symbols is the octet form when every symbol is
+    # below 256: the published vectors again, through the word function
+    assert oracle.fnv1a64_words([]) == 0xCBF29CE484222325
+    assert oracle.fnv1a64_words([ord("a")]) == 0xAF63DC4C8601EC8C
+    assert oracle.fnv1a64_words([ord(c) for c in "foobar"]) == 0x85944171F73967E8
 
 
 def test_digest_is_order_independent_and_sensitive():
@@ -157,9 +162,13 @@ def test_digest_is_order_independent_and_sensitive():
     rows2 = rows.copy()
     rows2[17, 3] ^= 1
     assert oracle.digest_rows(rows2) != d
-    # tuple hash covers the 4k little-endian bytes in query-vertex order
+    # the tuple hash takes the k values as FNV symbols in query-vertex order:
+    # with values below 256, the octet FNV-1a of those values
     t = np.array([1, 2], np.uint32)
-    assert oracle.tuple_hash(t) == oracle.splitmix64_finalize(oracle.fnv1a64(b"\x01\x00\x00\x00\x02\x00\x00\x00"))
+    assert oracle.tuple_hash(t) == oracle.splitmix64_finalize(oracle.fnv1a64(b"\x01\x02"))
+    assert oracle.tuple_hash(np.array([2, 1], np.uint32)) != oracle.tuple_hash(t)
+    # a value's high bits count: 0x100 is not 0x00
+    assert oracle.tuple_hash(np.array([0x100], np.uint32)) != oracle.tuple_hash(np.array([0], np.uint32))
 
 
 def test_invalid_inputs_rejected():

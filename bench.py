@@ -63,11 +63,11 @@ KERNEL_SOURCES = {
     "k_fused_levels": ("fused.hip", "fused.h", "join_device.h", "gsi_internal.h"),
     "k_fused_chunks": ("fused.hip", "fused.h", "join_device.h", "gsi_internal.h"),
     "k_filter": ("query.hip", "gsi_internal.h"),
-    "k_locate": ("query.hip", "join_device.h", "gsi_internal.h"),
-    "k_join": ("query.hip", "join_device.h", "scan_device.h", "gsi_internal.h"),
-    "k_link": ("query.hip", "join_device.h", "gsi_internal.h"),
-    "k_join_pass": ("query.hip", "join_device.h", "scan_device.h", "gsi_internal.h"),
-    "k_join_last": ("query.hip", "join_device.h", "scan_device.h", "gsi_internal.h"),
+    "k_locate": ("query.hip", "level.h", "join_device.h", "gsi_internal.h"),
+    "k_join": ("query.hip", "level.h", "join_device.h", "scan_device.h", "gsi_internal.h"),
+    "k_link": ("query.hip", "level.h", "join_device.h", "gsi_internal.h"),
+    "k_join_pass": ("query.hip", "level.h", "join_device.h", "scan_device.h", "gsi_internal.h"),
+    "k_join_last": ("query.hip", "level.h", "join_device.h", "scan_device.h", "gsi_internal.h"),
 }
 
 
@@ -246,7 +246,8 @@ def batched_section(args, vl_t, s_t, d_t, l_t, g, arena):
 
     def batched(**sched):
         b = dg.batch(qs, **sched)
-        out = [(b.count(i), b.digest(i)) for i in range(len(qs))]
+        counts, digests = b.results()
+        out = [(int(c), (int(d[0]), int(d[1]))) for c, d in zip(counts, digests)]
         info = b.info()
         b.free()
         torch.cuda.synchronize()
@@ -259,24 +260,31 @@ def batched_section(args, vl_t, s_t, d_t, l_t, g, arena):
             tune = dg.tune(qs, sample=256)
         parity &= ok(sequential())
         parity &= ok(batched()[0])
+    # (answers are checked after each timed loop, not inside it)
+    outs = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        parity &= ok(sequential())
+        outs.append(sequential())
     t_seq = (time.perf_counter() - t0) / args.steps
     t0 = time.perf_counter()
     for _ in range(args.steps):
         out, info = batched()
-        parity &= ok(out)
+        outs.append(out)
     t_bat = (time.perf_counter() - t0) / args.steps
+    for out in outs:
+        parity &= ok(out)
     # the untuned default schedule (256-thread first tier, full occupancy,
     # 4 engine tiles per workgroup) over the same passes
     default = dict(threads=256, grid_scale=8, engine_tiles=4)
     batched(**default)
+    outs = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         out, _ = batched(**default)
-        parity &= ok(out)
+        outs.append(out)
     t_def = (time.perf_counter() - t0) / args.steps
+    for out in outs:
+        parity &= ok(out)
     dg.free()
     ctx.close()
     # one batched pass again with HIP events around every launch
@@ -662,15 +670,19 @@ def single_query_section(name, args, arena, steps, warmup, keep_tensors=False):
             parity_ok = matches(out) if parity_ok is None else (parity_ok and matches(out))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lat_steps, emb = [], 0
+    lat_steps, outs = [], []
     for _ in range(steps):
         lat, out = step(dg)
         lat_steps.append(lat)
+        outs.append(out)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    # answers checked after the timed steps
+    emb = 0
+    for out in outs:
         emb += sum(c for c, _ in out)
         if gold:
             parity_ok = matches(out) if parity_ok is None else (parity_ok and matches(out))
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
     # D2H-inclusive latency: the same queries with the rows copied to host
     lat_d2h, _ = step(dg, rows_to_host=True) if not args.no_d2h_pass else ([float("nan")] * len(qs), None)
     dg.free()

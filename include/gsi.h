@@ -432,6 +432,9 @@ gsi_status gsi_batch_run(gsi_graph *g, uint32_t nq, const gsi_query_desc *querie
                          gsi_batch **out);
 gsi_status gsi_batch_count(const gsi_batch *b, uint32_t qi, uint64_t *rows);
 gsi_status gsi_batch_digest(const gsi_batch *b, uint32_t qi, uint64_t out_sum_xor[2]);
+/* Every query's count and digest at once: counts[nq], digests[2 nq] (sum,
+ * xor of query qi at 2 qi, 2 qi + 1), host memory of the batch's nq. */
+gsi_status gsi_batch_results(const gsi_batch *b, uint64_t *counts, uint64_t *digests);
 /* Rows of query qi, row-major in query-vertex order; GSI_E_CAPACITY if
  * capacity_rows is too small, GSI_E_INVALID for a GSI_COUNT_ONLY batch. */
 gsi_status gsi_batch_rows(const gsi_batch *b, uint32_t qi, uint32_t *host_dst, uint64_t capacity_rows);

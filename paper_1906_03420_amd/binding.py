@@ -176,6 +176,7 @@ SIGNATURES = {
     "gsi_batch_count": (ctypes.c_int, [VP, ctypes.c_uint32, U64P]),
     "gsi_batch_digest": (ctypes.c_int, [VP, ctypes.c_uint32, U64P]),
     "gsi_batch_rows": (ctypes.c_int, [VP, ctypes.c_uint32, U32P, ctypes.c_uint64]),
+    "gsi_batch_results": (ctypes.c_int, [VP, U64P, U64P]),
     "gsi_batch_get_info": (ctypes.c_int, [VP, ctypes.POINTER(gsi_batch_info)]),
     "gsi_batch_free": (ctypes.c_int, [VP]),
     "gsi_batch_tune": (ctypes.c_int, [VP, ctypes.c_uint32, ctypes.POINTER(gsi_query_desc), ctypes.c_uint32,
@@ -450,16 +451,46 @@ def gsi_result_free(r: int):
     _check(load_library().gsi_result_free(r))
 
 
+def _qargs(q):
+    """(vertex labels, edge count, src, dst, edge labels) of a query object as
+    ctypes pointers, with the arrays that back them.  Kept on the query while
+    its arrays are the same objects, so a query asked again is not marshalled
+    again (a few microseconds per call)."""
+    key = (id(q.vlabel), id(q.src), id(q.dst), id(q.elabel))
+    c = getattr(q, "_gsi_args", None)
+    if c is not None and c[0] == key:
+        return c[1]
+    vl, vlp = _u32(q.vlabel)
+    s, sp = _u32(q.src)
+    d, dp = _u32(q.dst)
+    l, lp = _u32(q.elabel)
+    args = (vlp, s.shape[0], sp, dp, lp, (vl, s, d, l))
+    try:
+        q._gsi_args = (key, args)
+    except AttributeError:  # objects without attributes: no cache
+        pass
+    return args
+
+
 def _descs(queries):
     """gsi_query_desc array for query objects (k, vlabel, src, dst, elabel);
     returns (array, keep-alive list)."""
     arr = (gsi_query_desc * max(1, len(queries)))()
     keep = []
     for i, q in enumerate(queries):
-        parts = [_u32(q.vlabel), _u32(q.src), _u32(q.dst), _u32(q.elabel)]
-        keep.append(parts)
-        arr[i] = gsi_query_desc(q.k, parts[0][1], parts[1][0].shape[0], parts[1][1], parts[2][1], parts[3][1])
+        vlp, m, sp, dp, lp, backing = _qargs(q)
+        keep.append(backing)
+        arr[i] = gsi_query_desc(q.k, vlp, m, sp, dp, lp)
     return arr, keep
+
+
+def gsi_batch_results(b: int, nq: int):
+    """(counts, digests) of every query of a batch: uint64 arrays of nq and
+    nq x 2."""
+    counts = np.zeros(nq, np.uint64)
+    digests = np.zeros((nq, 2), np.uint64)
+    _check(load_library().gsi_batch_results(b, counts.ctypes.data_as(U64P), digests.ctypes.data_as(U64P)))
+    return counts, digests
 
 
 def gsi_batch_run(g: int, queries, flags: int = 0, threads: int = 0, grid_scale: int = 0,
@@ -619,6 +650,10 @@ class Batch:
     def digest(self, qi: int) -> tuple:
         return gsi_batch_digest(self.h, qi)
 
+    def results(self):
+        """(counts, digests) of every query: uint64 arrays of nq and nq x 2."""
+        return gsi_batch_results(self.h, len(self.ks))
+
     def rows(self, qi: int) -> np.ndarray:
         return gsi_batch_rows(self.h, qi, self.ks[qi])
 
@@ -678,6 +713,14 @@ class Graph:
 
     def query(self, q, flags: int = 0, order=None, first_edge=None, max_rows: int = 0, fused_max_rows: int = 0,
               fused_max_slots: int = 0, chunk_rows: int = 0, chunk_min_rows: int = 0) -> Result:
+        if order is None and first_edge is None:
+            # the common case, with the query's marshalled arrays reused
+            vlp, m, sp, dp, lp, backing = _qargs(q)
+            o = gsi_query_options(flags, None, None, max_rows, fused_max_rows, fused_max_slots, chunk_rows,
+                                  chunk_min_rows)
+            h = VP()
+            _check(load_library().gsi_query_run(self.h, q.k, vlp, m, sp, dp, lp, ctypes.byref(o), ctypes.byref(h)))
+            return Result(h.value, q.k)
         h = gsi_query_run(self.h, q.k, q.vlabel, q.src, q.dst, q.elabel, flags, order, first_edge, max_rows,
                           fused_max_rows, fused_max_slots, chunk_rows, chunk_min_rows)
         return Result(h, q.k)
@@ -700,7 +743,18 @@ class Graph:
         return gsi_query_run_noalloc(self.h, q.k, q.vlabel, q.src, q.dst, q.elabel, flags, rows_t.data_ptr(), cap)
 
     def batch(self, queries, flags: int = 0, threads: int = 0, grid_scale: int = 0, engine_tiles: int = 0) -> Batch:
-        return Batch(gsi_batch_run(self.h, queries, flags, threads, grid_scale, engine_tiles), [q.k for q in queries])
+        # the descriptor array of the last query list is kept and reused when
+        # the same queries are asked again
+        key = tuple(id(q) for q in queries)
+        c = getattr(self, "_last_descs", None)
+        if c is None or c[0] != key:
+            arr, keep = _descs(queries)
+            c = (key, arr, keep, [q.k for q in queries])
+            self._last_descs = c
+        o = gsi_batch_options(flags, gsi_batch_schedule(threads, grid_scale, engine_tiles))
+        h = VP()
+        _check(load_library().gsi_batch_run(self.h, len(queries), c[1], ctypes.byref(o), ctypes.byref(h)))
+        return Batch(h.value, c[3])
 
     def tune(self, queries, sample: int = 128) -> dict:
         return gsi_batch_tune(self.h, queries, sample)

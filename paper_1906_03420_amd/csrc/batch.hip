@@ -489,6 +489,17 @@ gsi_status gsi_batch_digest(const gsi_batch *b, uint32_t qi, uint64_t out[2]) {
     })
 }
 
+gsi_status gsi_batch_results(const gsi_batch *b, uint64_t *counts, uint64_t *digests) {
+    GSI_TRY({
+        if (!b || !counts || !digests) fail(GSI_E_INVALID, "null argument");
+        for (uint32_t qi = 0; qi < b->nq; qi++) {
+            counts[qi] = b->slots[qi].count;
+            digests[2 * (uint64_t)qi] = b->slots[qi].digest[0];
+            digests[2 * (uint64_t)qi + 1] = b->slots[qi].digest[1];
+        }
+    })
+}
+
 gsi_status gsi_batch_rows(const gsi_batch *b, uint32_t qi, uint32_t *dst, uint64_t cap) {
     GSI_TRY({
         const auto &e = entry(b, qi);

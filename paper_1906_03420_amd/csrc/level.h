@@ -71,6 +71,9 @@ struct LevelArgs {
     // with u's label); every column on a multi-labelled graph
     uint32_t nmc;
     uint8_t mcol[GSI_MAX_K];
+    // the linking edges in the order the join tests them: rarest label
+    // first, so that most candidates fail at the first search
+    uint8_t eorder[GSI_MAX_K];
     uint32_t final_level, count_only;
 };
 
@@ -127,19 +130,24 @@ __device__ __forceinline__ void keep_many(const LevelArgs &a, const uint32_t *x,
     uint32_t be[U];
 #pragma unroll
     for (uint32_t u = 0; u < U; u++) be[u] = a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i[u]];
-    for (uint32_t e2 = 0; e2 < a.ne; e2++) {
+    for (uint32_t t = 0; t < a.ne; t++) {
+        const uint32_t e2 = a.eorder[t];
         uint32_t st[U], len[U];
-        bool act[U], hit[U];
+        bool act[U], hit[U], any = false;
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) {
+            act[u] = keep[u] && e2 != be[u];
+            any |= act[u];
+        }
+        if (!any) continue;
 #pragma unroll
         for (uint32_t u = 0; u < U; u++) {
             st[u] = a.loc[(uint64_t)e2 * a.R + i[u]];
             len[u] = a.loc[(uint64_t)(a.ne + e2) * a.R + i[u]];
         }
 #pragma unroll
-        for (uint32_t u = 0; u < U; u++) {
-            act[u] = keep[u] && e2 != be[u];
+        for (uint32_t u = 0; u < U; u++)
             if (!act[u]) len[u] = 0;
-        }
         in_sorted_many<U>(a.e[e2].ci, st, len, x, hit);
 #pragma unroll
         for (uint32_t u = 0; u < U; u++)

@@ -2090,6 +2090,12 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
                 }
         a.ne = ne;
         st.n_link[j] = ne;
+        {
+            uint32_t ord[GSI_MAX_K];
+            for (uint32_t e = 0; e < ne; e++) ord[e] = e;
+            std::stable_sort(ord, ord + ne, [&](uint32_t x, uint32_t y) { return g->edges[elab[x]] < g->edges[elab[y]]; });
+            for (uint32_t e = 0; e < ne; e++) a.eorder[e] = (uint8_t)ord[e];
+        }
         for (uint32_t v = 0; v < k; v++) a.qcol[v] = col[v];
         // columns of m_i the subtraction has to look at
         for (uint32_t c = 0; c < j; c++)

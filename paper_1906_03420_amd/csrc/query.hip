@@ -720,9 +720,14 @@ constexpr double FN_FACTOR = 2.0;
 // tile's set-up (its rows staged in LDS) is paid once per 1024 slots and
 // each thread has four independent gathers in flight; small levels keep
 // one slot per thread (SPT = 1) and four times as many workgroups.
-constexpr uint64_t WIDE_TILE_SLOTS = 1ull << 22;  // |GBA| from which SPT = 4
-// candidates a join thread tests at once (keep_many)
-constexpr uint32_t JU = 4;
+constexpr uint64_t WIDE_TILE_SLOTS = 1ull << 20;  // |GBA| from which SPT = 4
+// Candidates a join thread tests at once (keep_many).  The join is bound by
+// the latency of its dependent gathers, so waves in flight matter more than
+// loads per thread: two candidates per thread fit in 64 VGPRs, the most
+// that still lets a SIMD hold 8 waves (the join and the record link are
+// built for 8, their spare scalar registers going to VGPR lanes); four took
+// 95 VGPRs (5 waves) and were 19 % slower on R-MAT-23.
+constexpr uint32_t JU = 2;
 // rows of the last level are staged in LDS and written out as one
 // contiguous block per round (coalesced stores) when k is at most this
 constexpr uint32_t LINK_STAGE_K = 16;
@@ -824,7 +829,7 @@ __device__ __forceinline__ void slot_row(const LevelArgs &a, const TileRows &t, 
 }
 
 template <uint32_t SPT>
-__global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
+__global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(8))) void k_join(LevelArgs a) {
     constexpr uint32_t TS = SPT * QT;
     __shared__ uint32_t s_row[TS];    // row of each slot of the tile (staged tiles)
     __shared__ uint32_t s_base[TS];   // per row: ci_all position of slot 0
@@ -953,7 +958,7 @@ __global__ __launch_bounds__(QT) void k_join(LevelArgs a) {
 // tile_off[t] + q of M', extended from row tile_row[t] + rec_r of M by
 // rec_x.  No row search and no second gather of the element.
 template <uint32_t SPT>
-__global__ __launch_bounds__(QT) void k_link_rec(LevelArgs a) {
+__global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(8))) void k_link_rec(LevelArgs a) {
     constexpr uint32_t TS = SPT * QT;
     __shared__ uint64_t s_d[2][QT / 64];
     __shared__ uint32_t s_rows[QT * LINK_STAGE_K];

@@ -228,9 +228,8 @@ __global__ __launch_bounds__(NT) void k_abl_naive_isect(LevelArgs a, uint32_t *b
     const uint64_t i = row_of(a.F, 0, a.R - 1, p);
     const uint32_t be = a.ne > 1 ? a.loc[(uint64_t)(2 * a.ne + 1) * a.R + i] : a.e0;
     if (e == be) return;  // the row's scanned list
-    const uint32_t st = a.loc[(uint64_t)e * a.R + i];
-    const uint32_t len = a.loc[(uint64_t)(a.ne + e) * a.R + i];
-    if (!in_sorted(a.e[e].ci + st, len, x)) buf[p] = NONE32;
+    const uint2 sl = loc_pair(a, e, i);
+    if (!in_sorted(a.e[e].ci + sl.x, sl.y, x)) buf[p] = NONE32;
 }
 
 // keep bits from the buffer: one ballot word per wave (the grid covers every

@@ -383,7 +383,8 @@ void build_graph(gsi_graph *g, const uint32_t *vl, const uint32_t *src, const ui
 
     // persistent signature table first (independent of everything else)
     g->sig = persist<uint32_t>(c, (uint64_t)GSI_SIG_WORDS * n, "signature table");
-    g->ci = persist<uint32_t>(c, nd, "ci");
+    // CI_PAD spare elements: searches read aligned windows that may pass a list's end
+    g->ci = persist<uint32_t>(c, nd + CI_PAD, "ci");
 
     uint32_t *A[3], *B[3];
     for (int i = 0; i < 3; i++) {

@@ -15,6 +15,13 @@
 
 namespace gsi {
 
+// Elements the lists' array holds past its end (never read as list
+// entries): the last round of in_sorted_many reads a 16-byte-aligned window
+// that may reach up to 11 elements beyond a list, so the array is allocated
+// with this many spare elements.
+constexpr uint32_t CI_PAD = 16;
+
+
 constexpr uint32_t NONE32 = 0xFFFFFFFFu;
 constexpr uint32_t KEYS_PER_GROUP = GSI_PCSR_GPN - 1;  // 15 keys + (GID, END)
 constexpr uint32_t GROUP_WORDS = 2 * GSI_PCSR_GPN;      // 32 uint32 = 128 bytes

@@ -59,15 +59,22 @@ __host__ __device__ __forceinline__ bool in_sorted(const uint32_t *list, uint32_
     return hit;
 }
 
-// in_sorted for U (list, x) pairs at once: list u is base[st[u] ..
-// st[u] + len[u]).  Each round issues the probes of every pair before any
+// in_sorted for U (list, x) pairs at once, with A-ary rounds (A - 1 probes
+// each): list u is base[st[u] .. st[u] + len[u]).  Each round issues the probes of every pair before any
 // is compared, so a thread waits for one chain of dependent loads instead
-// of U.  A pair whose range is already down to 8 (or an empty list) probes
+// of U.  A pair whose range is already down to 9 (or an empty list) probes
 // base[lo] again, a valid address: base[0] when the list is empty, which
-// every label holding an edge has.
-template <uint32_t U>
-__device__ __forceinline__ void in_sorted_many(const uint32_t *base, const uint32_t *st, const uint32_t *len,
+// every label holding an edge has.  With VEC (the per-level join), the
+// last <= 9 elements are read as three aligned 16-byte words (12 elements
+// from the 16-byte boundary at or below base + lo), 3 vector loads instead
+// of 8 scalar ones: the join is bound by the address units, which pay per
+// load instruction.  The window may read up to CI_PAD elements past the
+// array's last list.  Without VEC the last <= 8 elements are read one by
+// one (fewer registers: the engine's join holds four pairs).
+template <uint32_t U, bool VEC = true, uint32_t A = 8>
+__host__ __device__ __forceinline__ void in_sorted_many(const uint32_t *base, const uint32_t *st, const uint32_t *len,
                                                const uint32_t *x, bool *hit) {
+    constexpr uint32_t TAIL = VEC ? 9u : 8u;  // elements the last round reads at most
     uint32_t lo[U], n[U];
 #pragma unroll
     for (uint32_t u = 0; u < U; u++) {
@@ -77,36 +84,63 @@ __device__ __forceinline__ void in_sorted_many(const uint32_t *base, const uint3
     for (;;) {
         bool more = false;
 #pragma unroll
-        for (uint32_t u = 0; u < U; u++) more |= n[u] > 8;
+        for (uint32_t u = 0; u < U; u++) more |= n[u] > TAIL;
         if (!more) break;
-        uint32_t v[U][7];
+        uint32_t v[U][A - 1];
 #pragma unroll
         for (uint32_t u = 0; u < U; u++) {
-            const uint32_t s = (n[u] + 7) / 8;
+            const uint32_t s = (n[u] + A - 1) / A;
 #pragma unroll
-            for (uint32_t t = 1; t < 8; t++) v[u][t - 1] = base[lo[u] + (n[u] > 8 && s * t < n[u] ? s * t : 0u)];
+            for (uint32_t t = 1; t < A; t++) v[u][t - 1] = base[lo[u] + (n[u] > TAIL && s * t < n[u] ? s * t : 0u)];
         }
 #pragma unroll
         for (uint32_t u = 0; u < U; u++) {
-            if (n[u] <= 8) continue;
-            const uint32_t s = (n[u] + 7) / 8;
+            if (n[u] <= TAIL) continue;
+            const uint32_t s = (n[u] + A - 1) / A;
             uint32_t c = 0;
 #pragma unroll
-            for (uint32_t t = 1; t < 8; t++) c += (s * t < n[u] && v[u][t - 1] <= x[u]) ? 1u : 0u;
+            for (uint32_t t = 1; t < A; t++) c += (s * t < n[u] && v[u][t - 1] <= x[u]) ? 1u : 0u;
             lo[u] += s * c;
             n[u] = (n[u] - s * c) < s ? (n[u] - s * c) : s;
         }
     }
-    uint32_t w[U][8];
+    if (!VEC) {
+        uint32_t w[U][8];
 #pragma unroll
-    for (uint32_t u = 0; u < U; u++)
+        for (uint32_t u = 0; u < U; u++)
 #pragma unroll
-        for (uint32_t t = 0; t < 8; t++) w[u][t] = base[lo[u] + (t < n[u] ? t : 0u)];
+            for (uint32_t t = 0; t < 8; t++) w[u][t] = base[lo[u] + (t < n[u] ? t : 0u)];
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) {
+            bool h = false;
+#pragma unroll
+            for (uint32_t t = 0; t < 8; t++) h |= t < n[u] && w[u][t] == x[u];
+            hit[u] = h;
+        }
+        return;
+    }
+    uint4 w[U][3];
+    uint32_t off[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; u++) {
+        const uint32_t *p = base + lo[u];
+        const uint4 *pa = reinterpret_cast<const uint4 *>(reinterpret_cast<uintptr_t>(p) & ~(uintptr_t)15);
+        off[u] = (uint32_t)(p - reinterpret_cast<const uint32_t *>(pa));
+#pragma unroll
+        for (uint32_t t = 0; t < 3; t++) w[u][t] = pa[t];
+    }
 #pragma unroll
     for (uint32_t u = 0; u < U; u++) {
         bool h = false;
 #pragma unroll
-        for (uint32_t t = 0; t < 8; t++) h |= t < n[u] && w[u][t] == x[u];
+        for (uint32_t t = 0; t < 3; t++) {
+            const uint32_t e[4] = {w[u][t].x, w[u][t].y, w[u][t].z, w[u][t].w};
+#pragma unroll
+            for (uint32_t q = 0; q < 4; q++) {
+                const uint32_t d = 4 * t + q - off[u];  // position in [lo, lo + n) when < n (wraps below lo)
+                h |= d < n[u] && e[q] == x[u];
+            }
+        }
         hit[u] = h;
     }
 }

@@ -237,11 +237,14 @@ __global__ __launch_bounds__(QT) void k_filter(const uint32_t *sig, uint32_t n, 
         const bool valid = tile * QT + threadIdx.x < n;
         uint32_t ok = 0;
         for (uint32_t u = 0; u < K; u++) {
+            const bool lab_ok = valid && (fa.subset0 ? (~w0[r] & fa.q[u][0]) == 0 : w0[r] == fa.q[u][0]);
+            // the word tests are most of the kernel's vector work: a wave
+            // none of whose vertices has u's label skips them (uniform)
+            if (__ballot(lab_ok) == 0) continue;
             uint32_t miss = 0;
 #pragma unroll
             for (int i = 1; i < GSI_SIG_WORDS; i++) miss |= nw[r][i] & fa.q[u][i];
-            const bool lab_ok = fa.subset0 ? (~w0[r] & fa.q[u][0]) == 0 : w0[r] == fa.q[u][0];
-            ok |= (valid && lab_ok && miss == 0) ? (1u << u) : 0u;
+            ok |= (lab_ok && miss == 0) ? (1u << u) : 0u;
         }
         uint64_t mine = 0;
         for (uint32_t u = 0; u < K; u++) {
@@ -583,8 +586,7 @@ __global__ __launch_bounds__(QT) void k_locate(LevelArgs a) {
             const EdgeRef &er = a.e[e];
             uint32_t v = a.M[(uint64_t)er.col * a.ldm + i];
             uint2 r = a.abl_cr ? cr_find(er, v) : pcsr_find(er.gl, er.G, er.H, v);
-            a.loc[(uint64_t)e * a.R + i] = r.x;
-            a.loc[(uint64_t)(a.ne + e) * a.R + i] = r.y;
+            reinterpret_cast<uint2 *>(a.loc)[(uint64_t)e * a.R + i] = r;
             all += r.y;
             if (e == a.e0) {
                 s0 = r.x;
@@ -611,22 +613,23 @@ __global__ __launch_bounds__(QT) void k_locate(LevelArgs a) {
             (void)all;
             for (uint32_t e = 0; e < a.ne; e++) {
                 if (e == be) continue;
-                const uint64_t L = a.loc[(uint64_t)(a.ne + e) * a.R + i];
+                const uint64_t L = loc_pair(a, e, i).y;
                 other += L < (uint64_t)bl ? L : (uint64_t)bl;
             }
         }
     }
-    if (!a.part) return;  // list-length totals are gathered for profiling only
-    __shared__ uint64_t s_o[QT / 64];
-    other = wave_sum(other);
-    if (lane_id() == 0) s_o[threadIdx.x >> 6] = other;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t t = 0;
+    if (a.part) {  // list-length totals are gathered for profiling only
+        __shared__ uint64_t s_o[QT / 64];
+        other = wave_sum(other);
+        if (lane_id() == 0) s_o[threadIdx.x >> 6] = other;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t t = 0;
 #pragma unroll
-        for (int q = 0; q < QT / 64; q++) t += s_o[q];
-        a.part[2 * (uint64_t)blockIdx.x] = t;
-        a.part[2 * (uint64_t)blockIdx.x + 1] = 0;
+            for (int q = 0; q < QT / 64; q++) t += s_o[q];
+            a.part[2 * (uint64_t)blockIdx.x] = t;
+            a.part[2 * (uint64_t)blockIdx.x + 1] = 0;
+        }
     }
 }
 
@@ -701,8 +704,8 @@ __device__ __forceinline__ uint64_t fn_rank(const uint64_t *bits, const uint64_t
 __global__ __launch_bounds__(QT) void k_fn_relocate(LevelArgs a, const uint64_t *bits, const uint64_t *wpre) {
     const uint64_t i = (uint64_t)blockIdx.x * QT + threadIdx.x;
     if (i >= a.R) return;
-    const uint32_t s = a.loc[(uint64_t)a.e0 * a.R + i];
-    const uint32_t len = a.loc[(uint64_t)(a.ne + a.e0) * a.R + i];
+    const uint2 sl = loc_pair(a, a.e0, i);
+    const uint32_t s = sl.x, len = sl.y;
     const uint64_t fs = len ? fn_rank(bits, wpre, s) : 0;
     const uint64_t fe = len ? fn_rank(bits, wpre, (uint64_t)s + len) : 0;
     a.bound[i] = (uint32_t)(fe - fs);
@@ -942,10 +945,8 @@ __global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(8))) void k_
                 a.rec_r[rb + q] = s_ri[e];
             }
         }
-        return;
-    }
-    // the tile's keep bits (one word per 64 slots) and their count
-    if (threadIdx.x < 64) {
+    } else if (threadIdx.x < 64) {
+        // the tile's keep bits (one word per 64 slots) and their count
         const uint64_t word = threadIdx.x < TS / 64 ? s_keep[threadIdx.x] : 0ull;
         if (threadIdx.x < TS / 64 && !a.abl_two_step) a.bitmap[(uint64_t)blockIdx.x * (TS / 64) + threadIdx.x] = word;
         const uint32_t t = wave_sum((uint32_t)__popcll(word));
@@ -996,6 +997,7 @@ __global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(8))) void k_
             uint64_t f = 14695981039346656037ull;
             for (uint32_t u0 = 0; u0 < a.k; u0 += 8) {
                 uint32_t val[8];
+                // every load issued before any is used (no branch between them)
 #pragma unroll
                 for (uint32_t k4 = 0; k4 < 8; k4++) {
                     const uint32_t c = u0 + k4 < a.k ? s_qc[u0 + k4] : a.j;
@@ -1146,6 +1148,7 @@ __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
                 uint64_t f = 14695981039346656037ull;
                 for (uint32_t u0 = 0; u0 < a.k; u0 += 8) {
                     uint32_t val[8];
+                    // every load issued before any is used (no branch between them)
 #pragma unroll
                     for (uint32_t k4 = 0; k4 < 8; k4++) {
                         const uint32_t c = u0 + k4 < a.k ? s_qc[u0 + k4] : a.j;
@@ -1408,6 +1411,7 @@ __global__ __launch_bounds__(QT) void k_join_pass(LevelArgs a) {
             uint64_t f = 14695981039346656037ull;
             for (uint32_t u0 = 0; u0 < a.k; u0 += 8) {
                 uint32_t val[8];
+                // every load issued before any is used (no branch between them)
 #pragma unroll
                 for (uint32_t k4 = 0; k4 < 8; k4++) {
                     const uint32_t c = u0 + k4 < a.k ? s_qc[u0 + k4] : a.j;
@@ -2099,12 +2103,12 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
             uint32_t ord[GSI_MAX_K];
             for (uint32_t e = 0; e < ne; e++) ord[e] = e;
             std::stable_sort(ord, ord + ne, [&](uint32_t x, uint32_t y) { return g->edges[elab[x]] < g->edges[elab[y]]; });
-            for (uint32_t e = 0; e < ne; e++) a.eorder[e] = (uint8_t)ord[e];
+            for (uint32_t e = 0; e < ne; e++) a.eorder[e] = ord[e];
         }
         for (uint32_t v = 0; v < k; v++) a.qcol[v] = col[v];
         // columns of m_i the subtraction has to look at
         for (uint32_t c = 0; c < j; c++)
-            if (q.multi || q.vl[order[c]] == q.vl[u]) a.mcol[a.nmc++] = (uint8_t)c;
+            if (q.multi || q.vl[order[c]] == q.vl[u]) a.mcol[a.nmc++] = c;
         a.final_level = final_level ? 1u : 0u;
         a.count_only = count_only ? 1u : 0u;
 
@@ -2129,12 +2133,13 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         // above what HBM can deliver).
         const double lbytes = (double)R * (4.0 * ne + 4.0 * (2.0 * ne + 2.0) + 4.0 + 8.0);
         launch(c, "k_locate", lbytes, k_locate, (uint32_t)nbr, QT, a);
-        if (prof) reduce_pairs(c, a.part, nbr, dscal + 2);
+        // |GBA| lands in dscal[3]; the profiling sums go to dscal[4..5]
+        if (prof) reduce_pairs(c, a.part, nbr, dscal + 4);
         exclusive_scan(c, a.bound, R, F, ls, dscal + 3);
         uint64_t sc[2];
-        read_scalars(c, dscal + 2, sc, 2);
-        if (!prof) sc[0] = 0;
-        uint64_t gba = sc[1];
+        read_scalars(c, dscal + 3, sc, 2);
+        uint64_t gba = sc[0];
+        sc[0] = prof ? sc[1] : 0;
         // a level whose rows rescan l0's lists many times over: filter those
         // lists by C(u) once and let the rows scan the filtered copies
         Block fnb(c);

@@ -340,6 +340,41 @@ def test_fused_and_per_level_paths_agree(ctx, seed):
     dg.free()
 
 
+def test_profiling_context_gives_identical_results():
+    """A context that times every launch (GSI_CTX_PROFILE) gives the same
+    answers on every route: per-level kernels with and without list
+    filtering, small and large scans, the fused workgroup and root chunks
+    (regression: a profiling reduction once overwrote |GBA| in the mailbox
+    after k_locate's last workgroup had scanned the row bounds)."""
+    import paper_1906_03420_amd as gsi
+    pc = gsi.Context(2 << 30, flags=gsi.GSI_CTX_PROFILE)
+    try:
+        for seed in range(4):
+            r = np.random.default_rng(2000 + seed)
+            n = int(r.integers(300, 2000))
+            g = w.random_small_graph(n, float(r.uniform(0.005, 0.02)), 2, 2, seed + 77)
+            if g.m == 0:
+                continue
+            dg = pc.load(g)
+            og = oracle.OracleGraph(g)
+            for t in range(3):
+                q = w.random_connected_query(int(r.integers(3, 7)), 1, 2, 2, seed * 17 + t)
+                want = og.match(q, threads=4, max_count=2_000_000)
+                if want.status != 0:
+                    continue
+                for mode in (dict(flags=4), dict(flags=4 | 0x8000), dict(), dict(chunk_min_rows=1)):
+                    print("seed", seed, "query", t, "mode", mode, flush=True)
+                    res = dg.query(q, **mode)
+                    assert res.count == want.count
+                    np.testing.assert_array_equal(res.sorted_rows(), want.tuples)
+                    assert res.digest == want.digest
+                    res.free()
+            dg.free()
+        assert any(k["launches"] for k in pc.kernel_stats())
+    finally:
+        pc.close()
+
+
 def test_fused_path_er1k_and_count_only(ctx):
     import paper_1906_03420_amd as gsi
     g = w.config_graph("er1k")

@@ -958,7 +958,11 @@ __global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(8))) void k_
 // slot order as (element, row) records): survivor q of tile t is row
 // tile_off[t] + q of M', extended from row tile_row[t] + rec_r of M by
 // rec_x.  No row search and no second gather of the element.
-template <uint32_t SPT>
+// W > 0: the row has at most 4W values to gather (j columns on an inner
+// level, k values on the last), so all 4W loads are issued in one
+// straight-line batch (entries past the row re-read a valid column); W = 0
+// takes any width, eight columns per batch.
+template <uint32_t SPT, uint32_t W>
 __global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(8))) void k_link_rec(LevelArgs a) {
     constexpr uint32_t TS = SPT * QT;
     __shared__ uint64_t s_d[2][QT / 64];
@@ -990,9 +994,37 @@ __global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         const uint64_t i = r_lo + a.rec_r[rb + qq];
         if (!a.final_level) {
             if (mine) {
-                copy_row(a, i, a.Mn, a.S, pos);
+                if (W) {
+                    uint32_t m[4 * (W ? W : 1)];
+#pragma unroll
+                    for (uint32_t c = 0; c < 4 * W; c++) m[c] = a.M[(uint64_t)(c < a.j ? c : a.j - 1) * a.ldm + i];
+#pragma unroll
+                    for (uint32_t c = 0; c < 4 * W; c++)
+                        if (c < a.j) a.Mn[(uint64_t)c * a.S + pos] = m[c];
+                } else {
+                    copy_row(a, i, a.Mn, a.S, pos);
+                }
                 a.Mn[(uint64_t)a.j * a.S + pos] = x;
             }
+        } else if (mine && W) {
+            uint64_t f = 14695981039346656037ull;
+            uint32_t val[4 * (W ? W : 1)];
+#pragma unroll
+            for (uint32_t u = 0; u < 4 * W; u++) {
+                const uint32_t c = u < a.k ? s_qc[u] : a.j;
+                const uint32_t mv = a.M[(uint64_t)(c < a.j ? c : 0u) * a.ldm + i];
+                val[u] = c < a.j ? mv : x;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 4 * W; u++) {
+                if (u >= a.k) break;
+                if (stage) s_rows[threadIdx.x * a.k + u] = val[u];
+                else if (!a.count_only) a.out[pos * a.k + u] = val[u];
+                f = fnv_word(f, val[u]);
+            }
+            const uint64_t h = mix64(f);
+            hs += h;
+            hx ^= h;
         } else if (mine) {
             uint64_t f = 14695981039346656037ull;
             for (uint32_t u0 = 0; u0 < a.k; u0 += 8) {
@@ -1049,6 +1081,23 @@ __global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     }
 }
 
+
+// k_link_rec for tiles of spt x 256 slots and rows of at most 4 * wg
+// values (wg = 0: any)
+template <uint32_t SPT>
+static void launch_link_rec_w(gsi_ctx *c, double lb, uint32_t wg, uint32_t ntiles, const LevelArgs &a) {
+    switch (wg) {
+        case 1: launch(c, "k_link", lb, k_link_rec<SPT, 1>, ntiles, QT, a); break;
+        case 2: launch(c, "k_link", lb, k_link_rec<SPT, 2>, ntiles, QT, a); break;
+        case 3: launch(c, "k_link", lb, k_link_rec<SPT, 3>, ntiles, QT, a); break;
+        case 4: launch(c, "k_link", lb, k_link_rec<SPT, 4>, ntiles, QT, a); break;
+        default: launch(c, "k_link", lb, k_link_rec<SPT, 0>, ntiles, QT, a); break;
+    }
+}
+static void launch_link_rec(gsi_ctx *c, double lb, uint32_t spt, uint32_t wg, uint32_t ntiles, const LevelArgs &a) {
+    if (spt == 4) launch_link_rec_w<4>(c, lb, wg, ntiles, a);
+    else launch_link_rec_w<1>(c, lb, wg, ntiles, a);
+}
 
 template <uint32_t SPT>
 __global__ __launch_bounds__(QT) void k_link(LevelArgs a) {
@@ -2329,8 +2378,10 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
             lb += 4.0 * (j + 1) * S;
         }
         if (recs) {
-            if (spt == 4) launch(c, "k_link", lb, k_link_rec<4>, (uint32_t)ntiles, QT, a);
-            else launch(c, "k_link", lb, k_link_rec<1>, (uint32_t)ntiles, QT, a);
+            // values a row gathers, in groups of 4 (0: more than 16)
+            const uint32_t width = final_level ? k : j;
+            const uint32_t wg = width <= 16 ? (width + 3) / 4 : 0;
+            launch_link_rec(c, lb, spt, wg, (uint32_t)ntiles, a);
         } else if (spt == 4) {
             launch(c, "k_link", lb, k_link<4>, (uint32_t)ntiles, QT, a);
         } else {

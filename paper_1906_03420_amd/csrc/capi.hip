@@ -1,5 +1,6 @@
 // C ABI entry points, error reporting, the device arena and kernel timing.
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <set>
 #include <vector>
@@ -167,9 +168,31 @@ static void drain_records(gsi_ctx *c) {
     c->recs.clear();
 }
 
+// how long read_scalars spins for an armed completion word before it
+// synchronises the stream instead
+constexpr int64_t SEQ_SPIN_US = 500;
+
 void read_scalars(gsi_ctx *c, const uint64_t *dev, uint64_t *host, int n) {
     if (c->mbox_dev && dev >= c->mbox_dev && dev + n <= c->mbox_dev + MAILBOX_WORDS) {
-        GSI_HIP(hipStreamSynchronize(c->stream));
+        bool seen = false;
+        if (c->seq_armed) {
+            // the last kernel posts c->seq after its scalars: spin for it a
+            // while (short levels), then fall back to a stream sync
+            const volatile uint64_t *w = c->mbox_host + MBOX_SEQ;
+            const auto t0 = std::chrono::steady_clock::now();
+            for (uint32_t it = 0;; it++) {
+                if (*w == c->seq) {
+                    seen = true;
+                    break;
+                }
+                if ((it & 255) == 255 &&
+                    std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(SEQ_SPIN_US))
+                    break;
+            }
+            c->seq_armed = false;
+        }
+        if (!seen) GSI_HIP(hipStreamSynchronize(c->stream));
+        std::atomic_thread_fence(std::memory_order_acquire);
         memcpy(host, c->mbox_host + (dev - c->mbox_dev), sizeof(uint64_t) * n);
         return;
     }

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t *in
 }
 
 __global__ __launch_bounds__(1024) void k_scan_partials(uint64_t *part, uint64_t nb, uint64_t *total,
-                                                       uint64_t *total2) {
+                                                       uint64_t *total2, uint64_t *seqp, uint64_t seqv) {
     uint64_t carry = 0;
     for (uint64_t c0 = 0; c0 < nb; c0 += 1024) {
         uint64_t idx = c0 + threadIdx.x;
@@ -82,6 +82,7 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint64_t *part, uint64_t
     if (threadIdx.x == 0) {
         *total = carry;
         if (total2) *total2 = carry;
+        post_seq(seqp, seqv);
     }
 }
 
@@ -109,7 +110,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t *in,
 // whole scan in one workgroup (1024 threads x 8 consecutive items), for
 // inputs of at most SMALL_SCAN items: one launch instead of three
 constexpr int SMALL_SCAN = 1024 * SCAN_ITEMS;
-__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *total) {
+__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *total,
+                                                    uint64_t *seqp, uint64_t seqv) {
     uint64_t base = (uint64_t)threadIdx.x * SCAN_ITEMS;
     uint32_t v[SCAN_ITEMS];
     uint64_t s = 0;
@@ -130,6 +132,7 @@ __global__ __launch_bounds__(1024) void k_scan_small(const uint32_t *in, uint64_
     if (threadIdx.x == 0) {
         out[n] = tot;
         if (total) *total = tot;
+        post_seq(seqp, seqv);
     }
 }
 
@@ -139,16 +142,22 @@ void exclusive_scan(gsi_ctx *c, const uint32_t *in, uint64_t n, uint64_t *out, S
         if (total) fill_u64(c, total, 0, 1);
         return;
     }
+    uint64_t seqv = 0;
+    uint64_t *seqp = seq_slot(c, total, &seqv);
     if (n <= (uint64_t)SMALL_SCAN) {
-        launch(c, "k_scan_small", 12.0 * n, k_scan_small, 1, 1024, in, n, out, total);
+        launch(c, "k_scan_small", 12.0 * n, k_scan_small, 1, 1024, in, n, out, total, seqp, seqv);
+        c->seq_armed = seqp != nullptr;
         return;
     }
     uint64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb > 0x7FFFFFFFull) fail(GSI_E_INVALID, "scan too large");
     uint64_t *part = s.get<uint64_t>(nb, "scan partials");
     launch(c, "k_scan_reduce", 4.0 * n, k_scan_reduce, (uint32_t)nb, SCAN_THREADS, in, n, part);
-    launch(c, "k_scan_partials", 16.0 * nb, k_scan_partials, 1, 1024, part, nb, out + n, total);
+    launch(c, "k_scan_partials", 16.0 * nb, k_scan_partials, 1, 1024, part, nb, out + n, total, seqp, seqv);
     launch(c, "k_scan_apply", 12.0 * n, k_scan_apply, (uint32_t)nb, SCAN_THREADS, in, n, (const uint64_t *)part, out);
+    // the total is posted before the apply pass ends; a reader of it alone
+    // need not wait for out[]: stream order makes later launches see out[]
+    c->seq_armed = seqp != nullptr;
     s.drop(part);
 }
 

@@ -1510,7 +1510,8 @@ __global__ __launch_bounds__(QT) void k_join_pass(LevelArgs a) {
 }
 
 // (sum, xor) over n pairs part[2i], part[2i+1]: one workgroup
-__global__ __launch_bounds__(1024) void k_reduce_pairs(const uint64_t *part, uint64_t n, uint64_t *out) {
+__global__ __launch_bounds__(1024) void k_reduce_pairs(const uint64_t *part, uint64_t n, uint64_t *out, uint64_t *seqp,
+                                                      uint64_t seqv) {
     __shared__ uint64_t s_s[16], s_x[16];
     uint64_t sm = 0, xr = 0;
     for (uint64_t i = threadIdx.x; i < n; i += 1024) {
@@ -1532,6 +1533,7 @@ __global__ __launch_bounds__(1024) void k_reduce_pairs(const uint64_t *part, uin
         }
         out[0] = ts;
         out[1] = tx;
+        post_seq(seqp, seqv);
     }
 }
 
@@ -1565,7 +1567,10 @@ __global__ __launch_bounds__(QT) void k_emit_single(const uint32_t *M, uint64_t 
 }
 
 static void reduce_pairs(gsi_ctx *c, const uint64_t *part, uint64_t n, uint64_t *out) {
-    launch(c, "k_reduce_pairs", 16.0 * n + 16.0, k_reduce_pairs, 1, 1024, part, n, out);
+    uint64_t seqv = 0;
+    uint64_t *seqp = seq_slot(c, out, &seqv);
+    launch(c, "k_reduce_pairs", 16.0 * n + 16.0, k_reduce_pairs, 1, 1024, part, n, out, seqp, seqv);
+    c->seq_armed = seqp != nullptr;
 }
 
 // ---------------------------------------------------------------- planner

@@ -168,31 +168,42 @@ static void drain_records(gsi_ctx *c) {
     c->recs.clear();
 }
 
-// how long read_scalars spins for an armed completion word before it
+// how long wait_mailbox spins for the completion word before it
 // synchronises the stream instead
 constexpr int64_t SEQ_SPIN_US = 500;
 
+// posts the completion word once every earlier launch on the stream is done
+__global__ void k_post(uint64_t *slot, uint64_t value) {
+    if (threadIdx.x == 0) post_seq(slot, value);
+}
+
+void wait_mailbox(gsi_ctx *c) {
+    if (!c->seq_armed) {
+        // no kernel posts the word after its scalars: a one-wave launch that
+        // runs after every earlier one does (still ~4 us sooner than a
+        // stream sync)
+        const uint64_t v = ++c->seq;
+        launch(c, "k_post", 0.0, k_post, 1, 64, c->mbox_dev + MBOX_SEQ, v);
+        c->seq_armed = true;
+    }
+    bool seen = false;
+    const volatile uint64_t *w = c->mbox_host + MBOX_SEQ;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint32_t it = 0;; it++) {
+        if (*w == c->seq) {
+            seen = true;
+            break;
+        }
+        if ((it & 255) == 255 && std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(SEQ_SPIN_US)) break;
+    }
+    c->seq_armed = false;
+    if (!seen) GSI_HIP(hipStreamSynchronize(c->stream));
+    std::atomic_thread_fence(std::memory_order_acquire);
+}
+
 void read_scalars(gsi_ctx *c, const uint64_t *dev, uint64_t *host, int n) {
     if (c->mbox_dev && dev >= c->mbox_dev && dev + n <= c->mbox_dev + MAILBOX_WORDS) {
-        bool seen = false;
-        if (c->seq_armed) {
-            // the last kernel posts c->seq after its scalars: spin for it a
-            // while (short levels), then fall back to a stream sync
-            const volatile uint64_t *w = c->mbox_host + MBOX_SEQ;
-            const auto t0 = std::chrono::steady_clock::now();
-            for (uint32_t it = 0;; it++) {
-                if (*w == c->seq) {
-                    seen = true;
-                    break;
-                }
-                if ((it & 255) == 255 &&
-                    std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(SEQ_SPIN_US))
-                    break;
-            }
-            c->seq_armed = false;
-        }
-        if (!seen) GSI_HIP(hipStreamSynchronize(c->stream));
-        std::atomic_thread_fence(std::memory_order_acquire);
+        wait_mailbox(c);
         memcpy(host, c->mbox_host + (dev - c->mbox_dev), sizeof(uint64_t) * n);
         return;
     }

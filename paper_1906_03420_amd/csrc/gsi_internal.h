@@ -238,6 +238,9 @@ __device__ __forceinline__ void post_seq(uint64_t *slot, uint64_t value) {
 // Reads back `n` uint64 values from device memory, or from the mailbox
 // without a copy (synchronises the stream either way).
 void read_scalars(gsi_ctx *c, const uint64_t *dev, uint64_t *host, int n);
+// Returns once the mailbox holds what every launch so far wrote there (the
+// completion word, else a stream sync); device memory is not covered.
+void wait_mailbox(gsi_ctx *c);
 void sync(gsi_ctx *c);
 
 // ------------------------------------------------------------- primitives

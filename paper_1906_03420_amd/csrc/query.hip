@@ -2073,10 +2073,13 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         launch_fused(c, fdplan, *finl, j0, M, (uint32_t)R, druns + (uint64_t)order[0] * BITS_RUNS, root_bits, nwords,
                      fbuf0, fbuf1, floc, out, fdst, 0.0);
         FStatus *hs = reinterpret_cast<FStatus *>(c->mbox_host + MBOX_STATUS);
-        sync(c);
+        wait_mailbox(c);
         const uint32_t last = hs->done ? (uint32_t)hs->levels : (uint32_t)hs->level;
         if ((c->flags & GSI_CTX_PROFILE) && !c->recs.empty())
-            c->recs.back().bytes = fused_bytes(fhp, last, hs->lv_rows, hs->lv_gba, hs->lv_surv);
+            // plus, when it builds M0 itself, the root's candidate bitset it
+            // scans and the rows it writes
+            c->recs.back().bytes = fused_bytes(fhp, last, hs->lv_rows, hs->lv_gba, hs->lv_surv) +
+                                   (root_bits ? 8.0 * (double)nwords + 4.0 * (double)R : 0.0);
         for (uint32_t j = j0; j <= last && j < k; j++) {
             st.rows[j] = hs->lv_rows[j];
             st.gba[j] = hs->lv_gba[j];

@@ -56,6 +56,8 @@ constexpr uint32_t WU = 4;
 // the last search round as vector loads (in_sorted_many): more registers,
 // one wave fewer per SIMD for the engine's join
 constexpr bool WVEC = false;
+// search rounds split a range in WARITY parts (in_sorted_many)
+constexpr uint32_t WARITY = 8;
 
 // The costly tests of U candidates of query Q at once (rows i[u] of Q's
 // table): keep[u] (on entry: candidate u is live) becomes x[u] not in the
@@ -101,7 +103,7 @@ __device__ __forceinline__ void wkeep_many(const WQ &Q, const uint32_t *loc, con
             act[u] = keep[u] && e2 != be[u];
             if (!act[u]) len[u] = 0;
         }
-        in_sorted_many<U, WVEC>(edges[Q.efirst + e2].ci, st, len, x, hit);
+        in_sorted_many<U, WVEC, WARITY>(edges[Q.efirst + e2].ci, st, len, x, hit);
 #pragma unroll
         for (uint32_t u = 0; u < U; u++)
             if (act[u]) keep[u] = hit[u];

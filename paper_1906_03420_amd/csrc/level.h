@@ -77,6 +77,16 @@ struct LevelArgs {
     // first, so that most candidates fail at the first search
     uint32_t eorder[GSI_MAX_K];
     uint32_t final_level, count_only;
+    // k_locate with one workgroup (R <= its threads): it also scans the
+    // row bounds into F, writes |GBA| to scan_total and posts seq_value to
+    // seq_slot (the mailbox completion word), so the level needs no scan
+    // launch; nullptr otherwise
+    uint64_t *scan_total;
+    uint64_t *seq_slot;
+    uint64_t seq_value;
+    // 1: R <= 256, the join finds each tile's rows in F itself and writes
+    // tile_row for the link (no k_tile_rows launch)
+    uint32_t rows_in_join;
 };
 
 // The located (start, length) of linking edge e for row i

@@ -540,12 +540,52 @@ void run_filter_many(gsi_graph *g, const std::vector<const HostQuery *> &qs, con
     sync(c);  // `passes` is read by the copy above
 }
 
+// The single-query filter through the grouped kernel (k_filter_multi, one
+// pass): a round's vertices whose label some query vertex has are listed in
+// LDS and tested against the query vertices of that label only.  Counts and
+// per-run counts come from the bitsets (k_bit_counts), as in launch_filter.
+constexpr bool GROUPED_SINGLE_FILTER = true;
+constexpr size_t PINNED_FILTER_ARGS = 5120;  // staging offset in c->pinned (status region, past the chunk summary)
+static void launch_filter_grouped(gsi_ctx *c, gsi_graph *g, const FilterArgs &f, uint64_t *bits, uint32_t *counts,
+                                  uint32_t *runs) {
+    static_assert(PINNED_FILTER_ARGS >= 4096 + sizeof(FChunkSummary) &&
+                      PINNED_FILTER_ARGS + sizeof(FilterArgs) <= 8192,
+                  "filter arguments between the chunk summary and the plans");
+    FilterArgs *fa = reinterpret_cast<FilterArgs *>(reinterpret_cast<char *>(c->pinned) + PINNED_FILTER_ARGS);
+    uint32_t idx[GSI_MAX_K];
+    for (uint32_t u = 0; u < f.k; u++) idx[u] = u;
+    std::stable_sort(idx, idx + f.k, [&](uint32_t x, uint32_t y) { return f.q[x][0] < f.q[y][0]; });
+    memset(fa, 0, sizeof(*fa));
+    fa->k = f.k;
+    fa->word_mask = f.word_mask;
+    for (uint32_t t = 0; t < f.k; t++) {
+        fa->dst[t] = f.dst[idx[t]];
+        memcpy(fa->q[t], f.q[idx[t]], sizeof(fa->q[t]));
+    }
+    Scratch s(c);
+    const uint64_t nwords = ((uint64_t)g->n + 63) / 64;
+    const uint32_t nrounds = (uint32_t)(((uint64_t)g->n + FM_TILE - 1) / FM_TILE);
+    const uint32_t nb = std::max<uint32_t>(1, std::min<uint32_t>(nrounds, 8192));
+    FilterArgs *dp = reinterpret_cast<FilterArgs *>(s.get<uint32_t>(sizeof(FilterArgs) / 4, "filter pass"));
+    uint32_t *part = s.get<uint32_t>((uint64_t)GSI_MAX_K * nb, "filter partial counts");
+    GSI_HIP(hipMemcpyAsync(dp, fa, sizeof(FilterArgs), hipMemcpyHostToDevice, c->stream));
+    const double bytes = 4.0 * g->n * (1 + __builtin_popcount(f.word_mask)) + (double)f.k * nwords * 8;
+    launch(c, "k_filter", bytes, k_filter_multi, dim3(nb, 1), QT, (const uint32_t *)g->sig, g->n, nwords,
+           (const FilterArgs *)dp, bits, part);
+    launch(c, "k_filter_counts", 8.0 * f.k * nwords, k_bit_counts, f.k, 1024, (const uint64_t *)bits, nwords, counts,
+           runs);
+}
+
 static void filter_impl(gsi_graph *g, const HostQuery &q, bool label_only, uint64_t *bits, uint32_t *counts,
                         bool homo = false, uint32_t *runs = nullptr) {
     gsi_ctx *c = g->ctx;
     FilterArgs fa;
     query_signatures(q, fa, homo);
     fa.label_only = label_only ? 1u : 0u;
+    if (GROUPED_SINGLE_FILTER && !label_only && !q.multi && !g->multi) {
+        launch_filter_grouped(c, g, fa, bits, counts, runs);
+        return;
+    }
     launch_filter(c, g, fa, bits, counts, runs, q.multi ? &q : nullptr);
 }
 
@@ -629,6 +669,26 @@ __global__ __launch_bounds__(QT) void k_locate(LevelArgs a) {
             for (int q = 0; q < QT / 64; q++) t += s_o[q];
             a.part[2 * (uint64_t)blockIdx.x] = t;
             a.part[2 * (uint64_t)blockIdx.x + 1] = 0;
+        }
+    }
+    if (a.scan_total) {  // the only workgroup: F = exclusive sums of the bounds
+        __shared__ uint64_t s_b[QT / 64];
+        const uint64_t b = valid ? a.bound[i] : 0u;
+        const uint64_t inc = wave_inclusive_sum(b);
+        if (lane_id() == 63) s_b[threadIdx.x >> 6] = inc;
+        __syncthreads();
+        uint64_t pre = 0, tot = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < QT / 64; q++) {
+            pre += q < (threadIdx.x >> 6) ? s_b[q] : 0ull;
+            tot += s_b[q];
+        }
+        uint64_t *F = const_cast<uint64_t *>(a.F);
+        if (valid) F[i] = pre + inc - b;
+        if (threadIdx.x == 0) {
+            F[a.R] = tot;
+            *a.scan_total = tot;
+            post_seq(a.seq_slot, a.seq_value);
         }
     }
 }
@@ -798,8 +858,37 @@ __device__ __forceinline__ TileRows stage_slot_rows(const LevelArgs &a, uint64_t
                                                     uint32_t *s_base, uint32_t *s_w) {
     constexpr uint32_t TS = SPT * QT;
     TileRows t;
-    t.r_lo = a.tile_row[tile];
-    t.r_hi = a.tile_row[tile + 1];
+    if (a.rows_in_join) {
+        // at most 256 rows: wave 0 counts the row starts at or before the
+        // tile's first slot and the next tile's (four per lane), which gives
+        // the rows holding them; the link reads tile_row[tile] later
+        __shared__ uint32_t s_rr[2];
+        if (threadIdx.x < 64) {
+            const uint64_t p0 = tile * TS, p1 = p0 + TS;
+            uint32_t c0 = 0, c1 = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < 4; k++) {
+                const uint64_t r = 4ull * threadIdx.x + k;
+                const uint64_t f = a.F[r < a.R ? r : 0];
+                c0 += (r < a.R && f <= p0) ? 1u : 0u;
+                c1 += (r < a.R && f <= p1) ? 1u : 0u;
+            }
+            c0 = wave_sum(c0);
+            c1 = wave_sum(c1);
+            if (threadIdx.x == 0) {
+                s_rr[0] = c0 - 1;
+                s_rr[1] = p1 < a.gba ? c1 - 1 : (uint32_t)(a.R - 1);
+                const_cast<uint64_t *>(a.tile_row)[tile] = c0 - 1;
+                if (tile + 1 == gridDim.x) const_cast<uint64_t *>(a.tile_row)[tile + 1] = a.R - 1;
+            }
+        }
+        __syncthreads();
+        t.r_lo = s_rr[0];
+        t.r_hi = s_rr[1];
+    } else {
+        t.r_lo = a.tile_row[tile];
+        t.r_hi = a.tile_row[tile + 1];
+    }
     const uint64_t nr = t.r_hi - t.r_lo + 1;
     t.staged = nr <= TS;
     if (t.staged) {
@@ -2189,10 +2278,18 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         // (counting every read, or every group of the label, gives rates
         // above what HBM can deliver).
         const double lbytes = (double)R * (4.0 * ne + 4.0 * (2.0 * ne + 2.0) + 4.0 + 8.0);
+        // one workgroup's worth of rows: k_locate scans F itself
+        const bool one_wg = nbr == 1;
+        if (one_wg) {
+            a.scan_total = dscal + 3;
+            a.seq_slot = seq_slot(c, a.scan_total, &a.seq_value);
+        }
         launch(c, "k_locate", lbytes, k_locate, (uint32_t)nbr, QT, a);
+        if (one_wg) c->seq_armed = a.seq_slot != nullptr;
+        a.scan_total = a.seq_slot = nullptr;
         // |GBA| lands in dscal[3]; the profiling sums go to dscal[4..5]
         if (prof) reduce_pairs(c, a.part, nbr, dscal + 4);
-        exclusive_scan(c, a.bound, R, F, ls, dscal + 3);
+        if (!one_wg) exclusive_scan(c, a.bound, R, F, ls, dscal + 3);
         uint64_t sc[2];
         read_scalars(c, dscal + 3, sc, 2);
         uint64_t gba = sc[0];
@@ -2349,12 +2446,17 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         a.tile_off = toff;
         uint64_t *trow = ls.get<uint64_t>(ntiles + 1, "tile rows");
         a.tile_row = trow;
-        launch(c, "k_tile_rows", 8.0 * (R + 1) + 8.0 * (ntiles + 1), k_tile_rows, nblocks(R), QT, (const uint64_t *)F, R, ntiles,
-               ts, trow);
+        // at most 256 rows: the join finds its tiles' rows in F itself
+        const bool rows_in_join = nbr == 1 && !(flags & JOIN_ABL);
+        if (!rows_in_join)
+            launch(c, "k_tile_rows", 8.0 * (R + 1) + 8.0 * (ntiles + 1), k_tile_rows, nblocks(R), QT,
+                   (const uint64_t *)F, R, ntiles, ts, trow);
         double jb = 4.0 * gba + (double)R * (8.0 + 8.0 * ne + 4.0 * j) + 4.0 * (double)sc[0] + gba / 8.0 + 4.0 * ntiles;
+        a.rows_in_join = rows_in_join ? 1u : 0u;
         if (flags & JOIN_ABL) run_join_ablation(c, a, flags, ntiles, ts, jb, ls);
         else if (spt == 4) launch(c, "k_join", jb, k_join<4>, (uint32_t)ntiles, QT, a);
         else launch(c, "k_join", jb, k_join<1>, (uint32_t)ntiles, QT, a);
+        a.rows_in_join = 0;
         const size_t join_rec = c->recs.size();
         exclusive_scan(c, a.tile_cnt, ntiles, toff, ls, dscal + 1);
         uint64_t S;

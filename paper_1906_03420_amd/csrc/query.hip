@@ -776,6 +776,13 @@ __global__ __launch_bounds__(QT) void k_fn_relocate(LevelArgs a, const uint64_t 
 // |GBA| over the label's directed entries from which the level filters its
 // first-edge lists once for the whole level
 constexpr double FN_FACTOR = 2.0;
+// The fused workgroup builds M0 from root bitsets of at most this many
+// words (2^20 vertices); a larger bitset is emitted grid-wide first
+// (popcounts, scan, emit), since one CU reading it all costs more: on
+// 8.4M vertices the fused launches went from 6.2 to 4.1 ms per 50 queries
+// for 0.8 ms of added launches.
+
+constexpr uint64_t M0_FUSED_MAX_WORDS = 16384;
 
 // The per-level join and link work on tiles of SPT x 256 |GBA| slots.  On
 // large levels (SPT = 4) a 256-thread workgroup takes four consecutive
@@ -1891,8 +1898,8 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
     if (opt && opt->fused_max_slots) fcap_slots = std::min(fcap_slots, opt->fused_max_slots);
     const uint32_t chunk_min = (opt && opt->chunk_min_rows) ? opt->chunk_min_rows : CHUNK_MIN_ROWS;
     const bool try_chunks = !(flags & GSI_NO_FUSED) && !(flags & GSI_NO_CHUNKS) && R >= chunk_min;
-    const bool m0_in_fused =
-        k >= 2 && !try_chunks && !(flags & GSI_NO_FUSED) && R <= fcap_rows && fcap_slots >= 64;
+    const bool m0_in_fused = k >= 2 && !try_chunks && !(flags & GSI_NO_FUSED) && R <= fcap_rows &&
+                             fcap_slots >= 64 && nwords <= M0_FUSED_MAX_WORDS;
     if (!m0_in_fused) {
         Scratch s0(c);
         uint32_t *wc = s0.get<uint32_t>(nwords, "word counts");

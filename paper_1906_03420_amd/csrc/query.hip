@@ -781,7 +781,6 @@ constexpr double FN_FACTOR = 2.0;
 // (popcounts, scan, emit), since one CU reading it all costs more: on
 // 8.4M vertices the fused launches went from 6.2 to 4.1 ms per 50 queries
 // for 0.8 ms of added launches.
-
 constexpr uint64_t M0_FUSED_MAX_WORDS = 16384;
 
 // The per-level join and link work on tiles of SPT x 256 |GBA| slots.  On

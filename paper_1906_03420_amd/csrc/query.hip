@@ -2167,14 +2167,15 @@ gsi_result *run_query(gsi_graph *g, const HostQuery &q, const gsi_query_options 
         res->rows = out;
         launch_fused(c, fdplan, *finl, j0, M, (uint32_t)R, druns + (uint64_t)order[0] * BITS_RUNS, root_bits, nwords,
                      fbuf0, fbuf1, floc, out, fdst, 0.0);
+        const size_t frec = c->recs.size();  // the fused launch's record (the wait may add one)
         FStatus *hs = reinterpret_cast<FStatus *>(c->mbox_host + MBOX_STATUS);
         wait_mailbox(c);
         const uint32_t last = hs->done ? (uint32_t)hs->levels : (uint32_t)hs->level;
-        if ((c->flags & GSI_CTX_PROFILE) && !c->recs.empty())
+        if ((c->flags & GSI_CTX_PROFILE) && frec > 0 && frec <= c->recs.size())
             // plus, when it builds M0 itself, the root's candidate bitset it
             // scans and the rows it writes
-            c->recs.back().bytes = fused_bytes(fhp, last, hs->lv_rows, hs->lv_gba, hs->lv_surv) +
-                                   (root_bits ? 8.0 * (double)nwords + 4.0 * (double)R : 0.0);
+            c->recs[frec - 1].bytes = fused_bytes(fhp, last, hs->lv_rows, hs->lv_gba, hs->lv_surv) +
+                                      (root_bits ? 8.0 * (double)nwords + 4.0 * (double)R : 0.0);
         for (uint32_t j = j0; j <= last && j < k; j++) {
             st.rows[j] = hs->lv_rows[j];
             st.gba[j] = hs->lv_gba[j];

@@ -127,7 +127,8 @@ __device__ __forceinline__ uint64_t row_of(const uint64_t *F, uint64_t lo, uint6
 // Search rounds of the per-level join split a range in JOIN_ARITY parts
 // (in_sorted_many).  The join is bound by its load instructions, so 4-ary
 // rounds (3 probes, one more dependent round per factor 16) beat 8-ary ones
-// (7 probes): 6 % less join time on R-MAT-23.
+// (7 probes): 6 % less join time on an R-MAT graph of 8.4M vertices and
+// 100M edges.
 constexpr uint32_t JOIN_ARITY = 4;
 
 // The row values of U rows in N consecutive entries of a column list

@@ -791,11 +791,12 @@ constexpr uint64_t M0_FUSED_MAX_WORDS = 16384;
 // one slot per thread (SPT = 1) and four times as many workgroups.
 constexpr uint64_t WIDE_TILE_SLOTS = 1ull << 20;  // |GBA| from which SPT = 4
 // Candidates a join thread tests at once (keep_many).  The join is bound by
-// the latency of its dependent gathers, so waves in flight matter more than
-// loads per thread: two candidates per thread fit in 64 VGPRs, the most
-// that still lets a SIMD hold 8 waves (the join and the record link are
-// built for 8, their spare scalar registers going to VGPR lanes); four took
-// 95 VGPRs (5 waves) and were 19 % slower on R-MAT-23.
+// its gathers (their issue and their latency), so waves in flight matter
+// more than loads per thread: two candidates per thread fit in 64 VGPRs,
+// the most that still lets a SIMD hold 8 waves (the join and the record
+// link are built for 8, their spare scalar registers going to VGPR lanes);
+// four took 95 VGPRs (5 waves) and were 19 % slower on an R-MAT graph of
+// 8.4M vertices and 100M edges.
 constexpr uint32_t JU = 2;
 // rows of the last level are staged in LDS and written out as one
 // contiguous block per round (coalesced stores) when k is at most this
